@@ -1,0 +1,392 @@
+"""Seeded synthetic inputs: weighted undirected graphs plus a spanning-tree parent array.
+
+This module only *builds inputs*. It holds none of the recovery method's arithmetic
+(no LCA, no resistance, no stretch, no similarity): both the CPU oracle and the GPU
+path consume what it produces.
+
+Conventions shared by every generator
+-------------------------------------
+* Undirected edges are listed once as (u, v) with u < v, sorted by (u, v).  This is
+  the *edge id* order: id = rank of (u, v) among the upper-triangle CSR entries.
+* Weights are float64, drawn per undirected edge in edge-id order.
+* The graph is returned as a symmetric CSR (rows ascending, columns ascending within
+  a row, no self-loops, no duplicates) with int32 indices.
+* The spanning tree is the maximum-weight spanning tree under the total order
+  (w descending, id ascending).  With that order all keys are distinct, so the tree
+  is unique and any MST routine returns it.  It is rooted at the lowest-id vertex of
+  maximum degree in G, and ``parent`` comes from a BFS over the tree (root: -1).
+
+The paper evaluates on public sparse-matrix graphs (meshes, redistricting graphs,
+social and collaboration networks) that are not available here; grids and random
+geometric graphs stand in for the uniform ones and R-MAT for the skewed ones.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+__all__ = [
+    "Graph", "grid", "rmat", "rgg", "random_connected", "path_graph", "star_graph",
+    "from_edges", "max_spanning_tree_parent", "config", "batch_config", "CONFIGS",
+    "k_of", "data_dir",
+]
+
+
+class Graph:
+    """A CSR graph plus its rooted spanning tree.  All arrays are host numpy arrays."""
+
+    def __init__(self, n, row_ptr, col, w, parent, root, alpha=0.02, beta=2, name="graph"):
+        self.n = int(n)
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        self.parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.root = int(root)
+        self.alpha = float(alpha)
+        self.beta = int(beta)
+        self.name = name
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+    @property
+    def m(self):
+        return self.nnz // 2
+
+    def upper_edges(self):
+        """(eu, ev, ew) in edge-id order."""
+        rows = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.row_ptr))
+        keep = self.col > rows
+        return rows[keep].astype(np.int32), self.col[keep], self.w[keep]
+
+    def __repr__(self):
+        return f"Graph({self.name}: n={self.n}, m={self.m}, alpha={self.alpha}, beta={self.beta})"
+
+
+def k_of(alpha, n, k_override=-1):
+    """Number of edges to recover: floor(fl(alpha * n)) unless overridden."""
+    if k_override >= 0:
+        return int(k_override)
+    return int(math.floor(float(alpha) * float(n)))
+
+
+# ----------------------------------------------------------------------------------------
+# assembly helpers
+# ----------------------------------------------------------------------------------------
+
+def _sort_edges(u, v, w=None):
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    a = np.minimum(u, v)
+    b = np.maximum(u, v)
+    o = np.lexsort((b, a))
+    if w is None:
+        return a[o], b[o]
+    return a[o], b[o], np.asarray(w, dtype=np.float64)[o]
+
+
+def to_csr(n, eu, ev, ew):
+    """Symmetric CSR from upper edges (eu < ev), columns sorted within each row."""
+    eu = np.asarray(eu, dtype=np.int64)
+    ev = np.asarray(ev, dtype=np.int64)
+    rows = np.concatenate([eu, ev])
+    cols = np.concatenate([ev, eu])
+    vals = np.concatenate([ew, ew])
+    o = np.lexsort((cols, rows))
+    rows, cols, vals = rows[o], cols[o], vals[o]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    if row_ptr[-1] >= 2 ** 31:
+        raise ValueError("graph too large for int32 CSR")
+    return row_ptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64)
+
+
+def max_spanning_tree_parent(n, eu, ev, ew, root=None):
+    """Parent array of the maximum spanning tree under (w desc, id asc), BFS-rooted.
+
+    Edges must be given in edge-id order.  Raises if G is disconnected.
+    """
+    m = len(eu)
+    deg = np.bincount(eu, minlength=n) + np.bincount(ev, minlength=n)
+    if root is None:
+        root = int(np.argmax(deg))  # lowest id among the maximum-degree vertices
+    if n == 1:
+        return np.array([-1], dtype=np.int32), root
+    ids = np.arange(m, dtype=np.int64)
+    order = np.lexsort((ids, -np.asarray(ew)))          # w desc, then id asc
+    rank = np.empty(m, dtype=np.float64)
+    rank[order] = np.arange(1, m + 1, dtype=np.float64)  # distinct positive keys
+    A = sp.coo_matrix((rank, (eu, ev)), shape=(n, n)).tocsr()
+    T = csg.minimum_spanning_tree(A)
+    T = (T + T.T).tocsr()
+    bfs, pred = csg.breadth_first_order(T, root, directed=False, return_predecessors=True)
+    if len(bfs) != n:
+        raise ValueError("graph is not connected")
+    parent = pred.astype(np.int64)
+    parent[root] = -1
+    return parent.astype(np.int32), root
+
+
+def from_edges(n, eu, ev, ew, alpha=0.02, beta=2, name="graph", parent=None, root=None):
+    eu, ev, ew = _sort_edges(eu, ev, ew)
+    if parent is None:
+        parent, root = max_spanning_tree_parent(n, eu, ev, ew, root)
+    row_ptr, col, w = to_csr(n, eu, ev, ew)
+    if root is None:
+        root = int(np.flatnonzero(np.asarray(parent) < 0)[0])
+    return Graph(n, row_ptr, col, w, parent, root, alpha, beta, name)
+
+
+def _largest_cc(n, x, y):
+    A = sp.coo_matrix((np.ones(len(x), dtype=np.int8), (x, y)), shape=(n, n))
+    _, lab = csg.connected_components(A, directed=False)
+    big = np.argmax(np.bincount(lab))
+    keepv = lab == big
+    newid = np.full(n, -1, dtype=np.int64)
+    newid[keepv] = np.arange(int(keepv.sum()))
+    ke = keepv[x]
+    return int(keepv.sum()), newid[x[ke]], newid[y[ke]]
+
+
+# ----------------------------------------------------------------------------------------
+# workload families
+# ----------------------------------------------------------------------------------------
+
+def grid(dims, wlo, whi, seed=0, alpha=0.02, beta=2, name=None):
+    """d-dimensional 2d-connected grid; vertex id is row-major; w log-uniform in [wlo, whi)."""
+    rng = np.random.default_rng(seed)
+    idx = np.arange(int(np.prod(dims)), dtype=np.int64).reshape(dims)
+    us, vs = [], []
+    for ax in range(len(dims)):
+        s0 = [slice(None)] * len(dims)
+        s1 = [slice(None)] * len(dims)
+        s0[ax] = slice(0, -1)
+        s1[ax] = slice(1, None)
+        us.append(idx[tuple(s0)].ravel())
+        vs.append(idx[tuple(s1)].ravel())
+    eu, ev = _sort_edges(np.concatenate(us), np.concatenate(vs))
+    ew = np.exp(rng.uniform(math.log(wlo), math.log(whi), len(eu)))
+    return from_edges(idx.size, eu, ev, ew, alpha, beta,
+                      name or "grid" + "x".join(map(str, dims)))
+
+
+def rmat(scale, avg_deg=16, a=0.57, b=0.19, c=0.19, seed=0, alpha=0.10, beta=2, name=None):
+    """R-MAT with avg_deg*2^scale/2 samples, symmetrised, deduplicated, largest CC; w in (0,1]."""
+    rng = np.random.default_rng(seed)
+    nfull = 1 << scale
+    samples = (avg_deg * nfull) // 2
+    u = np.zeros(samples, dtype=np.int64)
+    v = np.zeros(samples, dtype=np.int64)
+    for lvl in range(scale):
+        r = rng.random(samples)
+        bu = r >= a + b                                  # quadrants c, d set the row bit
+        bv = ((r >= a) & (r < a + b)) | (r >= a + b + c)  # quadrants b, d set the column bit
+        u |= bu.astype(np.int64) << lvl
+        v |= bv.astype(np.int64) << lvl
+        del r, bu, bv
+    perm = rng.permutation(nfull)
+    u = perm[u]
+    v = perm[v]
+    keep = u != v
+    u, v = u[keep], v[keep]
+    x = np.minimum(u, v)
+    y = np.maximum(u, v)
+    del u, v, keep
+    key = np.unique(x * nfull + y)
+    x, y = key // nfull, key % nfull
+    del key
+    n, x, y = _largest_cc(nfull, x, y)
+    x, y = _sort_edges(x, y)
+    w = 1.0 - rng.random(len(x))
+    return from_edges(n, x, y, w, alpha, beta, name or f"rmat{scale}")
+
+
+def rgg(n, rng, alpha=0.02, beta=2, name=None):
+    """Random geometric graph in the unit square, radius for average degree ~10, w = 1/dist."""
+    from scipy.spatial import cKDTree
+    pts = rng.random((n, 2))
+    r = math.sqrt(10.0 / (math.pi * n))
+    pr = cKDTree(pts).query_pairs(r, output_type="ndarray").astype(np.int64)
+    d = np.linalg.norm(pts[pr[:, 0]] - pts[pr[:, 1]], axis=1)
+    ok = d > 0
+    pr, d = pr[ok], d[ok]
+    # the largest component, compactly relabelled; weights follow the surviving pairs
+    A = sp.coo_matrix((np.ones(len(pr), dtype=np.int8), (pr[:, 0], pr[:, 1])), shape=(n, n))
+    _, lab = csg.connected_components(A, directed=False)
+    big = np.argmax(np.bincount(lab))
+    kv = lab == big
+    nid = np.full(n, -1, dtype=np.int64)
+    nid[kv] = np.arange(int(kv.sum()))
+    ke = kv[pr[:, 0]]
+    x, y, w = nid[pr[ke, 0]], nid[pr[ke, 1]], 1.0 / d[ke]
+    return from_edges(int(kv.sum()), x, y, w, alpha, beta, name or f"rgg{n}")
+
+
+def random_connected(n, extra, seed=0, alpha=0.1, beta=2, wlo=1.0, whi=100.0,
+                     tree="max", name=None):
+    """Small random connected graph: random recursive tree + ``extra`` random edges.
+
+    tree="max": spanning tree input is the max-weight spanning tree;
+    tree="random": it is the random recursive tree used to build G (rooted at vertex 0
+    after relabelling), which gives deeper, less weight-correlated trees.
+    """
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    par = np.array([-1] + [int(rng.integers(0, i)) for i in range(1, n)], dtype=np.int64)
+    tu = perm[np.arange(1, n)]
+    tv = perm[par[1:]]
+    eu = [tu]
+    ev = [tv]
+    if extra > 0 and n > 2:
+        a = rng.integers(0, n, 3 * extra + 8)
+        b = rng.integers(0, n, 3 * extra + 8)
+        eu.append(a)
+        ev.append(b)
+    u = np.concatenate(eu)
+    v = np.concatenate(ev)
+    keep = u != v
+    x = np.minimum(u[keep], v[keep])
+    y = np.maximum(u[keep], v[keep])
+    key, first = np.unique(x * n + y, return_index=True)
+    # keep every tree edge and the first `extra` distinct random edges
+    is_tree = first < (n - 1)
+    nontree = np.flatnonzero(~is_tree)
+    nontree = nontree[np.argsort(first[nontree], kind="stable")][:extra]
+    sel = np.sort(np.concatenate([np.flatnonzero(is_tree), nontree]))
+    key = key[sel]
+    x, y = key // n, key % n
+    w = np.exp(rng.uniform(math.log(wlo), math.log(whi), len(x)))
+    if tree == "max":
+        return from_edges(n, x, y, w, alpha, beta, name or f"rand{n}")
+    parent = np.full(n, -1, dtype=np.int64)
+    # orient the recursive tree from the relabelled root perm[0]
+    T = sp.coo_matrix((np.ones(n - 1), (tu, tv)), shape=(n, n)).tocsr()
+    T = (T + T.T).tocsr()
+    root = int(perm[0])
+    _, pred = csg.breadth_first_order(T, root, directed=False, return_predecessors=True)
+    parent[:] = pred
+    parent[root] = -1
+    return from_edges(n, x, y, w, alpha, beta, name or f"rand{n}", parent=parent.astype(np.int32),
+                      root=root)
+
+
+def path_graph(n, extra, seed=0, alpha=0.5, beta=2):
+    """Path 0-1-...-(n-1) as the tree (rooted at 0, an end) plus random chords."""
+    rng = np.random.default_rng(seed)
+    tu = np.arange(n - 1)
+    tv = tu + 1
+    a = rng.integers(0, n, 4 * extra + 8)
+    b = rng.integers(0, n, 4 * extra + 8)
+    keep = np.abs(a - b) > 1
+    x = np.minimum(a[keep], b[keep])
+    y = np.maximum(a[keep], b[keep])
+    key = np.unique(x * n + y)[:extra]
+    x = np.concatenate([tu, key // n])
+    y = np.concatenate([tv, key % n])
+    w = np.exp(rng.uniform(0.0, math.log(100.0), len(x)))
+    parent = np.concatenate([[-1], np.arange(n - 1)]).astype(np.int32)
+    return from_edges(n, x, y, w, alpha, beta, f"path{n}", parent=parent, root=0)
+
+
+def star_graph(n, extra, seed=0, alpha=0.5, beta=2):
+    """Star rooted at 0 as the tree plus random leaf-leaf chords."""
+    rng = np.random.default_rng(seed)
+    tu = np.zeros(n - 1, dtype=np.int64)
+    tv = np.arange(1, n)
+    a = rng.integers(1, n, 4 * extra + 8)
+    b = rng.integers(1, n, 4 * extra + 8)
+    keep = a != b
+    x = np.minimum(a[keep], b[keep])
+    y = np.maximum(a[keep], b[keep])
+    key = np.unique(x * n + y)[:extra]
+    x = np.concatenate([tu, key // n])
+    y = np.concatenate([tv, key % n])
+    w = np.exp(rng.uniform(0.0, math.log(100.0), len(x)))
+    parent = np.concatenate([[-1], np.zeros(n - 1)]).astype(np.int32)
+    return from_edges(n, x, y, w, alpha, beta, f"star{n}", parent=parent, root=0)
+
+
+# ----------------------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------------------
+
+CONFIGS = {
+    # 2D 4-connected grid 64x64, w log-uniform [1,100], alpha 0.02, beta 2
+    "grid2d_64": dict(kind="grid", dims=(64, 64), wlo=1.0, whi=100.0, alpha=0.02, beta=2),
+    # 3D 7-point grid 128^3, w log-uniform [1,1e4], alpha 0.05, beta 2
+    "grid3d_128": dict(kind="grid", dims=(128, 128, 128), wlo=1.0, whi=1e4, alpha=0.05, beta=2),
+    # R-MAT scale 22, avg degree 16, (.57,.19,.19,.05), LCC, w uniform (0,1], alpha 0.10
+    "rmat22": dict(kind="rmat", scale=22, alpha=0.10, beta=2),
+    # learned-scheduling pair: R-MAT scale 24 and 3D grid 160^3, alpha 0.10
+    "rmat24": dict(kind="rmat", scale=24, alpha=0.10, beta=2),
+    "grid3d_160": dict(kind="grid", dims=(160, 160, 160), wlo=1.0, whi=1e4, alpha=0.10, beta=2),
+    # scaled-down stand-ins used by fast tests
+    "grid3d_32": dict(kind="grid", dims=(32, 32, 32), wlo=1.0, whi=1e4, alpha=0.05, beta=2),
+    "rmat14": dict(kind="rmat", scale=14, alpha=0.10, beta=2),
+    "rmat16": dict(kind="rmat", scale=16, alpha=0.10, beta=2),
+}
+
+_GEN_VERSION = 1
+
+
+def data_dir():
+    d = os.environ.get("GSS_DATA_DIR")
+    if not d:
+        d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "_data")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def _save(g, path):
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, n=g.n, row_ptr=g.row_ptr, col=g.col, w=g.w, parent=g.parent, root=g.root,
+             alpha=g.alpha, beta=g.beta)
+    os.replace(tmp, path)
+
+
+def _load(path, name):
+    with np.load(path, allow_pickle=False) as z:
+        return Graph(int(z["n"]), z["row_ptr"], z["col"], z["w"], z["parent"], int(z["root"]),
+                     float(z["alpha"]), int(z["beta"]), name)
+
+
+def config(name, seed=0, cache=True):
+    """Build (or load from the on-disk cache) one named workload."""
+    spec = CONFIGS[name]
+    path = os.path.join(data_dir(), f"{name}_s{seed}_v{_GEN_VERSION}.npz")
+    if cache and os.path.exists(path):
+        return _load(path, name)
+    if spec["kind"] == "grid":
+        g = grid(spec["dims"], spec["wlo"], spec["whi"], seed, spec["alpha"], spec["beta"], name)
+    elif spec["kind"] == "rmat":
+        g = rmat(spec["scale"], seed=seed, alpha=spec["alpha"], beta=spec["beta"], name=name)
+    else:
+        raise KeyError(name)
+    if cache:
+        _save(g, path)
+    return g
+
+
+def batch_config(count=64, nmin=1e4, nmax=1e6, seed=0, cache=True):
+    """Batch of random geometric graphs, sizes log-uniform in [nmin, nmax), alpha in {.02,.05,.10}."""
+    rng = np.random.default_rng(seed)
+    ns = np.floor(np.exp(rng.uniform(math.log(nmin), math.log(nmax), count))).astype(np.int64)
+    alphas = rng.choice(np.array([0.02, 0.05, 0.10]), count)
+    out = []
+    for i in range(count):
+        path = os.path.join(data_dir(), f"rgg_b{count}_{int(nmin)}_{int(nmax)}_s{seed}_{i}_v{_GEN_VERSION}.npz")
+        if cache and os.path.exists(path):
+            g = _load(path, f"rgg{i}")
+            # keep the generator stream aligned with an uncached run
+            rng.random((int(ns[i]), 2))
+        else:
+            g = rgg(int(ns[i]), rng, float(alphas[i]), 2, f"rgg{i}")
+            if cache:
+                _save(g, path)
+        out.append(g)
+    return out
