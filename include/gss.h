@@ -1,0 +1,148 @@
+/*
+ * gss.h -- C ABI of the MI355X (gfx950) library for pdGRASS off-tree edge recovery.
+ *
+ * Problem (paper Sec. II-A, Sec. II-B, Alg. 1): given a weighted undirected graph
+ * G=(V,E,w) and a spanning tree T of G, recover K = floor(alpha*|V|) off-tree edges so
+ * that T plus the recovered edges is the sparsifier P (|V|-1+alpha|V| edges).  Off-tree
+ * edges are ranked by stretch = w(e) * R_T(e), where R_T is the tree-path resistance
+ * through the LCA (Def. "Resistance distance", eq. RT, resistive weight 1/w), in
+ * descending order with ties broken by ascending edge id.  Walking that order, an
+ * edge that is not marked is recovered, and it marks every later off-tree edge that is
+ * strictly similar to it under its density-aware BFS step
+ * beta* = min(dist(u,lca), dist(v,lca), c)  (eq. beta-new, Def. "Similar edge (Strict)").
+ * If a pass over all edges recovers fewer than K edges, further passes run over the
+ * unrecovered edges with all marks cleared (the multi-pass rule of Sec. II-B).
+ *
+ * Conventions
+ *  - Unless stated otherwise every array argument is a DEVICE pointer owned by the
+ *    caller; the library never frees or modifies caller arrays except the outputs.
+ *  - Vertex ids are int32 in [0,n).  The edge id of {u,v} (u<v) is the rank of the
+ *    CSR entry (u,v) among all entries with column > row, rows ascending, then columns
+ *    ascending.  Per-edge arrays are indexed by edge id, length m = nnz/2.
+ *  - Every call is stream-ordered on the context's HIP stream and returns after that
+ *    stream has finished the call's work (host outputs are then valid).
+ *  - No exception crosses the ABI: every function returns a gss_status.
+ *  - One context must be used by one host thread at a time.
+ */
+#ifndef GSS_H
+#define GSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gss_status;
+enum {
+    GSS_OK = 0,
+    GSS_SHORT = 1,            /* fewer than K off-tree edges exist; all were recovered   */
+    GSS_ERR_ARG = -1,         /* bad argument: null pointer, n<1, malformed row_ptr,
+                                 column index out of range, alpha not in [0,1], beta<0,
+                                 beta > GSS_MAX_BETA                                      */
+    GSS_ERR_NOT_SIMPLE = -2,  /* a row is not strictly increasing or holds a self-loop   */
+    GSS_ERR_ASYM = -3,        /* (u,v) present without (v,u), or w(u,v) != w(v,u)         */
+    GSS_ERR_WEIGHT = -4,      /* a weight is <= 0, NaN or infinite                        */
+    GSS_ERR_NOT_TREE = -5,    /* parent[] out of range, not exactly one root, or a cycle */
+    GSS_ERR_TREE_EDGE = -6,   /* some (x, parent[x]) is not an edge of G                  */
+    GSS_ERR_RANGE = -7,       /* 1/w not a normal double, tree resistances need more than
+                                 127 bits of fixed point, or a stretch is not finite      */
+    GSS_ERR_HIP = -8,         /* a HIP runtime call failed (see gss_last_error)           */
+    GSS_ERR_OOM = -9          /* device allocation failed                                 */
+};
+/* When several checks fail, the status reported is the first of: ARG, NOT_SIMPLE,
+ * WEIGHT, ASYM, NOT_TREE, TREE_EDGE, RANGE. */
+
+#define GSS_MAX_BETA 8        /* largest supported BFS-step constant c                     */
+
+typedef struct gss_ctx_s *gss_ctx;    /* device, stream binding and scratch pool          */
+typedef struct gss_tree_s *gss_tree;  /* prepared graph+tree; borrows the caller's CSR    */
+
+/* CSR graph: symmetric, rows strictly increasing, no self-loops, w > 0 finite. */
+typedef struct {
+    int32_t n;                 /* number of vertices, >= 1                               */
+    int64_t nnz;               /* number of stored entries (2m), < 2^31                  */
+    const int32_t *row_ptr;    /* device [n+1]                                           */
+    const int32_t *col;        /* device [nnz]                                           */
+    const double *w;           /* device [nnz]                                           */
+} gss_csr;
+
+/* gss_params.flags */
+#define GSS_F_MASK_TREE 1u     /* also set mask[] = 1 on tree edges (mask = sparsifier P) */
+
+/* gss_params.sched: order in which the subtask work queue is drained (never changes
+ * the output). */
+enum { GSS_SCHED_EDGECOUNT = 0, GSS_SCHED_LEARNED = 1 };
+
+typedef struct {
+    double alpha;              /* fraction of |V| to recover, in [0,1]                   */
+    int32_t beta;              /* BFS-step constant c >= 0 of eq. beta-new               */
+    int32_t sched;             /* GSS_SCHED_*                                             */
+    int64_t k_override;        /* >= 0: recover exactly this many; < 0: floor(alpha*n)   */
+    uint32_t flags;            /* GSS_F_*                                                 */
+    int32_t reserved;          /* must be 0                                               */
+} gss_params;
+
+typedef struct {
+    int64_t m;                 /* undirected edges                                       */
+    int64_t n_offtree;         /* M = m - n + 1                                          */
+    int64_t k;                 /* target count K                                         */
+    int64_t n_recovered;       /* min(K, M)                                              */
+    int64_t n_subtasks;        /* distinct LCAs over all off-tree edges                  */
+    int64_t largest_subtask;   /* edges sharing the most common LCA                      */
+    int64_t prefix_len;        /* length of the criticality-order prefix resolved        */
+    int64_t n_arcs;            /* strict-similarity pairs found inside that prefix       */
+    int32_t passes;            /* passes that recovered at least one edge                */
+    int32_t rounds;            /* dependency rounds used to resolve the prefix           */
+} gss_info;
+
+/* Creates a context on `device` bound to `hip_stream` (a hipStream_t, may be NULL for
+ * the default stream).  *out receives the handle.  Errors: ARG, HIP. */
+gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out);
+/* Rebinds the context to another stream. */
+gss_status gss_ctx_set_stream(gss_ctx ctx, void *hip_stream);
+/* Frees the context's device memory.  Trees built on it must be freed first. */
+gss_status gss_ctx_destroy(gss_ctx ctx);
+
+/* Tree preparation (Alg. 1 Step 1 set-up: the ancestor/LCA structure and the
+ * root-to-node distances): validates g and parent (unless flags has
+ * GSS_PREP_TRUSTED), enumerates edges, and builds the Euler-tour LCA structure, depths
+ * and the exact fixed-point root resistances.  parent: device [n], parent[root] = -1.
+ * The tree keeps pointers to g's arrays; the caller keeps them alive and unchanged
+ * until gss_tree_free.  Errors: ARG, NOT_SIMPLE, WEIGHT, ASYM, NOT_TREE, TREE_EDGE,
+ * RANGE, HIP, OOM. */
+#define GSS_PREP_TRUSTED 1u
+gss_status gss_tree_prep(gss_ctx ctx, const gss_csr *g, const int32_t *parent, uint32_t flags,
+                         gss_tree *out);
+gss_status gss_tree_free(gss_tree tree);
+
+/* Off-tree edge recovery (Alg. 1 Steps 1-4).
+ *   mask    device uint8 [m]: 1 = recovered off-tree edge (and tree edges if
+ *           GSS_F_MASK_TREE), 0 otherwise.  Required.
+ *   order   device int32 [K] or NULL: recovered edge ids in recovery order.
+ *   stretch device double [m] or NULL: stretch of every off-tree edge, 0 on tree edges.
+ *   info    host or NULL.
+ * Errors: ARG, RANGE, HIP, OOM.  Returns GSS_SHORT when M < K. */
+gss_status gss_recover(gss_ctx ctx, gss_tree tree, const gss_params *params, uint8_t *mask,
+                       int32_t *order, double *stretch, gss_info *info);
+
+/* Diagnostics used by the parity tests (same kernels as the path above).
+ *   depth  device int32 [n]; Dlo, Dhi device uint64 [n]: root resistance D(x) = (Dhi*2^64
+ *   + Dlo) * 2^scale; scale host int32.  Any pointer may be NULL. */
+gss_status gss_tree_export(gss_tree tree, int32_t *depth, uint64_t *Dlo, uint64_t *Dhi,
+                           int32_t *scale);
+/* Per-edge LCA (-1 on tree edges) and beta* (0 on tree edges) for BFS-step constant
+ * beta; device int32 [m] each, either may be NULL. */
+gss_status gss_edge_lca(gss_ctx ctx, gss_tree tree, int32_t beta, int32_t *lca, int32_t *bstar);
+
+/* Returns the number of undirected edges m of a prepared tree, or -1. */
+int64_t gss_tree_num_edges(gss_tree tree);
+
+/* Library-owned, static strings. */
+const char *gss_status_str(gss_status s);
+const char *gss_last_error(gss_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSS_H */

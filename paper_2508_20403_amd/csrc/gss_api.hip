@@ -1,0 +1,191 @@
+// gss_api.hip -- the exported C ABI (declared in include/gss.h).
+#include "gss_impl.h"
+
+namespace {
+thread_local std::string g_err;
+
+template <typename F>
+gss_status guarded(gss_ctx ctx, F &&f)
+{
+    try {
+        return f();
+    } catch (const gss_error &e) {
+        if (ctx) ctx->last_error = e.msg;
+        g_err = e.msg;
+        if (ctx && e.status == GSS_ERR_HIP) (void)hipGetLastError();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->last_error = "host allocation failed";
+        return GSS_ERR_OOM;
+    } catch (...) {
+        if (ctx) ctx->last_error = "unexpected exception";
+        return GSS_ERR_HIP;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
+{
+    if (!out) return GSS_ERR_ARG;
+    *out = nullptr;
+    gss_ctx ctx = new (std::nothrow) gss_ctx_s();
+    if (!ctx) return GSS_ERR_OOM;
+    gss_status s = guarded(ctx, [&]() -> gss_status {
+        int count = 0;
+        HIP_OK(hipGetDeviceCount(&count));
+        if (device < 0 || device >= count) throw gss_error{GSS_ERR_ARG, "no such device"};
+        HIP_OK(hipSetDevice(device));
+        ctx->device = device;
+        ctx->stream = (hipStream_t)hip_stream;
+        HIP_OK(hipMalloc(&ctx->d_flags, 256));
+        HIP_OK(hipMalloc(&ctx->d_counters, 16 * sizeof(int64_t)));
+        HIP_OK(hipHostMalloc(&ctx->h_counters, 16 * sizeof(int64_t), hipHostMallocDefault));
+        HIP_OK(hipMemset(ctx->d_flags, 0, 256));
+        return GSS_OK;
+    });
+    if (s != GSS_OK) {
+        g_err = ctx->last_error;
+        if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+        if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+        if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+        delete ctx;
+        return s;
+    }
+    *out = ctx;
+    return GSS_OK;
+}
+
+gss_status gss_ctx_set_stream(gss_ctx ctx, void *hip_stream)
+{
+    if (!ctx) return GSS_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return GSS_OK;
+}
+
+gss_status gss_ctx_destroy(gss_ctx ctx)
+{
+    if (!ctx) return GSS_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->pool.release_all();
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+    if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+    delete ctx;
+    return GSS_OK;
+}
+
+gss_status gss_tree_prep(gss_ctx ctx, const gss_csr *g, const int32_t *parent, uint32_t flags, gss_tree *out)
+{
+    if (!ctx || !g || !out) return GSS_ERR_ARG;
+    *out = nullptr;
+    if (g->n < 1 || g->nnz < 0 || g->nnz >= ((int64_t)1 << 31) || g->n >= (1 << 30) || !g->row_ptr ||
+        !parent || (g->nnz > 0 && (!g->col || !g->w))) {
+        ctx->last_error = "bad graph arguments";
+        return GSS_ERR_ARG;
+    }
+    gss_tree t = new (std::nothrow) gss_tree_s();
+    if (!t) return GSS_ERR_OOM;
+    t->ctx = ctx;
+    t->n = g->n;
+    t->nnz = g->nnz;
+    t->row_ptr = g->row_ptr;
+    t->col = g->col;
+    t->w = g->w;
+    t->parent = parent;
+    gss_status s = guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        prep_tree(ctx, t, flags);
+        return GSS_OK;
+    });
+    if (s != GSS_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        free_tree_arrays(t);
+        delete t;
+        return s;
+    }
+    *out = t;
+    return GSS_OK;
+}
+
+gss_status gss_tree_free(gss_tree t)
+{
+    if (!t) return GSS_ERR_ARG;
+    (void)hipStreamSynchronize(t->ctx->stream);
+    free_tree_arrays(t);
+    delete t;
+    return GSS_OK;
+}
+
+int64_t gss_tree_num_edges(gss_tree t) { return t ? t->m : -1; }
+
+gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *mask, int32_t *order,
+                       double *stretch, gss_info *info)
+{
+    if (!ctx || !t || !p || !mask || t->ctx != ctx) return GSS_ERR_ARG;
+    if (!(p->alpha >= 0.0 && p->alpha <= 1.0) || p->beta < 0 || p->beta > GSS_MAX_BETA || p->reserved != 0 ||
+        (p->sched != GSS_SCHED_EDGECOUNT && p->sched != GSS_SCHED_LEARNED)) {
+        ctx->last_error = "bad recovery parameters";
+        return GSS_ERR_ARG;
+    }
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        return recover_impl(ctx, t, p, mask, order, stretch, info);
+    });
+}
+
+gss_status gss_tree_export(gss_tree t, int32_t *depth, uint64_t *Dlo, uint64_t *Dhi, int32_t *scale)
+{
+    if (!t) return GSS_ERR_ARG;
+    gss_ctx ctx = t->ctx;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        if (depth)
+            HIP_OK(hipMemcpyAsync(depth, t->depth, sizeof(int32_t) * t->n, hipMemcpyDeviceToDevice, ctx->stream));
+        if (Dlo) HIP_OK(hipMemcpy2DAsync(Dlo, sizeof(uint64_t), &t->D[0].lo, sizeof(u128), sizeof(uint64_t), t->n,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+        if (Dhi) HIP_OK(hipMemcpy2DAsync(Dhi, sizeof(uint64_t), &t->D[0].hi, sizeof(u128), sizeof(uint64_t), t->n,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+        if (scale) *scale = t->scale;
+        ctx->sync();
+        return GSS_OK;
+    });
+}
+
+gss_status gss_edge_lca(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar)
+{
+    if (!ctx || !t || t->ctx != ctx || beta < 0 || beta > GSS_MAX_BETA) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        edge_lca_impl(ctx, t, beta, lca, bstar);
+        return GSS_OK;
+    });
+}
+
+const char *gss_status_str(gss_status s)
+{
+    switch (s) {
+    case GSS_OK: return "GSS_OK";
+    case GSS_SHORT: return "GSS_SHORT";
+    case GSS_ERR_ARG: return "GSS_ERR_ARG";
+    case GSS_ERR_NOT_SIMPLE: return "GSS_ERR_NOT_SIMPLE";
+    case GSS_ERR_ASYM: return "GSS_ERR_ASYM";
+    case GSS_ERR_WEIGHT: return "GSS_ERR_WEIGHT";
+    case GSS_ERR_NOT_TREE: return "GSS_ERR_NOT_TREE";
+    case GSS_ERR_TREE_EDGE: return "GSS_ERR_TREE_EDGE";
+    case GSS_ERR_RANGE: return "GSS_ERR_RANGE";
+    case GSS_ERR_HIP: return "GSS_ERR_HIP";
+    case GSS_ERR_OOM: return "GSS_ERR_OOM";
+    default: return "GSS_UNKNOWN";
+    }
+}
+
+const char *gss_last_error(gss_ctx ctx)
+{
+    if (!ctx) return g_err.c_str();
+    return ctx->last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// gss_impl.h -- host-side internals of the gfx950 library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gss.h"
+#include "gss_dev.h"
+
+// Thrown inside the library only; every exported function catches it.
+struct gss_error {
+    gss_status status;
+    std::string msg;
+};
+
+#define HIP_OK(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw gss_error{GSS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// Caching device allocator: blocks are kept per context and reused by size.  All work
+// of a context runs on its one stream, so a block returned to the cache may be handed
+// out again immediately (stream order keeps earlier users ahead of later ones).
+struct dev_pool {
+    std::multimap<size_t, void *> free_blocks;  // capacity -> pointer
+    std::map<void *, size_t> live;              // pointer -> capacity
+    size_t bytes_held = 0;
+
+    void *get(size_t bytes);
+    void put(void *p);
+    void release_all();
+};
+
+struct gss_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    dev_pool pool;
+    uint32_t *d_flags = nullptr;      // device error flags
+    int64_t *d_counters = nullptr;    // small device scratch (16 words)
+    int64_t *h_counters = nullptr;    // pinned host mirror
+    hipEvent_t ev_done = nullptr;
+
+    template <typename T>
+    T *alloc(size_t count)
+    {
+        return (T *)pool.get(count * sizeof(T) + 16);
+    }
+    void free(void *p)
+    {
+        if (p) pool.put(p);
+    }
+    void sync() { HIP_OK(hipStreamSynchronize(stream)); }
+};
+
+struct gss_tree_s {
+    gss_ctx ctx = nullptr;
+    int32_t n = 0;
+    int64_t nnz = 0, m = 0, M = 0;
+    const int32_t *row_ptr = nullptr, *col = nullptr, *parent = nullptr;
+    const double *w = nullptr;
+    int32_t root = 0;
+    int32_t emin = 0;    // smallest binary exponent of any tree resistance 1/w
+    int32_t scale = 0;   // root resistances are integers in units of 2^scale
+    // edges
+    int32_t *uptr = nullptr;     // [n+1] id of the first upper entry of each row
+    int32_t *ufirst = nullptr;   // [n] CSR index of the first upper entry of each row
+    int32_t *tpos = nullptr;     // [n] CSR index of (x, parent x) in row x, -1 at root
+    int32_t *tree_eid = nullptr; // [n] edge id of (x, parent x), -1 at root
+    // tree / Euler tour
+    int32_t *depth = nullptr;    // [n]
+    u128 *D = nullptr;           // [n] root resistance, fixed point
+    int32_t *first = nullptr;    // [n] first Euler position
+    int32_t L = 0;               // Euler sequence length 2n-1
+    uint64_t *epk = nullptr;     // [L] (depth << 32) | vertex
+    uint64_t *pmask = nullptr;   // [L] in-block suffix-minimum masks
+    int32_t nb = 0, nsb = 0, sblevels = 0;
+    uint64_t *bmin = nullptr;    // [nb] block minima
+    uint64_t *bmask = nullptr;   // [nb] in-superblock masks over block minima
+    uint64_t *sbst = nullptr;    // [sblevels * nsb] sparse table over superblock minima
+    // off-tree edges in id order
+    int32_t *off_id = nullptr, *off_u = nullptr, *off_v = nullptr;
+    double *off_w = nullptr;
+};
+
+// ---- host entry points of the translation units --------------------------------------
+void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags);
+void free_tree_arrays(gss_tree t);
+gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *mask,
+                        int32_t *order, double *stretch, gss_info *info);
+void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar);
+
+// ---- shared launch helpers (gss_prims.hip) -------------------------------------------
+// exclusive scan of int32 counts in place over [0,n); returns the total (host sync)
+int64_t scan_exclusive_i32(gss_ctx ctx, int32_t *data, int64_t n, bool want_total);
+uint32_t read_flags(gss_ctx ctx);
+gss_status status_from_flags(uint32_t f);
+
+inline unsigned grid_for(int64_t items, int block, int per_thread = 1)
+{
+    int64_t g = (items + (int64_t)block * per_thread - 1) / ((int64_t)block * per_thread);
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}

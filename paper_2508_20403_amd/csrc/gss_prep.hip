@@ -1,0 +1,849 @@
+// gss_prep.hip -- tree preparation on gfx950.
+//
+// Builds everything the per-edge step needs from a CSR graph and a parent array:
+//   * validation flags (simple, symmetric, positive weights, a rooted spanning tree),
+//   * edge numbering: the id of {u,v}, u<v, is the rank of entry (u,v) among the
+//     upper-triangle CSR entries,
+//   * the Euler tour of the tree, ranked by a recursive sparse-ruling-set list ranking
+//     that carries (position, depth, root resistance) sums along the walk,
+//   * depth, first Euler position and the exact root-to-node resistance
+//     D(x) = sum over the root->x path of RN(1/w) in 128-bit fixed point
+//     (paper: Def. "Resistance distance", eq. RT, resistive weight 1/w),
+//   * a two-level in-block-mask RMQ over the Euler depth sequence (for LCA queries),
+//   * the list of off-tree edges in id order.
+#include "gss_impl.h"
+
+#define PB 256          // default block size
+#define ENT_ITEMS 16    // CSR entries per thread in entry-parallel kernels
+#define RULE_RATE 8     // one ruler per ~8 list elements (power of two)
+#define BASE_MAX 1024   // lists this short are ranked by one workgroup
+
+// ------------------------------------------------------------------------------------
+// small device helpers
+// ------------------------------------------------------------------------------------
+// row u with row_ptr[u] <= k < row_ptr[u+1]  (largest u with row_ptr[u] <= k)
+__device__ __forceinline__ int32_t row_of(const int32_t *__restrict__ row_ptr, int32_t n, int64_t k)
+{
+    int32_t lo = 0, hi = n;  // invariant: row_ptr[lo] <= k, answer in [lo, hi)
+    while (hi - lo > 1) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)row_ptr[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// index of key in the sorted range col[lo,hi), or -1
+__device__ __forceinline__ int64_t find_in_row(const int32_t *__restrict__ col, int64_t lo, int64_t hi,
+                                               int32_t key)
+{
+    int64_t end = hi;
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && col[lo] == key) ? lo : -1;
+}
+
+// ------------------------------------------------------------------------------------
+// validation and edge numbering
+// ------------------------------------------------------------------------------------
+__global__ void k_check_rowptr(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
+                               uint32_t *flags)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    bool bad = false;
+    if (u == 0 && row_ptr[0] != 0) bad = true;
+    if (u < n && row_ptr[u + 1] < row_ptr[u]) bad = true;
+    if (u == n && (int64_t)row_ptr[n] != nnz) bad = true;
+    if (bad) atomicOr(flags, F_ARG);
+}
+
+__global__ void k_check_entries(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                const double *__restrict__ w, int32_t n, int64_t nnz, uint32_t *flags)
+{
+    int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * ENT_ITEMS;
+    if (k0 >= nnz) return;
+    int32_t u = row_of(row_ptr, n, k0);
+    uint32_t f = 0;
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        int64_t k = k0 + i;
+        if (k >= nnz) break;
+        while ((int64_t)row_ptr[u + 1] <= k) u++;
+        int32_t c = col[k];
+        if (c < 0 || c >= n) {
+            f |= F_ARG;
+            continue;
+        }
+        if (c == u) f |= F_NOT_SIMPLE;
+        if (k > row_ptr[u] && col[k - 1] >= c) f |= F_NOT_SIMPLE;
+        double x = w[k];
+        if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// first upper entry of each row and the number of upper entries
+__global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t n,
+                       int32_t *__restrict__ ufirst, int32_t *__restrict__ ucnt)
+{
+    int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int64_t lo = row_ptr[u], hi = row_ptr[u + 1], end = hi;
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] <= u) lo = mid + 1;
+        else hi = mid;
+    }
+    ufirst[u] = (int32_t)lo;
+    ucnt[u] = (int32_t)(end - lo);
+}
+
+// every upper entry (u,v,w) needs its mirror (v,u,w)
+__global__ void k_check_sym(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ w, int32_t n, int64_t nnz, uint32_t *flags)
+{
+    int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * ENT_ITEMS;
+    if (k0 >= nnz) return;
+    int32_t u = row_of(row_ptr, n, k0);
+    bool bad = false;
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        int64_t k = k0 + i;
+        if (k >= nnz) break;
+        while ((int64_t)row_ptr[u + 1] <= k) u++;
+        int32_t v = col[k];
+        if (v <= u) continue;
+        int64_t j = find_in_row(col, row_ptr[v], row_ptr[v + 1], u);
+        if (j < 0 || w[j] != w[k]) bad = true;
+    }
+    if (bad) atomicOr(flags, F_ASYM);
+}
+
+// parent checks, child counts, tree-edge positions and the exponent range of 1/w
+__global__ void k_tree_check(const int32_t *__restrict__ parent, const int32_t *__restrict__ row_ptr,
+                             const int32_t *__restrict__ col, const double *__restrict__ w, int32_t n,
+                             int32_t *__restrict__ ccnt, int32_t *__restrict__ tpos, uint32_t *flags,
+                             int64_t *counters)
+{
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int32_t p = parent[x];
+    tpos[x] = -1;
+    if (p == -1) {
+        atomicAdd((unsigned long long *)&counters[0], 1ull);
+        atomicMin((long long *)&counters[1], (long long)x);
+        return;
+    }
+    if (p < 0 || p >= n || p == x) {
+        atomicOr(flags, F_NOT_TREE);
+        return;
+    }
+    atomicAdd(&ccnt[p], 1);
+    int64_t k = find_in_row(col, row_ptr[x], row_ptr[x + 1], p);
+    if (k < 0) {
+        atomicOr(flags, F_TREE_EDGE);
+        return;
+    }
+    tpos[x] = (int32_t)k;
+    double t = 1.0 / w[k];
+    uint64_t b = (uint64_t)__double_as_longlong(t);
+    int ef = (int)((b >> 52) & 0x7ff);
+    if (ef == 0 || ef == 0x7ff) {
+        atomicOr(flags, F_RANGE);
+        return;
+    }
+    int e = ef - 1023;
+    atomicMin((long long *)&counters[2], (long long)e);
+    atomicMax((long long *)&counters[3], (long long)e);
+}
+
+__global__ void k_children_fill(const int32_t *__restrict__ parent, int32_t n,
+                                const int32_t *__restrict__ cptr, int32_t *__restrict__ cfill,
+                                int32_t *__restrict__ clist, int32_t *__restrict__ cslot)
+{
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int32_t p = parent[x];
+    if (p < 0) {
+        cslot[x] = -1;
+        return;
+    }
+    int32_t s = cptr[p] + atomicAdd(&cfill[p], 1);
+    clist[s] = x;
+    cslot[x] = s;
+}
+
+// fixed-point resistance term of each tree edge, and per-block sums for the range check
+__global__ __launch_bounds__(PB) void k_terms(const int32_t *__restrict__ tpos,
+                                              const double *__restrict__ w, int32_t n, int32_t root,
+                                              int emin, int ok, u128 *__restrict__ T,
+                                              u128 *__restrict__ bsum, uint64_t *__restrict__ bcarry)
+{
+    __shared__ uint64_t slo[PB], shi[PB], sc[PB];
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    u128 t = mk128(0, 0);
+    if (ok && x < n && x != root && tpos[x] >= 0) t = fixed_term(1.0 / w[tpos[x]], emin);
+    if (x < n) T[x] = t;
+    slo[threadIdx.x] = t.lo;
+    shi[threadIdx.x] = t.hi;
+    sc[threadIdx.x] = 0;
+    __syncthreads();
+    for (int s = PB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            u128 a = mk128(slo[threadIdx.x], shi[threadIdx.x]);
+            u128 b = mk128(slo[threadIdx.x + s], shi[threadIdx.x + s]);
+            u128 r = add128(a, b);
+            uint64_t c = sc[threadIdx.x] + sc[threadIdx.x + s];
+            if (r.hi < a.hi || (r.hi == a.hi && r.lo < a.lo)) c++;
+            slo[threadIdx.x] = r.lo;
+            shi[threadIdx.x] = r.hi;
+            sc[threadIdx.x] = c;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = mk128(slo[0], shi[0]);
+        bcarry[blockIdx.x] = sc[0];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_terms_total(const u128 *__restrict__ bsum,
+                                                      const uint64_t *__restrict__ bcarry, int64_t nb,
+                                                      uint32_t *flags)
+{
+    __shared__ uint64_t slo[1024], shi[1024], sc[1024];
+    u128 s = mk128(0, 0);
+    uint64_t c = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 1024) {
+        u128 r = add128(s, bsum[i]);
+        if (r.hi < s.hi || (r.hi == s.hi && r.lo < s.lo)) c++;
+        c += bcarry[i];
+        s = r;
+    }
+    slo[threadIdx.x] = s.lo;
+    shi[threadIdx.x] = s.hi;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            u128 a = mk128(slo[threadIdx.x], shi[threadIdx.x]);
+            u128 b = mk128(slo[threadIdx.x + h], shi[threadIdx.x + h]);
+            u128 r = add128(a, b);
+            uint64_t cc = sc[threadIdx.x] + sc[threadIdx.x + h];
+            if (r.hi < a.hi || (r.hi == a.hi && r.lo < a.lo)) cc++;
+            slo[threadIdx.x] = r.lo;
+            shi[threadIdx.x] = r.hi;
+            sc[threadIdx.x] = cc;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && (sc[0] != 0 || (shi[0] >> 63))) atomicOr(flags, F_RANGE);
+}
+
+// ------------------------------------------------------------------------------------
+// Euler tour successor: arc 2x = down(parent x -> x), arc 2x+1 = up(x -> parent x)
+// ------------------------------------------------------------------------------------
+__global__ void k_succ(const int32_t *__restrict__ parent, const int32_t *__restrict__ cptr,
+                       const int32_t *__restrict__ clist, const int32_t *__restrict__ cslot,
+                       int32_t n, int32_t root, int32_t *__restrict__ succ)
+{
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    if (x == root) {
+        succ[2 * x] = -2;
+        succ[2 * x + 1] = -2;
+        return;
+    }
+    int32_t c0 = cptr[x], c1 = cptr[x + 1];
+    succ[2 * x] = (c0 < c1) ? 2 * clist[c0] : 2 * x + 1;
+    int32_t p = parent[x];
+    int32_t s = cslot[x] + 1;
+    int32_t up;
+    if (s < cptr[p + 1]) up = 2 * clist[s];
+    else if (p == root) up = GSS_END;
+    else up = 2 * p + 1;
+    succ[2 * x + 1] = up;
+}
+
+// ------------------------------------------------------------------------------------
+// list ranking
+// ------------------------------------------------------------------------------------
+struct LVal {
+    int32_t cnt, dep;
+    u128 D;
+};
+__device__ __forceinline__ LVal lv_add(LVal a, LVal b)
+{
+    LVal r;
+    r.cnt = a.cnt + b.cnt;
+    r.dep = a.dep + b.dep;
+    r.D = add128(a.D, b.D);
+    return r;
+}
+__device__ __forceinline__ LVal lv_sub(LVal a, LVal b)
+{
+    LVal r;
+    r.cnt = a.cnt - b.cnt;
+    r.dep = a.dep - b.dep;
+    r.D = sub128(a.D, b.D);
+    return r;
+}
+__device__ __forceinline__ LVal lv_zero()
+{
+    LVal r;
+    r.cnt = 0;
+    r.dep = 0;
+    r.D = mk128(0, 0);
+    return r;
+}
+
+__device__ __forceinline__ bool is_ruler(int32_t i, int32_t head, int32_t level)
+{
+    return i == head || (mix32((uint32_t)i * 0x9E3779B9u + (uint32_t)level * 0x7F4A7C15u) &
+                         (RULE_RATE - 1)) == 0;
+}
+
+// level-0 element value: arc i of vertex x = i>>1
+__device__ __forceinline__ LVal arc_val(int32_t i, const u128 *__restrict__ T)
+{
+    LVal v;
+    u128 t = T[i >> 1];
+    v.cnt = 1;
+    if (i & 1) {
+        v.dep = -1;
+        v.D = neg128(t);
+    } else {
+        v.dep = 1;
+        v.D = t;
+    }
+    return v;
+}
+
+struct ListLevel {
+    int32_t N;
+    const int32_t *nxt;   // successor (GSS_END terminates, -2 = not in the list)
+    const LVal *val;      // element values (null at level 0: arc values)
+    int32_t head;
+};
+
+__global__ void k_ruler_flags(int32_t N, const int32_t *__restrict__ nxt, int32_t head, int32_t level,
+                              int32_t *__restrict__ flag)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    flag[i] = (nxt[i] != -2 && is_ruler(i, head, level)) ? 1 : 0;
+}
+
+__global__ void k_ruler_list(int32_t N, const int32_t *__restrict__ nxt, int32_t head, int32_t level,
+                             const int32_t *__restrict__ rid, int32_t *__restrict__ relem)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (nxt[i] != -2 && is_ruler(i, head, level)) relem[rid[i]] = i;
+}
+
+// walk 1: sum of each ruler's sublist and the next ruler
+__global__ void k_walk1(int32_t R, const int32_t *__restrict__ relem, const int32_t *__restrict__ rid,
+                        const int32_t *__restrict__ nxt, const LVal *__restrict__ val,
+                        const u128 *__restrict__ T, int32_t head, int32_t level, int32_t N,
+                        int32_t *__restrict__ rnxt, LVal *__restrict__ rval, uint32_t *flags)
+{
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    int32_t i = relem[r];
+    LVal acc = val ? val[i] : arc_val(i, T);
+    int32_t j = nxt[i];
+    int32_t steps = 1;
+    while (j >= 0 && !is_ruler(j, head, level)) {
+        acc = lv_add(acc, val ? val[j] : arc_val(j, T));
+        j = nxt[j];
+        if (++steps > N) {
+            atomicOr(flags, F_NOT_TREE);
+            j = GSS_END;
+            break;
+        }
+    }
+    rnxt[r] = (j < 0) ? GSS_END : rid[j];
+    rval[r] = acc;
+}
+
+// walk 2 at levels >= 1: exclusive prefix of every element
+__global__ void k_walk2(int32_t R, const int32_t *__restrict__ relem, const int32_t *__restrict__ nxt,
+                        const LVal *__restrict__ val, const LVal *__restrict__ rpre, int32_t head,
+                        int32_t level, int32_t N, LVal *__restrict__ pre)
+{
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    int32_t i = relem[r];
+    LVal acc = rpre[r];
+    for (int32_t steps = 0; steps <= N; steps++) {
+        pre[i] = acc;
+        acc = lv_add(acc, val[i]);
+        int32_t j = nxt[i];
+        if (j < 0 || is_ruler(j, head, level)) break;
+        i = j;
+    }
+}
+
+// walk 2 at level 0: emit the Euler tour, depth, first position and root resistance
+__global__ void k_walk2_euler(int32_t R, const int32_t *__restrict__ relem,
+                              const int32_t *__restrict__ nxt, const u128 *__restrict__ T,
+                              const LVal *__restrict__ rpre, const int32_t *__restrict__ parent,
+                              int32_t head, int32_t N, int32_t *__restrict__ first,
+                              int32_t *__restrict__ depth, u128 *__restrict__ D,
+                              uint64_t *__restrict__ epk)
+{
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    int32_t i = relem[r];
+    LVal acc = rpre[r];
+    for (int32_t steps = 0; steps <= N; steps++) {
+        LVal v = arc_val(i, T);
+        LVal after = lv_add(acc, v);
+        int32_t x = i >> 1;
+        int32_t pos = acc.cnt + 1;  // Euler index of the vertex entered by this arc
+        if (i & 1) {
+            int32_t p = parent[x];
+            epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)p;
+        } else {
+            first[x] = pos;
+            depth[x] = after.dep;
+            D[x] = after.D;
+            epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)x;
+        }
+        acc = after;
+        int32_t j = nxt[i];
+        if (j < 0 || is_ruler(j, head, 0)) break;
+        i = j;
+    }
+}
+
+// base case: Wyllie pointer jumping in LDS, exclusive prefix from the head
+__global__ __launch_bounds__(BASE_MAX) void k_rank_base(int32_t N, const int32_t *__restrict__ nxt,
+                                                        const LVal *__restrict__ val, int32_t head,
+                                                        LVal *__restrict__ pre, uint32_t *flags)
+{
+    __shared__ int32_t snx[BASE_MAX];
+    __shared__ LVal ssuf[BASE_MAX];
+    int32_t i = threadIdx.x;
+    if (i < N) {
+        snx[i] = nxt[i];
+        ssuf[i] = val[i];
+    }
+    __syncthreads();
+    int rounds = 1;
+    while ((1 << rounds) < N + 1) rounds++;
+    rounds += 1;
+    for (int r = 0; r < rounds; r++) {
+        int32_t nx = -1;
+        LVal add = lv_zero();
+        bool upd = false;
+        if (i < N) {
+            nx = snx[i];
+            if (nx >= 0) {
+                add = ssuf[nx];
+                upd = true;
+                nx = snx[nx];
+            }
+        }
+        __syncthreads();
+        if (upd) {
+            ssuf[i] = lv_add(ssuf[i], add);
+            snx[i] = nx;
+        }
+        __syncthreads();
+    }
+    if (i < N && snx[i] >= 0) atomicOr(flags, F_NOT_TREE);
+    __syncthreads();
+    if (i < N) pre[i] = lv_sub(ssuf[head], ssuf[i]);
+}
+
+// recursive ranking of a level >= 1 list: pre[i] = exclusive prefix from the head
+static void rank_list(gss_ctx ctx, int32_t level, int32_t N, const int32_t *nxt, const LVal *val,
+                      int32_t head, LVal *pre)
+{
+    hipStream_t st = ctx->stream;
+    if (N <= BASE_MAX) {
+        hipLaunchKernelGGL(k_rank_base, dim3(1), dim3(BASE_MAX), 0, st, N, nxt, val, head, pre,
+                           ctx->d_flags);
+        HIP_OK(hipGetLastError());
+        return;
+    }
+    int32_t *rid = ctx->alloc<int32_t>(N + 1);
+    hipLaunchKernelGGL(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid);
+    int64_t R = scan_exclusive_i32(ctx, rid, N, true);
+    int32_t *relem = ctx->alloc<int32_t>(R + 1);
+    int32_t *rnxt = ctx->alloc<int32_t>(R + 1);
+    LVal *rval = ctx->alloc<LVal>(R + 1);
+    LVal *rpre = ctx->alloc<LVal>(R + 1);
+    hipLaunchKernelGGL(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid,
+                       relem);
+    hipLaunchKernelGGL(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, nxt,
+                       val, (const u128 *)nullptr, head, level, N, rnxt, rval, ctx->d_flags);
+    HIP_OK(hipGetLastError());
+    // the head is always a ruler; its ruler id is rid[head]
+    int32_t rhead = 0;
+    HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], rid + head, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    ctx->sync();
+    memcpy(&rhead, &ctx->h_counters[13], sizeof rhead);
+    rank_list(ctx, level + 1, (int32_t)R, rnxt, rval, rhead, rpre);
+    hipLaunchKernelGGL(k_walk2, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, nxt, val, rpre,
+                       head, level, N, pre);
+    HIP_OK(hipGetLastError());
+    ctx->free(rid);
+    ctx->free(relem);
+    ctx->free(rnxt);
+    ctx->free(rval);
+    ctx->free(rpre);
+}
+
+// ------------------------------------------------------------------------------------
+// RMQ over the Euler sequence: blocks of 64 positions, superblocks of 64 blocks
+// ------------------------------------------------------------------------------------
+// suffix-minimum masks of a run of up to 64 packed values; returns the run minimum
+__device__ __forceinline__ uint64_t run_masks(const uint64_t *__restrict__ v, int32_t cnt,
+                                              uint64_t *__restrict__ mask_out)
+{
+    uint64_t mask = 0;
+    for (int32_t i = 0; i < cnt; i++) {
+        uint64_t x = v[i];
+        while (mask) {
+            int q = 63 - __clzll((long long)mask);
+            if (v[q] >= x) mask &= ~(1ull << q);
+            else break;
+        }
+        mask |= 1ull << i;
+        mask_out[i] = mask;
+    }
+    return v[__ffsll((long long)mask) - 1];
+}
+
+__global__ void k_rmq_blocks(const uint64_t *__restrict__ epk, int32_t L, uint64_t *__restrict__ pmask,
+                             uint64_t *__restrict__ bmin, int32_t nb)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    int32_t s = b * 64;
+    int32_t cnt = min(64, L - s);
+    bmin[b] = run_masks(epk + s, cnt, pmask + s);
+}
+
+__global__ void k_rmq_super(const uint64_t *__restrict__ bmin, int32_t nb, uint64_t *__restrict__ bmask,
+                            uint64_t *__restrict__ sb0, int32_t nsb)
+{
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsb) return;
+    int32_t b = s * 64;
+    int32_t cnt = min(64, nb - b);
+    sb0[s] = run_masks(bmin + b, cnt, bmask + b);
+}
+
+__global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, int32_t nsb,
+                                                     int32_t levels)
+{
+    for (int32_t k = 1; k < levels; k++) {
+        const uint64_t *prev = st + (int64_t)(k - 1) * nsb;
+        uint64_t *cur = st + (int64_t)k * nsb;
+        int32_t half = 1 << (k - 1);
+        for (int32_t i = threadIdx.x; i + 2 * half <= nsb; i += blockDim.x) {
+            uint64_t a = prev[i], b = prev[i + half];
+            cur[i] = a < b ? a : b;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// off-tree edges (id order) and tree edge ids
+// ------------------------------------------------------------------------------------
+__global__ void k_offtree_count(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                const int32_t *__restrict__ parent, int32_t n, int64_t nnz,
+                                int32_t *__restrict__ cnt)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t k0 = t * ENT_ITEMS;
+    if (k0 >= nnz) return;
+    int32_t u = row_of(row_ptr, n, k0);
+    int32_t c = 0;
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        int64_t k = k0 + i;
+        if (k >= nnz) break;
+        while ((int64_t)row_ptr[u + 1] <= k) u++;
+        int32_t v = col[k];
+        if (v > u && parent[u] != v && parent[v] != u) c++;
+    }
+    cnt[t] = c;
+}
+
+__global__ void k_offtree_write(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                const double *__restrict__ w, const int32_t *__restrict__ parent,
+                                const int32_t *__restrict__ uptr, const int32_t *__restrict__ ufirst,
+                                int32_t n, int64_t nnz, const int32_t *__restrict__ off0,
+                                int32_t *__restrict__ off_id, int32_t *__restrict__ off_u,
+                                int32_t *__restrict__ off_v, double *__restrict__ off_w)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t k0 = t * ENT_ITEMS;
+    if (k0 >= nnz) return;
+    int32_t u = row_of(row_ptr, n, k0);
+    int32_t q = off0[t];
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        int64_t k = k0 + i;
+        if (k >= nnz) break;
+        while ((int64_t)row_ptr[u + 1] <= k) u++;
+        int32_t v = col[k];
+        if (v > u && parent[u] != v && parent[v] != u) {
+            off_id[q] = uptr[u] + (int32_t)(k - ufirst[u]);
+            off_u[q] = u;
+            off_v[q] = v;
+            off_w[q] = w[k];
+            q++;
+        }
+    }
+}
+
+__global__ void k_tree_eid(const int32_t *__restrict__ parent, const int32_t *__restrict__ row_ptr,
+                           const int32_t *__restrict__ col, const int32_t *__restrict__ uptr,
+                           const int32_t *__restrict__ ufirst, const int32_t *__restrict__ tpos,
+                           int32_t n, int32_t *__restrict__ tree_eid)
+{
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    int32_t p = parent[x];
+    if (p < 0) {
+        tree_eid[x] = -1;
+        return;
+    }
+    if (x < p) {
+        tree_eid[x] = uptr[x] + (tpos[x] - ufirst[x]);
+    } else {
+        int64_t k = find_in_row(col, row_ptr[p], row_ptr[p + 1], x);
+        tree_eid[x] = uptr[p] + (int32_t)(k - ufirst[p]);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_check_reached(const int32_t *__restrict__ first, int32_t n, uint32_t *flags)
+{
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n && first[x] < 0) atomicOr(flags, F_NOT_TREE);
+}
+
+__global__ void k_root_init(int32_t root, int32_t *first, int32_t *depth, u128 *D, uint64_t *epk)
+{
+    first[root] = 0;
+    depth[root] = 0;
+    D[root] = mk128(0, 0);
+    epk[0] = (uint64_t)(uint32_t)root;
+}
+
+// ------------------------------------------------------------------------------------
+// host orchestration
+// ------------------------------------------------------------------------------------
+static void fail(gss_status s, const char *msg) { throw gss_error{s, msg}; }
+
+void free_tree_arrays(gss_tree t)
+{
+    gss_ctx c = t->ctx;
+    void *ptrs[] = {t->uptr, t->ufirst, t->tpos, t->tree_eid, t->depth, t->D, t->first, t->epk,
+                    t->pmask, t->bmin, t->bmask, t->sbst, t->off_id, t->off_u, t->off_v, t->off_w};
+    for (void *p : ptrs) c->free(p);
+}
+
+void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
+{
+    hipStream_t st = ctx->stream;
+    const int32_t n = t->n;
+    const int64_t nnz = t->nnz;
+    const bool validate = !(flags & GSS_PREP_TRUSTED);
+    HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+
+    if (validate) {
+        hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
+                           ctx->d_flags);
+        uint32_t f = read_flags(ctx);
+        if (f) fail(status_from_flags(f), "malformed row_ptr");
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz, PB, ENT_ITEMS)), dim3(PB), 0, st,
+                               t->row_ptr, t->col, t->w, n, nnz, ctx->d_flags);
+        f = read_flags(ctx);
+        if (f & F_ARG) fail(GSS_ERR_ARG, "column index out of range");
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nnz, PB, ENT_ITEMS)), dim3(PB), 0, st, t->row_ptr,
+                               t->col, t->w, n, nnz, ctx->d_flags);
+    }
+    // edge numbering
+    t->ufirst = ctx->alloc<int32_t>(n);
+    t->uptr = ctx->alloc<int32_t>(n + 1);
+    hipLaunchKernelGGL(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, t->ufirst,
+                       t->uptr);
+    HIP_OK(hipMemsetAsync(t->uptr + n, 0, sizeof(int32_t), st));
+    int64_t m = scan_exclusive_i32(ctx, t->uptr, n + 1, true);
+    if (validate) {
+        uint32_t f = read_flags(ctx);
+        if (f) fail(status_from_flags(f), "invalid graph");
+        if (2 * m != nnz) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
+    }
+    t->m = m;
+
+    // tree checks
+    int32_t *ccnt = ctx->alloc<int32_t>(n + 1);
+    t->tpos = ctx->alloc<int32_t>(n);
+    HIP_OK(hipMemsetAsync(ccnt, 0, sizeof(int32_t) * (n + 1), st));
+    int64_t init_c[4] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40)};
+    memcpy(ctx->h_counters, init_c, sizeof init_c);
+    HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_tree_check, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col,
+                       t->w, n, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
+    HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    uint32_t f = read_flags(ctx);  // syncs
+    int64_t roots = ctx->h_counters[0];
+    t->root = (int32_t)ctx->h_counters[1];
+    int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
+    if (f & F_NOT_TREE || roots != 1) {
+        ctx->free(ccnt);
+        fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
+    }
+    bool tree_edge_missing = (f & F_TREE_EDGE) != 0;
+    bool range_bad = (f & F_RANGE) != 0;
+    if (n == 1) {
+        emin = emax = 0;
+    }
+    if (!range_bad && !tree_edge_missing && emax - emin > 74) range_bad = true;
+    if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
+    t->emin = (int32_t)emin;
+    t->scale = (int32_t)emin - 52;
+
+    // children CSR
+    int32_t *cptr = ccnt;  // scanned in place, cptr[n] = n-1
+    scan_exclusive_i32(ctx, cptr, n + 1, false);
+    int32_t *cfill = ctx->alloc<int32_t>(n);
+    int32_t *clist = ctx->alloc<int32_t>(n);
+    int32_t *cslot = ctx->alloc<int32_t>(n);
+    HIP_OK(hipMemsetAsync(cfill, 0, sizeof(int32_t) * n, st));
+    hipLaunchKernelGGL(k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr, cfill,
+                       clist, cslot);
+
+    // fixed-point terms and the 127-bit range check
+    u128 *T = ctx->alloc<u128>(n);
+    int64_t tb = grid_for(n, PB);
+    u128 *tbs = ctx->alloc<u128>(tb);
+    uint64_t *tbc = ctx->alloc<uint64_t>(tb);
+    const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
+    hipLaunchKernelGGL(k_terms, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, n, t->root, (int)emin,
+                       terms_ok, T, tbs, tbc);
+    hipLaunchKernelGGL(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
+
+    // Euler tour
+    t->L = 2 * n - 1;
+    t->first = ctx->alloc<int32_t>(n);
+    t->depth = ctx->alloc<int32_t>(n);
+    t->D = ctx->alloc<u128>(n);
+    t->epk = ctx->alloc<uint64_t>(t->L);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->first, (int64_t)n, -1);
+    hipLaunchKernelGGL(k_root_init, dim3(1), dim3(1), 0, st, t->root, t->first, t->depth, t->D, t->epk);
+    if (n > 1) {
+        int32_t N = 2 * n;
+        int32_t *succ = ctx->alloc<int32_t>(N);
+        hipLaunchKernelGGL(k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n,
+                           t->root, succ);
+        // head arc = down(first child of the root)
+        int32_t root_c0 = 0;
+        HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], cptr + t->root, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        ctx->sync();
+        memcpy(&root_c0, &ctx->h_counters[12], sizeof root_c0);
+        int32_t first_child = 0;
+        HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], clist + root_c0, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        ctx->sync();
+        memcpy(&first_child, &ctx->h_counters[12], sizeof first_child);
+        int32_t head = 2 * first_child;
+
+        int32_t *rid = ctx->alloc<int32_t>(N + 1);
+        hipLaunchKernelGGL(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid);
+        int64_t R = scan_exclusive_i32(ctx, rid, N, true);
+        int32_t *relem = ctx->alloc<int32_t>(R + 1);
+        int32_t *rnxt = ctx->alloc<int32_t>(R + 1);
+        LVal *rval = ctx->alloc<LVal>(R + 1);
+        LVal *rpre = ctx->alloc<LVal>(R + 1);
+        hipLaunchKernelGGL(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid, relem);
+        hipLaunchKernelGGL(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, succ,
+                           (const LVal *)nullptr, T, head, 0, N, rnxt, rval, ctx->d_flags);
+        int32_t rhead = 0;
+        HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], rid + head, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        ctx->sync();
+        memcpy(&rhead, &ctx->h_counters[13], sizeof rhead);
+        rank_list(ctx, 1, (int32_t)R, rnxt, rval, rhead, rpre);
+        hipLaunchKernelGGL(k_walk2_euler, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, succ, T,
+                           rpre, t->parent, head, N, t->first, t->depth, t->D, t->epk);
+        hipLaunchKernelGGL(k_check_reached, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->first, n, ctx->d_flags);
+        HIP_OK(hipGetLastError());
+        ctx->free(rid);
+        ctx->free(relem);
+        ctx->free(rnxt);
+        ctx->free(rval);
+        ctx->free(rpre);
+        ctx->free(succ);
+    }
+    f = read_flags(ctx);
+    ctx->free(cfill);
+    ctx->free(clist);
+    ctx->free(cslot);
+    ctx->free(ccnt);
+    ctx->free(T);
+    ctx->free(tbs);
+    ctx->free(tbc);
+    if (f & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array has a cycle");
+    if (tree_edge_missing) fail(GSS_ERR_TREE_EDGE, "a tree edge is not an edge of the graph");
+    if (range_bad || (f & F_RANGE)) fail(GSS_ERR_RANGE, "tree resistances exceed the 127-bit fixed point");
+
+    // RMQ structure
+    int32_t L = t->L;
+    t->nb = (L + 63) / 64;
+    t->nsb = (t->nb + 63) / 64;
+    int lv = 1;
+    while ((1 << lv) <= t->nsb) lv++;
+    t->sblevels = lv;
+    t->pmask = ctx->alloc<uint64_t>(L);
+    t->bmin = ctx->alloc<uint64_t>(t->nb);
+    t->bmask = ctx->alloc<uint64_t>(t->nb);
+    t->sbst = ctx->alloc<uint64_t>((int64_t)t->sblevels * t->nsb);
+    hipLaunchKernelGGL(k_rmq_blocks, dim3(grid_for(t->nb, PB)), dim3(PB), 0, st, t->epk, L, t->pmask, t->bmin,
+                       t->nb);
+    hipLaunchKernelGGL(k_rmq_super, dim3(grid_for(t->nsb, PB)), dim3(PB), 0, st, t->bmin, t->nb, t->bmask,
+                       t->sbst, t->nsb);
+    hipLaunchKernelGGL(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
+
+    // off-tree edges
+    t->M = t->m - (n - 1);
+    int64_t nthr = (nnz + ENT_ITEMS - 1) / ENT_ITEMS;
+    t->off_id = ctx->alloc<int32_t>(t->M + 1);
+    t->off_u = ctx->alloc<int32_t>(t->M + 1);
+    t->off_v = ctx->alloc<int32_t>(t->M + 1);
+    t->off_w = ctx->alloc<double>(t->M + 1);
+    if (nnz > 0) {
+        int32_t *ocnt = ctx->alloc<int32_t>(nthr + 1);
+        hipLaunchKernelGGL(k_offtree_count, dim3(grid_for(nthr, PB)), dim3(PB), 0, st, t->row_ptr, t->col,
+                           t->parent, n, nnz, ocnt);
+        int64_t M2 = scan_exclusive_i32(ctx, ocnt, nthr, true);
+        if (M2 != t->M) {
+            ctx->free(ocnt);
+            fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
+        }
+        hipLaunchKernelGGL(k_offtree_write, dim3(grid_for(nthr, PB)), dim3(PB), 0, st, t->row_ptr, t->col, t->w,
+                           t->parent, t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v,
+                           t->off_w);
+        ctx->free(ocnt);
+    }
+    t->tree_eid = ctx->alloc<int32_t>(n);
+    hipLaunchKernelGGL(k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col, t->uptr,
+                       t->ufirst, t->tpos, n, t->tree_eid);
+    HIP_OK(hipGetLastError());
+    ctx->sync();
+}

@@ -1,0 +1,202 @@
+"""Thin ctypes binding of libgss.so (include/gss.h).
+
+Argument marshalling only: every step of the recovery runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  There is no fallback: if the
+library is missing this module raises on load.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgss.so")
+
+GSS_OK, GSS_SHORT = 0, 1
+STATUS_NAMES = {0: "GSS_OK", 1: "GSS_SHORT", -1: "GSS_ERR_ARG", -2: "GSS_ERR_NOT_SIMPLE",
+                -3: "GSS_ERR_ASYM", -4: "GSS_ERR_WEIGHT", -5: "GSS_ERR_NOT_TREE",
+                -6: "GSS_ERR_TREE_EDGE", -7: "GSS_ERR_RANGE", -8: "GSS_ERR_HIP", -9: "GSS_ERR_OOM"}
+GSS_F_MASK_TREE = 1
+GSS_PREP_TRUSTED = 1
+SCHED_EDGECOUNT, SCHED_LEARNED = 0, 1
+
+# the symbols include/gss.h declares
+EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
+           "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca",
+           "gss_tree_num_edges", "gss_status_str", "gss_last_error"]
+
+
+class GSSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_int32), ("sched", ctypes.c_int32),
+                ("k_override", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n_offtree", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("n_recovered", ctypes.c_int64), ("n_subtasks", ctypes.c_int64),
+                ("largest_subtask", ctypes.c_int64), ("prefix_len", ctypes.c_int64),
+                ("n_arcs", ctypes.c_int64), ("passes", ctypes.c_int32), ("rounds", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Loads libgss.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2508_20403_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.gss_ctx_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.gss_ctx_set_stream.argtypes = [P, P]
+    lib.gss_ctx_destroy.argtypes = [P]
+    lib.gss_tree_prep.argtypes = [P, ctypes.POINTER(Csr), P, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.gss_tree_free.argtypes = [P]
+    lib.gss_recover.argtypes = [P, P, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Info)]
+    lib.gss_tree_export.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_int32)]
+    lib.gss_edge_lca.argtypes = [P, P, ctypes.c_int32, P, P]
+    lib.gss_tree_num_edges.argtypes = [P]
+    lib.gss_tree_num_edges.restype = ctypes.c_int64
+    lib.gss_status_str.argtypes = [ctypes.c_int32]
+    lib.gss_status_str.restype = ctypes.c_char_p
+    lib.gss_last_error.argtypes = [P]
+    lib.gss_last_error.restype = ctypes.c_char_p
+    for name in ("gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
+                 "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca"):
+        getattr(lib, name).restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """A gss_ctx bound to a torch stream on one device."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = load_library()
+        self.device = device
+        self.handle = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            st = self.lib.gss_ctx_create(device, _stream_handle(stream), ctypes.byref(self.handle))
+        if st != GSS_OK:
+            raise GSSError(st, self.lib.gss_last_error(None).decode())
+
+    def check(self, st):
+        if st not in (GSS_OK, GSS_SHORT):
+            raise GSSError(st, self.lib.gss_last_error(self.handle).decode())
+        return st
+
+    def set_stream(self, stream):
+        self.check(self.lib.gss_ctx_set_stream(self.handle, _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            self.lib.gss_ctx_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    """A prepared graph + spanning tree (gss_tree).  Keeps the device arrays alive."""
+
+    def __init__(self, ctx, row_ptr, col, w, parent, trusted=False):
+        self.ctx = ctx
+        self.arrays = (row_ptr, col, w, parent)  # the library borrows them
+        n = parent.numel()
+        csr = Csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                  w.data_ptr() if w.numel() else None)
+        self.n = n
+        self.handle = ctypes.c_void_p()
+        st = ctx.lib.gss_tree_prep(ctx.handle, ctypes.byref(csr), _ptr(parent),
+                                   GSS_PREP_TRUSTED if trusted else 0, ctypes.byref(self.handle))
+        ctx.check(st)
+        self.m = ctx.lib.gss_tree_num_edges(self.handle)
+
+    @classmethod
+    def from_graph(cls, ctx, g, device="cuda", trusted=False):
+        """Copies a synth.Graph to the device and prepares it."""
+        t = lambda a: torch.from_numpy(a).to(device)  # noqa: E731
+        return cls(ctx, t(g.row_ptr), t(g.col), t(g.w), t(g.parent), trusted)
+
+    def export(self):
+        dev = self.arrays[3].device
+        depth = torch.empty(self.n, dtype=torch.int32, device=dev)
+        dlo = torch.empty(self.n, dtype=torch.int64, device=dev)
+        dhi = torch.empty(self.n, dtype=torch.int64, device=dev)
+        scale = ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.gss_tree_export(self.handle, _ptr(depth), _ptr(dlo), _ptr(dhi),
+                                                    ctypes.byref(scale)))
+        return depth, dlo, dhi, scale.value
+
+    def edge_lca(self, beta):
+        dev = self.arrays[3].device
+        lca = torch.empty(self.m, dtype=torch.int32, device=dev)
+        bstar = torch.empty(self.m, dtype=torch.int32, device=dev)
+        self.ctx.check(self.ctx.lib.gss_edge_lca(self.ctx.handle, self.handle, int(beta), _ptr(lca),
+                                                 _ptr(bstar)))
+        return lca, bstar
+
+    def recover(self, alpha, beta, k_override=-1, sched=SCHED_EDGECOUNT, mask_tree=False,
+                want_order=True, want_stretch=False, out=None):
+        """Runs gss_recover.  Returns (status, mask, order, stretch, info dict)."""
+        dev = self.arrays[3].device
+        k = int(k_override) if k_override >= 0 else int(float(alpha) * float(self.n) // 1)
+        if out is None:
+            mask = torch.empty(max(self.m, 1), dtype=torch.uint8, device=dev)
+            order = torch.empty(max(k, 1), dtype=torch.int32, device=dev) if want_order else None
+            stretch = torch.empty(max(self.m, 1), dtype=torch.float64, device=dev) if want_stretch else None
+        else:
+            mask, order, stretch = out
+        p = Params(float(alpha), int(beta), int(sched), int(k_override),
+                   GSS_F_MASK_TREE if mask_tree else 0, 0)
+        info = Info()
+        st = self.ctx.lib.gss_recover(self.ctx.handle, self.handle, ctypes.byref(p), _ptr(mask),
+                                      _ptr(order), _ptr(stretch), ctypes.byref(info))
+        self.ctx.check(st)
+        return st, mask[: self.m], (order[:k] if order is not None else None), \
+            (stretch[: self.m] if stretch is not None else None), info.as_dict()
+
+    def free(self):
+        if self.handle:
+            self.ctx.lib.gss_tree_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,78 @@
+"""GPU path vs the serial oracle, element by element (bit-exact).
+
+Inputs are seeded and synthetic.  Small graphs span several 64-wide blocks, Euler
+blocks and hash tiles and end in ragged tails; the named workloads are the full
+64x64 grid and the 128^3 grid.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2508_20403_amd import gss, synth
+from tests.gpu_util import assert_same_recovery, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    ("rand_max", lambda s: synth.random_connected(300, 900, seed=s, alpha=0.1, beta=2)),
+    ("rand_tree", lambda s: synth.random_connected(517, 1400, seed=s, alpha=0.2, beta=3, tree="random")),
+    ("path", lambda s: synth.path_graph(200, 300, seed=s, alpha=0.5, beta=2)),
+    ("star", lambda s: synth.star_graph(150, 400, seed=s, alpha=0.5, beta=2)),
+    ("grid", lambda s: synth.grid((23, 17), 1.0, 100.0, seed=s, alpha=0.1, beta=2)),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tree_prep_matches_oracle(gpu_ctx, name, make, seed):
+    g = make(seed)
+    orc = run_oracle(g)
+    tree = gss.Tree.from_graph(gpu_ctx, g)
+    depth, dlo, dhi, scale = tree.export()
+    np.testing.assert_array_equal(depth.cpu().numpy(), orc.depth)
+    np.testing.assert_array_equal(dlo.cpu().numpy().view(np.uint64), orc.Dlo)
+    np.testing.assert_array_equal(dhi.cpu().numpy().view(np.uint64), orc.Dhi)
+    assert scale == orc.info["scale"]
+    for beta in (0, 1, 2, 5):
+        lca, bstar = tree.edge_lca(beta)
+        o2 = run_oracle(g, beta=beta)
+        np.testing.assert_array_equal(lca.cpu().numpy(), o2.lca)
+        np.testing.assert_array_equal(bstar.cpu().numpy(), o2.bstar)
+    tree.free()
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_recover_small(gpu_ctx, name, make, seed):
+    g = make(seed)
+    for beta in (0, 1, 2, 4):
+        for k in (-1, 1, 7, g.m):  # k=m forces extra passes and a short result
+            gpu = run_gpu(gpu_ctx, g, beta=beta, k_override=k)
+            orc = run_oracle(g, beta=beta, k_override=k)
+            assert_same_recovery(gpu, orc)
+
+
+def test_recover_grid2d_64(gpu_ctx):
+    g = synth.config("grid2d_64")
+    gpu = run_gpu(gpu_ctx, g)
+    orc = run_oracle(g)
+    assert gpu["info"]["k"] == 81 and orc.info["n_offtree"] == 3969
+    assert_same_recovery(gpu, orc)
+
+
+def test_recover_grid3d_128(gpu_ctx):
+    g = synth.config("grid3d_128")
+    gpu = run_gpu(gpu_ctx, g)
+    orc = run_oracle(g)
+    assert gpu["info"]["n_subtasks"] == orc.info["n_subtasks"]
+    assert gpu["info"]["largest_subtask"] == orc.info["largest_subtask"]
+    assert_same_recovery(gpu, orc)
+
+
+def test_recover_rmat14(gpu_ctx):
+    g = synth.config("rmat14")
+    for beta in (1, 2):
+        gpu = run_gpu(gpu_ctx, g, beta=beta)
+        orc = run_oracle(g, beta=beta)
+        assert_same_recovery(gpu, orc)
