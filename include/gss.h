@@ -138,6 +138,16 @@ gss_status gss_edge_lca(gss_ctx ctx, gss_tree tree, int32_t beta, int32_t *lca, 
 /* Returns the number of undirected edges m of a prepared tree, or -1. */
 int64_t gss_tree_num_edges(gss_tree tree);
 
+/* Live kernel timing (diagnostics): every launch of the selected kernels is bracketed by
+ * HIP events on the context stream and the elapsed times are summed per kernel.
+ * enable = 0 turns timing off; kernel_name NULL or "" selects every kernel.  Each call
+ * clears the accumulated figures. */
+gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name);
+/* Reads accumulated entry idx: its kernel name (copied into buf, NUL-terminated), total
+ * milliseconds and launch count.  Returns the number of entries, -1 on a bad argument. */
+int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
+                             int64_t *launches);
+
 /* Library-owned, static strings. */
 const char *gss_status_str(gss_status s);
 const char *gss_last_error(gss_ctx ctx);

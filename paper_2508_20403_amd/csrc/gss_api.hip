@@ -1,4 +1,7 @@
 // gss_api.hip -- the exported C ABI (declared in include/gss.h).
+#include <algorithm>
+#include <iterator>
+
 #include "gss_impl.h"
 
 namespace {
@@ -8,7 +11,9 @@ template <typename F>
 gss_status guarded(gss_ctx ctx, F &&f)
 {
     try {
-        return f();
+        gss_status s = f();
+        if (ctx && ctx->prof) ctx->prof_collect();
+        return s;
     } catch (const gss_error &e) {
         if (ctx) ctx->last_error = e.msg;
         g_err = e.msg;
@@ -143,11 +148,12 @@ gss_status gss_tree_export(gss_tree t, int32_t *depth, uint64_t *Dlo, uint64_t *
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         if (depth)
-            HIP_OK(hipMemcpyAsync(depth, t->depth, sizeof(int32_t) * t->n, hipMemcpyDeviceToDevice, ctx->stream));
-        if (Dlo) HIP_OK(hipMemcpy2DAsync(Dlo, sizeof(uint64_t), &t->D[0].lo, sizeof(u128), sizeof(uint64_t), t->n,
-                                         hipMemcpyDeviceToDevice, ctx->stream));
-        if (Dhi) HIP_OK(hipMemcpy2DAsync(Dhi, sizeof(uint64_t), &t->D[0].hi, sizeof(u128), sizeof(uint64_t), t->n,
-                                         hipMemcpyDeviceToDevice, ctx->stream));
+            HIP_OK(hipMemcpy2DAsync(depth, sizeof(int32_t), &t->vrec[0].depth, sizeof(VRec), sizeof(int32_t), t->n,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        if (Dlo) HIP_OK(hipMemcpy2DAsync(Dlo, sizeof(uint64_t), &t->vrec[0].D.lo, sizeof(VRec), sizeof(uint64_t),
+                                         t->n, hipMemcpyDeviceToDevice, ctx->stream));
+        if (Dhi) HIP_OK(hipMemcpy2DAsync(Dhi, sizeof(uint64_t), &t->vrec[0].D.hi, sizeof(VRec), sizeof(uint64_t),
+                                         t->n, hipMemcpyDeviceToDevice, ctx->stream));
         if (scale) *scale = t->scale;
         ctx->sync();
         return GSS_OK;
@@ -162,6 +168,37 @@ gss_status gss_edge_lca(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int
         edge_lca_impl(ctx, t, beta, lca, bstar);
         return GSS_OK;
     });
+}
+
+gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name)
+{
+    if (!ctx) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        ctx->sync();
+        ctx->prof_collect();
+        ctx->prof = enable != 0;
+        ctx->prof_filter = kernel_name ? kernel_name : "";
+        ctx->prof_acc.clear();
+        return GSS_OK;
+    });
+}
+
+int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
+                             int64_t *launches)
+{
+    if (!ctx) return -1;
+    int32_t count = (int32_t)ctx->prof_acc.size();
+    if (idx < 0 || idx >= count) return count;
+    auto it = ctx->prof_acc.begin();
+    std::advance(it, idx);
+    if (buf && buflen > 0) {
+        size_t k = std::min<size_t>((size_t)buflen - 1, it->first.size());
+        memcpy(buf, it->first.data(), k);
+        buf[k] = 0;
+    }
+    if (total_ms) *total_ms = it->second.first;
+    if (launches) *launches = it->second.second;
+    return count;
 }
 
 const char *gss_status_str(gss_status s)

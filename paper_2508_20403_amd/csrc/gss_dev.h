@@ -43,6 +43,15 @@ __host__ __device__ __forceinline__ u128 shl128(uint64_t m, int s)
     return mk128(0, m << (s - 64));
 }
 
+// per-vertex record read by the per-edge kernel with one 32-byte gather
+struct VRec {
+    u128 D;          // root resistance in fixed point (units of 2^scale)
+    int32_t first;   // first Euler position
+    int32_t depth;   // hops from the root
+    int32_t parent;  // -1 at the root
+    int32_t pad;
+};
+
 // Fixed-point term of a positive normal double t: t = mant * 2^(e-52); returns
 // mant << (e - emin), i.e. t in units of 2^(emin-52).  Requires e - emin in [0, 74].
 __device__ __forceinline__ u128 fixed_term(double t, int emin)

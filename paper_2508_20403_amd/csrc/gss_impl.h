@@ -37,7 +37,22 @@ struct dev_pool {
     void release_all();
 };
 
+struct prof_rec {
+    const char *name;
+    hipEvent_t a, b;
+};
+
 struct gss_ctx_s {
+    // live kernel timing with HIP events on the context stream (off by default)
+    bool prof = false;
+    std::string prof_filter;                       // empty: every kernel
+    std::vector<prof_rec> prof_pending;
+    std::vector<hipEvent_t> prof_events;           // free events
+    std::map<std::string, std::pair<double, int64_t>> prof_acc;  // name -> (ms, launches)
+    void prof_begin(const char *name);
+    void prof_end();
+    void prof_collect();                           // after a sync: accumulate elapsed times
+
     int device = 0;
     hipStream_t stream = nullptr;
     std::string last_error;
@@ -74,15 +89,17 @@ struct gss_tree_s {
     int32_t *tpos = nullptr;     // [n] CSR index of (x, parent x) in row x, -1 at root
     int32_t *tree_eid = nullptr; // [n] edge id of (x, parent x), -1 at root
     // tree / Euler tour
-    int32_t *depth = nullptr;    // [n]
-    u128 *D = nullptr;           // [n] root resistance, fixed point
-    int32_t *first = nullptr;    // [n] first Euler position
+    VRec *vrec = nullptr;        // [n] root resistance, first Euler position, depth, parent
     int32_t L = 0;               // Euler sequence length 2n-1
     uint64_t *epk = nullptr;     // [L] (depth << 32) | vertex
     uint64_t *pmask = nullptr;   // [L] in-block suffix-minimum masks
+    uint64_t *ppre = nullptr;    // [L] minimum from the block start to each position
+    uint64_t *psuf = nullptr;    // [L] minimum from each position to the block end
     int32_t nb = 0, nsb = 0, sblevels = 0;
     uint64_t *bmin = nullptr;    // [nb] block minima
     uint64_t *bmask = nullptr;   // [nb] in-superblock masks over block minima
+    uint64_t *bpre = nullptr;    // [nb] prefix minima of block minima within a superblock
+    uint64_t *bsuf = nullptr;    // [nb] suffix minima of block minima within a superblock
     uint64_t *sbst = nullptr;    // [sblevels * nsb] sparse table over superblock minima
     // off-tree edges in id order
     int32_t *off_id = nullptr, *off_u = nullptr, *off_v = nullptr;
@@ -101,6 +118,14 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t 
 int64_t scan_exclusive_i32(gss_ctx ctx, int32_t *data, int64_t n, bool want_total);
 uint32_t read_flags(gss_ctx ctx);
 gss_status status_from_flags(uint32_t f);
+
+// every kernel launch goes through this, so it can be timed with events when asked
+#define GSS_LAUNCH(kern, grid, block, shmem, stream, ...)               \
+    do {                                                                \
+        if (ctx->prof) ctx->prof_begin(#kern);                          \
+        hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__); \
+        if (ctx->prof) ctx->prof_end();                                 \
+    } while (0)
 
 inline unsigned grid_for(int64_t items, int block, int per_thread = 1)
 {

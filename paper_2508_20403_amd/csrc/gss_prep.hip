@@ -11,6 +11,8 @@
 //     (paper: Def. "Resistance distance", eq. RT, resistive weight 1/w),
 //   * a two-level in-block-mask RMQ over the Euler depth sequence (for LCA queries),
 //   * the list of off-tree edges in id order.
+#include <algorithm>
+
 #include "gss_impl.h"
 
 #define PB 256          // default block size
@@ -47,42 +49,123 @@ __device__ __forceinline__ int64_t find_in_row(const int32_t *__restrict__ col, 
 }
 
 // ------------------------------------------------------------------------------------
-// validation and edge numbering
+// entry tiles: a block owns ETILE consecutive CSR entries; the row of every entry of the
+// tile is written to LDS once, so threads then walk the entries coalesced (entry
+// base + i*PB + tid).  Reads of row_ptr are clamped so malformed input stays in bounds.
 // ------------------------------------------------------------------------------------
+#define ETILE (PB * ENT_ITEMS)
+
+__device__ __forceinline__ int64_t clamp_idx(int64_t x, int64_t lo, int64_t hi)
+{
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// fills srow[k - base] = row of entry k for the tile starting at base
+__device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
+                                               int64_t base, int32_t *srow)
+{
+    __shared__ int32_t sr[2];
+    if (threadIdx.x == 0) {
+        int64_t last = base + ETILE - 1;
+        if (last >= nnz) last = nnz - 1;
+        sr[0] = row_of(row_ptr, n, base);
+        sr[1] = row_of(row_ptr, n, last);
+    }
+    __syncthreads();
+    const int32_t r0 = sr[0], r1 = sr[1];
+    for (int i = threadIdx.x; i < ETILE; i += PB) srow[i] = r0;
+    __syncthreads();
+    const int64_t end = base + ETILE < nnz ? base + ETILE : nnz;
+    for (int32_t r = r0 + threadIdx.x; r <= r1; r += PB) {
+        int64_t lo = clamp_idx(row_ptr[r], base, end), hi = clamp_idx(row_ptr[r + 1], base, end);
+        for (int64_t k = lo; k < hi; k++) srow[k - base] = r;
+    }
+    __syncthreads();
+}
+
 __global__ void k_check_rowptr(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
                                uint32_t *flags)
 {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u > n) return;
     bool bad = false;
-    if (u == 0 && row_ptr[0] != 0) bad = true;
-    if (u < n && row_ptr[u + 1] < row_ptr[u]) bad = true;
-    if (u == n && (int64_t)row_ptr[n] != nnz) bad = true;
-    if (bad) atomicOr(flags, F_ARG);
+    if (u <= n) {
+        if (u == 0 && row_ptr[0] != 0) bad = true;
+        if (u < n && row_ptr[u + 1] < row_ptr[u]) bad = true;
+        if (u == n && (int64_t)row_ptr[n] != nnz) bad = true;
+        if ((int64_t)row_ptr[u] < 0 || (int64_t)row_ptr[u] > nnz) bad = true;
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_ARG);
 }
 
-__global__ void k_check_entries(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                const double *__restrict__ w, int32_t n, int64_t nnz, uint32_t *flags)
+// Symmetry is checked as a multiset identity: the upper entries (u,v,w) and the
+// transposed lower entries must be the same multiset.  Each entry contributes two
+// independent 64-bit hashes of (min, max, bits(w)), added with sign +1 (upper) or -1
+// (lower); a symmetric graph sums to zero, an asymmetric one to zero with probability
+// 2^-128.  Together with the equal triangle sizes this replaces a mirror search per entry.
+__device__ __forceinline__ void entry_hash(int32_t a, int32_t b, double w, uint64_t &h1, uint64_t &h2)
 {
-    int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * ENT_ITEMS;
-    if (k0 >= nnz) return;
-    int32_t u = row_of(row_ptr, n, k0);
+    uint64_t key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+    uint64_t wb = (uint64_t)__double_as_longlong(w);
+    h1 = mix64(key ^ mix64(wb + 0x9E3779B97F4A7C15ull));
+    h2 = mix64((key * 0xD1B54A32D192ED03ull) ^ mix64(wb ^ 0xA0761D6478BD642Full) ^ 0x8CB92BA72F3D8DD7ull);
+}
+
+// column range, strictly increasing rows, no self-loops, positive finite weights, and
+// the symmetric-multiset hash sums
+__global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ w, int32_t n, int64_t nnz,
+                                                      uint32_t *flags, unsigned long long *hsum)
+{
+    __shared__ int32_t srow[ETILE];
+    __shared__ uint64_t sh[2][PB / GSS_WAVE];
+    int64_t base = (int64_t)blockIdx.x * ETILE;
+    load_tile_rows(row_ptr, n, nnz, base, srow);
     uint32_t f = 0;
+    uint64_t h1 = 0, h2 = 0;
     for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = k0 + i;
+        int64_t k = base + (int64_t)i * PB + threadIdx.x;
         if (k >= nnz) break;
-        while ((int64_t)row_ptr[u + 1] <= k) u++;
+        int32_t u = srow[k - base];
         int32_t c = col[k];
         if (c < 0 || c >= n) {
             f |= F_ARG;
             continue;
         }
         if (c == u) f |= F_NOT_SIMPLE;
-        if (k > row_ptr[u] && col[k - 1] >= c) f |= F_NOT_SIMPLE;
+        int64_t rs = clamp_idx(row_ptr[u], 0, nnz);
+        if (k > rs && col[k - 1] >= c) f |= F_NOT_SIMPLE;
         double x = w[k];
         if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
+        uint64_t a1, a2;
+        entry_hash(min(u, c), max(u, c), x, a1, a2);
+        if (c > u) {
+            h1 += a1;
+            h2 += a2;
+        } else {
+            h1 -= a1;
+            h2 -= a2;
+        }
     }
-    if (f) atomicOr(flags, f);
+    for (int d = 32; d > 0; d >>= 1) {
+        f |= __shfl_xor(f, d, GSS_WAVE);
+        h1 += __shfl_xor(h1, d, GSS_WAVE);
+        h2 += __shfl_xor(h2, d, GSS_WAVE);
+    }
+    if (lane_id() == 0) {
+        sh[0][threadIdx.x / GSS_WAVE] = h1;
+        sh[1][threadIdx.x / GSS_WAVE] = h2;
+        if (f) atomicOr(flags, f);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < PB / GSS_WAVE; i++) {
+            h1 += sh[0][i];
+            h2 += sh[1][i];
+        }
+        if (h1) atomicAdd(&hsum[0], (unsigned long long)h1);
+        if (h2) atomicAdd(&hsum[1], (unsigned long long)h2);
+    }
 }
 
 // first upper entry of each row and the number of upper entries
@@ -101,62 +184,82 @@ __global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__res
     ucnt[u] = (int32_t)(end - lo);
 }
 
-// every upper entry (u,v,w) needs its mirror (v,u,w)
-__global__ void k_check_sym(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                            const double *__restrict__ w, int32_t n, int64_t nnz, uint32_t *flags)
+// parent checks, child counts, tree-edge positions and the exponent range of 1/w;
+// a fixed grid strides over the vertices and each block issues one set of atomics
+__global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ parent,
+                                                   const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ w,
+                                                   int32_t n, int32_t *__restrict__ ccnt,
+                                                   int32_t *__restrict__ tpos, uint32_t *flags, int64_t *counters)
 {
-    int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * ENT_ITEMS;
-    if (k0 >= nnz) return;
-    int32_t u = row_of(row_ptr, n, k0);
-    bool bad = false;
-    for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = k0 + i;
-        if (k >= nnz) break;
-        while ((int64_t)row_ptr[u + 1] <= k) u++;
-        int32_t v = col[k];
-        if (v <= u) continue;
-        int64_t j = find_in_row(col, row_ptr[v], row_ptr[v + 1], u);
-        if (j < 0 || w[j] != w[k]) bad = true;
+    __shared__ int32_t sred[5][PB / GSS_WAVE];
+    uint32_t f = 0;
+    int roots = 0;
+    int32_t root = INT32_MAX;
+    int emin = 1 << 30, emax = -(1 << 30);
+    for (int64_t xx = (int64_t)blockIdx.x * PB + threadIdx.x; xx < n; xx += (int64_t)gridDim.x * PB) {
+        int32_t x = (int32_t)xx;
+        int32_t p = parent[x];
+        int32_t tp = -1;
+        if (p == -1) {
+            roots++;
+            root = min(root, x);
+        } else if (p < 0 || p >= n || p == x) {
+            f |= F_NOT_TREE;
+        } else {
+            atomicAdd(&ccnt[p], 1);
+            int64_t k = find_in_row(col, row_ptr[x], row_ptr[x + 1], p);
+            if (k < 0) {
+                f |= F_TREE_EDGE;
+            } else {
+                tp = (int32_t)k;
+                double t = 1.0 / w[k];
+                uint64_t b = (uint64_t)__double_as_longlong(t);
+                int ef = (int)((b >> 52) & 0x7ff);
+                if (ef == 0 || ef == 0x7ff) {
+                    f |= F_RANGE;
+                } else {
+                    emin = min(emin, ef - 1023);
+                    emax = max(emax, ef - 1023);
+                }
+            }
+        }
+        tpos[x] = tp;
     }
-    if (bad) atomicOr(flags, F_ASYM);
-}
-
-// parent checks, child counts, tree-edge positions and the exponent range of 1/w
-__global__ void k_tree_check(const int32_t *__restrict__ parent, const int32_t *__restrict__ row_ptr,
-                             const int32_t *__restrict__ col, const double *__restrict__ w, int32_t n,
-                             int32_t *__restrict__ ccnt, int32_t *__restrict__ tpos, uint32_t *flags,
-                             int64_t *counters)
-{
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    int32_t p = parent[x];
-    tpos[x] = -1;
-    if (p == -1) {
-        atomicAdd((unsigned long long *)&counters[0], 1ull);
-        atomicMin((long long *)&counters[1], (long long)x);
-        return;
+    for (int d = 32; d > 0; d >>= 1) {
+        f |= __shfl_xor(f, d, GSS_WAVE);
+        roots += __shfl_xor(roots, d, GSS_WAVE);
+        root = min(root, __shfl_xor(root, d, GSS_WAVE));
+        emin = min(emin, __shfl_xor(emin, d, GSS_WAVE));
+        emax = max(emax, __shfl_xor(emax, d, GSS_WAVE));
     }
-    if (p < 0 || p >= n || p == x) {
-        atomicOr(flags, F_NOT_TREE);
-        return;
+    const int wid = threadIdx.x / GSS_WAVE;
+    if (lane_id() == 0) {
+        sred[0][wid] = (int32_t)f;
+        sred[1][wid] = roots;
+        sred[2][wid] = root;
+        sred[3][wid] = emin;
+        sred[4][wid] = emax;
     }
-    atomicAdd(&ccnt[p], 1);
-    int64_t k = find_in_row(col, row_ptr[x], row_ptr[x + 1], p);
-    if (k < 0) {
-        atomicOr(flags, F_TREE_EDGE);
-        return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < PB / GSS_WAVE; i++) {
+            f |= (uint32_t)sred[0][i];
+            roots += sred[1][i];
+            root = min(root, sred[2][i]);
+            emin = min(emin, sred[3][i]);
+            emax = max(emax, sred[4][i]);
+        }
+        if (f) atomicOr(flags, f);
+        if (roots) {
+            atomicAdd((unsigned long long *)&counters[0], (unsigned long long)roots);
+            atomicMin((long long *)&counters[1], (long long)root);
+        }
+        if (emin <= emax) {
+            atomicMin((long long *)&counters[2], (long long)emin);
+            atomicMax((long long *)&counters[3], (long long)emax);
+        }
     }
-    tpos[x] = (int32_t)k;
-    double t = 1.0 / w[k];
-    uint64_t b = (uint64_t)__double_as_longlong(t);
-    int ef = (int)((b >> 52) & 0x7ff);
-    if (ef == 0 || ef == 0x7ff) {
-        atomicOr(flags, F_RANGE);
-        return;
-    }
-    int e = ef - 1023;
-    atomicMin((long long *)&counters[2], (long long)e);
-    atomicMax((long long *)&counters[3], (long long)e);
 }
 
 __global__ void k_children_fill(const int32_t *__restrict__ parent, int32_t n,
@@ -391,8 +494,7 @@ __global__ void k_walk2(int32_t R, const int32_t *__restrict__ relem, const int3
 __global__ void k_walk2_euler(int32_t R, const int32_t *__restrict__ relem,
                               const int32_t *__restrict__ nxt, const u128 *__restrict__ T,
                               const LVal *__restrict__ rpre, const int32_t *__restrict__ parent,
-                              int32_t head, int32_t N, int32_t *__restrict__ first,
-                              int32_t *__restrict__ depth, u128 *__restrict__ D,
+                              int32_t head, int32_t N, VRec *__restrict__ vrec,
                               uint64_t *__restrict__ epk)
 {
     int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -408,9 +510,13 @@ __global__ void k_walk2_euler(int32_t R, const int32_t *__restrict__ relem,
             int32_t p = parent[x];
             epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)p;
         } else {
-            first[x] = pos;
-            depth[x] = after.dep;
-            D[x] = after.D;
+            VRec r;
+            r.D = after.D;
+            r.first = pos;
+            r.depth = after.dep;
+            r.parent = parent[x];
+            r.pad = 0;
+            vrec[x] = r;
             epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)x;
         }
         acc = after;
@@ -466,21 +572,21 @@ static void rank_list(gss_ctx ctx, int32_t level, int32_t N, const int32_t *nxt,
 {
     hipStream_t st = ctx->stream;
     if (N <= BASE_MAX) {
-        hipLaunchKernelGGL(k_rank_base, dim3(1), dim3(BASE_MAX), 0, st, N, nxt, val, head, pre,
+        GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_MAX), 0, st, N, nxt, val, head, pre,
                            ctx->d_flags);
         HIP_OK(hipGetLastError());
         return;
     }
     int32_t *rid = ctx->alloc<int32_t>(N + 1);
-    hipLaunchKernelGGL(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid);
+    GSS_LAUNCH(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid);
     int64_t R = scan_exclusive_i32(ctx, rid, N, true);
     int32_t *relem = ctx->alloc<int32_t>(R + 1);
     int32_t *rnxt = ctx->alloc<int32_t>(R + 1);
     LVal *rval = ctx->alloc<LVal>(R + 1);
     LVal *rpre = ctx->alloc<LVal>(R + 1);
-    hipLaunchKernelGGL(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid,
+    GSS_LAUNCH(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid,
                        relem);
-    hipLaunchKernelGGL(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, nxt,
+    GSS_LAUNCH(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, nxt,
                        val, (const u128 *)nullptr, head, level, N, rnxt, rval, ctx->d_flags);
     HIP_OK(hipGetLastError());
     // the head is always a ruler; its ruler id is rid[head]
@@ -489,7 +595,7 @@ static void rank_list(gss_ctx ctx, int32_t level, int32_t N, const int32_t *nxt,
     ctx->sync();
     memcpy(&rhead, &ctx->h_counters[13], sizeof rhead);
     rank_list(ctx, level + 1, (int32_t)R, rnxt, rval, rhead, rpre);
-    hipLaunchKernelGGL(k_walk2, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, nxt, val, rpre,
+    GSS_LAUNCH(k_walk2, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, nxt, val, rpre,
                        head, level, N, pre);
     HIP_OK(hipGetLastError());
     ctx->free(rid);
@@ -502,42 +608,82 @@ static void rank_list(gss_ctx ctx, int32_t level, int32_t N, const int32_t *nxt,
 // ------------------------------------------------------------------------------------
 // RMQ over the Euler sequence: blocks of 64 positions, superblocks of 64 blocks
 // ------------------------------------------------------------------------------------
-// suffix-minimum masks of a run of up to 64 packed values; returns the run minimum
-__device__ __forceinline__ uint64_t run_masks(const uint64_t *__restrict__ v, int32_t cnt,
-                                              uint64_t *__restrict__ mask_out)
+// One wave handles a run of up to 64 packed values, lane i holding value i (+inf past
+// the end).  Lane i computes: mask = positions q <= i whose value is strictly smaller
+// than every value in (q, i] (so the lowest set bit at or above a start s is the
+// position of the minimum of [s, i]); the prefix minimum of [0, i]; the suffix minimum
+// of [i, run end].
+__device__ __forceinline__ void wave_run(uint64_t v, uint64_t &mask, uint64_t &pre, uint64_t &suf)
 {
-    uint64_t mask = 0;
-    for (int32_t i = 0; i < cnt; i++) {
-        uint64_t x = v[i];
-        while (mask) {
-            int q = 63 - __clzll((long long)mask);
-            if (v[q] >= x) mask &= ~(1ull << q);
-            else break;
+    const int lane = lane_id();
+    uint64_t m = ~0ull;
+    mask = 0;
+    for (int q = 63; q >= 0; q--) {
+        uint64_t vq = __shfl(v, q, GSS_WAVE);
+        if (q == lane) {
+            mask |= 1ull << q;
+            m = vq;
+        } else if (q < lane) {
+            if (vq < m) mask |= 1ull << q;
+            m = vq < m ? vq : m;
         }
-        mask |= 1ull << i;
-        mask_out[i] = mask;
     }
-    return v[__ffsll((long long)mask) - 1];
+    pre = v;
+    suf = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t a = __shfl_up(pre, d, GSS_WAVE);
+        if (lane >= d) pre = a < pre ? a : pre;
+        uint64_t b = __shfl_down(suf, d, GSS_WAVE);
+        if (lane + d < 64) suf = b < suf ? b : suf;
+    }
 }
 
-__global__ void k_rmq_blocks(const uint64_t *__restrict__ epk, int32_t L, uint64_t *__restrict__ pmask,
-                             uint64_t *__restrict__ bmin, int32_t nb)
+#define RMQ_WPB 4
+// positions -> blocks of 64: masks, prefix and suffix minima, block minima
+__global__ __launch_bounds__(RMQ_WPB * 64) void k_rmq_blocks(const uint64_t *__restrict__ epk, int32_t L,
+                                                             uint64_t *__restrict__ pmask,
+                                                             uint64_t *__restrict__ ppre,
+                                                             uint64_t *__restrict__ psuf,
+                                                             uint64_t *__restrict__ bmin, int32_t nb)
 {
-    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    int32_t s = b * 64;
-    int32_t cnt = min(64, L - s);
-    bmin[b] = run_masks(epk + s, cnt, pmask + s);
+    const int lane = lane_id();
+    int32_t b = blockIdx.x * RMQ_WPB + threadIdx.x / 64;
+    if (b >= nb) return;  // whole wave
+    int32_t p = b * 64 + lane;
+    int32_t cnt = min(64, L - b * 64);
+    uint64_t v = (lane < cnt) ? epk[p] : ~0ull;
+    uint64_t mask, pre, suf;
+    wave_run(v, mask, pre, suf);
+    if (lane < cnt) {
+        pmask[p] = mask;
+        ppre[p] = pre;
+        psuf[p] = suf;
+    }
+    if (lane == cnt - 1) bmin[b] = pre;
 }
 
-__global__ void k_rmq_super(const uint64_t *__restrict__ bmin, int32_t nb, uint64_t *__restrict__ bmask,
-                            uint64_t *__restrict__ sb0, int32_t nsb)
+// blocks -> superblocks of 64 blocks: the same over block minima
+__global__ __launch_bounds__(RMQ_WPB * 64) void k_rmq_super(const uint64_t *__restrict__ bmin, int32_t nb,
+                                                            uint64_t *__restrict__ bmask,
+                                                            uint64_t *__restrict__ bpre,
+                                                            uint64_t *__restrict__ bsuf,
+                                                            uint64_t *__restrict__ sb0, int32_t nsb)
 {
-    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    int32_t s = blockIdx.x * RMQ_WPB + threadIdx.x / 64;
     if (s >= nsb) return;
-    int32_t b = s * 64;
-    int32_t cnt = min(64, nb - b);
-    sb0[s] = run_masks(bmin + b, cnt, bmask + b);
+    int32_t b = s * 64 + lane;
+    int32_t cnt = min(64, nb - s * 64);
+    uint64_t v = (lane < cnt) ? bmin[b] : ~0ull;
+    uint64_t mask, pre, suf;
+    wave_run(v, mask, pre, suf);
+    if (lane < cnt) {
+        bmask[b] = mask;
+        bpre[b] = pre;
+        bsuf[b] = suf;
+    }
+    if (lane == cnt - 1) sb0[s] = pre;
 }
 
 __global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, int32_t nsb,
@@ -558,49 +704,68 @@ __global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, 
 // ------------------------------------------------------------------------------------
 // off-tree edges (id order) and tree edge ids
 // ------------------------------------------------------------------------------------
-__global__ void k_offtree_count(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                const int32_t *__restrict__ parent, int32_t n, int64_t nnz,
-                                int32_t *__restrict__ cnt)
+// off-tree upper entries per tile
+__global__ __launch_bounds__(PB) void k_offtree_count(const int32_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const int32_t *__restrict__ parent, int32_t n, int64_t nnz,
+                                                      int32_t *__restrict__ cnt)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t k0 = t * ENT_ITEMS;
-    if (k0 >= nnz) return;
-    int32_t u = row_of(row_ptr, n, k0);
+    __shared__ int32_t srow[ETILE];
+    __shared__ int32_t sc[PB / GSS_WAVE];
+    int64_t base = (int64_t)blockIdx.x * ETILE;
+    load_tile_rows(row_ptr, n, nnz, base, srow);
     int32_t c = 0;
     for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = k0 + i;
+        int64_t k = base + (int64_t)i * PB + threadIdx.x;
         if (k >= nnz) break;
-        while ((int64_t)row_ptr[u + 1] <= k) u++;
+        int32_t u = srow[k - base];
         int32_t v = col[k];
         if (v > u && parent[u] != v && parent[v] != u) c++;
     }
-    cnt[t] = c;
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, GSS_WAVE);
+    if (lane_id() == 0) sc[threadIdx.x / GSS_WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < PB / GSS_WAVE; i++) c += sc[i];
+        cnt[blockIdx.x] = c;
+    }
 }
 
-__global__ void k_offtree_write(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                const double *__restrict__ w, const int32_t *__restrict__ parent,
-                                const int32_t *__restrict__ uptr, const int32_t *__restrict__ ufirst,
-                                int32_t n, int64_t nnz, const int32_t *__restrict__ off0,
-                                int32_t *__restrict__ off_id, int32_t *__restrict__ off_u,
-                                int32_t *__restrict__ off_v, double *__restrict__ off_w)
+// stable compaction: round i of a tile holds entries base+i*PB .. +PB-1 in thread order
+__global__ __launch_bounds__(PB) void k_offtree_write(const int32_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ w,
+                                                      const int32_t *__restrict__ parent,
+                                                      const int32_t *__restrict__ uptr,
+                                                      const int32_t *__restrict__ ufirst, int32_t n, int64_t nnz,
+                                                      const int32_t *__restrict__ off0,
+                                                      int32_t *__restrict__ off_id, int32_t *__restrict__ off_u,
+                                                      int32_t *__restrict__ off_v, double *__restrict__ off_w)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t k0 = t * ENT_ITEMS;
-    if (k0 >= nnz) return;
-    int32_t u = row_of(row_ptr, n, k0);
-    int32_t q = off0[t];
+    __shared__ int32_t srow[ETILE];
+    __shared__ int32_t lds[PB / GSS_WAVE + 1];
+    int64_t base = (int64_t)blockIdx.x * ETILE;
+    load_tile_rows(row_ptr, n, nnz, base, srow);
+    int32_t q = off0[blockIdx.x];
     for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = k0 + i;
-        if (k >= nnz) break;
-        while ((int64_t)row_ptr[u + 1] <= k) u++;
-        int32_t v = col[k];
-        if (v > u && parent[u] != v && parent[v] != u) {
-            off_id[q] = uptr[u] + (int32_t)(k - ufirst[u]);
-            off_u[q] = u;
-            off_v[q] = v;
-            off_w[q] = w[k];
-            q++;
+        int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        bool keep = false;
+        int32_t u = 0, v = 0;
+        if (k < nnz) {
+            u = srow[k - base];
+            v = col[k];
+            keep = v > u && parent[u] != v && parent[v] != u;
         }
+        int32_t tot;
+        int32_t pos = block_exclusive_scan<int32_t>(keep ? 1 : 0, lds, &tot);
+        if (keep) {
+            int32_t o = q + pos;
+            off_id[o] = uptr[u] + (int32_t)(k - ufirst[u]);
+            off_u[o] = u;
+            off_v[o] = v;
+            off_w[o] = w[k];
+        }
+        q += tot;
     }
 }
 
@@ -630,17 +795,35 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_check_reached(const int32_t *__restrict__ first, int32_t n, uint32_t *flags)
+__global__ void k_vrec_init(VRec *vrec, int32_t n)
 {
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < n && first[x] < 0) atomicOr(flags, F_NOT_TREE);
+    if (x >= n) return;
+    VRec r;
+    r.D = mk128(0, 0);
+    r.first = -1;
+    r.depth = 0;
+    r.parent = -1;
+    r.pad = 0;
+    vrec[x] = r;
 }
 
-__global__ void k_root_init(int32_t root, int32_t *first, int32_t *depth, u128 *D, uint64_t *epk)
+__global__ void k_check_reached(const VRec *__restrict__ vrec, int32_t n, uint32_t *flags)
 {
-    first[root] = 0;
-    depth[root] = 0;
-    D[root] = mk128(0, 0);
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = x < n && vrec[x].first < 0;
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_NOT_TREE);
+}
+
+__global__ void k_root_init(int32_t root, VRec *vrec, uint64_t *epk)
+{
+    VRec r;
+    r.D = mk128(0, 0);
+    r.first = 0;
+    r.depth = 0;
+    r.parent = -1;
+    r.pad = 0;
+    vrec[root] = r;
     epk[0] = (uint64_t)(uint32_t)root;
 }
 
@@ -652,9 +835,17 @@ static void fail(gss_status s, const char *msg) { throw gss_error{s, msg}; }
 void free_tree_arrays(gss_tree t)
 {
     gss_ctx c = t->ctx;
-    void *ptrs[] = {t->uptr, t->ufirst, t->tpos, t->tree_eid, t->depth, t->D, t->first, t->epk,
-                    t->pmask, t->bmin, t->bmask, t->sbst, t->off_id, t->off_u, t->off_v, t->off_w};
+    void *ptrs[] = {t->uptr,  t->ufirst, t->tpos,  t->tree_eid, t->vrec, t->epk,  t->pmask,
+                    t->ppre,  t->psuf,   t->bmin,  t->bmask,    t->bpre, t->bsuf, t->sbst,
+                    t->off_id, t->off_u, t->off_v, t->off_w};
     for (void *p : ptrs) c->free(p);
+}
+
+// head of the Euler list: the down arc of the root's first child
+__global__ void k_head(const int32_t *__restrict__ cptr, const int32_t *__restrict__ clist, int32_t root,
+                       int64_t *out)
+{
+    out[0] = 2 * (int64_t)clist[cptr[root]];
 }
 
 void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
@@ -665,32 +856,27 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     const bool validate = !(flags & GSS_PREP_TRUSTED);
     HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
 
+    // validation (memory-safe on malformed input) and edge numbering
     if (validate) {
-        hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
-                           ctx->d_flags);
-        uint32_t f = read_flags(ctx);
-        if (f) fail(status_from_flags(f), "malformed row_ptr");
+        HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, 2 * sizeof(int64_t), st));
+        GSS_LAUNCH(k_check_rowptr, dim3(grid_for(n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
+                   ctx->d_flags);
         if (nnz > 0)
-            hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz, PB, ENT_ITEMS)), dim3(PB), 0, st,
-                               t->row_ptr, t->col, t->w, n, nnz, ctx->d_flags);
-        f = read_flags(ctx);
-        if (f & F_ARG) fail(GSS_ERR_ARG, "column index out of range");
-        if (nnz > 0)
-            hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nnz, PB, ENT_ITEMS)), dim3(PB), 0, st, t->row_ptr,
-                               t->col, t->w, n, nnz, ctx->d_flags);
-    }
-    // edge numbering
-    t->ufirst = ctx->alloc<int32_t>(n);
-    t->uptr = ctx->alloc<int32_t>(n + 1);
-    hipLaunchKernelGGL(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, t->ufirst,
-                       t->uptr);
-    HIP_OK(hipMemsetAsync(t->uptr + n, 0, sizeof(int32_t), st));
-    int64_t m = scan_exclusive_i32(ctx, t->uptr, n + 1, true);
-    if (validate) {
+            GSS_LAUNCH(k_check_entries, dim3(grid_for(nnz, ETILE)), dim3(PB), 0, st, t->row_ptr, t->col, t->w, n,
+                       nnz, ctx->d_flags, (unsigned long long *)(ctx->d_counters + 10));
+        HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, 2 * sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
         uint32_t f = read_flags(ctx);
         if (f) fail(status_from_flags(f), "invalid graph");
-        if (2 * m != nnz) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
+        if (ctx->h_counters[10] != 0 || ctx->h_counters[11] != 0)
+            fail(GSS_ERR_ASYM, "the graph is not symmetric");
     }
+    t->ufirst = ctx->alloc<int32_t>(n);
+    t->uptr = ctx->alloc<int32_t>(n + 1);
+    GSS_LAUNCH(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, t->ufirst, t->uptr);
+    HIP_OK(hipMemsetAsync(t->uptr + n, 0, sizeof(int32_t), st));
+    int64_t m = scan_exclusive_i32(ctx, t->uptr, n + 1, true);
+    if (validate && 2 * m != nnz) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
     t->m = m;
 
     // tree checks
@@ -700,8 +886,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     int64_t init_c[4] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40)};
     memcpy(ctx->h_counters, init_c, sizeof init_c);
     HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_tree_check, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col,
-                       t->w, n, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
+    GSS_LAUNCH(k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st, t->parent, t->row_ptr,
+               t->col, t->w, n, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     uint32_t f = read_flags(ctx);  // syncs
     int64_t roots = ctx->h_counters[0];
@@ -713,9 +899,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     }
     bool tree_edge_missing = (f & F_TREE_EDGE) != 0;
     bool range_bad = (f & F_RANGE) != 0;
-    if (n == 1) {
-        emin = emax = 0;
-    }
+    if (n == 1) emin = emax = 0;
     if (!range_bad && !tree_edge_missing && emax - emin > 74) range_bad = true;
     if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
     t->emin = (int32_t)emin;
@@ -728,8 +912,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     int32_t *clist = ctx->alloc<int32_t>(n);
     int32_t *cslot = ctx->alloc<int32_t>(n);
     HIP_OK(hipMemsetAsync(cfill, 0, sizeof(int32_t) * n, st));
-    hipLaunchKernelGGL(k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr, cfill,
-                       clist, cslot);
+    GSS_LAUNCH(k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr, cfill, clist, cslot);
 
     // fixed-point terms and the 127-bit range check
     u128 *T = ctx->alloc<u128>(n);
@@ -737,52 +920,44 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     u128 *tbs = ctx->alloc<u128>(tb);
     uint64_t *tbc = ctx->alloc<uint64_t>(tb);
     const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
-    hipLaunchKernelGGL(k_terms, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, n, t->root, (int)emin,
-                       terms_ok, T, tbs, tbc);
-    hipLaunchKernelGGL(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
+    GSS_LAUNCH(k_terms, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, n, t->root, (int)emin, terms_ok, T, tbs,
+               tbc);
+    GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
 
     // Euler tour
     t->L = 2 * n - 1;
-    t->first = ctx->alloc<int32_t>(n);
-    t->depth = ctx->alloc<int32_t>(n);
-    t->D = ctx->alloc<u128>(n);
+    t->vrec = ctx->alloc<VRec>(n);
     t->epk = ctx->alloc<uint64_t>(t->L);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->first, (int64_t)n, -1);
-    hipLaunchKernelGGL(k_root_init, dim3(1), dim3(1), 0, st, t->root, t->first, t->depth, t->D, t->epk);
+    GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n);
+    GSS_LAUNCH(k_root_init, dim3(1), dim3(1), 0, st, t->root, t->vrec, t->epk);
     if (n > 1) {
         int32_t N = 2 * n;
         int32_t *succ = ctx->alloc<int32_t>(N);
-        hipLaunchKernelGGL(k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n,
-                           t->root, succ);
-        // head arc = down(first child of the root)
-        int32_t root_c0 = 0;
-        HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], cptr + t->root, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GSS_LAUNCH(k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n, t->root, succ);
+        GSS_LAUNCH(k_head, dim3(1), dim3(1), 0, st, cptr, clist, t->root, ctx->d_counters + 12);
+        HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], ctx->d_counters + 12, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
         ctx->sync();
-        memcpy(&root_c0, &ctx->h_counters[12], sizeof root_c0);
-        int32_t first_child = 0;
-        HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], clist + root_c0, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        ctx->sync();
-        memcpy(&first_child, &ctx->h_counters[12], sizeof first_child);
-        int32_t head = 2 * first_child;
+        int32_t head = (int32_t)ctx->h_counters[12];
 
         int32_t *rid = ctx->alloc<int32_t>(N + 1);
-        hipLaunchKernelGGL(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid);
+        GSS_LAUNCH(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid);
         int64_t R = scan_exclusive_i32(ctx, rid, N, true);
         int32_t *relem = ctx->alloc<int32_t>(R + 1);
         int32_t *rnxt = ctx->alloc<int32_t>(R + 1);
         LVal *rval = ctx->alloc<LVal>(R + 1);
         LVal *rpre = ctx->alloc<LVal>(R + 1);
-        hipLaunchKernelGGL(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid, relem);
-        hipLaunchKernelGGL(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, succ,
-                           (const LVal *)nullptr, T, head, 0, N, rnxt, rval, ctx->d_flags);
+        GSS_LAUNCH(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid, relem);
+        GSS_LAUNCH(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, succ,
+                   (const LVal *)nullptr, T, head, 0, N, rnxt, rval, ctx->d_flags);
         int32_t rhead = 0;
         HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], rid + head, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         ctx->sync();
         memcpy(&rhead, &ctx->h_counters[13], sizeof rhead);
         rank_list(ctx, 1, (int32_t)R, rnxt, rval, rhead, rpre);
-        hipLaunchKernelGGL(k_walk2_euler, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, succ, T,
-                           rpre, t->parent, head, N, t->first, t->depth, t->D, t->epk);
-        hipLaunchKernelGGL(k_check_reached, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->first, n, ctx->d_flags);
+        GSS_LAUNCH(k_walk2_euler, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, succ, T, rpre, t->parent,
+                   head, N, t->vrec, t->epk);
+        GSS_LAUNCH(k_check_reached, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, ctx->d_flags);
         HIP_OK(hipGetLastError());
         ctx->free(rid);
         ctx->free(relem);
@@ -811,39 +986,42 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     while ((1 << lv) <= t->nsb) lv++;
     t->sblevels = lv;
     t->pmask = ctx->alloc<uint64_t>(L);
+    t->ppre = ctx->alloc<uint64_t>(L);
+    t->psuf = ctx->alloc<uint64_t>(L);
     t->bmin = ctx->alloc<uint64_t>(t->nb);
     t->bmask = ctx->alloc<uint64_t>(t->nb);
+    t->bpre = ctx->alloc<uint64_t>(t->nb);
+    t->bsuf = ctx->alloc<uint64_t>(t->nb);
     t->sbst = ctx->alloc<uint64_t>((int64_t)t->sblevels * t->nsb);
-    hipLaunchKernelGGL(k_rmq_blocks, dim3(grid_for(t->nb, PB)), dim3(PB), 0, st, t->epk, L, t->pmask, t->bmin,
-                       t->nb);
-    hipLaunchKernelGGL(k_rmq_super, dim3(grid_for(t->nsb, PB)), dim3(PB), 0, st, t->bmin, t->nb, t->bmask,
-                       t->sbst, t->nsb);
-    hipLaunchKernelGGL(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
+    GSS_LAUNCH(k_rmq_blocks, dim3(grid_for(t->nb, RMQ_WPB)), dim3(RMQ_WPB * 64), 0, st, t->epk, L, t->pmask, t->ppre,
+               t->psuf, t->bmin, t->nb);
+    GSS_LAUNCH(k_rmq_super, dim3(grid_for(t->nsb, RMQ_WPB)), dim3(RMQ_WPB * 64), 0, st, t->bmin, t->nb, t->bmask,
+               t->bpre, t->bsuf, t->sbst, t->nsb);
+    GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
 
     // off-tree edges
     t->M = t->m - (n - 1);
-    int64_t nthr = (nnz + ENT_ITEMS - 1) / ENT_ITEMS;
     t->off_id = ctx->alloc<int32_t>(t->M + 1);
     t->off_u = ctx->alloc<int32_t>(t->M + 1);
     t->off_v = ctx->alloc<int32_t>(t->M + 1);
     t->off_w = ctx->alloc<double>(t->M + 1);
     if (nnz > 0) {
-        int32_t *ocnt = ctx->alloc<int32_t>(nthr + 1);
-        hipLaunchKernelGGL(k_offtree_count, dim3(grid_for(nthr, PB)), dim3(PB), 0, st, t->row_ptr, t->col,
-                           t->parent, n, nnz, ocnt);
-        int64_t M2 = scan_exclusive_i32(ctx, ocnt, nthr, true);
+        int64_t nblk = grid_for(nnz, ETILE);
+        int32_t *ocnt = ctx->alloc<int32_t>(nblk + 1);
+        GSS_LAUNCH(k_offtree_count, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr, t->col, t->parent, n, nnz,
+                   ocnt);
+        int64_t M2 = scan_exclusive_i32(ctx, ocnt, nblk, true);
         if (M2 != t->M) {
             ctx->free(ocnt);
             fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
         }
-        hipLaunchKernelGGL(k_offtree_write, dim3(grid_for(nthr, PB)), dim3(PB), 0, st, t->row_ptr, t->col, t->w,
-                           t->parent, t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v,
-                           t->off_w);
+        GSS_LAUNCH(k_offtree_write, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr, t->col, t->w, t->parent,
+                   t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v, t->off_w);
         ctx->free(ocnt);
     }
     t->tree_eid = ctx->alloc<int32_t>(n);
-    hipLaunchKernelGGL(k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col, t->uptr,
-                       t->ufirst, t->tpos, n, t->tree_eid);
+    GSS_LAUNCH(k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col, t->uptr, t->ufirst,
+               t->tpos, n, t->tree_eid);
     HIP_OK(hipGetLastError());
     ctx->sync();
 }

@@ -56,6 +56,50 @@ void dev_pool::release_all()
 }
 
 // ------------------------------------------------------------------------------------
+// live kernel timing
+// ------------------------------------------------------------------------------------
+void gss_ctx_s::prof_begin(const char *name)
+{
+    if (!prof_filter.empty() && prof_filter != name) {
+        prof_pending.push_back(prof_rec{nullptr, nullptr, nullptr});
+        return;
+    }
+    prof_rec r;
+    r.name = name;
+    for (hipEvent_t *e : {&r.a, &r.b}) {
+        if (prof_events.empty()) HIP_OK(hipEventCreate(e));
+        else {
+            *e = prof_events.back();
+            prof_events.pop_back();
+        }
+    }
+    HIP_OK(hipEventRecord(r.a, stream));
+    prof_pending.push_back(r);
+}
+
+void gss_ctx_s::prof_end()
+{
+    prof_rec &r = prof_pending.back();
+    if (r.name) HIP_OK(hipEventRecord(r.b, stream));
+}
+
+void gss_ctx_s::prof_collect()
+{
+    for (prof_rec &r : prof_pending) {
+        if (!r.name) continue;
+        float ms = 0.f;
+        HIP_OK(hipEventSynchronize(r.b));
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        auto &acc = prof_acc[r.name];
+        acc.first += ms;
+        acc.second += 1;
+        prof_events.push_back(r.a);
+        prof_events.push_back(r.b);
+    }
+    prof_pending.clear();
+}
+
+// ------------------------------------------------------------------------------------
 // flags
 // ------------------------------------------------------------------------------------
 uint32_t read_flags(gss_ctx ctx)
@@ -142,16 +186,53 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(int32_t *__restrict__
     }
 }
 
+// one workgroup scans the whole array in chunks (short arrays: one launch instead of three)
+#define SMALL_ITEMS 8
+__global__ __launch_bounds__(1024) void k_scan_single(int32_t *__restrict__ data, int64_t n,
+                                                      int64_t *__restrict__ total)
+{
+    __shared__ int64_t lds[1024 / GSS_WAVE + 1];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += 1024 * SMALL_ITEMS) {
+        int64_t base = c0 + (int64_t)threadIdx.x * SMALL_ITEMS;
+        int32_t v[SMALL_ITEMS];
+        int64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < SMALL_ITEMS; i++) {
+            v[i] = (base + i < n) ? data[base + i] : 0;
+            s += v[i];
+        }
+        int64_t tot;
+        int64_t ex = block_exclusive_scan<int64_t>(s, lds, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < SMALL_ITEMS; i++) {
+            if (base + i < n) data[base + i] = (int32_t)ex;
+            ex += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
 int64_t scan_exclusive_i32(gss_ctx ctx, int32_t *data, int64_t n, bool want_total)
 {
     if (n <= 0) return 0;
+    if (n <= 32 * 1024) {
+        GSS_LAUNCH(k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, data, n, ctx->d_counters + 14);
+        HIP_OK(hipGetLastError());
+        if (!want_total) return -1;
+        HIP_OK(hipMemcpyAsync(&ctx->h_counters[14], ctx->d_counters + 14, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        return ctx->h_counters[14];
+    }
     int64_t nb = (n + SCAN_BLOCK * SCAN_ITEMS - 1) / (SCAN_BLOCK * SCAN_ITEMS);
     int64_t *bsum = ctx->alloc<int64_t>(nb + 1);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, ctx->stream, data, n,
+    GSS_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, ctx->stream, data, n,
                        bsum);
-    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, ctx->stream, bsum, nb,
+    GSS_LAUNCH(k_scan_bsums, dim3(1), dim3(1024), 0, ctx->stream, bsum, nb,
                        ctx->d_counters + 14);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, ctx->stream, data, n,
+    GSS_LAUNCH(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, ctx->stream, data, n,
                        bsum);
     HIP_OK(hipGetLastError());
     ctx->free(bsum);

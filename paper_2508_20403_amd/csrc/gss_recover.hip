@@ -37,7 +37,7 @@
 enum : uint8_t { ST_UNDEC = 0, ST_CAND = 1, ST_MARK = 2 };
 
 struct RmqView {
-    const uint64_t *epk, *pmask, *bmin, *bmask, *sbst;
+    const uint64_t *epk, *pmask, *ppre, *psuf, *bmin, *bmask, *bpre, *bsuf, *sbst;
     int32_t nsb;
 };
 
@@ -52,9 +52,7 @@ __device__ __forceinline__ uint64_t rmq_blocks(const RmqView &q, int32_t b0, int
         uint64_t m = q.bmask[b1] & (~0ull << (b0 & 63));
         return q.bmin[(s0 << 6) + ctz64(m)];
     }
-    uint64_t ml = q.bmask[(s0 << 6) + 63] & (~0ull << (b0 & 63));
-    uint64_t best = q.bmin[(s0 << 6) + ctz64(ml)];
-    best = umin64(best, q.bmin[(s1 << 6) + ctz64(q.bmask[b1])]);
+    uint64_t best = umin64(q.bsuf[b0], q.bpre[b1]);
     int32_t a = s0 + 1, c = s1 - 1;
     if (a <= c) {
         int32_t len = c - a + 1;
@@ -73,9 +71,7 @@ __device__ __forceinline__ uint64_t rmq(const RmqView &q, int32_t i, int32_t j)
         uint64_t m = q.pmask[j] & (~0ull << (i & 63));
         return q.epk[(bi << 6) + ctz64(m)];
     }
-    uint64_t ml = q.pmask[(bi << 6) + 63] & (~0ull << (i & 63));
-    uint64_t best = q.epk[(bi << 6) + ctz64(ml)];
-    best = umin64(best, q.epk[(bj << 6) + ctz64(q.pmask[j])]);
+    uint64_t best = umin64(q.psuf[i], q.ppre[j]);
     if (bi + 1 <= bj - 1) best = umin64(best, rmq_blocks(q, bi + 1, bj - 1));
     return best;
 }
@@ -86,8 +82,7 @@ __device__ __forceinline__ uint64_t rmq(const RmqView &q, int32_t i, int32_t j)
 __global__ __launch_bounds__(RB) void k_edge_stretch(
     int64_t M, const int32_t *__restrict__ off_id, const int32_t *__restrict__ off_u,
     const int32_t *__restrict__ off_v, const double *__restrict__ off_w,
-    const int32_t *__restrict__ first, const int32_t *__restrict__ depth, const u128 *__restrict__ D,
-    RmqView q, int32_t scale, int32_t c, uint64_t *__restrict__ key, int32_t *__restrict__ lca,
+    const VRec *__restrict__ vrec, RmqView q, int32_t scale, int32_t c, uint64_t *__restrict__ key, int32_t *__restrict__ lca,
     uint8_t *__restrict__ bst, double *__restrict__ stretch_out, uint32_t *__restrict__ hist,
     int32_t *__restrict__ lcacnt, uint32_t *flags)
 {
@@ -98,13 +93,14 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
     int32_t l = -1;
     if (j < M) {
         int32_t u = off_u[j], v = off_v[j];
-        int32_t fu = first[u], fv = first[v];
+        VRec ru = vrec[u], rv = vrec[v];
+        int32_t fu = ru.first, fv = rv.first;
         uint64_t pk = (fu <= fv) ? rmq(q, fu, fv) : rmq(q, fv, fu);
         l = (int32_t)(uint32_t)pk;
         int32_t dl = (int32_t)(pk >> 32);
-        int32_t du = depth[u] - dl, dv = depth[v] - dl;
-        u128 Dl = D[l];
-        u128 R = add128(sub128(D[u], Dl), sub128(D[v], Dl));
+        int32_t du = ru.depth - dl, dv = rv.depth - dl;
+        u128 Dl = vrec[l].D;
+        u128 R = add128(sub128(ru.D, Dl), sub128(rv.D, Dl));
         double r;
         bool ok = u128_to_double_rne(R, scale, &r);
         double s = off_w[j] * r;
@@ -121,15 +117,16 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
         if (stretch_out) stretch_out[off_id[j]] = s;
         atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
     }
-    // subtask sizes: one atomic per distinct LCA in the wave
+    // subtask sizes: lanes sharing the first lane's LCA add once (skewed graphs put most
+    // edges on a few LCAs), the others add individually
     if (lcacnt) {
         uint64_t active = __ballot(l >= 0);
-        while (active) {
+        if (active) {
             int leader = ctz64(active);
             int32_t lv = __shfl(l, leader, GSS_WAVE);
             uint64_t same = __ballot(l == lv) & active;
             if (lane_id() == leader) atomicAdd(&lcacnt[lv], __popcll(same));
-            active &= ~same;
+            else if (l >= 0 && l != lv) atomicAdd(&lcacnt[l], 1);
         }
     }
     __syncthreads();
@@ -141,13 +138,28 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
 __global__ __launch_bounds__(RB) void k_lca_stats(const int32_t *__restrict__ lcacnt, int32_t n,
                                                   int64_t *counters)
 {
-    int32_t x = blockIdx.x * RB + threadIdx.x;
-    int32_t c = (x < n) ? lcacnt[x] : 0;
-    uint64_t nz = __ballot(c > 0);
-    int32_t mx = c;
-    for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d, GSS_WAVE));
+    __shared__ int32_t snz[RB / GSS_WAVE], smx[RB / GSS_WAVE];
+    int32_t nz = 0, mx = 0;
+    for (int64_t x = (int64_t)blockIdx.x * RB + threadIdx.x; x < n; x += (int64_t)gridDim.x * RB) {
+        int32_t c = lcacnt[x];
+        nz += c > 0;
+        mx = max(mx, c);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        nz += __shfl_xor(nz, d, GSS_WAVE);
+        mx = max(mx, __shfl_xor(mx, d, GSS_WAVE));
+    }
     if (lane_id() == 0) {
-        if (nz) atomicAdd((unsigned long long *)&counters[0], (unsigned long long)__popcll(nz));
+        snz[threadIdx.x / GSS_WAVE] = nz;
+        smx[threadIdx.x / GSS_WAVE] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < RB / GSS_WAVE; i++) {
+            nz += snz[i];
+            mx = max(mx, smx[i]);
+        }
+        atomicAdd((unsigned long long *)&counters[0], (unsigned long long)nz);
         atomicMax((long long *)&counters[1], (long long)mx);
     }
 }
@@ -561,8 +573,12 @@ static RmqView rmq_view(gss_tree t)
     RmqView q;
     q.epk = t->epk;
     q.pmask = t->pmask;
+    q.ppre = t->ppre;
+    q.psuf = t->psuf;
     q.bmin = t->bmin;
     q.bmask = t->bmask;
+    q.bpre = t->bpre;
+    q.bsuf = t->bsuf;
     q.sbst = t->sbst;
     q.nsb = t->nsb;
     return q;
@@ -580,7 +596,7 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
 {
     if (n <= 1) return;
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_key_varying, dim3(1), dim3(1024), 0, st, k, n, (uint64_t *)ctx->d_counters);
+    GSS_LAUNCH(k_key_varying, dim3(1), dim3(1024), 0, st, k, n, (uint64_t *)ctx->d_counters);
     read_counters(ctx, 1);
     uint64_t varying = (uint64_t)ctx->h_counters[0];
     int32_t ntiles = (int32_t)((n + RS_TILE - 1) / RS_TILE);
@@ -588,9 +604,9 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     int32_t *cnt = ctx->alloc<int32_t>(cn + 1);
     for (int shift = 0; shift < 64; shift += 8) {
         if (((varying >> shift) & 255ull) == 0) continue;
-        hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(RS_BLOCK), 0, st, k, n, shift, ntiles, cnt);
+        GSS_LAUNCH(k_rs_hist, dim3(ntiles), dim3(RS_BLOCK), 0, st, k, n, shift, ntiles, cnt);
         scan_exclusive_i32(ctx, cnt, cn, false);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(RS_BLOCK), 0, st, k, v, n, shift, ntiles, cnt, k2,
+        GSS_LAUNCH(k_rs_scatter, dim3(ntiles), dim3(RS_BLOCK), 0, st, k, v, n, shift, ntiles, cnt, k2,
                            v2);
         HIP_OK(hipGetLastError());
         std::swap(k, k2);
@@ -625,12 +641,12 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     // compaction (id order)
     int64_t nthr = (M + CHUNK - 1) / CHUNK;
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
-    hipLaunchKernelGGL(k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc);
+    GSS_LAUNCH(k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc);
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
     uint64_t *pk = ctx->alloc<uint64_t>(P + 1), *pk2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *pj = ctx->alloc<int32_t>(P + 1), *pj2 = ctx->alloc<int32_t>(P + 1);
-    hipLaunchKernelGGL(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc, pj, pk);
+    GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc, pj, pk);
     ctx->free(pc);
     radix_sort_pairs(ctx, pk, pj, pk2, pj2, P);
     ctx->free(pk);
@@ -642,7 +658,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     B.rb = ctx->alloc<uint8_t>(P + 1);
     B.ancU = ctx->alloc<int32_t>((int64_t)(c + 1) * P + 1);
     B.ancV = ctx->alloc<int32_t>((int64_t)(c + 1) * P + 1);
-    hipLaunchKernelGGL(k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_id, t->off_u,
+    GSS_LAUNCH(k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_id, t->off_u,
                        t->off_v, bst, t->parent, c, B.rid, B.rb, B.ancU, B.ancV);
     // hash join
     int64_t entries = 2 * (int64_t)(c + 1) * (c + 1) * P;
@@ -650,7 +666,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     while (cap < 2 * (uint64_t)entries) cap <<= 1;
     Slot *tab = ctx->alloc<Slot>(cap);
     HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(Slot) * cap, st));
-    hipLaunchKernelGGL(k_join_build, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV, tab, cap - 1);
+    GSS_LAUNCH(k_join_build, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV, tab, cap - 1);
     B.indeg = ctx->alloc<int32_t>(P + 1);
     int64_t arc_cap = std::max<int64_t>(4 * P, 1 << 16);
     for (;;) {
@@ -658,7 +674,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
         HIP_OK(hipMemsetAsync(ctx->d_counters, 0, sizeof(int64_t) * 2, st));
         HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
-        hipLaunchKernelGGL(k_join_probe, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.rb, B.ancU, B.ancV, tab,
+        GSS_LAUNCH(k_join_probe, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.rb, B.ancU, B.ancV, tab,
                            cap - 1, arcs, arc_cap, (unsigned long long *)ctx->d_counters, B.indeg, ctx->d_flags);
         HIP_OK(hipGetLastError());
         read_counters(ctx, 1);
@@ -672,14 +688,14 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         B.state = ctx->alloc<uint8_t>(P + 1);
         B.mcnt = ctx->alloc<int32_t>(P + 1);
         HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
-        hipLaunchKernelGGL(k_state_init, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.indeg, B.state);
+        GSS_LAUNCH(k_state_init, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.indeg, B.state);
         if (A > 0)
-            hipLaunchKernelGGL(k_resolve, dim3(1), dim3(1024), 0, st, A, arcs, B.indeg, B.state, B.mcnt,
+            GSS_LAUNCH(k_resolve, dim3(1), dim3(1024), 0, st, A, arcs, B.indeg, B.state, B.mcnt,
                                ctx->d_counters + 1);
         HIP_OK(hipGetLastError());
         int64_t nthr2 = (P + CHUNK - 1) / CHUNK;
         B.ccnt = ctx->alloc<int32_t>(nthr2 + 1);
-        hipLaunchKernelGGL(k_cand_count, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, P, B.state, B.ccnt);
+        GSS_LAUNCH(k_cand_count, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, P, B.state, B.ccnt);
         res.cand = scan_exclusive_i32(ctx, B.ccnt, nthr2, true);
         read_counters(ctx, 2);
         res.rounds = A > 0 ? ctx->h_counters[1] : 0;
@@ -704,10 +720,10 @@ static uint64_t select_threshold(gss_ctx ctx, gss_tree t, const uint64_t *key, u
     for (int lv = 0; lv < 6; lv++) {
         if (lv > 0 || !hist_ready) {
             HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
-            hipLaunchKernelGGL(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key,
+            GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key,
                                t->M, shifts[lv], widths[lv], pmask, pval, hist);
         }
-        hipLaunchKernelGGL(k_pick_bucket, dim3(1), dim3(1024), 0, st, hist, widths[lv], want - above,
+        GSS_LAUNCH(k_pick_bucket, dim3(1), dim3(1024), 0, st, hist, widths[lv], want - above,
                            ctx->d_counters);
         HIP_OK(hipGetLastError());
         read_counters(ctx, 3);
@@ -734,7 +750,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prm, uint8_t 
     HIP_OK(hipMemsetAsync(mask, 0, (size_t)m, st));
     if (stretch) HIP_OK(hipMemsetAsync(stretch, 0, sizeof(double) * (size_t)m, st));
     if (prm->flags & GSS_F_MASK_TREE)
-        hipLaunchKernelGGL(k_mask_tree, dim3(grid_for(n, RB)), dim3(RB), 0, st, t->tree_eid, n, mask);
+        GSS_LAUNCH(k_mask_tree, dim3(grid_for(n, RB)), dim3(RB), 0, st, t->tree_eid, n, mask);
     HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
 
     uint64_t *key = ctx->alloc<uint64_t>(M + 1);
@@ -745,14 +761,15 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prm, uint8_t 
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
     if (M > 0)
-        hipLaunchKernelGGL(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u,
-                           t->off_v, t->off_w, t->first, t->depth, t->D, rmq_view(t), t->scale, c, key, lca, bst,
+        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u,
+                           t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
                            stretch, hist, lcacnt, ctx->d_flags);
     HIP_OK(hipGetLastError());
     int64_t init2[2] = {0, 0};
     memcpy(ctx->h_counters + 2, init2, sizeof init2);
     HIP_OK(hipMemcpyAsync(ctx->d_counters + 2, ctx->h_counters + 2, sizeof init2, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_lca_stats, dim3(grid_for(n, RB)), dim3(RB), 0, st, lcacnt, n, ctx->d_counters + 2);
+    GSS_LAUNCH(k_lca_stats, dim3(std::min<int64_t>(grid_for(n, RB), 1024)), dim3(RB), 0, st, lcacnt, n,
+               ctx->d_counters + 2);
     read_counters(ctx, 4);
     int64_t nsub = ctx->h_counters[2], largest = ctx->h_counters[3];
     uint32_t f = read_flags(ctx);
@@ -789,7 +806,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prm, uint8_t 
         }
         int64_t take = std::min<int64_t>(r.cand, need);
         int64_t nthr2 = (r.P + CHUNK - 1) / CHUNK;
-        hipLaunchKernelGGL(k_cand_write, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, r.P, B.state, B.ccnt, take,
+        GSS_LAUNCH(k_cand_write, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, r.P, B.state, B.ccnt, take,
                            B.rid, B.sj, order, nrec, mask, key);
         HIP_OK(hipGetLastError());
         B.release(ctx);
@@ -823,7 +840,7 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     hipStream_t st = ctx->stream;
     const int64_t M = t->M, m = t->m;
     if (lca_out) {
-        hipLaunchKernelGGL(k_fill_i32_r, dim3(grid_for(m, RB)), dim3(RB), 0, st, lca_out, m, -1);
+        GSS_LAUNCH(k_fill_i32_r, dim3(grid_for(m, RB)), dim3(RB), 0, st, lca_out, m, -1);
     }
     if (b_out) HIP_OK(hipMemsetAsync(b_out, 0, sizeof(int32_t) * (size_t)m, st));
     uint64_t *key = ctx->alloc<uint64_t>(M + 1);
@@ -832,10 +849,10 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     uint32_t *hist = ctx->alloc<uint32_t>(SEL_BINS);
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (M > 0) {
-        hipLaunchKernelGGL(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u,
-                           t->off_v, t->off_w, t->first, t->depth, t->D, rmq_view(t), t->scale, beta, key, lca, bst,
+        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u,
+                           t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta, key, lca, bst,
                            (double *)nullptr, hist, (int32_t *)nullptr, ctx->d_flags);
-        hipLaunchKernelGGL(k_edge_lca_out, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, lca, bst,
+        GSS_LAUNCH(k_edge_lca_out, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, lca, bst,
                            lca_out, b_out);
     }
     HIP_OK(hipGetLastError());

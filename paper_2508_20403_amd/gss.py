@@ -25,7 +25,8 @@ SCHED_EDGECOUNT, SCHED_LEARNED = 0, 1
 # the symbols include/gss.h declares
 EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
            "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca",
-           "gss_tree_num_edges", "gss_status_str", "gss_last_error"]
+           "gss_tree_num_edges", "gss_status_str", "gss_last_error", "gss_ctx_profile",
+           "gss_ctx_profile_read"]
 
 
 class GSSError(RuntimeError):
@@ -81,6 +82,11 @@ def load_library(path=LIB_PATH):
     lib.gss_status_str.restype = ctypes.c_char_p
     lib.gss_last_error.argtypes = [P]
     lib.gss_last_error.restype = ctypes.c_char_p
+    lib.gss_ctx_profile.argtypes = [P, ctypes.c_int32, ctypes.c_char_p]
+    lib.gss_ctx_profile.restype = ctypes.c_int32
+    lib.gss_ctx_profile_read.argtypes = [P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.gss_ctx_profile_read.restype = ctypes.c_int32
     for name in ("gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
                  "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca"):
         getattr(lib, name).restype = ctypes.c_int32
@@ -117,6 +123,23 @@ class Context:
 
     def set_stream(self, stream):
         self.check(self.lib.gss_ctx_set_stream(self.handle, _stream_handle(stream)))
+
+    def profile(self, enable=True, kernel=None):
+        """Starts (or stops) live HIP-event timing of one kernel (None: all kernels)."""
+        self.check(self.lib.gss_ctx_profile(self.handle, 1 if enable else 0,
+                                            kernel.encode() if kernel else None))
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} accumulated since profile()."""
+        out = {}
+        count = self.lib.gss_ctx_profile_read(self.handle, 0, None, 0, None, None)
+        buf = ctypes.create_string_buffer(128)
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        for i in range(max(count, 0)):
+            self.lib.gss_ctx_profile_read(self.handle, i, buf, 128, ctypes.byref(ms), ctypes.byref(n))
+            out[buf.value.decode()] = (ms.value, n.value)
+        return out
 
     def close(self):
         if self.handle:

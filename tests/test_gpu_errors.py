@@ -1,0 +1,96 @@
+"""Error paths of the GPU library: the same invalid inputs as the oracle's status-code
+test must give the same status through the C ABI (nothing here faults: every input is
+rejected by the library's own checks before it could be used to index memory)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2508_20403_amd import gss, synth
+from tests.test_oracle_pins import graph_from_json
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_status(ctx, g, *, row_ptr=None, col=None, w=None, parent=None, alpha=None, beta=None):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rp = t(g.row_ptr if row_ptr is None else row_ptr)
+    c = t(g.col if col is None else col)
+    ww = t(g.w if w is None else w)
+    p = t(g.parent if parent is None else parent)
+    print(f"[gpu-err] {g.name}", flush=True)
+    try:
+        tree = gss.Tree(ctx, rp, c, ww, p)
+    except gss.GSSError as e:
+        return e.status
+    try:
+        st = tree.recover(g.alpha if alpha is None else alpha, g.beta if beta is None else beta)[0]
+    except gss.GSSError as e:
+        st = e.status
+    tree.free()
+    return st
+
+
+def both(ctx, g, **kw):
+    o = oracle.recover(**{**dict(n=g.n, row_ptr=g.row_ptr, col=g.col, w=g.w, parent=g.parent, alpha=g.alpha,
+                                 beta=g.beta), **kw}).status
+    return gpu_status(ctx, g, **kw), o
+
+
+def test_error_statuses_match_oracle(gpu_ctx):
+    g = synth.random_connected(30, 40, seed=9)
+    rp, col, w, par = g.row_ptr, g.col, g.w, g.parent
+    cases = []
+    cases.append(dict(alpha=1.5))
+    cases.append(dict(beta=-1))
+    c2 = col.copy(); c2[3] = g.n + 5; cases.append(dict(col=c2))
+    c2 = col.copy(); c2[rp[4]] = 4; cases.append(dict(col=c2))
+    r0 = rp[7]; c2 = col.copy(); c2[r0], c2[r0 + 1] = c2[r0 + 1], c2[r0]; cases.append(dict(col=c2))
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        w2 = w.copy(); w2[5] = bad; cases.append(dict(w=w2))
+    w2 = w.copy(); w2[rp[2]] *= 2.0; cases.append(dict(w=w2))
+    x = int(np.flatnonzero(par >= 0)[0])
+    p2 = par.copy(); p2[x] = -1; cases.append(dict(parent=p2))
+    ch = [v for v in range(g.n) if par[v] >= 0 and par[par[v]] >= 0][0]
+    p2 = par.copy(); p2[par[ch]] = ch; cases.append(dict(parent=p2))
+    p2 = par.copy(); p2[x] = g.n; cases.append(dict(parent=p2))
+    root = int(np.flatnonzero(par < 0)[0])
+    leaf = [v for v in range(g.n) if v != root and not np.any(par == v)][0]
+    nb = set(col[rp[leaf]:rp[leaf + 1]].tolist())
+    target = [v for v in range(g.n) if v not in nb and v != leaf][0]
+    p2 = par.copy(); p2[leaf] = target; cases.append(dict(parent=p2))
+    rp2 = rp.copy(); rp2[5] = rp2[6] + 1; cases.append(dict(row_ptr=rp2))
+    for kw in cases:
+        got, want = both(gpu_ctx, g, **kw)
+        assert got == want and want < 0, (list(kw), got, want)
+
+
+def test_range_error(gpu_ctx):
+    edges = [[0, 1, 1.0], [1, 2, 2.0 ** 80], [2, 3, 1.0], [3, 4, 1.0], [0, 4, 1.0]]
+    g = graph_from_json(5, edges, [-1, 0, 1, 2, 3])
+    assert gpu_status(gpu_ctx, g) == oracle.recover(g).status == -7
+
+
+def test_missing_mirror_is_asym(gpu_ctx):
+    """Drop one lower entry: triangle sizes differ."""
+    g = synth.random_connected(40, 60, seed=3)
+    rp, col, w = g.row_ptr.copy(), g.col.copy(), g.w.copy()
+    u = 10
+    r0, r1 = rp[u], rp[u + 1]
+    lower = [k for k in range(r0, r1) if col[k] < u]
+    assert lower
+    k = lower[0]
+    col2 = np.delete(col, k)
+    w2 = np.delete(w, k)
+    rp2 = rp.copy(); rp2[u + 1:] -= 1
+    o = oracle.recover(n=g.n, row_ptr=rp2, col=col2, w=w2, parent=g.parent, alpha=g.alpha, beta=g.beta).status
+    assert o == -3
+    assert gpu_status(gpu_ctx, g, row_ptr=rp2, col=col2, w=w2) == -3
+
+
+def test_tree_only_and_tiny(gpu_ctx):
+    for n in (1, 2, 5):
+        g = synth.random_connected(n, 0, seed=1) if n > 1 else synth.Graph(
+            1, np.zeros(2, np.int32), np.zeros(0, np.int32), np.zeros(0), np.array([-1], np.int32), 0, 0.5, 2, "one")
+        st = gpu_status(gpu_ctx, g)
+        assert st == oracle.recover(g, k_override=-1).status
