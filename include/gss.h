@@ -69,6 +69,8 @@ typedef struct {
 
 /* gss_params.flags */
 #define GSS_F_MASK_TREE 1u     /* also set mask[] = 1 on tree edges (mask = sparsifier P) */
+#define GSS_F_RECORD 2u        /* append per-subtask features and measured cycles of the work-
+                                  queue kernel to the context trace (cost-model training data) */
 
 /* gss_params.sched: order in which the subtask work queue is drained (never changes
  * the output). */
@@ -137,6 +139,40 @@ gss_status gss_edge_lca(gss_ctx ctx, gss_tree tree, int32_t beta, int32_t *lca, 
 
 /* Returns the number of undirected edges m of a prepared tree, or -1. */
 int64_t gss_tree_num_edges(gss_tree tree);
+
+/* ---- subtask scheduling and the learned cost model --------------------------------
+ * The recovery groups the resolved prefix of the criticality order into LCA subtasks
+ * (paper: Lemma "strictly similar edges share their LCA", Alg. 1 Step 3).  Subtasks of at
+ * most local_max edges are drained by a persistent work-queue kernel, one wavefront per
+ * subtask; larger ones use a global hash join.  The queue runs longest-predicted first:
+ * by edge count (GSS_SCHED_EDGECOUNT), or by a 12-64-64-1 ReLU network of 12 subtask
+ * features (GSS_SCHED_LEARNED, BF16 matrix-core inference).  The order never changes the
+ * output.  Weights are GSS_COSTMODEL_FLOATS floats: W1[64][12] b1[64] W2[64][64] b2[64]
+ * W3[64] b3, then the feature mean[12] and standard deviation[12]. */
+#define GSS_NFEAT 12
+#define GSS_COSTMODEL_FLOATS 5081
+#define GSS_COSTMODEL_PARAMS 5057
+
+/* Sets the work-queue limits: subtasks of at most local_max edges (1..1024) use the
+ * persistent kernel, which runs local_blocks workgroups of four wavefronts. */
+gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks);
+/* Copies up to cap rows of the context trace (host arrays feat[cap][12], cycles[cap],
+ * size[cap]; any may be NULL) and returns the number of rows held, or -1. */
+int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int64_t cap);
+gss_status gss_trace_clear(gss_ctx ctx);
+/* Trains the cost model on the GPU (FP32 forward/backward/Adam kernels, one workgroup,
+ * device-resident for all epochs) from host arrays feat[n][12] and cycles[n]; the target
+ * is log2(cycles).  loss: host [epochs] mean squared error per epoch, or NULL. */
+gss_status gss_costmodel_train(gss_ctx ctx, const float *feat, const double *cycles, int64_t n, int32_t epochs,
+                               float lr, uint64_t seed, float *loss);
+/* Loads / saves the weights (host arrays of GSS_COSTMODEL_FLOATS floats). */
+gss_status gss_costmodel_load(gss_ctx ctx, const float *weights);
+gss_status gss_costmodel_save(gss_ctx ctx, float *weights);
+/* BF16 inference: out[i] = predicted log2(cycles) of device feat[i][12], device out[n]. */
+gss_status gss_costmodel_predict(gss_ctx ctx, const float *feat, int64_t n, float *out);
+/* FP32 gradient of the mean squared error of host batch x[nb][12] (raw features), targets
+ * y[nb] (1 <= nb <= 64) at the current weights: grad host [GSS_COSTMODEL_PARAMS]. */
+gss_status gss_costmodel_grad(gss_ctx ctx, const float *x, const float *y, int32_t nb, float *grad, float *loss);
 
 /* Live kernel timing (diagnostics): every launch of the selected kernels is bracketed by
  * HIP events on the context stream and the elapsed times are summed per kernel.

@@ -3,6 +3,7 @@
 #include <iterator>
 
 #include "gss_impl.h"
+#include "gss_subtask.h"
 
 namespace {
 thread_local std::string g_err;
@@ -135,9 +136,16 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
         ctx->last_error = "bad recovery parameters";
         return GSS_ERR_ARG;
     }
+    if (p->sched == GSS_SCHED_LEARNED && !ctx->model_ready) {
+        ctx->last_error = "learned schedule requested but no cost model is loaded";
+        return GSS_ERR_ARG;
+    }
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
-        return recover_impl(ctx, t, p, mask, order, stretch, info);
+        ctx->record = (p->flags & GSS_F_RECORD) != 0;
+        gss_status s = recover_impl(ctx, t, p, mask, order, stretch, info);
+        ctx->record = false;
+        return s;
     });
 }
 
@@ -199,6 +207,87 @@ int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen
     if (total_ms) *total_ms = it->second.first;
     if (launches) *launches = it->second.second;
     return count;
+}
+
+gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks)
+{
+    if (!ctx || local_max < 1 || local_max > GSS_LOCAL_CAP || local_blocks < 1 || local_blocks > 65536)
+        return GSS_ERR_ARG;
+    ctx->local_max = local_max;
+    ctx->local_blocks = local_blocks;
+    return GSS_OK;
+}
+
+int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int64_t cap)
+{
+    if (!ctx || cap < 0) return -1;
+    int64_t rows = (int64_t)ctx->trace_cycles.size();
+    int64_t k = rows < cap ? rows : cap;
+    if (feat) memcpy(feat, ctx->trace_feat.data(), sizeof(float) * GSS_NFEAT * k);
+    if (cycles) memcpy(cycles, ctx->trace_cycles.data(), sizeof(double) * k);
+    if (size) memcpy(size, ctx->trace_size.data(), sizeof(int32_t) * k);
+    return rows;
+}
+
+gss_status gss_trace_clear(gss_ctx ctx)
+{
+    if (!ctx) return GSS_ERR_ARG;
+    ctx->trace_feat.clear();
+    ctx->trace_cycles.clear();
+    ctx->trace_size.clear();
+    return GSS_OK;
+}
+
+gss_status gss_costmodel_train(gss_ctx ctx, const float *feat, const double *cycles, int64_t n, int32_t epochs,
+                               float lr, uint64_t seed, float *loss)
+{
+    if (!ctx || !feat || !cycles || n < 2 || epochs < 1 || !(lr > 0.f)) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        costmodel_train(ctx, feat, cycles, n, epochs, lr, seed, loss);
+        return GSS_OK;
+    });
+}
+
+gss_status gss_costmodel_load(gss_ctx ctx, const float *weights)
+{
+    if (!ctx || !weights) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        costmodel_load(ctx, weights);
+        return GSS_OK;
+    });
+}
+
+gss_status gss_costmodel_save(gss_ctx ctx, float *weights)
+{
+    if (!ctx || !weights) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        costmodel_save(ctx, weights);
+        return GSS_OK;
+    });
+}
+
+gss_status gss_costmodel_predict(gss_ctx ctx, const float *feat, int64_t n, float *out)
+{
+    if (!ctx || (n > 0 && (!feat || !out)) || n < 0) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        costmodel_predict_log2(ctx, feat, n, out);
+        ctx->sync();
+        return GSS_OK;
+    });
+}
+
+gss_status gss_costmodel_grad(gss_ctx ctx, const float *x, const float *y, int32_t nb, float *grad, float *loss)
+{
+    if (!ctx || !x || !y || !grad || !loss) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        costmodel_grad(ctx, x, y, nb, grad, loss);
+        return GSS_OK;
+    });
 }
 
 const char *gss_status_str(gss_status s)

@@ -53,6 +53,17 @@ struct gss_ctx_s {
     void prof_end();
     void prof_collect();                           // after a sync: accumulate elapsed times
 
+    // subtask engine settings (autotuned) and the learned cost model
+    int32_t local_max = 1024;     // subtasks up to this size use the persistent kernel
+    int32_t local_blocks = 2048;  // workgroups of the persistent kernel (4 wavefronts each)
+    bool record = false;          // record per-subtask features and cycles
+    bool model_ready = false;     // cost-model weights loaded
+    std::vector<float> trace_feat;      // [rows * 12]
+    std::vector<double> trace_cycles;   // [rows]
+    std::vector<int32_t> trace_size;    // [rows]
+    float *mlp_w = nullptr;             // device weights (FP32 master copy)
+    void *mlp_wbf16 = nullptr;          // device BF16 copy for inference
+
     int device = 0;
     hipStream_t stream = nullptr;
     std::string last_error;

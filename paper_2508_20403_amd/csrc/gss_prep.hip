@@ -815,6 +815,13 @@ __global__ void k_check_reached(const VRec *__restrict__ vrec, int32_t n, uint32
     if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_NOT_TREE);
 }
 
+// number of tree children of each vertex, kept in the vertex record
+__global__ void k_vrec_tdeg(const int32_t *__restrict__ cptr, int32_t n, VRec *__restrict__ vrec)
+{
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) vrec[x].pad = cptr[x + 1] - cptr[x];
+}
+
 __global__ void k_root_init(int32_t root, VRec *vrec, uint64_t *epk)
 {
     VRec r;
@@ -966,6 +973,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         ctx->free(rpre);
         ctx->free(succ);
     }
+    GSS_LAUNCH(k_vrec_tdeg, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec);
     f = read_flags(ctx);
     ctx->free(cfill);
     ctx->free(clist);

@@ -28,6 +28,7 @@
 #include <cmath>
 
 #include "gss_impl.h"
+#include "gss_subtask.h"
 
 #define RB 256
 #define SEL_BITS 12
@@ -364,8 +365,11 @@ struct Slot {
 
 __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const int32_t *__restrict__ off_id,
                               const int32_t *__restrict__ off_u, const int32_t *__restrict__ off_v,
-                              const uint8_t *__restrict__ bst, const int32_t *__restrict__ parent, int32_t c,
-                              int32_t *__restrict__ rid, uint8_t *__restrict__ rb,
+                              const uint8_t *__restrict__ bst, const int32_t *__restrict__ lca,
+                              const VRec *__restrict__ vrec, int32_t c, int32_t *__restrict__ rid,
+                              uint8_t *__restrict__ rb, int32_t *__restrict__ ru, int32_t *__restrict__ rv,
+                              int32_t *__restrict__ rdu, int32_t *__restrict__ rdv, int32_t *__restrict__ rl,
+                              uint64_t *__restrict__ lkey, int32_t *__restrict__ lval,
                               int32_t *__restrict__ ancU, int32_t *__restrict__ ancV)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -374,11 +378,23 @@ __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const i
     rid[p] = off_id[j];
     rb[p] = bst[j];
     int32_t a = off_u[j], b = off_v[j];
-    for (int i = 0; i <= c; i++) {
-        ancU[(int64_t)i * P + p] = a;
-        ancV[(int64_t)i * P + p] = b;
-        a = (a >= 0) ? parent[a] : -1;
-        b = (b >= 0) ? parent[b] : -1;
+    ru[p] = a;
+    rv[p] = b;
+    int32_t l = lca[j];
+    rl[p] = l;
+    lkey[p] = (uint64_t)(uint32_t)l;
+    lval[p] = (int32_t)p;
+    VRec ra = vrec[a], rbv = vrec[b];
+    rdu[p] = ra.depth;
+    rdv[p] = rbv.depth;
+    ancU[p] = a;
+    ancV[p] = b;
+    int32_t pa = ra.parent, pb = rbv.parent;
+    for (int i = 1; i <= c; i++) {
+        ancU[(int64_t)i * P + p] = pa;
+        ancV[(int64_t)i * P + p] = pb;
+        pa = (pa >= 0) ? vrec[pa].parent : -1;
+        pb = (pb >= 0) ? vrec[pb].parent : -1;
     }
 }
 
@@ -401,10 +417,11 @@ __device__ __forceinline__ void join_insert(Slot *tab, uint64_t cap_mask, int32_
 }
 
 __global__ void k_join_build(int64_t P, int32_t c, const int32_t *__restrict__ ancU,
-                             const int32_t *__restrict__ ancV, Slot *tab, uint64_t cap_mask)
+                             const int32_t *__restrict__ ancV, const uint8_t *__restrict__ is_global, Slot *tab,
+                             uint64_t cap_mask)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    if (p >= P || !is_global[p]) return;
     for (int orient = 0; orient < 2; orient++) {
         const int32_t *X = orient ? ancV : ancU;
         const int32_t *Y = orient ? ancU : ancV;
@@ -421,12 +438,13 @@ __global__ void k_join_build(int64_t P, int32_t c, const int32_t *__restrict__ a
 }
 
 __global__ void k_join_probe(int64_t P, const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
-                             const int32_t *__restrict__ ancV, const Slot *__restrict__ tab,
-                             uint64_t cap_mask, int2 *__restrict__ arcs, int64_t arc_cap,
-                             unsigned long long *arc_count, int32_t *__restrict__ indeg, uint32_t *flags)
+                             const int32_t *__restrict__ ancV, const uint8_t *__restrict__ is_global,
+                             const Slot *__restrict__ tab, uint64_t cap_mask, int2 *__restrict__ arcs,
+                             int64_t arc_cap, unsigned long long *arc_count, int32_t *__restrict__ indeg,
+                             uint32_t *flags)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    if (p >= P || !is_global[p]) return;
     int beta = rb[p];
     if (beta == 0) return;  // S_u = {u}, S_v = {v}: only the edge itself is similar
     for (int j = 0; j <= beta; j++) {
@@ -462,10 +480,11 @@ __global__ void k_join_probe(int64_t P, const uint8_t *__restrict__ rb, const in
 // ------------------------------------------------------------------------------------
 // 5. dependency rounds (one workgroup)
 // ------------------------------------------------------------------------------------
-__global__ void k_state_init(int64_t P, const int32_t *__restrict__ indeg, uint8_t *__restrict__ state)
+__global__ void k_state_init(int64_t P, const int32_t *__restrict__ indeg, const uint8_t *__restrict__ is_global,
+                             uint8_t *__restrict__ state)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < P) state[p] = indeg[p] == 0 ? ST_CAND : ST_UNDEC;
+    if (p < P && is_global[p]) state[p] = indeg[p] == 0 ? ST_CAND : ST_UNDEC;
 }
 
 __global__ __launch_bounds__(1024) void k_resolve(int64_t A, const int2 *__restrict__ arcs,
@@ -616,93 +635,182 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
 }
 
 struct PrefixResult {
-    int64_t P = 0, cand = 0, arcs = 0, rounds = 0;
+    int64_t P = 0, cand = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0;
 };
 
 // resolves the prefix {key >= T}; leaves state/rid/sj for the caller to select from
 struct PrefixBufs {
     int32_t *sj = nullptr, *rid = nullptr, *ancU = nullptr, *ancV = nullptr, *indeg = nullptr, *mcnt = nullptr;
-    int32_t *ccnt = nullptr;
-    uint8_t *rb = nullptr, *state = nullptr;
+    int32_t *ccnt = nullptr, *ru = nullptr, *rv = nullptr, *rdu = nullptr, *rdv = nullptr, *rl = nullptr;
+    int32_t *grp = nullptr, *sub_ptr = nullptr, *sub_lca = nullptr;
+    uint8_t *rb = nullptr, *state = nullptr, *is_global = nullptr;
     void release(gss_ctx ctx)
     {
-        void *ps[] = {sj, rid, ancU, ancV, indeg, mcnt, ccnt, rb, state};
+        void *ps[] = {sj, rid, ancU, ancV, indeg, mcnt, ccnt, ru, rv, rdu, rdv, rl, grp, sub_ptr, sub_lca, rb, state,
+                      is_global};
         for (void *p : ps) ctx->free(p);
         *this = PrefixBufs();
     }
 };
 
 static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uint64_t *key, const uint8_t *bst,
-                                   uint64_t T, PrefixBufs &B)
+                                   const int32_t *lca, const int32_t *lcacnt, uint64_t T, PrefixBufs &B,
+                                   const gss_params *prm)
 {
     hipStream_t st = ctx->stream;
     const int64_t M = t->M;
     PrefixResult res;
+    std::vector<void *> scratch;
     // compaction (id order)
     int64_t nthr = (M + CHUNK - 1) / CHUNK;
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
     GSS_LAUNCH(k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc);
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
-    uint64_t *pk = ctx->alloc<uint64_t>(P + 1), *pk2 = ctx->alloc<uint64_t>(P + 1);
-    int32_t *pj = ctx->alloc<int32_t>(P + 1), *pj2 = ctx->alloc<int32_t>(P + 1);
-    GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc, pj, pk);
+    uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
+    int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
+    GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc, v1, k1);
     ctx->free(pc);
-    radix_sort_pairs(ctx, pk, pj, pk2, pj2, P);
-    ctx->free(pk);
-    ctx->free(pk2);
-    ctx->free(pj2);
-    B.sj = pj;
-    // per-rank data
+    radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // rank order: v1[p] = off-tree index of rank p
+    B.sj = v1;
+    // per-rank data, and (lca, rank) pairs for the grouping
     B.rid = ctx->alloc<int32_t>(P + 1);
     B.rb = ctx->alloc<uint8_t>(P + 1);
+    B.ru = ctx->alloc<int32_t>(P + 1);
+    B.rv = ctx->alloc<int32_t>(P + 1);
+    B.rdu = ctx->alloc<int32_t>(P + 1);
+    B.rdv = ctx->alloc<int32_t>(P + 1);
+    B.rl = ctx->alloc<int32_t>(P + 1);
     B.ancU = ctx->alloc<int32_t>((int64_t)(c + 1) * P + 1);
     B.ancV = ctx->alloc<int32_t>((int64_t)(c + 1) * P + 1);
-    GSS_LAUNCH(k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_id, t->off_u,
-                       t->off_v, bst, t->parent, c, B.rid, B.rb, B.ancU, B.ancV);
-    // hash join
-    int64_t entries = 2 * (int64_t)(c + 1) * (c + 1) * P;
-    uint64_t cap = 1024;
-    while (cap < 2 * (uint64_t)entries) cap <<= 1;
-    Slot *tab = ctx->alloc<Slot>(cap);
-    HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(Slot) * cap, st));
-    GSS_LAUNCH(k_join_build, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV, tab, cap - 1);
-    B.indeg = ctx->alloc<int32_t>(P + 1);
-    int64_t arc_cap = std::max<int64_t>(4 * P, 1 << 16);
-    for (;;) {
-        int2 *arcs = ctx->alloc<int2>(arc_cap);
-        HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
-        HIP_OK(hipMemsetAsync(ctx->d_counters, 0, sizeof(int64_t) * 2, st));
-        HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
-        GSS_LAUNCH(k_join_probe, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.rb, B.ancU, B.ancV, tab,
-                           cap - 1, arcs, arc_cap, (unsigned long long *)ctx->d_counters, B.indeg, ctx->d_flags);
-        HIP_OK(hipGetLastError());
-        read_counters(ctx, 1);
-        int64_t A = ctx->h_counters[0];
-        if (A > arc_cap) {
-            ctx->free(arcs);
-            arc_cap = A + A / 4 + 1024;
-            continue;
+    uint64_t *lkey = k1, *lkey2 = k2;
+    int32_t *lval = v2, *lval2 = ctx->alloc<int32_t>(P + 1);
+    GSS_LAUNCH(k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_id, t->off_u, t->off_v, bst,
+               lca, t->vrec, c, B.rid, B.rb, B.ru, B.rv, B.rdu, B.rdv, B.rl, lkey, lval, B.ancU, B.ancV);
+
+    // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA
+    radix_sort_pairs(ctx, lkey, lval, lkey2, lval2, P);
+    B.grp = lval;
+    scratch.push_back(lkey2);
+    scratch.push_back(lval2);
+    const uint64_t *glca = lkey;
+    scratch.push_back(lkey);
+    int32_t *hid = ctx->alloc<int32_t>(P + 1);
+    scratch.push_back(hid);
+    launch_grouping_kernels(ctx, P, glca, hid);
+    int64_t nsub = scan_exclusive_i32(ctx, hid, P, true);
+    res.nsub = nsub;
+    B.sub_ptr = ctx->alloc<int32_t>(nsub + 1);
+    B.sub_lca = ctx->alloc<int32_t>(nsub + 1);
+    launch_group_ptr(ctx, P, glca, hid, B.sub_ptr, B.sub_lca, (int32_t)nsub);
+
+    // work queue: local subtasks first, heaviest predicted cost first
+    const int32_t local_max = std::min<int32_t>(ctx->local_max, GSS_LOCAL_CAP);
+    float *feat = nullptr, *pred = nullptr;
+    const bool want_feat = (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) || ctx->record;
+    if (want_feat && nsub > 0) {
+        feat = ctx->alloc<float>(nsub * GSS_NFEAT + 1);
+        scratch.push_back(feat);
+        launch_subtask_features(ctx, (int32_t)nsub, B.sub_ptr, B.sub_lca, B.grp, B.rdu, B.rdv, B.rb, B.ru, B.rv,
+                                t->vrec, lcacnt, feat);
+        if (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) {
+            pred = ctx->alloc<float>(nsub + 1);
+            scratch.push_back(pred);
+            costmodel_predict(ctx, feat, nsub, pred);
         }
-        res.arcs = A;
-        B.state = ctx->alloc<uint8_t>(P + 1);
-        B.mcnt = ctx->alloc<int32_t>(P + 1);
-        HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
-        GSS_LAUNCH(k_state_init, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.indeg, B.state);
-        if (A > 0)
-            GSS_LAUNCH(k_resolve, dim3(1), dim3(1024), 0, st, A, arcs, B.indeg, B.state, B.mcnt,
-                               ctx->d_counters + 1);
-        HIP_OK(hipGetLastError());
-        int64_t nthr2 = (P + CHUNK - 1) / CHUNK;
-        B.ccnt = ctx->alloc<int32_t>(nthr2 + 1);
-        GSS_LAUNCH(k_cand_count, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, P, B.state, B.ccnt);
-        res.cand = scan_exclusive_i32(ctx, B.ccnt, nthr2, true);
-        read_counters(ctx, 2);
-        res.rounds = A > 0 ? ctx->h_counters[1] : 0;
-        ctx->free(arcs);
-        break;
     }
-    ctx->free(tab);
+    uint64_t *qk = ctx->alloc<uint64_t>(nsub + 1), *qk2 = ctx->alloc<uint64_t>(nsub + 1);
+    int32_t *qv = ctx->alloc<int32_t>(nsub + 1), *qv2 = ctx->alloc<int32_t>(nsub + 1);
+    int32_t *is_local = ctx->alloc<int32_t>(nsub + 1);
+    HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, sizeof(int64_t), st));
+    launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, qk, qv, is_local,
+                        (int32_t *)(ctx->d_counters + 4));
+    radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub);
+    read_counters(ctx, 5);
+    const int32_t nlocal = (int32_t)ctx->h_counters[4];
+    res.nlocal = nlocal;
+    scratch.push_back(qk);
+    scratch.push_back(qk2);
+    scratch.push_back(qv);
+    scratch.push_back(qv2);
+    scratch.push_back(is_local);
+
+    B.state = ctx->alloc<uint8_t>(P + 1);
+    B.is_global = ctx->alloc<uint8_t>(P + 1);
+    HIP_OK(hipMemsetAsync(B.is_global, 0, P + 1, st));
+    if (nsub > nlocal) launch_mark_global(ctx, (int32_t)nsub, B.sub_ptr, is_local, B.grp, B.is_global);
+
+    // Step 4, small and medium subtasks: persistent work-queue kernel
+    uint64_t *cycles = nullptr;
+    if (nlocal > 0) {
+        if (ctx->record) {
+            cycles = ctx->alloc<uint64_t>(nsub + 1);
+            scratch.push_back(cycles);
+            HIP_OK(hipMemsetAsync(cycles, 0, sizeof(uint64_t) * (nsub + 1), st));
+        }
+        HIP_OK(hipMemsetAsync(ctx->d_counters + 5, 0, sizeof(int64_t), st));
+        SubtaskArgs a;
+        a.P = P;
+        a.grp = B.grp;
+        a.sub_ptr = B.sub_ptr;
+        a.queue = qv;
+        a.nqueue = nlocal;
+        a.local_max = local_max;
+        a.queue_head = (unsigned int *)(ctx->d_counters + 5);
+        a.ancU = B.ancU;
+        a.ancV = B.ancV;
+        a.rdu = B.rdu;
+        a.rdv = B.rdv;
+        a.rb = B.rb;
+        a.state = B.state;
+        a.cycles = cycles;
+        int blocks = std::max(1, std::min<int>(ctx->local_blocks, (nlocal + 3) / 4));
+        launch_local_recover(ctx, c, a, blocks);
+    }
+    // Step 4, large subtasks: hash join + dependency rounds over their edges
+    B.indeg = ctx->alloc<int32_t>(P + 1);
+    B.mcnt = ctx->alloc<int32_t>(P + 1);
+    if (nsub > nlocal) {
+        int64_t entries = 2 * (int64_t)(c + 1) * (c + 1) * P;
+        uint64_t cap = 1024;
+        while (cap < 2 * (uint64_t)entries) cap <<= 1;
+        Slot *tab = ctx->alloc<Slot>(cap);
+        HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(Slot) * cap, st));
+        GSS_LAUNCH(k_join_build, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV, B.is_global, tab,
+                   cap - 1);
+        int64_t arc_cap = std::max<int64_t>(4 * P, 1 << 16);
+        for (;;) {
+            int2 *arcs = ctx->alloc<int2>(arc_cap);
+            HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
+            HIP_OK(hipMemsetAsync(ctx->d_counters, 0, sizeof(int64_t) * 2, st));
+            GSS_LAUNCH(k_join_probe, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.rb, B.ancU, B.ancV, B.is_global,
+                       tab, cap - 1, arcs, arc_cap, (unsigned long long *)ctx->d_counters, B.indeg, ctx->d_flags);
+            read_counters(ctx, 1);
+            int64_t A = ctx->h_counters[0];
+            if (A > arc_cap) {
+                ctx->free(arcs);
+                arc_cap = A + A / 4 + 1024;
+                continue;
+            }
+            res.arcs = A;
+            HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
+            GSS_LAUNCH(k_state_init, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.indeg, B.is_global, B.state);
+            if (A > 0)
+                GSS_LAUNCH(k_resolve, dim3(1), dim3(1024), 0, st, A, arcs, B.indeg, B.state, B.mcnt,
+                           ctx->d_counters + 1);
+            read_counters(ctx, 2);
+            res.rounds = A > 0 ? ctx->h_counters[1] : 0;
+            ctx->free(arcs);
+            break;
+        }
+        ctx->free(tab);
+    }
+    int64_t nthr2 = (P + CHUNK - 1) / CHUNK;
+    B.ccnt = ctx->alloc<int32_t>(nthr2 + 1);
+    GSS_LAUNCH(k_cand_count, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, P, B.state, B.ccnt);
+    res.cand = scan_exclusive_i32(ctx, B.ccnt, nthr2, true);
+    if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, feat, cycles, qv, nlocal);
+    for (void *p : scratch) ctx->free(p);
     return res;
 }
 
@@ -796,7 +904,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prm, uint8_t 
         for (;;) {
             uint64_t T = select_threshold(ctx, t, key, hist, hist_ready, want, eligible);
             hist_ready = false;
-            r = resolve_prefix(ctx, t, c, key, bst, T, B);
+            r = resolve_prefix(ctx, t, c, key, bst, lca, lcacnt, T, B, prm);
             if (r.cand >= need || r.P >= eligible) break;
             // not enough recovered edges in this prefix: a longer one is needed
             double ratio = (double)need / (double)std::max<int64_t>(r.cand, 1);

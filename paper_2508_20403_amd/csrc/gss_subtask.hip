@@ -1,0 +1,299 @@
+// gss_subtask.hip -- LCA subtasks of the resolved prefix (paper: Lemmas "strictly similar
+// edges share their LCA" and "contraposition", Alg. 1 Steps 3-4).
+//
+// The prefix edges, already in rank order, are grouped by LCA (stable, so each subtask
+// keeps rank order).  Subtasks up to a size limit are drained by a persistent kernel: each
+// wavefront pops the next subtask from a device work queue and runs the serial greedy of
+// that subtask with wavefront ballots, 64 edges at a time:
+//   * lanes hold consecutive edges of the subtask; each lane first tests its edge against
+//     the candidates recovered in earlier chunks (uniform loads of their descriptors);
+//   * the unmarked lanes are then resolved in rank order: the lowest pending lane is a
+//     candidate, its descriptor is broadcast, lanes after it test strict similarity and
+//     the ballot of hits removes them.
+// Strict similarity is tested with ancestor chains: x is in the beta-ball of u iff
+// anc_i(x) = anc_j(u) for some i + j <= beta; with depths known, for each i only
+// j = depth(u) - depth(x) + i can match.  Larger subtasks go to the global hash-join path.
+// Each wavefront records the cycles it spent on every subtask (the cost model's targets).
+#include "gss_subtask.h"
+
+namespace {
+
+template <int C>
+struct Desc {
+    int32_t au[C + 1];  // u, parent(u), ...   (-1 above the root)
+    int32_t av[C + 1];
+    int32_t du, dv;     // depths of u and v
+    int32_t beta;       // beta* of the edge
+};
+
+template <int C>
+__device__ __forceinline__ void load_desc(Desc<C> &d, int64_t P, int32_t p, const int32_t *__restrict__ ancU,
+                                          const int32_t *__restrict__ ancV, const int32_t *__restrict__ rdu,
+                                          const int32_t *__restrict__ rdv, const uint8_t *__restrict__ rb)
+{
+#pragma unroll
+    for (int i = 0; i <= C; i++) {
+        d.au[i] = ancU[(int64_t)i * P + p];
+        d.av[i] = ancV[(int64_t)i * P + p];
+    }
+    d.du = rdu[p];
+    d.dv = rdv[p];
+    d.beta = rb[p];
+}
+
+// is vertex x (chain ax, depth dx) within `beta` tree hops of vertex u (chain au, depth du)?
+template <int C>
+__device__ __forceinline__ bool in_ball(const int32_t *ax, int32_t dx, const int32_t *au, int32_t du, int beta)
+{
+    bool hit = false;
+#pragma unroll
+    for (int i = 0; i <= C; i++) {
+        int j = du - dx + i;
+        if (i <= beta && j >= 0 && i + j <= beta) {
+            int32_t aj = au[0];
+#pragma unroll
+            for (int q = 1; q <= C; q++)
+                if (q == j) aj = au[q];
+            hit |= (ax[i] == aj) && (ax[i] >= 0);
+        }
+    }
+    return hit;
+}
+
+// is edge t strictly similar to marker m under m's beta*?
+template <int C>
+__device__ __forceinline__ bool strictly_similar(const Desc<C> &t, const Desc<C> &m)
+{
+    const int b = m.beta;
+    if (b == 0) return false;  // the balls are {u} and {v}: only the edge itself
+    bool o1 = in_ball<C>(t.au, t.du, m.au, m.du, b) && in_ball<C>(t.av, t.dv, m.av, m.dv, b);
+    bool o2 = in_ball<C>(t.au, t.du, m.av, m.dv, b) && in_ball<C>(t.av, t.dv, m.au, m.du, b);
+    return o1 || o2;
+}
+
+template <int C>
+__device__ __forceinline__ Desc<C> shfl_desc(const Desc<C> &d, int src)
+{
+    Desc<C> r;
+#pragma unroll
+    for (int i = 0; i <= C; i++) {
+        r.au[i] = __shfl(d.au[i], src, GSS_WAVE);
+        r.av[i] = __shfl(d.av[i], src, GSS_WAVE);
+    }
+    r.du = __shfl(d.du, src, GSS_WAVE);
+    r.dv = __shfl(d.dv, src, GSS_WAVE);
+    r.beta = __shfl(d.beta, src, GSS_WAVE);
+    return r;
+}
+
+// persistent kernel: one wavefront per subtask, pulled from a device work queue
+template <int C>
+__global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
+{
+    __shared__ int32_t scand[256 / GSS_WAVE][GSS_LOCAL_CAP];  // candidate ranks per wavefront
+    const int lane = lane_id();
+    int32_t *cand = scand[threadIdx.x / GSS_WAVE];
+    for (;;) {
+        int32_t qi = 0;
+        if (lane == 0) qi = (int32_t)atomicAdd(a.queue_head, 1u);
+        qi = __shfl(qi, 0, GSS_WAVE);
+        if (qi >= a.nqueue) break;
+        const int32_t s = a.queue[qi];
+        const uint64_t t0 = clock64();
+        const int32_t g0 = a.sub_ptr[s], g1 = a.sub_ptr[s + 1];
+        int32_t ncand = 0;
+        for (int32_t c0 = g0; c0 < g1; c0 += GSS_WAVE) {
+            const int32_t gi = c0 + lane;
+            const bool valid = gi < g1;
+            const int32_t p = valid ? a.grp[gi] : 0;
+            Desc<C> me;
+            if (valid) load_desc<C>(me, a.P, p, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+            // against candidates of earlier chunks (uniform loads)
+            bool marked = false;
+            for (int32_t k = 0; k < ncand; k++) {
+                Desc<C> m;
+                load_desc<C>(m, a.P, cand[k], a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+                marked |= valid && strictly_similar<C>(me, m);
+            }
+            // in-chunk greedy in rank order
+            uint64_t pending = __ballot(valid && !marked);
+            uint64_t recovered = 0;
+            while (pending) {
+                const int i = __ffsll((long long)pending) - 1;
+                Desc<C> m = shfl_desc<C>(me, i);
+                const bool hit = valid && lane > i && strictly_similar<C>(me, m);
+                const uint64_t hits = __ballot(hit);
+                recovered |= 1ull << i;
+                pending &= ~((1ull << i) | hits);
+            }
+            const bool is_cand = (recovered >> lane) & 1ull;
+            if (valid) a.state[p] = is_cand ? ST_CAND_ : ST_MARK_;
+            // append this chunk's candidates (rank order) to the candidate list
+            const int before = __popcll(recovered & lanemask_lt());
+            if (is_cand && ncand + before < a.local_max) cand[ncand + before] = p;
+            ncand += __popcll(recovered);
+            __threadfence_block();
+        }
+        const uint64_t t1 = clock64();
+        if (lane == 0 && a.cycles) a.cycles[s] = t1 - t0;
+    }
+}
+
+}  // namespace
+
+void launch_local_recover(gss_ctx ctx, int C, const SubtaskArgs &a, int blocks)
+{
+    hipStream_t st = ctx->stream;
+    switch (C) {
+#define CASE(k) \
+    case k: GSS_LAUNCH(k_local_recover<k>, dim3(blocks), dim3(256), 0, st, a); break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: throw gss_error{GSS_ERR_ARG, "beta out of range"};
+    }
+    HIP_OK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------------------------
+// grouping helpers
+// ------------------------------------------------------------------------------------
+// subtask boundaries of the LCA-grouped list: head flag where the LCA changes
+__global__ void k_group_heads(int64_t P, const uint64_t *__restrict__ glca, int32_t *__restrict__ head)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) head[i] = (i == 0 || glca[i] != glca[i - 1]) ? 1 : 0;
+}
+
+// sub_ptr[id] = start of subtask id (head flags scanned exclusively give the ids)
+__global__ void k_group_ptr(int64_t P, const uint64_t *__restrict__ glca, const int32_t *__restrict__ hid,
+                            int32_t *__restrict__ sub_ptr, int32_t *__restrict__ sub_lca)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    if (i == 0 || glca[i] != glca[i - 1]) {
+        sub_ptr[hid[i]] = (int32_t)i;
+        sub_lca[hid[i]] = (int32_t)glca[i];
+    }
+}
+
+__global__ void k_group_end(int32_t nsub, int64_t P, int32_t *__restrict__ sub_ptr) { sub_ptr[nsub] = (int32_t)P; }
+
+// per subtask: queue key (descending cost first) and the local/global split
+__global__ void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr, int32_t local_max,
+                               const float *__restrict__ pred, uint64_t *__restrict__ qkey,
+                               int32_t *__restrict__ qval, int32_t *__restrict__ is_local,
+                               int32_t *__restrict__ nlocal)
+{
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsub) return;
+    int32_t size = sub_ptr[s + 1] - sub_ptr[s];
+    bool loc = size <= local_max;
+    is_local[s] = loc ? 1 : 0;
+    uint64_t cost;
+    if (pred) cost = (uint64_t)__float_as_uint(fmaxf(pred[s], 0.f));  // non-negative floats order as ints
+    else cost = (uint64_t)size;
+    // ascending sort of this key = local subtasks first, by cost descending, then id
+    qkey[s] = ((uint64_t)(loc ? 0 : 1) << 63) | ((~cost) & 0x7fffffffffffffffull);
+    qval[s] = s;
+    if (loc) atomicAdd(nlocal, 1);
+}
+
+// global-path flag per rank (edges of subtasks above the local limit)
+__global__ void k_mark_global(int32_t nsub, const int32_t *__restrict__ sub_ptr, const int32_t *__restrict__ is_local,
+                              const int32_t *__restrict__ grp, uint8_t *__restrict__ is_global)
+{
+    int32_t s = blockIdx.x;
+    if (s >= nsub || is_local[s]) return;
+    for (int32_t g = sub_ptr[s] + threadIdx.x; g < sub_ptr[s + 1]; g += blockDim.x) is_global[grp[g]] = 1;
+}
+
+// 12 features per subtask for the cost model (one wave per subtask)
+__global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const int32_t *__restrict__ sub_ptr,
+                                                          const int32_t *__restrict__ sub_lca,
+                                                          const int32_t *__restrict__ grp,
+                                                          const int32_t *__restrict__ rdu,
+                                                          const int32_t *__restrict__ rdv,
+                                                          const uint8_t *__restrict__ rb,
+                                                          const int32_t *__restrict__ ru,
+                                                          const int32_t *__restrict__ rv,
+                                                          const VRec *__restrict__ vrec,
+                                                          const int32_t *__restrict__ lcacnt, float *__restrict__ feat)
+{
+    const int lane = lane_id();
+    const int32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
+    if (s >= nsub) return;
+    const int32_t g0 = sub_ptr[s], g1 = sub_ptr[s + 1];
+    const int32_t l = sub_lca[s];
+    const VRec rl = vrec[l];
+    float sum_path = 0, max_path = 0, sum_beta = 0, nb0 = 0, sum_deg = 0, max_deg = 0;
+    for (int32_t g = g0 + lane; g < g1; g += GSS_WAVE) {
+        int32_t p = grp[g];
+        float path = (float)(rdu[p] - rl.depth + rdv[p] - rl.depth);
+        sum_path += path;
+        max_path = fmaxf(max_path, path);
+        sum_beta += (float)rb[p];
+        nb0 += rb[p] == 0 ? 1.f : 0.f;
+        float deg = (float)(vrec[ru[p]].pad + vrec[rv[p]].pad + 2);
+        sum_deg += deg;
+        max_deg = fmaxf(max_deg, deg);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        sum_path += __shfl_xor(sum_path, d, GSS_WAVE);
+        max_path = fmaxf(max_path, __shfl_xor(max_path, d, GSS_WAVE));
+        sum_beta += __shfl_xor(sum_beta, d, GSS_WAVE);
+        nb0 += __shfl_xor(nb0, d, GSS_WAVE);
+        sum_deg += __shfl_xor(sum_deg, d, GSS_WAVE);
+        max_deg = fmaxf(max_deg, __shfl_xor(max_deg, d, GSS_WAVE));
+    }
+    if (lane == 0) {
+        float S = (float)(g1 - g0);
+        float full = (float)lcacnt[l];
+        float *f = feat + (int64_t)s * GSS_NFEAT;
+        f[0] = log2f(1.f + S);
+        f[1] = sum_path / S;
+        f[2] = max_path;
+        f[3] = sum_beta / S;
+        f[4] = nb0 / S;
+        f[5] = sum_deg / S;
+        f[6] = max_deg;
+        f[7] = log2f(1.f + (float)rl.pad);
+        f[8] = log2f(1.f + (float)rl.depth);
+        f[9] = S / fmaxf(full, 1.f);
+        f[10] = log2f(1.f + full);
+        f[11] = log2f(1.f + S * S);
+    }
+}
+
+void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32_t *head)
+{
+    GSS_LAUNCH(k_group_heads, dim3(grid_for(P, 256)), dim3(256), 0, ctx->stream, P, glca, head);
+}
+
+void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, int32_t *sub_ptr,
+                      int32_t *sub_lca, int32_t nsub)
+{
+    GSS_LAUNCH(k_group_ptr, dim3(grid_for(P, 256)), dim3(256), 0, ctx->stream, P, glca, hid, sub_ptr, sub_lca);
+    GSS_LAUNCH(k_group_end, dim3(1), dim3(1), 0, ctx->stream, nsub, P, sub_ptr);
+}
+
+void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
+                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal)
+{
+    GSS_LAUNCH(k_subtask_keys, dim3(grid_for(nsub, 256)), dim3(256), 0, ctx->stream, nsub, sub_ptr, local_max, pred,
+               qkey, qval, is_local, nlocal);
+}
+
+void launch_mark_global(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *is_local,
+                        const int32_t *grp, uint8_t *is_global)
+{
+    GSS_LAUNCH(k_mark_global, dim3(nsub), dim3(256), 0, ctx->stream, nsub, sub_ptr, is_local, grp, is_global);
+}
+
+void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
+                             const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
+                             const int32_t *ru, const int32_t *rv, const VRec *vrec, const int32_t *lcacnt,
+                             float *feat)
+{
+    GSS_LAUNCH(k_subtask_features, dim3(grid_for((int64_t)nsub * GSS_WAVE, 256)), dim3(256), 0, ctx->stream, nsub,
+               sub_ptr, sub_lca, grp, rdu, rdv, rb, ru, rv, vrec, lcacnt, feat);
+}

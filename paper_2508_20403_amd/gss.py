@@ -26,7 +26,13 @@ SCHED_EDGECOUNT, SCHED_LEARNED = 0, 1
 EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
            "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca",
            "gss_tree_num_edges", "gss_status_str", "gss_last_error", "gss_ctx_profile",
-           "gss_ctx_profile_read"]
+           "gss_ctx_profile_read", "gss_ctx_set_tuning", "gss_trace_read", "gss_trace_clear",
+           "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
+           "gss_costmodel_grad"]
+GSS_F_RECORD = 2
+NFEAT = 12
+COSTMODEL_FLOATS = 5081
+COSTMODEL_PARAMS = 5057
 
 
 class GSSError(RuntimeError):
@@ -87,8 +93,19 @@ def load_library(path=LIB_PATH):
     lib.gss_ctx_profile_read.argtypes = [P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.gss_ctx_profile_read.restype = ctypes.c_int32
+    lib.gss_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.gss_trace_read.argtypes = [P, P, P, P, ctypes.c_int64]
+    lib.gss_trace_read.restype = ctypes.c_int64
+    lib.gss_trace_clear.argtypes = [P]
+    lib.gss_costmodel_train.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, P]
+    lib.gss_costmodel_load.argtypes = [P, P]
+    lib.gss_costmodel_save.argtypes = [P, P]
+    lib.gss_costmodel_predict.argtypes = [P, P, ctypes.c_int64, P]
+    lib.gss_costmodel_grad.argtypes = [P, P, P, ctypes.c_int32, P, P]
     for name in ("gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
-                 "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca"):
+                 "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca", "gss_ctx_set_tuning",
+                 "gss_trace_clear", "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save",
+                 "gss_costmodel_predict", "gss_costmodel_grad"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -140,6 +157,68 @@ class Context:
             self.lib.gss_ctx_profile_read(self.handle, i, buf, 128, ctypes.byref(ms), ctypes.byref(n))
             out[buf.value.decode()] = (ms.value, n.value)
         return out
+
+    # ---- subtask scheduling and the learned cost model --------------------------------
+    def set_tuning(self, local_max, local_blocks):
+        self.check(self.lib.gss_ctx_set_tuning(self.handle, int(local_max), int(local_blocks)))
+
+    def trace_read(self):
+        """(features [rows,12] float32, cycles [rows] float64, sizes [rows] int32) recorded so far."""
+        import numpy as np
+        rows = self.lib.gss_trace_read(self.handle, None, None, None, 0)
+        feat = np.zeros((rows, NFEAT), np.float32)
+        cyc = np.zeros(rows, np.float64)
+        size = np.zeros(rows, np.int32)
+        if rows:
+            self.lib.gss_trace_read(self.handle, feat.ctypes.data_as(ctypes.c_void_p),
+                                    cyc.ctypes.data_as(ctypes.c_void_p), size.ctypes.data_as(ctypes.c_void_p),
+                                    rows)
+        return feat, cyc, size
+
+    def trace_clear(self):
+        self.check(self.lib.gss_trace_clear(self.handle))
+
+    def costmodel_train(self, feat, cycles, epochs=10, lr=1e-3, seed=0):
+        import numpy as np
+        feat = np.ascontiguousarray(feat, np.float32)
+        cycles = np.ascontiguousarray(cycles, np.float64)
+        loss = np.zeros(epochs, np.float32)
+        self.check(self.lib.gss_costmodel_train(self.handle, feat.ctypes.data_as(ctypes.c_void_p),
+                                                cycles.ctypes.data_as(ctypes.c_void_p), len(cycles),
+                                                int(epochs), float(lr), int(seed),
+                                                loss.ctypes.data_as(ctypes.c_void_p)))
+        return loss
+
+    def costmodel_load(self, weights):
+        import numpy as np
+        w = np.ascontiguousarray(weights, np.float32)
+        assert w.size == COSTMODEL_FLOATS
+        self.check(self.lib.gss_costmodel_load(self.handle, w.ctypes.data_as(ctypes.c_void_p)))
+
+    def costmodel_save(self):
+        import numpy as np
+        w = np.zeros(COSTMODEL_FLOATS, np.float32)
+        self.check(self.lib.gss_costmodel_save(self.handle, w.ctypes.data_as(ctypes.c_void_p)))
+        return w
+
+    def costmodel_predict(self, feat):
+        """feat: device float32 tensor [n,12]; returns device float32 [n] of log2(cycles)."""
+        n = feat.shape[0]
+        out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
+        self.check(self.lib.gss_costmodel_predict(self.handle, _ptr(feat.contiguous()), n, _ptr(out)))
+        return out[:n]
+
+    def costmodel_grad(self, x, y):
+        import numpy as np
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        g = np.zeros(COSTMODEL_PARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        self.check(self.lib.gss_costmodel_grad(self.handle, x.ctypes.data_as(ctypes.c_void_p),
+                                               y.ctypes.data_as(ctypes.c_void_p), len(y),
+                                               g.ctypes.data_as(ctypes.c_void_p),
+                                               loss.ctypes.data_as(ctypes.c_void_p)))
+        return g, float(loss[0])
 
     def close(self):
         if self.handle:
@@ -194,7 +273,7 @@ class Tree:
         return lca, bstar
 
     def recover(self, alpha, beta, k_override=-1, sched=SCHED_EDGECOUNT, mask_tree=False,
-                want_order=True, want_stretch=False, out=None):
+                want_order=True, want_stretch=False, out=None, record=False):
         """Runs gss_recover.  Returns (status, mask, order, stretch, info dict)."""
         dev = self.arrays[3].device
         k = int(k_override) if k_override >= 0 else int(float(alpha) * float(self.n) // 1)
@@ -204,8 +283,8 @@ class Tree:
             stretch = torch.empty(max(self.m, 1), dtype=torch.float64, device=dev) if want_stretch else None
         else:
             mask, order, stretch = out
-        p = Params(float(alpha), int(beta), int(sched), int(k_override),
-                   GSS_F_MASK_TREE if mask_tree else 0, 0)
+        flags = (GSS_F_MASK_TREE if mask_tree else 0) | (GSS_F_RECORD if record else 0)
+        p = Params(float(alpha), int(beta), int(sched), int(k_override), flags, 0)
         info = Info()
         st = self.ctx.lib.gss_recover(self.ctx.handle, self.handle, ctypes.byref(p), _ptr(mask),
                                       _ptr(order), _ptr(stretch), ctypes.byref(info))

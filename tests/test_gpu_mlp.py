@@ -1,0 +1,67 @@
+"""Cost-model kernels against the CPU reference (oracle/mlp.py)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+from paper_2508_20403_amd import gss, synth
+from tests.gpu_util import assert_same_recovery, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fp32_gradient_matches_cpu(gpu_ctx):
+    rng = np.random.default_rng(0)
+    for seed, nb in ((1, 64), (2, 17), (3, 1)):
+        w = mlp.random_weights(seed)
+        gpu_ctx.costmodel_load(w.astype(np.float32))
+        w32 = w.astype(np.float32).astype(np.float64)
+        x = rng.normal(0, 2, (nb, mlp.NF)).astype(np.float32)
+        y = rng.normal(12, 3, nb).astype(np.float32)
+        g_gpu, l_gpu = gpu_ctx.costmodel_grad(x, y)
+        l_cpu, g_cpu = mlp.loss_and_grad(w32, x.astype(np.float64), y.astype(np.float64))
+        assert abs(l_gpu - l_cpu) <= 1e-4 * max(1.0, abs(l_cpu))
+        err = np.abs(g_gpu - g_cpu)
+        assert np.linalg.norm(err) <= 1e-4 * np.linalg.norm(g_cpu), (seed, np.linalg.norm(err), np.linalg.norm(g_cpu))
+        assert np.all(err <= 1e-4 * np.abs(g_cpu) + 1e-4 * np.abs(g_cpu).max())
+
+
+def test_bf16_inference_close_to_fp64(gpu_ctx):
+    rng = np.random.default_rng(5)
+    w = mlp.random_weights(7, scale=0.5)
+    gpu_ctx.costmodel_load(w.astype(np.float32))
+    for n in (1, 15, 64, 1000, 4097):
+        x = rng.normal(0, 1.5, (n, mlp.NF)).astype(np.float32)
+        y_cpu, _ = mlp.forward(w.astype(np.float32).astype(np.float64), x.astype(np.float64))
+        y_gpu = gpu_ctx.costmodel_predict(torch.from_numpy(x).cuda()).cpu().numpy()
+        scale = np.abs(y_cpu).mean() + 1e-3
+        assert np.all(np.abs(y_gpu - y_cpu) <= 2e-2 * (np.abs(y_cpu) + scale)), (n, np.abs(y_gpu - y_cpu).max(), scale)
+
+
+def test_training_fits_a_smooth_target(gpu_ctx):
+    rng = np.random.default_rng(11)
+    n = 4096
+    x = rng.normal(0, 1, (n, mlp.NF)).astype(np.float32)
+    logc = 10 + 2 * x[:, 0] + np.abs(x[:, 1]) - 0.5 * x[:, 2] * x[:, 3]
+    cyc = np.exp2(logc).astype(np.float64)
+    loss = gpu_ctx.costmodel_train(x, cyc, epochs=30, lr=3e-3, seed=1)
+    assert np.all(np.isfinite(loss))
+    assert loss[-1] < 0.1 * np.var(logc), (loss[0], loss[-1], np.var(logc))
+    w = gpu_ctx.costmodel_save()
+    y_cpu, _ = mlp.forward(w.astype(np.float64), x.astype(np.float64))
+    assert np.mean((y_cpu - logc) ** 2) < 0.15 * np.var(logc)
+
+
+def test_learned_schedule_is_bit_exact(gpu_ctx):
+    g = synth.config("grid3d_32")
+    gpu_ctx.trace_clear()
+    gss_tree = gss.Tree.from_graph(gpu_ctx, g)
+    gss_tree.recover(g.alpha, g.beta, record=True)
+    gss_tree.free()
+    feat, cyc, size = gpu_ctx.trace_read()
+    gpu_ctx.trace_clear()
+    gpu_ctx.costmodel_train(feat, cyc, epochs=5, lr=1e-3, seed=3)
+    orc = run_oracle(g)
+    for sched in (gss.SCHED_LEARNED, gss.SCHED_EDGECOUNT):
+        gpu = run_gpu(gpu_ctx, g, sched=sched)
+        assert_same_recovery(gpu, orc)
