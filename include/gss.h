@@ -128,6 +128,25 @@ gss_status gss_tree_free(gss_tree tree);
 gss_status gss_recover(gss_ctx ctx, gss_tree tree, const gss_params *params, uint8_t *mask,
                        int32_t *order, double *stretch, gss_info *info);
 
+/* ---- batches: many graphs recovered by one pass of kernels -------------------------
+ * gss_batch_prep copies nb graphs (host array of device CSRs, host array of device
+ * parent arrays) into one disjoint union whose trees hang under a virtual root with
+ * zero-resistance links, validates every graph as gss_tree_prep does, and prepares the
+ * union once.  Edge ids, masks and orders stay per graph.  The caller's arrays may be
+ * released after the call.  Errors: as gss_tree_prep. */
+gss_status gss_batch_prep(gss_ctx ctx, int32_t nb, const gss_csr *graphs, const int32_t *const *parents,
+                          uint32_t flags, gss_tree *out);
+/* Recovers every graph of a batch tree: params, masks (device uint8 [m_g]) and orders
+ * (device int32 [K_g], or NULL for the whole array or an entry) are host arrays of nb;
+ * infos host [nb] or NULL.  All graphs must use the same beta and schedule.  Subtasks of
+ * all graphs share one work queue and one persistent launch.  Returns GSS_SHORT if any
+ * graph had fewer than K_g off-tree edges. */
+gss_status gss_recover_batch(gss_ctx ctx, gss_tree batch, const gss_params *params, uint8_t *const *masks,
+                             int32_t *const *orders, gss_info *infos);
+/* Number of graphs of a tree (1 for gss_tree_prep) and the edge count m_g of graph g. */
+int32_t gss_tree_num_graphs(gss_tree tree);
+int64_t gss_tree_graph_edges(gss_tree tree, int32_t g);
+
 /* Diagnostics used by the parity tests (same kernels as the path above).
  *   depth  device int32 [n]; Dlo, Dhi device uint64 [n]: root resistance D(x) = (Dhi*2^64
  *   + Dlo) * 2^scale; scale host int32.  Any pointer may be NULL. */

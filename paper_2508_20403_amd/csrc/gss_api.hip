@@ -116,6 +116,69 @@ gss_status gss_tree_prep(gss_ctx ctx, const gss_csr *g, const int32_t *parent, u
     return GSS_OK;
 }
 
+gss_status gss_batch_prep(gss_ctx ctx, int32_t nb, const gss_csr *graphs, const int32_t *const *parents,
+                          uint32_t flags, gss_tree *out)
+{
+    if (!ctx || nb < 1 || !graphs || !parents || !out) return GSS_ERR_ARG;
+    *out = nullptr;
+    for (int32_t g = 0; g < nb; g++) {
+        const gss_csr &c = graphs[g];
+        if (c.n < 1 || c.nnz < 0 || !c.row_ptr || !parents[g] || (c.nnz > 0 && (!c.col || !c.w))) {
+            ctx->last_error = "bad graph arguments in the batch";
+            return GSS_ERR_ARG;
+        }
+    }
+    gss_tree t = new (std::nothrow) gss_tree_s();
+    if (!t) return GSS_ERR_OOM;
+    t->ctx = ctx;
+    gss_status s = guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        prep_batch(ctx, t, nb, graphs, parents, flags);
+        return GSS_OK;
+    });
+    if (s != GSS_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        free_tree_arrays(t);
+        delete t;
+        return s;
+    }
+    *out = t;
+    return GSS_OK;
+}
+
+int32_t gss_tree_num_graphs(gss_tree t) { return t ? t->G : -1; }
+
+int64_t gss_tree_graph_edges(gss_tree t, int32_t g)
+{
+    if (!t || g < 0 || g >= t->G) return -1;
+    return t->ebase[g + 1] - t->ebase[g];
+}
+
+gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, uint8_t *const *masks,
+                             int32_t *const *orders, gss_info *infos)
+{
+    if (!ctx || !t || !params || !masks || t->ctx != ctx) return GSS_ERR_ARG;
+    for (int32_t g = 0; g < t->G; g++) {
+        const gss_params &p = params[g];
+        if (!masks[g] || !(p.alpha >= 0.0 && p.alpha <= 1.0) || p.beta < 0 || p.beta > GSS_MAX_BETA ||
+            p.reserved != 0 || (p.sched != GSS_SCHED_EDGECOUNT && p.sched != GSS_SCHED_LEARNED)) {
+            ctx->last_error = "bad recovery parameters in the batch";
+            return GSS_ERR_ARG;
+        }
+    }
+    if (params[0].sched == GSS_SCHED_LEARNED && !ctx->model_ready) {
+        ctx->last_error = "learned schedule requested but no cost model is loaded";
+        return GSS_ERR_ARG;
+    }
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        ctx->record = (params[0].flags & GSS_F_RECORD) != 0;
+        gss_status s = recover_impl(ctx, t, params, masks, orders, nullptr, infos);
+        ctx->record = false;
+        return s;
+    });
+}
+
 gss_status gss_tree_free(gss_tree t)
 {
     if (!t) return GSS_ERR_ARG;
@@ -143,7 +206,10 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         ctx->record = (p->flags & GSS_F_RECORD) != 0;
-        gss_status s = recover_impl(ctx, t, p, mask, order, stretch, info);
+        if (t->virt_root >= 0) throw gss_error{GSS_ERR_ARG, "a batch tree needs gss_recover_batch"};
+        uint8_t *masks[1] = {mask};
+        int32_t *orders[1] = {order};
+        gss_status s = recover_impl(ctx, t, p, masks, order ? orders : nullptr, stretch, info);
         ctx->record = false;
         return s;
     });

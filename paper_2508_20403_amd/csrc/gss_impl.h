@@ -115,13 +115,28 @@ struct gss_tree_s {
     // off-tree edges in id order
     int32_t *off_id = nullptr, *off_u = nullptr, *off_v = nullptr;
     double *off_w = nullptr;
+    // batches: the union of G graphs whose trees hang under a virtual root (a vertex
+    // with no graph edges; its tree edges carry zero resistance)
+    int32_t G = 1;
+    int32_t virt_root = -1;
+    int32_t *off_g = nullptr;            // [M] graph of each off-tree edge (batches only)
+    int32_t *d_vbase = nullptr;          // [G+1] first union vertex of each graph
+    std::vector<int64_t> vbase;          // host copy
+    std::vector<int64_t> ebase;          // [G+1] first union edge id of each graph
+    std::vector<int64_t> Mg;             // [G] off-tree edges of each graph
+    std::vector<int64_t> obase;          // [G+1] first off-tree index of each graph
+    // union arrays owned by a batch tree
+    int32_t *own_row_ptr = nullptr, *own_col = nullptr, *own_parent = nullptr;
+    double *own_w = nullptr;
 };
 
 // ---- host entry points of the translation units --------------------------------------
 void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags);
+void prep_batch(gss_ctx ctx, gss_tree t, int32_t G, const gss_csr *gs, const int32_t *const *parents,
+                uint32_t flags);
 void free_tree_arrays(gss_tree t);
-gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *mask,
-                        int32_t *order, double *stretch, gss_info *info);
+gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t *const *masks,
+                        int32_t *const *orders, double *stretch, gss_info *infos);
 void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar);
 
 // ---- shared launch helpers (gss_prims.hip) -------------------------------------------

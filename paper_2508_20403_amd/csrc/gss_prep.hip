@@ -189,7 +189,7 @@ __global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__res
 __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ parent,
                                                    const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const double *__restrict__ w,
-                                                   int32_t n, int32_t *__restrict__ ccnt,
+                                                   int32_t n, int32_t virt_root, int32_t *__restrict__ ccnt,
                                                    int32_t *__restrict__ tpos, uint32_t *flags, int64_t *counters)
 {
     __shared__ int32_t sred[5][PB / GSS_WAVE];
@@ -206,6 +206,8 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
             root = min(root, x);
         } else if (p < 0 || p >= n || p == x) {
             f |= F_NOT_TREE;
+        } else if (p == virt_root) {
+            atomicAdd(&ccnt[p], 1);  // zero-resistance link of a batch graph's root
         } else {
             atomicAdd(&ccnt[p], 1);
             int64_t k = find_in_row(col, row_ptr[x], row_ptr[x + 1], p);
@@ -740,7 +742,9 @@ __global__ __launch_bounds__(PB) void k_offtree_write(const int32_t *__restrict_
                                                       const int32_t *__restrict__ ufirst, int32_t n, int64_t nnz,
                                                       const int32_t *__restrict__ off0,
                                                       int32_t *__restrict__ off_id, int32_t *__restrict__ off_u,
-                                                      int32_t *__restrict__ off_v, double *__restrict__ off_w)
+                                                      int32_t *__restrict__ off_v, double *__restrict__ off_w,
+                                                      const int32_t *__restrict__ vbase, int32_t G,
+                                                      int32_t *__restrict__ off_g)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t lds[PB / GSS_WAVE + 1];
@@ -764,6 +768,15 @@ __global__ __launch_bounds__(PB) void k_offtree_write(const int32_t *__restrict_
             off_u[o] = u;
             off_v[o] = v;
             off_w[o] = w[k];
+            if (off_g) {
+                int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
+                while (hi - lo > 1) {
+                    int32_t mid = (lo + hi) >> 1;
+                    if (vbase[mid] <= u) lo = mid;
+                    else hi = mid;
+                }
+                off_g[o] = lo;
+            }
         }
         q += tot;
     }
@@ -777,7 +790,7 @@ __global__ void k_tree_eid(const int32_t *__restrict__ parent, const int32_t *__
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     int32_t p = parent[x];
-    if (p < 0) {
+    if (p < 0 || tpos[x] < 0) {
         tree_eid[x] = -1;
         return;
     }
@@ -842,9 +855,10 @@ static void fail(gss_status s, const char *msg) { throw gss_error{s, msg}; }
 void free_tree_arrays(gss_tree t)
 {
     gss_ctx c = t->ctx;
-    void *ptrs[] = {t->uptr,  t->ufirst, t->tpos,  t->tree_eid, t->vrec, t->epk,  t->pmask,
-                    t->ppre,  t->psuf,   t->bmin,  t->bmask,    t->bpre, t->bsuf, t->sbst,
-                    t->off_id, t->off_u, t->off_v, t->off_w};
+    void *ptrs[] = {t->uptr,   t->ufirst, t->tpos,   t->tree_eid, t->vrec,       t->epk,    t->pmask,
+                    t->ppre,   t->psuf,   t->bmin,   t->bmask,    t->bpre,       t->bsuf,   t->sbst,
+                    t->off_id, t->off_u,  t->off_v,  t->off_w,    t->off_g,      t->d_vbase, t->own_row_ptr,
+                    t->own_col, t->own_parent, t->own_w};
     for (void *p : ptrs) c->free(p);
 }
 
@@ -894,7 +908,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     memcpy(ctx->h_counters, init_c, sizeof init_c);
     HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
     GSS_LAUNCH(k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st, t->parent, t->row_ptr,
-               t->col, t->w, n, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
+               t->col, t->w, n, t->virt_root, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     uint32_t f = read_flags(ctx);  // syncs
     int64_t roots = ctx->h_counters[0];
@@ -1007,8 +1021,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
                t->bpre, t->bsuf, t->sbst, t->nsb);
     GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
 
-    // off-tree edges
-    t->M = t->m - (n - 1);
+    // off-tree edges (links to a batch's virtual root are tree edges without graph edges)
+    t->M = t->m - (n - 1) + (t->virt_root >= 0 ? t->G : 0);
     t->off_id = ctx->alloc<int32_t>(t->M + 1);
     t->off_u = ctx->alloc<int32_t>(t->M + 1);
     t->off_v = ctx->alloc<int32_t>(t->M + 1);
@@ -1023,8 +1037,10 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
             ctx->free(ocnt);
             fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
         }
+        if (t->G > 1 || t->virt_root >= 0) t->off_g = ctx->alloc<int32_t>(t->M + 1);
         GSS_LAUNCH(k_offtree_write, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr, t->col, t->w, t->parent,
-                   t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v, t->off_w);
+                   t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G,
+                   t->off_g);
         ctx->free(ocnt);
     }
     t->tree_eid = ctx->alloc<int32_t>(n);
@@ -1032,4 +1048,134 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
                t->tpos, n, t->tree_eid);
     HIP_OK(hipGetLastError());
     ctx->sync();
+    if (t->virt_root < 0) {  // a single graph: one range covering everything
+        t->vbase = {0, (int64_t)n};
+        t->ebase = {0, t->m};
+        t->Mg = {t->M};
+        t->obase = {0, t->M};
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// batches: the disjoint union of G graphs, each graph's root linked to a virtual root
+// ------------------------------------------------------------------------------------
+struct UnionDesc {
+    const int32_t *row_ptr, *col, *parent;
+    const double *w;
+    int32_t n;
+    int32_t pad;
+    int64_t nnz, vbase, ebase;  // first union vertex and first union CSR entry
+};
+
+// union CSR rows, columns and parents; per-graph checks that the union could hide
+__global__ void k_union_fill(const UnionDesc *__restrict__ d, int32_t G, int64_t Ntot, int64_t nnz_tot,
+                             int32_t vroot, int32_t *__restrict__ rp, int32_t *__restrict__ col,
+                             double *__restrict__ w, int32_t *__restrict__ parent, int32_t *__restrict__ roots,
+                             uint32_t *flags)
+{
+    int32_t g = blockIdx.y;
+    const UnionDesc D = d[g];
+    uint32_t f = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D.n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t r = D.row_ptr[i];
+        if (i == 0 && r != 0) f |= F_ARG;
+        if (i == D.n - 1 && (int64_t)D.row_ptr[D.n] != D.nnz) f |= F_ARG;
+        rp[D.vbase + i] = (int32_t)(D.ebase + r);
+        int32_t p = D.parent[i];
+        if (p == -1) {
+            atomicAdd(&roots[g], 1);
+            parent[D.vbase + i] = vroot;
+        } else if (p < 0 || p >= D.n) {
+            f |= F_NOT_TREE;
+            parent[D.vbase + i] = -2;  // out of range in the union too
+        } else {
+            parent[D.vbase + i] = (int32_t)(D.vbase + p);
+        }
+    }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < D.nnz; k += (int64_t)gridDim.x * blockDim.x) {
+        int32_t c = D.col[k];
+        if (c < 0 || c >= D.n) f |= F_ARG;
+        col[D.ebase + k] = (int32_t)(D.vbase + c);
+        w[D.ebase + k] = D.w[k];
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        rp[Ntot] = (int32_t)nnz_tot;      // the virtual root's row is empty
+        rp[Ntot + 1] = (int32_t)nnz_tot;
+        parent[vroot] = -1;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_roots_check(const int32_t *__restrict__ roots, int32_t G, uint32_t *flags)
+{
+    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < G && roots[g] != 1) atomicOr(flags, F_NOT_TREE);
+}
+
+void prep_batch(gss_ctx ctx, gss_tree t, int32_t G, const gss_csr *gs, const int32_t *const *parents, uint32_t flags)
+{
+    hipStream_t st = ctx->stream;
+    std::vector<UnionDesc> hd(G);
+    int64_t N = 0, E = 0;
+    t->vbase.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; g++) {
+        hd[g].row_ptr = gs[g].row_ptr;
+        hd[g].col = gs[g].col;
+        hd[g].w = gs[g].w;
+        hd[g].parent = parents[g];
+        hd[g].n = gs[g].n;
+        hd[g].pad = 0;
+        hd[g].nnz = gs[g].nnz;
+        hd[g].vbase = N;
+        hd[g].ebase = E;
+        t->vbase[g] = N;
+        N += gs[g].n;
+        E += gs[g].nnz;
+    }
+    t->vbase[G] = N;
+    if (N + 1 >= (1 << 30) || E >= ((int64_t)1 << 31)) fail(GSS_ERR_ARG, "batch too large");
+    const int32_t n = (int32_t)(N + 1);
+    t->n = n;
+    t->nnz = E;
+    t->G = G;
+    t->virt_root = (int32_t)N;
+    t->own_row_ptr = ctx->alloc<int32_t>(n + 1);
+    t->own_col = ctx->alloc<int32_t>(E + 1);
+    t->own_w = ctx->alloc<double>(E + 1);
+    t->own_parent = ctx->alloc<int32_t>(n);
+    t->row_ptr = t->own_row_ptr;
+    t->col = t->own_col;
+    t->w = t->own_w;
+    t->parent = t->own_parent;
+    std::vector<int32_t> vb32(G + 1);
+    for (int32_t g = 0; g <= G; g++) vb32[g] = (int32_t)t->vbase[g];
+    t->d_vbase = ctx->alloc<int32_t>(G + 1);
+    UnionDesc *dd = ctx->alloc<UnionDesc>(G);
+    int32_t *roots = ctx->alloc<int32_t>(G);
+    HIP_OK(hipMemcpyAsync(t->d_vbase, vb32.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(dd, hd.data(), sizeof(UnionDesc) * G, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemsetAsync(roots, 0, sizeof(int32_t) * G, st));
+    HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+    GSS_LAUNCH(k_union_fill, dim3(64, G), dim3(PB), 0, st, dd, G, N, E, t->virt_root, t->own_row_ptr, t->own_col,
+               t->own_w, t->own_parent, roots, ctx->d_flags);
+    GSS_LAUNCH(k_roots_check, dim3(grid_for(G, PB)), dim3(PB), 0, st, roots, G, ctx->d_flags);
+    uint32_t f = read_flags(ctx);
+    ctx->free(dd);
+    ctx->free(roots);
+    if (f) fail(status_from_flags(f), "invalid graph in the batch");
+    prep_tree(ctx, t, flags);
+    // per-graph edge and off-tree ranges
+    t->ebase.assign(G + 1, 0);
+    std::vector<int32_t> up(G + 1);
+    for (int32_t g = 0; g <= G; g++) {
+        HIP_OK(hipMemcpyAsync(&up[g], t->uptr + t->vbase[g], sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
+    ctx->sync();
+    for (int32_t g = 0; g <= G; g++) t->ebase[g] = up[g];
+    t->Mg.assign(G, 0);
+    t->obase.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; g++) {
+        t->Mg[g] = (t->ebase[g + 1] - t->ebase[g]) - (gs[g].n - 1);
+        t->obase[g + 1] = t->obase[g] + t->Mg[g];
+    }
 }

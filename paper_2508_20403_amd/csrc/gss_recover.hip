@@ -116,7 +116,7 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
         lca[j] = l;
         bst[j] = (uint8_t)b;
         if (stretch_out) stretch_out[off_id[j]] = s;
-        atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
+        if (hist) atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
     }
     // subtask sizes: lanes sharing the first lane's LCA add once (skewed graphs put most
     // edges on a few LCAs), the others add individually
@@ -131,8 +131,9 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < SEL_BINS; i += RB)
-        if (sh[i]) atomicAdd(&hist[i], sh[i]);
+    if (hist)
+        for (int i = threadIdx.x; i < SEL_BINS; i += RB)
+            if (sh[i]) atomicAdd(&hist[i], sh[i]);
 }
 
 // number of subtasks (non-zero LCA counts) and the largest
@@ -166,38 +167,58 @@ __global__ __launch_bounds__(RB) void k_lca_stats(const int32_t *__restrict__ lc
 }
 
 // ------------------------------------------------------------------------------------
-// 2. radix select of the prefix threshold
+// 2. radix select of each graph's prefix threshold
 // ------------------------------------------------------------------------------------
-// histogram of key digit [shift, shift+width) over eligible keys matching the prefix
-__global__ __launch_bounds__(RB) void k_key_hist(const uint64_t *__restrict__ key, int64_t M, int shift,
-                                                 int width, uint64_t pmask, uint64_t pval,
-                                                 uint32_t *__restrict__ hist)
+// histogram of key digit [shift, shift+width) over eligible keys of refining graphs whose
+// higher digits match that graph's selected prefix; hist is [G][SEL_BINS]
+__global__ __launch_bounds__(RB) void k_key_hist(const uint64_t *__restrict__ key, int64_t M,
+                                                 const int32_t *__restrict__ off_g, int shift, int width,
+                                                 const uint64_t *__restrict__ pmask, const uint64_t *__restrict__ pval,
+                                                 const int64_t *__restrict__ need, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t sh[SEL_BINS];
+    __shared__ int32_t gblk;
     for (int i = threadIdx.x; i < SEL_BINS; i += RB) sh[i] = 0;
+    const int64_t per = ((M + gridDim.x - 1) / gridDim.x + RB - 1) / RB * RB;  // contiguous range per block
+    const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(M, j0 + per);
+    if (threadIdx.x == 0) gblk = (off_g && j0 < M) ? off_g[j0] : 0;
     __syncthreads();
-    uint32_t dmask = (1u << width) - 1;
-    for (int64_t j = (int64_t)blockIdx.x * RB + threadIdx.x; j < M; j += (int64_t)gridDim.x * RB) {
+    const uint32_t dmask = (1u << width) - 1;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += RB) {
         uint64_t k = key[j];
-        if (k != 0 && (k & pmask) == pval) atomicAdd(&sh[(uint32_t)(k >> shift) & dmask], 1u);
+        int32_t g = off_g ? off_g[j] : 0;
+        if (k == 0 || need[g] <= 0 || (k & pmask[g]) != pval[g]) continue;
+        uint32_t d = (uint32_t)(k >> shift) & dmask;
+        if (g == gblk) atomicAdd(&sh[d], 1u);
+        else atomicAdd(&hist[(int64_t)g * SEL_BINS + d], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < SEL_BINS; i += RB)
-        if (sh[i]) atomicAdd(&hist[i], sh[i]);
+        if (sh[i]) atomicAdd(&hist[(int64_t)gblk * SEL_BINS + i], sh[i]);
 }
 
-// digit holding the need-th largest element; writes {digit, count above it, its count}
+// per graph (block): digit holding the need-th largest key -> {digit, count above, count}
 __global__ __launch_bounds__(1024) void k_pick_bucket(const uint32_t *__restrict__ hist, int width,
-                                                      int64_t need, int64_t *out)
+                                                      const int64_t *__restrict__ need_in, int64_t *out)
 {
     __shared__ int64_t lds[1024 / GSS_WAVE + 1];
+    const int g = blockIdx.x;
+    const int64_t need = need_in[g];
+    if (need <= 0) {
+        if (threadIdx.x == 0) {
+            out[3 * g] = -2;
+            out[3 * g + 1] = 0;
+            out[3 * g + 2] = 0;
+        }
+        return;
+    }
+    const uint32_t *h = hist + (int64_t)g * SEL_BINS;
     const int nb = 1 << width;
     const int per = (nb + 1023) / 1024;
-    // thread t owns digits (from the top) [t*per, t*per+per)
     int64_t s = 0;
     for (int i = 0; i < per; i++) {
         int r = threadIdx.x * per + i;
-        if (r < nb) s += hist[nb - 1 - r];
+        if (r < nb) s += h[nb - 1 - r];
     }
     int64_t tot;
     int64_t before = block_exclusive_scan<int64_t>(s, lds, &tot);
@@ -206,43 +227,56 @@ __global__ __launch_bounds__(1024) void k_pick_bucket(const uint32_t *__restrict
         for (int i = 0; i < per; i++) {
             int r = threadIdx.x * per + i;
             if (r >= nb) break;
-            int64_t h = hist[nb - 1 - r];
-            if (acc + h >= need) {
-                out[0] = nb - 1 - r;
-                out[1] = acc;
-                out[2] = h;
+            int64_t c = h[nb - 1 - r];
+            if (acc + c >= need) {
+                out[3 * g] = nb - 1 - r;
+                out[3 * g + 1] = acc;
+                out[3 * g + 2] = c;
                 break;
             }
-            acc += h;
+            acc += c;
         }
     }
     if (threadIdx.x == 0 && tot < need) {
-        out[0] = -1;
-        out[1] = tot;
-        out[2] = 0;
+        out[3 * g] = -1;
+        out[3 * g + 1] = tot;
+        out[3 * g + 2] = 0;
     }
 }
 
 // ------------------------------------------------------------------------------------
-// 3. compaction of {key >= T} (id order) and the stable radix sort
+// 3. compaction of {key >= T[graph]} (id order, hence graph-major) and the radix sort
 // ------------------------------------------------------------------------------------
-__global__ void k_prefix_count(const uint64_t *__restrict__ key, int64_t M, uint64_t T,
-                               int32_t *__restrict__ cnt)
+__global__ void k_prefix_count(const uint64_t *__restrict__ key, int64_t M, const int32_t *__restrict__ off_g,
+                               const uint64_t *__restrict__ thr, int32_t *__restrict__ cnt,
+                               unsigned long long *__restrict__ gcount)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t j0 = t * CHUNK;
     if (j0 >= M) return;
     int32_t c = 0;
+    int32_t gcur = -1, gc = 0;
     for (int i = 0; i < CHUNK; i++) {
         int64_t j = j0 + i;
-        if (j < M && key[j] >= T) c++;
+        if (j >= M) break;
+        int32_t g = off_g ? off_g[j] : 0;
+        if (key[j] >= thr[g]) {
+            c++;
+            if (g != gcur) {
+                if (gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
+                gcur = g;
+                gc = 0;
+            }
+            gc++;
+        }
     }
+    if (gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
     cnt[t] = c;
 }
 
-__global__ void k_prefix_write(const uint64_t *__restrict__ key, int64_t M, uint64_t T,
-                               const int32_t *__restrict__ off, int32_t *__restrict__ pj,
-                               uint64_t *__restrict__ pk)
+__global__ void k_prefix_write(const uint64_t *__restrict__ key, int64_t M, const int32_t *__restrict__ off_g,
+                               const uint64_t *__restrict__ thr, const int32_t *__restrict__ off,
+                               int32_t *__restrict__ pj, uint64_t *__restrict__ pk)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t j0 = t * CHUNK;
@@ -252,13 +286,21 @@ __global__ void k_prefix_write(const uint64_t *__restrict__ key, int64_t M, uint
         int64_t j = j0 + i;
         if (j < M) {
             uint64_t k = key[j];
-            if (k >= T) {
+            if (k >= thr[off_g ? off_g[j] : 0]) {
                 pj[q] = (int32_t)j;
                 pk[q] = ~k;  // ascending order of ~key = descending stretch
                 q++;
             }
         }
     }
+}
+
+// graph id of each compacted edge, as a sort key
+__global__ void k_graph_key(int64_t P, const int32_t *__restrict__ pj, const int32_t *__restrict__ off_g,
+                            uint64_t *__restrict__ gk)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) gk[p] = (uint64_t)(uint32_t)off_g[pj[p]];
 }
 
 __global__ __launch_bounds__(1024) void k_key_varying(const uint64_t *__restrict__ k, int64_t n,
@@ -525,40 +567,46 @@ __global__ __launch_bounds__(1024) void k_resolve(int64_t A, const int2 *__restr
 // ------------------------------------------------------------------------------------
 // 6. selection of the first `need` recovered edges in rank order
 // ------------------------------------------------------------------------------------
-__global__ void k_cand_count(int64_t P, const uint8_t *__restrict__ state, int32_t *__restrict__ cnt)
+// candidate flags (1 = recovered) per rank, scanned into ranks among candidates
+__global__ void k_cand_flags(int64_t P, const uint8_t *__restrict__ state, int32_t *__restrict__ flag)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t p0 = t * CHUNK;
-    if (p0 >= P) return;
-    int32_t c = 0;
-    for (int i = 0; i < CHUNK; i++) {
-        int64_t p = p0 + i;
-        if (p < P && state[p] == ST_CAND) c++;
-    }
-    cnt[t] = c;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) flag[p] = state[p] == ST_CAND ? 1 : 0;
+    if (p == P) flag[p] = 0;
 }
 
-__global__ void k_cand_write(int64_t P, const uint8_t *__restrict__ state, const int32_t *__restrict__ off,
-                             int64_t need, const int32_t *__restrict__ rid, const int32_t *__restrict__ sj,
-                             int32_t *__restrict__ order, int64_t order_base, uint8_t *__restrict__ mask,
+// per graph: candidates in its rank range [pstart[g], pstart[g+1])
+__global__ void k_cand_per_graph(int32_t G, const int64_t *__restrict__ pstart, const int32_t *__restrict__ candq,
+                                 int64_t *__restrict__ out)
+{
+    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < G) out[g] = (int64_t)candq[pstart[g + 1]] - (int64_t)candq[pstart[g]];
+}
+
+struct GraphOut {
+    int32_t *order;      // may be null
+    uint8_t *mask;
+    int64_t ebase;       // union edge id of the graph's first edge
+    int64_t nrec;        // edges already recovered (earlier passes)
+    int64_t take;        // candidates to take now
+    int64_t pstart;      // first rank of the graph in the prefix
+};
+
+__global__ void k_cand_write(int64_t P, const uint8_t *__restrict__ state, const int32_t *__restrict__ candq,
+                             const int32_t *__restrict__ rg, const GraphOut *__restrict__ go,
+                             const int32_t *__restrict__ rid, const int32_t *__restrict__ sj,
                              uint64_t *__restrict__ key)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t p0 = t * CHUNK;
-    if (p0 >= P) return;
-    int64_t q = off[t];
-    for (int i = 0; i < CHUNK; i++) {
-        int64_t p = p0 + i;
-        if (p < P && state[p] == ST_CAND) {
-            if (q < need) {
-                int32_t id = rid[p];
-                if (order) order[order_base + q] = id;
-                mask[id] = 1;
-                key[sj[p]] = 0;  // recovered: leaves the pool of later passes
-            }
-            q++;
-        }
-    }
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P || state[p] != ST_CAND) return;
+    const int32_t g = rg ? rg[p] : 0;
+    const GraphOut o = go[g];
+    int64_t r = (int64_t)candq[p] - (int64_t)candq[o.pstart];
+    if (r >= o.take) return;
+    int32_t local = (int32_t)(rid[p] - o.ebase);
+    if (o.order) o.order[o.nrec + r] = local;
+    o.mask[local] = 1;
+    key[sj[p]] = 0;  // recovered: leaves the pool of later passes
 }
 
 __global__ void k_fill_i32_r(int32_t *p, int64_t n, int32_t v)
@@ -567,10 +615,39 @@ __global__ void k_fill_i32_r(int32_t *p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_mask_tree(const int32_t *__restrict__ tree_eid, int32_t n, uint8_t *__restrict__ mask)
+__global__ void k_mask_tree(const int32_t *__restrict__ tree_eid, int32_t x0, int32_t x1, int64_t ebase,
+                            uint8_t *__restrict__ mask)
 {
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < n && tree_eid[x] >= 0) mask[tree_eid[x]] = 1;
+    int32_t x = x0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < x1 && tree_eid[x] >= 0) mask[tree_eid[x] - ebase] = 1;
+}
+
+// subtask statistics of one graph (block) over its vertex range
+__global__ __launch_bounds__(RB) void k_lca_stats_g(const int32_t *__restrict__ lcacnt,
+                                                    const int32_t *__restrict__ vbase, int64_t *__restrict__ out)
+{
+    __shared__ int64_t snz[RB], smx[RB];
+    int32_t g = blockIdx.x;
+    int64_t nz = 0, mx = 0;
+    for (int32_t x = vbase[g] + threadIdx.x; x < vbase[g + 1]; x += RB) {
+        int32_t c = lcacnt[x];
+        nz += c > 0;
+        mx = c > mx ? c : mx;
+    }
+    snz[threadIdx.x] = nz;
+    smx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            snz[threadIdx.x] += snz[threadIdx.x + h];
+            smx[threadIdx.x] = max(smx[threadIdx.x], smx[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * g] = snz[0];
+        out[2 * g + 1] = smx[0];
+    }
 }
 
 __global__ void k_edge_lca_out(int64_t M, const int32_t *__restrict__ off_id, const int32_t *__restrict__ lca,
@@ -635,44 +712,72 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
 }
 
 struct PrefixResult {
-    int64_t P = 0, cand = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0;
+    int64_t P = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0;
+    std::vector<int64_t> Pg, cand;  // per graph
 };
 
-// resolves the prefix {key >= T}; leaves state/rid/sj for the caller to select from
 struct PrefixBufs {
     int32_t *sj = nullptr, *rid = nullptr, *ancU = nullptr, *ancV = nullptr, *indeg = nullptr, *mcnt = nullptr;
-    int32_t *ccnt = nullptr, *ru = nullptr, *rv = nullptr, *rdu = nullptr, *rdv = nullptr, *rl = nullptr;
-    int32_t *grp = nullptr, *sub_ptr = nullptr, *sub_lca = nullptr;
+    int32_t *ru = nullptr, *rv = nullptr, *rdu = nullptr, *rdv = nullptr, *rl = nullptr, *rg = nullptr;
+    int32_t *grp = nullptr, *sub_ptr = nullptr, *sub_lca = nullptr, *candq = nullptr;
+    int64_t *pstart = nullptr;
     uint8_t *rb = nullptr, *state = nullptr, *is_global = nullptr;
     void release(gss_ctx ctx)
     {
-        void *ps[] = {sj, rid, ancU, ancV, indeg, mcnt, ccnt, ru, rv, rdu, rdv, rl, grp, sub_ptr, sub_lca, rb, state,
-                      is_global};
+        void *ps[] = {sj, rid, ancU,    ancV,    indeg, mcnt,  ru,        rv,    rdu,   rdv,
+                      rl, rg,  grp,     sub_ptr, sub_lca, candq, pstart, rb,    state, is_global};
         for (void *p : ps) ctx->free(p);
         *this = PrefixBufs();
     }
 };
 
+__global__ void k_rank_graph(int64_t P, const int32_t *__restrict__ sj, const int32_t *__restrict__ off_g,
+                             int32_t *__restrict__ rg)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) rg[p] = off_g[sj[p]];
+}
+
+// Resolves, for every graph g, the prefix {key >= thr[g]} of its criticality order.
 static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uint64_t *key, const uint8_t *bst,
-                                   const int32_t *lca, const int32_t *lcacnt, uint64_t T, PrefixBufs &B,
+                                   const int32_t *lca, const int32_t *lcacnt, const uint64_t *thr, PrefixBufs &B,
                                    const gss_params *prm)
 {
     hipStream_t st = ctx->stream;
     const int64_t M = t->M;
+    const int32_t G = t->G;
+    const int32_t *off_g = (G > 1) ? t->off_g : nullptr;
     PrefixResult res;
     std::vector<void *> scratch;
-    // compaction (id order)
+    // compaction (id order: graph-major)
     int64_t nthr = (M + CHUNK - 1) / CHUNK;
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
-    GSS_LAUNCH(k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc);
+    unsigned long long *gcount = ctx->alloc<unsigned long long>(G);
+    HIP_OK(hipMemsetAsync(gcount, 0, sizeof(unsigned long long) * G, st));
+    GSS_LAUNCH(k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, gcount);
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
+    res.Pg.assign(G, 0);
+    HIP_OK(hipMemcpyAsync(res.Pg.data(), gcount, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
     uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
-    GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, T, pc, v1, k1);
+    GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, v1, k1);
     ctx->free(pc);
-    radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // rank order: v1[p] = off-tree index of rank p
+    ctx->free(gcount);
+    radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
+    if (G > 1) {  // stable by graph: each graph's prefix becomes contiguous, in rank order
+        GSS_LAUNCH(k_graph_key, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, v1, t->off_g, k1);
+        radix_sort_pairs(ctx, k1, v1, k2, v2, P);
+    }
     B.sj = v1;
+    std::vector<int64_t> ps(G + 1, 0);
+    for (int32_t g = 0; g < G; g++) ps[g + 1] = ps[g] + res.Pg[g];
+    B.pstart = ctx->alloc<int64_t>(G + 1);
+    HIP_OK(hipMemcpyAsync(B.pstart, ps.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+    if (G > 1) {
+        B.rg = ctx->alloc<int32_t>(P + 1);
+        GSS_LAUNCH(k_rank_graph, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_g, B.rg);
+    }
     // per-rank data, and (lca, rank) pairs for the grouping
     B.rid = ctx->alloc<int32_t>(P + 1);
     B.rb = ctx->alloc<uint8_t>(P + 1);
@@ -688,7 +793,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     GSS_LAUNCH(k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_id, t->off_u, t->off_v, bst,
                lca, t->vrec, c, B.rid, B.rb, B.ru, B.rv, B.rdu, B.rdv, B.rl, lkey, lval, B.ancU, B.ancV);
 
-    // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA
+    // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA.  LCAs
+    // of different graphs of a batch are different vertices, so subtasks never mix graphs.
     radix_sort_pairs(ctx, lkey, lval, lkey2, lval2, P);
     B.grp = lval;
     scratch.push_back(lkey2);
@@ -805,81 +911,151 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         }
         ctx->free(tab);
     }
-    int64_t nthr2 = (P + CHUNK - 1) / CHUNK;
-    B.ccnt = ctx->alloc<int32_t>(nthr2 + 1);
-    GSS_LAUNCH(k_cand_count, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, P, B.state, B.ccnt);
-    res.cand = scan_exclusive_i32(ctx, B.ccnt, nthr2, true);
+    // candidates per graph (ranks among the recovered edges)
+    B.candq = ctx->alloc<int32_t>(P + 2);
+    GSS_LAUNCH(k_cand_flags, dim3(grid_for(P + 1, RB)), dim3(RB), 0, st, P, B.state, B.candq);
+    scan_exclusive_i32(ctx, B.candq, P + 1, false);
+    int64_t *cg = ctx->alloc<int64_t>(G);
+    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, cg);
+    res.cand.assign(G, 0);
+    HIP_OK(hipMemcpyAsync(res.cand.data(), cg, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
+    ctx->sync();
+    ctx->free(cg);
     if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, feat, cycles, qv, nlocal);
     for (void *p : scratch) ctx->free(p);
     return res;
 }
 
-// threshold T such that {key >= T} holds at least `want` eligible edges (and not many more)
-static uint64_t select_threshold(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist, bool hist_ready,
-                                 int64_t want, int64_t eligible)
+// Per graph, a key threshold T such that {key >= T} holds at least want[g] eligible edges
+// (and not many more).  want[g] <= 0: graph not selected (threshold above every key).
+static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist,
+                                               bool hist_ready, const std::vector<int64_t> &want,
+                                               const std::vector<int64_t> &eligible)
 {
     hipStream_t st = ctx->stream;
-    if (want >= eligible) return 1;  // every eligible key is >= 1
+    const int32_t G = t->G;
+    const int32_t *off_g = (G > 1) ? t->off_g : nullptr;
+    std::vector<uint64_t> thr(G, ~0ull), pmask(G, 0), pval(G, 0);
+    std::vector<int64_t> above(G, 0), need(G, 0);
+    bool any = false;
+    for (int32_t g = 0; g < G; g++) {
+        if (want[g] <= 0) continue;
+        if (want[g] >= eligible[g]) {
+            thr[g] = 1;  // every eligible key is >= 1
+            continue;
+        }
+        need[g] = want[g];
+        any = true;
+    }
     const int shifts[6] = {51, 39, 27, 15, 3, 0};
     const int widths[6] = {12, 12, 12, 12, 12, 3};
-    uint64_t pmask = 0, pval = 0;
-    int64_t above = 0;
-    const int64_t slack = std::max<int64_t>(1024, want / 16);
-    for (int lv = 0; lv < 6; lv++) {
-        if (lv > 0 || !hist_ready) {
-            HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
-            GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key,
-                               t->M, shifts[lv], widths[lv], pmask, pval, hist);
+    int64_t *dneed = ctx->alloc<int64_t>(G);
+    uint64_t *dpm = ctx->alloc<uint64_t>(G), *dpv = ctx->alloc<uint64_t>(G);
+    int64_t *dout = ctx->alloc<int64_t>(3 * G);
+    std::vector<int64_t> out(3 * G);
+    for (int lv = 0; lv < 6 && any; lv++) {
+        std::vector<int64_t> needl(G, 0);
+        for (int32_t g = 0; g < G; g++) needl[g] = need[g] > 0 ? need[g] - above[g] : 0;
+        HIP_OK(hipMemcpyAsync(dneed, needl.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
+        if (lv > 0 || !hist_ready || G > 1) {
+            HIP_OK(hipMemcpyAsync(dpm, pmask.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
+            HIP_OK(hipMemcpyAsync(dpv, pval.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
+            HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS * G, st));
+            GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key, t->M,
+                       off_g, shifts[lv], widths[lv], dpm, dpv, dneed, hist);
         }
-        GSS_LAUNCH(k_pick_bucket, dim3(1), dim3(1024), 0, st, hist, widths[lv], want - above,
-                           ctx->d_counters);
-        HIP_OK(hipGetLastError());
-        read_counters(ctx, 3);
-        int64_t d = ctx->h_counters[0], cum = ctx->h_counters[1], cnt = ctx->h_counters[2];
-        if (d < 0) return 1;  // fewer than `want` keys: take everything
-        uint64_t dmask = ((1ull << widths[lv]) - 1) << shifts[lv];
-        pmask |= dmask;
-        pval |= (uint64_t)d << shifts[lv];
-        above += cum;
-        if (above + cnt - want <= slack || lv == 5) return pval;  // lowest key of the bucket
+        GSS_LAUNCH(k_pick_bucket, dim3(G), dim3(1024), 0, st, hist, widths[lv], dneed, dout);
+        HIP_OK(hipMemcpyAsync(out.data(), dout, sizeof(int64_t) * 3 * G, hipMemcpyDeviceToHost, st));
+        ctx->sync();
+        any = false;
+        const int64_t dmask = ((1ll << widths[lv]) - 1);
+        for (int32_t g = 0; g < G; g++) {
+            if (need[g] <= 0) continue;
+            int64_t d = out[3 * g], cum = out[3 * g + 1], cnt = out[3 * g + 2];
+            if (d < 0) {  // fewer keys than wanted: take everything
+                thr[g] = 1;
+                need[g] = 0;
+                continue;
+            }
+            pmask[g] |= (uint64_t)dmask << shifts[lv];
+            pval[g] |= (uint64_t)d << shifts[lv];
+            above[g] += cum;
+            const int64_t slack = std::max<int64_t>(1024, need[g] / 16);
+            thr[g] = pval[g];  // lowest key of the bucket
+            if (above[g] + cnt - need[g] <= slack || lv == 5) need[g] = 0;
+            else any = true;
+        }
     }
-    return pval;
+    ctx->free(dneed);
+    ctx->free(dpm);
+    ctx->free(dpv);
+    ctx->free(dout);
+    return thr;
 }
 
-gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prm, uint8_t *mask, int32_t *order,
-                        double *stretch, gss_info *info)
+// Recovery of every graph of a tree (a single graph, or a batch).
+gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t *const *masks,
+                        int32_t *const *orders, double *stretch, gss_info *infos)
 {
     hipStream_t st = ctx->stream;
-    const int32_t n = t->n;
-    const int64_t M = t->M, m = t->m;
-    const int32_t c = prm->beta;
-    const int64_t K = prm->k_override >= 0 ? prm->k_override : (int64_t)std::floor(prm->alpha * (double)n);
-
-    HIP_OK(hipMemsetAsync(mask, 0, (size_t)m, st));
-    if (stretch) HIP_OK(hipMemsetAsync(stretch, 0, sizeof(double) * (size_t)m, st));
-    if (prm->flags & GSS_F_MASK_TREE)
-        GSS_LAUNCH(k_mask_tree, dim3(grid_for(n, RB)), dim3(RB), 0, st, t->tree_eid, n, mask);
+    const int32_t n = t->n, G = t->G;
+    const int64_t M = t->M;
+    const int32_t c = prms[0].beta;
+    for (int32_t g = 1; g < G; g++)
+        if (prms[g].beta != c || prms[g].sched != prms[0].sched)
+            throw gss_error{GSS_ERR_ARG, "all graphs of a batch need the same beta and schedule"};
+    std::vector<int64_t> K(G), nrec(G, 0), eligible(G), want(G), mg(G);
+    std::vector<int32_t> passes(G, 0);
+    std::vector<int64_t> lastP(G, 0), nsubg(G, 0), largest(G, 0);
+    std::vector<bool> active(G);
+    for (int32_t g = 0; g < G; g++) {
+        const int64_t ng = t->vbase[g + 1] - t->vbase[g];
+        K[g] = prms[g].k_override >= 0 ? prms[g].k_override : (int64_t)std::floor(prms[g].alpha * (double)ng);
+        mg[g] = t->ebase[g + 1] - t->ebase[g];
+        eligible[g] = t->Mg[g];
+        HIP_OK(hipMemsetAsync(masks[g], 0, (size_t)mg[g], st));
+        if (prms[g].flags & GSS_F_MASK_TREE) {
+            int32_t x0 = (int32_t)t->vbase[g], x1 = (int32_t)t->vbase[g + 1];
+            GSS_LAUNCH(k_mask_tree, dim3(grid_for(x1 - x0, RB)), dim3(RB), 0, st, t->tree_eid, x0, x1, t->ebase[g],
+                       masks[g]);
+        }
+    }
+    if (stretch) HIP_OK(hipMemsetAsync(stretch, 0, sizeof(double) * (size_t)t->m, st));
     HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
 
     uint64_t *key = ctx->alloc<uint64_t>(M + 1);
     int32_t *lca = ctx->alloc<int32_t>(M + 1);
     uint8_t *bst = ctx->alloc<uint8_t>(M + 1);
-    uint32_t *hist = ctx->alloc<uint32_t>(SEL_BINS);
+    uint32_t *hist = ctx->alloc<uint32_t>((int64_t)SEL_BINS * G);
     int32_t *lcacnt = ctx->alloc<int32_t>(n);
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
     if (M > 0)
-        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u,
-                           t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
-                           stretch, hist, lcacnt, ctx->d_flags);
+        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u, t->off_v, t->off_w,
+                   t->vrec, rmq_view(t), t->scale, c, key, lca, bst, stretch, G == 1 ? hist : (uint32_t *)nullptr,
+                   lcacnt, ctx->d_flags);
     HIP_OK(hipGetLastError());
-    int64_t init2[2] = {0, 0};
-    memcpy(ctx->h_counters + 2, init2, sizeof init2);
-    HIP_OK(hipMemcpyAsync(ctx->d_counters + 2, ctx->h_counters + 2, sizeof init2, hipMemcpyHostToDevice, st));
-    GSS_LAUNCH(k_lca_stats, dim3(std::min<int64_t>(grid_for(n, RB), 1024)), dim3(RB), 0, st, lcacnt, n,
-               ctx->d_counters + 2);
-    read_counters(ctx, 4);
-    int64_t nsub = ctx->h_counters[2], largest = ctx->h_counters[3];
+    if (G == 1) {
+        int64_t init2[2] = {0, 0};
+        memcpy(ctx->h_counters + 2, init2, sizeof init2);
+        HIP_OK(hipMemcpyAsync(ctx->d_counters + 2, ctx->h_counters + 2, sizeof init2, hipMemcpyHostToDevice, st));
+        GSS_LAUNCH(k_lca_stats, dim3(std::min<int64_t>(grid_for(n, RB), 1024)), dim3(RB), 0, st, lcacnt, n,
+                   ctx->d_counters + 2);
+        read_counters(ctx, 4);
+        nsubg[0] = ctx->h_counters[2];
+        largest[0] = ctx->h_counters[3];
+    } else {
+        int64_t *dst = ctx->alloc<int64_t>(2 * G);
+        std::vector<int64_t> hs(2 * G);
+        GSS_LAUNCH(k_lca_stats_g, dim3(G), dim3(RB), 0, st, lcacnt, t->d_vbase, dst);
+        HIP_OK(hipMemcpyAsync(hs.data(), dst, sizeof(int64_t) * 2 * G, hipMemcpyDeviceToHost, st));
+        ctx->sync();
+        ctx->free(dst);
+        for (int32_t g = 0; g < G; g++) {
+            nsubg[g] = hs[2 * g];
+            largest[g] = hs[2 * g + 1];
+        }
+    }
     uint32_t f = read_flags(ctx);
     auto cleanup = [&]() {
         ctx->free(key);
@@ -893,54 +1069,100 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prm, uint8_t 
         throw gss_error{GSS_ERR_RANGE, "a stretch is not a finite double"};
     }
 
-    int64_t nrec = 0, eligible = M, last_P = 0, last_arcs = 0, last_rounds = 0;
-    int32_t passes = 0;
-    bool hist_ready = true;
-    while (nrec < K && eligible > 0) {
-        int64_t need = K - nrec;
-        int64_t want = std::min<int64_t>(eligible, need + need / 4 + 1024);
+    auto first_want = [&](int32_t g) {
+        int64_t need = K[g] - nrec[g];
+        return std::min<int64_t>(eligible[g], need + need / 4 + 1024);
+    };
+    int any_active = 0;
+    for (int32_t g = 0; g < G; g++) {
+        active[g] = K[g] > 0 && eligible[g] > 0;
+        want[g] = active[g] ? first_want(g) : 0;
+        any_active |= active[g];
+    }
+    bool hist_ready = (G == 1);
+    int64_t arcs = 0, rounds = 0;
+    GraphOut *dgo = ctx->alloc<GraphOut>(G);
+    std::vector<GraphOut> go(G);
+    while (any_active) {
+        std::vector<uint64_t> thr = select_thresholds(ctx, t, key, hist, hist_ready, want, eligible);
+        hist_ready = false;
+        uint64_t *dthr = ctx->alloc<uint64_t>(G);
+        HIP_OK(hipMemcpyAsync(dthr, thr.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
         PrefixBufs B;
-        PrefixResult r;
-        for (;;) {
-            uint64_t T = select_threshold(ctx, t, key, hist, hist_ready, want, eligible);
-            hist_ready = false;
-            r = resolve_prefix(ctx, t, c, key, bst, lca, lcacnt, T, B, prm);
-            if (r.cand >= need || r.P >= eligible) break;
-            // not enough recovered edges in this prefix: a longer one is needed
-            double ratio = (double)need / (double)std::max<int64_t>(r.cand, 1);
-            int64_t next = (int64_t)((double)r.P * ratio * 1.15) + 1024;
-            want = std::min<int64_t>(eligible, std::max<int64_t>(next, r.P + 1024));
-            B.release(ctx);
+        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, lcacnt, dthr, B, &prms[0]);
+        ctx->free(dthr);
+        arcs = r.arcs;
+        rounds = r.rounds;
+        int64_t pst = 0;
+        bool write = false;
+        for (int32_t g = 0; g < G; g++) {
+            go[g].order = orders ? orders[g] : nullptr;
+            go[g].mask = masks[g];
+            go[g].ebase = t->ebase[g];
+            go[g].nrec = nrec[g];
+            go[g].take = 0;
+            go[g].pstart = pst;
+            pst += r.Pg[g];
+            if (!active[g]) continue;
+            const int64_t need = K[g] - nrec[g];
+            lastP[g] = r.Pg[g];
+            if (r.cand[g] >= need || r.Pg[g] >= eligible[g]) {
+                go[g].take = std::min<int64_t>(r.cand[g], need);
+                write |= go[g].take > 0;
+            }
         }
-        int64_t take = std::min<int64_t>(r.cand, need);
-        int64_t nthr2 = (r.P + CHUNK - 1) / CHUNK;
-        GSS_LAUNCH(k_cand_write, dim3(grid_for(nthr2, RB)), dim3(RB), 0, st, r.P, B.state, B.ccnt, take,
-                           B.rid, B.sj, order, nrec, mask, key);
-        HIP_OK(hipGetLastError());
+        if (write) {
+            HIP_OK(hipMemcpyAsync(dgo, go.data(), sizeof(GraphOut) * G, hipMemcpyHostToDevice, st));
+            GSS_LAUNCH(k_cand_write, dim3(grid_for(r.P, RB)), dim3(RB), 0, st, r.P, B.state, B.candq, B.rg, dgo,
+                       B.rid, B.sj, key);
+            HIP_OK(hipGetLastError());
+        }
+        any_active = 0;
+        for (int32_t g = 0; g < G; g++) {
+            if (!active[g]) continue;
+            const int64_t need = K[g] - nrec[g];
+            if (r.cand[g] >= need) {  // done: the first `need` candidates are final
+                nrec[g] += need;
+                eligible[g] -= need;
+                if (need > 0) passes[g]++;
+                active[g] = false;
+            } else if (r.Pg[g] >= eligible[g]) {  // the pass ended short: next pass
+                const int64_t take = r.cand[g];
+                nrec[g] += take;
+                eligible[g] -= take;
+                if (take > 0) passes[g]++;
+                active[g] = take > 0 && eligible[g] > 0 && nrec[g] < K[g];
+                if (active[g]) want[g] = first_want(g);
+            } else {  // the prefix held too few candidates: a longer one is needed
+                double ratio = (double)need / (double)std::max<int64_t>(r.cand[g], 1);
+                int64_t next = (int64_t)((double)r.Pg[g] * ratio * 1.15) + 1024;
+                want[g] = std::min<int64_t>(eligible[g], std::max<int64_t>(next, r.Pg[g] + 1024));
+            }
+            if (!active[g]) want[g] = 0;
+            any_active |= active[g];
+        }
         B.release(ctx);
-        last_P = r.P;
-        last_arcs = r.arcs;
-        last_rounds = r.rounds;
-        nrec += take;
-        eligible -= take;
-        if (take > 0) passes++;
-        if (take == 0) break;
     }
     ctx->sync();
+    ctx->free(dgo);
     cleanup();
-    if (info) {
-        info->m = m;
-        info->n_offtree = M;
-        info->k = K;
-        info->n_recovered = nrec;
-        info->n_subtasks = nsub;
-        info->largest_subtask = largest;
-        info->prefix_len = last_P;
-        info->n_arcs = last_arcs;
-        info->passes = passes;
-        info->rounds = (int32_t)last_rounds;
+    bool short_any = false;
+    for (int32_t g = 0; g < G; g++) {
+        short_any |= nrec[g] < K[g];
+        if (!infos) continue;
+        gss_info &info = infos[g];
+        info.m = mg[g];
+        info.n_offtree = t->Mg[g];
+        info.k = K[g];
+        info.n_recovered = nrec[g];
+        info.n_subtasks = nsubg[g];
+        info.largest_subtask = largest[g];
+        info.prefix_len = lastP[g];
+        info.n_arcs = arcs;
+        info.passes = passes[g];
+        info.rounds = (int32_t)rounds;
     }
-    return nrec < K ? GSS_SHORT : GSS_OK;
+    return short_any ? GSS_SHORT : GSS_OK;
 }
 
 void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int32_t *b_out)

@@ -28,7 +28,8 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_tree_num_edges", "gss_status_str", "gss_last_error", "gss_ctx_profile",
            "gss_ctx_profile_read", "gss_ctx_set_tuning", "gss_trace_read", "gss_trace_clear",
            "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
-           "gss_costmodel_grad"]
+           "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
+           "gss_tree_graph_edges"]
 GSS_F_RECORD = 2
 NFEAT = 12
 COSTMODEL_FLOATS = 5081
@@ -102,7 +103,13 @@ def load_library(path=LIB_PATH):
     lib.gss_costmodel_save.argtypes = [P, P]
     lib.gss_costmodel_predict.argtypes = [P, P, ctypes.c_int64, P]
     lib.gss_costmodel_grad.argtypes = [P, P, P, ctypes.c_int32, P, P]
-    for name in ("gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
+    lib.gss_batch_prep.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.gss_recover_batch.argtypes = [P, P, P, P, P, P]
+    lib.gss_tree_num_graphs.argtypes = [P]
+    lib.gss_tree_num_graphs.restype = ctypes.c_int32
+    lib.gss_tree_graph_edges.argtypes = [P, ctypes.c_int32]
+    lib.gss_tree_graph_edges.restype = ctypes.c_int64
+    for name in ("gss_batch_prep", "gss_recover_batch", "gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
                  "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca", "gss_ctx_set_tuning",
                  "gss_trace_clear", "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save",
                  "gss_costmodel_predict", "gss_costmodel_grad"):
@@ -291,6 +298,70 @@ class Tree:
         self.ctx.check(st)
         return st, mask[: self.m], (order[:k] if order is not None else None), \
             (stretch[: self.m] if stretch is not None else None), info.as_dict()
+
+    def free(self):
+        if self.handle:
+            self.ctx.lib.gss_tree_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many graphs prepared as one union (gss_batch_prep) and recovered together."""
+
+    def __init__(self, ctx, graphs, device="cuda", trusted=False):
+        self.ctx = ctx
+        self.graphs = list(graphs)
+        nb = len(self.graphs)
+        t = lambda a: torch.from_numpy(a).to(device)  # noqa: E731
+        self.arrays = [(t(g.row_ptr), t(g.col), t(g.w), t(g.parent)) for g in self.graphs]
+        csrs = (Csr * nb)()
+        parents = (ctypes.c_void_p * nb)()
+        for i, (rp, col, w, par) in enumerate(self.arrays):
+            csrs[i] = Csr(par.numel(), col.numel(), rp.data_ptr(), col.data_ptr() if col.numel() else None,
+                          w.data_ptr() if w.numel() else None)
+            parents[i] = par.data_ptr()
+        self.handle = ctypes.c_void_p()
+        st = ctx.lib.gss_batch_prep(ctx.handle, nb, ctypes.cast(csrs, ctypes.c_void_p),
+                                    ctypes.cast(parents, ctypes.c_void_p), GSS_PREP_TRUSTED if trusted else 0,
+                                    ctypes.byref(self.handle))
+        ctx.check(st)
+        self.arrays = None  # the union holds copies
+        self.m = [ctx.lib.gss_tree_graph_edges(self.handle, i) for i in range(nb)]
+        self.n = [g.n for g in self.graphs]
+
+    def recover(self, alphas=None, beta=None, sched=SCHED_EDGECOUNT, k_override=None, out=None, record=False):
+        """Returns (status, masks, orders, infos) lists over the graphs."""
+        nb = len(self.graphs)
+        dev = torch.device("cuda")
+        alphas = [g.alpha for g in self.graphs] if alphas is None else alphas
+        beta = self.graphs[0].beta if beta is None else beta
+        ks = [int(k_override[i]) if k_override is not None else int(float(alphas[i]) * float(self.n[i]) // 1)
+              for i in range(nb)]
+        if out is None:
+            masks = [torch.empty(max(self.m[i], 1), dtype=torch.uint8, device=dev) for i in range(nb)]
+            orders = [torch.empty(max(ks[i], 1), dtype=torch.int32, device=dev) for i in range(nb)]
+        else:
+            masks, orders = out
+        params = (Params * nb)()
+        for i in range(nb):
+            params[i] = Params(float(alphas[i]), int(beta), int(sched),
+                               int(k_override[i]) if k_override is not None else -1,
+                               GSS_F_RECORD if record else 0, 0)
+        mp = (ctypes.c_void_p * nb)(*[m.data_ptr() for m in masks])
+        op = (ctypes.c_void_p * nb)(*[o.data_ptr() for o in orders])
+        infos = (Info * nb)()
+        st = self.ctx.lib.gss_recover_batch(self.ctx.handle, self.handle, ctypes.cast(params, ctypes.c_void_p),
+                                            ctypes.cast(mp, ctypes.c_void_p), ctypes.cast(op, ctypes.c_void_p),
+                                            ctypes.cast(infos, ctypes.c_void_p))
+        self.ctx.check(st)
+        return st, [masks[i][: self.m[i]] for i in range(nb)], [orders[i][: ks[i]] for i in range(nb)], \
+            [infos[i].as_dict() for i in range(nb)]
 
     def free(self):
         if self.handle:
