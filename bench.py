@@ -73,6 +73,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline entry (default: dominant)")
     ap.add_argument("--breakdown", action="store_true", help="print a per-kernel time table to stderr")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch"],
+                    help="plain: one sparsifier (the headline line); batch: many graphs, plain form vs "
+                         "batched and learned-scheduled forms")
+    ap.add_argument("--graphs", default="rgg64", help="batch mode workload: rgg64, or a comma list of names")
+    ap.add_argument("--epochs", type=int, default=20, help="batch mode: cost-model training epochs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -84,6 +89,8 @@ def main():
     from paper_2508_20403_amd import gss, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.mode == "batch":
+        return bench_batch(args)
     t0 = time.time()
     g = synth.config(args.workload)
     print(f"[bench] workload {args.workload}: n={g.n} m={g.m} ({time.time() - t0:.1f}s to build)",
@@ -187,6 +194,106 @@ def main():
                    "prefix_len": info["prefix_len"], "passes": info["passes"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_batch(args):
+    """Plain form (gss_tree_prep + gss_recover per graph) against the batched form
+    (gss_batch_prep + one gss_recover_batch), with the edge-count and the learned
+    schedule.  All forms must give identical outputs."""
+    import torch
+    from paper_2508_20403_amd import gss, synth
+
+    t0 = time.time()
+    if args.graphs == "rgg64":
+        graphs = synth.batch_config()
+        desc = ("64 random geometric graphs, n log-uniform in [1e4,1e6) (sum n = %d), radius for average "
+                "degree ~10, w = 1/distance, alpha in {.02,.05,.10}, beta 2, seed 0" % sum(g.n for g in graphs))
+    else:
+        graphs = [synth.config(x) for x in args.graphs.split(",")]
+        desc = " + ".join(WORKLOADS.get(x, x) for x in args.graphs.split(","))
+    print(f"[bench] batch of {len(graphs)} graphs built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    arrays = [tuple(torch.from_numpy(a).to(dev) for a in (g.row_ptr, g.col, g.w, g.parent)) for g in graphs]
+    Ks = [synth.k_of(g.alpha, g.n) for g in graphs]
+    outs = [(torch.empty(max(g.m, 1), dtype=torch.uint8, device=dev), torch.empty(max(k, 1), dtype=torch.int32,
+                                                                                   device=dev)) for g, k in zip(graphs, Ks)]
+    bmasks = [torch.empty(max(g.m, 1), dtype=torch.uint8, device=dev) for g in graphs]
+    borders = [torch.empty(max(k, 1), dtype=torch.int32, device=dev) for k in Ks]
+    torch.cuda.synchronize()
+    ctx = gss.Context(0, torch.cuda.current_stream())
+
+    def plain_step():
+        for g, (rp, col, w, par), (mk, od) in zip(graphs, arrays, outs):
+            tr = gss.Tree(ctx, rp, col, w, par)
+            tr.recover(g.alpha, g.beta, out=(mk, od, None))
+            tr.free()
+
+    def batch_step(sched):
+        b = gss.Batch(ctx, graphs, arrays=arrays)
+        b.recover(sched=sched, out=(bmasks, borders))
+        b.free()
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps
+
+    for _ in range(max(args.warmup, 1)):
+        plain_step()
+        batch_step(gss.SCHED_EDGECOUNT)
+    # autotune the work queue on this batch (untimed, cached per device and workload)
+    b = gss.Batch(ctx, graphs, arrays=arrays)
+    lm, lb, tms = b.autotune(os.path.join(ROOT, "_data", "autotune.txt"))
+    print(f"[bench] autotune: local_max={lm} blocks={lb} ({tms:.3f} ms)", file=sys.stderr, flush=True)
+    # the plain kernel records per-subtask cycles; the cost model trains on them (untimed)
+    ctx.trace_clear()
+    for _ in range(3):
+        b.recover(record=True, out=(bmasks, borders))
+    feat, cyc, size = ctx.trace_read()
+    ctx.trace_clear()
+    b.free()
+    t = time.perf_counter()
+    loss = ctx.costmodel_train(feat, cyc, epochs=args.epochs, lr=1e-3, seed=0)
+    train_s = time.perf_counter() - t
+    print(f"[bench] cost model: {len(cyc)} samples, loss {loss[0]:.3f} -> {loss[-1]:.3f}, {train_s:.2f}s",
+          file=sys.stderr, flush=True)
+
+    steps = max(args.steps // 4, 2)
+    ms_plain = timed(plain_step, steps)
+    ref = [(mk[:g.m].cpu().numpy().copy(), od[:k].cpu().numpy().copy()) for g, (mk, od), k in zip(graphs, outs, Ks)]
+    ms_batch = timed(lambda: batch_step(gss.SCHED_EDGECOUNT), steps)
+    same_b = all(np.array_equal(bmasks[i][:g.m].cpu().numpy(), ref[i][0]) and
+                 np.array_equal(borders[i][:Ks[i]].cpu().numpy(), ref[i][1]) for i, g in enumerate(graphs))
+    ms_learn = timed(lambda: batch_step(gss.SCHED_LEARNED), steps)
+    same_l = all(np.array_equal(bmasks[i][:g.m].cpu().numpy(), ref[i][0]) and
+                 np.array_equal(borders[i][:Ks[i]].cpu().numpy(), ref[i][1]) for i, g in enumerate(graphs))
+    M = sum(g.m - g.n + 1 for g in graphs)
+    out = {
+        "metric": "off-tree edges recovered/s + ms per sparsifier, learned-sched vs plain, bit-exact",
+        "value": round(M / (ms_learn * 1e-3), 1),
+        "unit": "off-tree edges/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_learn, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "graphs": len(graphs), "offtree_edges": M,
+                   "plain_ms_per_batch": round(ms_plain, 3), "batched_ms_per_batch": round(ms_batch, 3),
+                   "batched_learned_ms_per_batch": round(ms_learn, 3),
+                   "ms_per_sparsifier_plain": round(ms_plain / len(graphs), 4),
+                   "ms_per_sparsifier_batched_learned": round(ms_learn / len(graphs), 4),
+                   "gain_batched_learned_vs_plain": round(ms_plain / ms_learn, 3),
+                   "gain_batched_vs_plain": round(ms_plain / ms_batch, 3),
+                   "gain_learned_vs_edgecount_batched": round(ms_batch / ms_learn, 3),
+                   "bit_exact_batched": bool(same_b), "bit_exact_learned": bool(same_l),
+                   "autotune": {"local_max": lm, "blocks": lb},
+                   "costmodel": {"samples": int(len(cyc)), "epochs": args.epochs,
+                                 "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
+                                 "train_s": round(train_s, 3)}},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -143,6 +143,16 @@ gss_status gss_batch_prep(gss_ctx ctx, int32_t nb, const gss_csr *graphs, const 
  * graph had fewer than K_g off-tree edges. */
 gss_status gss_recover_batch(gss_ctx ctx, gss_tree batch, const gss_params *params, uint8_t *const *masks,
                              int32_t *const *orders, gss_info *infos);
+/* Autotuner of the work-queue settings (gss_ctx_set_tuning) for a tree (a single graph or
+ * a batch) and its parameters: runs the recovery for each candidate setting, timed with
+ * HIP events on the context stream, keeps the fastest in the context and appends it to
+ * the text file cache_path (NULL: no cache; an entry for the same device and workload
+ * is reused without timing).  masks/orders as for gss_recover_batch (their contents are
+ * overwritten).  Outputs (host, may be NULL): the chosen local_max and local_blocks and
+ * the best time in ms (-1 when taken from the cache). */
+gss_status gss_autotune(gss_ctx ctx, gss_tree tree, const gss_params *params, uint8_t *const *masks,
+                        int32_t *const *orders, const char *cache_path, int32_t *local_max, int32_t *local_blocks,
+                        double *best_ms);
 /* Number of graphs of a tree (1 for gss_tree_prep) and the edge count m_g of graph g. */
 int32_t gss_tree_num_graphs(gss_tree tree);
 int64_t gss_tree_graph_edges(gss_tree tree, int32_t g);

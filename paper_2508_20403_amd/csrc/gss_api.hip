@@ -179,6 +179,17 @@ gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, 
     });
 }
 
+gss_status gss_autotune(gss_ctx ctx, gss_tree t, const gss_params *params, uint8_t *const *masks,
+                        int32_t *const *orders, const char *cache_path, int32_t *local_max, int32_t *local_blocks,
+                        double *best_ms)
+{
+    if (!ctx || !t || !params || !masks || t->ctx != ctx) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        return autotune_impl(ctx, t, params, masks, orders, cache_path, local_max, local_blocks, best_ms);
+    });
+}
+
 gss_status gss_tree_free(gss_tree t)
 {
     if (!t) return GSS_ERR_ARG;

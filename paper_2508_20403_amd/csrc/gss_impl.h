@@ -138,6 +138,9 @@ void free_tree_arrays(gss_tree t);
 gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t *const *masks,
                         int32_t *const *orders, double *stretch, gss_info *infos);
 void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar);
+gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *const *masks,
+                         int32_t *const *orders, const char *cache_path, int32_t *out_lm, int32_t *out_lb,
+                         double *out_ms);
 
 // ---- shared launch helpers (gss_prims.hip) -------------------------------------------
 // exclusive scan of int32 counts in place over [0,n); returns the total (host sync)

@@ -1,0 +1,103 @@
+// gss_tune.hip -- autotuner of the subtask work queue (largest subtask on the persistent
+// kernel, workgroups of that kernel).  Times each candidate on the context stream with
+// HIP events over a full recovery and keeps the fastest; results are cached in a text
+// file keyed by device name and workload signature.  The output never depends on the
+// setting (tests check it), so tuning only changes speed.
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <string>
+
+#include "gss_impl.h"
+
+static std::string tune_key(gss_ctx ctx, gss_tree t, const gss_params *p)
+{
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, ctx->device));
+    std::ostringstream k;
+    k << prop.gcnArchName << "|cu" << prop.multiProcessorCount << "|G" << t->G << "|n" << t->n << "|m" << t->m
+      << "|M" << t->M << "|b" << p[0].beta;
+    for (int32_t g = 0; g < t->G && g < 4; g++) k << "|a" << p[g].alpha << "k" << p[g].k_override;
+    std::string s = k.str();
+    for (char &c : s)
+        if (c == ' ') c = '_';
+    return s;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, int32_t &lm, int32_t &lb)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string k;
+    int32_t a, b;
+    bool found = false;
+    while (f >> k >> a >> b)
+        if (k == key) {
+            lm = a;
+            lb = b;
+            found = true;  // the last entry wins
+        }
+    return found;
+}
+
+gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *const *masks,
+                         int32_t *const *orders, const char *cache_path, int32_t *out_lm, int32_t *out_lb,
+                         double *out_ms)
+{
+    const std::string key = tune_key(ctx, t, p);
+    int32_t lm = ctx->local_max, lb = ctx->local_blocks;
+    if (cache_lookup(cache_path, key, lm, lb)) {
+        ctx->local_max = lm;
+        ctx->local_blocks = lb;
+        if (out_lm) *out_lm = lm;
+        if (out_lb) *out_lb = lb;
+        if (out_ms) *out_ms = -1.0;
+        return GSS_OK;
+    }
+    const int32_t cand_lm[] = {64, 256, 1024};
+    const int32_t cand_lb[] = {256, 1024, 4096};
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    double best = 1e300;
+    int32_t best_lm = ctx->local_max, best_lb = ctx->local_blocks;
+    const bool saved_prof = ctx->prof;
+    ctx->prof = false;
+    for (int32_t m : cand_lm)
+        for (int32_t bl : cand_lb) {
+            ctx->local_max = m;
+            ctx->local_blocks = bl;
+            double t_best = 1e300;
+            for (int rep = 0; rep < 2; rep++) {
+                HIP_OK(hipEventRecord(a, ctx->stream));
+                gss_status s = recover_impl(ctx, t, p, masks, orders, nullptr, nullptr);
+                HIP_OK(hipEventRecord(b, ctx->stream));
+                HIP_OK(hipEventSynchronize(b));
+                if (s < 0) {
+                    ctx->prof = saved_prof;
+                    return s;
+                }
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, a, b));
+                t_best = ms < t_best ? ms : t_best;
+            }
+            if (t_best < best) {
+                best = t_best;
+                best_lm = m;
+                best_lb = bl;
+            }
+        }
+    ctx->prof = saved_prof;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx->local_max = best_lm;
+    ctx->local_blocks = best_lb;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        if (f) f << key << " " << best_lm << " " << best_lb << "\n";
+    }
+    if (out_lm) *out_lm = best_lm;
+    if (out_lb) *out_lb = best_lb;
+    if (out_ms) *out_ms = best;
+    return GSS_OK;
+}

@@ -29,7 +29,7 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_ctx_profile_read", "gss_ctx_set_tuning", "gss_trace_read", "gss_trace_clear",
            "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
            "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
-           "gss_tree_graph_edges"]
+           "gss_tree_graph_edges", "gss_autotune"]
 GSS_F_RECORD = 2
 NFEAT = 12
 COSTMODEL_FLOATS = 5081
@@ -109,7 +109,9 @@ def load_library(path=LIB_PATH):
     lib.gss_tree_num_graphs.restype = ctypes.c_int32
     lib.gss_tree_graph_edges.argtypes = [P, ctypes.c_int32]
     lib.gss_tree_graph_edges.restype = ctypes.c_int64
-    for name in ("gss_batch_prep", "gss_recover_batch", "gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
+    lib.gss_autotune.argtypes = [P, P, P, P, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    for name in ("gss_autotune", "gss_batch_prep", "gss_recover_batch", "gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
                  "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca", "gss_ctx_set_tuning",
                  "gss_trace_clear", "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save",
                  "gss_costmodel_predict", "gss_costmodel_grad"):
@@ -314,12 +316,15 @@ class Tree:
 class Batch:
     """Many graphs prepared as one union (gss_batch_prep) and recovered together."""
 
-    def __init__(self, ctx, graphs, device="cuda", trusted=False):
+    def __init__(self, ctx, graphs, device="cuda", trusted=False, arrays=None):
+        """graphs: synth.Graph list; arrays: optional device tensors (row_ptr, col, w, parent)
+        per graph, already resident (else they are copied from the graphs)."""
         self.ctx = ctx
         self.graphs = list(graphs)
         nb = len(self.graphs)
         t = lambda a: torch.from_numpy(a).to(device)  # noqa: E731
-        self.arrays = [(t(g.row_ptr), t(g.col), t(g.w), t(g.parent)) for g in self.graphs]
+        self.arrays = arrays if arrays is not None else \
+            [(t(g.row_ptr), t(g.col), t(g.w), t(g.parent)) for g in self.graphs]
         csrs = (Csr * nb)()
         parents = (ctypes.c_void_p * nb)()
         for i, (rp, col, w, par) in enumerate(self.arrays):
@@ -331,9 +336,32 @@ class Batch:
                                     ctypes.cast(parents, ctypes.c_void_p), GSS_PREP_TRUSTED if trusted else 0,
                                     ctypes.byref(self.handle))
         ctx.check(st)
-        self.arrays = None  # the union holds copies
+        self.arrays = None  # the union holds copies of the graphs
         self.m = [ctx.lib.gss_tree_graph_edges(self.handle, i) for i in range(nb)]
         self.n = [g.n for g in self.graphs]
+
+    def _params(self, alphas, beta, sched, k_override, record):
+        nb = len(self.graphs)
+        params = (Params * nb)()
+        for i in range(nb):
+            params[i] = Params(float(alphas[i]), int(beta), int(sched),
+                               int(k_override[i]) if k_override is not None else -1,
+                               GSS_F_RECORD if record else 0, 0)
+        return params
+
+    def autotune(self, cache_path=None, sched=SCHED_EDGECOUNT):
+        """Picks the work-queue settings for this batch; returns (local_max, blocks, ms)."""
+        nb = len(self.graphs)
+        params = self._params([g.alpha for g in self.graphs], self.graphs[0].beta, sched, None, False)
+        dev = torch.device("cuda")
+        masks = [torch.empty(max(self.m[i], 1), dtype=torch.uint8, device=dev) for i in range(nb)]
+        mp = (ctypes.c_void_p * nb)(*[m.data_ptr() for m in masks])
+        lm, lb, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self.ctx.check(self.ctx.lib.gss_autotune(self.ctx.handle, self.handle, ctypes.cast(params, ctypes.c_void_p),
+                                                 ctypes.cast(mp, ctypes.c_void_p), None,
+                                                 cache_path.encode() if cache_path else None,
+                                                 ctypes.byref(lm), ctypes.byref(lb), ctypes.byref(ms)))
+        return lm.value, lb.value, ms.value
 
     def recover(self, alphas=None, beta=None, sched=SCHED_EDGECOUNT, k_override=None, out=None, record=False):
         """Returns (status, masks, orders, infos) lists over the graphs."""
@@ -348,11 +376,7 @@ class Batch:
             orders = [torch.empty(max(ks[i], 1), dtype=torch.int32, device=dev) for i in range(nb)]
         else:
             masks, orders = out
-        params = (Params * nb)()
-        for i in range(nb):
-            params[i] = Params(float(alphas[i]), int(beta), int(sched),
-                               int(k_override[i]) if k_override is not None else -1,
-                               GSS_F_RECORD if record else 0, 0)
+        params = self._params(alphas, beta, sched, k_override, record)
         mp = (ctypes.c_void_p * nb)(*[m.data_ptr() for m in masks])
         op = (ctypes.c_void_p * nb)(*[o.data_ptr() for o in orders])
         infos = (Info * nb)()
