@@ -78,6 +78,10 @@ def main():
                          "batched and learned-scheduled forms")
     ap.add_argument("--graphs", default="rgg64", help="batch mode workload: rgg64, or a comma list of names")
     ap.add_argument("--epochs", type=int, default=20, help="batch mode: cost-model training epochs")
+    ap.add_argument("--tuning", default=None, metavar="LOCAL_MAX,BLOCKS",
+                    help="plain mode: work-queue limits (default: the library's)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -105,6 +109,16 @@ def main():
     order = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     ctx = gss.Context(0, torch.cuda.current_stream())
+    if args.tuning:
+        lm, nb = (int(x) for x in args.tuning.split(","))
+        ctx.set_tuning(lm, nb)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         tree = gss.Tree(ctx, row_ptr, col, w, parent)

@@ -71,6 +71,8 @@ typedef struct {
 #define GSS_F_MASK_TREE 1u     /* also set mask[] = 1 on tree edges (mask = sparsifier P) */
 #define GSS_F_RECORD 2u        /* append per-subtask features and measured cycles of the work-
                                   queue kernel to the context trace (cost-model training data) */
+#define GSS_F_STATS 4u         /* fill gss_info.n_subtasks / largest_subtask (an extra per-edge
+                                  count; -1 in those fields otherwise)                     */
 
 /* gss_params.sched: order in which the subtask work queue is drained (never changes
  * the output). */
@@ -90,8 +92,8 @@ typedef struct {
     int64_t n_offtree;         /* M = m - n + 1                                          */
     int64_t k;                 /* target count K                                         */
     int64_t n_recovered;       /* min(K, M)                                              */
-    int64_t n_subtasks;        /* distinct LCAs over all off-tree edges                  */
-    int64_t largest_subtask;   /* edges sharing the most common LCA                      */
+    int64_t n_subtasks;        /* distinct LCAs over all off-tree edges (GSS_F_STATS)    */
+    int64_t largest_subtask;   /* edges sharing the most common LCA (GSS_F_STATS)        */
     int64_t prefix_len;        /* length of the criticality-order prefix resolved        */
     int64_t n_arcs;            /* strict-similarity pairs found inside that prefix       */
     int32_t passes;            /* passes that recovered at least one edge                */
@@ -182,8 +184,9 @@ int64_t gss_tree_num_edges(gss_tree tree);
 #define GSS_COSTMODEL_FLOATS 5081
 #define GSS_COSTMODEL_PARAMS 5057
 
-/* Sets the work-queue limits: subtasks of at most local_max edges (1..1024) use the
- * persistent kernel, which runs local_blocks workgroups of four wavefronts. */
+/* Sets the work-queue limits: subtasks of at most local_max edges (0..1024; 0 sends every
+ * subtask to the hash join) use the persistent kernel, which runs local_blocks (1..65536)
+ * workgroups of four wavefronts.  Returns GSS_ERR_ARG outside those ranges. */
 gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks);
 /* Copies up to cap rows of the context trace (host arrays feat[cap][12], cycles[cap],
  * size[cap]; any may be NULL) and returns the number of rows held, or -1. */

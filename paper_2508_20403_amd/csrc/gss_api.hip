@@ -288,7 +288,7 @@ int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen
 
 gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks)
 {
-    if (!ctx || local_max < 1 || local_max > GSS_LOCAL_CAP || local_blocks < 1 || local_blocks > 65536)
+    if (!ctx || local_max < 0 || local_max > GSS_LOCAL_CAP || local_blocks < 1 || local_blocks > 65536)
         return GSS_ERR_ARG;
     ctx->local_max = local_max;
     ctx->local_blocks = local_blocks;

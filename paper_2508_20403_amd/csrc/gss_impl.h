@@ -54,7 +54,7 @@ struct gss_ctx_s {
     void prof_collect();                           // after a sync: accumulate elapsed times
 
     // subtask engine settings (autotuned) and the learned cost model
-    int32_t local_max = 1024;     // subtasks up to this size use the persistent kernel
+    int32_t local_max = 64;       // subtasks up to this size use the persistent kernel
     int32_t local_blocks = 2048;  // workgroups of the persistent kernel (4 wavefronts each)
     bool record = false;          // record per-subtask features and cycles
     bool model_ready = false;     // cost-model weights loaded

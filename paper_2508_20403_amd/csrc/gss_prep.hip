@@ -17,7 +17,7 @@
 
 #define PB 256          // default block size
 #define ENT_ITEMS 16    // CSR entries per thread in entry-parallel kernels
-#define RULE_RATE 8     // one ruler per ~8 list elements (power of two)
+#define RULE_RATE 4     // one ruler per ~4 list elements (power of two)
 #define BASE_MAX 1024   // lists this short are ranked by one workgroup
 
 // ------------------------------------------------------------------------------------
@@ -620,8 +620,10 @@ __device__ __forceinline__ void wave_run(uint64_t v, uint64_t &mask, uint64_t &p
     const int lane = lane_id();
     uint64_t m = ~0ull;
     mask = 0;
+    const uint32_t vlo = (uint32_t)v, vhi = (uint32_t)(v >> 32);
     for (int q = 63; q >= 0; q--) {
-        uint64_t vq = __shfl(v, q, GSS_WAVE);
+        uint64_t vq = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vhi, q) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)vlo, q);
         if (q == lane) {
             mask |= 1ull << q;
             m = vq;

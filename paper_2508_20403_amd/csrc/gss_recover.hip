@@ -45,68 +45,148 @@ struct RmqView {
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int ctz64(uint64_t x) { return __ffsll((long long)x) - 1; }
 
-// minimum packed (depth<<32|vertex) over block minima b0..b1 (inclusive, b0 <= b1)
-__device__ __forceinline__ uint64_t rmq_blocks(const RmqView &q, int32_t b0, int32_t b1)
+// RMQ over Euler positions i..j (i <= j) with every load addressable from (i, j) issued
+// up front; only the in-block argmin reads depend on an earlier load.
+struct RmqPlan {
+    int32_t i, j, bi, bj, b0, b1, s0, s1, a, c, k;
+    bool same_block, has_blocks, same_super, has_super;
+};
+
+__device__ __forceinline__ RmqPlan rmq_plan(const RmqView &q, int32_t i, int32_t j)
 {
-    int32_t s0 = b0 >> 6, s1 = b1 >> 6;
-    if (s0 == s1) {
-        uint64_t m = q.bmask[b1] & (~0ull << (b0 & 63));
-        return q.bmin[(s0 << 6) + ctz64(m)];
+    RmqPlan P;
+    P.i = i;
+    P.j = j;
+    P.bi = i >> 6;
+    P.bj = j >> 6;
+    P.same_block = P.bi == P.bj;
+    P.b0 = P.bi + 1;
+    P.b1 = P.bj - 1;
+    P.has_blocks = !P.same_block && P.b0 <= P.b1;
+    P.s0 = P.b0 >> 6;
+    P.s1 = P.b1 >> 6;
+    P.same_super = P.has_blocks && P.s0 == P.s1;
+    P.a = P.s0 + 1;
+    P.c = P.s1 - 1;
+    P.has_super = P.has_blocks && !P.same_super && P.a <= P.c;
+    P.k = P.has_super ? 31 - __clz(P.c - P.a + 1) : 0;
+    if (!P.has_blocks) {  // keep every index valid; the loads are then ignored
+        P.b0 = P.b1 = 0;
+        P.s0 = P.s1 = 0;
     }
-    uint64_t best = umin64(q.bsuf[b0], q.bpre[b1]);
-    int32_t a = s0 + 1, c = s1 - 1;
-    if (a <= c) {
-        int32_t len = c - a + 1;
-        int k = 31 - __clz(len);
-        const uint64_t *lv = q.sbst + (int64_t)k * q.nsb;
-        best = umin64(best, umin64(lv[a], lv[c - (1 << k) + 1]));
+    if (!P.has_super) P.a = P.c = 0;
+    return P;
+}
+
+struct RmqLoads {
+    uint64_t psuf, ppre, pmask, bsuf, bpre, bmask, st0, st1;
+};
+
+__device__ __forceinline__ RmqLoads rmq_issue(const RmqView &q, const RmqPlan &P)
+{
+    RmqLoads L;
+    L.pmask = q.pmask[P.j];
+    L.psuf = q.psuf[P.i];
+    L.ppre = q.ppre[P.j];
+    L.bmask = q.bmask[P.b1];
+    L.bsuf = q.bsuf[P.b0];
+    L.bpre = q.bpre[P.b1];
+    const uint64_t *lv = q.sbst + (int64_t)P.k * q.nsb;
+    L.st0 = lv[P.a];
+    L.st1 = lv[P.c - (P.has_super ? (1 << P.k) - 1 : 0)];
+    return L;
+}
+
+__device__ __forceinline__ uint64_t rmq_finish(const RmqView &q, const RmqPlan &P, const RmqLoads &L)
+{
+    if (P.same_block) {
+        uint64_t m = L.pmask & (~0ull << (P.i & 63));
+        return q.epk[(P.bi << 6) + ctz64(m)];
+    }
+    uint64_t best = umin64(L.psuf, L.ppre);
+    if (P.same_super) {
+        uint64_t m = L.bmask & (~0ull << (P.b0 & 63));
+        best = umin64(best, q.bmin[(P.s0 << 6) + ctz64(m)]);
+    } else if (P.has_blocks) {
+        best = umin64(best, umin64(L.bsuf, L.bpre));
+        if (P.has_super) best = umin64(best, umin64(L.st0, L.st1));
     }
     return best;
 }
 
-// minimum packed value over Euler positions i..j (i <= j)
+// minimum packed (depth<<32|vertex) over Euler positions i..j (i <= j)
 __device__ __forceinline__ uint64_t rmq(const RmqView &q, int32_t i, int32_t j)
 {
-    int32_t bi = i >> 6, bj = j >> 6;
-    if (bi == bj) {
-        uint64_t m = q.pmask[j] & (~0ull << (i & 63));
-        return q.epk[(bi << 6) + ctz64(m)];
-    }
-    uint64_t best = umin64(q.psuf[i], q.ppre[j]);
-    if (bi + 1 <= bj - 1) best = umin64(best, rmq_blocks(q, bi + 1, bj - 1));
-    return best;
+    RmqPlan P = rmq_plan(q, i, j);
+    RmqLoads L = rmq_issue(q, P);
+    return rmq_finish(q, P, L);
 }
 
 // ------------------------------------------------------------------------------------
 // 1. per-edge LCA / resistance / stretch / beta*
 // ------------------------------------------------------------------------------------
+#define EDGE_ITEMS 2
 __global__ __launch_bounds__(RB) void k_edge_stretch(
     int64_t M, const int32_t *__restrict__ off_id, const int32_t *__restrict__ off_u,
     const int32_t *__restrict__ off_v, const double *__restrict__ off_w,
-    const VRec *__restrict__ vrec, RmqView q, int32_t scale, int32_t c, uint64_t *__restrict__ key, int32_t *__restrict__ lca,
-    uint8_t *__restrict__ bst, double *__restrict__ stretch_out, uint32_t *__restrict__ hist,
-    int32_t *__restrict__ lcacnt, uint32_t *flags)
+    const VRec *__restrict__ vrec, RmqView q, int32_t scale, int32_t c, uint64_t *__restrict__ key,
+    int32_t *__restrict__ lca, uint8_t *__restrict__ bst, double *__restrict__ stretch_out,
+    uint32_t *__restrict__ hist, int32_t *__restrict__ lcacnt, uint32_t *flags)
 {
     __shared__ uint32_t sh[SEL_BINS];
-    for (int i = threadIdx.x; i < SEL_BINS; i += RB) sh[i] = 0;
-    __syncthreads();
-    int64_t j = (int64_t)blockIdx.x * RB + threadIdx.x;
-    int32_t l = -1;
-    if (j < M) {
-        int32_t u = off_u[j], v = off_v[j];
-        VRec ru = vrec[u], rv = vrec[v];
-        int32_t fu = ru.first, fv = rv.first;
-        uint64_t pk = (fu <= fv) ? rmq(q, fu, fv) : rmq(q, fv, fu);
-        l = (int32_t)(uint32_t)pk;
-        int32_t dl = (int32_t)(pk >> 32);
-        int32_t du = ru.depth - dl, dv = rv.depth - dl;
-        u128 Dl = vrec[l].D;
-        u128 R = add128(sub128(ru.D, Dl), sub128(rv.D, Dl));
+    if (hist) {
+        for (int i = threadIdx.x; i < SEL_BINS; i += RB) sh[i] = 0;
+        __syncthreads();
+    }
+    const int64_t base = (int64_t)blockIdx.x * RB * EDGE_ITEMS + threadIdx.x;
+    int64_t jj[EDGE_ITEMS];
+    bool ok[EDGE_ITEMS];
+    int32_t u[EDGE_ITEMS], v[EDGE_ITEMS];
+    double w[EDGE_ITEMS];
+#pragma unroll
+    for (int t = 0; t < EDGE_ITEMS; t++) {
+        jj[t] = base + (int64_t)t * RB;
+        ok[t] = jj[t] < M;
+        int64_t j = ok[t] ? jj[t] : 0;
+        u[t] = off_u[j];
+        v[t] = off_v[j];
+        w[t] = off_w[j];
+    }
+    VRec ru[EDGE_ITEMS], rv[EDGE_ITEMS];
+#pragma unroll
+    for (int t = 0; t < EDGE_ITEMS; t++) {
+        ru[t] = vrec[u[t]];
+        rv[t] = vrec[v[t]];
+    }
+    RmqPlan pl[EDGE_ITEMS];
+    RmqLoads ld[EDGE_ITEMS];
+#pragma unroll
+    for (int t = 0; t < EDGE_ITEMS; t++) {
+        int32_t fu = ru[t].first, fv = rv[t].first;
+        pl[t] = rmq_plan(q, min(fu, fv), max(fu, fv));
+        ld[t] = rmq_issue(q, pl[t]);
+    }
+    uint64_t pk[EDGE_ITEMS];
+#pragma unroll
+    for (int t = 0; t < EDGE_ITEMS; t++) pk[t] = rmq_finish(q, pl[t], ld[t]);
+    u128 Dl[EDGE_ITEMS];
+#pragma unroll
+    for (int t = 0; t < EDGE_ITEMS; t++) Dl[t] = vrec[(int32_t)(uint32_t)pk[t]].D;
+    int32_t lw[EDGE_ITEMS];
+#pragma unroll
+    for (int t = 0; t < EDGE_ITEMS; t++) {
+        lw[t] = -1;
+        if (!ok[t]) continue;
+        const int64_t j = jj[t];
+        const int32_t l = (int32_t)(uint32_t)pk[t];
+        const int32_t dl = (int32_t)(pk[t] >> 32);
+        const int32_t du = ru[t].depth - dl, dv = rv[t].depth - dl;
+        u128 R = add128(sub128(ru[t].D, Dl[t]), sub128(rv[t].D, Dl[t]));
         double r;
-        bool ok = u128_to_double_rne(R, scale, &r);
-        double s = off_w[j] * r;
+        bool good = u128_to_double_rne(R, scale, &r);
+        double s = w[t] * r;
         uint64_t bits = (uint64_t)__double_as_longlong(s);
-        if (!ok || ((bits >> 52) & 0x7ff) == 0x7ff) {
+        if (!good || ((bits >> 52) & 0x7ff) == 0x7ff) {
             atomicOr(flags, F_RANGE);
             bits = 1;
         }
@@ -117,23 +197,28 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
         bst[j] = (uint8_t)b;
         if (stretch_out) stretch_out[off_id[j]] = s;
         if (hist) atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
+        lw[t] = l;
     }
-    // subtask sizes: lanes sharing the first lane's LCA add once (skewed graphs put most
-    // edges on a few LCAs), the others add individually
+    // subtask sizes (only when asked for): lanes sharing the first lane's LCA add once
     if (lcacnt) {
-        uint64_t active = __ballot(l >= 0);
-        if (active) {
-            int leader = ctz64(active);
-            int32_t lv = __shfl(l, leader, GSS_WAVE);
-            uint64_t same = __ballot(l == lv) & active;
-            if (lane_id() == leader) atomicAdd(&lcacnt[lv], __popcll(same));
-            else if (l >= 0 && l != lv) atomicAdd(&lcacnt[l], 1);
+#pragma unroll
+        for (int t = 0; t < EDGE_ITEMS; t++) {
+            const int32_t l = lw[t];
+            uint64_t active = __ballot(l >= 0);
+            if (active) {
+                int leader = ctz64(active);
+                int32_t lv = __shfl(l, leader, GSS_WAVE);
+                uint64_t same = __ballot(l == lv) & active;
+                if (lane_id() == leader) atomicAdd(&lcacnt[lv], __popcll(same));
+                else if (l >= 0 && l != lv) atomicAdd(&lcacnt[l], 1);
+            }
         }
     }
-    __syncthreads();
-    if (hist)
+    if (hist) {
+        __syncthreads();
         for (int i = threadIdx.x; i < SEL_BINS; i += RB)
             if (sh[i]) atomicAdd(&hist[i], sh[i]);
+    }
 }
 
 // number of subtasks (non-zero LCA counts) and the largest
@@ -262,7 +347,7 @@ __global__ void k_prefix_count(const uint64_t *__restrict__ key, int64_t M, cons
         int32_t g = off_g ? off_g[j] : 0;
         if (key[j] >= thr[g]) {
             c++;
-            if (g != gcur) {
+            if (off_g && g != gcur) {
                 if (gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
                 gcur = g;
                 gc = 0;
@@ -270,7 +355,7 @@ __global__ void k_prefix_count(const uint64_t *__restrict__ key, int64_t M, cons
             gc++;
         }
     }
-    if (gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
+    if (off_g && gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
     cnt[t] = c;
 }
 
@@ -326,7 +411,7 @@ __global__ __launch_bounds__(1024) void k_key_varying(const uint64_t *__restrict
 }
 
 #define RS_BLOCK 256
-#define RS_ITEMS 16
+#define RS_ITEMS 4
 #define RS_TILE (RS_BLOCK * RS_ITEMS)
 
 // per-tile digit counts, stored digit-major: cnt[d * ntiles + tile]
@@ -458,62 +543,87 @@ __device__ __forceinline__ void join_insert(Slot *tab, uint64_t cap_mask, int32_
     }
 }
 
+// one thread per (edge, orientation, i, k): insert (anc_i(x), anc_k(y)) -> (rank, i, k)
 __global__ void k_join_build(int64_t P, int32_t c, const int32_t *__restrict__ ancU,
                              const int32_t *__restrict__ ancV, const uint8_t *__restrict__ is_global, Slot *tab,
                              uint64_t cap_mask)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = 2 * (c + 1) * (c + 1);
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = tid / per;
     if (p >= P || !is_global[p]) return;
-    for (int orient = 0; orient < 2; orient++) {
-        const int32_t *X = orient ? ancV : ancU;
-        const int32_t *Y = orient ? ancU : ancV;
-        for (int i = 0; i <= c; i++) {
-            int32_t A = X[(int64_t)i * P + p];
-            if (A < 0) break;
-            for (int k = 0; k <= c; k++) {
-                int32_t B = Y[(int64_t)k * P + p];
-                if (B < 0) break;
-                join_insert(tab, cap_mask, A, B, (int32_t)p, (i << 8) | k);
-            }
-        }
-    }
+    int r = (int)(tid - p * per);
+    const int orient = r / ((c + 1) * (c + 1));
+    r -= orient * (c + 1) * (c + 1);
+    const int i = r / (c + 1), k = r % (c + 1);
+    const int32_t *X = orient ? ancV : ancU;
+    const int32_t *Y = orient ? ancU : ancV;
+    int32_t A = X[(int64_t)i * P + p];
+    int32_t B = Y[(int64_t)k * P + p];
+    if (A < 0 || B < 0) return;
+    join_insert(tab, cap_mask, A, B, (int32_t)p, (i << 8) | k);
 }
 
-__global__ void k_join_probe(int64_t P, const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
+// one thread per (marker edge, j, l): probe (anc_j(u), anc_l(v)) and keep entries with
+// i <= beta*-j and k <= beta*-l of a later rank.  The probe loop is wave-uniform so that
+// the arcs found in one step are appended with one atomic per wavefront.
+__global__ void k_join_probe(int64_t P, int32_t c, const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
                              const int32_t *__restrict__ ancV, const uint8_t *__restrict__ is_global,
                              const Slot *__restrict__ tab, uint64_t cap_mask, int2 *__restrict__ arcs,
                              int64_t arc_cap, unsigned long long *arc_count, int32_t *__restrict__ indeg,
                              uint32_t *flags)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P || !is_global[p]) return;
-    int beta = rb[p];
-    if (beta == 0) return;  // S_u = {u}, S_v = {v}: only the edge itself is similar
-    for (int j = 0; j <= beta; j++) {
+    const int per = (c + 1) * (c + 1);
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = tid / per;
+    bool active = p < P && is_global[p];
+    int beta = 0, j = 0, l = 0;
+    unsigned long long ab = 0;
+    uint64_t h = 0;
+    if (active) {
+        beta = rb[p];
+        const int r = (int)(tid - p * per);
+        j = r / (c + 1);
+        l = r % (c + 1);
+        active = beta > 0 && j <= beta && l <= beta;  // beta* = 0: only the edge itself is similar
+    }
+    if (active) {
         int32_t A = ancU[(int64_t)j * P + p];
-        if (A < 0) break;
-        for (int l = 0; l <= beta; l++) {
-            int32_t B = ancV[(int64_t)l * P + p];
-            if (B < 0) break;
-            unsigned long long ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
-            uint64_t h = slot_hash(ab) & cap_mask;
-            for (;;) {
-                unsigned long long s = tab[h].ab;
-                if (s == SLOT_EMPTY) break;
+        int32_t B = ancV[(int64_t)l * P + p];
+        active = A >= 0 && B >= 0;
+        ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
+        h = slot_hash(ab) & cap_mask;
+    }
+    while (__ballot(active)) {
+        bool hit = false;
+        int32_t t = 0;
+        if (active) {
+            unsigned long long s = tab[h].ab;
+            if (s == SLOT_EMPTY) {
+                active = false;
+            } else {
                 if (s == ab) {
                     int ik = tab[h].ik;
-                    int32_t t = tab[h].p;
-                    if ((ik >> 8) <= beta - j && (ik & 255) <= beta - l && t > p) {
-                        unsigned long long a = atomicAdd(arc_count, 1ull);
-                        if ((int64_t)a < arc_cap) {
-                            arcs[a] = make_int2((int32_t)p, t);
-                            atomicAdd(&indeg[t], 1);
-                        } else {
-                            atomicOr(flags, F_OVERFLOW);
-                        }
-                    }
+                    t = tab[h].p;
+                    hit = (ik >> 8) <= beta - j && (ik & 255) <= beta - l && t > p;
                 }
                 h = (h + 1) & cap_mask;
+            }
+        }
+        uint64_t m = __ballot(hit);
+        if (m) {
+            int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane_id() == leader) base = atomicAdd(arc_count, (unsigned long long)__popcll(m));
+            base = __shfl(base, leader, GSS_WAVE);
+            if (hit) {
+                unsigned long long a = base + __popcll(m & lanemask_lt());
+                if ((int64_t)a < arc_cap) {
+                    arcs[a] = make_int2((int32_t)p, t);
+                    atomicAdd(&indeg[t], 1);
+                } else {
+                    atomicOr(flags, F_OVERFLOW);
+                }
             }
         }
     }
@@ -527,6 +637,37 @@ __global__ void k_state_init(int64_t P, const int32_t *__restrict__ indeg, const
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < P && is_global[p]) state[p] = indeg[p] == 0 ? ST_CAND : ST_UNDEC;
+}
+
+// Every edge without in-arcs is recovered (k_state_init), so every target of such an edge
+// is marked; one pass over all arcs settles those, and only arcs into still-undecided
+// targets go on to the rounds.
+__global__ void k_arc_settle(int64_t A, const int2 *__restrict__ arcs, const int32_t *__restrict__ indeg,
+                             uint8_t *__restrict__ state)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= A) return;
+    int2 e = arcs[a];
+    if (indeg[e.x] == 0) state[e.y] = ST_MARK;  // the source has no in-arcs: recovered
+}
+
+__global__ void k_arc_compact(int64_t A, const int2 *__restrict__ arcs, const uint8_t *__restrict__ state,
+                              int2 *__restrict__ out, unsigned long long *count)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool keep = false;
+    int2 e = make_int2(0, 0);
+    if (a < A) {
+        e = arcs[a];
+        keep = state[e.y] == ST_UNDEC;
+    }
+    uint64_t m = __ballot(keep);
+    if (!m) return;
+    unsigned long long base = 0;
+    int leader = __ffsll((long long)m) - 1;
+    if (lane_id() == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, GSS_WAVE);
+    if (keep) out[base + __popcll(m & lanemask_lt())] = e;
 }
 
 __global__ __launch_bounds__(1024) void k_resolve(int64_t A, const int2 *__restrict__ arcs,
@@ -552,6 +693,43 @@ __global__ __launch_bounds__(1024) void k_resolve(int64_t A, const int2 *__restr
         __syncthreads();
         int undec = 0;
         for (int64_t a = threadIdx.x; a < A; a += blockDim.x) {
+            int2 e = arcs[a];
+            if (state[e.y] == ST_UNDEC) {
+                mcnt[e.y] = 0;
+                undec = 1;
+            }
+        }
+        rounds++;
+        if (!__syncthreads_or(undec)) break;
+    }
+    if (threadIdx.x == 0) *rounds_out = rounds;
+}
+
+// rounds over the compacted arcs; the count is read from device memory
+__global__ __launch_bounds__(1024) void k_resolve_dev(const unsigned long long *A, const int2 *__restrict__ arcs,
+                                                      const int32_t *__restrict__ indeg, uint8_t *state, int32_t *mcnt,
+                                                      int64_t *rounds_out)
+{
+    const int64_t n = (int64_t)*A;
+    int64_t rounds = 0;
+    while (n > 0) {
+        for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+            int2 e = arcs[a];
+            if (state[e.y] == ST_UNDEC && state[e.x] == ST_CAND) state[e.y] = ST_MARK;
+        }
+        __syncthreads();
+        for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+            int2 e = arcs[a];
+            if (state[e.y] == ST_UNDEC && state[e.x] == ST_MARK) atomicAdd(&mcnt[e.y], 1);
+        }
+        __syncthreads();
+        for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+            int2 e = arcs[a];
+            if (state[e.y] == ST_UNDEC && mcnt[e.y] == indeg[e.y]) state[e.y] = ST_CAND;
+        }
+        __syncthreads();
+        int undec = 0;
+        for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
             int2 e = arcs[a];
             if (state[e.y] == ST_UNDEC) {
                 mcnt[e.y] = 0;
@@ -758,7 +936,12 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
     res.Pg.assign(G, 0);
-    HIP_OK(hipMemcpyAsync(res.Pg.data(), gcount, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
+    if (G > 1) {
+        HIP_OK(hipMemcpyAsync(res.Pg.data(), gcount, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
+        ctx->sync();
+    } else {
+        res.Pg[0] = P;
+    }
     uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
     GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, v1, k1);
@@ -828,12 +1011,13 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     uint64_t *qk = ctx->alloc<uint64_t>(nsub + 1), *qk2 = ctx->alloc<uint64_t>(nsub + 1);
     int32_t *qv = ctx->alloc<int32_t>(nsub + 1), *qv2 = ctx->alloc<int32_t>(nsub + 1);
     int32_t *is_local = ctx->alloc<int32_t>(nsub + 1);
-    HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, sizeof(int64_t), st));
+    HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, 3 * sizeof(int64_t), st));
     launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, qk, qv, is_local,
-                        (int32_t *)(ctx->d_counters + 4));
+                        (int32_t *)(ctx->d_counters + 4), (unsigned long long *)(ctx->d_counters + 6));
     radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub);
-    read_counters(ctx, 5);
+    read_counters(ctx, 7);
     const int32_t nlocal = (int32_t)ctx->h_counters[4];
+    const int64_t nglobal_edges = ctx->h_counters[6];
     res.nlocal = nlocal;
     scratch.push_back(qk);
     scratch.push_back(qk2);
@@ -871,26 +1055,33 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         a.state = B.state;
         a.cycles = cycles;
         int blocks = std::max(1, std::min<int>(ctx->local_blocks, (nlocal + 3) / 4));
+        // candidate scratch: at most ~256 MB whatever the setting
+        const size_t per_wave = (size_t)std::max<int32_t>(local_max, 1) * local_desc_bytes(c);
+        blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(1, ((int64_t)256 << 20) / (4 * per_wave)));
+        void *scr = ctx->alloc<uint8_t>((size_t)blocks * 4 * per_wave + 64);
+        scratch.push_back(scr);
+        a.cand_scratch = scr;
         launch_local_recover(ctx, c, a, blocks);
     }
     // Step 4, large subtasks: hash join + dependency rounds over their edges
     B.indeg = ctx->alloc<int32_t>(P + 1);
     B.mcnt = ctx->alloc<int32_t>(P + 1);
     if (nsub > nlocal) {
-        int64_t entries = 2 * (int64_t)(c + 1) * (c + 1) * P;
+        int64_t entries = 2 * (int64_t)(c + 1) * (c + 1) * nglobal_edges;
         uint64_t cap = 1024;
         while (cap < 2 * (uint64_t)entries) cap <<= 1;
         Slot *tab = ctx->alloc<Slot>(cap);
         HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(Slot) * cap, st));
-        GSS_LAUNCH(k_join_build, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV, B.is_global, tab,
-                   cap - 1);
+        GSS_LAUNCH(k_join_build, dim3(grid_for(P * 2 * (c + 1) * (c + 1), RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV,
+                   B.is_global, tab, cap - 1);
         int64_t arc_cap = std::max<int64_t>(4 * P, 1 << 16);
         for (;;) {
             int2 *arcs = ctx->alloc<int2>(arc_cap);
             HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
             HIP_OK(hipMemsetAsync(ctx->d_counters, 0, sizeof(int64_t) * 2, st));
-            GSS_LAUNCH(k_join_probe, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.rb, B.ancU, B.ancV, B.is_global,
-                       tab, cap - 1, arcs, arc_cap, (unsigned long long *)ctx->d_counters, B.indeg, ctx->d_flags);
+            GSS_LAUNCH(k_join_probe, dim3(grid_for(P * (c + 1) * (c + 1), RB)), dim3(RB), 0, st, P, c, B.rb, B.ancU,
+                       B.ancV, B.is_global, tab, cap - 1, arcs, arc_cap, (unsigned long long *)ctx->d_counters, B.indeg,
+                       ctx->d_flags);
             read_counters(ctx, 1);
             int64_t A = ctx->h_counters[0];
             if (A > arc_cap) {
@@ -901,11 +1092,18 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             res.arcs = A;
             HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
             GSS_LAUNCH(k_state_init, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.indeg, B.is_global, B.state);
-            if (A > 0)
-                GSS_LAUNCH(k_resolve, dim3(1), dim3(1024), 0, st, A, arcs, B.indeg, B.state, B.mcnt,
-                           ctx->d_counters + 1);
-            read_counters(ctx, 2);
-            res.rounds = A > 0 ? ctx->h_counters[1] : 0;
+            if (A > 0) {
+                int2 *arcs2 = ctx->alloc<int2>(A + 1);
+                HIP_OK(hipMemsetAsync(ctx->d_counters + 2, 0, sizeof(int64_t), st));
+                GSS_LAUNCH(k_arc_settle, dim3(grid_for(A, RB)), dim3(RB), 0, st, A, arcs, B.indeg, B.state);
+                GSS_LAUNCH(k_arc_compact, dim3(grid_for(A, RB)), dim3(RB), 0, st, A, arcs, B.state, arcs2,
+                           (unsigned long long *)(ctx->d_counters + 2));
+                GSS_LAUNCH(k_resolve_dev, dim3(1), dim3(1024), 0, st, (const unsigned long long *)(ctx->d_counters + 2),
+                           arcs2, B.indeg, B.state, B.mcnt, ctx->d_counters + 1);
+                read_counters(ctx, 2);
+                res.rounds = ctx->h_counters[1];
+                ctx->free(arcs2);
+            }
             ctx->free(arcs);
             break;
         }
@@ -1027,15 +1225,20 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     int32_t *lca = ctx->alloc<int32_t>(M + 1);
     uint8_t *bst = ctx->alloc<uint8_t>(M + 1);
     uint32_t *hist = ctx->alloc<uint32_t>((int64_t)SEL_BINS * G);
-    int32_t *lcacnt = ctx->alloc<int32_t>(n);
+    // per-LCA edge counts: subtask statistics, and two of the cost model's features
+    const bool need_lca_counts = (prms[0].flags & GSS_F_STATS) || ctx->record ||
+                                 (prms[0].sched == GSS_SCHED_LEARNED && ctx->model_ready);
+    int32_t *lcacnt = need_lca_counts ? ctx->alloc<int32_t>(n) : nullptr;
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
-    HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
+    if (lcacnt) HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
     if (M > 0)
-        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u, t->off_v, t->off_w,
-                   t->vrec, rmq_view(t), t->scale, c, key, lca, bst, stretch, G == 1 ? hist : (uint32_t *)nullptr,
-                   lcacnt, ctx->d_flags);
+        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB * EDGE_ITEMS)), dim3(RB), 0, st, M, t->off_id, t->off_u,
+                   t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst, stretch,
+                   G == 1 ? hist : (uint32_t *)nullptr, lcacnt, ctx->d_flags);
     HIP_OK(hipGetLastError());
-    if (G == 1) {
+    if (!lcacnt) {
+        for (int32_t g = 0; g < G; g++) nsubg[g] = largest[g] = -1;
+    } else if (G == 1) {
         int64_t init2[2] = {0, 0};
         memcpy(ctx->h_counters + 2, init2, sizeof init2);
         HIP_OK(hipMemcpyAsync(ctx->d_counters + 2, ctx->h_counters + 2, sizeof init2, hipMemcpyHostToDevice, st));
@@ -1179,7 +1382,7 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     uint32_t *hist = ctx->alloc<uint32_t>(SEL_BINS);
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (M > 0) {
-        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, t->off_u,
+        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB * EDGE_ITEMS)), dim3(RB), 0, st, M, t->off_id, t->off_u,
                            t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta, key, lca, bst,
                            (double *)nullptr, hist, (int32_t *)nullptr, ctx->d_flags);
         GSS_LAUNCH(k_edge_lca_out, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, lca, bst,

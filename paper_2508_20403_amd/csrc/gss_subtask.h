@@ -19,6 +19,7 @@ struct SubtaskArgs {
     const uint8_t *rb;            // beta* per rank
     uint8_t *state;               // [P] out: recovered / marked
     uint64_t *cycles;             // [nsub] out: cycles spent per subtask (may be null)
+    void *cand_scratch;           // per wavefront: local_max candidate descriptors
 };
 
 void launch_local_recover(gss_ctx ctx, int C, const SubtaskArgs &a, int blocks);
@@ -26,7 +27,8 @@ void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32
 void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, int32_t *sub_ptr,
                       int32_t *sub_lca, int32_t nsub);
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
-                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal);
+                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
+                         unsigned long long *nglobal_edges);
 void launch_mark_global(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *is_local,
                         const int32_t *grp, uint8_t *is_global);
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
@@ -47,3 +49,4 @@ void costmodel_train(gss_ctx ctx, const float *host_feat, const double *host_cyc
 void costmodel_grad(gss_ctx ctx, const float *host_x, const float *host_y, int32_t nb, float *host_g,
                     float *host_loss);
 int64_t costmodel_nparam_total();
+size_t local_desc_bytes(int C);

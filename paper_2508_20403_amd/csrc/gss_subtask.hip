@@ -6,7 +6,8 @@
 // wavefront pops the next subtask from a device work queue and runs the serial greedy of
 // that subtask with wavefront ballots, 64 edges at a time:
 //   * lanes hold consecutive edges of the subtask; each lane first tests its edge against
-//     the candidates recovered in earlier chunks (uniform loads of their descriptors);
+//     the candidates recovered in earlier chunks (their descriptors are kept in a
+//     per-wavefront scratch that stays in cache);
 //   * the unmarked lanes are then resolved in rank order: the lowest pending lane is a
 //     candidate, its descriptor is broadcast, lanes after it test strict similarity and
 //     the ballot of hits removes them.
@@ -90,9 +91,12 @@ __device__ __forceinline__ Desc<C> shfl_desc(const Desc<C> &d, int src)
 template <int C>
 __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
 {
-    __shared__ int32_t scand[256 / GSS_WAVE][GSS_LOCAL_CAP];  // candidate ranks per wavefront
+    // descriptors of the candidates recovered so far in the current subtask, per wavefront,
+    // in global scratch: written by the lanes, read back with wave-uniform vector loads
+    // that stay in this CU's caches
     const int lane = lane_id();
-    int32_t *cand = scand[threadIdx.x / GSS_WAVE];
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
+    Desc<C> *cand = (Desc<C> *)a.cand_scratch + gw * a.local_max;
     for (;;) {
         int32_t qi = 0;
         if (lane == 0) qi = (int32_t)atomicAdd(a.queue_head, 1u);
@@ -108,11 +112,10 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
             const int32_t p = valid ? a.grp[gi] : 0;
             Desc<C> me;
             if (valid) load_desc<C>(me, a.P, p, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
-            // against candidates of earlier chunks (uniform loads)
+            // against candidates of earlier chunks
             bool marked = false;
             for (int32_t k = 0; k < ncand; k++) {
-                Desc<C> m;
-                load_desc<C>(m, a.P, cand[k], a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+                const Desc<C> m = cand[k];
                 marked |= valid && strictly_similar<C>(me, m);
             }
             // in-chunk greedy in rank order
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
             if (valid) a.state[p] = is_cand ? ST_CAND_ : ST_MARK_;
             // append this chunk's candidates (rank order) to the candidate list
             const int before = __popcll(recovered & lanemask_lt());
-            if (is_cand && ncand + before < a.local_max) cand[ncand + before] = p;
+            if (is_cand && ncand + before < a.local_max) cand[ncand + before] = me;
             ncand += __popcll(recovered);
             __threadfence_block();
         }
@@ -140,6 +143,17 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
 }
 
 }  // namespace
+
+size_t local_desc_bytes(int C)
+{
+    switch (C) {
+#define CASE(k) \
+    case k: return sizeof(Desc<k>);
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: throw gss_error{GSS_ERR_ARG, "beta out of range"};
+    }
+}
 
 void launch_local_recover(gss_ctx ctx, int C, const SubtaskArgs &a, int blocks)
 {
@@ -182,9 +196,20 @@ __global__ void k_group_end(int32_t nsub, int64_t P, int32_t *__restrict__ sub_p
 __global__ void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr, int32_t local_max,
                                const float *__restrict__ pred, uint64_t *__restrict__ qkey,
                                int32_t *__restrict__ qval, int32_t *__restrict__ is_local,
-                               int32_t *__restrict__ nlocal)
+                               int32_t *__restrict__ nlocal, unsigned long long *__restrict__ nglobal_edges)
 {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    // edges on the global path, one atomic per wave
+    {
+        int32_t ge = 0;
+        if (s < nsub) {
+            int32_t sz = sub_ptr[s + 1] - sub_ptr[s];
+            if (sz > local_max) ge = sz;
+        }
+        unsigned long long tot = (unsigned long long)ge;
+        for (int d = 32; d > 0; d >>= 1) tot += __shfl_xor(tot, d, GSS_WAVE);
+        if (lane_id() == 0 && tot) atomicAdd(nglobal_edges, tot);
+    }
     if (s >= nsub) return;
     int32_t size = sub_ptr[s + 1] - sub_ptr[s];
     bool loc = size <= local_max;
@@ -195,7 +220,8 @@ __global__ void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr
     // ascending sort of this key = local subtasks first, by cost descending, then id
     qkey[s] = ((uint64_t)(loc ? 0 : 1) << 63) | ((~cost) & 0x7fffffffffffffffull);
     qval[s] = s;
-    if (loc) atomicAdd(nlocal, 1);
+    uint64_t lm = __ballot(loc);
+    if (lane_id() == __ffsll((long long)__ballot(true)) - 1 && lm) atomicAdd(nlocal, (int32_t)__popcll(lm));
 }
 
 // global-path flag per rank (edges of subtasks above the local limit)
@@ -277,10 +303,11 @@ void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
 }
 
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
-                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal)
+                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
+                         unsigned long long *nglobal_edges)
 {
     GSS_LAUNCH(k_subtask_keys, dim3(grid_for(nsub, 256)), dim3(256), 0, ctx->stream, nsub, sub_ptr, local_max, pred,
-               qkey, qval, is_local, nlocal);
+               qkey, qval, is_local, nlocal, nglobal_edges);
 }
 
 void launch_mark_global(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *is_local,

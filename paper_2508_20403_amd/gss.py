@@ -31,6 +31,7 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
            "gss_tree_graph_edges", "gss_autotune"]
 GSS_F_RECORD = 2
+GSS_F_STATS = 4
 NFEAT = 12
 COSTMODEL_FLOATS = 5081
 COSTMODEL_PARAMS = 5057
@@ -282,7 +283,7 @@ class Tree:
         return lca, bstar
 
     def recover(self, alpha, beta, k_override=-1, sched=SCHED_EDGECOUNT, mask_tree=False,
-                want_order=True, want_stretch=False, out=None, record=False):
+                want_order=True, want_stretch=False, out=None, record=False, stats=False):
         """Runs gss_recover.  Returns (status, mask, order, stretch, info dict)."""
         dev = self.arrays[3].device
         k = int(k_override) if k_override >= 0 else int(float(alpha) * float(self.n) // 1)
@@ -292,7 +293,8 @@ class Tree:
             stretch = torch.empty(max(self.m, 1), dtype=torch.float64, device=dev) if want_stretch else None
         else:
             mask, order, stretch = out
-        flags = (GSS_F_MASK_TREE if mask_tree else 0) | (GSS_F_RECORD if record else 0)
+        flags = (GSS_F_MASK_TREE if mask_tree else 0) | (GSS_F_RECORD if record else 0) | \
+            (GSS_F_STATS if stats else 0)
         p = Params(float(alpha), int(beta), int(sched), int(k_override), flags, 0)
         info = Info()
         st = self.ctx.lib.gss_recover(self.ctx.handle, self.handle, ctypes.byref(p), _ptr(mask),
@@ -340,13 +342,13 @@ class Batch:
         self.m = [ctx.lib.gss_tree_graph_edges(self.handle, i) for i in range(nb)]
         self.n = [g.n for g in self.graphs]
 
-    def _params(self, alphas, beta, sched, k_override, record):
+    def _params(self, alphas, beta, sched, k_override, record, stats=False):
         nb = len(self.graphs)
         params = (Params * nb)()
         for i in range(nb):
             params[i] = Params(float(alphas[i]), int(beta), int(sched),
                                int(k_override[i]) if k_override is not None else -1,
-                               GSS_F_RECORD if record else 0, 0)
+                               (GSS_F_RECORD if record else 0) | (GSS_F_STATS if stats else 0), 0)
         return params
 
     def autotune(self, cache_path=None, sched=SCHED_EDGECOUNT):
@@ -363,7 +365,8 @@ class Batch:
                                                  ctypes.byref(lm), ctypes.byref(lb), ctypes.byref(ms)))
         return lm.value, lb.value, ms.value
 
-    def recover(self, alphas=None, beta=None, sched=SCHED_EDGECOUNT, k_override=None, out=None, record=False):
+    def recover(self, alphas=None, beta=None, sched=SCHED_EDGECOUNT, k_override=None, out=None, record=False,
+                stats=False):
         """Returns (status, masks, orders, infos) lists over the graphs."""
         nb = len(self.graphs)
         dev = torch.device("cuda")
@@ -376,7 +379,7 @@ class Batch:
             orders = [torch.empty(max(ks[i], 1), dtype=torch.int32, device=dev) for i in range(nb)]
         else:
             masks, orders = out
-        params = self._params(alphas, beta, sched, k_override, record)
+        params = self._params(alphas, beta, sched, k_override, record, stats)
         mp = (ctypes.c_void_p * nb)(*[m.data_ptr() for m in masks])
         op = (ctypes.c_void_p * nb)(*[o.data_ptr() for o in orders])
         infos = (Info * nb)()

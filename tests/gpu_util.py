@@ -12,7 +12,7 @@ def run_gpu(ctx, g, alpha=None, beta=None, k_override=-1, want_stretch=True, sch
     print(f"[gpu] {g.name} n={g.n} m={g.m} alpha={alpha} beta={beta} k={k_override}", flush=True)
     tree = gss.Tree.from_graph(ctx, g)
     st, mask, order, stretch, info = tree.recover(alpha, beta, k_override, sched=sched,
-                                                  want_stretch=want_stretch, mask_tree=mask_tree)
+                                                  want_stretch=want_stretch, mask_tree=mask_tree, stats=True)
     torch.cuda.synchronize()
     out = dict(status=st, mask=mask.cpu().numpy(), order=order.cpu().numpy() if order is not None else None,
                stretch=stretch.cpu().numpy() if stretch is not None else None, info=info)

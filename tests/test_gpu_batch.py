@@ -33,7 +33,7 @@ def test_batch_matches_per_graph_oracle(gpu_ctx, seed):
     graphs = small_batch(seed)
     print(f"[gpu-batch] seed {seed}: sizes {[g.n for g in graphs]}", flush=True)
     b = gss.Batch(gpu_ctx, graphs)
-    st, masks, orders, infos = b.recover()
+    st, masks, orders, infos = b.recover(stats=True)
     torch.cuda.synchronize()
     for g, mk, od, inf in zip(graphs, masks, orders, infos):
         ref = oracle.recover(g)

@@ -22,12 +22,12 @@ def test_output_independent_of_schedule(gpu_ctx, make):
     g = make()
     orc = run_oracle(g)
     try:
-        for local_max, blocks in ((1024, 2048), (1, 2048), (64, 3), (300, 1), (1024, 7)):
+        for local_max, blocks in ((1024, 2048), (0, 2048), (1, 2048), (64, 3), (300, 1), (1024, 7)):
             gpu_ctx.set_tuning(local_max, blocks)
             gpu = run_gpu(gpu_ctx, g)
             assert_same_recovery(gpu, orc)
     finally:
-        gpu_ctx.set_tuning(1024, 2048)
+        gpu_ctx.set_tuning(64, 2048)
 
 
 def test_trace_records_features_and_cycles(gpu_ctx):
