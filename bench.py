@@ -39,21 +39,12 @@ WORKLOADS = {
 }
 
 
-def kernel_bytes(name, g, info, tree_M):
-    """Algorithmic bytes one launch of `name` must move (per-unit figure x units)."""
-    n, m, nnz, M = g.n, g.m, g.nnz, tree_M
-    if name == "k_edge_stretch":
-        # per off-tree edge: read u,v (8) and w (8); gather first[u],first[v] (8),
-        # depth[u],depth[v] (8), D[u],D[v],D[lca] (48), two Euler entries for the
-        # RMQ answer (16); write key (8), lca (4), beta* (1)  -> 109 B
-        return 109 * M
-    if name == "k_walk2_euler":
-        # per arc (2(n-1)): succ (4) + term (16) read, and per vertex first/depth (8),
-        # D (16) and two Euler entries (16) written -> 20*2 + 40 per vertex
-        return 40 * (n - 1) + 40 * (n - 1)
-    if name == "k_walk1":
-        return 20 * 2 * (n - 1)
-    return None
+def step_alg_bytes(n, m, M, K):
+    """Algorithmic bytes of one whole step (tree preparation + recovery): the input CSR,
+    weights and parent array read once (8n + 16m), the per-vertex tree arrays and Euler
+    sequence written and read once (64n), per off-tree edge the LCA/resistance gathers,
+    its record, one regroup and one final read (172 B), and the outputs (m + 4K)."""
+    return 8 * n + 16 * m + 64 * n + 172 * M + m + 4 * K
 
 
 def src_digest(paths):
@@ -139,8 +130,9 @@ def main():
     dominant = args.kernel or max(table, key=lambda k: table[k][0])
     if args.breakdown:
         tot = sum(v[0] for v in table.values())
-        for k, (ms, nl) in sorted(table.items(), key=lambda kv: -kv[1][0]):
-            print(f"  {k:24s} {ms:9.3f} ms  {nl:5d} launches  {100 * ms / tot:5.1f}%", file=sys.stderr)
+        for k, (ms, nl, nb) in sorted(table.items(), key=lambda kv: -kv[1][0]):
+            gbs = f"{nb / (ms * 1e-3) / 1e9:8.1f} GB/s" if nb else "       -     "
+            print(f"  {k:24s} {ms:9.3f} ms  {nl:5d} launches  {100 * ms / tot:5.1f}%  {gbs}", file=sys.stderr)
     print(f"[bench] dominant kernel {dominant}; info {info}", file=sys.stderr, flush=True)
 
     ctx.profile(True, dominant)
@@ -156,15 +148,16 @@ def main():
     M = info["n_offtree"]
     value = M / (ms_step * 1e-3)
 
-    dom_ms, dom_n = prof.get(dominant, (float("nan"), 0))
+    dom_ms, dom_n, dom_bytes = prof.get(dominant, (float("nan"), 0, 0))
     dom_avg_ms = dom_ms / max(dom_n, 1)
-    nbytes = kernel_bytes(dominant, g, info, M)
     roofline = None
-    if nbytes is not None and dom_n > 0:
-        ach = nbytes / (dom_avg_ms * 1e-3) / 1e9
+    if dom_bytes > 0 and dom_n > 0:
+        per_launch = dom_bytes / dom_n
+        ach = per_launch / (dom_avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
-                    "kernel_ms": round(dom_avg_ms, 4), "alg_bytes": int(nbytes)}
+                    "kernel_ms": round(dom_avg_ms, 4), "launches_per_step": round(dom_n / args.steps, 2),
+                    "alg_bytes_per_launch": int(per_launch)}
         tfile = os.path.join(ROOT, "profiles", f"traffic_{dominant}_{args.workload}.json")
         if os.path.exists(tfile):
             tr = json.load(open(tfile))
@@ -172,6 +165,10 @@ def main():
             digest = src_digest([os.path.join(csrc, f) for f in sorted(os.listdir(csrc))])
             if tr.get("source_digest") == digest:
                 roofline["traffic"] = tr.get("traffic_bytes")
+    K_all = info["k"]
+    step_bytes = step_alg_bytes(g.n, g.m, M, K_all)
+    step_roof = {"alg_bytes": int(step_bytes), "achieved_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+                 "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     # parity of the benchmarked output and the CPU baseline: the serial oracle
     cpu = None
@@ -205,7 +202,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m, "offtree_edges": M, "k": K,
                    "alpha": g.alpha, "beta": g.beta, "ms_per_sparsifier": round(ms_step, 4),
                    "recovered_per_s": round(K / (ms_step * 1e-3), 1), "bit_exact_vs_oracle": bit_exact,
-                   "prefix_len": info["prefix_len"], "passes": info["passes"]},
+                   "prefix_len": info["prefix_len"], "passes": info["passes"], "join_edges": info["n_join"],
+                   "step_roofline": step_roof},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -96,6 +96,8 @@ typedef struct {
     int64_t largest_subtask;   /* edges sharing the most common LCA (GSS_F_STATS)        */
     int64_t prefix_len;        /* length of the criticality-order prefix resolved        */
     int64_t n_arcs;            /* strict-similarity pairs found inside that prefix       */
+    int64_t n_join;            /* prefix edges in subtasks above the work-queue limit,
+                                  resolved by the anchor hash join (all graphs of a batch) */
     int32_t passes;            /* passes that recovered at least one edge                */
     int32_t rounds;            /* dependency rounds used to resolve the prefix           */
 } gss_info;
@@ -103,7 +105,8 @@ typedef struct {
 /* Creates a context on `device` bound to `hip_stream` (a hipStream_t, may be NULL for
  * the default stream).  *out receives the handle.  Errors: ARG, HIP. */
 gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out);
-/* Rebinds the context to another stream. */
+/* Rebinds the context to another stream, after waiting for the work already queued on
+ * the old one (a context's work must form a single stream order).  Errors: ARG, HIP. */
 gss_status gss_ctx_set_stream(gss_ctx ctx, void *hip_stream);
 /* Frees the context's device memory.  Trees built on it must be freed first. */
 gss_status gss_ctx_destroy(gss_ctx ctx);
@@ -212,9 +215,12 @@ gss_status gss_costmodel_grad(gss_ctx ctx, const float *x, const float *y, int32
  * clears the accumulated figures. */
 gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name);
 /* Reads accumulated entry idx: its kernel name (copied into buf, NUL-terminated), total
- * milliseconds and launch count.  Returns the number of entries, -1 on a bad argument. */
+ * milliseconds, launch count and the algorithmic bytes of those launches (the least HBM
+ * traffic each launch's step needs: inputs read once, outputs written once; 0 for kernels
+ * without such a model).  Any output pointer may be NULL.  Returns the number of entries,
+ * -1 on a bad argument. */
 int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
-                             int64_t *launches);
+                             int64_t *launches, int64_t *alg_bytes);
 
 /* Library-owned, static strings. */
 const char *gss_status_str(gss_status s);

@@ -49,6 +49,7 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         HIP_OK(hipMalloc(&ctx->d_counters, 16 * sizeof(int64_t)));
         HIP_OK(hipHostMalloc(&ctx->h_counters, 16 * sizeof(int64_t), hipHostMallocDefault));
         HIP_OK(hipMemset(ctx->d_flags, 0, 256));
+        HIP_OK(hipMemset(ctx->d_counters, 0, 16 * sizeof(int64_t)));
         return GSS_OK;
     });
     if (s != GSS_OK) {
@@ -66,8 +67,13 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
 gss_status gss_ctx_set_stream(gss_ctx ctx, void *hip_stream)
 {
     if (!ctx) return GSS_ERR_ARG;
-    ctx->stream = (hipStream_t)hip_stream;
-    return GSS_OK;
+    // the context's work must stay in one stream order: drain the old stream first
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        ctx->stream = (hipStream_t)hip_stream;
+        return GSS_OK;
+    });
 }
 
 gss_status gss_ctx_destroy(gss_ctx ctx)
@@ -269,7 +275,7 @@ gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name)
 }
 
 int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
-                             int64_t *launches)
+                             int64_t *launches, int64_t *alg_bytes)
 {
     if (!ctx) return -1;
     int32_t count = (int32_t)ctx->prof_acc.size();
@@ -281,8 +287,9 @@ int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen
         memcpy(buf, it->first.data(), k);
         buf[k] = 0;
     }
-    if (total_ms) *total_ms = it->second.first;
-    if (launches) *launches = it->second.second;
+    if (total_ms) *total_ms = it->second.ms;
+    if (launches) *launches = it->second.launches;
+    if (alg_bytes) *alg_bytes = it->second.bytes;
     return count;
 }
 

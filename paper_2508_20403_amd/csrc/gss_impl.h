@@ -40,6 +40,12 @@ struct dev_pool {
 struct prof_rec {
     const char *name;
     hipEvent_t a, b;
+    int64_t bytes;  // algorithmic bytes of the launch (0: no model)
+};
+struct prof_sum {
+    double ms = 0;
+    int64_t launches = 0;
+    int64_t bytes = 0;
 };
 
 struct gss_ctx_s {
@@ -48,7 +54,8 @@ struct gss_ctx_s {
     std::string prof_filter;                       // empty: every kernel
     std::vector<prof_rec> prof_pending;
     std::vector<hipEvent_t> prof_events;           // free events
-    std::map<std::string, std::pair<double, int64_t>> prof_acc;  // name -> (ms, launches)
+    std::map<std::string, prof_sum> prof_acc;      // name -> totals
+    int64_t prof_bytes = 0;                        // algorithmic bytes of the next launch
     void prof_begin(const char *name);
     void prof_end();
     void prof_collect();                           // after a sync: accumulate elapsed times
@@ -69,9 +76,13 @@ struct gss_ctx_s {
     std::string last_error;
     dev_pool pool;
     uint32_t *d_flags = nullptr;      // device error flags
-    int64_t *d_counters = nullptr;    // small device scratch (16 words)
+    int64_t *d_counters = nullptr;    // small device scratch (16 words; word 15: look-back ticket)
     int64_t *h_counters = nullptr;    // pinned host mirror
     hipEvent_t ev_done = nullptr;
+    // status words of single-pass (look-back) scans and sorts, reused by epoch
+    uint64_t *lb_status = nullptr;
+    int64_t lb_cap = 0;
+    uint32_t lb_epoch = 0;
 
     template <typename T>
     T *alloc(size_t count)
@@ -145,6 +156,12 @@ gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *
 // ---- shared launch helpers (gss_prims.hip) -------------------------------------------
 // exclusive scan of int32 counts in place over [0,n); returns the total (host sync)
 int64_t scan_exclusive_i32(gss_ctx ctx, int32_t *data, int64_t n, bool want_total);
+// the same, leaving the total in device memory (no host round trip)
+void scan_exclusive_i32_dev(gss_ctx ctx, int32_t *data, int64_t n, int64_t *d_total);
+// status array of at least `words` words for one look-back launch, its epoch, and the
+// ticket counter (always zero between launches)
+uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch);
+inline unsigned long long *lb_ticket_ptr(gss_ctx ctx) { return (unsigned long long *)(ctx->d_counters + 15); }
 uint32_t read_flags(gss_ctx ctx);
 gss_status status_from_flags(uint32_t f);
 
@@ -154,6 +171,13 @@ gss_status status_from_flags(uint32_t f);
         if (ctx->prof) ctx->prof_begin(#kern);                          \
         hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__); \
         if (ctx->prof) ctx->prof_end();                                 \
+    } while (0)
+// the same, stating the launch's algorithmic bytes: the least HBM traffic the step it
+// performs needs (each input read once, each output written once), for roofline figures
+#define GSS_LAUNCH_B(bytes, kern, grid, block, shmem, stream, ...)          \
+    do {                                                                    \
+        if (ctx->prof) ctx->prof_bytes = (int64_t)(bytes);                  \
+        GSS_LAUNCH(kern, grid, block, shmem, stream, __VA_ARGS__);          \
     } while (0)
 
 inline unsigned grid_for(int64_t items, int block, int per_thread = 1)

@@ -426,115 +426,108 @@ __device__ __forceinline__ LVal arc_val(int32_t i, const u128 *__restrict__ T)
     return v;
 }
 
-struct ListLevel {
-    int32_t N;
-    const int32_t *nxt;   // successor (GSS_END terminates, -2 = not in the list)
-    const LVal *val;      // element values (null at level 0: arc values)
-    int32_t head;
-};
-
-__global__ void k_ruler_flags(int32_t N, const int32_t *__restrict__ nxt, int32_t head, int32_t level,
-                              int32_t *__restrict__ flag)
+// The list ranking runs without host round trips: every level's length and head live
+// in device memory, and each level's buffers are sized by a capacity (1.3x the expected
+// ruler count plus a margin).  A level that outgrows its capacity raises F_OVERFLOW and
+// the host repeats the ranking with larger capacities.
+//
+// Level l: elements i < N_l with successor nxt[i] (GSS_END ends the list, -2 = not in
+// the list) and value val(i).  Rulers (the head and a hashed 1/RULE_RATE sample) walk
+// their sublists once, recording for every element its ruler (owner) and the exclusive
+// sum of the sublist before it (loc); the rulers form the level l+1 list.  Once level
+// l+1 is ranked, every element's exclusive prefix is rpre[owner] + loc, one coalesced
+// pass with no walking.
+__device__ __forceinline__ LVal level_val(const LVal *__restrict__ val, const u128 *__restrict__ T, int32_t i)
 {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    flag[i] = (nxt[i] != -2 && is_ruler(i, head, level)) ? 1 : 0;
+    return val ? val[i] : arc_val(i, T);
 }
 
-__global__ void k_ruler_list(int32_t N, const int32_t *__restrict__ nxt, int32_t head, int32_t level,
-                             const int32_t *__restrict__ rid, int32_t *__restrict__ relem)
+// rid[i] = 1 for rulers (0 past N and for elements outside the list); owner[i] = -1
+__global__ void k_ruler_flags(int64_t cap, const int64_t *__restrict__ Np, const int32_t *__restrict__ nxt,
+                              const int32_t *__restrict__ headp, int32_t level, int32_t *__restrict__ rid,
+                              int32_t *__restrict__ owner)
 {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    if (nxt[i] != -2 && is_ruler(i, head, level)) relem[rid[i]] = i;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    const int64_t N = *Np;
+    const int32_t head = *headp;
+    int32_t f = 0;
+    if (i < N) {
+        f = (nxt[i] != -2 && is_ruler((int32_t)i, head, level)) ? 1 : 0;
+        owner[i] = -1;
+    }
+    rid[i] = f;
 }
 
-// walk 1: sum of each ruler's sublist and the next ruler
-__global__ void k_walk1(int32_t R, const int32_t *__restrict__ relem, const int32_t *__restrict__ rid,
-                        const int32_t *__restrict__ nxt, const LVal *__restrict__ val,
-                        const u128 *__restrict__ T, int32_t head, int32_t level, int32_t N,
-                        int32_t *__restrict__ rnxt, LVal *__restrict__ rval, uint32_t *flags)
+// relem[rid[i]] = i for rulers; the head's ruler id becomes the next level's head
+__global__ void k_ruler_list(int64_t cap, const int64_t *__restrict__ Np, const int32_t *__restrict__ nxt,
+                             const int32_t *__restrict__ headp, int32_t level, const int32_t *__restrict__ rid,
+                             int32_t *__restrict__ relem, int64_t cap_next, int32_t *__restrict__ head_next,
+                             uint32_t *flags)
 {
-    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap || i >= *Np) return;
+    const int32_t head = *headp;
+    if (nxt[i] == -2 || !is_ruler((int32_t)i, head, level)) return;
+    const int32_t r = rid[i];
+    if (r >= cap_next) {
+        atomicOr(flags, F_OVERFLOW);
+        return;
+    }
+    relem[r] = (int32_t)i;
+    if (i == head) *head_next = r;
+}
+
+// walk: one thread per ruler r < R_{l+1}
+__global__ void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp, const int32_t *__restrict__ relem,
+                        const int32_t *__restrict__ rid, const int32_t *__restrict__ nxt,
+                        const LVal *__restrict__ val, const u128 *__restrict__ T, const int32_t *__restrict__ headp,
+                        int32_t level, const int64_t *__restrict__ Np, int32_t *__restrict__ owner,
+                        LVal *__restrict__ loc, int32_t *__restrict__ rnxt, LVal *__restrict__ rval,
+                        uint32_t *flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= cap_next || r >= *Rp) return;
+    const int64_t N = *Np;
+    const int32_t head = *headp;
     int32_t i = relem[r];
-    LVal acc = val ? val[i] : arc_val(i, T);
-    int32_t j = nxt[i];
-    int32_t steps = 1;
-    while (j >= 0 && !is_ruler(j, head, level)) {
-        acc = lv_add(acc, val ? val[j] : arc_val(j, T));
-        j = nxt[j];
-        if (++steps > N) {
+    LVal acc = lv_zero();
+    int32_t j;
+    for (int64_t steps = 0;; steps++) {
+        owner[i] = (int32_t)r;
+        loc[i] = acc;
+        acc = lv_add(acc, level_val(val, T, i));
+        j = nxt[i];
+        if (j < 0 || is_ruler(j, head, level)) break;
+        if (steps > N) {  // a cycle without rulers beyond this one: not a tree
             atomicOr(flags, F_NOT_TREE);
             j = GSS_END;
             break;
         }
+        i = j;
     }
-    rnxt[r] = (j < 0) ? GSS_END : rid[j];
+    int32_t nr = (j < 0) ? GSS_END : rid[j];
+    if (nr >= cap_next) nr = GSS_END;  // overflow, already flagged by k_ruler_list
+    rnxt[r] = nr;
     rval[r] = acc;
 }
 
-// walk 2 at levels >= 1: exclusive prefix of every element
-__global__ void k_walk2(int32_t R, const int32_t *__restrict__ relem, const int32_t *__restrict__ nxt,
-                        const LVal *__restrict__ val, const LVal *__restrict__ rpre, int32_t head,
-                        int32_t level, int32_t N, LVal *__restrict__ pre)
-{
-    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    int32_t i = relem[r];
-    LVal acc = rpre[r];
-    for (int32_t steps = 0; steps <= N; steps++) {
-        pre[i] = acc;
-        acc = lv_add(acc, val[i]);
-        int32_t j = nxt[i];
-        if (j < 0 || is_ruler(j, head, level)) break;
-        i = j;
-    }
-}
-
-// walk 2 at level 0: emit the Euler tour, depth, first position and root resistance
-__global__ void k_walk2_euler(int32_t R, const int32_t *__restrict__ relem,
-                              const int32_t *__restrict__ nxt, const u128 *__restrict__ T,
-                              const LVal *__restrict__ rpre, const int32_t *__restrict__ parent,
-                              int32_t head, int32_t N, VRec *__restrict__ vrec,
-                              uint64_t *__restrict__ epk)
-{
-    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    int32_t i = relem[r];
-    LVal acc = rpre[r];
-    for (int32_t steps = 0; steps <= N; steps++) {
-        LVal v = arc_val(i, T);
-        LVal after = lv_add(acc, v);
-        int32_t x = i >> 1;
-        int32_t pos = acc.cnt + 1;  // Euler index of the vertex entered by this arc
-        if (i & 1) {
-            int32_t p = parent[x];
-            epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)p;
-        } else {
-            VRec r;
-            r.D = after.D;
-            r.first = pos;
-            r.depth = after.dep;
-            r.parent = parent[x];
-            r.pad = 0;
-            vrec[x] = r;
-            epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)x;
-        }
-        acc = after;
-        int32_t j = nxt[i];
-        if (j < 0 || is_ruler(j, head, 0)) break;
-        i = j;
-    }
-}
-
 // base case: Wyllie pointer jumping in LDS, exclusive prefix from the head
-__global__ __launch_bounds__(BASE_MAX) void k_rank_base(int32_t N, const int32_t *__restrict__ nxt,
-                                                        const LVal *__restrict__ val, int32_t head,
+__global__ __launch_bounds__(BASE_MAX) void k_rank_base(const int64_t *__restrict__ Np,
+                                                        const int32_t *__restrict__ nxt,
+                                                        const LVal *__restrict__ val,
+                                                        const int32_t *__restrict__ headp, int64_t expect,
                                                         LVal *__restrict__ pre, uint32_t *flags)
 {
     __shared__ int32_t snx[BASE_MAX];
     __shared__ LVal ssuf[BASE_MAX];
+    const int64_t N64 = *Np;
+    if (N64 > BASE_MAX) {  // uniform across the workgroup
+        if (threadIdx.x == 0) atomicOr(flags, F_OVERFLOW);
+        return;
+    }
+    const int32_t N = (int32_t)N64;
+    const int32_t head = *headp;
     int32_t i = threadIdx.x;
     if (i < N) {
         snx[i] = nxt[i];
@@ -564,47 +557,145 @@ __global__ __launch_bounds__(BASE_MAX) void k_rank_base(int32_t N, const int32_t
         __syncthreads();
     }
     if (i < N && snx[i] >= 0) atomicOr(flags, F_NOT_TREE);
+    // the tour from the head must hold every arc: fewer means some vertices never reach
+    // the root through their parents (a cycle)
+    if (i == 0 && (head < 0 || head >= N || ssuf[head].cnt != expect)) atomicOr(flags, F_NOT_TREE);
     __syncthreads();
-    if (i < N) pre[i] = lv_sub(ssuf[head], ssuf[i]);
+    if (i < N && head >= 0 && head < N) pre[i] = lv_sub(ssuf[head], ssuf[i]);
 }
 
-// recursive ranking of a level >= 1 list: pre[i] = exclusive prefix from the head
-static void rank_list(gss_ctx ctx, int32_t level, int32_t N, const int32_t *nxt, const LVal *val,
-                      int32_t head, LVal *pre)
+// downward pass, levels >= 1: pre[i] = rpre[owner[i]] + loc[i]
+__global__ void k_rank_apply(int64_t cap, const int64_t *__restrict__ Np, const int32_t *__restrict__ owner,
+                             const LVal *__restrict__ loc, const LVal *__restrict__ rpre, LVal *__restrict__ pre)
 {
-    hipStream_t st = ctx->stream;
-    if (N <= BASE_MAX) {
-        GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_MAX), 0, st, N, nxt, val, head, pre,
-                           ctx->d_flags);
-        HIP_OK(hipGetLastError());
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap || i >= *Np) return;
+    const int32_t o = owner[i];
+    pre[i] = (o >= 0) ? lv_add(rpre[o], loc[i]) : lv_zero();
+}
+
+// downward pass, level 0: emit the Euler tour, depth, first position and root resistance
+// of every arc's vertex.  Arc 2x enters x from its parent, arc 2x+1 returns to it.
+__global__ void k_euler_emit(int32_t N, const int32_t *__restrict__ owner, const LVal *__restrict__ loc,
+                             const LVal *__restrict__ rpre, const u128 *__restrict__ T,
+                             const int32_t *__restrict__ parent, int32_t L, VRec *__restrict__ vrec,
+                             uint64_t *__restrict__ epk, uint32_t *flags)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t o = owner[i];
+    if (o < 0) return;  // not on the tour: k_check_reached reports it
+    const LVal acc = lv_add(rpre[o], loc[i]);
+    const LVal after = lv_add(acc, arc_val(i, T));
+    const int32_t x = i >> 1;
+    const int32_t pos = acc.cnt + 1;  // Euler index of the vertex entered by this arc
+    if (pos < 1 || pos >= L) {
+        atomicOr(flags, F_NOT_TREE);
         return;
     }
-    int32_t *rid = ctx->alloc<int32_t>(N + 1);
-    GSS_LAUNCH(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid);
-    int64_t R = scan_exclusive_i32(ctx, rid, N, true);
-    int32_t *relem = ctx->alloc<int32_t>(R + 1);
-    int32_t *rnxt = ctx->alloc<int32_t>(R + 1);
-    LVal *rval = ctx->alloc<LVal>(R + 1);
-    LVal *rpre = ctx->alloc<LVal>(R + 1);
-    GSS_LAUNCH(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, nxt, head, level, rid,
-                       relem);
-    GSS_LAUNCH(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, nxt,
-                       val, (const u128 *)nullptr, head, level, N, rnxt, rval, ctx->d_flags);
+    const int32_t p = parent[x];
+    if (i & 1) {
+        epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)p;
+    } else {
+        VRec r;
+        r.D = after.D;
+        r.first = pos;
+        r.depth = after.dep;
+        r.parent = p;
+        r.pad = 0;
+        vrec[x] = r;
+        epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)x;
+    }
+}
+
+__global__ void k_level_init(int64_t N0, const int64_t *__restrict__ head0, int nlev, int64_t *__restrict__ len,
+                             int32_t *__restrict__ heads)
+{
+    for (int l = threadIdx.x; l <= nlev; l += blockDim.x) {
+        len[l] = (l == 0) ? N0 : 0;
+        heads[l] = (l == 0) ? (int32_t)*head0 : -1;
+    }
+}
+
+static inline int64_t next_cap(int64_t cap, int mult)
+{
+    return cap * mult * 21 / (RULE_RATE * 16) + 256;  // 1.3125x the expected ruler count
+}
+
+// Ranks the Euler tour (succ over N = 2n arcs, head arc in *d_head) and emits vrec / epk.
+// Returns without a host round trip; F_OVERFLOW in the flags asks for a retry with a
+// larger capacity multiplier.
+static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 *T, const int64_t *d_head,
+                       int mult, std::vector<void *> &bufs)
+{
+    hipStream_t st = ctx->stream;
+    const int32_t n = t->n;
+    const int64_t N0 = 2 * (int64_t)n;
+    struct Lv {
+        int64_t cap;
+        const int32_t *nxt;
+        const LVal *val;
+        const int32_t *headp;
+        const int64_t *Np;
+        int32_t *owner;
+        LVal *loc;
+        LVal *pre;
+    };
+    // device scalars: level lengths and heads
+    const int max_levels = 40;
+    int64_t *d_len = ctx->alloc<int64_t>(max_levels + 1);
+    int32_t *d_heads = ctx->alloc<int32_t>(max_levels + 1);
+    bufs.push_back(d_len);
+    bufs.push_back(d_heads);
+    GSS_LAUNCH(k_level_init, dim3(1), dim3(64), 0, st, N0, d_head, max_levels, d_len, d_heads);
+    std::vector<Lv> lv;
+    lv.push_back(Lv{N0, succ, nullptr, d_heads, d_len, nullptr, nullptr, nullptr});
+    // upward: build levels until the capacity fits one workgroup
+    for (int l = 0; l == 0 || lv.back().cap > BASE_MAX; l++) {
+        if (l + 1 >= max_levels) throw gss_error{GSS_ERR_HIP, "list ranking: too many levels"};
+        Lv &a = lv.back();
+        const int64_t cap = a.cap;
+        const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult), cap);
+        int32_t *rid = ctx->alloc<int32_t>(cap + 1);
+        a.owner = ctx->alloc<int32_t>(cap + 1);
+        a.loc = ctx->alloc<LVal>(cap + 1);
+        int32_t *relem = ctx->alloc<int32_t>(cap2 + 1);
+        int32_t *rnxt = ctx->alloc<int32_t>(cap2 + 1);
+        LVal *rval = ctx->alloc<LVal>(cap2 + 1);
+        for (void *p : {(void *)rid, (void *)a.owner, (void *)a.loc, (void *)relem, (void *)rnxt, (void *)rval})
+            bufs.push_back(p);
+        GSS_LAUNCH_B(8 * cap, k_ruler_flags, dim3(grid_for(cap, PB)), dim3(PB), 0, st, cap, a.Np, a.nxt, a.headp, l,
+                     rid, a.owner);
+        scan_exclusive_i32_dev(ctx, rid, cap, d_len + l + 1);
+        GSS_LAUNCH_B(4 * cap + 8 * cap2 / 1, k_ruler_list, dim3(grid_for(cap, PB)), dim3(PB), 0, st, cap, a.Np, a.nxt,
+                     a.headp, l, rid, relem, cap2, d_heads + l + 1, ctx->d_flags);
+        // one walk over every element: successor and value read, owner and local prefix
+        // written; one record per ruler
+        GSS_LAUNCH_B((l == 0 ? 24 : 32) * cap + 28 * cap + 36 * cap2, k_walk1, dim3(grid_for(cap2, PB)), dim3(PB), 0,
+                     st, cap2, d_len + l + 1, relem, rid, a.nxt, a.val, T, a.headp, l, a.Np, a.owner, a.loc, rnxt,
+                     rval, ctx->d_flags);
+        lv.push_back(Lv{cap2, rnxt, rval, d_heads + l + 1, d_len + l + 1, nullptr, nullptr, nullptr});
+    }
+    // base level
+    Lv &b = lv.back();
+    b.pre = ctx->alloc<LVal>(b.cap + 1);
+    bufs.push_back(b.pre);
+    GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_MAX), 0, st, b.Np, b.nxt, b.val, b.headp, N0 - 2, b.pre,
+               ctx->d_flags);
+    // downward
+    for (int l = (int)lv.size() - 2; l >= 1; l--) {
+        Lv &a = lv[l];
+        a.pre = ctx->alloc<LVal>(a.cap + 1);
+        bufs.push_back(a.pre);
+        GSS_LAUNCH_B(4 * a.cap + 24 * a.cap + 24 * lv[l + 1].cap + 24 * a.cap, k_rank_apply,
+                     dim3(grid_for(a.cap, PB)), dim3(PB), 0, st, a.cap, a.Np, a.owner, a.loc, lv[l + 1].pre, a.pre);
+    }
+    if (lv.size() == 1) throw gss_error{GSS_ERR_HIP, "list ranking: tour shorter than one workgroup"};
+    // level 0: per arc owner, local prefix, term and parent read, Euler entry written; per
+    // vertex a 32-byte record
+    GSS_LAUNCH_B(52 * N0 + 24 * lv[1].cap + 8 * N0 + 16 * N0, k_euler_emit, dim3(grid_for(N0, PB)), dim3(PB), 0, st,
+                 (int32_t)N0, lv[0].owner, lv[0].loc, lv[1].pre, T, t->parent, t->L, t->vrec, t->epk, ctx->d_flags);
     HIP_OK(hipGetLastError());
-    // the head is always a ruler; its ruler id is rid[head]
-    int32_t rhead = 0;
-    HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], rid + head, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    ctx->sync();
-    memcpy(&rhead, &ctx->h_counters[13], sizeof rhead);
-    rank_list(ctx, level + 1, (int32_t)R, rnxt, rval, rhead, rpre);
-    GSS_LAUNCH(k_walk2, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, nxt, val, rpre,
-                       head, level, N, pre);
-    HIP_OK(hipGetLastError());
-    ctx->free(rid);
-    ctx->free(relem);
-    ctx->free(rnxt);
-    ctx->free(rval);
-    ctx->free(rpre);
 }
 
 // ------------------------------------------------------------------------------------
@@ -615,23 +706,50 @@ static void rank_list(gss_ctx ctx, int32_t level, int32_t N, const int32_t *nxt,
 // than every value in (q, i] (so the lowest set bit at or above a start s is the
 // position of the minimum of [s, i]); the prefix minimum of [0, i]; the suffix minimum
 // of [i, run end].
+//
+// The mask is the chain i, psv(i), psv(psv(i)), ... of previous strictly smaller values
+// (mask(i) = {i} + mask(psv(i))).  psv comes from binary lifting over window minima
+// that end at each lane, and the chain union from six pointer-doubling steps, all with
+// lane permutes: about 170 instructions per run instead of a 64-step scan per lane.
+__device__ __forceinline__ uint64_t bperm64(uint64_t v, int src)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
 __device__ __forceinline__ void wave_run(uint64_t v, uint64_t &mask, uint64_t &pre, uint64_t &suf)
 {
     const int lane = lane_id();
-    uint64_t m = ~0ull;
-    mask = 0;
-    const uint32_t vlo = (uint32_t)v, vhi = (uint32_t)(v >> 32);
-    for (int q = 63; q >= 0; q--) {
-        uint64_t vq = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vhi, q) << 32) |
-                      (uint32_t)__builtin_amdgcn_readlane((int)vlo, q);
-        if (q == lane) {
-            mask |= 1ull << q;
-            m = vq;
-        } else if (q < lane) {
-            if (vq < m) mask |= 1ull << q;
-            m = vq < m ? vq : m;
+    // win[k] = minimum of the (up to) 2^k values ending at this lane
+    uint64_t win[6];
+    win[0] = v;
+#pragma unroll
+    for (int k = 1; k < 6; k++) {
+        const int h = 1 << (k - 1);
+        const uint64_t y = __shfl_up(win[k - 1], h, GSS_WAVE);
+        win[k] = (lane >= h && y < win[k - 1]) ? y : win[k - 1];
+    }
+    // previous strictly smaller value: skip maximal windows whose minimum is >= v
+    int pos = lane - 1;
+#pragma unroll
+    for (int k = 5; k >= 0; k--) {
+        const uint64_t t = bperm64(win[k], pos > 0 ? pos : 0);
+        if (pos >= 0 && t >= v) pos -= 1 << k;
+    }
+    int j = pos >= 0 ? pos : -1;
+    uint64_t m = 1ull << lane;
+#pragma unroll
+    for (int s = 0; s < 6; s++) {
+        const int src = j > 0 ? j : 0;
+        const uint64_t mj = bperm64(m, src);
+        const int jj = __builtin_amdgcn_ds_bpermute(src << 2, j);
+        if (j >= 0) {
+            m |= mj;
+            j = jj;
         }
     }
+    mask = m;
     pre = v;
     suf = v;
 #pragma unroll
@@ -885,7 +1003,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         GSS_LAUNCH(k_check_rowptr, dim3(grid_for(n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
                    ctx->d_flags);
         if (nnz > 0)
-            GSS_LAUNCH(k_check_entries, dim3(grid_for(nnz, ETILE)), dim3(PB), 0, st, t->row_ptr, t->col, t->w, n,
+            GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3(grid_for(nnz, ETILE)), dim3(PB), 0,
+                         st, t->row_ptr, t->col, t->w, n,
                        nnz, ctx->d_flags, (unsigned long long *)(ctx->d_counters + 10));
         HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, 2 * sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
@@ -909,7 +1028,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     int64_t init_c[4] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40)};
     memcpy(ctx->h_counters, init_c, sizeof init_c);
     HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
-    GSS_LAUNCH(k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st, t->parent, t->row_ptr,
+    GSS_LAUNCH_B(32 * (int64_t)n, k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st,
+                 t->parent, t->row_ptr,
                t->col, t->w, n, t->virt_root, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     uint32_t f = read_flags(ctx);  // syncs
@@ -935,7 +1055,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     int32_t *clist = ctx->alloc<int32_t>(n);
     int32_t *cslot = ctx->alloc<int32_t>(n);
     HIP_OK(hipMemsetAsync(cfill, 0, sizeof(int32_t) * n, st));
-    GSS_LAUNCH(k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr, cfill, clist, cslot);
+    GSS_LAUNCH_B(20 * (int64_t)n, k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr,
+                 cfill, clist, cslot);
 
     // fixed-point terms and the 127-bit range check
     u128 *T = ctx->alloc<u128>(n);
@@ -943,7 +1064,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     u128 *tbs = ctx->alloc<u128>(tb);
     uint64_t *tbc = ctx->alloc<uint64_t>(tb);
     const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
-    GSS_LAUNCH(k_terms, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, n, t->root, (int)emin, terms_ok, T, tbs,
+    GSS_LAUNCH_B(28 * (int64_t)n, k_terms, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, n, t->root, (int)emin,
+                 terms_ok, T, tbs,
                tbc);
     GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
 
@@ -956,41 +1078,31 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     if (n > 1) {
         int32_t N = 2 * n;
         int32_t *succ = ctx->alloc<int32_t>(N);
-        GSS_LAUNCH(k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n, t->root, succ);
+        GSS_LAUNCH_B(24 * (int64_t)n, k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n,
+                     t->root, succ);
         GSS_LAUNCH(k_head, dim3(1), dim3(1), 0, st, cptr, clist, t->root, ctx->d_counters + 12);
-        HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], ctx->d_counters + 12, sizeof(int64_t), hipMemcpyDeviceToHost,
-                              st));
-        ctx->sync();
-        int32_t head = (int32_t)ctx->h_counters[12];
-
-        int32_t *rid = ctx->alloc<int32_t>(N + 1);
-        GSS_LAUNCH(k_ruler_flags, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid);
-        int64_t R = scan_exclusive_i32(ctx, rid, N, true);
-        int32_t *relem = ctx->alloc<int32_t>(R + 1);
-        int32_t *rnxt = ctx->alloc<int32_t>(R + 1);
-        LVal *rval = ctx->alloc<LVal>(R + 1);
-        LVal *rpre = ctx->alloc<LVal>(R + 1);
-        GSS_LAUNCH(k_ruler_list, dim3(grid_for(N, PB)), dim3(PB), 0, st, N, succ, head, 0, rid, relem);
-        GSS_LAUNCH(k_walk1, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, rid, succ,
-                   (const LVal *)nullptr, T, head, 0, N, rnxt, rval, ctx->d_flags);
-        int32_t rhead = 0;
-        HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], rid + head, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        ctx->sync();
-        memcpy(&rhead, &ctx->h_counters[13], sizeof rhead);
-        rank_list(ctx, 1, (int32_t)R, rnxt, rval, rhead, rpre);
-        GSS_LAUNCH(k_walk2_euler, dim3(grid_for(R, PB)), dim3(PB), 0, st, (int32_t)R, relem, succ, T, rpre, t->parent,
-                   head, N, t->vrec, t->epk);
-        GSS_LAUNCH(k_check_reached, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, ctx->d_flags);
-        HIP_OK(hipGetLastError());
-        ctx->free(rid);
-        ctx->free(relem);
-        ctx->free(rnxt);
-        ctx->free(rval);
-        ctx->free(rpre);
+        for (int mult = 1;; mult *= 2) {
+            std::vector<void *> bufs;
+            euler_rank(ctx, t, succ, T, ctx->d_counters + 12, mult, bufs);
+            GSS_LAUNCH(k_check_reached, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, ctx->d_flags);
+            GSS_LAUNCH(k_vrec_tdeg, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec);
+            f = read_flags(ctx);
+            for (void *p : bufs) ctx->free(p);
+            if (!(f & F_OVERFLOW) || (f & F_NOT_TREE)) break;
+            if (mult >= 8) {
+                ctx->free(succ);
+                fail(GSS_ERR_HIP, "list ranking: level capacity exceeded");
+            }
+            // a level outgrew its capacity (vanishingly rare): rank again with more room
+            HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+            GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n);
+            GSS_LAUNCH(k_root_init, dim3(1), dim3(1), 0, st, t->root, t->vrec, t->epk);
+        }
         ctx->free(succ);
+    } else {
+        GSS_LAUNCH(k_vrec_tdeg, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec);
+        f = read_flags(ctx);
     }
-    GSS_LAUNCH(k_vrec_tdeg, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec);
-    f = read_flags(ctx);
     ctx->free(cfill);
     ctx->free(clist);
     ctx->free(cslot);
@@ -1017,7 +1129,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->bpre = ctx->alloc<uint64_t>(t->nb);
     t->bsuf = ctx->alloc<uint64_t>(t->nb);
     t->sbst = ctx->alloc<uint64_t>((int64_t)t->sblevels * t->nsb);
-    GSS_LAUNCH(k_rmq_blocks, dim3(grid_for(t->nb, RMQ_WPB)), dim3(RMQ_WPB * 64), 0, st, t->epk, L, t->pmask, t->ppre,
+    GSS_LAUNCH_B(32 * (int64_t)L + 8 * (int64_t)t->nb, k_rmq_blocks, dim3(grid_for(t->nb, RMQ_WPB)),
+                 dim3(RMQ_WPB * 64), 0, st, t->epk, L, t->pmask, t->ppre,
                t->psuf, t->bmin, t->nb);
     GSS_LAUNCH(k_rmq_super, dim3(grid_for(t->nsb, RMQ_WPB)), dim3(RMQ_WPB * 64), 0, st, t->bmin, t->nb, t->bmask,
                t->bpre, t->bsuf, t->sbst, t->nsb);
@@ -1032,7 +1145,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     if (nnz > 0) {
         int64_t nblk = grid_for(nnz, ETILE);
         int32_t *ocnt = ctx->alloc<int32_t>(nblk + 1);
-        GSS_LAUNCH(k_offtree_count, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr, t->col, t->parent, n, nnz,
+        GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n, k_offtree_count, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr,
+                     t->col, t->parent, n, nnz,
                    ocnt);
         int64_t M2 = scan_exclusive_i32(ctx, ocnt, nblk, true);
         if (M2 != t->M) {
@@ -1040,13 +1154,15 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
             fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
         }
         if (t->G > 1 || t->virt_root >= 0) t->off_g = ctx->alloc<int32_t>(t->M + 1);
-        GSS_LAUNCH(k_offtree_write, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr, t->col, t->w, t->parent,
+        GSS_LAUNCH_B(4 * nnz + 8 * t->m + 12 * (int64_t)n + 20 * t->M, k_offtree_write, dim3((unsigned)nblk), dim3(PB),
+                     0, st, t->row_ptr, t->col, t->w, t->parent,
                    t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G,
                    t->off_g);
         ctx->free(ocnt);
     }
     t->tree_eid = ctx->alloc<int32_t>(n);
-    GSS_LAUNCH(k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col, t->uptr, t->ufirst,
+    GSS_LAUNCH_B(20 * (int64_t)n, k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col,
+                 t->uptr, t->ufirst,
                t->tpos, n, t->tree_eid);
     HIP_OK(hipGetLastError());
     ctx->sync();

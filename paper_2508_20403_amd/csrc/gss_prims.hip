@@ -1,5 +1,6 @@
 // gss_prims.hip -- device allocator, error flags and the exclusive scan used throughout.
 #include "gss_impl.h"
+#include "gss_lookback.h"
 
 // ------------------------------------------------------------------------------------
 // caching allocator
@@ -60,12 +61,15 @@ void dev_pool::release_all()
 // ------------------------------------------------------------------------------------
 void gss_ctx_s::prof_begin(const char *name)
 {
+    const int64_t bytes = prof_bytes;
+    prof_bytes = 0;
     if (!prof_filter.empty() && prof_filter != name) {
-        prof_pending.push_back(prof_rec{nullptr, nullptr, nullptr});
+        prof_pending.push_back(prof_rec{nullptr, nullptr, nullptr, 0});
         return;
     }
     prof_rec r;
     r.name = name;
+    r.bytes = bytes;
     for (hipEvent_t *e : {&r.a, &r.b}) {
         if (prof_events.empty()) HIP_OK(hipEventCreate(e));
         else {
@@ -90,9 +94,10 @@ void gss_ctx_s::prof_collect()
         float ms = 0.f;
         HIP_OK(hipEventSynchronize(r.b));
         HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
-        auto &acc = prof_acc[r.name];
-        acc.first += ms;
-        acc.second += 1;
+        prof_sum &acc = prof_acc[r.name];
+        acc.ms += ms;
+        acc.launches += 1;
+        acc.bytes += r.bytes;
         prof_events.push_back(r.a);
         prof_events.push_back(r.b);
     }
@@ -125,65 +130,112 @@ gss_status status_from_flags(uint32_t f)
 }
 
 // ------------------------------------------------------------------------------------
-// exclusive scan of int32, three phases
+// exclusive scan of int32, one pass (decoupled look-back between tiles)
 // ------------------------------------------------------------------------------------
 #define SCAN_BLOCK 256
-#define SCAN_ITEMS 16
+#define SCAN_ROUNDS 4
+#define SCAN_TILE (SCAN_BLOCK * 4 * SCAN_ROUNDS)  // elements per tile
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *__restrict__ in,
-                                                            int64_t n, int64_t *__restrict__ bsum)
+// Thread t of round r owns the four consecutive elements at tile offset 4 (r*256 + t),
+// read and written as one 16-byte vector, so every round is fully coalesced.
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_onepass(int32_t *__restrict__ data, int64_t n,
+                                                             int64_t ntiles, uint64_t *__restrict__ status,
+                                                             uint32_t epoch, unsigned long long *ticket,
+                                                             int64_t *__restrict__ total)
 {
-    __shared__ int64_t lds[SCAN_BLOCK / GSS_WAVE + 1];
-    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK * SCAN_ITEMS;
-    int64_t s = 0;
+    constexpr int NW = SCAN_BLOCK / GSS_WAVE;
+    __shared__ int64_t s_wsum[SCAN_ROUNDS][NW];
+    __shared__ int64_t s_tile, s_excl;
+    const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
+    if (threadIdx.x == 0) s_tile = lb_ticket(ticket, ntiles);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * SCAN_TILE;
+    int4 v[SCAN_ROUNDS];
+    int64_t incl[SCAN_ROUNDS];
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t k = base + (int64_t)i * SCAN_BLOCK + threadIdx.x;
-        if (k < n) s += in[k];
+    for (int r = 0; r < SCAN_ROUNDS; r++) {
+        const int64_t e = base + ((int64_t)r * SCAN_BLOCK + threadIdx.x) * 4;
+        if (e + 4 <= n) {
+            v[r] = *(const int4 *)(data + e);
+        } else {
+            v[r].x = (e < n) ? data[e] : 0;
+            v[r].y = (e + 1 < n) ? data[e + 1] : 0;
+            v[r].z = (e + 2 < n) ? data[e + 2] : 0;
+            v[r].w = 0;
+        }
+        int64_t x = (int64_t)v[r].x + v[r].y + v[r].z + v[r].w;
+#pragma unroll
+        for (int d = 1; d < GSS_WAVE; d <<= 1) {
+            int64_t y = __shfl_up(x, d, GSS_WAVE);
+            if (lane >= d) x += y;
+        }
+        incl[r] = x;
+        if (lane == GSS_WAVE - 1) s_wsum[r][wid] = x;
     }
-    int64_t tot;
-    block_exclusive_scan<int64_t>(s, lds, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    __syncthreads();
+    // offsets of (round, wave) pieces in tile order, and the tile total
+    int64_t off[SCAN_ROUNDS];
+    int64_t run = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ROUNDS; r++) {
+        for (int w = 0; w < NW; w++) {
+            if (w == wid) off[r] = run;
+            run += s_wsum[r][w];
+        }
+    }
+    const int64_t tile_total = run;
+    if (wid == 0) {
+        int64_t excl = 0;
+        if (tile == 0) {
+            if (lane == 0) lb_store(status, lb_word(LB_INC, epoch, (uint64_t)tile_total));
+        } else {
+            if (lane == 0) lb_store(status + tile, lb_word(LB_AGG, epoch, (uint64_t)tile_total));
+            excl = lb_lookback_wave(status, 1, tile, epoch);
+            if (lane == 0) lb_store(status + tile, lb_word(LB_INC, epoch, (uint64_t)(excl + tile_total)));
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            if (tile == ntiles - 1) *total = excl + tile_total;
+        }
+    }
+    __syncthreads();
+    const int64_t excl = s_excl;
+#pragma unroll
+    for (int r = 0; r < SCAN_ROUNDS; r++) {
+        const int64_t e = base + ((int64_t)r * SCAN_BLOCK + threadIdx.x) * 4;
+        const int64_t p0 = excl + off[r] + incl[r] - ((int64_t)v[r].x + v[r].y + v[r].z + v[r].w);
+        int4 o;
+        o.x = (int32_t)p0;
+        o.y = (int32_t)(p0 + v[r].x);
+        o.z = (int32_t)(p0 + v[r].x + v[r].y);
+        o.w = (int32_t)(p0 + v[r].x + v[r].y + v[r].z);
+        if (e + 4 <= n) {
+            *(int4 *)(data + e) = o;
+        } else {
+            if (e < n) data[e] = o.x;
+            if (e + 1 < n) data[e + 1] = o.y;
+            if (e + 2 < n) data[e + 2] = o.z;
+        }
+    }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_bsums(int64_t *__restrict__ bsum, int64_t nb,
-                                                     int64_t *__restrict__ total)
+uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch)
 {
-    __shared__ int64_t lds[1024 / GSS_WAVE + 1];
-    int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
-        int64_t k = b0 + threadIdx.x;
-        int64_t v = (k < nb) ? bsum[k] : 0;
-        int64_t tot;
-        int64_t ex = block_exclusive_scan<int64_t>(v, lds, &tot);
-        if (k < nb) bsum[k] = ex + carry;
-        carry += tot;
+    if (words > ctx->lb_cap) {
+        ctx->free(ctx->lb_status);
+        const int64_t cap = std::max<int64_t>(words, 1 << 16);
+        ctx->lb_status = ctx->alloc<uint64_t>(cap);
+        HIP_OK(hipMemsetAsync(ctx->lb_status, 0, sizeof(uint64_t) * cap, ctx->stream));
+        ctx->lb_cap = cap;
+        ctx->lb_epoch = 0;
     }
-    if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(int32_t *__restrict__ data, int64_t n,
-                                                           const int64_t *__restrict__ bsum)
-{
-    __shared__ int64_t lds[SCAN_BLOCK / GSS_WAVE + 1];
-    // each thread owns SCAN_ITEMS consecutive elements of the block's tile
-    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK * SCAN_ITEMS + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int32_t v[SCAN_ITEMS];
-    int64_t s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t k = base + i;
-        v[i] = (k < n) ? data[k] : 0;
-        s += v[i];
+    if (++ctx->lb_epoch >= (1u << LB_EPOCH_BITS)) {
+        HIP_OK(hipMemsetAsync(ctx->lb_status, 0, sizeof(uint64_t) * ctx->lb_cap, ctx->stream));
+        ctx->lb_epoch = 1;
     }
-    int64_t tot;
-    int64_t ex = block_exclusive_scan<int64_t>(s, lds, &tot) + bsum[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t k = base + i;
-        if (k < n) data[k] = (int32_t)ex;
-        ex += v[i];
-    }
+    *epoch = ctx->lb_epoch;
+    return ctx->lb_status;
 }
 
 // one workgroup scans the whole array in chunks (short arrays: one launch instead of three)
@@ -214,28 +266,26 @@ __global__ __launch_bounds__(1024) void k_scan_single(int32_t *__restrict__ data
     if (threadIdx.x == 0) *total = carry;
 }
 
+void scan_exclusive_i32_dev(gss_ctx ctx, int32_t *data, int64_t n, int64_t *d_total)
+{
+    if (n <= 0) throw gss_error{GSS_ERR_ARG, "scan: empty array"};
+    if (n <= 32 * 1024) {
+        GSS_LAUNCH_B(8 * n, k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, data, n, d_total);
+    } else {
+        if (((uintptr_t)data & 15) != 0) throw gss_error{GSS_ERR_ARG, "scan: misaligned array"};
+        const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+        uint32_t epoch = 0;
+        uint64_t *status = lb_begin(ctx, ntiles, &epoch);
+        GSS_LAUNCH_B(8 * n, k_scan_onepass, dim3((unsigned)ntiles), dim3(SCAN_BLOCK), 0, ctx->stream, data, n, ntiles,
+                     status, epoch, lb_ticket_ptr(ctx), d_total);
+    }
+    HIP_OK(hipGetLastError());
+}
+
 int64_t scan_exclusive_i32(gss_ctx ctx, int32_t *data, int64_t n, bool want_total)
 {
     if (n <= 0) return 0;
-    if (n <= 32 * 1024) {
-        GSS_LAUNCH(k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, data, n, ctx->d_counters + 14);
-        HIP_OK(hipGetLastError());
-        if (!want_total) return -1;
-        HIP_OK(hipMemcpyAsync(&ctx->h_counters[14], ctx->d_counters + 14, sizeof(int64_t),
-                              hipMemcpyDeviceToHost, ctx->stream));
-        ctx->sync();
-        return ctx->h_counters[14];
-    }
-    int64_t nb = (n + SCAN_BLOCK * SCAN_ITEMS - 1) / (SCAN_BLOCK * SCAN_ITEMS);
-    int64_t *bsum = ctx->alloc<int64_t>(nb + 1);
-    GSS_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, ctx->stream, data, n,
-                       bsum);
-    GSS_LAUNCH(k_scan_bsums, dim3(1), dim3(1024), 0, ctx->stream, bsum, nb,
-                       ctx->d_counters + 14);
-    GSS_LAUNCH(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, ctx->stream, data, n,
-                       bsum);
-    HIP_OK(hipGetLastError());
-    ctx->free(bsum);
+    scan_exclusive_i32_dev(ctx, data, n, ctx->d_counters + 14);
     if (!want_total) return -1;
     HIP_OK(hipMemcpyAsync(&ctx->h_counters[14], ctx->d_counters + 14, sizeof(int64_t),
                           hipMemcpyDeviceToHost, ctx->stream));

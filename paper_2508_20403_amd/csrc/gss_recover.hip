@@ -28,6 +28,7 @@
 #include <cmath>
 
 #include "gss_impl.h"
+#include "gss_lookback.h"
 #include "gss_subtask.h"
 
 #define RB 256
@@ -388,95 +389,118 @@ __global__ void k_graph_key(int64_t P, const int32_t *__restrict__ pj, const int
     if (p < P) gk[p] = (uint64_t)(uint32_t)off_g[pj[p]];
 }
 
-__global__ __launch_bounds__(1024) void k_key_varying(const uint64_t *__restrict__ k, int64_t n,
-                                                      uint64_t *out)
-{
-    __shared__ uint64_t so[1024], sa[1024];
-    uint64_t o = 0, a = ~0ull;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
-        o |= k[i];
-        a &= k[i];
-    }
-    so[threadIdx.x] = o;
-    sa[threadIdx.x] = a;
-    __syncthreads();
-    for (int h = 512; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            so[threadIdx.x] |= so[threadIdx.x + h];
-            sa[threadIdx.x] &= sa[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = so[0] ^ sa[0];
-}
-
+// ------------------------------------------------------------------------------------
+// stable LSD radix sort of (64-bit key, int32 value) pairs, 8-bit digits: one histogram
+// pass over the keys for all digit positions, then one scatter kernel per varying
+// digit, whose tiles learn their per-digit output bases by decoupled look-back
+// ------------------------------------------------------------------------------------
 #define RS_BLOCK 256
-#define RS_ITEMS 4
+#define RS_ITEMS 8
 #define RS_TILE (RS_BLOCK * RS_ITEMS)
 
-// per-tile digit counts, stored digit-major: cnt[d * ntiles + tile]
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *__restrict__ k, int64_t n, int shift,
-                                                      int32_t ntiles, int32_t *__restrict__ cnt)
+// global digit counts of all eight byte positions: ghist[pos * 256 + digit] (zeroed)
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restrict__ k, int64_t n,
+                                                       int32_t *__restrict__ ghist)
 {
-    __shared__ int32_t sh[256];
-    sh[threadIdx.x] = 0;
+    __shared__ int32_t sh[8][256];
+#pragma unroll
+    for (int p = 0; p < 8; p++) sh[p][threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int i = 0; i < RS_ITEMS; i++) {
-        int64_t idx = base + (int64_t)i * RS_BLOCK + threadIdx.x;
-        if (idx < n) atomicAdd(&sh[(uint32_t)(k[idx] >> shift) & 255u], 1);
+    for (int64_t i = (int64_t)blockIdx.x * RS_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * RS_BLOCK) {
+        const uint64_t kk = k[i];
+#pragma unroll
+        for (int p = 0; p < 8; p++) atomicAdd(&sh[p][(uint32_t)(kk >> (8 * p)) & 255u], 1);
     }
     __syncthreads();
-    cnt[(int64_t)threadIdx.x * ntiles + blockIdx.x] = sh[threadIdx.x];
+#pragma unroll
+    for (int p = 0; p < 8; p++) {
+        const int32_t c = sh[p][threadIdx.x];
+        if (c) atomicAdd(&ghist[p * 256 + threadIdx.x], c);
+    }
 }
 
-// stable scatter: items are ranked in (round, thread) order, which is index order
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *__restrict__ kin,
-                                                         const int32_t *__restrict__ vin, int64_t n,
-                                                         int shift, int32_t ntiles,
-                                                         const int32_t *__restrict__ off,
-                                                         uint64_t *__restrict__ kout,
-                                                         int32_t *__restrict__ vout)
+// One pass: tile items are ranked within the tile in (round, thread) order, which is
+// index order; the tile's base for digit d is the global start of d plus the count of d
+// in all earlier tiles (look-back over status[tile][256]).
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__restrict__ kin,
+                                                          const int32_t *__restrict__ vin, int64_t n, int shift,
+                                                          int64_t ntiles, const int32_t *__restrict__ ghist,
+                                                          uint64_t *__restrict__ status, uint32_t epoch,
+                                                          unsigned long long *ticket, uint64_t *__restrict__ kout,
+                                                          int32_t *__restrict__ vout)
 {
-    __shared__ int32_t run[256];
-    __shared__ int32_t wc[RS_BLOCK / GSS_WAVE][256];
-    const int wid = threadIdx.x / GSS_WAVE;
-    run[threadIdx.x] = off[(int64_t)threadIdx.x * ntiles + blockIdx.x];
-    for (int w = 0; w < RS_BLOCK / GSS_WAVE; w++) wc[w][threadIdx.x] = 0;
+    constexpr int NW = RS_BLOCK / GSS_WAVE;
+    __shared__ int32_t s_run[256];
+    __shared__ int32_t s_wc[NW][256];
+    __shared__ int32_t s_base[256];
+    __shared__ int32_t s_scan[NW + 1];
+    __shared__ int64_t s_tile;
+    const int t = threadIdx.x, wid = t / GSS_WAVE;
+    if (t == 0) s_tile = lb_ticket(ticket, ntiles);
+    int32_t gtot;
+    const int32_t gstart = block_exclusive_scan<int32_t>(ghist[t], s_scan, &gtot);  // synchronises
+    s_run[t] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) s_wc[w][t] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile = s_tile;
+    const int64_t base = tile * RS_TILE;
+    uint64_t kk[RS_ITEMS];
+    int32_t vv[RS_ITEMS], pos[RS_ITEMS];
+#pragma unroll
     for (int i = 0; i < RS_ITEMS; i++) {
-        int64_t idx = base + (int64_t)i * RS_BLOCK + threadIdx.x;
-        bool valid = idx < n;
-        uint64_t kk = valid ? kin[idx] : 0;
-        int32_t vv = valid ? vin[idx] : 0;
-        uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const int64_t idx = base + (int64_t)i * RS_BLOCK + t;
+        const bool valid = idx < n;
+        kk[i] = valid ? kin[idx] : 0;
+        vv[i] = valid ? vin[idx] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const bool valid = base + (int64_t)i * RS_BLOCK + t < n;
+        const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            uint64_t bb = __ballot((d >> b) & 1u);
+            const uint64_t bb = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        int rank = __popcll(peers & lanemask_lt());
-        if (valid && rank == 0) wc[wid][d] = __popcll(peers);
+        const int rank = __popcll(peers & lanemask_lt());
+        if (valid && rank == 0) s_wc[wid][d] = __popcll(peers);
         __syncthreads();
+        int32_t o = s_run[d] + rank;
+        for (int w = 0; w < wid; w++) o += s_wc[w][d];
+        pos[i] = o;
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            add += s_wc[w][t];
+            s_wc[w][t] = 0;
+        }
+        s_run[t] += add;
+        __syncthreads();
+    }
+    // thread t publishes and resolves digit t
+    const int32_t cnt = s_run[t];
+    int64_t excl = 0;
+    if (tile == 0) {
+        lb_store(status + t, lb_word(LB_INC, epoch, (uint64_t)cnt));
+    } else {
+        lb_store(status + tile * 256 + t, lb_word(LB_AGG, epoch, (uint64_t)cnt));
+        excl = lb_lookback_thread<16>(status, 256, t, tile, epoch);
+        lb_store(status + tile * 256 + t, lb_word(LB_INC, epoch, (uint64_t)(excl + cnt)));
+    }
+    s_base[t] = gstart + (int32_t)excl;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+        const bool valid = base + (int64_t)i * RS_BLOCK + t < n;
         if (valid) {
-            int32_t o = run[d] + rank;
-            for (int w = 0; w < wid; w++) o += wc[w][d];
-            kout[o] = kk;
-            vout[o] = vv;
+            const int32_t o = s_base[(uint32_t)(kk[i] >> shift) & 255u] + pos[i];
+            kout[o] = kk[i];
+            vout[o] = vv[i];
         }
-        __syncthreads();
-        {
-            int32_t s = 0;
-            for (int w = 0; w < RS_BLOCK / GSS_WAVE; w++) {
-                s += wc[w][threadIdx.x];
-                wc[w][threadIdx.x] = 0;
-            }
-            run[threadIdx.x] += s;
-        }
-        __syncthreads();
     }
 }
 
@@ -543,16 +567,17 @@ __device__ __forceinline__ void join_insert(Slot *tab, uint64_t cap_mask, int32_
     }
 }
 
-// one thread per (edge, orientation, i, k): insert (anc_i(x), anc_k(y)) -> (rank, i, k)
-__global__ void k_join_build(int64_t P, int32_t c, const int32_t *__restrict__ ancU,
-                             const int32_t *__restrict__ ancV, const uint8_t *__restrict__ is_global, Slot *tab,
+// one thread per (listed edge, orientation, i, k): insert (anc_i(x), anc_k(y)) -> (rank, i, k)
+__global__ void k_join_build(int64_t NG, const int32_t *__restrict__ glist, int64_t P, int32_t c,
+                             const int32_t *__restrict__ ancU, const int32_t *__restrict__ ancV, Slot *tab,
                              uint64_t cap_mask)
 {
     const int per = 2 * (c + 1) * (c + 1);
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t p = tid / per;
-    if (p >= P || !is_global[p]) return;
-    int r = (int)(tid - p * per);
+    int64_t gi = tid / per;
+    if (gi >= NG) return;
+    const int32_t p = glist[gi];
+    int r = (int)(tid - gi * per);
     const int orient = r / ((c + 1) * (c + 1));
     r -= orient * (c + 1) * (c + 1);
     const int i = r / (c + 1), k = r % (c + 1);
@@ -561,28 +586,30 @@ __global__ void k_join_build(int64_t P, int32_t c, const int32_t *__restrict__ a
     int32_t A = X[(int64_t)i * P + p];
     int32_t B = Y[(int64_t)k * P + p];
     if (A < 0 || B < 0) return;
-    join_insert(tab, cap_mask, A, B, (int32_t)p, (i << 8) | k);
+    join_insert(tab, cap_mask, A, B, p, (i << 8) | k);
 }
 
-// one thread per (marker edge, j, l): probe (anc_j(u), anc_l(v)) and keep entries with
-// i <= beta*-j and k <= beta*-l of a later rank.  The probe loop is wave-uniform so that
-// the arcs found in one step are appended with one atomic per wavefront.
-__global__ void k_join_probe(int64_t P, int32_t c, const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
-                             const int32_t *__restrict__ ancV, const uint8_t *__restrict__ is_global,
-                             const Slot *__restrict__ tab, uint64_t cap_mask, int2 *__restrict__ arcs,
-                             int64_t arc_cap, unsigned long long *arc_count, int32_t *__restrict__ indeg,
-                             uint32_t *flags)
+// one thread per (listed marker edge, j, l): probe (anc_j(u), anc_l(v)) and keep entries
+// with i <= beta*-j and k <= beta*-l of a later rank.  The probe loop is wave-uniform so
+// that the arcs found in one step are appended with one atomic per wavefront.
+__global__ void k_join_probe(int64_t NG, const int32_t *__restrict__ glist, int64_t P, int32_t c,
+                             const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
+                             const int32_t *__restrict__ ancV, const Slot *__restrict__ tab, uint64_t cap_mask,
+                             int2 *__restrict__ arcs, int64_t arc_cap, unsigned long long *arc_count,
+                             int32_t *__restrict__ indeg, uint32_t *flags)
 {
     const int per = (c + 1) * (c + 1);
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t p = tid / per;
-    bool active = p < P && is_global[p];
+    int64_t gi = tid / per;
+    bool active = gi < NG;
+    int32_t p = 0;
     int beta = 0, j = 0, l = 0;
     unsigned long long ab = 0;
     uint64_t h = 0;
     if (active) {
+        p = glist[gi];
         beta = rb[p];
-        const int r = (int)(tid - p * per);
+        const int r = (int)(tid - gi * per);
         j = r / (c + 1);
         l = r % (c + 1);
         active = beta > 0 && j <= beta && l <= beta;  // beta* = 0: only the edge itself is similar
@@ -619,7 +646,7 @@ __global__ void k_join_probe(int64_t P, int32_t c, const uint8_t *__restrict__ r
             if (hit) {
                 unsigned long long a = base + __popcll(m & lanemask_lt());
                 if ((int64_t)a < arc_cap) {
-                    arcs[a] = make_int2((int32_t)p, t);
+                    arcs[a] = make_int2(p, t);
                     atomicAdd(&indeg[t], 1);
                 } else {
                     atomicOr(flags, F_OVERFLOW);
@@ -629,14 +656,14 @@ __global__ void k_join_probe(int64_t P, int32_t c, const uint8_t *__restrict__ r
     }
 }
 
-// ------------------------------------------------------------------------------------
-// 5. dependency rounds (one workgroup)
-// ------------------------------------------------------------------------------------
-__global__ void k_state_init(int64_t P, const int32_t *__restrict__ indeg, const uint8_t *__restrict__ is_global,
+__global__ void k_state_init(int64_t NG, const int32_t *__restrict__ glist, const int32_t *__restrict__ indeg,
                              uint8_t *__restrict__ state)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < P && is_global[p]) state[p] = indeg[p] == 0 ? ST_CAND : ST_UNDEC;
+    int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi < NG) {
+        const int32_t p = glist[gi];
+        state[p] = indeg[p] == 0 ? ST_CAND : ST_UNDEC;
+    }
 }
 
 // Every edge without in-arcs is recovered (k_state_init), so every target of such an edge
@@ -870,27 +897,32 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
 {
     if (n <= 1) return;
     hipStream_t st = ctx->stream;
-    GSS_LAUNCH(k_key_varying, dim3(1), dim3(1024), 0, st, k, n, (uint64_t *)ctx->d_counters);
-    read_counters(ctx, 1);
-    uint64_t varying = (uint64_t)ctx->h_counters[0];
-    int32_t ntiles = (int32_t)((n + RS_TILE - 1) / RS_TILE);
-    int64_t cn = (int64_t)ntiles * 256;
-    int32_t *cnt = ctx->alloc<int32_t>(cn + 1);
-    for (int shift = 0; shift < 64; shift += 8) {
-        if (((varying >> shift) & 255ull) == 0) continue;
-        GSS_LAUNCH(k_rs_hist, dim3(ntiles), dim3(RS_BLOCK), 0, st, k, n, shift, ntiles, cnt);
-        scan_exclusive_i32(ctx, cnt, cn, false);
-        GSS_LAUNCH(k_rs_scatter, dim3(ntiles), dim3(RS_BLOCK), 0, st, k, v, n, shift, ntiles, cnt, k2,
-                           v2);
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    int32_t *ghist = ctx->alloc<int32_t>(8 * 256);
+    HIP_OK(hipMemsetAsync(ghist, 0, sizeof(int32_t) * 8 * 256, st));
+    GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n,
+                 ghist);
+    std::vector<int32_t> h(8 * 256);
+    HIP_OK(hipMemcpyAsync(h.data(), ghist, sizeof(int32_t) * 8 * 256, hipMemcpyDeviceToHost, st));
+    ctx->sync();
+    for (int p = 0; p < 8; p++) {
+        // a byte position is constant when one digit holds every key
+        bool constant = false;
+        for (int d = 0; d < 256; d++) constant |= (h[p * 256 + d] == n);
+        if (constant) continue;
+        uint32_t epoch = 0;
+        uint64_t *status = lb_begin(ctx, ntiles * 256, &epoch);
+        GSS_LAUNCH_B(24 * n, k_rs_onesweep, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, k, v, n, 8 * p, ntiles,
+                   ghist + p * 256, status, epoch, lb_ticket_ptr(ctx), k2, v2);
         HIP_OK(hipGetLastError());
         std::swap(k, k2);
         std::swap(v, v2);
     }
-    ctx->free(cnt);
+    ctx->free(ghist);
 }
 
 struct PrefixResult {
-    int64_t P = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0;
+    int64_t P = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0, njoin = 0;
     std::vector<int64_t> Pg, cand;  // per graph
 };
 
@@ -899,11 +931,12 @@ struct PrefixBufs {
     int32_t *ru = nullptr, *rv = nullptr, *rdu = nullptr, *rdv = nullptr, *rl = nullptr, *rg = nullptr;
     int32_t *grp = nullptr, *sub_ptr = nullptr, *sub_lca = nullptr, *candq = nullptr;
     int64_t *pstart = nullptr;
-    uint8_t *rb = nullptr, *state = nullptr, *is_global = nullptr;
+    uint8_t *rb = nullptr, *state = nullptr;
+    int32_t *glist = nullptr;
     void release(gss_ctx ctx)
     {
         void *ps[] = {sj, rid, ancU,    ancV,    indeg, mcnt,  ru,        rv,    rdu,   rdv,
-                      rl, rg,  grp,     sub_ptr, sub_lca, candq, pstart, rb,    state, is_global};
+                      rl, rg,  grp,     sub_ptr, sub_lca, candq, pstart, rb,    state, glist};
         for (void *p : ps) ctx->free(p);
         *this = PrefixBufs();
     }
@@ -932,7 +965,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
     unsigned long long *gcount = ctx->alloc<unsigned long long>(G);
     HIP_OK(hipMemsetAsync(gcount, 0, sizeof(unsigned long long) * G, st));
-    GSS_LAUNCH(k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, gcount);
+    GSS_LAUNCH_B(8 * M, k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, gcount);
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
     res.Pg.assign(G, 0);
@@ -944,7 +977,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     }
     uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
-    GSS_LAUNCH(k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, v1, k1);
+    GSS_LAUNCH_B(8 * M + 12 * P, k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, v1,
+                 k1);
     ctx->free(pc);
     ctx->free(gcount);
     radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
@@ -973,7 +1007,10 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     B.ancV = ctx->alloc<int32_t>((int64_t)(c + 1) * P + 1);
     uint64_t *lkey = k1, *lkey2 = k2;
     int32_t *lval = v2, *lval2 = ctx->alloc<int32_t>(P + 1);
-    GSS_LAUNCH(k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_id, t->off_u, t->off_v, bst,
+    // per prefix edge: id, endpoints, beta*, LCA and 2(c+1) ancestors read; the rank
+    // record, the (LCA, rank) pair and the ancestor columns written
+    GSS_LAUNCH_B((58 + 16 * (int64_t)(c + 1)) * P, k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj,
+                 t->off_id, t->off_u, t->off_v, bst,
                lca, t->vrec, c, B.rid, B.rb, B.ru, B.rv, B.rdu, B.rdv, B.rl, lkey, lval, B.ancU, B.ancV);
 
     // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA.  LCAs
@@ -1011,7 +1048,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     uint64_t *qk = ctx->alloc<uint64_t>(nsub + 1), *qk2 = ctx->alloc<uint64_t>(nsub + 1);
     int32_t *qv = ctx->alloc<int32_t>(nsub + 1), *qv2 = ctx->alloc<int32_t>(nsub + 1);
     int32_t *is_local = ctx->alloc<int32_t>(nsub + 1);
-    HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, 3 * sizeof(int64_t), st));
+    HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(int64_t), st));
     launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, qk, qv, is_local,
                         (int32_t *)(ctx->d_counters + 4), (unsigned long long *)(ctx->d_counters + 6));
     radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub);
@@ -1019,6 +1056,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     const int32_t nlocal = (int32_t)ctx->h_counters[4];
     const int64_t nglobal_edges = ctx->h_counters[6];
     res.nlocal = nlocal;
+    res.njoin = nglobal_edges;
     scratch.push_back(qk);
     scratch.push_back(qk2);
     scratch.push_back(qv);
@@ -1026,9 +1064,10 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     scratch.push_back(is_local);
 
     B.state = ctx->alloc<uint8_t>(P + 1);
-    B.is_global = ctx->alloc<uint8_t>(P + 1);
-    HIP_OK(hipMemsetAsync(B.is_global, 0, P + 1, st));
-    if (nsub > nlocal) launch_mark_global(ctx, (int32_t)nsub, B.sub_ptr, is_local, B.grp, B.is_global);
+    // ranks of the edges on the join path (the global subtasks sit at the tail of the queue)
+    B.glist = ctx->alloc<int32_t>(nglobal_edges + 1);
+    launch_global_list(ctx, (int32_t)(nsub - nlocal), qv + nlocal, B.sub_ptr, B.grp,
+                       (unsigned long long *)(ctx->d_counters + 7), B.glist);
 
     // Step 4, small and medium subtasks: persistent work-queue kernel
     uint64_t *cycles = nullptr;
@@ -1061,6 +1100,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         void *scr = ctx->alloc<uint8_t>((size_t)blocks * 4 * per_wave + 64);
         scratch.push_back(scr);
         a.cand_scratch = scr;
+        // per queued edge: rank, 2(c+1) ancestors, depths and beta* read, state written;
+        // per subtask: queue entry and bounds
+        if (ctx->prof) ctx->prof_bytes = (P - nglobal_edges) * (14 + 8 * (int64_t)(c + 1)) + 12 * (int64_t)nlocal;
         launch_local_recover(ctx, c, a, blocks);
     }
     // Step 4, large subtasks: hash join + dependency rounds over their edges
@@ -1072,16 +1114,20 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         while (cap < 2 * (uint64_t)entries) cap <<= 1;
         Slot *tab = ctx->alloc<Slot>(cap);
         HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(Slot) * cap, st));
-        GSS_LAUNCH(k_join_build, dim3(grid_for(P * 2 * (c + 1) * (c + 1), RB)), dim3(RB), 0, st, P, c, B.ancU, B.ancV,
-                   B.is_global, tab, cap - 1);
+        // per listed edge: its rank, 2(c+1) ancestors, 2(c+1)^2 slots of 16 B written
+        GSS_LAUNCH_B(nglobal_edges * (4 + 8 * (c + 1) + 32 * (c + 1) * (c + 1)), k_join_build,
+                     dim3(grid_for(nglobal_edges * 2 * (c + 1) * (c + 1), RB)), dim3(RB), 0, st,
+                   nglobal_edges, B.glist, P, c, B.ancU, B.ancV, tab, cap - 1);
         int64_t arc_cap = std::max<int64_t>(4 * P, 1 << 16);
         for (;;) {
             int2 *arcs = ctx->alloc<int2>(arc_cap);
             HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
             HIP_OK(hipMemsetAsync(ctx->d_counters, 0, sizeof(int64_t) * 2, st));
-            GSS_LAUNCH(k_join_probe, dim3(grid_for(P * (c + 1) * (c + 1), RB)), dim3(RB), 0, st, P, c, B.rb, B.ancU,
-                       B.ancV, B.is_global, tab, cap - 1, arcs, arc_cap, (unsigned long long *)ctx->d_counters, B.indeg,
-                       ctx->d_flags);
+            // per listed edge: rank, beta*, 2(c+1) ancestors, (c+1)^2 slots of 16 B read
+            GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1) + 16 * (c + 1) * (c + 1)), k_join_probe,
+                         dim3(grid_for(nglobal_edges * (c + 1) * (c + 1), RB)), dim3(RB), 0, st,
+                       nglobal_edges, B.glist, P, c, B.rb, B.ancU, B.ancV, tab, cap - 1, arcs, arc_cap,
+                       (unsigned long long *)ctx->d_counters, B.indeg, ctx->d_flags);
             read_counters(ctx, 1);
             int64_t A = ctx->h_counters[0];
             if (A > arc_cap) {
@@ -1091,7 +1137,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             }
             res.arcs = A;
             HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
-            GSS_LAUNCH(k_state_init, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.indeg, B.is_global, B.state);
+            GSS_LAUNCH(k_state_init, dim3(grid_for(nglobal_edges, RB)), dim3(RB), 0, st, nglobal_edges, B.glist,
+                       B.indeg, B.state);
             if (A > 0) {
                 int2 *arcs2 = ctx->alloc<int2>(A + 1);
                 HIP_OK(hipMemsetAsync(ctx->d_counters + 2, 0, sizeof(int64_t), st));
@@ -1231,8 +1278,12 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     int32_t *lcacnt = need_lca_counts ? ctx->alloc<int32_t>(n) : nullptr;
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (lcacnt) HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
+    // per off-tree edge: u, v, w (16 B); first, depth and D of u and v and D of the LCA
+    // (56 B); the two Euler entries that answer the range minimum (16 B); key, LCA and
+    // beta* written (13 B); optional stretch (8 B)
     if (M > 0)
-        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB * EDGE_ITEMS)), dim3(RB), 0, st, M, t->off_id, t->off_u,
+        GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch, dim3(grid_for(M, RB * EDGE_ITEMS)), dim3(RB), 0,
+                     st, M, t->off_id, t->off_u,
                    t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst, stretch,
                    G == 1 ? hist : (uint32_t *)nullptr, lcacnt, ctx->d_flags);
     HIP_OK(hipGetLastError());
@@ -1283,7 +1334,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         any_active |= active[g];
     }
     bool hist_ready = (G == 1);
-    int64_t arcs = 0, rounds = 0;
+    int64_t arcs = 0, rounds = 0, njoin = 0;
     GraphOut *dgo = ctx->alloc<GraphOut>(G);
     std::vector<GraphOut> go(G);
     while (any_active) {
@@ -1296,6 +1347,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         ctx->free(dthr);
         arcs = r.arcs;
         rounds = r.rounds;
+        njoin = r.njoin;
         int64_t pst = 0;
         bool write = false;
         for (int32_t g = 0; g < G; g++) {
@@ -1362,6 +1414,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         info.largest_subtask = largest[g];
         info.prefix_len = lastP[g];
         info.n_arcs = arcs;
+        info.n_join = njoin;
         info.passes = passes[g];
         info.rounds = (int32_t)rounds;
     }

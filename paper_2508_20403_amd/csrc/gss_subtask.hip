@@ -225,12 +225,18 @@ __global__ void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr
 }
 
 // global-path flag per rank (edges of subtasks above the local limit)
-__global__ void k_mark_global(int32_t nsub, const int32_t *__restrict__ sub_ptr, const int32_t *__restrict__ is_local,
-                              const int32_t *__restrict__ grp, uint8_t *__restrict__ is_global)
+// lists the ranks of the edges in subtasks on the join path (order within the list is
+// immaterial); one workgroup per such subtask, taken from the tail of the sorted queue
+__global__ void k_global_list(const int32_t *__restrict__ gsub, const int32_t *__restrict__ sub_ptr,
+                              const int32_t *__restrict__ grp, unsigned long long *__restrict__ count,
+                              int32_t *__restrict__ glist)
 {
-    int32_t s = blockIdx.x;
-    if (s >= nsub || is_local[s]) return;
-    for (int32_t g = sub_ptr[s] + threadIdx.x; g < sub_ptr[s + 1]; g += blockDim.x) is_global[grp[g]] = 1;
+    __shared__ unsigned long long base;
+    const int32_t s = gsub[blockIdx.x];
+    const int32_t g0 = sub_ptr[s], g1 = sub_ptr[s + 1];
+    if (threadIdx.x == 0) base = atomicAdd(count, (unsigned long long)(g1 - g0));
+    __syncthreads();
+    for (int32_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) glist[base + (g - g0)] = grp[g];
 }
 
 // 12 features per subtask for the cost model (one wave per subtask)
@@ -310,10 +316,11 @@ void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int3
                qkey, qval, is_local, nlocal, nglobal_edges);
 }
 
-void launch_mark_global(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *is_local,
-                        const int32_t *grp, uint8_t *is_global)
+void launch_global_list(gss_ctx ctx, int32_t nglob_sub, const int32_t *gsub, const int32_t *sub_ptr,
+                        const int32_t *grp, unsigned long long *count, int32_t *glist)
 {
-    GSS_LAUNCH(k_mark_global, dim3(nsub), dim3(256), 0, ctx->stream, nsub, sub_ptr, is_local, grp, is_global);
+    if (nglob_sub <= 0) return;
+    GSS_LAUNCH(k_global_list, dim3(nglob_sub), dim3(256), 0, ctx->stream, gsub, sub_ptr, grp, count, glist);
 }
 
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,

@@ -58,7 +58,8 @@ class Info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n_offtree", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("n_recovered", ctypes.c_int64), ("n_subtasks", ctypes.c_int64),
                 ("largest_subtask", ctypes.c_int64), ("prefix_len", ctypes.c_int64),
-                ("n_arcs", ctypes.c_int64), ("passes", ctypes.c_int32), ("rounds", ctypes.c_int32)]
+                ("n_arcs", ctypes.c_int64), ("n_join", ctypes.c_int64), ("passes", ctypes.c_int32),
+                ("rounds", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -93,7 +94,8 @@ def load_library(path=LIB_PATH):
     lib.gss_ctx_profile.argtypes = [P, ctypes.c_int32, ctypes.c_char_p]
     lib.gss_ctx_profile.restype = ctypes.c_int32
     lib.gss_ctx_profile_read.argtypes = [P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
-                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]
     lib.gss_ctx_profile_read.restype = ctypes.c_int32
     lib.gss_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.gss_trace_read.argtypes = [P, P, P, P, ctypes.c_int64]
@@ -157,15 +159,17 @@ class Context:
                                             kernel.encode() if kernel else None))
 
     def profile_read(self):
-        """{kernel name: (total ms, launches)} accumulated since profile()."""
+        """{kernel name: (total ms, launches, algorithmic bytes)} accumulated since profile()."""
         out = {}
-        count = self.lib.gss_ctx_profile_read(self.handle, 0, None, 0, None, None)
+        count = self.lib.gss_ctx_profile_read(self.handle, 0, None, 0, None, None, None)
         buf = ctypes.create_string_buffer(128)
         ms = ctypes.c_double()
         n = ctypes.c_int64()
+        nb = ctypes.c_int64()
         for i in range(max(count, 0)):
-            self.lib.gss_ctx_profile_read(self.handle, i, buf, 128, ctypes.byref(ms), ctypes.byref(n))
-            out[buf.value.decode()] = (ms.value, n.value)
+            self.lib.gss_ctx_profile_read(self.handle, i, buf, 128, ctypes.byref(ms), ctypes.byref(n),
+                                          ctypes.byref(nb))
+            out[buf.value.decode()] = (ms.value, n.value, nb.value)
         return out
 
     # ---- subtask scheduling and the learned cost model --------------------------------
