@@ -14,11 +14,13 @@
 #include <algorithm>
 
 #include "gss_impl.h"
+#include "gss_lookback.h"
 
 #define PB 256          // default block size
 #define ENT_ITEMS 16    // CSR entries per thread in entry-parallel kernels
 #define RULE_RATE 4     // one ruler per ~4 list elements (power of two)
-#define BASE_MAX 1024   // lists this short are ranked by one workgroup
+#define BASE_MAX 4096   // lists this short are ranked by one workgroup
+#define BASE_THREADS 1024
 
 // ------------------------------------------------------------------------------------
 // small device helpers
@@ -442,40 +444,110 @@ __device__ __forceinline__ LVal level_val(const LVal *__restrict__ val, const u1
     return val ? val[i] : arc_val(i, T);
 }
 
-// rid[i] = 1 for rulers (0 past N and for elements outside the list); owner[i] = -1
-__global__ void k_ruler_flags(int64_t cap, const int64_t *__restrict__ Np, const int32_t *__restrict__ nxt,
-                              const int32_t *__restrict__ headp, int32_t level, int32_t *__restrict__ rid,
-                              int32_t *__restrict__ owner)
+// Ruler selection and numbering in one pass (a stream compaction with decoupled
+// look-back): rid[i] = number of rulers before i (written for rulers only), relem[rid] =
+// i, the level length R_{l+1} and head; owner[i] = -1 for every element.  Thread t of
+// round r owns the four consecutive elements at tile offset 4 (r*256 + t).
+#define RC_BLOCK 256
+#define RC_ROUNDS 4
+#define RC_TILE (RC_BLOCK * 4 * RC_ROUNDS)
+__global__ __launch_bounds__(RC_BLOCK) void k_ruler_compact(int64_t cap, int64_t ntiles, const int64_t *__restrict__ Np,
+                                                           const int32_t *__restrict__ nxt,
+                                                           const int32_t *__restrict__ headp, int32_t level,
+                                                           int32_t *__restrict__ rid, int32_t *__restrict__ owner,
+                                                           int32_t *__restrict__ relem, int64_t cap_next,
+                                                           int32_t *__restrict__ head_next, int64_t *__restrict__ R_out,
+                                                           uint64_t *__restrict__ status, uint32_t epoch,
+                                                           unsigned long long *ticket, uint32_t *flags)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cap) return;
-    const int64_t N = *Np;
+    constexpr int NW = RC_BLOCK / GSS_WAVE;
+    __shared__ int32_t s_wsum[RC_ROUNDS][NW];
+    __shared__ int64_t s_tile, s_excl;
+    const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
+    if (threadIdx.x == 0) s_tile = lb_ticket(ticket, ntiles);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t Nr = *Np;
+    const int64_t N = Nr < cap ? Nr : cap;  // a longer list has already raised F_OVERFLOW
     const int32_t head = *headp;
-    int32_t f = 0;
-    if (i < N) {
-        f = (nxt[i] != -2 && is_ruler((int32_t)i, head, level)) ? 1 : 0;
-        owner[i] = -1;
+    const int64_t base = tile * RC_TILE;
+    uint32_t fl[RC_ROUNDS];
+    int32_t incl[RC_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RC_ROUNDS; r++) {
+        const int64_t e = base + ((int64_t)r * RC_BLOCK + threadIdx.x) * 4;
+        int nx[4];
+        if (e + 4 <= N) {
+            const int4 v = *(const int4 *)(nxt + e);
+            nx[0] = v.x;
+            nx[1] = v.y;
+            nx[2] = v.z;
+            nx[3] = v.w;
+            *(int4 *)(owner + e) = make_int4(-1, -1, -1, -1);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                nx[q] = (e + q < N) ? nxt[e + q] : -2;
+                if (e + q < N) owner[e + q] = -1;
+            }
+        }
+        uint32_t f = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (nx[q] != -2 && is_ruler((int32_t)(e + q), head, level)) f |= 1u << q;
+        fl[r] = f;
+        int32_t x = __popc(f);
+#pragma unroll
+        for (int d = 1; d < GSS_WAVE; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, GSS_WAVE);
+            if (lane >= d) x += y;
+        }
+        incl[r] = x;
+        if (lane == GSS_WAVE - 1) s_wsum[r][wid] = x;
     }
-    rid[i] = f;
-}
-
-// relem[rid[i]] = i for rulers; the head's ruler id becomes the next level's head
-__global__ void k_ruler_list(int64_t cap, const int64_t *__restrict__ Np, const int32_t *__restrict__ nxt,
-                             const int32_t *__restrict__ headp, int32_t level, const int32_t *__restrict__ rid,
-                             int32_t *__restrict__ relem, int64_t cap_next, int32_t *__restrict__ head_next,
-                             uint32_t *flags)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cap || i >= *Np) return;
-    const int32_t head = *headp;
-    if (nxt[i] == -2 || !is_ruler((int32_t)i, head, level)) return;
-    const int32_t r = rid[i];
-    if (r >= cap_next) {
-        atomicOr(flags, F_OVERFLOW);
-        return;
+    __syncthreads();
+    int64_t off[RC_ROUNDS];
+    int64_t run = 0;
+#pragma unroll
+    for (int r = 0; r < RC_ROUNDS; r++) {
+        for (int w = 0; w < NW; w++) {
+            if (w == wid) off[r] = run;
+            run += s_wsum[r][w];
+        }
     }
-    relem[r] = (int32_t)i;
-    if (i == head) *head_next = r;
+    const int64_t tile_total = run;
+    if (wid == 0) {
+        int64_t excl = 0;
+        if (tile == 0) {
+            if (lane == 0) lb_store(status, lb_word(LB_INC, epoch, (uint64_t)tile_total));
+        } else {
+            if (lane == 0) lb_store(status + tile, lb_word(LB_AGG, epoch, (uint64_t)tile_total));
+            excl = lb_lookback_wave(status, 1, tile, epoch);
+            if (lane == 0) lb_store(status + tile, lb_word(LB_INC, epoch, (uint64_t)(excl + tile_total)));
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            if (tile == ntiles - 1) *R_out = excl + tile_total;
+        }
+    }
+    __syncthreads();
+    const int64_t excl = s_excl;
+#pragma unroll
+    for (int r = 0; r < RC_ROUNDS; r++) {
+        const int64_t e = base + ((int64_t)r * RC_BLOCK + threadIdx.x) * 4;
+        int64_t p = excl + off[r] + incl[r] - __popc(fl[r]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if ((fl[r] >> q) & 1u) {
+                const int64_t i = e + q;
+                rid[i] = (int32_t)p;
+                if (p < cap_next) relem[p] = (int32_t)i;
+                else atomicOr(flags, F_OVERFLOW);
+                if (i == head) *head_next = (int32_t)p;
+                p++;
+            }
+        }
+    }
 }
 
 // walk: one thread per ruler r < R_{l+1}
@@ -507,18 +579,20 @@ __global__ void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp, const 
         i = j;
     }
     int32_t nr = (j < 0) ? GSS_END : rid[j];
-    if (nr >= cap_next) nr = GSS_END;  // overflow, already flagged by k_ruler_list
+    if (nr >= cap_next) nr = GSS_END;  // overflow, already flagged by k_ruler_compact
     rnxt[r] = nr;
     rval[r] = acc;
 }
 
-// base case: Wyllie pointer jumping in LDS, exclusive prefix from the head
-__global__ __launch_bounds__(BASE_MAX) void k_rank_base(const int64_t *__restrict__ Np,
-                                                        const int32_t *__restrict__ nxt,
-                                                        const LVal *__restrict__ val,
-                                                        const int32_t *__restrict__ headp, int64_t expect,
-                                                        LVal *__restrict__ pre, uint32_t *flags)
+// base case: Wyllie pointer jumping in LDS, exclusive prefix from the head; every thread
+// owns BASE_MAX / BASE_THREADS elements
+__global__ __launch_bounds__(BASE_THREADS) void k_rank_base(const int64_t *__restrict__ Np,
+                                                            const int32_t *__restrict__ nxt,
+                                                            const LVal *__restrict__ val,
+                                                            const int32_t *__restrict__ headp, int64_t expect,
+                                                            LVal *__restrict__ pre, uint32_t *flags)
 {
+    constexpr int PER = BASE_MAX / BASE_THREADS;
     __shared__ int32_t snx[BASE_MAX];
     __shared__ LVal ssuf[BASE_MAX];
     const int64_t N64 = *Np;
@@ -528,8 +602,7 @@ __global__ __launch_bounds__(BASE_MAX) void k_rank_base(const int64_t *__restric
     }
     const int32_t N = (int32_t)N64;
     const int32_t head = *headp;
-    int32_t i = threadIdx.x;
-    if (i < N) {
+    for (int32_t i = threadIdx.x; i < N; i += BASE_THREADS) {
         snx[i] = nxt[i];
         ssuf[i] = val[i];
     }
@@ -538,30 +611,44 @@ __global__ __launch_bounds__(BASE_MAX) void k_rank_base(const int64_t *__restric
     while ((1 << rounds) < N + 1) rounds++;
     rounds += 1;
     for (int r = 0; r < rounds; r++) {
-        int32_t nx = -1;
-        LVal add = lv_zero();
-        bool upd = false;
-        if (i < N) {
-            nx = snx[i];
-            if (nx >= 0) {
-                add = ssuf[nx];
-                upd = true;
-                nx = snx[nx];
+        int32_t nxv[PER];
+        LVal add[PER];
+        bool upd[PER];
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int32_t i = threadIdx.x + k * BASE_THREADS;
+            nxv[k] = -1;
+            add[k] = lv_zero();
+            upd[k] = false;
+            if (i < N) {
+                int32_t nx = snx[i];
+                if (nx >= 0) {
+                    add[k] = ssuf[nx];
+                    upd[k] = true;
+                    nx = snx[nx];
+                }
+                nxv[k] = nx;
             }
         }
         __syncthreads();
-        if (upd) {
-            ssuf[i] = lv_add(ssuf[i], add);
-            snx[i] = nx;
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int32_t i = threadIdx.x + k * BASE_THREADS;
+            if (upd[k]) {
+                ssuf[i] = lv_add(ssuf[i], add[k]);
+                snx[i] = nxv[k];
+            }
         }
         __syncthreads();
     }
-    if (i < N && snx[i] >= 0) atomicOr(flags, F_NOT_TREE);
+    for (int32_t i = threadIdx.x; i < N; i += BASE_THREADS)
+        if (snx[i] >= 0) atomicOr(flags, F_NOT_TREE);
     // the tour from the head must hold every arc: fewer means some vertices never reach
     // the root through their parents (a cycle)
-    if (i == 0 && (head < 0 || head >= N || ssuf[head].cnt != expect)) atomicOr(flags, F_NOT_TREE);
+    if (threadIdx.x == 0 && (head < 0 || head >= N || ssuf[head].cnt != expect)) atomicOr(flags, F_NOT_TREE);
     __syncthreads();
-    if (i < N && head >= 0 && head < N) pre[i] = lv_sub(ssuf[head], ssuf[i]);
+    if (head >= 0 && head < N)
+        for (int32_t i = threadIdx.x; i < N; i += BASE_THREADS) pre[i] = lv_sub(ssuf[head], ssuf[i]);
 }
 
 // downward pass, levels >= 1: pre[i] = rpre[owner[i]] + loc[i]
@@ -664,11 +751,13 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
         LVal *rval = ctx->alloc<LVal>(cap2 + 1);
         for (void *p : {(void *)rid, (void *)a.owner, (void *)a.loc, (void *)relem, (void *)rnxt, (void *)rval})
             bufs.push_back(p);
-        GSS_LAUNCH_B(8 * cap, k_ruler_flags, dim3(grid_for(cap, PB)), dim3(PB), 0, st, cap, a.Np, a.nxt, a.headp, l,
-                     rid, a.owner);
-        scan_exclusive_i32_dev(ctx, rid, cap, d_len + l + 1);
-        GSS_LAUNCH_B(4 * cap + 8 * cap2 / 1, k_ruler_list, dim3(grid_for(cap, PB)), dim3(PB), 0, st, cap, a.Np, a.nxt,
-                     a.headp, l, rid, relem, cap2, d_heads + l + 1, ctx->d_flags);
+        const int64_t ntiles = (cap + RC_TILE - 1) / RC_TILE;
+        uint32_t epoch = 0;
+        uint64_t *status = lb_begin(ctx, ntiles, &epoch);
+        // successor read and owner cleared per element; rid and relem written per ruler
+        GSS_LAUNCH_B(8 * cap + 8 * cap2, k_ruler_compact, dim3((unsigned)ntiles), dim3(RC_BLOCK), 0, st, cap, ntiles,
+                     a.Np, a.nxt, a.headp, l, rid, a.owner, relem, cap2, d_heads + l + 1, d_len + l + 1, status, epoch,
+                     lb_ticket_ptr(ctx), ctx->d_flags);
         // one walk over every element: successor and value read, owner and local prefix
         // written; one record per ruler
         GSS_LAUNCH_B((l == 0 ? 24 : 32) * cap + 28 * cap + 36 * cap2, k_walk1, dim3(grid_for(cap2, PB)), dim3(PB), 0,
@@ -680,7 +769,7 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
     Lv &b = lv.back();
     b.pre = ctx->alloc<LVal>(b.cap + 1);
     bufs.push_back(b.pre);
-    GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_MAX), 0, st, b.Np, b.nxt, b.val, b.headp, N0 - 2, b.pre,
+    GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_THREADS), 0, st, b.Np, b.nxt, b.val, b.headp, N0 - 2, b.pre,
                ctx->d_flags);
     // downward
     for (int l = (int)lv.size() - 2; l >= 1; l--) {

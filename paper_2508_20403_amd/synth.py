@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import math
 import os
+import sys
 
 import numpy as np
 import scipy.sparse as sp
@@ -175,6 +176,12 @@ def grid(dims, wlo, whi, seed=0, alpha=0.02, beta=2, name=None):
                       name or "grid" + "x".join(map(str, dims)))
 
 
+def _log(msg):
+    """Progress line for long generator runs (GSS_VERBOSE=1)."""
+    if os.environ.get("GSS_VERBOSE") == "1":
+        print(f"[synth] {msg}", file=sys.stderr, flush=True)
+
+
 def rmat(scale, avg_deg=16, a=0.57, b=0.19, c=0.19, seed=0, alpha=0.10, beta=2, name=None):
     """R-MAT with avg_deg*2^scale/2 samples, symmetrised, deduplicated, largest CC; w in (0,1]."""
     rng = np.random.default_rng(seed)
@@ -189,6 +196,7 @@ def rmat(scale, avg_deg=16, a=0.57, b=0.19, c=0.19, seed=0, alpha=0.10, beta=2, 
         u |= bu.astype(np.int64) << lvl
         v |= bv.astype(np.int64) << lvl
         del r, bu, bv
+        _log(f"rmat{scale}: level {lvl + 1}/{scale}")
     perm = rng.permutation(nfull)
     u = perm[u]
     v = perm[v]
@@ -200,9 +208,11 @@ def rmat(scale, avg_deg=16, a=0.57, b=0.19, c=0.19, seed=0, alpha=0.10, beta=2, 
     key = np.unique(x * nfull + y)
     x, y = key // nfull, key % nfull
     del key
+    _log(f"rmat{scale}: {len(x)} distinct edges")
     n, x, y = _largest_cc(nfull, x, y)
     x, y = _sort_edges(x, y)
     w = 1.0 - rng.random(len(x))
+    _log(f"rmat{scale}: largest component n={n} m={len(x)}; spanning tree")
     return from_edges(n, x, y, w, alpha, beta, name or f"rmat{scale}")
 
 
