@@ -47,30 +47,61 @@ __device__ __forceinline__ int64_t lb_ticket(unsigned long long *ctr, int64_t nt
 }
 
 // Exclusive prefix of tile `tile` >= 1 over tiles [0, tile) for one counter whose
-// status words sit `stride` apart; called by a whole wavefront, which inspects 64
-// predecessors per step.  Returns the same value in every lane.
+// status words sit `stride` apart; called by a whole wavefront.  Every step inspects
+// LB_SPAN = 64 * LB_PER predecessors with independent loads (slot s = q * 64 + lane is
+// tile hi - s), so a tile far from the last inclusive prefix still resolves in a few
+// round trips: the chain of waits shortens by LB_SPAN tiles per memory latency.
+// Returns the same value in every lane.
+#define LB_PER 4
+#define LB_SPAN (GSS_WAVE * LB_PER)
 __device__ __forceinline__ int64_t lb_lookback_wave(const uint64_t *status, int64_t stride, int64_t tile,
                                                     uint32_t epoch)
 {
     const int lane = lane_id();
     int64_t excl = 0;
-    for (int64_t hi = tile - 1;; hi -= GSS_WAVE) {
-        const int64_t j = hi - lane;
-        uint64_t w = 0;
-        if (j >= 0) {
-            w = lb_load(status + j * stride);
-            while (!lb_ready(w, epoch)) {
-                __builtin_amdgcn_s_sleep(1);
-                w = lb_load(status + j * stride);
-            }
+    for (int64_t hi = tile - 1;; hi -= LB_SPAN) {
+        uint64_t w[LB_PER];
+#pragma unroll
+        for (int q = 0; q < LB_PER; q++) {
+            const int64_t j = hi - (q * GSS_WAVE + lane);
+            w[q] = (j >= 0) ? lb_load(status + j * stride) : 0;
         }
-        const uint64_t incm = __ballot(j < 0 || (w >> 62) == LB_INC);
-        const int stop = incm ? __ffsll((long long)incm) - 1 : GSS_WAVE - 1;
-        int64_t v = (j >= 0 && lane <= stop) ? (int64_t)(w & LB_VALUE_MASK) : 0;
+        for (;;) {
+            bool ready = true;
+#pragma unroll
+            for (int q = 0; q < LB_PER; q++) {
+                const int64_t j = hi - (q * GSS_WAVE + lane);
+                if (j >= 0 && !lb_ready(w[q], epoch)) {
+                    ready = false;
+                    w[q] = lb_load(status + j * stride);
+                }
+            }
+            if (__ballot(!ready) == 0) break;
+            __builtin_amdgcn_s_sleep(4);
+        }
+        // nearest slot holding an inclusive prefix (tiles before 0 count as inclusive 0)
+        int first = LB_SPAN;
+#pragma unroll
+        for (int q = LB_PER - 1; q >= 0; q--) {
+            const int64_t j = hi - (q * GSS_WAVE + lane);
+            if (j < 0 || (w[q] >> 62) == LB_INC) first = q * GSS_WAVE + lane;
+        }
+#pragma unroll
+        for (int d = GSS_WAVE / 2; d >= 1; d >>= 1) {
+            const int o = __shfl_xor(first, d, GSS_WAVE);
+            first = o < first ? o : first;
+        }
+        int64_t v = 0;
+#pragma unroll
+        for (int q = 0; q < LB_PER; q++) {
+            const int s = q * GSS_WAVE + lane;
+            const int64_t j = hi - s;
+            if (j >= 0 && s <= first) v += (int64_t)(w[q] & LB_VALUE_MASK);
+        }
 #pragma unroll
         for (int d = GSS_WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, GSS_WAVE);
         excl += v;
-        if (incm) break;
+        if (first < LB_SPAN) break;
     }
     return excl;
 }

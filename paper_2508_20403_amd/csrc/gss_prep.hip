@@ -62,19 +62,30 @@ __device__ __forceinline__ int64_t clamp_idx(int64_t x, int64_t lo, int64_t hi)
     return x < lo ? lo : (x > hi ? hi : x);
 }
 
-// fills srow[k - base] = row of entry k for the tile starting at base
-__device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
-                                               int64_t base, int32_t *srow)
+// tile_row[b] = the row holding entry b*ETILE: one thread per row marks the tiles that
+// start inside it (row_ptr reads are clamped; malformed input yields wrong but in-range
+// rows, and k_check_rowptr reports it)
+__global__ void k_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz, int64_t ntiles,
+                            int32_t *__restrict__ tile_row)
 {
-    __shared__ int32_t sr[2];
-    if (threadIdx.x == 0) {
-        int64_t last = base + ETILE - 1;
-        if (last >= nnz) last = nnz - 1;
-        sr[0] = row_of(row_ptr, n, base);
-        sr[1] = row_of(row_ptr, n, last);
-    }
-    __syncthreads();
-    const int32_t r0 = sr[0], r1 = sr[1];
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t lo = clamp_idx(row_ptr[x], 0, nnz), hi = clamp_idx(row_ptr[x + 1], 0, nnz);
+    if (hi <= lo) return;
+    const int64_t b1 = (hi - 1) / ETILE;
+    for (int64_t b = (lo + ETILE - 1) / ETILE; b <= b1 && b < ntiles; b++) tile_row[b] = (int32_t)x;
+}
+
+// fills srow[k - base] = row of entry k for tile b (rows r0 .. r1 from the tile table)
+__device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
+                                               int64_t base, const int32_t *__restrict__ tile_row, int32_t *srow)
+{
+    const int64_t b = base / ETILE;
+    const int64_t ntiles = (nnz + ETILE - 1) / ETILE;
+    int32_t r0 = tile_row[b];
+    int32_t r1 = (b + 1 < ntiles) ? tile_row[b + 1] : n - 1;
+    r0 = r0 < 0 ? 0 : (r0 > n - 1 ? n - 1 : r0);
+    r1 = r1 < r0 ? r0 : (r1 > n - 1 ? n - 1 : r1);
     for (int i = threadIdx.x; i < ETILE; i += PB) srow[i] = r0;
     __syncthreads();
     const int64_t end = base + ETILE < nnz ? base + ETILE : nnz;
@@ -117,27 +128,56 @@ __device__ __forceinline__ void entry_hash(int32_t a, int32_t b, double w, uint6
 __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
-                                                      uint32_t *flags, unsigned long long *hsum)
+                                                      const int32_t *__restrict__ tile_row, uint32_t *flags,
+                                                      unsigned long long *hsum)
 {
     __shared__ int32_t srow[ETILE];
+    __shared__ int32_t scol[ETILE];
     __shared__ uint64_t sh[2][PB / GSS_WAVE];
-    int64_t base = (int64_t)blockIdx.x * ETILE;
-    load_tile_rows(row_ptr, n, nnz, base, srow);
+    __shared__ int32_t s_prev[2];  // row and column of entry base-1 (-1 if none)
+    const int64_t base = (int64_t)blockIdx.x * ETILE;
+    // every global load of the tile is issued before any is used
+    int32_t cv[ENT_ITEMS];
+    double wv[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        cv[i] = k < nnz ? col[k] : 0;
+        wv[i] = k < nnz ? w[k] : 1.0;
+    }
+    if (threadIdx.x == 0) {
+        s_prev[0] = -1;
+        s_prev[1] = -1;
+        if (base > 0) {
+            const int32_t r0 = tile_row[blockIdx.x];
+            const int32_t rc = r0 < 0 ? 0 : (r0 > n - 1 ? n - 1 : r0);
+            // entry base-1 lies in row r0 exactly when that row starts before the tile
+            if ((int64_t)row_ptr[rc] < base) s_prev[0] = rc;
+            s_prev[1] = col[base - 1];
+        }
+    }
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) scol[i * PB + threadIdx.x] = cv[i];
+    __syncthreads();
     uint32_t f = 0;
     uint64_t h1 = 0, h2 = 0;
+#pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
         if (k >= nnz) break;
-        int32_t u = srow[k - base];
-        int32_t c = col[k];
+        const int32_t u = srow[k - base];
+        const int32_t c = cv[i];
         if (c < 0 || c >= n) {
             f |= F_ARG;
             continue;
         }
         if (c == u) f |= F_NOT_SIMPLE;
-        int64_t rs = clamp_idx(row_ptr[u], 0, nnz);
-        if (k > rs && col[k - 1] >= c) f |= F_NOT_SIMPLE;
-        double x = w[k];
+        // columns strictly increase within a row
+        const bool prev_same = (k > base) ? (srow[k - 1 - base] == u) : (s_prev[0] == u);
+        const int32_t pc = (k > base) ? scol[k - 1 - base] : s_prev[1];
+        if (prev_same && pc >= c) f |= F_NOT_SIMPLE;
+        const double x = wv[i];
         if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
         uint64_t a1, a2;
         entry_hash(min(u, c), max(u, c), x, a1, a2);
@@ -916,85 +956,100 @@ __global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, 
 // off-tree edges (id order) and tree edge ids
 // ------------------------------------------------------------------------------------
 // off-tree upper entries per tile
-__global__ __launch_bounds__(PB) void k_offtree_count(const int32_t *__restrict__ row_ptr,
-                                                      const int32_t *__restrict__ col,
-                                                      const int32_t *__restrict__ parent, int32_t n, int64_t nnz,
-                                                      int32_t *__restrict__ cnt)
+// Off-tree edges in id order: entry (u,v) with u < v is kept unless its edge id carries
+// the tree flag.  A counting pass gives every tile its number of kept entries, a scan
+// turns the counts into offsets, and the writing pass keeps (round, wave, lane) = index
+// order inside each tile.
+template <bool WRITE>
+__global__ __launch_bounds__(PB) void k_offtree(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ w,
+    const uint8_t *__restrict__ tflag, const int32_t *__restrict__ uptr, const int32_t *__restrict__ ufirst,
+    int32_t n, int64_t nnz, int64_t m, const int32_t *__restrict__ tile_row, int32_t *__restrict__ tile_cnt,
+    int64_t Mcap, int32_t *__restrict__ off_id, int32_t *__restrict__ off_u, int32_t *__restrict__ off_v,
+    double *__restrict__ off_w, const int32_t *__restrict__ vbase, int32_t G, int32_t *__restrict__ off_g,
+    uint32_t *flags)
 {
+    constexpr int NW = PB / GSS_WAVE;
     __shared__ int32_t srow[ETILE];
-    __shared__ int32_t sc[PB / GSS_WAVE];
-    int64_t base = (int64_t)blockIdx.x * ETILE;
-    load_tile_rows(row_ptr, n, nnz, base, srow);
-    int32_t c = 0;
+    __shared__ int32_t s_wsum[ENT_ITEMS][NW];
+    const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
+    const int64_t base = (int64_t)blockIdx.x * ETILE;
+    int32_t cv[ENT_ITEMS];
+#pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        if (k >= nnz) break;
-        int32_t u = srow[k - base];
-        int32_t v = col[k];
-        if (v > u && parent[u] != v && parent[v] != u) c++;
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        cv[i] = k < nnz ? col[k] : -1;
     }
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, GSS_WAVE);
-    if (lane_id() == 0) sc[threadIdx.x / GSS_WAVE] = c;
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);
+    // edge id of every upper entry, then its tree flag (consecutive ids of a row are
+    // consecutive bytes)
+    int32_t eid[ENT_ITEMS];
+    uint8_t tf[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        const int32_t u = srow[(k - base) & (ETILE - 1)];
+        eid[i] = -1;
+        if (k < nnz && cv[i] > u) eid[i] = uptr[u] + (int32_t)(k - ufirst[u]);
+    }
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) tf[i] = (eid[i] >= 0 && eid[i] < m) ? tflag[eid[i]] : 1;
+    uint64_t keepm[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        keepm[i] = __ballot(tf[i] == 0);
+        if (lane == 0) s_wsum[i][wid] = __popcll(keepm[i]);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < PB / GSS_WAVE; i++) c += sc[i];
-        cnt[blockIdx.x] = c;
+    if (!WRITE) {
+        if (threadIdx.x == 0) {
+            int32_t t = 0;
+            for (int i = 0; i < ENT_ITEMS; i++)
+                for (int w2 = 0; w2 < NW; w2++) t += s_wsum[i][w2];
+            tile_cnt[blockIdx.x] = t;
+        }
+        return;
     }
-}
-
-// stable compaction: round i of a tile holds entries base+i*PB .. +PB-1 in thread order
-__global__ __launch_bounds__(PB) void k_offtree_write(const int32_t *__restrict__ row_ptr,
-                                                      const int32_t *__restrict__ col,
-                                                      const double *__restrict__ w,
-                                                      const int32_t *__restrict__ parent,
-                                                      const int32_t *__restrict__ uptr,
-                                                      const int32_t *__restrict__ ufirst, int32_t n, int64_t nnz,
-                                                      const int32_t *__restrict__ off0,
-                                                      int32_t *__restrict__ off_id, int32_t *__restrict__ off_u,
-                                                      int32_t *__restrict__ off_v, double *__restrict__ off_w,
-                                                      const int32_t *__restrict__ vbase, int32_t G,
-                                                      int32_t *__restrict__ off_g)
-{
-    __shared__ int32_t srow[ETILE];
-    __shared__ int32_t lds[PB / GSS_WAVE + 1];
-    int64_t base = (int64_t)blockIdx.x * ETILE;
-    load_tile_rows(row_ptr, n, nnz, base, srow);
-    int32_t q = off0[blockIdx.x];
+    int64_t off[ENT_ITEMS];
+    int64_t run = tile_cnt[blockIdx.x];
+#pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        bool keep = false;
-        int32_t u = 0, v = 0;
-        if (k < nnz) {
-            u = srow[k - base];
-            v = col[k];
-            keep = v > u && parent[u] != v && parent[v] != u;
+        for (int w2 = 0; w2 < NW; w2++) {
+            if (w2 == wid) off[i] = run;
+            run += s_wsum[i][w2];
         }
-        int32_t tot;
-        int32_t pos = block_exclusive_scan<int32_t>(keep ? 1 : 0, lds, &tot);
-        if (keep) {
-            int32_t o = q + pos;
-            off_id[o] = uptr[u] + (int32_t)(k - ufirst[u]);
-            off_u[o] = u;
-            off_v[o] = v;
-            off_w[o] = w[k];
-            if (off_g) {
-                int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
-                while (hi - lo > 1) {
-                    int32_t mid = (lo + hi) >> 1;
-                    if (vbase[mid] <= u) lo = mid;
-                    else hi = mid;
-                }
-                off_g[o] = lo;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        if (!((keepm[i] >> lane) & 1ull)) continue;
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        const int64_t o = off[i] + __popcll(keepm[i] & lt);
+        if (o >= Mcap) {
+            atomicOr(flags, F_TREE_EDGE);  // more off-tree entries than m - n + 1
+            continue;
+        }
+        const int32_t u = srow[k - base];
+        off_id[o] = eid[i];
+        off_u[o] = u;
+        off_v[o] = cv[i];
+        off_w[o] = w[k];
+        if (off_g) {
+            int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (vbase[mid] <= u) lo = mid;
+                else hi = mid;
             }
+            off_g[o] = lo;
         }
-        q += tot;
     }
 }
 
 __global__ void k_tree_eid(const int32_t *__restrict__ parent, const int32_t *__restrict__ row_ptr,
                            const int32_t *__restrict__ col, const int32_t *__restrict__ uptr,
                            const int32_t *__restrict__ ufirst, const int32_t *__restrict__ tpos,
-                           int32_t n, int32_t *__restrict__ tree_eid)
+                           int32_t n, int64_t m, int32_t *__restrict__ tree_eid, uint8_t *__restrict__ tflag)
 {
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
@@ -1003,12 +1058,15 @@ __global__ void k_tree_eid(const int32_t *__restrict__ parent, const int32_t *__
         tree_eid[x] = -1;
         return;
     }
+    int32_t e;
     if (x < p) {
-        tree_eid[x] = uptr[x] + (tpos[x] - ufirst[x]);
+        e = uptr[x] + (tpos[x] - ufirst[x]);
     } else {
         int64_t k = find_in_row(col, row_ptr[p], row_ptr[p + 1], x);
-        tree_eid[x] = uptr[p] + (int32_t)(k - ufirst[p]);
+        e = k < 0 ? -1 : uptr[p] + (int32_t)(k - ufirst[p]);
     }
+    tree_eid[x] = e;
+    if (e >= 0 && e < m) tflag[e] = 1;
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
@@ -1086,6 +1144,20 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     const bool validate = !(flags & GSS_PREP_TRUSTED);
     HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
 
+    // the row at the start of every tile of ETILE entries
+    const int64_t etiles = nnz > 0 ? (nnz + ETILE - 1) / ETILE : 0;
+    int32_t *tile_row = ctx->alloc<int32_t>(etiles + 1);
+    if (nnz > 0) {
+        HIP_OK(hipMemsetAsync(tile_row, 0, sizeof(int32_t) * (etiles + 1), st));
+        GSS_LAUNCH_B(8 * (int64_t)n, k_tile_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz, etiles,
+                     tile_row);
+    }
+    struct TileRowsFree {
+        gss_ctx c;
+        int32_t *p;
+        ~TileRowsFree() { c->free(p); }
+    } tile_row_guard{ctx, tile_row};
+
     // validation (memory-safe on malformed input) and edge numbering
     if (validate) {
         HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, 2 * sizeof(int64_t), st));
@@ -1093,8 +1165,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
                    ctx->d_flags);
         if (nnz > 0)
             GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3(grid_for(nnz, ETILE)), dim3(PB), 0,
-                         st, t->row_ptr, t->col, t->w, n,
-                       nnz, ctx->d_flags, (unsigned long long *)(ctx->d_counters + 10));
+                         st, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags,
+                         (unsigned long long *)(ctx->d_counters + 10));
         HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, 2 * sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
         uint32_t f = read_flags(ctx);
@@ -1231,30 +1303,36 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->off_u = ctx->alloc<int32_t>(t->M + 1);
     t->off_v = ctx->alloc<int32_t>(t->M + 1);
     t->off_w = ctx->alloc<double>(t->M + 1);
-    if (nnz > 0) {
-        int64_t nblk = grid_for(nnz, ETILE);
-        int32_t *ocnt = ctx->alloc<int32_t>(nblk + 1);
-        GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n, k_offtree_count, dim3((unsigned)nblk), dim3(PB), 0, st, t->row_ptr,
-                     t->col, t->parent, n, nnz,
-                   ocnt);
-        int64_t M2 = scan_exclusive_i32(ctx, ocnt, nblk, true);
-        if (M2 != t->M) {
-            ctx->free(ocnt);
-            fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
-        }
-        if (t->G > 1 || t->virt_root >= 0) t->off_g = ctx->alloc<int32_t>(t->M + 1);
-        GSS_LAUNCH_B(4 * nnz + 8 * t->m + 12 * (int64_t)n + 20 * t->M, k_offtree_write, dim3((unsigned)nblk), dim3(PB),
-                     0, st, t->row_ptr, t->col, t->w, t->parent,
-                   t->uptr, t->ufirst, n, nnz, ocnt, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G,
-                   t->off_g);
-        ctx->free(ocnt);
-    }
+    // tree edge ids, and a flag byte per edge id
     t->tree_eid = ctx->alloc<int32_t>(n);
-    GSS_LAUNCH_B(20 * (int64_t)n, k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col,
-                 t->uptr, t->ufirst,
-               t->tpos, n, t->tree_eid);
+    uint8_t *tflag = ctx->alloc<uint8_t>(t->m + 1);
+    struct TflagFree {
+        gss_ctx c;
+        uint8_t *p;
+        ~TflagFree() { c->free(p); }
+    } tflag_guard{ctx, tflag};
+    HIP_OK(hipMemsetAsync(tflag, 0, t->m + 1, st));
+    GSS_LAUNCH_B(21 * (int64_t)n, k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col,
+                 t->uptr, t->ufirst, t->tpos, n, t->m, t->tree_eid, tflag);
+    if (nnz > 0) {
+        if (t->G > 1 || t->virt_root >= 0) t->off_g = ctx->alloc<int32_t>(t->M + 1);
+        int32_t *tcnt = ctx->alloc<int32_t>(etiles + 1);
+        // CSR columns, row starts and tree flags read; one count per tile
+        GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m, k_offtree<false>, dim3((unsigned)etiles), dim3(PB), 0, st,
+                     t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row, tcnt, t->M,
+                     t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, ctx->d_flags);
+        scan_exclusive_i32_dev(ctx, tcnt, etiles, ctx->d_counters + 9);
+        // the same reads again; per off-tree edge its id, endpoints and weight written
+        GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m + 28 * t->M, k_offtree<true>, dim3((unsigned)etiles), dim3(PB),
+                     0, st, t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row, tcnt, t->M,
+                     t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, ctx->d_flags);
+        ctx->free(tcnt);
+    }
     HIP_OK(hipGetLastError());
-    ctx->sync();
+    HIP_OK(hipMemcpyAsync(&ctx->h_counters[9], ctx->d_counters + 9, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    f = read_flags(ctx);  // syncs
+    if (nnz > 0 && (ctx->h_counters[9] != t->M || (f & F_TREE_EDGE)))
+        fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
     if (t->virt_root < 0) {  // a single graph: one range covering everything
         t->vbase = {0, (int64_t)n};
         t->ebase = {0, t->m};
