@@ -129,7 +129,7 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
                                                       const int32_t *__restrict__ tile_row, uint32_t *flags,
-                                                      unsigned long long *hsum)
+                                                      uint64_t *__restrict__ hpart)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t scol[ETILE];
@@ -205,8 +205,37 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
             h1 += sh[0][i];
             h2 += sh[1][i];
         }
-        if (h1) atomicAdd(&hsum[0], (unsigned long long)h1);
-        if (h2) atomicAdd(&hsum[1], (unsigned long long)h2);
+        hpart[2 * (int64_t)blockIdx.x] = h1;  // per-block partial sums (no contended atomics)
+        hpart[2 * (int64_t)blockIdx.x + 1] = h2;
+    }
+}
+
+// sums the per-block hash partials of k_check_entries into hsum[0..1]
+__global__ __launch_bounds__(1024) void k_hash_total(const uint64_t *__restrict__ hpart, int64_t nblk,
+                                                     unsigned long long *hsum)
+{
+    __shared__ uint64_t s1[1024 / GSS_WAVE], s2[1024 / GSS_WAVE];
+    uint64_t a = 0, b = 0;
+    for (int64_t i = threadIdx.x; i < nblk; i += 1024) {
+        a += hpart[2 * i];
+        b += hpart[2 * i + 1];
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        a += __shfl_xor(a, d, GSS_WAVE);
+        b += __shfl_xor(b, d, GSS_WAVE);
+    }
+    if (lane_id() == 0) {
+        s1[threadIdx.x / GSS_WAVE] = a;
+        s2[threadIdx.x / GSS_WAVE] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 1024 / GSS_WAVE; i++) {
+            a += s1[i];
+            b += s2[i];
+        }
+        hsum[0] = a;
+        hsum[1] = b;
     }
 }
 
@@ -1163,10 +1192,14 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, 2 * sizeof(int64_t), st));
         GSS_LAUNCH(k_check_rowptr, dim3(grid_for(n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
                    ctx->d_flags);
-        if (nnz > 0)
-            GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3(grid_for(nnz, ETILE)), dim3(PB), 0,
-                         st, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags,
-                         (unsigned long long *)(ctx->d_counters + 10));
+        if (nnz > 0) {
+            uint64_t *hpart = ctx->alloc<uint64_t>(2 * etiles + 2);
+            GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0, st,
+                         t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, hpart);
+            GSS_LAUNCH(k_hash_total, dim3(1), dim3(1024), 0, st, hpart, etiles,
+                       (unsigned long long *)(ctx->d_counters + 10));
+            ctx->free(hpart);
+        }
         HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, 2 * sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
         uint32_t f = read_flags(ctx);

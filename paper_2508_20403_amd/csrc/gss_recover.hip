@@ -507,12 +507,6 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__rest
 // ------------------------------------------------------------------------------------
 // per-rank gather and the anchor hash join
 // ------------------------------------------------------------------------------------
-struct Slot {
-    unsigned long long ab;  // (A << 32) | B, all ones = empty
-    int32_t p;              // rank of the inserted edge
-    int32_t ik;             // (i << 8) | k
-};
-#define SLOT_EMPTY 0xffffffffffffffffull
 
 __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const int32_t *__restrict__ off_id,
                               const int32_t *__restrict__ off_u, const int32_t *__restrict__ off_v,
@@ -549,111 +543,262 @@ __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const i
     }
 }
 
-__device__ __forceinline__ uint64_t slot_hash(uint64_t ab) { return mix64(ab * 0x9E3779B97F4A7C15ull + 1); }
+// ------------------------------------------------------------------------------------
+// Anchor join, partitioned.  Marker p = (u,v) with beta* b marks a later edge t = (x,y)
+// of its subtask when x is within b tree hops of u and y within b of v (or x of v and y
+// of u).  Within b hops means a common ancestor anc_i(x) = anc_j(u) with i + j <= b, so
+// every edge emits records keyed by an ancestor pair:
+//   build  (t): (anc_i(x), anc_k(y)) and (anc_i(y), anc_k(x)) for i, k <= c,
+//   probe  (p): (anc_j(u), anc_l(v)) for j, l <= b,
+// and a probe record matches a build record of equal key with i <= b - j, k <= b - l
+// and t later than p.  Records are scattered into JP_PARTS partitions by a hash of the
+// key (per-block histograms, a scan, then a scatter with LDS cursors: no global
+// atomics), and every partition is joined in LDS by one workgroup.
+// ------------------------------------------------------------------------------------
+#define JP_BITS 11
+#define JP_PARTS (1 << JP_BITS)
+#define JP_BLOCK 256
+#define JP_ITEMS 32                      // record slots per thread in the partition passes
+#define JP_SPB (JP_BLOCK * JP_ITEMS)     // record slots per block
+#define JP_CAP 2048                      // records of a partition held in LDS at once
+#define JP_TAB (2 * JP_CAP)              // LDS hash slots
+#define JP_PROBE (1u << 31)
 
-__device__ __forceinline__ void join_insert(Slot *tab, uint64_t cap_mask, int32_t A, int32_t B, int32_t p,
-                                            int ik)
+struct JRec {
+    unsigned long long ab;  // (A << 32) | B
+    int32_t p;              // rank of the edge
+    uint32_t meta;          // build: (i << 8) | k; probe: JP_PROBE | (j << 16) | (l << 8) | beta*
+};
+
+__device__ __forceinline__ uint64_t jp_hash(uint64_t ab) { return mix64(ab * 0x9E3779B97F4A7C15ull + 1); }
+__device__ __forceinline__ uint32_t jp_part(uint64_t ab) { return (uint32_t)(jp_hash(ab) >> (64 - JP_BITS)); }
+
+// record slot s = (listed edge gi, r): r < 2(c+1)^2 build, then (c+1)^2 probe slots.
+// Stage 1 reads the rank, stage 2 the ancestors, so that a batch of slots has all its
+// loads of one stage in flight together.
+__device__ __forceinline__ int32_t jp_rank(int64_t s, int64_t nslots, int32_t S, const int32_t *__restrict__ glist)
 {
-    unsigned long long ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
-    uint64_t h = slot_hash(ab) & cap_mask;
-    for (;;) {
-        unsigned long long old = atomicCAS(&tab[h].ab, SLOT_EMPTY, ab);
-        if (old == SLOT_EMPTY) {
-            tab[h].p = p;
-            tab[h].ik = ik;
-            return;
+    return s < nslots ? glist[s / S] : -1;
+}
+__device__ __forceinline__ bool jp_record(int64_t s, int32_t S, int32_t p, int64_t P, int32_t c,
+                                          const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
+                                          const int32_t *__restrict__ ancV, JRec &rec)
+{
+    if (p < 0) return false;
+    const int C1 = c + 1, nb = 2 * C1 * C1;
+    int r = (int)(s % S);
+    int32_t A, B;
+    if (r < nb) {
+        const int orient = r / (C1 * C1);
+        r -= orient * C1 * C1;
+        const int i = r / C1, k = r % C1;
+        A = (orient ? ancV : ancU)[(int64_t)i * P + p];
+        B = (orient ? ancU : ancV)[(int64_t)k * P + p];
+        rec.meta = ((uint32_t)i << 8) | (uint32_t)k;
+    } else {
+        r -= nb;
+        const int j = r / C1, l = r % C1;
+        const int beta = rb[p];
+        if (beta == 0 || j > beta || l > beta) return false;  // beta* = 0 marks nothing
+        A = ancU[(int64_t)j * P + p];
+        B = ancV[(int64_t)l * P + p];
+        rec.meta = JP_PROBE | ((uint32_t)j << 16) | ((uint32_t)l << 8) | (uint32_t)beta;
+    }
+    if (A < 0 || B < 0) return false;
+    rec.ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
+    rec.p = p;
+    return true;
+}
+#define JP_BATCH 8
+
+// pass 1: per-block partition histogram, stored partition-major: hist[part * nblk + block]
+__global__ __launch_bounds__(JP_BLOCK) void k_jp_count(int64_t nslots, int32_t S, const int32_t *__restrict__ glist,
+                                                        int64_t P, int32_t c, const uint8_t *__restrict__ rb,
+                                                        const int32_t *__restrict__ ancU,
+                                                        const int32_t *__restrict__ ancV, int32_t nblk,
+                                                        int32_t *__restrict__ hist)
+{
+    __shared__ int32_t sh[JP_PARTS];
+    for (int b = threadIdx.x; b < JP_PARTS; b += JP_BLOCK) sh[b] = 0;
+    __syncthreads();
+    const int64_t s0 = (int64_t)blockIdx.x * JP_SPB;
+    for (int it0 = 0; it0 < JP_ITEMS; it0 += JP_BATCH) {
+        int32_t pr[JP_BATCH];
+#pragma unroll
+        for (int b = 0; b < JP_BATCH; b++) pr[b] = jp_rank(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, nslots, S, glist);
+        uint32_t part[JP_BATCH];
+#pragma unroll
+        for (int b = 0; b < JP_BATCH; b++) {
+            JRec rec;
+            part[b] = jp_record(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, S, pr[b], P, c, rb, ancU, ancV, rec)
+                          ? jp_part(rec.ab) : JP_PARTS;
         }
-        h = (h + 1) & cap_mask;
+#pragma unroll
+        for (int b = 0; b < JP_BATCH; b++)
+            if (part[b] < JP_PARTS) atomicAdd(&sh[part[b]], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < JP_PARTS; b += JP_BLOCK) hist[(int64_t)b * nblk + blockIdx.x] = sh[b];
+}
+
+// pass 2: the same records, written at their partition offsets (order inside a
+// partition is immaterial)
+__global__ __launch_bounds__(JP_BLOCK) void k_jp_scatter(int64_t nslots, int32_t S,
+                                                          const int32_t *__restrict__ glist, int64_t P, int32_t c,
+                                                          const uint8_t *__restrict__ rb,
+                                                          const int32_t *__restrict__ ancU,
+                                                          const int32_t *__restrict__ ancV, int32_t nblk,
+                                                          const int32_t *__restrict__ off, JRec *__restrict__ recs)
+{
+    __shared__ int32_t sh[JP_PARTS];
+    for (int b = threadIdx.x; b < JP_PARTS; b += JP_BLOCK) sh[b] = off[(int64_t)b * nblk + blockIdx.x];
+    __syncthreads();
+    const int64_t s0 = (int64_t)blockIdx.x * JP_SPB;
+    for (int it0 = 0; it0 < JP_ITEMS; it0 += JP_BATCH) {
+        int32_t pr[JP_BATCH];
+#pragma unroll
+        for (int b = 0; b < JP_BATCH; b++) pr[b] = jp_rank(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, nslots, S, glist);
+        JRec rec[JP_BATCH];
+        bool ok[JP_BATCH];
+#pragma unroll
+        for (int b = 0; b < JP_BATCH; b++)
+            ok[b] = jp_record(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, S, pr[b], P, c, rb, ancU, ancV, rec[b]);
+#pragma unroll
+        for (int b = 0; b < JP_BATCH; b++) {
+            if (ok[b]) {
+                const int32_t pos = atomicAdd(&sh[jp_part(rec[b].ab)], 1);
+                recs[pos] = rec[b];
+            }
+        }
     }
 }
 
-// one thread per (listed edge, orientation, i, k): insert (anc_i(x), anc_k(y)) -> (rank, i, k)
-__global__ void k_join_build(int64_t NG, const int32_t *__restrict__ glist, int64_t P, int32_t c,
-                             const int32_t *__restrict__ ancU, const int32_t *__restrict__ ancV, Slot *tab,
-                             uint64_t cap_mask)
+// pass 3: one workgroup per partition.  Build records of a chunk of JP_CAP records go
+// into an LDS hash table; every probe record of the partition then looks up its key.
+// arcs found by a workgroup are staged in LDS (the first JP_ARC_LDS) and stored in its
+// partition's own slice of the arc buffer (no global counter to contend on)
+#define JP_ARC_LDS 1024
+__device__ __forceinline__ void jp_probe(const JRec &r, bool active, const unsigned long long *s_ab,
+                                         const int32_t *s_p, const uint32_t *s_meta, const int32_t *s_tab,
+                                         int2 *s_arc, int32_t *s_narc, int32_t arc_slot, int2 *arc_slice,
+                                         int32_t *__restrict__ indeg)
 {
-    const int per = 2 * (c + 1) * (c + 1);
-    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t gi = tid / per;
-    if (gi >= NG) return;
-    const int32_t p = glist[gi];
-    int r = (int)(tid - gi * per);
-    const int orient = r / ((c + 1) * (c + 1));
-    r -= orient * (c + 1) * (c + 1);
-    const int i = r / (c + 1), k = r % (c + 1);
-    const int32_t *X = orient ? ancV : ancU;
-    const int32_t *Y = orient ? ancU : ancV;
-    int32_t A = X[(int64_t)i * P + p];
-    int32_t B = Y[(int64_t)k * P + p];
-    if (A < 0 || B < 0) return;
-    join_insert(tab, cap_mask, A, B, p, (i << 8) | k);
-}
-
-// one thread per (listed marker edge, j, l): probe (anc_j(u), anc_l(v)) and keep entries
-// with i <= beta*-j and k <= beta*-l of a later rank.  The probe loop is wave-uniform so
-// that the arcs found in one step are appended with one atomic per wavefront.
-__global__ void k_join_probe(int64_t NG, const int32_t *__restrict__ glist, int64_t P, int32_t c,
-                             const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
-                             const int32_t *__restrict__ ancV, const Slot *__restrict__ tab, uint64_t cap_mask,
-                             int2 *__restrict__ arcs, int64_t arc_cap, unsigned long long *arc_count,
-                             int32_t *__restrict__ indeg, uint32_t *flags)
-{
-    const int per = (c + 1) * (c + 1);
-    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t gi = tid / per;
-    bool active = gi < NG;
-    int32_t p = 0;
-    int beta = 0, j = 0, l = 0;
-    unsigned long long ab = 0;
-    uint64_t h = 0;
-    if (active) {
-        p = glist[gi];
-        beta = rb[p];
-        const int r = (int)(tid - gi * per);
-        j = r / (c + 1);
-        l = r % (c + 1);
-        active = beta > 0 && j <= beta && l <= beta;  // beta* = 0: only the edge itself is similar
-    }
-    if (active) {
-        int32_t A = ancU[(int64_t)j * P + p];
-        int32_t B = ancV[(int64_t)l * P + p];
-        active = A >= 0 && B >= 0;
-        ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
-        h = slot_hash(ab) & cap_mask;
-    }
+    const int j = (r.meta >> 16) & 255, l = (r.meta >> 8) & 255, beta = r.meta & 255;
+    uint32_t h = (uint32_t)jp_hash(r.ab) & (JP_TAB - 1);
     while (__ballot(active)) {
         bool hit = false;
         int32_t t = 0;
         if (active) {
-            unsigned long long s = tab[h].ab;
-            if (s == SLOT_EMPTY) {
+            const int li = s_tab[h];
+            if (li < 0) {
                 active = false;
             } else {
-                if (s == ab) {
-                    int ik = tab[h].ik;
-                    t = tab[h].p;
-                    hit = (ik >> 8) <= beta - j && (ik & 255) <= beta - l && t > p;
+                if (s_ab[li] == r.ab) {
+                    const uint32_t mk = s_meta[li];
+                    t = s_p[li];
+                    hit = (int)(mk >> 8) <= beta - j && (int)(mk & 255) <= beta - l && t > r.p;
                 }
-                h = (h + 1) & cap_mask;
+                h = (h + 1) & (JP_TAB - 1);
             }
         }
-        uint64_t m = __ballot(hit);
-        if (m) {
-            int leader = __ffsll((long long)m) - 1;
-            unsigned long long base = 0;
-            if (lane_id() == leader) base = atomicAdd(arc_count, (unsigned long long)__popcll(m));
-            base = __shfl(base, leader, GSS_WAVE);
-            if (hit) {
-                unsigned long long a = base + __popcll(m & lanemask_lt());
-                if ((int64_t)a < arc_cap) {
-                    arcs[a] = make_int2(p, t);
-                    atomicAdd(&indeg[t], 1);
-                } else {
-                    atomicOr(flags, F_OVERFLOW);
-                }
-            }
+        if (hit) {
+            const int32_t a = atomicAdd(s_narc, 1);
+            if (a < JP_ARC_LDS) s_arc[a] = make_int2(r.p, t);
+            else if (a < arc_slot) arc_slice[a] = make_int2(r.p, t);
+            atomicAdd(&indeg[t], 1);
         }
     }
+}
+
+__global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ recs, const int32_t *__restrict__ off,
+                                                       int32_t nblk, const int64_t *__restrict__ total,
+                                                       int32_t arc_slot, int2 *__restrict__ arc_buf,
+                                                       int32_t *__restrict__ arc_cnt, int32_t *__restrict__ indeg)
+{
+    constexpr int PER = JP_CAP / JP_BLOCK;
+    __shared__ unsigned long long s_ab[JP_CAP];
+    __shared__ int32_t s_p[JP_CAP];
+    __shared__ uint32_t s_meta[JP_CAP];
+    __shared__ int32_t s_tab[JP_TAB];
+    __shared__ int2 s_arc[JP_ARC_LDS];
+    __shared__ int32_t s_narc;
+    const int64_t part = blockIdx.x;
+    const int64_t start = off[part * nblk];
+    const int64_t end = (part + 1 < JP_PARTS) ? off[(part + 1) * nblk] : *total;
+    int2 *arc_slice = arc_buf + part * (int64_t)arc_slot;
+    if (threadIdx.x == 0) s_narc = 0;
+    JRec zero;
+    zero.ab = 0;
+    zero.p = 0;
+    zero.meta = 0;
+    for (int64_t c0 = start; c0 < end; c0 += JP_CAP) {
+        const int64_t c1 = (end - c0 < JP_CAP) ? end : c0 + JP_CAP;
+        // this chunk's records: all loads in flight together
+        JRec rr[PER];
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int64_t q = c0 + k * JP_BLOCK + threadIdx.x;
+            rr[k] = q < c1 ? recs[q] : zero;
+        }
+        for (int h = threadIdx.x; h < JP_TAB; h += JP_BLOCK) s_tab[h] = -1;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int li = k * JP_BLOCK + threadIdx.x;
+            if (c0 + li < c1) {
+                s_ab[li] = rr[k].ab;
+                s_p[li] = rr[k].p;
+                s_meta[li] = rr[k].meta;
+                if (!(rr[k].meta & JP_PROBE)) {
+                    uint32_t h = (uint32_t)jp_hash(rr[k].ab) & (JP_TAB - 1);
+                    while (atomicCAS(&s_tab[h], -1, li) != -1) h = (h + 1) & (JP_TAB - 1);
+                }
+            }
+        }
+        __syncthreads();
+        if (c0 == start && c1 == end) {
+            // the whole partition is this chunk: its probe records are already in registers
+#pragma unroll
+            for (int k = 0; k < PER; k++) {
+                const bool act = c0 + k * JP_BLOCK + threadIdx.x < c1 && (rr[k].meta & JP_PROBE);
+                jp_probe(rr[k], act, s_ab, s_p, s_meta, s_tab, s_arc, &s_narc, arc_slot, arc_slice, indeg);
+            }
+        } else {
+            for (int64_t q0 = start; q0 < end; q0 += JP_BLOCK) {
+                const int64_t q = q0 + threadIdx.x;
+                const JRec r = q < end ? recs[q] : zero;
+                jp_probe(r, q < end && (r.meta & JP_PROBE), s_ab, s_p, s_meta, s_tab, s_arc, &s_narc, arc_slot,
+                         arc_slice, indeg);
+            }
+        }
+        __syncthreads();
+    }
+    const int32_t na = s_narc;
+    if (threadIdx.x == 0) arc_cnt[part] = na;  // the true count: above arc_slot the host retries
+    for (int a = threadIdx.x; a < na && a < arc_slot && a < JP_ARC_LDS; a += JP_BLOCK) arc_slice[a] = s_arc[a];
+}
+
+__global__ __launch_bounds__(1024) void k_max_i32(const int32_t *__restrict__ x, int32_t n, int64_t *out)
+{
+    __shared__ int32_t sm[1024 / GSS_WAVE];
+    int32_t v = 0;
+    for (int32_t i = threadIdx.x; i < n; i += 1024) v = max(v, x[i]);
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, GSS_WAVE));
+    if (lane_id() == 0) sm[threadIdx.x / GSS_WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / GSS_WAVE; w++) v = max(v, sm[w]);
+        *out = v;
+    }
+}
+
+// the partitions' arcs, packed (arc_cnt scanned to offsets)
+__global__ void k_jp_pack(const int2 *__restrict__ arc_buf, const int32_t *__restrict__ arc_cnt,
+                          const int32_t *__restrict__ arc_off, int32_t arc_slot, int2 *__restrict__ arcs)
+{
+    const int64_t part = blockIdx.x;
+    const int32_t n = arc_cnt[part], o = arc_off[part];
+    for (int a = threadIdx.x; a < n; a += blockDim.x) arcs[o + a] = arc_buf[part * (int64_t)arc_slot + a];
 }
 
 __global__ void k_state_init(int64_t NG, const int32_t *__restrict__ glist, const int32_t *__restrict__ indeg,
@@ -1097,6 +1242,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         // candidate scratch: at most ~256 MB whatever the setting
         const size_t per_wave = (size_t)std::max<int32_t>(local_max, 1) * local_desc_bytes(c);
         blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(1, ((int64_t)256 << 20) / (4 * per_wave)));
+        // about 16 chunks per wavefront; one subtask per take while the queue is short
+        a.chunk = std::max<int32_t>(1, std::min<int32_t>(64, nlocal / (blocks * 4 * 16)));
         void *scr = ctx->alloc<uint8_t>((size_t)blocks * 4 * per_wave + 64);
         scratch.push_back(scr);
         a.cand_scratch = scr;
@@ -1109,32 +1256,43 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     B.indeg = ctx->alloc<int32_t>(P + 1);
     B.mcnt = ctx->alloc<int32_t>(P + 1);
     if (nsub > nlocal) {
-        int64_t entries = 2 * (int64_t)(c + 1) * (c + 1) * nglobal_edges;
-        uint64_t cap = 1024;
-        while (cap < 2 * (uint64_t)entries) cap <<= 1;
-        Slot *tab = ctx->alloc<Slot>(cap);
-        HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(Slot) * cap, st));
-        // per listed edge: its rank, 2(c+1) ancestors, 2(c+1)^2 slots of 16 B written
-        GSS_LAUNCH_B(nglobal_edges * (4 + 8 * (c + 1) + 32 * (c + 1) * (c + 1)), k_join_build,
-                     dim3(grid_for(nglobal_edges * 2 * (c + 1) * (c + 1), RB)), dim3(RB), 0, st,
-                   nglobal_edges, B.glist, P, c, B.ancU, B.ancV, tab, cap - 1);
-        int64_t arc_cap = std::max<int64_t>(4 * P, 1 << 16);
+        // partition the join records by key hash
+        const int64_t nslots = nglobal_edges * 3 * (int64_t)(c + 1) * (c + 1);
+        const int32_t nblk = (int32_t)((nslots + JP_SPB - 1) / JP_SPB);
+        int32_t *jhist = ctx->alloc<int32_t>((int64_t)JP_PARTS * nblk + 1);
+        JRec *recs = ctx->alloc<JRec>(nslots + 1);
+        int64_t *d_total = ctx->d_counters + 8;
+        // per listed edge: rank, beta* and 2(c+1) ancestors read (twice: count, scatter);
+        // 16 B per record written and read back by the join
+        const int32_t S = 3 * (c + 1) * (c + 1);
+        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)), k_jp_count, dim3(nblk), dim3(JP_BLOCK), 0, st, nslots, S,
+                     B.glist, P, c, B.rb, B.ancU, B.ancV, nblk, jhist);
+        scan_exclusive_i32_dev(ctx, jhist, (int64_t)JP_PARTS * nblk, d_total);
+        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)) + 16 * nslots, k_jp_scatter, dim3(nblk), dim3(JP_BLOCK), 0, st,
+                     nslots, S, B.glist, P, c, B.rb, B.ancU, B.ancV, nblk, jhist, recs);
+        int32_t arc_slot = 128;
+        int32_t *arc_cnt = ctx->alloc<int32_t>(JP_PARTS + 1);
+        int32_t *arc_off = ctx->alloc<int32_t>(JP_PARTS + 1);
         for (;;) {
-            int2 *arcs = ctx->alloc<int2>(arc_cap);
+            int2 *arc_buf = ctx->alloc<int2>((int64_t)JP_PARTS * arc_slot);
             HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
-            HIP_OK(hipMemsetAsync(ctx->d_counters, 0, sizeof(int64_t) * 2, st));
-            // per listed edge: rank, beta*, 2(c+1) ancestors, (c+1)^2 slots of 16 B read
-            GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1) + 16 * (c + 1) * (c + 1)), k_join_probe,
-                         dim3(grid_for(nglobal_edges * (c + 1) * (c + 1), RB)), dim3(RB), 0, st,
-                       nglobal_edges, B.glist, P, c, B.rb, B.ancU, B.ancV, tab, cap - 1, arcs, arc_cap,
-                       (unsigned long long *)ctx->d_counters, B.indeg, ctx->d_flags);
-            read_counters(ctx, 1);
-            int64_t A = ctx->h_counters[0];
-            if (A > arc_cap) {
-                ctx->free(arcs);
-                arc_cap = A + A / 4 + 1024;
+            GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(JP_PARTS), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, d_total,
+                         arc_slot, arc_buf, arc_cnt, B.indeg);
+            GSS_LAUNCH(k_max_i32, dim3(1), dim3(1024), 0, st, arc_cnt, (int32_t)JP_PARTS, ctx->d_counters + 3);
+            HIP_OK(hipMemcpyAsync(arc_off, arc_cnt, sizeof(int32_t) * JP_PARTS, hipMemcpyDeviceToDevice, st));
+            scan_exclusive_i32_dev(ctx, arc_off, JP_PARTS, ctx->d_counters);
+            read_counters(ctx, 4);
+            const int64_t most = ctx->h_counters[3];
+            if (most > arc_slot) {  // some partition found more arcs than its slice holds
+                ctx->free(arc_buf);
+                while (arc_slot < most) arc_slot *= 2;
                 continue;
             }
+            const int64_t A = ctx->h_counters[0];
+            int2 *arcs = ctx->alloc<int2>(A + 1);
+            if (A > 0)
+                GSS_LAUNCH(k_jp_pack, dim3(JP_PARTS), dim3(64), 0, st, arc_buf, arc_cnt, arc_off, arc_slot, arcs);
+            ctx->free(arc_buf);
             res.arcs = A;
             HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
             GSS_LAUNCH(k_state_init, dim3(grid_for(nglobal_edges, RB)), dim3(RB), 0, st, nglobal_edges, B.glist,
@@ -1154,7 +1312,10 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             ctx->free(arcs);
             break;
         }
-        ctx->free(tab);
+        ctx->free(jhist);
+        ctx->free(recs);
+        ctx->free(arc_cnt);
+        ctx->free(arc_off);
     }
     // candidates per graph (ranks among the recovered edges)
     B.candq = ctx->alloc<int32_t>(P + 2);

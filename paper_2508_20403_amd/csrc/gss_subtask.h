@@ -13,6 +13,7 @@ struct SubtaskArgs {
     const int32_t *queue;         // subtask ids in work order
     int32_t nqueue;               // subtasks in the queue
     int32_t local_max;            // size limit of queued subtasks (<= GSS_LOCAL_CAP)
+    int32_t chunk;                // queue entries taken per atomic on the head
     unsigned int *queue_head;     // atomic pop counter
     const int32_t *ancU, *ancV;   // [(c+1) * P] ancestor chains per rank
     const int32_t *rdu, *rdv;     // depths of the endpoints per rank

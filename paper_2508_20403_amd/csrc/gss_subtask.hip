@@ -97,48 +97,53 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
     Desc<C> *cand = (Desc<C> *)a.cand_scratch + gw * a.local_max;
+    // queue entries are taken `chunk` at a time, so the shared head sees one atomic per
+    // chunk rather than one per subtask
     for (;;) {
-        int32_t qi = 0;
-        if (lane == 0) qi = (int32_t)atomicAdd(a.queue_head, 1u);
-        qi = __shfl(qi, 0, GSS_WAVE);
-        if (qi >= a.nqueue) break;
-        const int32_t s = a.queue[qi];
-        const uint64_t t0 = clock64();
-        const int32_t g0 = a.sub_ptr[s], g1 = a.sub_ptr[s + 1];
-        int32_t ncand = 0;
-        for (int32_t c0 = g0; c0 < g1; c0 += GSS_WAVE) {
-            const int32_t gi = c0 + lane;
-            const bool valid = gi < g1;
-            const int32_t p = valid ? a.grp[gi] : 0;
-            Desc<C> me;
-            if (valid) load_desc<C>(me, a.P, p, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
-            // against candidates of earlier chunks
-            bool marked = false;
-            for (int32_t k = 0; k < ncand; k++) {
-                const Desc<C> m = cand[k];
-                marked |= valid && strictly_similar<C>(me, m);
+        int32_t q0 = 0;
+        if (lane == 0) q0 = (int32_t)atomicAdd(a.queue_head, (unsigned)a.chunk);
+        q0 = __shfl(q0, 0, GSS_WAVE);
+        if (q0 >= a.nqueue) break;
+        const int32_t q1 = (q0 + a.chunk < a.nqueue) ? q0 + a.chunk : a.nqueue;
+        for (int32_t qi = q0; qi < q1; qi++) {
+            const int32_t s = a.queue[qi];
+            const uint64_t t0 = clock64();
+            const int32_t g0 = a.sub_ptr[s], g1 = a.sub_ptr[s + 1];
+            int32_t ncand = 0;
+            for (int32_t c0 = g0; c0 < g1; c0 += GSS_WAVE) {
+                const int32_t gi = c0 + lane;
+                const bool valid = gi < g1;
+                const int32_t p = valid ? a.grp[gi] : 0;
+                Desc<C> me;
+                if (valid) load_desc<C>(me, a.P, p, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+                // against candidates of earlier chunks
+                bool marked = false;
+                for (int32_t k = 0; k < ncand; k++) {
+                    const Desc<C> m = cand[k];
+                    marked |= valid && strictly_similar<C>(me, m);
+                }
+                // in-chunk greedy in rank order
+                uint64_t pending = __ballot(valid && !marked);
+                uint64_t recovered = 0;
+                while (pending) {
+                    const int i = __ffsll((long long)pending) - 1;
+                    Desc<C> m = shfl_desc<C>(me, i);
+                    const bool hit = valid && lane > i && strictly_similar<C>(me, m);
+                    const uint64_t hits = __ballot(hit);
+                    recovered |= 1ull << i;
+                    pending &= ~((1ull << i) | hits);
+                }
+                const bool is_cand = (recovered >> lane) & 1ull;
+                if (valid) a.state[p] = is_cand ? ST_CAND_ : ST_MARK_;
+                // append this chunk's candidates (rank order) to the candidate list
+                const int before = __popcll(recovered & lanemask_lt());
+                if (is_cand && ncand + before < a.local_max) cand[ncand + before] = me;
+                ncand += __popcll(recovered);
+                __threadfence_block();
             }
-            // in-chunk greedy in rank order
-            uint64_t pending = __ballot(valid && !marked);
-            uint64_t recovered = 0;
-            while (pending) {
-                const int i = __ffsll((long long)pending) - 1;
-                Desc<C> m = shfl_desc<C>(me, i);
-                const bool hit = valid && lane > i && strictly_similar<C>(me, m);
-                const uint64_t hits = __ballot(hit);
-                recovered |= 1ull << i;
-                pending &= ~((1ull << i) | hits);
-            }
-            const bool is_cand = (recovered >> lane) & 1ull;
-            if (valid) a.state[p] = is_cand ? ST_CAND_ : ST_MARK_;
-            // append this chunk's candidates (rank order) to the candidate list
-            const int before = __popcll(recovered & lanemask_lt());
-            if (is_cand && ncand + before < a.local_max) cand[ncand + before] = me;
-            ncand += __popcll(recovered);
-            __threadfence_block();
+            const uint64_t t1 = clock64();
+            if (lane == 0 && a.cycles) a.cycles[s] = t1 - t0;
         }
-        const uint64_t t1 = clock64();
-        if (lane == 0 && a.cycles) a.cycles[s] = t1 - t0;
     }
 }
 
@@ -193,35 +198,47 @@ __global__ void k_group_ptr(int64_t P, const uint64_t *__restrict__ glca, const 
 __global__ void k_group_end(int32_t nsub, int64_t P, int32_t *__restrict__ sub_ptr) { sub_ptr[nsub] = (int32_t)P; }
 
 // per subtask: queue key (descending cost first) and the local/global split
-__global__ void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr, int32_t local_max,
-                               const float *__restrict__ pred, uint64_t *__restrict__ qkey,
-                               int32_t *__restrict__ qval, int32_t *__restrict__ is_local,
-                               int32_t *__restrict__ nlocal, unsigned long long *__restrict__ nglobal_edges)
+__global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr,
+                                                      int32_t local_max, const float *__restrict__ pred,
+                                                      uint64_t *__restrict__ qkey, int32_t *__restrict__ qval,
+                                                      int32_t *__restrict__ is_local, int32_t *__restrict__ nlocal,
+                                                      unsigned long long *__restrict__ nglobal_edges)
 {
-    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    // edges on the global path, one atomic per wave
-    {
-        int32_t ge = 0;
-        if (s < nsub) {
-            int32_t sz = sub_ptr[s + 1] - sub_ptr[s];
-            if (sz > local_max) ge = sz;
-        }
-        unsigned long long tot = (unsigned long long)ge;
-        for (int d = 32; d > 0; d >>= 1) tot += __shfl_xor(tot, d, GSS_WAVE);
-        if (lane_id() == 0 && tot) atomicAdd(nglobal_edges, tot);
+    __shared__ unsigned long long s_ge[256 / GSS_WAVE];
+    __shared__ int32_t s_nl[256 / GSS_WAVE];
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t size = 0;
+    if (s < nsub) size = sub_ptr[s + 1] - sub_ptr[s];
+    const bool loc = s < nsub && size <= local_max;
+    if (s < nsub) {
+        is_local[s] = loc ? 1 : 0;
+        uint64_t cost;
+        if (pred) cost = (uint64_t)__float_as_uint(fmaxf(pred[s], 0.f));  // non-negative floats order as ints
+        else cost = (uint64_t)size;
+        // ascending sort of this key = local subtasks first, by cost descending, then id
+        qkey[s] = ((uint64_t)(loc ? 0 : 1) << 63) | ((~cost) & 0x7fffffffffffffffull);
+        qval[s] = s;
     }
-    if (s >= nsub) return;
-    int32_t size = sub_ptr[s + 1] - sub_ptr[s];
-    bool loc = size <= local_max;
-    is_local[s] = loc ? 1 : 0;
-    uint64_t cost;
-    if (pred) cost = (uint64_t)__float_as_uint(fmaxf(pred[s], 0.f));  // non-negative floats order as ints
-    else cost = (uint64_t)size;
-    // ascending sort of this key = local subtasks first, by cost descending, then id
-    qkey[s] = ((uint64_t)(loc ? 0 : 1) << 63) | ((~cost) & 0x7fffffffffffffffull);
-    qval[s] = s;
-    uint64_t lm = __ballot(loc);
-    if (lane_id() == __ffsll((long long)__ballot(true)) - 1 && lm) atomicAdd(nlocal, (int32_t)__popcll(lm));
+    // edges on the join path and local subtasks: one atomic per workgroup each
+    unsigned long long ge = (s < nsub && !loc) ? (unsigned long long)size : 0ull;
+    int32_t nl = loc ? 1 : 0;
+    for (int d = 32; d > 0; d >>= 1) {
+        ge += __shfl_xor(ge, d, GSS_WAVE);
+        nl += __shfl_xor(nl, d, GSS_WAVE);
+    }
+    if (lane_id() == 0) {
+        s_ge[threadIdx.x / GSS_WAVE] = ge;
+        s_nl[threadIdx.x / GSS_WAVE] = nl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / GSS_WAVE; w++) {
+            ge += s_ge[w];
+            nl += s_nl[w];
+        }
+        if (ge) atomicAdd(nglobal_edges, ge);
+        if (nl) atomicAdd(nlocal, nl);
+    }
 }
 
 // global-path flag per rank (edges of subtasks above the local limit)
