@@ -76,10 +76,16 @@ __global__ void k_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int6
     for (int64_t b = (lo + ETILE - 1) / ETILE; b <= b1 && b < ntiles; b++) tile_row[b] = (int32_t)x;
 }
 
-// fills srow[k - base] = row of entry k for tile b (rows r0 .. r1 from the tile table)
+// fills srow[k - base] = row of entry k for the tile starting at base: every row that
+// starts inside the tile marks its first entry (LDS max, so the last of several empty
+// rows wins), then an inclusive prefix maximum over the tile carries each row to its
+// entries.  The work is independent of row lengths (a hub row spanning many tiles costs
+// the same as short rows).
 __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
                                                int64_t base, const int32_t *__restrict__ tile_row, int32_t *srow)
 {
+    constexpr int PER = ETILE / PB;
+    __shared__ int32_t s_tmax[PB / GSS_WAVE];
     const int64_t b = base / ETILE;
     const int64_t ntiles = (nnz + ETILE - 1) / ETILE;
     int32_t r0 = tile_row[b];
@@ -88,11 +94,33 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
     r1 = r1 < r0 ? r0 : (r1 > n - 1 ? n - 1 : r1);
     for (int i = threadIdx.x; i < ETILE; i += PB) srow[i] = r0;
     __syncthreads();
-    const int64_t end = base + ETILE < nnz ? base + ETILE : nnz;
-    for (int32_t r = r0 + threadIdx.x; r <= r1; r += PB) {
-        int64_t lo = clamp_idx(row_ptr[r], base, end), hi = clamp_idx(row_ptr[r + 1], base, end);
-        for (int64_t k = lo; k < hi; k++) srow[k - base] = r;
+    for (int32_t r = r0 + 1 + threadIdx.x; r <= r1; r += PB) {
+        const int64_t k = row_ptr[r];
+        if (k >= base && k < base + ETILE) atomicMax(&srow[k - base], r);
     }
+    __syncthreads();
+    // inclusive prefix maximum: thread t owns entries [PER t, PER t + PER)
+    int32_t v[PER];
+    int32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        v[i] = srow[threadIdx.x * PER + i];
+        run = v[i] > run ? v[i] : run;
+        v[i] = run;
+    }
+    int32_t x = run;  // inclusive max across threads, then shifted to exclusive
+#pragma unroll
+    for (int d = 1; d < GSS_WAVE; d <<= 1) {
+        const int32_t y = __shfl_up(x, d, GSS_WAVE);
+        if (lane_id() >= d) x = y > x ? y : x;
+    }
+    if (lane_id() == GSS_WAVE - 1) s_tmax[threadIdx.x / GSS_WAVE] = x;
+    int32_t ex = __shfl_up(x, 1, GSS_WAVE);
+    if (lane_id() == 0) ex = r0;
+    __syncthreads();
+    for (int w = 0; w < (int)(threadIdx.x / GSS_WAVE); w++) ex = s_tmax[w] > ex ? s_tmax[w] : ex;
+#pragma unroll
+    for (int i = 0; i < PER; i++) srow[threadIdx.x * PER + i] = v[i] > ex ? v[i] : ex;
     __syncthreads();
 }
 
