@@ -34,7 +34,6 @@
 #define RB 256
 #define SEL_BITS 12
 #define SEL_BINS (1 << SEL_BITS)
-#define CHUNK 16
 
 enum : uint8_t { ST_UNDEC = 0, ST_CAND = 1, ST_MARK = 2 };
 
@@ -333,50 +332,86 @@ __global__ __launch_bounds__(1024) void k_pick_bucket(const uint32_t *__restrict
 // ------------------------------------------------------------------------------------
 // 3. compaction of {key >= T[graph]} (id order, hence graph-major) and the radix sort
 // ------------------------------------------------------------------------------------
-__global__ void k_prefix_count(const uint64_t *__restrict__ key, int64_t M, const int32_t *__restrict__ off_g,
-                               const uint64_t *__restrict__ thr, int32_t *__restrict__ cnt,
-                               unsigned long long *__restrict__ gcount)
+// Prefix compaction {key >= thr[graph]}, in id order.  A tile of PX_TILE keys is read
+// round-major (key base + i*256 + t), so every load is coalesced; the counting pass
+// stores one count per tile, the writing pass keeps (round, wave, lane) = id order.
+#define PX_ITEMS 16
+#define PX_TILE (256 * PX_ITEMS)
+__global__ __launch_bounds__(256) void k_prefix_count(const uint64_t *__restrict__ key, int64_t M,
+                                                      const int32_t *__restrict__ off_g,
+                                                      const uint64_t *__restrict__ thr, int32_t *__restrict__ cnt,
+                                                      unsigned long long *__restrict__ gcount)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t j0 = t * CHUNK;
-    if (j0 >= M) return;
-    int32_t c = 0;
-    int32_t gcur = -1, gc = 0;
-    for (int i = 0; i < CHUNK; i++) {
-        int64_t j = j0 + i;
-        if (j >= M) break;
-        int32_t g = off_g ? off_g[j] : 0;
-        if (key[j] >= thr[g]) {
+    __shared__ int32_t s_c[256 / GSS_WAVE];
+    const int64_t base = (int64_t)blockIdx.x * PX_TILE;
+    uint64_t kv[PX_ITEMS];
+    int32_t gv[PX_ITEMS];
+#pragma unroll
+    for (int i = 0; i < PX_ITEMS; i++) {
+        const int64_t j = base + (int64_t)i * 256 + threadIdx.x;
+        kv[i] = j < M ? key[j] : 0;
+        gv[i] = (off_g && j < M) ? off_g[j] : 0;
+    }
+    int32_t c = 0, gcur = -1, gc = 0;
+#pragma unroll
+    for (int i = 0; i < PX_ITEMS; i++) {
+        const int64_t j = base + (int64_t)i * 256 + threadIdx.x;
+        if (j < M && kv[i] >= thr[gv[i]]) {
             c++;
-            if (off_g && g != gcur) {
+            // a thread's keys are 256 ids apart: runs of one graph are long in batches
+            if (off_g && gv[i] != gcur) {
                 if (gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
-                gcur = g;
+                gcur = gv[i];
                 gc = 0;
             }
             gc++;
         }
     }
     if (off_g && gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
-    cnt[t] = c;
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, GSS_WAVE);
+    if (lane_id() == 0) s_c[threadIdx.x / GSS_WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / GSS_WAVE; w++) c += s_c[w];
+        cnt[blockIdx.x] = c;
+    }
 }
-
-__global__ void k_prefix_write(const uint64_t *__restrict__ key, int64_t M, const int32_t *__restrict__ off_g,
-                               const uint64_t *__restrict__ thr, const int32_t *__restrict__ off,
-                               int32_t *__restrict__ pj, uint64_t *__restrict__ pk)
+__global__ __launch_bounds__(256) void k_prefix_write(const uint64_t *__restrict__ key, int64_t M,
+                                                      const int32_t *__restrict__ off_g,
+                                                      const uint64_t *__restrict__ thr, const int32_t *__restrict__ off,
+                                                      int32_t *__restrict__ pj, uint64_t *__restrict__ pk)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t j0 = t * CHUNK;
-    if (j0 >= M) return;
-    int32_t q = off[t];
-    for (int i = 0; i < CHUNK; i++) {
-        int64_t j = j0 + i;
-        if (j < M) {
-            uint64_t k = key[j];
-            if (k >= thr[off_g ? off_g[j] : 0]) {
-                pj[q] = (int32_t)j;
-                pk[q] = ~k;  // ascending order of ~key = descending stretch
-                q++;
-            }
+    constexpr int NW = 256 / GSS_WAVE;
+    __shared__ int32_t s_w[PX_ITEMS][NW];
+    const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
+    const int64_t base = (int64_t)blockIdx.x * PX_TILE;
+    uint64_t kv[PX_ITEMS];
+    uint64_t keepm[PX_ITEMS];
+#pragma unroll
+    for (int i = 0; i < PX_ITEMS; i++) {
+        const int64_t j = base + (int64_t)i * 256 + threadIdx.x;
+        kv[i] = j < M ? key[j] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < PX_ITEMS; i++) {
+        const int64_t j = base + (int64_t)i * 256 + threadIdx.x;
+        keepm[i] = __ballot(j < M && kv[i] >= thr[off_g ? off_g[j] : 0]);
+        if (lane == 0) s_w[i][wid] = __popcll(keepm[i]);
+    }
+    __syncthreads();
+    int64_t q = off[blockIdx.x];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < PX_ITEMS; i++) {
+        int64_t o = q;
+        for (int w = 0; w < NW; w++) {
+            if (w < wid) o += s_w[i][w];
+            q += s_w[i][w];
+        }
+        if ((keepm[i] >> lane) & 1ull) {
+            o += __popcll(keepm[i] & lt);
+            pj[o] = (int32_t)(base + (int64_t)i * 256 + threadIdx.x);
+            pk[o] = ~kv[i];  // ascending order of ~key = descending stretch
         }
     }
 }
@@ -1106,11 +1141,12 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     PrefixResult res;
     std::vector<void *> scratch;
     // compaction (id order: graph-major)
-    int64_t nthr = (M + CHUNK - 1) / CHUNK;
+    int64_t nthr = (M + PX_TILE - 1) / PX_TILE;  // tiles
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
     unsigned long long *gcount = ctx->alloc<unsigned long long>(G);
     HIP_OK(hipMemsetAsync(gcount, 0, sizeof(unsigned long long) * G, st));
-    GSS_LAUNCH_B(8 * M, k_prefix_count, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, gcount);
+    GSS_LAUNCH_B(8 * M, k_prefix_count, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M, off_g,
+                 thr, pc, gcount);
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
     res.Pg.assign(G, 0);
@@ -1122,7 +1158,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     }
     uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
-    GSS_LAUNCH_B(8 * M + 12 * P, k_prefix_write, dim3(grid_for(nthr, RB)), dim3(RB), 0, st, key, M, off_g, thr, pc, v1,
+    GSS_LAUNCH_B(8 * M + 12 * P, k_prefix_write, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M,
+                 off_g, thr, pc, v1,
                  k1);
     ctx->free(pc);
     ctx->free(gcount);
@@ -1209,10 +1246,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     scratch.push_back(is_local);
 
     B.state = ctx->alloc<uint8_t>(P + 1);
-    // ranks of the edges on the join path (the global subtasks sit at the tail of the queue)
+    // ranks of the edges on the join path, in grouped order
     B.glist = ctx->alloc<int32_t>(nglobal_edges + 1);
-    launch_global_list(ctx, (int32_t)(nsub - nlocal), qv + nlocal, B.sub_ptr, B.grp,
-                       (unsigned long long *)(ctx->d_counters + 7), B.glist);
+    if (nsub > nlocal) launch_join_list(ctx, P, glca, hid, is_local, B.grp, B.glist);
 
     // Step 4, small and medium subtasks: persistent work-queue kernel
     uint64_t *cycles = nullptr;

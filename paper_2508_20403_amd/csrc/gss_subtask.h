@@ -30,8 +30,8 @@ void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
                          uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
                          unsigned long long *nglobal_edges);
-void launch_global_list(gss_ctx ctx, int32_t nglob_sub, const int32_t *gsub, const int32_t *sub_ptr,
-                        const int32_t *grp, unsigned long long *count, int32_t *glist);
+void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
+                      const int32_t *grp, int32_t *glist);
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
                              const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
                              const int32_t *ru, const int32_t *rv, const VRec *vrec, const int32_t *lcacnt,

@@ -242,18 +242,27 @@ __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_
 }
 
 // global-path flag per rank (edges of subtasks above the local limit)
-// lists the ranks of the edges in subtasks on the join path (order within the list is
-// immaterial); one workgroup per such subtask, taken from the tail of the sorted queue
-__global__ void k_global_list(const int32_t *__restrict__ gsub, const int32_t *__restrict__ sub_ptr,
-                              const int32_t *__restrict__ grp, unsigned long long *__restrict__ count,
-                              int32_t *__restrict__ glist)
+// Ranks of the edges in subtasks on the join path, in grouped order: a flag per grouped
+// position (its subtask is not on the work queue), a scan, and a write pass.  The
+// subtask of position g is hid[g] (heads scanned exclusively) less one unless g is a head.
+__device__ __forceinline__ bool on_join_path(int64_t g, const uint64_t *__restrict__ glca,
+                                             const int32_t *__restrict__ hid, const int32_t *__restrict__ is_local)
 {
-    __shared__ unsigned long long base;
-    const int32_t s = gsub[blockIdx.x];
-    const int32_t g0 = sub_ptr[s], g1 = sub_ptr[s + 1];
-    if (threadIdx.x == 0) base = atomicAdd(count, (unsigned long long)(g1 - g0));
-    __syncthreads();
-    for (int32_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) glist[base + (g - g0)] = grp[g];
+    const bool head = g == 0 || glca[g] != glca[g - 1];
+    return !is_local[hid[g] - (head ? 0 : 1)];
+}
+__global__ void k_join_flags(int64_t P, const uint64_t *__restrict__ glca, const int32_t *__restrict__ hid,
+                             const int32_t *__restrict__ is_local, int32_t *__restrict__ flag)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P) flag[g] = on_join_path(g, glca, hid, is_local) ? 1 : 0;
+}
+__global__ void k_join_write(int64_t P, const uint64_t *__restrict__ glca, const int32_t *__restrict__ hid,
+                             const int32_t *__restrict__ is_local, const int32_t *__restrict__ pos,
+                             const int32_t *__restrict__ grp, int32_t *__restrict__ glist)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P && on_join_path(g, glca, hid, is_local)) glist[pos[g]] = grp[g];
 }
 
 // 12 features per subtask for the cost model (one wave per subtask)
@@ -333,11 +342,16 @@ void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int3
                qkey, qval, is_local, nlocal, nglobal_edges);
 }
 
-void launch_global_list(gss_ctx ctx, int32_t nglob_sub, const int32_t *gsub, const int32_t *sub_ptr,
-                        const int32_t *grp, unsigned long long *count, int32_t *glist)
+void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
+                      const int32_t *grp, int32_t *glist)
 {
-    if (nglob_sub <= 0) return;
-    GSS_LAUNCH(k_global_list, dim3(nglob_sub), dim3(256), 0, ctx->stream, gsub, sub_ptr, grp, count, glist);
+    if (P <= 0) return;
+    int32_t *flag = ctx->alloc<int32_t>(P + 1);
+    GSS_LAUNCH_B(13 * P, k_join_flags, dim3(grid_for(P, 256)), dim3(256), 0, ctx->stream, P, glca, hid, is_local, flag);
+    scan_exclusive_i32_dev(ctx, flag, P, ctx->d_counters + 7);
+    GSS_LAUNCH_B(21 * P, k_join_write, dim3(grid_for(P, 256)), dim3(256), 0, ctx->stream, P, glca, hid, is_local,
+                 flag, grp, glist);
+    ctx->free(flag);
 }
 
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
