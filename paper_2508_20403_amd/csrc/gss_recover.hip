@@ -454,9 +454,12 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restric
     }
 }
 
-// One pass: tile items are ranked within the tile in (round, thread) order, which is
-// index order; the tile's base for digit d is the global start of d plus the count of d
-// in all earlier tiles (look-back over status[tile][256]).
+// One pass.  Wavefront w of a tile owns the RS_ITEMS * 64 consecutive keys starting at
+// tile offset w * RS_ITEMS * 64 and ranks them round by round (64 consecutive keys per
+// round) with wave-private digit counters, so the only workgroup barriers are around the
+// per-digit totals; tile order = (wave, round, lane) = index order.  The tile's base for
+// digit d is the global start of d plus the count of d in all earlier tiles (look-back
+// over status[tile][256]).
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__restrict__ kin,
                                                           const int32_t *__restrict__ vin, int64_t n, int shift,
                                                           int64_t ntiles, const int32_t *__restrict__ ghist,
@@ -465,74 +468,72 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__rest
                                                           int32_t *__restrict__ vout)
 {
     constexpr int NW = RS_BLOCK / GSS_WAVE;
-    __shared__ int32_t s_run[256];
-    __shared__ int32_t s_wc[NW][256];
-    __shared__ int32_t s_base[256];
+    __shared__ int32_t s_cnt[NW][256];  // per wavefront: digit counts so far
+    __shared__ int32_t s_base[NW][256];  // per wavefront: output base of each digit
     __shared__ int32_t s_scan[NW + 1];
     __shared__ int64_t s_tile;
-    const int t = threadIdx.x, wid = t / GSS_WAVE;
+    const int t = threadIdx.x, wid = t / GSS_WAVE, lane = lane_id();
     if (t == 0) s_tile = lb_ticket(ticket, ntiles);
+#pragma unroll
+    for (int w = 0; w < NW; w++) s_cnt[w][t] = 0;
     int32_t gtot;
     const int32_t gstart = block_exclusive_scan<int32_t>(ghist[t], s_scan, &gtot);  // synchronises
-    s_run[t] = 0;
-#pragma unroll
-    for (int w = 0; w < NW; w++) s_wc[w][t] = 0;
-    __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t base = tile * RS_TILE;
+    const int64_t wbase = tile * RS_TILE + (int64_t)wid * (RS_ITEMS * GSS_WAVE);
     uint64_t kk[RS_ITEMS];
     int32_t vv[RS_ITEMS], pos[RS_ITEMS];
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; i++) {
-        const int64_t idx = base + (int64_t)i * RS_BLOCK + t;
+        const int64_t idx = wbase + i * GSS_WAVE + lane;
         const bool valid = idx < n;
         kk[i] = valid ? kin[idx] : 0;
         vv[i] = valid ? vin[idx] : 0;
     }
+    int32_t *cnt = s_cnt[wid];
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; i++) {
-        const bool valid = base + (int64_t)i * RS_BLOCK + t < n;
+        const bool valid = wbase + i * GSS_WAVE + lane < n;
         const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
-        // lanes of this wave holding the same digit
+        // lanes of this wavefront holding the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
             const uint64_t bb = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        const int rank = __popcll(peers & lanemask_lt());
-        if (valid && rank == 0) s_wc[wid][d] = __popcll(peers);
-        __syncthreads();
-        int32_t o = s_run[d] + rank;
-        for (int w = 0; w < wid; w++) o += s_wc[w][d];
-        pos[i] = o;
-        __syncthreads();
-        int32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < NW; w++) {
-            add += s_wc[w][t];
-            s_wc[w][t] = 0;
+        const int leader = peers ? __ffsll((long long)peers) - 1 : lane;
+        int32_t old = 0;
+        if (valid && lane == leader) {
+            old = cnt[d];
+            cnt[d] = old + __popcll(peers);
         }
-        s_run[t] += add;
-        __syncthreads();
+        old = __shfl(old, leader, GSS_WAVE);
+        pos[i] = old + __popcll(peers & lanemask_lt());
     }
-    // thread t publishes and resolves digit t
-    const int32_t cnt = s_run[t];
+    __syncthreads();
+    // thread t resolves digit t: wave offsets inside the tile, then the tile's base
+    int32_t tc = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        s_base[w][t] = tc;
+        tc += s_cnt[w][t];
+    }
     int64_t excl = 0;
     if (tile == 0) {
-        lb_store(status + t, lb_word(LB_INC, epoch, (uint64_t)cnt));
+        lb_store(status + t, lb_word(LB_INC, epoch, (uint64_t)tc));
     } else {
-        lb_store(status + tile * 256 + t, lb_word(LB_AGG, epoch, (uint64_t)cnt));
+        lb_store(status + tile * 256 + t, lb_word(LB_AGG, epoch, (uint64_t)tc));
         excl = lb_lookback_thread<16>(status, 256, t, tile, epoch);
-        lb_store(status + tile * 256 + t, lb_word(LB_INC, epoch, (uint64_t)(excl + cnt)));
+        lb_store(status + tile * 256 + t, lb_word(LB_INC, epoch, (uint64_t)(excl + tc)));
     }
-    s_base[t] = gstart + (int32_t)excl;
+#pragma unroll
+    for (int w = 0; w < NW; w++) s_base[w][t] += gstart + (int32_t)excl;
     __syncthreads();
+    const int32_t *base = s_base[wid];
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; i++) {
-        const bool valid = base + (int64_t)i * RS_BLOCK + t < n;
-        if (valid) {
-            const int32_t o = s_base[(uint32_t)(kk[i] >> shift) & 255u] + pos[i];
+        if (wbase + i * GSS_WAVE + lane < n) {
+            const int32_t o = base[(uint32_t)(kk[i] >> shift) & 255u] + pos[i];
             kout[o] = kk[i];
             vout[o] = vv[i];
         }
@@ -1072,8 +1073,12 @@ static void read_counters(gss_ctx ctx, int nwords)
     ctx->sync();
 }
 
-// stable LSD radix sort of (key, val) pairs by key ascending, only over varying digits
-static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n)
+// Stable LSD radix sort of (key, val) pairs by key ascending.  With key_bytes = 0 the
+// digit histograms are read back and only varying digits are sorted; with key_bytes > 0
+// (keys known to be below 2^(8 key_bytes)) every low digit is sorted and the host never
+// waits for the device.
+static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n,
+                             int key_bytes = 0)
 {
     if (n <= 1) return;
     hipStream_t st = ctx->stream;
@@ -1082,23 +1087,38 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     HIP_OK(hipMemsetAsync(ghist, 0, sizeof(int32_t) * 8 * 256, st));
     GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n,
                  ghist);
-    std::vector<int32_t> h(8 * 256);
-    HIP_OK(hipMemcpyAsync(h.data(), ghist, sizeof(int32_t) * 8 * 256, hipMemcpyDeviceToHost, st));
-    ctx->sync();
+    bool run[8];
+    if (key_bytes > 0) {
+        for (int p = 0; p < 8; p++) run[p] = p < key_bytes;
+    } else {
+        std::vector<int32_t> h(8 * 256);
+        HIP_OK(hipMemcpyAsync(h.data(), ghist, sizeof(int32_t) * 8 * 256, hipMemcpyDeviceToHost, st));
+        ctx->sync();
+        for (int p = 0; p < 8; p++) {
+            // a byte position is constant when one digit holds every key
+            bool constant = false;
+            for (int d = 0; d < 256; d++) constant |= (h[p * 256 + d] == n);
+            run[p] = !constant;
+        }
+    }
     for (int p = 0; p < 8; p++) {
-        // a byte position is constant when one digit holds every key
-        bool constant = false;
-        for (int d = 0; d < 256; d++) constant |= (h[p * 256 + d] == n);
-        if (constant) continue;
+        if (!run[p]) continue;
         uint32_t epoch = 0;
         uint64_t *status = lb_begin(ctx, ntiles * 256, &epoch);
         GSS_LAUNCH_B(24 * n, k_rs_onesweep, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, k, v, n, 8 * p, ntiles,
-                   ghist + p * 256, status, epoch, lb_ticket_ptr(ctx), k2, v2);
+                     ghist + p * 256, status, epoch, lb_ticket_ptr(ctx), k2, v2);
         HIP_OK(hipGetLastError());
         std::swap(k, k2);
         std::swap(v, v2);
     }
     ctx->free(ghist);
+}
+
+static int bytes_for(uint64_t maxkey)
+{
+    int b = 1;
+    while (b < 8 && (maxkey >> (8 * b)) != 0) b++;
+    return b;
 }
 
 struct PrefixResult {
@@ -1197,7 +1217,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
 
     // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA.  LCAs
     // of different graphs of a batch are different vertices, so subtasks never mix graphs.
-    radix_sort_pairs(ctx, lkey, lval, lkey2, lval2, P);
+    radix_sort_pairs(ctx, lkey, lval, lkey2, lval2, P, bytes_for((uint64_t)(t->n - 1)));  // LCA < n
     B.grp = lval;
     scratch.push_back(lkey2);
     scratch.push_back(lval2);
@@ -1231,9 +1251,14 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     int32_t *qv = ctx->alloc<int32_t>(nsub + 1), *qv2 = ctx->alloc<int32_t>(nsub + 1);
     int32_t *is_local = ctx->alloc<int32_t>(nsub + 1);
     HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(int64_t), st));
-    launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, qk, qv, is_local,
+    // queue keys: cost in the low cost_bits (sizes are at most P; predicted costs are float
+    // bits), the on-join-path flag above them
+    int cost_bits = 1;
+    while (cost_bits < 31 && ((int64_t)1 << cost_bits) <= P) cost_bits++;
+    if (pred) cost_bits = 32;
+    launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
                         (int32_t *)(ctx->d_counters + 4), (unsigned long long *)(ctx->d_counters + 6));
-    radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub);
+    radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub, bytes_for(((uint64_t)2 << cost_bits) - 1));
     read_counters(ctx, 7);
     const int32_t nlocal = (int32_t)ctx->h_counters[4];
     const int64_t nglobal_edges = ctx->h_counters[6];

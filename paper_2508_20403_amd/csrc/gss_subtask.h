@@ -28,7 +28,7 @@ void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32
 void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, int32_t *sub_ptr,
                       int32_t *sub_lca, int32_t nsub);
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
-                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
+                         int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
                          unsigned long long *nglobal_edges);
 void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
                       const int32_t *grp, int32_t *glist);

@@ -200,7 +200,8 @@ __global__ void k_group_end(int32_t nsub, int64_t P, int32_t *__restrict__ sub_p
 // per subtask: queue key (descending cost first) and the local/global split
 __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr,
                                                       int32_t local_max, const float *__restrict__ pred,
-                                                      uint64_t *__restrict__ qkey, int32_t *__restrict__ qval,
+                                                      int cost_bits, uint64_t *__restrict__ qkey,
+                                                      int32_t *__restrict__ qval,
                                                       int32_t *__restrict__ is_local, int32_t *__restrict__ nlocal,
                                                       unsigned long long *__restrict__ nglobal_edges)
 {
@@ -216,7 +217,9 @@ __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_
         if (pred) cost = (uint64_t)__float_as_uint(fmaxf(pred[s], 0.f));  // non-negative floats order as ints
         else cost = (uint64_t)size;
         // ascending sort of this key = local subtasks first, by cost descending, then id
-        qkey[s] = ((uint64_t)(loc ? 0 : 1) << 63) | ((~cost) & 0x7fffffffffffffffull);
+        // (a stable sort of ids in order); cost < 2^cost_bits
+        const uint64_t cmask = ((uint64_t)1 << cost_bits) - 1;
+        qkey[s] = ((uint64_t)(loc ? 0 : 1) << cost_bits) | ((~cost) & cmask);
         qval[s] = s;
     }
     // edges on the join path and local subtasks: one atomic per workgroup each
@@ -335,11 +338,11 @@ void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
 }
 
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
-                         uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
+                         int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
                          unsigned long long *nglobal_edges)
 {
     GSS_LAUNCH(k_subtask_keys, dim3(grid_for(nsub, 256)), dim3(256), 0, ctx->stream, nsub, sub_ptr, local_max, pred,
-               qkey, qval, is_local, nlocal, nglobal_edges);
+               cost_bits, qkey, qval, is_local, nlocal, nglobal_edges);
 }
 
 void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,

@@ -54,3 +54,24 @@ def test_full_size_matches_oracle(gpu_ctx, name):
     _, _, _, _, info2 = tree.recover(g.alpha, g.beta, stats=True)
     assert (info2["n_subtasks"], info2["largest_subtask"]) == (ref["n_subtasks"], ref["largest_subtask"])
     tree.free()
+
+
+def test_full_batch_matches_oracle(gpu_ctx):
+    """The 64-graph random geometric batch in one batched call: every graph's mask and
+    order hash to the oracle's digests."""
+    if "rgg64" not in GOLD:
+        pytest.skip("no stored oracle result for the batch")
+    ref = GOLD["rgg64"]["graphs"]
+    print("[full] generating the 64-graph batch", flush=True)
+    graphs = synth.batch_config()
+    assert [(g.n, g.m) for g in graphs] == [(r["n"], r["m"]) for r in ref]
+    print("[full] batch: GPU recovery", flush=True)
+    b = gss.Batch(gpu_ctx, graphs)
+    st, masks, orders, infos = b.recover()
+    torch.cuda.synchronize()
+    for i, (r, info) in enumerate(zip(ref, infos)):
+        nrec = info["n_recovered"]
+        assert (info["k"], nrec, info["passes"]) == (r["k"], r["n_recovered"], r["passes"]), i
+        assert sha(orders[i].cpu().numpy()[:nrec], "<i4") == r["order_sha256"], i
+        assert sha(masks[i].cpu().numpy()[:r["m"]], np.uint8) == r["mask_sha256"], i
+    b.free()
