@@ -178,11 +178,16 @@ int64_t gss_tree_num_edges(gss_tree tree);
  * The recovery groups the resolved prefix of the criticality order into LCA subtasks
  * (paper: Lemma "strictly similar edges share their LCA", Alg. 1 Step 3).  Subtasks of at
  * most local_max edges are drained by a persistent work-queue kernel, one wavefront per
- * subtask; larger ones use a global hash join.  The queue runs longest-predicted first:
- * by edge count (GSS_SCHED_EDGECOUNT), or by a 12-64-64-1 ReLU network of 12 subtask
- * features (GSS_SCHED_LEARNED, BF16 matrix-core inference).  The order never changes the
- * output.  Weights are GSS_COSTMODEL_FLOATS floats: W1[64][12] b1[64] W2[64][64] b2[64]
- * W3[64] b3, then the feature mean[12] and standard deviation[12]. */
+ * subtask; larger ones use a partitioned join on ancestor pairs.  The queue runs
+ * longest-predicted first: by edge count (GSS_SCHED_EDGECOUNT), or by a 12-64-64-1 ReLU
+ * network of 12 subtask features (GSS_SCHED_LEARNED, BF16 matrix-core inference).  The
+ * order never changes the output.  Features of a subtask of S edges with LCA l:
+ * log2(1+S); mean and max tree-path hop length d(u)+d(v)-2d(l); mean beta*; share of
+ * beta* = 0; mean and max tree degree of the endpoints; log2(1+deg_T(l)); log2(1+d(l));
+ * S / (resolved prefix length); log2(1 + total path length); log2(1+S^2).  The target is
+ * log2 of the cycles the work-queue kernel spent on the subtask.  Weights are
+ * GSS_COSTMODEL_FLOATS floats: W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3, then the
+ * feature mean[12] and standard deviation[12]. */
 #define GSS_NFEAT 12
 #define GSS_COSTMODEL_FLOATS 5081
 #define GSS_COSTMODEL_PARAMS 5057

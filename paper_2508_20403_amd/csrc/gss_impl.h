@@ -136,6 +136,7 @@ struct gss_tree_s {
     std::vector<int64_t> ebase;          // [G+1] first union edge id of each graph
     std::vector<int64_t> Mg;             // [G] off-tree edges of each graph
     std::vector<int64_t> obase;          // [G+1] first off-tree index of each graph
+    int64_t *d_obase = nullptr;          // device copy (batches only)
     // union arrays owned by a batch tree
     int32_t *own_row_ptr = nullptr, *own_col = nullptr, *own_parent = nullptr;
     double *own_w = nullptr;

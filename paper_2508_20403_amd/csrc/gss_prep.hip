@@ -18,7 +18,8 @@
 
 #define PB 256          // default block size
 #define ENT_ITEMS 16    // CSR entries per thread in entry-parallel kernels
-#define RULE_RATE 4     // one ruler per ~4 list elements (power of two)
+#define RULE_RATE0 4    // level 0 of the list ranking: one ruler per ~RULE_RATE0 arcs (power of two)
+#define RULE_RATE 4     // upper levels: one ruler per ~RULE_RATE elements (power of two)
 #define BASE_MAX 4096   // lists this short are ranked by one workgroup
 #define BASE_THREADS 1024
 
@@ -506,7 +507,7 @@ __device__ __forceinline__ LVal lv_zero()
 __device__ __forceinline__ bool is_ruler(int32_t i, int32_t head, int32_t level)
 {
     return i == head || (mix32((uint32_t)i * 0x9E3779B9u + (uint32_t)level * 0x7F4A7C15u) &
-                         (RULE_RATE - 1)) == 0;
+                         ((level == 0 ? RULE_RATE0 : RULE_RATE) - 1)) == 0;
 }
 
 // level-0 element value: arc i of vertex x = i>>1
@@ -801,9 +802,10 @@ __global__ void k_level_init(int64_t N0, const int64_t *__restrict__ head0, int 
     }
 }
 
-static inline int64_t next_cap(int64_t cap, int mult)
+static inline int64_t next_cap(int64_t cap, int mult, int level)
 {
-    return cap * mult * 21 / (RULE_RATE * 16) + 256;  // 1.3125x the expected ruler count
+    const int64_t rate = level == 0 ? RULE_RATE0 : RULE_RATE;
+    return cap * mult * 21 / (rate * 16) + 256;  // 1.3125x the expected ruler count
 }
 
 // Ranks the Euler tour (succ over N = 2n arcs, head arc in *d_head) and emits vrec / epk.
@@ -839,7 +841,7 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
         if (l + 1 >= max_levels) throw gss_error{GSS_ERR_HIP, "list ranking: too many levels"};
         Lv &a = lv.back();
         const int64_t cap = a.cap;
-        const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult), cap);
+        const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult, l), cap);
         int32_t *rid = ctx->alloc<int32_t>(cap + 1);
         a.owner = ctx->alloc<int32_t>(cap + 1);
         a.loc = ctx->alloc<LVal>(cap + 1);
@@ -1182,7 +1184,7 @@ void free_tree_arrays(gss_tree t)
     void *ptrs[] = {t->uptr,   t->ufirst, t->tpos,   t->tree_eid, t->vrec,       t->epk,    t->pmask,
                     t->ppre,   t->psuf,   t->bmin,   t->bmask,    t->bpre,       t->bsuf,   t->sbst,
                     t->off_id, t->off_u,  t->off_v,  t->off_w,    t->off_g,      t->d_vbase, t->own_row_ptr,
-                    t->own_col, t->own_parent, t->own_w};
+                    t->own_col, t->own_parent, t->own_w, t->d_obase};
     for (void *p : ptrs) c->free(p);
 }
 
@@ -1524,4 +1526,7 @@ void prep_batch(gss_ctx ctx, gss_tree t, int32_t G, const gss_csr *gs, const int
         t->Mg[g] = (t->ebase[g + 1] - t->ebase[g]) - (gs[g].n - 1);
         t->obase[g + 1] = t->obase[g] + t->Mg[g];
     }
+    t->d_obase = ctx->alloc<int64_t>(G + 1);
+    HIP_OK(hipMemcpyAsync(t->d_obase, t->obase.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+    ctx->sync();  // the host vector is the copy's source
 }

@@ -126,6 +126,7 @@ __device__ __forceinline__ uint64_t rmq(const RmqView &q, int32_t i, int32_t j)
 // 1. per-edge LCA / resistance / stretch / beta*
 // ------------------------------------------------------------------------------------
 #define EDGE_ITEMS 2
+#define EDGE_GRID 2048  // workgroups of the grid-stride per-edge kernel
 __global__ __launch_bounds__(RB) void k_edge_stretch(
     int64_t M, const int32_t *__restrict__ off_id, const int32_t *__restrict__ off_u,
     const int32_t *__restrict__ off_v, const double *__restrict__ off_w,
@@ -138,79 +139,84 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
         for (int i = threadIdx.x; i < SEL_BINS; i += RB) sh[i] = 0;
         __syncthreads();
     }
-    const int64_t base = (int64_t)blockIdx.x * RB * EDGE_ITEMS + threadIdx.x;
-    int64_t jj[EDGE_ITEMS];
-    bool ok[EDGE_ITEMS];
-    int32_t u[EDGE_ITEMS], v[EDGE_ITEMS];
-    double w[EDGE_ITEMS];
-#pragma unroll
-    for (int t = 0; t < EDGE_ITEMS; t++) {
-        jj[t] = base + (int64_t)t * RB;
-        ok[t] = jj[t] < M;
-        int64_t j = ok[t] ? jj[t] : 0;
-        u[t] = off_u[j];
-        v[t] = off_v[j];
-        w[t] = off_w[j];
-    }
-    VRec ru[EDGE_ITEMS], rv[EDGE_ITEMS];
-#pragma unroll
-    for (int t = 0; t < EDGE_ITEMS; t++) {
-        ru[t] = vrec[u[t]];
-        rv[t] = vrec[v[t]];
-    }
-    RmqPlan pl[EDGE_ITEMS];
-    RmqLoads ld[EDGE_ITEMS];
-#pragma unroll
-    for (int t = 0; t < EDGE_ITEMS; t++) {
-        int32_t fu = ru[t].first, fv = rv[t].first;
-        pl[t] = rmq_plan(q, min(fu, fv), max(fu, fv));
-        ld[t] = rmq_issue(q, pl[t]);
-    }
-    uint64_t pk[EDGE_ITEMS];
-#pragma unroll
-    for (int t = 0; t < EDGE_ITEMS; t++) pk[t] = rmq_finish(q, pl[t], ld[t]);
-    u128 Dl[EDGE_ITEMS];
-#pragma unroll
-    for (int t = 0; t < EDGE_ITEMS; t++) Dl[t] = vrec[(int32_t)(uint32_t)pk[t]].D;
-    int32_t lw[EDGE_ITEMS];
-#pragma unroll
-    for (int t = 0; t < EDGE_ITEMS; t++) {
-        lw[t] = -1;
-        if (!ok[t]) continue;
-        const int64_t j = jj[t];
-        const int32_t l = (int32_t)(uint32_t)pk[t];
-        const int32_t dl = (int32_t)(pk[t] >> 32);
-        const int32_t du = ru[t].depth - dl, dv = rv[t].depth - dl;
-        u128 R = add128(sub128(ru[t].D, Dl[t]), sub128(rv[t].D, Dl[t]));
-        double r;
-        bool good = u128_to_double_rne(R, scale, &r);
-        double s = w[t] * r;
-        uint64_t bits = (uint64_t)__double_as_longlong(s);
-        if (!good || ((bits >> 52) & 0x7ff) == 0x7ff) {
-            atomicOr(flags, F_RANGE);
-            bits = 1;
-        }
-        int32_t b = du < dv ? du : dv;
-        if (c < b) b = c;
-        key[j] = bits;
-        lca[j] = l;
-        bst[j] = (uint8_t)b;
-        if (stretch_out) stretch_out[off_id[j]] = s;
-        if (hist) atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
-        lw[t] = l;
-    }
-    // subtask sizes (only when asked for): lanes sharing the first lane's LCA add once
-    if (lcacnt) {
+    // grid-stride over tiles of RB * EDGE_ITEMS edges, so the histogram is flushed once
+    // per workgroup rather than once per tile
+    const int64_t ntiles = (M + RB * EDGE_ITEMS - 1) / (RB * EDGE_ITEMS);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t base = tile * RB * EDGE_ITEMS + threadIdx.x;
+        int64_t jj[EDGE_ITEMS];
+        bool ok[EDGE_ITEMS];
+        int32_t u[EDGE_ITEMS], v[EDGE_ITEMS];
+        double w[EDGE_ITEMS];
 #pragma unroll
         for (int t = 0; t < EDGE_ITEMS; t++) {
-            const int32_t l = lw[t];
-            uint64_t active = __ballot(l >= 0);
-            if (active) {
-                int leader = ctz64(active);
-                int32_t lv = __shfl(l, leader, GSS_WAVE);
-                uint64_t same = __ballot(l == lv) & active;
-                if (lane_id() == leader) atomicAdd(&lcacnt[lv], __popcll(same));
-                else if (l >= 0 && l != lv) atomicAdd(&lcacnt[l], 1);
+            jj[t] = base + (int64_t)t * RB;
+            ok[t] = jj[t] < M;
+            int64_t j = ok[t] ? jj[t] : 0;
+            u[t] = off_u[j];
+            v[t] = off_v[j];
+            w[t] = off_w[j];
+        }
+        VRec ru[EDGE_ITEMS], rv[EDGE_ITEMS];
+#pragma unroll
+        for (int t = 0; t < EDGE_ITEMS; t++) {
+            ru[t] = vrec[u[t]];
+            rv[t] = vrec[v[t]];
+        }
+        RmqPlan pl[EDGE_ITEMS];
+        RmqLoads ld[EDGE_ITEMS];
+#pragma unroll
+        for (int t = 0; t < EDGE_ITEMS; t++) {
+            int32_t fu = ru[t].first, fv = rv[t].first;
+            pl[t] = rmq_plan(q, min(fu, fv), max(fu, fv));
+            ld[t] = rmq_issue(q, pl[t]);
+        }
+        uint64_t pk[EDGE_ITEMS];
+#pragma unroll
+        for (int t = 0; t < EDGE_ITEMS; t++) pk[t] = rmq_finish(q, pl[t], ld[t]);
+        u128 Dl[EDGE_ITEMS];
+#pragma unroll
+        for (int t = 0; t < EDGE_ITEMS; t++) Dl[t] = vrec[(int32_t)(uint32_t)pk[t]].D;
+        int32_t lw[EDGE_ITEMS];
+#pragma unroll
+        for (int t = 0; t < EDGE_ITEMS; t++) {
+            lw[t] = -1;
+            if (!ok[t]) continue;
+            const int64_t j = jj[t];
+            const int32_t l = (int32_t)(uint32_t)pk[t];
+            const int32_t dl = (int32_t)(pk[t] >> 32);
+            const int32_t du = ru[t].depth - dl, dv = rv[t].depth - dl;
+            u128 R = add128(sub128(ru[t].D, Dl[t]), sub128(rv[t].D, Dl[t]));
+            double r;
+            bool good = u128_to_double_rne(R, scale, &r);
+            double s = w[t] * r;
+            uint64_t bits = (uint64_t)__double_as_longlong(s);
+            if (!good || ((bits >> 52) & 0x7ff) == 0x7ff) {
+                atomicOr(flags, F_RANGE);
+                bits = 1;
+            }
+            int32_t b = du < dv ? du : dv;
+            if (c < b) b = c;
+            key[j] = bits;
+            lca[j] = l;
+            bst[j] = (uint8_t)b;
+            if (stretch_out) stretch_out[off_id[j]] = s;
+            if (hist) atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
+            lw[t] = l;
+        }
+        // subtask sizes (only when asked for): one atomic per distinct LCA of the wavefront
+        if (lcacnt) {
+#pragma unroll
+            for (int t = 0; t < EDGE_ITEMS; t++) {
+                const int32_t l = lw[t];
+                uint64_t active = __ballot(l >= 0);
+                while (active) {
+                    const int leader = ctz64(active);
+                    const int32_t lv = __shfl(l, leader, GSS_WAVE);
+                    const uint64_t same = __ballot(l == lv) & active;
+                    if (lane_id() == leader) atomicAdd(&lcacnt[lv], __popcll(same));
+                    active &= ~same;
+                }
             }
         }
     }
@@ -339,8 +345,7 @@ __global__ __launch_bounds__(1024) void k_pick_bucket(const uint32_t *__restrict
 #define PX_TILE (256 * PX_ITEMS)
 __global__ __launch_bounds__(256) void k_prefix_count(const uint64_t *__restrict__ key, int64_t M,
                                                       const int32_t *__restrict__ off_g,
-                                                      const uint64_t *__restrict__ thr, int32_t *__restrict__ cnt,
-                                                      unsigned long long *__restrict__ gcount)
+                                                      const uint64_t *__restrict__ thr, int32_t *__restrict__ cnt)
 {
     __shared__ int32_t s_c[256 / GSS_WAVE];
     const int64_t base = (int64_t)blockIdx.x * PX_TILE;
@@ -352,28 +357,46 @@ __global__ __launch_bounds__(256) void k_prefix_count(const uint64_t *__restrict
         kv[i] = j < M ? key[j] : 0;
         gv[i] = (off_g && j < M) ? off_g[j] : 0;
     }
-    int32_t c = 0, gcur = -1, gc = 0;
+    int32_t c = 0;
 #pragma unroll
     for (int i = 0; i < PX_ITEMS; i++) {
         const int64_t j = base + (int64_t)i * 256 + threadIdx.x;
-        if (j < M && kv[i] >= thr[gv[i]]) {
-            c++;
-            // a thread's keys are 256 ids apart: runs of one graph are long in batches
-            if (off_g && gv[i] != gcur) {
-                if (gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
-                gcur = gv[i];
-                gc = 0;
-            }
-            gc++;
-        }
+        if (j < M && kv[i] >= thr[gv[i]]) c++;
     }
-    if (off_g && gc) atomicAdd(&gcount[gcur], (unsigned long long)gc);
     for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, GSS_WAVE);
     if (lane_id() == 0) s_c[threadIdx.x / GSS_WAVE] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < 256 / GSS_WAVE; w++) c += s_c[w];
         cnt[blockIdx.x] = c;
+    }
+}
+
+// Batches: before[g] = prefix edges with an off-tree index below obase[g] (graphs are
+// contiguous in that index), from the scanned tile counts plus a count inside the tile
+// holding the boundary.  One workgroup per boundary; no shared counters.
+__global__ __launch_bounds__(256) void k_prefix_before(const uint64_t *__restrict__ key, int64_t M,
+                                                       const int32_t *__restrict__ off_g,
+                                                       const uint64_t *__restrict__ thr,
+                                                       const int64_t *__restrict__ obase,
+                                                       const int32_t *__restrict__ tile_off, int64_t P,
+                                                       int64_t *__restrict__ before)
+{
+    __shared__ int32_t s_c[256 / GSS_WAVE];
+    const int64_t b = obase[blockIdx.x];
+    if (b >= M) {
+        if (threadIdx.x == 0) before[blockIdx.x] = P;
+        return;
+    }
+    const int64_t tile = b / PX_TILE, t0 = tile * PX_TILE;
+    int32_t c = 0;
+    for (int64_t j = t0 + threadIdx.x; j < b; j += 256) c += key[j] >= thr[off_g ? off_g[j] : 0] ? 1 : 0;
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, GSS_WAVE);
+    if (lane_id() == 0) s_c[threadIdx.x / GSS_WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / GSS_WAVE; w++) c += s_c[w];
+        before[blockIdx.x] = (int64_t)tile_off[tile] + c;
     }
 }
 __global__ __launch_bounds__(256) void k_prefix_write(const uint64_t *__restrict__ key, int64_t M,
@@ -1151,7 +1174,7 @@ __global__ void k_rank_graph(int64_t P, const int32_t *__restrict__ sj, const in
 
 // Resolves, for every graph g, the prefix {key >= thr[g]} of its criticality order.
 static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uint64_t *key, const uint8_t *bst,
-                                   const int32_t *lca, const int32_t *lcacnt, const uint64_t *thr, PrefixBufs &B,
+                                   const int32_t *lca, const uint64_t *thr, PrefixBufs &B,
                                    const gss_params *prm)
 {
     hipStream_t st = ctx->stream;
@@ -1163,16 +1186,19 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     // compaction (id order: graph-major)
     int64_t nthr = (M + PX_TILE - 1) / PX_TILE;  // tiles
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
-    unsigned long long *gcount = ctx->alloc<unsigned long long>(G);
-    HIP_OK(hipMemsetAsync(gcount, 0, sizeof(unsigned long long) * G, st));
     GSS_LAUNCH_B(8 * M, k_prefix_count, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M, off_g,
-                 thr, pc, gcount);
+                 thr, pc);
     int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
     res.P = P;
     res.Pg.assign(G, 0);
     if (G > 1) {
-        HIP_OK(hipMemcpyAsync(res.Pg.data(), gcount, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
+        int64_t *before = ctx->alloc<int64_t>(G + 1);
+        GSS_LAUNCH(k_prefix_before, dim3(G + 1), dim3(256), 0, st, key, M, off_g, thr, t->d_obase, pc, P, before);
+        std::vector<int64_t> hb(G + 1);
+        HIP_OK(hipMemcpyAsync(hb.data(), before, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, st));
         ctx->sync();
+        for (int32_t g = 0; g < G; g++) res.Pg[g] = hb[g + 1] - hb[g];
+        ctx->free(before);
     } else {
         res.Pg[0] = P;
     }
@@ -1182,7 +1208,6 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                  off_g, thr, pc, v1,
                  k1);
     ctx->free(pc);
-    ctx->free(gcount);
     radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
     if (G > 1) {  // stable by graph: each graph's prefix becomes contiguous, in rank order
         GSS_LAUNCH(k_graph_key, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, v1, t->off_g, k1);
@@ -1240,7 +1265,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         feat = ctx->alloc<float>(nsub * GSS_NFEAT + 1);
         scratch.push_back(feat);
         launch_subtask_features(ctx, (int32_t)nsub, B.sub_ptr, B.sub_lca, B.grp, B.rdu, B.rdv, B.rb, B.ru, B.rv,
-                                t->vrec, lcacnt, feat);
+                                t->vrec, P, feat);
         if (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) {
             pred = ctx->alloc<float>(nsub + 1);
             scratch.push_back(pred);
@@ -1495,8 +1520,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     uint8_t *bst = ctx->alloc<uint8_t>(M + 1);
     uint32_t *hist = ctx->alloc<uint32_t>((int64_t)SEL_BINS * G);
     // per-LCA edge counts: subtask statistics, and two of the cost model's features
-    const bool need_lca_counts = (prms[0].flags & GSS_F_STATS) || ctx->record ||
-                                 (prms[0].sched == GSS_SCHED_LEARNED && ctx->model_ready);
+    const bool need_lca_counts = (prms[0].flags & GSS_F_STATS) != 0;
     int32_t *lcacnt = need_lca_counts ? ctx->alloc<int32_t>(n) : nullptr;
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (lcacnt) HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
@@ -1504,7 +1528,8 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     // (56 B); the two Euler entries that answer the range minimum (16 B); key, LCA and
     // beta* written (13 B); optional stretch (8 B)
     if (M > 0)
-        GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch, dim3(grid_for(M, RB * EDGE_ITEMS)), dim3(RB), 0,
+        GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch,
+                     dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0,
                      st, M, t->off_id, t->off_u,
                    t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst, stretch,
                    G == 1 ? hist : (uint32_t *)nullptr, lcacnt, ctx->d_flags);
@@ -1565,7 +1590,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         uint64_t *dthr = ctx->alloc<uint64_t>(G);
         HIP_OK(hipMemcpyAsync(dthr, thr.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
         PrefixBufs B;
-        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, lcacnt, dthr, B, &prms[0]);
+        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, B, &prms[0]);
         ctx->free(dthr);
         arcs = r.arcs;
         rounds = r.rounds;
@@ -1657,7 +1682,8 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     uint32_t *hist = ctx->alloc<uint32_t>(SEL_BINS);
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (M > 0) {
-        GSS_LAUNCH(k_edge_stretch, dim3(grid_for(M, RB * EDGE_ITEMS)), dim3(RB), 0, st, M, t->off_id, t->off_u,
+        GSS_LAUNCH(k_edge_stretch, dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)),
+                   dim3(RB), 0, st, M, t->off_id, t->off_u,
                            t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta, key, lca, bst,
                            (double *)nullptr, hist, (int32_t *)nullptr, ctx->d_flags);
         GSS_LAUNCH(k_edge_lca_out, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, lca, bst,

@@ -277,8 +277,8 @@ __global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const in
                                                           const uint8_t *__restrict__ rb,
                                                           const int32_t *__restrict__ ru,
                                                           const int32_t *__restrict__ rv,
-                                                          const VRec *__restrict__ vrec,
-                                                          const int32_t *__restrict__ lcacnt, float *__restrict__ feat)
+                                                          const VRec *__restrict__ vrec, int64_t P,
+                                                          float *__restrict__ feat)
 {
     const int lane = lane_id();
     const int32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
@@ -308,7 +308,6 @@ __global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const in
     }
     if (lane == 0) {
         float S = (float)(g1 - g0);
-        float full = (float)lcacnt[l];
         float *f = feat + (int64_t)s * GSS_NFEAT;
         f[0] = log2f(1.f + S);
         f[1] = sum_path / S;
@@ -319,8 +318,8 @@ __global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const in
         f[6] = max_deg;
         f[7] = log2f(1.f + (float)rl.pad);
         f[8] = log2f(1.f + (float)rl.depth);
-        f[9] = S / fmaxf(full, 1.f);
-        f[10] = log2f(1.f + full);
+        f[9] = S / fmaxf((float)P, 1.f);  // share of the resolved prefix
+        f[10] = log2f(1.f + sum_path);    // total tree-path length
         f[11] = log2f(1.f + S * S);
     }
 }
@@ -359,9 +358,8 @@ void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
 
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
                              const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
-                             const int32_t *ru, const int32_t *rv, const VRec *vrec, const int32_t *lcacnt,
-                             float *feat)
+                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, float *feat)
 {
     GSS_LAUNCH(k_subtask_features, dim3(grid_for((int64_t)nsub * GSS_WAVE, 256)), dim3(256), 0, ctx->stream, nsub,
-               sub_ptr, sub_lca, grp, rdu, rdv, rb, ru, rv, vrec, lcacnt, feat);
+               sub_ptr, sub_lca, grp, rdu, rdv, rb, ru, rv, vrec, P, feat);
 }
