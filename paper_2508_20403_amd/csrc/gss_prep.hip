@@ -1504,8 +1504,12 @@ void prep_batch(gss_ctx ctx, gss_tree t, int32_t G, const gss_csr *gs, const int
     HIP_OK(hipMemcpyAsync(dd, hd.data(), sizeof(UnionDesc) * G, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(roots, 0, sizeof(int32_t) * G, st));
     HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
-    GSS_LAUNCH(k_union_fill, dim3(64, G), dim3(PB), 0, st, dd, G, N, E, t->virt_root, t->own_row_ptr, t->own_col,
-               t->own_w, t->own_parent, roots, ctx->d_flags);
+    // enough workgroups per graph that the largest graph's copy runs at bandwidth
+    int64_t most = 1;
+    for (int32_t g = 0; g < G; g++) most = std::max<int64_t>(most, std::max<int64_t>(gs[g].nnz, gs[g].n));
+    const unsigned gx = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(64, most / (PB * 16)));
+    GSS_LAUNCH_B(24 * (int64_t)E + 16 * (int64_t)N, k_union_fill, dim3(gx, G), dim3(PB), 0, st, dd, G, N, E,
+                 t->virt_root, t->own_row_ptr, t->own_col, t->own_w, t->own_parent, roots, ctx->d_flags);
     GSS_LAUNCH(k_roots_check, dim3(grid_for(G, PB)), dim3(PB), 0, st, roots, G, ctx->d_flags);
     uint32_t f = read_flags(ctx);
     ctx->free(dd);

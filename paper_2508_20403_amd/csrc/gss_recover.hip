@@ -764,7 +764,7 @@ __device__ __forceinline__ void jp_probe(const JRec &r, bool active, const unsig
             const int32_t a = atomicAdd(s_narc, 1);
             if (a < JP_ARC_LDS) s_arc[a] = make_int2(r.p, t);
             else if (a < arc_slot) arc_slice[a] = make_int2(r.p, t);
-            atomicAdd(&indeg[t], 1);
+            if (indeg) atomicAdd(&indeg[t], 1);
         }
     }
 }
@@ -772,7 +772,8 @@ __device__ __forceinline__ void jp_probe(const JRec &r, bool active, const unsig
 __global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ recs, const int32_t *__restrict__ off,
                                                        int32_t nblk, const int64_t *__restrict__ total,
                                                        int32_t arc_slot, int2 *__restrict__ arc_buf,
-                                                       int32_t *__restrict__ arc_cnt, int32_t *__restrict__ indeg)
+                                                       int32_t *__restrict__ arc_cnt, int32_t *__restrict__ indeg,
+                                                       const int32_t *__restrict__ parts)
 {
     constexpr int PER = JP_CAP / JP_BLOCK;
     __shared__ unsigned long long s_ab[JP_CAP];
@@ -781,10 +782,14 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ r
     __shared__ int32_t s_tab[JP_TAB];
     __shared__ int2 s_arc[JP_ARC_LDS];
     __shared__ int32_t s_narc;
-    const int64_t part = blockIdx.x;
+    // parts == null: every partition, arc slices indexed by partition, in-degrees counted.
+    // Otherwise a second run over the listed partitions whose arcs overflowed their slice:
+    // slices indexed by list position, in-degrees already counted by the first run.
+    const int64_t part = parts ? parts[blockIdx.x] : blockIdx.x;
+    if (parts) indeg = nullptr;
     const int64_t start = off[part * nblk];
     const int64_t end = (part + 1 < JP_PARTS) ? off[(part + 1) * nblk] : *total;
-    int2 *arc_slice = arc_buf + part * (int64_t)arc_slot;
+    int2 *arc_slice = arc_buf + (int64_t)blockIdx.x * arc_slot;
     if (threadIdx.x == 0) s_narc = 0;
     JRec zero;
     zero.ab = 0;
@@ -852,12 +857,17 @@ __global__ __launch_bounds__(1024) void k_max_i32(const int32_t *__restrict__ x,
 }
 
 // the partitions' arcs, packed (arc_cnt scanned to offsets)
+// packs every partition's arcs (arc_cnt scanned to offsets); partitions that overflowed
+// their first slice read from the second run's buffer (ov_slot[part] >= 0)
 __global__ void k_jp_pack(const int2 *__restrict__ arc_buf, const int32_t *__restrict__ arc_cnt,
-                          const int32_t *__restrict__ arc_off, int32_t arc_slot, int2 *__restrict__ arcs)
+                          const int32_t *__restrict__ arc_off, int32_t arc_slot, const int32_t *__restrict__ ov_slot,
+                          const int2 *__restrict__ ov_buf, int32_t ov_size, int2 *__restrict__ arcs)
 {
     const int64_t part = blockIdx.x;
     const int32_t n = arc_cnt[part], o = arc_off[part];
-    for (int a = threadIdx.x; a < n; a += blockDim.x) arcs[o + a] = arc_buf[part * (int64_t)arc_slot + a];
+    const int32_t os = ov_slot ? ov_slot[part] : -1;
+    const int2 *src = os >= 0 ? ov_buf + (int64_t)os * ov_size : arc_buf + part * (int64_t)arc_slot;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) arcs[o + a] = src[a];
 }
 
 __global__ void k_state_init(int64_t NG, const int32_t *__restrict__ glist, const int32_t *__restrict__ indeg,
@@ -1356,29 +1366,52 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         scan_exclusive_i32_dev(ctx, jhist, (int64_t)JP_PARTS * nblk, d_total);
         GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)) + 16 * nslots, k_jp_scatter, dim3(nblk), dim3(JP_BLOCK), 0, st,
                      nslots, S, B.glist, P, c, B.rb, B.ancU, B.ancV, nblk, jhist, recs);
-        int32_t arc_slot = 128;
+        const int32_t arc_slot = 128;
         int32_t *arc_cnt = ctx->alloc<int32_t>(JP_PARTS + 1);
         int32_t *arc_off = ctx->alloc<int32_t>(JP_PARTS + 1);
-        for (;;) {
+        {
             int2 *arc_buf = ctx->alloc<int2>((int64_t)JP_PARTS * arc_slot);
             HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
             GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(JP_PARTS), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, d_total,
-                         arc_slot, arc_buf, arc_cnt, B.indeg);
+                         arc_slot, arc_buf, arc_cnt, B.indeg, (const int32_t *)nullptr);
             GSS_LAUNCH(k_max_i32, dim3(1), dim3(1024), 0, st, arc_cnt, (int32_t)JP_PARTS, ctx->d_counters + 3);
             HIP_OK(hipMemcpyAsync(arc_off, arc_cnt, sizeof(int32_t) * JP_PARTS, hipMemcpyDeviceToDevice, st));
             scan_exclusive_i32_dev(ctx, arc_off, JP_PARTS, ctx->d_counters);
             read_counters(ctx, 4);
             const int64_t most = ctx->h_counters[3];
-            if (most > arc_slot) {  // some partition found more arcs than its slice holds
-                ctx->free(arc_buf);
-                while (arc_slot < most) arc_slot *= 2;
-                continue;
-            }
             const int64_t A = ctx->h_counters[0];
+            // partitions with more arcs than their slice: joined again into a buffer of their own
+            int32_t *ov_slot = nullptr, *ov_parts = nullptr;
+            int2 *ov_buf = nullptr;
+            int32_t ov_size = 0;
+            if (most > arc_slot) {
+                std::vector<int32_t> hc(JP_PARTS), slot(JP_PARTS, -1), list;
+                HIP_OK(hipMemcpyAsync(hc.data(), arc_cnt, sizeof(int32_t) * JP_PARTS, hipMemcpyDeviceToHost, st));
+                ctx->sync();
+                for (int32_t q = 0; q < JP_PARTS; q++)
+                    if (hc[q] > arc_slot) {
+                        slot[q] = (int32_t)list.size();
+                        list.push_back(q);
+                    }
+                ov_size = (int32_t)most;
+                ov_slot = ctx->alloc<int32_t>(JP_PARTS);
+                ov_parts = ctx->alloc<int32_t>(list.size());
+                ov_buf = ctx->alloc<int2>((int64_t)list.size() * ov_size);
+                HIP_OK(hipMemcpyAsync(ov_slot, slot.data(), sizeof(int32_t) * JP_PARTS, hipMemcpyHostToDevice, st));
+                HIP_OK(hipMemcpyAsync(ov_parts, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice,
+                                      st));
+                GSS_LAUNCH(k_jp_join, dim3((unsigned)list.size()), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, d_total,
+                           ov_size, ov_buf, arc_cnt, B.indeg, (const int32_t *)ov_parts);
+                ctx->sync();  // the host vectors are the copies' sources
+            }
             int2 *arcs = ctx->alloc<int2>(A + 1);
             if (A > 0)
-                GSS_LAUNCH(k_jp_pack, dim3(JP_PARTS), dim3(64), 0, st, arc_buf, arc_cnt, arc_off, arc_slot, arcs);
+                GSS_LAUNCH(k_jp_pack, dim3(JP_PARTS), dim3(64), 0, st, arc_buf, arc_cnt, arc_off, arc_slot, ov_slot,
+                           ov_buf, ov_size, arcs);
             ctx->free(arc_buf);
+            ctx->free(ov_slot);
+            ctx->free(ov_parts);
+            ctx->free(ov_buf);
             res.arcs = A;
             HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
             GSS_LAUNCH(k_state_init, dim3(grid_for(nglobal_edges, RB)), dim3(RB), 0, st, nglobal_edges, B.glist,
@@ -1396,7 +1429,6 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                 ctx->free(arcs2);
             }
             ctx->free(arcs);
-            break;
         }
         ctx->free(jhist);
         ctx->free(recs);
