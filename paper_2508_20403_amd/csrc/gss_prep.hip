@@ -1241,8 +1241,19 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->uptr = ctx->alloc<int32_t>(n + 1);
     GSS_LAUNCH(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, t->ufirst, t->uptr);
     HIP_OK(hipMemsetAsync(t->uptr + n, 0, sizeof(int32_t), st));
-    int64_t m = scan_exclusive_i32(ctx, t->uptr, n + 1, true);
-    if (validate && 2 * m != nnz) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
+    int64_t m;
+    scan_exclusive_i32_dev(ctx, t->uptr, n + 1, ctx->d_counters + 13);
+    if (validate) {
+        // the symmetry check above makes m = nnz / 2; the scan total is compared with it
+        // at the final synchronisation instead of waiting for it here
+        if (nnz % 2) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
+        m = nnz / 2;
+    } else {
+        HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], ctx->d_counters + 13, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
+        ctx->sync();
+        m = ctx->h_counters[13];
+    }
     t->m = m;
 
     // tree checks
@@ -1392,8 +1403,9 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         ctx->free(tcnt);
     }
     HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(&ctx->h_counters[9], ctx->d_counters + 9, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&ctx->h_counters[9], ctx->d_counters + 9, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     f = read_flags(ctx);  // syncs
+    if (ctx->h_counters[13] != t->m) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
     if (nnz > 0 && (ctx->h_counters[9] != t->M || (f & F_TREE_EDGE)))
         fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
     if (t->virt_root < 0) {  // a single graph: one range covering everything

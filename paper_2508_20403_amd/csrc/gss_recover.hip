@@ -1156,6 +1156,7 @@ static int bytes_for(uint64_t maxkey)
 
 struct PrefixResult {
     int64_t P = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0, njoin = 0;
+    bool rounds_pending = false;  // rounds is in h_counters[12] after the next synchronisation
     std::vector<int64_t> Pg, cand;  // per graph
 };
 
@@ -1424,8 +1425,10 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                            (unsigned long long *)(ctx->d_counters + 2));
                 GSS_LAUNCH(k_resolve_dev, dim3(1), dim3(1024), 0, st, (const unsigned long long *)(ctx->d_counters + 2),
                            arcs2, B.indeg, B.state, B.mcnt, ctx->d_counters + 1);
-                read_counters(ctx, 2);
-                res.rounds = ctx->h_counters[1];
+                // rounds (for the info record) arrive with the next synchronisation
+                HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], ctx->d_counters + 1, sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, st));
+                res.rounds_pending = true;
                 ctx->free(arcs2);
             }
             ctx->free(arcs);
@@ -1444,6 +1447,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     res.cand.assign(G, 0);
     HIP_OK(hipMemcpyAsync(res.cand.data(), cg, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
     ctx->sync();
+    if (res.rounds_pending) res.rounds = ctx->h_counters[12];
     ctx->free(cg);
     if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, feat, cycles, qv, nlocal);
     for (void *p : scratch) ctx->free(p);
@@ -1589,7 +1593,10 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             largest[g] = hs[2 * g + 1];
         }
     }
-    uint32_t f = read_flags(ctx);
+    // the range flag is fetched without waiting; it is checked after the first prefix is
+    // resolved (that step synchronises, and nothing is written to the outputs before it)
+    HIP_OK(hipMemcpyAsync(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    bool flags_checked = false;
     auto cleanup = [&]() {
         ctx->free(key);
         ctx->free(lca);
@@ -1597,10 +1604,6 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         ctx->free(hist);
         ctx->free(lcacnt);
     };
-    if (f & F_RANGE) {
-        cleanup();
-        throw gss_error{GSS_ERR_RANGE, "a stretch is not a finite double"};
-    }
 
     auto first_want = [&](int32_t g) {
         int64_t need = K[g] - nrec[g];
@@ -1624,6 +1627,18 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         PrefixBufs B;
         PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, B, &prms[0]);
         ctx->free(dthr);
+        if (!flags_checked) {
+            ctx->sync();
+            uint32_t f = 0;
+            memcpy(&f, &ctx->h_counters[15], sizeof f);
+            flags_checked = true;
+            if (f & F_RANGE) {
+                B.release(ctx);
+                ctx->free(dgo);
+                cleanup();
+                throw gss_error{GSS_ERR_RANGE, "a stretch is not a finite double"};
+            }
+        }
         arcs = r.arcs;
         rounds = r.rounds;
         njoin = r.njoin;
@@ -1678,6 +1693,15 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         B.release(ctx);
     }
     ctx->sync();
+    if (!flags_checked) {
+        uint32_t f = 0;
+        memcpy(&f, &ctx->h_counters[15], sizeof f);  // the synchronisation above delivered it
+        if (f & F_RANGE) {
+            ctx->free(dgo);
+            cleanup();
+            throw gss_error{GSS_ERR_RANGE, "a stretch is not a finite double"};
+        }
+    }
     ctx->free(dgo);
     cleanup();
     bool short_any = false;
