@@ -64,13 +64,24 @@ __device__ __forceinline__ int64_t clamp_idx(int64_t x, int64_t lo, int64_t hi)
 }
 
 // tile_row[b] = the row holding entry b*ETILE: one thread per row marks the tiles that
-// start inside it (row_ptr reads are clamped; malformed input yields wrong but in-range
-// rows, and k_check_rowptr reports it)
+// start inside it (row_ptr reads are clamped, so malformed input yields wrong but
+// in-range rows).  With `validate`, the same pass checks row_ptr: row_ptr[0] = 0,
+// non-decreasing, row_ptr[n] = nnz, every entry in [0, nnz].
 __global__ void k_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz, int64_t ntiles,
-                            int32_t *__restrict__ tile_row)
+                            int32_t *__restrict__ tile_row, int validate, uint32_t *flags)
 {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
+    if (validate) {
+        bool bad = false;
+        if (x <= n) {
+            if (x == 0 && row_ptr[0] != 0) bad = true;
+            if (x < n && row_ptr[x + 1] < row_ptr[x]) bad = true;
+            if (x == n && (int64_t)row_ptr[n] != nnz) bad = true;
+            if ((int64_t)row_ptr[x] < 0 || (int64_t)row_ptr[x] > nnz) bad = true;
+        }
+        if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_ARG);
+    }
+    if (x >= n || ntiles == 0) return;
     const int64_t lo = clamp_idx(row_ptr[x], 0, nnz), hi = clamp_idx(row_ptr[x + 1], 0, nnz);
     if (hi <= lo) return;
     const int64_t b1 = (hi - 1) / ETILE;
@@ -125,19 +136,6 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
     __syncthreads();
 }
 
-__global__ void k_check_rowptr(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
-                               uint32_t *flags)
-{
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (u <= n) {
-        if (u == 0 && row_ptr[0] != 0) bad = true;
-        if (u < n && row_ptr[u + 1] < row_ptr[u]) bad = true;
-        if (u == n && (int64_t)row_ptr[n] != nnz) bad = true;
-        if ((int64_t)row_ptr[u] < 0 || (int64_t)row_ptr[u] > nnz) bad = true;
-    }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_ARG);
-}
 
 // Symmetry is checked as a multiset identity: the upper entries (u,v,w) and the
 // transposed lower entries must be the same multiset.  Each entry contributes two
@@ -769,7 +767,7 @@ __global__ void k_euler_emit(int32_t N, const int32_t *__restrict__ owner, const
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int32_t o = owner[i];
-    if (o < 0) return;  // not on the tour: k_check_reached reports it
+    if (o < 0) return;  // not on the tour: k_vrec_finish reports it
     const LVal acc = lv_add(rpre[o], loc[i]);
     const LVal after = lv_add(acc, arc_val(i, T));
     const int32_t x = i >> 1;
@@ -1134,44 +1132,39 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_vrec_init(VRec *vrec, int32_t n)
+// vertex records before the tour: the root's is final (first = 0, depth 0, D = 0), the
+// others are marked unreached; the root's thread also writes the first Euler entry and
+// the head arc of the tour (the down arc into its first child; n > 1)
+__global__ void k_vrec_init(VRec *vrec, int32_t n, int32_t root, uint64_t *__restrict__ epk,
+                            const int32_t *__restrict__ cptr, const int32_t *__restrict__ clist, int64_t *head)
 {
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     VRec r;
     r.D = mk128(0, 0);
-    r.first = -1;
+    r.first = x == root ? 0 : -1;
     r.depth = 0;
     r.parent = -1;
     r.pad = 0;
     vrec[x] = r;
+    if (x == root) {
+        epk[0] = (uint64_t)(uint32_t)root;
+        if (n > 1) *head = 2 * (int64_t)clist[cptr[root]];
+    }
 }
 
-__global__ void k_check_reached(const VRec *__restrict__ vrec, int32_t n, uint32_t *flags)
+// every vertex must have been reached by the tour; its tree degree goes to the record
+__global__ void k_vrec_finish(const int32_t *__restrict__ cptr, int32_t n, VRec *__restrict__ vrec, uint32_t *flags)
 {
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = x < n && vrec[x].first < 0;
+    bool bad = false;
+    if (x < n) {
+        bad = vrec[x].first < 0;
+        vrec[x].pad = cptr[x + 1] - cptr[x];
+    }
     if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_NOT_TREE);
 }
 
-// number of tree children of each vertex, kept in the vertex record
-__global__ void k_vrec_tdeg(const int32_t *__restrict__ cptr, int32_t n, VRec *__restrict__ vrec)
-{
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < n) vrec[x].pad = cptr[x + 1] - cptr[x];
-}
-
-__global__ void k_root_init(int32_t root, VRec *vrec, uint64_t *epk)
-{
-    VRec r;
-    r.D = mk128(0, 0);
-    r.first = 0;
-    r.depth = 0;
-    r.parent = -1;
-    r.pad = 0;
-    vrec[root] = r;
-    epk[0] = (uint64_t)(uint32_t)root;
-}
 
 // ------------------------------------------------------------------------------------
 // host orchestration
@@ -1189,11 +1182,6 @@ void free_tree_arrays(gss_tree t)
 }
 
 // head of the Euler list: the down arc of the root's first child
-__global__ void k_head(const int32_t *__restrict__ cptr, const int32_t *__restrict__ clist, int32_t root,
-                       int64_t *out)
-{
-    out[0] = 2 * (int64_t)clist[cptr[root]];
-}
 
 void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
 {
@@ -1203,14 +1191,12 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     const bool validate = !(flags & GSS_PREP_TRUSTED);
     HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
 
-    // the row at the start of every tile of ETILE entries
+    // the row at the start of every tile of ETILE entries (and the row_ptr checks)
     const int64_t etiles = nnz > 0 ? (nnz + ETILE - 1) / ETILE : 0;
     int32_t *tile_row = ctx->alloc<int32_t>(etiles + 1);
-    if (nnz > 0) {
-        HIP_OK(hipMemsetAsync(tile_row, 0, sizeof(int32_t) * (etiles + 1), st));
-        GSS_LAUNCH_B(8 * (int64_t)n, k_tile_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz, etiles,
-                     tile_row);
-    }
+    if (nnz > 0) HIP_OK(hipMemsetAsync(tile_row, 0, sizeof(int32_t) * (etiles + 1), st));
+    GSS_LAUNCH_B(8 * (int64_t)n, k_tile_rows, dim3(grid_for((int64_t)n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
+                 etiles, tile_row, validate ? 1 : 0, ctx->d_flags);
     struct TileRowsFree {
         gss_ctx c;
         int32_t *p;
@@ -1220,8 +1206,6 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     // validation (memory-safe on malformed input) and edge numbering
     if (validate) {
         HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, 2 * sizeof(int64_t), st));
-        GSS_LAUNCH(k_check_rowptr, dim3(grid_for(n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
-                   ctx->d_flags);
         if (nnz > 0) {
             uint64_t *hpart = ctx->alloc<uint64_t>(2 * etiles + 2);
             GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0, st,
@@ -1308,19 +1292,17 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->L = 2 * n - 1;
     t->vrec = ctx->alloc<VRec>(n);
     t->epk = ctx->alloc<uint64_t>(t->L);
-    GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n);
-    GSS_LAUNCH(k_root_init, dim3(1), dim3(1), 0, st, t->root, t->vrec, t->epk);
+    GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, t->root, t->epk, cptr, clist,
+               ctx->d_counters + 12);
     if (n > 1) {
         int32_t N = 2 * n;
         int32_t *succ = ctx->alloc<int32_t>(N);
         GSS_LAUNCH_B(24 * (int64_t)n, k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n,
                      t->root, succ);
-        GSS_LAUNCH(k_head, dim3(1), dim3(1), 0, st, cptr, clist, t->root, ctx->d_counters + 12);
         for (int mult = 1;; mult *= 2) {
             std::vector<void *> bufs;
             euler_rank(ctx, t, succ, T, ctx->d_counters + 12, mult, bufs);
-            GSS_LAUNCH(k_check_reached, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, ctx->d_flags);
-            GSS_LAUNCH(k_vrec_tdeg, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec);
+            GSS_LAUNCH(k_vrec_finish, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec, ctx->d_flags);
             f = read_flags(ctx);
             for (void *p : bufs) ctx->free(p);
             if (!(f & F_OVERFLOW) || (f & F_NOT_TREE)) break;
@@ -1330,12 +1312,12 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
             }
             // a level outgrew its capacity (vanishingly rare): rank again with more room
             HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
-            GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n);
-            GSS_LAUNCH(k_root_init, dim3(1), dim3(1), 0, st, t->root, t->vrec, t->epk);
+            GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, t->root, t->epk, cptr,
+                       clist, ctx->d_counters + 12);
         }
         ctx->free(succ);
     } else {
-        GSS_LAUNCH(k_vrec_tdeg, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec);
+        GSS_LAUNCH(k_vrec_finish, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec, ctx->d_flags);
         f = read_flags(ctx);
     }
     ctx->free(cfill);

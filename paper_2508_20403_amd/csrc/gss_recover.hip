@@ -842,20 +842,28 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ r
     for (int a = threadIdx.x; a < na && a < arc_slot && a < JP_ARC_LDS; a += JP_BLOCK) arc_slice[a] = s_arc[a];
 }
 
-__global__ __launch_bounds__(1024) void k_max_i32(const int32_t *__restrict__ x, int32_t n, int64_t *out)
+// arc_off = exclusive scan of the partitions' arc counts, total[0] = their sum and
+// total[3] = the largest count (one workgroup; JP_PARTS = 2 * 1024)
+__global__ __launch_bounds__(1024) void k_jp_offsets(const int32_t *__restrict__ cnt, int32_t *__restrict__ arc_off,
+                                                    int64_t *total)
 {
-    __shared__ int32_t sm[1024 / GSS_WAVE];
-    int32_t v = 0;
-    for (int32_t i = threadIdx.x; i < n; i += 1024) v = max(v, x[i]);
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, GSS_WAVE));
-    if (lane_id() == 0) sm[threadIdx.x / GSS_WAVE] = v;
+    __shared__ int32_t s_sum[1024 / GSS_WAVE + 1];
+    __shared__ int32_t s_max[1024 / GSS_WAVE];
+    const int32_t a = cnt[2 * threadIdx.x], b = cnt[2 * threadIdx.x + 1];
+    int32_t tot;
+    const int32_t ex = block_exclusive_scan<int32_t>(a + b, s_sum, &tot);
+    arc_off[2 * threadIdx.x] = ex;
+    arc_off[2 * threadIdx.x + 1] = ex + a;
+    int32_t mx = max(a, b);
+    for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d, GSS_WAVE));
+    if (lane_id() == 0) s_max[threadIdx.x / GSS_WAVE] = mx;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < 1024 / GSS_WAVE; w++) v = max(v, sm[w]);
-        *out = v;
+        for (int w = 1; w < 1024 / GSS_WAVE; w++) mx = max(mx, s_max[w]);
+        total[0] = tot;
+        total[3] = mx;
     }
 }
-
 // the partitions' arcs, packed (arc_cnt scanned to offsets)
 // packs every partition's arcs (arc_cnt scanned to offsets); partitions that overflowed
 // their first slice read from the second run's buffer (ov_slot[part] >= 0)
@@ -1375,9 +1383,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
             GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(JP_PARTS), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, d_total,
                          arc_slot, arc_buf, arc_cnt, B.indeg, (const int32_t *)nullptr);
-            GSS_LAUNCH(k_max_i32, dim3(1), dim3(1024), 0, st, arc_cnt, (int32_t)JP_PARTS, ctx->d_counters + 3);
-            HIP_OK(hipMemcpyAsync(arc_off, arc_cnt, sizeof(int32_t) * JP_PARTS, hipMemcpyDeviceToDevice, st));
-            scan_exclusive_i32_dev(ctx, arc_off, JP_PARTS, ctx->d_counters);
+            static_assert(JP_PARTS == 2048, "k_jp_offsets covers 2 * 1024 partitions");
+            GSS_LAUNCH(k_jp_offsets, dim3(1), dim3(1024), 0, st, arc_cnt, arc_off, ctx->d_counters);
             read_counters(ctx, 4);
             const int64_t most = ctx->h_counters[3];
             const int64_t A = ctx->h_counters[0];

@@ -184,18 +184,20 @@ __global__ void k_group_heads(int64_t P, const uint64_t *__restrict__ glca, int3
 }
 
 // sub_ptr[id] = start of subtask id (head flags scanned exclusively give the ids)
+// sub_ptr[id] = start of subtask id (head flags scanned exclusively give the ids), and
+// sub_ptr[nsub] = P from the last position
 __global__ void k_group_ptr(int64_t P, const uint64_t *__restrict__ glca, const int32_t *__restrict__ hid,
                             int32_t *__restrict__ sub_ptr, int32_t *__restrict__ sub_lca)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
-    if (i == 0 || glca[i] != glca[i - 1]) {
+    const bool head = i == 0 || glca[i] != glca[i - 1];
+    if (head) {
         sub_ptr[hid[i]] = (int32_t)i;
         sub_lca[hid[i]] = (int32_t)glca[i];
     }
+    if (i == P - 1) sub_ptr[hid[i] + (head ? 1 : 0)] = (int32_t)P;
 }
-
-__global__ void k_group_end(int32_t nsub, int64_t P, int32_t *__restrict__ sub_ptr) { sub_ptr[nsub] = (int32_t)P; }
 
 // per subtask: queue key (descending cost first) and the local/global split
 __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr,
@@ -333,7 +335,6 @@ void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
                       int32_t *sub_lca, int32_t nsub)
 {
     GSS_LAUNCH(k_group_ptr, dim3(grid_for(P, 256)), dim3(256), 0, ctx->stream, P, glca, hid, sub_ptr, sub_lca);
-    GSS_LAUNCH(k_group_end, dim3(1), dim3(1), 0, ctx->stream, nsub, P, sub_ptr);
 }
 
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
