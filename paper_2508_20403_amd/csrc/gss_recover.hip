@@ -127,6 +127,8 @@ __device__ __forceinline__ uint64_t rmq(const RmqView &q, int32_t i, int32_t j)
 // ------------------------------------------------------------------------------------
 #define EDGE_ITEMS 2
 #define EDGE_GRID 2048  // workgroups of the grid-stride per-edge kernel
+#define STRETCH_HIST 1  // single graphs: the per-edge kernel also builds the first key histogram
+template <bool HIST>
 __global__ __launch_bounds__(RB) void k_edge_stretch(
     int64_t M, const int32_t *__restrict__ off_id, const int32_t *__restrict__ off_u,
     const int32_t *__restrict__ off_v, const double *__restrict__ off_w,
@@ -134,8 +136,9 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
     int32_t *__restrict__ lca, uint8_t *__restrict__ bst, double *__restrict__ stretch_out,
     uint32_t *__restrict__ hist, int32_t *__restrict__ lcacnt, uint32_t *flags)
 {
-    __shared__ uint32_t sh[SEL_BINS];
-    if (hist) {
+    // the first-level key histogram (HIST only: the LDS array limits occupancy)
+    __shared__ uint32_t sh[HIST ? SEL_BINS : 1];
+    if (HIST) {
         for (int i = threadIdx.x; i < SEL_BINS; i += RB) sh[i] = 0;
         __syncthreads();
     }
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
             lca[j] = l;
             bst[j] = (uint8_t)b;
             if (stretch_out) stretch_out[off_id[j]] = s;
-            if (hist) atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
+            if (HIST) atomicAdd(&sh[(uint32_t)(bits >> 51) & (SEL_BINS - 1)], 1u);
             lw[t] = l;
         }
         // subtask sizes (only when asked for): one atomic per distinct LCA of the wavefront
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
             }
         }
     }
-    if (hist) {
+    if (HIST) {
         __syncthreads();
         for (int i = threadIdx.x; i < SEL_BINS; i += RB)
             if (sh[i]) atomicAdd(&hist[i], sh[i]);
@@ -1571,11 +1574,16 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     // (56 B); the two Euler entries that answer the range minimum (16 B); key, LCA and
     // beta* written (13 B); optional stretch (8 B)
     if (M > 0)
-        GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch,
-                     dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0,
-                     st, M, t->off_id, t->off_u,
-                   t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst, stretch,
-                   G == 1 ? hist : (uint32_t *)nullptr, lcacnt, ctx->d_flags);
+        if (STRETCH_HIST && G == 1)
+            GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch<true>,
+                         dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0, st,
+                         M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
+                         stretch, hist, lcacnt, ctx->d_flags);
+        else
+            GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch<false>,
+                         dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0, st,
+                         M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
+                         stretch, (uint32_t *)nullptr, lcacnt, ctx->d_flags);
     HIP_OK(hipGetLastError());
     if (!lcacnt) {
         for (int32_t g = 0; g < G; g++) nsubg[g] = largest[g] = -1;
@@ -1622,7 +1630,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         want[g] = active[g] ? first_want(g) : 0;
         any_active |= active[g];
     }
-    bool hist_ready = (G == 1);
+    bool hist_ready = STRETCH_HIST && G == 1;
     int64_t arcs = 0, rounds = 0, njoin = 0;
     GraphOut *dgo = ctx->alloc<GraphOut>(G);
     std::vector<GraphOut> go(G);
@@ -1745,10 +1753,9 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     uint32_t *hist = ctx->alloc<uint32_t>(SEL_BINS);
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (M > 0) {
-        GSS_LAUNCH(k_edge_stretch, dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)),
-                   dim3(RB), 0, st, M, t->off_id, t->off_u,
-                           t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta, key, lca, bst,
-                           (double *)nullptr, hist, (int32_t *)nullptr, ctx->d_flags);
+        GSS_LAUNCH(k_edge_stretch<false>, dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)),
+                   dim3(RB), 0, st, M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta,
+                   key, lca, bst, (double *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr, ctx->d_flags);
         GSS_LAUNCH(k_edge_lca_out, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, lca, bst,
                            lca_out, b_out);
     }
