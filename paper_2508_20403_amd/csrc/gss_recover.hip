@@ -613,15 +613,14 @@ __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const i
 //   build  (t): (anc_i(x), anc_k(y)) and (anc_i(y), anc_k(x)) for i, k <= c,
 //   probe  (p): (anc_j(u), anc_l(v)) for j, l <= b,
 // and a probe record matches a build record of equal key with i <= b - j, k <= b - l
-// and t later than p.  Records are scattered into JP_PARTS partitions by a hash of the
+// and t later than p.  Records are scattered into 2^bits partitions by a hash of the
 // key (per-block histograms, a scan, then a scatter with LDS cursors: no global
 // atomics), and every partition is joined in LDS by one workgroup.
 // ------------------------------------------------------------------------------------
-#define JP_BITS 11
-#define JP_PARTS (1 << JP_BITS)
+#define JP_BITS_MIN 11                   // 2048 partitions ...
+#define JP_BITS_MAX 14                   // ... up to 16384, about 1024 records each
 #define JP_BLOCK 256
-#define JP_ITEMS 32                      // record slots per thread in the partition passes
-#define JP_SPB (JP_BLOCK * JP_ITEMS)     // record slots per block
+#define JP_ITEMS 32                      // record slots per thread per 2048 partitions
 #define JP_CAP 2048                      // records of a partition held in LDS at once
 #define JP_TAB (2 * JP_CAP)              // LDS hash slots
 #define JP_PROBE (1u << 31)
@@ -633,7 +632,7 @@ struct JRec {
 };
 
 __device__ __forceinline__ uint64_t jp_hash(uint64_t ab) { return mix64(ab * 0x9E3779B97F4A7C15ull + 1); }
-__device__ __forceinline__ uint32_t jp_part(uint64_t ab) { return (uint32_t)(jp_hash(ab) >> (64 - JP_BITS)); }
+__device__ __forceinline__ uint32_t jp_part(uint64_t ab, int bits) { return (uint32_t)(jp_hash(ab) >> (64 - bits)); }
 
 // record slot s = (listed edge gi, r): r < 2(c+1)^2 build, then (c+1)^2 probe slots.
 // Stage 1 reads the rank, stage 2 the ancestors, so that a batch of slots has all its
@@ -677,14 +676,15 @@ __device__ __forceinline__ bool jp_record(int64_t s, int32_t S, int32_t p, int64
 __global__ __launch_bounds__(JP_BLOCK) void k_jp_count(int64_t nslots, int32_t S, const int32_t *__restrict__ glist,
                                                         int64_t P, int32_t c, const uint8_t *__restrict__ rb,
                                                         const int32_t *__restrict__ ancU,
-                                                        const int32_t *__restrict__ ancV, int32_t nblk,
-                                                        int32_t *__restrict__ hist)
+                                                        const int32_t *__restrict__ ancV, int bits, int items,
+                                                        int32_t nblk, int32_t *__restrict__ hist)
 {
-    __shared__ int32_t sh[JP_PARTS];
-    for (int b = threadIdx.x; b < JP_PARTS; b += JP_BLOCK) sh[b] = 0;
+    extern __shared__ int32_t sh[];  // one counter per partition
+    const int nparts = 1 << bits;
+    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) sh[b] = 0;
     __syncthreads();
-    const int64_t s0 = (int64_t)blockIdx.x * JP_SPB;
-    for (int it0 = 0; it0 < JP_ITEMS; it0 += JP_BATCH) {
+    const int64_t s0 = (int64_t)blockIdx.x * JP_BLOCK * items;
+    for (int it0 = 0; it0 < items; it0 += JP_BATCH) {
         int32_t pr[JP_BATCH];
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++) pr[b] = jp_rank(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, nslots, S, glist);
@@ -693,14 +693,14 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_count(int64_t nslots, int32_t S
         for (int b = 0; b < JP_BATCH; b++) {
             JRec rec;
             part[b] = jp_record(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, S, pr[b], P, c, rb, ancU, ancV, rec)
-                          ? jp_part(rec.ab) : JP_PARTS;
+                          ? jp_part(rec.ab, bits) : (uint32_t)nparts;
         }
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++)
-            if (part[b] < JP_PARTS) atomicAdd(&sh[part[b]], 1);
+            if (part[b] < (uint32_t)nparts) atomicAdd(&sh[part[b]], 1);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < JP_PARTS; b += JP_BLOCK) hist[(int64_t)b * nblk + blockIdx.x] = sh[b];
+    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) hist[(int64_t)b * nblk + blockIdx.x] = sh[b];
 }
 
 // pass 2: the same records, written at their partition offsets (order inside a
@@ -709,14 +709,16 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_scatter(int64_t nslots, int32_t
                                                           const int32_t *__restrict__ glist, int64_t P, int32_t c,
                                                           const uint8_t *__restrict__ rb,
                                                           const int32_t *__restrict__ ancU,
-                                                          const int32_t *__restrict__ ancV, int32_t nblk,
-                                                          const int32_t *__restrict__ off, JRec *__restrict__ recs)
+                                                          const int32_t *__restrict__ ancV, int bits, int items,
+                                                          int32_t nblk, const int32_t *__restrict__ off,
+                                                          JRec *__restrict__ recs)
 {
-    __shared__ int32_t sh[JP_PARTS];
-    for (int b = threadIdx.x; b < JP_PARTS; b += JP_BLOCK) sh[b] = off[(int64_t)b * nblk + blockIdx.x];
+    extern __shared__ int32_t sh[];  // one output cursor per partition
+    const int nparts = 1 << bits;
+    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) sh[b] = off[(int64_t)b * nblk + blockIdx.x];
     __syncthreads();
-    const int64_t s0 = (int64_t)blockIdx.x * JP_SPB;
-    for (int it0 = 0; it0 < JP_ITEMS; it0 += JP_BATCH) {
+    const int64_t s0 = (int64_t)blockIdx.x * JP_BLOCK * items;
+    for (int it0 = 0; it0 < items; it0 += JP_BATCH) {
         int32_t pr[JP_BATCH];
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++) pr[b] = jp_rank(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, nslots, S, glist);
@@ -728,7 +730,7 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_scatter(int64_t nslots, int32_t
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++) {
             if (ok[b]) {
-                const int32_t pos = atomicAdd(&sh[jp_part(rec[b].ab)], 1);
+                const int32_t pos = atomicAdd(&sh[jp_part(rec[b].ab, bits)], 1);
                 recs[pos] = rec[b];
             }
         }
@@ -773,7 +775,7 @@ __device__ __forceinline__ void jp_probe(const JRec &r, bool active, const unsig
 }
 
 __global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ recs, const int32_t *__restrict__ off,
-                                                       int32_t nblk, const int64_t *__restrict__ total,
+                                                       int32_t nblk, int32_t nparts, const int64_t *__restrict__ total,
                                                        int32_t arc_slot, int2 *__restrict__ arc_buf,
                                                        int32_t *__restrict__ arc_cnt, int32_t *__restrict__ indeg,
                                                        const int32_t *__restrict__ parts)
@@ -791,7 +793,7 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ r
     const int64_t part = parts ? parts[blockIdx.x] : blockIdx.x;
     if (parts) indeg = nullptr;
     const int64_t start = off[part * nblk];
-    const int64_t end = (part + 1 < JP_PARTS) ? off[(part + 1) * nblk] : *total;
+    const int64_t end = (part + 1 < nparts) ? off[(part + 1) * nblk] : *total;
     int2 *arc_slice = arc_buf + (int64_t)blockIdx.x * arc_slot;
     if (threadIdx.x == 0) s_narc = 0;
     JRec zero;
@@ -846,18 +848,25 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_join(const JRec *__restrict__ r
 }
 
 // arc_off = exclusive scan of the partitions' arc counts, total[0] = their sum and
-// total[3] = the largest count (one workgroup; JP_PARTS = 2 * 1024)
-__global__ __launch_bounds__(1024) void k_jp_offsets(const int32_t *__restrict__ cnt, int32_t *__restrict__ arc_off,
-                                                    int64_t *total)
+// total[3] = the largest count (one workgroup; nparts a multiple of 1024, at most 16384)
+__global__ __launch_bounds__(1024) void k_jp_offsets(const int32_t *__restrict__ cnt, int32_t nparts,
+                                                    int32_t *__restrict__ arc_off, int64_t *total)
 {
     __shared__ int32_t s_sum[1024 / GSS_WAVE + 1];
     __shared__ int32_t s_max[1024 / GSS_WAVE];
-    const int32_t a = cnt[2 * threadIdx.x], b = cnt[2 * threadIdx.x + 1];
+    const int per = nparts / 1024;
+    const int32_t b0 = threadIdx.x * per;
+    int32_t sum = 0, mx = 0;
+    for (int k = 0; k < per; k++) {
+        sum += cnt[b0 + k];
+        mx = max(mx, cnt[b0 + k]);
+    }
     int32_t tot;
-    const int32_t ex = block_exclusive_scan<int32_t>(a + b, s_sum, &tot);
-    arc_off[2 * threadIdx.x] = ex;
-    arc_off[2 * threadIdx.x + 1] = ex + a;
-    int32_t mx = max(a, b);
+    int32_t ex = block_exclusive_scan<int32_t>(sum, s_sum, &tot);
+    for (int k = 0; k < per; k++) {
+        arc_off[b0 + k] = ex;
+        ex += cnt[b0 + k];
+    }
     for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d, GSS_WAVE));
     if (lane_id() == 0) s_max[threadIdx.x / GSS_WAVE] = mx;
     __syncthreads();
@@ -1364,30 +1373,35 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     B.indeg = ctx->alloc<int32_t>(P + 1);
     B.mcnt = ctx->alloc<int32_t>(P + 1);
     if (nsub > nlocal) {
-        // partition the join records by key hash
+        // partition the join records by key hash: about 1024 records per partition, so a
+        // partition usually fits one LDS chunk of the join
         const int64_t nslots = nglobal_edges * 3 * (int64_t)(c + 1) * (c + 1);
-        const int32_t nblk = (int32_t)((nslots + JP_SPB - 1) / JP_SPB);
-        int32_t *jhist = ctx->alloc<int32_t>((int64_t)JP_PARTS * nblk + 1);
+        int bits = JP_BITS_MIN;
+        while (bits < JP_BITS_MAX && nslots > ((int64_t)1024 << bits)) bits++;
+        const int32_t nparts = 1 << bits;
+        const int items = JP_ITEMS << (bits - JP_BITS_MIN);  // keeps the histogram matrix at nslots / 4 entries
+        const int32_t nblk = (int32_t)((nslots + (int64_t)JP_BLOCK * items - 1) / ((int64_t)JP_BLOCK * items));
+        int32_t *jhist = ctx->alloc<int32_t>((int64_t)nparts * nblk + 1);
         JRec *recs = ctx->alloc<JRec>(nslots + 1);
         int64_t *d_total = ctx->d_counters + 8;
+        const size_t lds = sizeof(int32_t) * nparts;
+        const int32_t S = 3 * (c + 1) * (c + 1);
         // per listed edge: rank, beta* and 2(c+1) ancestors read (twice: count, scatter);
         // 16 B per record written and read back by the join
-        const int32_t S = 3 * (c + 1) * (c + 1);
-        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)), k_jp_count, dim3(nblk), dim3(JP_BLOCK), 0, st, nslots, S,
-                     B.glist, P, c, B.rb, B.ancU, B.ancV, nblk, jhist);
-        scan_exclusive_i32_dev(ctx, jhist, (int64_t)JP_PARTS * nblk, d_total);
-        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)) + 16 * nslots, k_jp_scatter, dim3(nblk), dim3(JP_BLOCK), 0, st,
-                     nslots, S, B.glist, P, c, B.rb, B.ancU, B.ancV, nblk, jhist, recs);
+        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)), k_jp_count, dim3(nblk), dim3(JP_BLOCK), lds, st, nslots, S,
+                     B.glist, P, c, B.rb, B.ancU, B.ancV, bits, items, nblk, jhist);
+        scan_exclusive_i32_dev(ctx, jhist, (int64_t)nparts * nblk, d_total);
+        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)) + 16 * nslots, k_jp_scatter, dim3(nblk), dim3(JP_BLOCK), lds, st,
+                     nslots, S, B.glist, P, c, B.rb, B.ancU, B.ancV, bits, items, nblk, jhist, recs);
         const int32_t arc_slot = 128;
-        int32_t *arc_cnt = ctx->alloc<int32_t>(JP_PARTS + 1);
-        int32_t *arc_off = ctx->alloc<int32_t>(JP_PARTS + 1);
+        int32_t *arc_cnt = ctx->alloc<int32_t>(nparts + 1);
+        int32_t *arc_off = ctx->alloc<int32_t>(nparts + 1);
         {
-            int2 *arc_buf = ctx->alloc<int2>((int64_t)JP_PARTS * arc_slot);
+            int2 *arc_buf = ctx->alloc<int2>((int64_t)nparts * arc_slot);
             HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
-            GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(JP_PARTS), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, d_total,
+            GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(nparts), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, nparts, d_total,
                          arc_slot, arc_buf, arc_cnt, B.indeg, (const int32_t *)nullptr);
-            static_assert(JP_PARTS == 2048, "k_jp_offsets covers 2 * 1024 partitions");
-            GSS_LAUNCH(k_jp_offsets, dim3(1), dim3(1024), 0, st, arc_cnt, arc_off, ctx->d_counters);
+            GSS_LAUNCH(k_jp_offsets, dim3(1), dim3(1024), 0, st, arc_cnt, nparts, arc_off, ctx->d_counters);
             read_counters(ctx, 4);
             const int64_t most = ctx->h_counters[3];
             const int64_t A = ctx->h_counters[0];
@@ -1396,28 +1410,29 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             int2 *ov_buf = nullptr;
             int32_t ov_size = 0;
             if (most > arc_slot) {
-                std::vector<int32_t> hc(JP_PARTS), slot(JP_PARTS, -1), list;
-                HIP_OK(hipMemcpyAsync(hc.data(), arc_cnt, sizeof(int32_t) * JP_PARTS, hipMemcpyDeviceToHost, st));
+                std::vector<int32_t> hc(nparts), slot(nparts, -1), list;
+                HIP_OK(hipMemcpyAsync(hc.data(), arc_cnt, sizeof(int32_t) * nparts, hipMemcpyDeviceToHost, st));
                 ctx->sync();
-                for (int32_t q = 0; q < JP_PARTS; q++)
+                for (int32_t q = 0; q < nparts; q++)
                     if (hc[q] > arc_slot) {
                         slot[q] = (int32_t)list.size();
                         list.push_back(q);
                     }
                 ov_size = (int32_t)most;
-                ov_slot = ctx->alloc<int32_t>(JP_PARTS);
+                ov_slot = ctx->alloc<int32_t>(nparts);
                 ov_parts = ctx->alloc<int32_t>(list.size());
                 ov_buf = ctx->alloc<int2>((int64_t)list.size() * ov_size);
-                HIP_OK(hipMemcpyAsync(ov_slot, slot.data(), sizeof(int32_t) * JP_PARTS, hipMemcpyHostToDevice, st));
+                HIP_OK(hipMemcpyAsync(ov_slot, slot.data(), sizeof(int32_t) * nparts, hipMemcpyHostToDevice, st));
                 HIP_OK(hipMemcpyAsync(ov_parts, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice,
                                       st));
-                GSS_LAUNCH(k_jp_join, dim3((unsigned)list.size()), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, d_total,
+                GSS_LAUNCH(k_jp_join, dim3((unsigned)list.size()), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, nparts,
+                           d_total,
                            ov_size, ov_buf, arc_cnt, B.indeg, (const int32_t *)ov_parts);
                 ctx->sync();  // the host vectors are the copies' sources
             }
             int2 *arcs = ctx->alloc<int2>(A + 1);
             if (A > 0)
-                GSS_LAUNCH(k_jp_pack, dim3(JP_PARTS), dim3(64), 0, st, arc_buf, arc_cnt, arc_off, arc_slot, ov_slot,
+                GSS_LAUNCH(k_jp_pack, dim3(nparts), dim3(64), 0, st, arc_buf, arc_cnt, arc_off, arc_slot, ov_slot,
                            ov_buf, ov_size, arcs);
             ctx->free(arc_buf);
             ctx->free(ov_slot);
