@@ -276,8 +276,9 @@ def bench_batch(args):
     print(f"[bench] cost model: {len(cyc)} samples, loss {loss[0]:.3f} -> {loss[-1]:.3f}, {train_s:.2f}s",
           file=sys.stderr, flush=True)
 
-    if args.breakdown:  # per-kernel tables of one plain and one batched step (untimed)
-        for label, fn in (("plain", plain_step), ("batched", lambda: batch_step(gss.SCHED_EDGECOUNT))):
+    if args.breakdown:  # per-kernel tables of one plain, one batched and one learned step (untimed)
+        for label, fn in (("plain", plain_step), ("batched", lambda: batch_step(gss.SCHED_EDGECOUNT)),
+                          ("learned", lambda: batch_step(gss.SCHED_LEARNED))):
             torch.cuda.synchronize()
             ctx.profile(True, None)
             fn()
@@ -286,7 +287,7 @@ def bench_batch(args):
             ctx.profile(False)
             tot = sum(v[0] for v in table.values())
             print(f"[bench] {label} step: {tot:.3f} ms of kernels", file=sys.stderr)
-            for k, (ms, nl, nb) in sorted(table.items(), key=lambda kv: -kv[1][0])[:16]:
+            for k, (ms, nl, nb) in sorted(table.items(), key=lambda kv: -kv[1][0])[:24]:
                 print(f"  {k:24s} {ms:9.3f} ms  {nl:5d} launches", file=sys.stderr)
     steps = max(args.steps // 4, 2)
     ms_plain = timed(plain_step, steps)

@@ -183,8 +183,10 @@ int64_t gss_tree_num_edges(gss_tree tree);
  * network of 12 subtask features (GSS_SCHED_LEARNED, BF16 matrix-core inference).  The
  * order never changes the output.  Features of a subtask of S edges with LCA l:
  * log2(1+S); mean and max tree-path hop length d(u)+d(v)-2d(l); mean beta*; share of
- * beta* = 0; mean and max tree degree of the endpoints; log2(1+deg_T(l)); log2(1+d(l));
- * S / (resolved prefix length); log2(1 + total path length); log2(1+S^2).  The target is
+ * beta* = 0; mean and max of deg_T(u)+deg_T(v); log2(1+deg_T(l)); log2(1+d(l));
+ * S / (resolved prefix length); log2(1 + total path length); log2(1+S^2), all from exact
+ * integer sums.  Only queued subtasks are ranked by cost, so only they are featurised and
+ * predicted; the rows of larger subtasks are zero.  The target is
  * log2 of the cycles the work-queue kernel spent on the subtask.  Weights are
  * GSS_COSTMODEL_FLOATS floats: W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3, then the
  * feature mean[12] and standard deviation[12]. */
@@ -200,9 +202,12 @@ gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_bloc
  * size[cap]; any may be NULL) and returns the number of rows held, or -1. */
 int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int64_t cap);
 gss_status gss_trace_clear(gss_ctx ctx);
-/* Trains the cost model on the GPU (FP32 forward/backward/Adam kernels, one workgroup,
- * device-resident for all epochs) from host arrays feat[n][12] and cycles[n]; the target
- * is log2(cycles).  loss: host [epochs] mean squared error per epoch, or NULL. */
+/* Trains the cost model on the GPU (FP32 forward/backward and Adam kernels, data
+ * parallel: each mini-batch is cut into 64-sample slices, one workgroup per slice, and
+ * the slice gradients are summed in a fixed order, so training is deterministic) from
+ * host arrays feat[n][12] and cycles[n]; the target is log2(cycles).  Mini-batches hold
+ * 64 * clamp(n / 16384, 1, 64) samples; rows are visited in a seeded permutation per
+ * epoch.  loss: host [epochs] mean squared error per epoch, or NULL. */
 gss_status gss_costmodel_train(gss_ctx ctx, const float *feat, const double *cycles, int64_t n, int32_t epochs,
                                float lr, uint64_t seed, float *loss);
 /* Loads / saves the weights (host arrays of GSS_COSTMODEL_FLOATS floats). */

@@ -5,9 +5,11 @@
 // prediction (longest first); the recovery output never depends on it.
 //   * inference: layers 1 and 2 on BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k, FP32
 //     accumulation), one wavefront per 16 subtasks; layer 3 in FP32;
-//   * training: one workgroup keeps weights, Adam moments and a 64-sample mini-batch in
-//     LDS and runs forward, MSE loss, backward and the Adam update in FP32 for all epochs,
-//     with no host round trip;
+//   * training: FP32 mini-batch Adam, data parallel: a step's mini-batch is cut into
+//     64-sample slices, one workgroup per slice runs forward, MSE loss and backward in
+//     LDS and writes its share of the gradient, and a second kernel sums the shares in a
+//     fixed order and applies Adam (deterministic; one workgroup and 64-sample batches
+//     for small training sets);
 //   * a gradient-only entry runs the same FP32 forward/backward on one batch (tests).
 // Parameter layout (floats): W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3, then the
 // feature normalisation mean[12] and std[12].
@@ -135,49 +137,50 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
 // ------------------------------------------------------------------------------------
 // training (FP32, one workgroup)
 // ------------------------------------------------------------------------------------
+// Activation rows are padded to HD + 1 floats and feature rows to NF + 1, so that lanes
+// walking samples (stride one row) hit different LDS banks.
 struct TrainLds {
     float w[NPARAM];
-    float x[TB][NF];
-    float z1[TB][HD];
-    float z2[TB][HD];
+    float x[TB][NF + 1];
+    float z1[TB][HD + 1];
+    float z2[TB][HD + 1];
     float dy[TB];
     float y[TB];
 };
 
-// forward + backward of one mini-batch held in LDS; returns the batch MSE (thread 0)
-// and leaves the gradient in g[NPARAM] (global memory, fully overwritten).
-__device__ float mlp_fwd_bwd(TrainLds &L, int nb, float *__restrict__ g)
+// forward + backward of nb <= TB samples held in LDS.  The gradient is that of
+// sum_b (yhat_b - y_b)^2 / denom, written to g[NPARAM] (global memory, fully overwritten);
+// returns the sum of squared errors (thread 0).
+__device__ float mlp_fwd_bwd(TrainLds &L, int nb, float denom, float *__restrict__ g)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    // z1 = x W1^T + b1
+    // z1 = x W1^T + b1  (lanes over samples)
     for (int e = tid; e < nb * HD; e += nt) {
-        int b = e / HD, h = e % HD;
+        int h = e / nb, b = e % nb;
         float s = L.w[OFF_B1 + h];
         for (int k = 0; k < NF; k++) s += L.x[b][k] * L.w[OFF_W1 + h * NF + k];
         L.z1[b][h] = s;
     }
     __syncthreads();
-    // z2 = relu(z1) W2^T + b2
+    // z2 = relu(z1) W2^T + b2  (lanes over samples, weights broadcast)
     for (int e = tid; e < nb * HD; e += nt) {
-        int b = e / HD, h = e % HD;
+        int h = e / nb, b = e % nb;
         float s = L.w[OFF_B2 + h];
         for (int k = 0; k < HD; k++) s += fmaxf(L.z1[b][k], 0.f) * L.w[OFF_W2 + h * HD + k];
         L.z2[b][h] = s;
     }
     __syncthreads();
-    // y_hat, dy = 2 (y_hat - y) / nb
+    // y_hat, dy = 2 (y_hat - y) / denom
     for (int b = tid; b < nb; b += nt) {
         float s = L.w[OFF_B3];
         for (int k = 0; k < HD; k++) s += fmaxf(L.z2[b][k], 0.f) * L.w[OFF_W3 + k];
-        L.dy[b] = 2.f * (s - L.y[b]) / (float)nb;
+        L.dy[b] = 2.f * (s - L.y[b]) / denom;
         L.y[b] = (s - L.y[b]) * (s - L.y[b]);  // squared error, kept for the loss
     }
     __syncthreads();
-    float loss = 0.f;
-    if (tid == 0) {
-        for (int b = 0; b < nb; b++) loss += L.y[b];
-        loss /= (float)nb;
-    }
+    float sse = 0.f;
+    if (tid == 0)
+        for (int b = 0; b < nb; b++) sse += L.y[b];
     // gradients of layer 3
     for (int k = tid; k <= HD; k += nt) {
         float s = 0.f;
@@ -227,10 +230,10 @@ __device__ float mlp_fwd_bwd(TrainLds &L, int nb, float *__restrict__ g)
         }
     }
     __syncthreads();
-    return loss;
+    return sse;
 }
 
-// loads mini-batch rows idx[0..nb) (normalised features, log2 targets) into LDS
+// loads rows (start + b * stride) mod n, b < nb (normalised features, log2 targets) into LDS
 __device__ void load_batch(TrainLds &L, const float *__restrict__ feat, const float *__restrict__ tgt,
                            const float *__restrict__ stats, int64_t n, int64_t start, int nb, int64_t stride)
 {
@@ -243,59 +246,53 @@ __device__ void load_batch(TrainLds &L, const float *__restrict__ feat, const fl
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_mlp_train(float *__restrict__ w, float *__restrict__ mom,
-                                                   float *__restrict__ g, const float *__restrict__ feat,
-                                                   const float *__restrict__ tgt, int64_t n, int32_t epochs,
-                                                   float lr, uint64_t seed, float *__restrict__ loss_out)
+// One training step, forward/backward part: workgroup q takes slice q of the step's
+// mini-batch (rows (offset + (row0 + q * TB + b) * stride) mod n, b < TB, clipped to the
+// rnb rows of the batch) and writes its gradient share gpart[q] and its squared-error
+// sum sse[q].  The shares are scaled by the whole mini-batch size, so they sum to the
+// mini-batch gradient.
+__global__ __launch_bounds__(256) void k_mlp_step(const float *__restrict__ w, const float *__restrict__ feat,
+                                                  const float *__restrict__ tgt, int64_t n, int64_t offset,
+                                                  int64_t stride, int64_t row0, int32_t rnb,
+                                                  float *__restrict__ gpart, float *__restrict__ sse)
 {
     __shared__ TrainLds L;
-    for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) L.w[i] = w[i];
-    __syncthreads();
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const int64_t steps_per_epoch = (n + TB - 1) / TB;
-    // a permutation of the rows per epoch: r = (start + b * stride) mod n with stride
-    // coprime to n
-    int64_t step = 0;
-    float last = 0.f;
-    for (int ep = 0; ep < epochs; ep++) {
-        uint64_t h = mix64(seed + 0x9E3779B97F4A7C15ull * (uint64_t)(ep + 1));
-        int64_t stride = (int64_t)(h % (uint64_t)n) | 1;
-        while (true) {  // make the stride coprime to n
-            int64_t a = stride, bb = n;
-            while (bb) {
-                int64_t t = a % bb;
-                a = bb;
-                bb = t;
-            }
-            if (a == 1) break;
-            stride = (stride + 2) % n;
-            if (stride == 0) stride = 1;
-        }
-        int64_t offset = (int64_t)(mix64(h) % (uint64_t)n);
-        float ep_loss = 0.f;
-        for (int64_t s = 0; s < steps_per_epoch; s++) {
-            int nb = (int)min<int64_t>(TB, n - s * TB);
-            load_batch(L, feat, tgt, w + OFF_MEAN, n, (offset + s * TB * stride) % n, nb, stride);
-            float loss = mlp_fwd_bwd(L, nb, g);
-            if (threadIdx.x == 0) ep_loss += loss * nb;
-            __threadfence_block();
-            __syncthreads();
-            step++;
-            const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-            for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) {
-                float gi = g[i];
-                float m = b1 * mom[i] + (1.f - b1) * gi;
-                float v = b2 * mom[NPARAM + i] + (1.f - b2) * gi * gi;
-                mom[i] = m;
-                mom[NPARAM + i] = v;
-                L.w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
-            }
-            __syncthreads();
-        }
-        last = ep_loss / (float)n;
-        if (threadIdx.x == 0 && loss_out) loss_out[ep] = last;
+    const int q = blockIdx.x;
+    const int nb = min(TB, rnb - q * TB);
+    float *g = gpart + (int64_t)q * NPARAM;
+    if (nb <= 0) {
+        for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) g[i] = 0.f;
+        if (threadIdx.x == 0) sse[q] = 0.f;
+        return;
     }
-    for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) w[i] = L.w[i];
+    for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) L.w[i] = w[i];
+    load_batch(L, feat, tgt, w + OFF_MEAN, n, (offset + (row0 + (int64_t)q * TB) % n * stride) % n, nb, stride);
+    const float e = mlp_fwd_bwd(L, nb, (float)rnb, g);
+    if (threadIdx.x == 0) sse[q] = e;
+}
+
+// One training step, update part: g = sum of the nq shares in slice order, then Adam
+// (step t >= 1) on every parameter; workgroup 0 adds the squared errors to loss[0].
+__global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ w, float *__restrict__ mom,
+                                                  const float *__restrict__ gpart, const float *__restrict__ sse,
+                                                  int32_t nq, int64_t t, float lr, float *__restrict__ loss)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float e = 0.f;
+        for (int q = 0; q < nq; q++) e += sse[q];
+        loss[0] += e;
+    }
+    if (i >= NPARAM) return;
+    float gi = 0.f;
+    for (int q = 0; q < nq; q++) gi += gpart[(int64_t)q * NPARAM + i];
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    const float m = b1 * mom[i] + (1.f - b1) * gi;
+    const float v = b2 * mom[NPARAM + i] + (1.f - b2) * gi * gi;
+    mom[i] = m;
+    mom[NPARAM + i] = v;
+    w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
 // gradient of the batch MSE at the current weights (FP32), for checks against a CPU model
@@ -306,8 +303,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ w, c
     __shared__ TrainLds L;
     for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) L.w[i] = w[i];
     load_batch(L, xraw, tgt, w + OFF_MEAN, nb, 0, nb, 1);
-    float loss = mlp_fwd_bwd(L, nb, g);
-    if (threadIdx.x == 0) *loss_out = loss;
+    const float sse = mlp_fwd_bwd(L, nb, (float)nb, g);
+    if (threadIdx.x == 0) *loss_out = sse / (float)nb;
 }
 
 // feature statistics (mean, std) and log2 targets of a training set
@@ -411,33 +408,75 @@ void costmodel_save(gss_ctx ctx, float *host_w)
     ctx->sync();
 }
 
+// Row order of epoch ep: row (offset + i * stride) mod n for i = 0..n-1, a permutation
+// because the stride is made coprime to n.
+static void epoch_order(uint64_t seed, int32_t ep, int64_t n, int64_t &offset, int64_t &stride)
+{
+    const uint64_t h = mix64(seed + 0x9E3779B97F4A7C15ull * (uint64_t)(ep + 1));
+    stride = (int64_t)(h % (uint64_t)n) | 1;
+    for (;;) {
+        int64_t a = stride, b = n;
+        while (b) {
+            const int64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        if (a == 1) break;
+        stride = (stride + 2) % n;
+        if (stride == 0) stride = 1;
+    }
+    offset = (int64_t)(mix64(h) % (uint64_t)n);
+}
+
 void costmodel_train(gss_ctx ctx, const float *host_feat, const double *host_cycles, int64_t n, int32_t epochs,
                      float lr, uint64_t seed, float *host_loss)
 {
     if (n < 2 || epochs < 1) throw gss_error{GSS_ERR_ARG, "training needs at least 2 samples and 1 epoch"};
     hipStream_t st = ctx->stream;
     ensure_model(ctx);
+    // slices per mini-batch: one for small sets, growing so that an epoch keeps at least
+    // 256 steps, at most 64 (a 4096-sample mini-batch)
+    const int32_t nq = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n / (TB * 256)));
+    const int64_t NB = (int64_t)nq * TB;
+    const int64_t steps_per_epoch = (n + NB - 1) / NB;
     float *feat = ctx->alloc<float>(n * NF);
     double *cyc = ctx->alloc<double>(n);
     float *tgt = ctx->alloc<float>(n);
     float *mom = ctx->alloc<float>(2 * NPARAM);
-    float *g = ctx->alloc<float>(NPARAM);
+    float *gpart = ctx->alloc<float>((int64_t)nq * NPARAM);
+    float *sse = ctx->alloc<float>(nq);
     float *loss = ctx->alloc<float>(epochs);
     HIP_OK(hipMemcpyAsync(feat, host_feat, sizeof(float) * n * NF, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(cyc, host_cycles, sizeof(double) * n, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(mom, 0, sizeof(float) * 2 * NPARAM, st));
+    HIP_OK(hipMemsetAsync(loss, 0, sizeof(float) * epochs, st));
     GSS_LAUNCH(k_mlp_init, dim3(grid_for(NPARAM, 256)), dim3(256), 0, st, ctx->mlp_w, seed);
     GSS_LAUNCH(k_mlp_prepare, dim3(1), dim3(256), 0, st, feat, cyc, n, ctx->mlp_w, tgt);
-    GSS_LAUNCH(k_mlp_train, dim3(1), dim3(256), 0, st, ctx->mlp_w, mom, g, feat, tgt, n, epochs, lr, seed, loss);
+    int64_t t = 0;
+    for (int32_t ep = 0; ep < epochs; ep++) {
+        int64_t offset, stride;
+        epoch_order(seed, ep, n, offset, stride);
+        for (int64_t s = 0; s < steps_per_epoch; s++) {
+            const int32_t rnb = (int32_t)std::min<int64_t>(NB, n - s * NB);
+            GSS_LAUNCH(k_mlp_step, dim3(nq), dim3(256), 0, st, ctx->mlp_w, feat, tgt, n, offset, stride, s * NB, rnb,
+                       gpart, sse);
+            GSS_LAUNCH(k_mlp_adam, dim3(grid_for(NPARAM, 256)), dim3(256), 0, st, ctx->mlp_w, mom, gpart, sse, nq,
+                       ++t, lr, loss + ep);
+        }
+    }
     refresh_bf16(ctx);
-    if (host_loss) HIP_OK(hipMemcpyAsync(host_loss, loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, st));
+    std::vector<float> lh(epochs);
+    HIP_OK(hipMemcpyAsync(lh.data(), loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, st));
     ctx->sync();
+    if (host_loss)
+        for (int32_t ep = 0; ep < epochs; ep++) host_loss[ep] = lh[ep] / (float)n;  // mean squared error
     ctx->model_ready = true;
     ctx->free(feat);
     ctx->free(cyc);
     ctx->free(tgt);
     ctx->free(mom);
-    ctx->free(g);
+    ctx->free(gpart);
+    ctx->free(sse);
     ctx->free(loss);
 }
 

@@ -1296,7 +1296,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         feat = ctx->alloc<float>(nsub * GSS_NFEAT + 1);
         scratch.push_back(feat);
         launch_subtask_features(ctx, (int32_t)nsub, B.sub_ptr, B.sub_lca, B.grp, B.rdu, B.rdv, B.rb, B.ru, B.rv,
-                                t->vrec, P, feat);
+                                t->vrec, P, local_max, feat);
         if (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) {
             pred = ctx->alloc<float>(nsub + 1);
             scratch.push_back(pred);

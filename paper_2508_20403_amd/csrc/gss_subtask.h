@@ -34,7 +34,8 @@ void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
                       const int32_t *grp, int32_t *glist);
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
                              const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
-                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, float *feat);
+                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, int32_t local_max,
+                             float *feat);
 
 // learned cost model (gss_mlp.hip): predicted cost per subtask from its features
 void costmodel_predict(gss_ctx ctx, const float *feat, int64_t nsub, float *pred);

@@ -270,7 +270,63 @@ __global__ void k_join_write(int64_t P, const uint64_t *__restrict__ glca, const
     if (g < P && on_join_path(g, glca, hid, is_local)) glist[pos[g]] = grp[g];
 }
 
-// 12 features per subtask for the cost model (one wave per subtask)
+// 12 features per subtask for the cost model.  They derive from integer sums over the
+// subtask's edges (tree-path lengths below the LCA, beta*, endpoint tree degrees), which
+// are exact and independent of the summation order.  Only queued subtasks (at most
+// local_max edges) are scheduled by cost, so larger ones, which go to the join, get zero
+// rows and no wave ever walks a hub subtask.
+struct FeatSums {
+    unsigned long long path, beta, nb0, deg;
+    int32_t max_path, max_deg;
+};
+
+__device__ __forceinline__ void feat_edge(int32_t p, int32_t lca_depth, const int32_t *__restrict__ rdu,
+                                          const int32_t *__restrict__ rdv, const uint8_t *__restrict__ rb,
+                                          const int32_t *__restrict__ ru, const int32_t *__restrict__ rv,
+                                          const VRec *__restrict__ vrec, FeatSums &a)
+{
+    const int32_t path = rdu[p] - lca_depth + rdv[p] - lca_depth;
+    const int32_t b = rb[p];
+    const int32_t deg = vrec[ru[p]].pad + vrec[rv[p]].pad + 2;
+    a.path += (unsigned long long)path;
+    a.max_path = max(a.max_path, path);
+    a.beta += (unsigned long long)b;
+    a.nb0 += b == 0 ? 1ull : 0ull;
+    a.deg += (unsigned long long)deg;
+    a.max_deg = max(a.max_deg, deg);
+}
+
+__device__ __forceinline__ void feat_wave_reduce(FeatSums &a)
+{
+    for (int d = GSS_WAVE / 2; d > 0; d >>= 1) {
+        a.path += __shfl_xor(a.path, d, GSS_WAVE);
+        a.beta += __shfl_xor(a.beta, d, GSS_WAVE);
+        a.nb0 += __shfl_xor(a.nb0, d, GSS_WAVE);
+        a.deg += __shfl_xor(a.deg, d, GSS_WAVE);
+        a.max_path = max(a.max_path, __shfl_xor(a.max_path, d, GSS_WAVE));
+        a.max_deg = max(a.max_deg, __shfl_xor(a.max_deg, d, GSS_WAVE));
+    }
+}
+
+__device__ __forceinline__ void feat_write(float *__restrict__ f, int32_t size, const FeatSums &a, const VRec &rl,
+                                           int64_t P)
+{
+    const float S = (float)size;
+    f[0] = log2f(1.f + S);
+    f[1] = (float)((double)a.path / size);  // mean tree-path length below the LCA
+    f[2] = (float)a.max_path;
+    f[3] = (float)((double)a.beta / size);  // mean beta*
+    f[4] = (float)((double)a.nb0 / size);   // share of edges with beta* = 0
+    f[5] = (float)((double)a.deg / size);   // mean endpoint tree-degree sum
+    f[6] = (float)a.max_deg;
+    f[7] = log2f(1.f + (float)rl.pad);      // tree degree of the LCA
+    f[8] = log2f(1.f + (float)rl.depth);    // depth of the LCA
+    f[9] = S / fmaxf((float)P, 1.f);        // share of the resolved prefix
+    f[10] = log2f(1.f + (float)a.path);     // total tree-path length
+    f[11] = log2f(1.f + S * S);
+}
+
+// one wave per subtask
 __global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const int32_t *__restrict__ sub_ptr,
                                                           const int32_t *__restrict__ sub_lca,
                                                           const int32_t *__restrict__ grp,
@@ -280,50 +336,21 @@ __global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const in
                                                           const int32_t *__restrict__ ru,
                                                           const int32_t *__restrict__ rv,
                                                           const VRec *__restrict__ vrec, int64_t P,
-                                                          float *__restrict__ feat)
+                                                          int32_t local_max, float *__restrict__ feat)
 {
     const int lane = lane_id();
     const int32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
     if (s >= nsub) return;
     const int32_t g0 = sub_ptr[s], g1 = sub_ptr[s + 1];
-    const int32_t l = sub_lca[s];
-    const VRec rl = vrec[l];
-    float sum_path = 0, max_path = 0, sum_beta = 0, nb0 = 0, sum_deg = 0, max_deg = 0;
-    for (int32_t g = g0 + lane; g < g1; g += GSS_WAVE) {
-        int32_t p = grp[g];
-        float path = (float)(rdu[p] - rl.depth + rdv[p] - rl.depth);
-        sum_path += path;
-        max_path = fmaxf(max_path, path);
-        sum_beta += (float)rb[p];
-        nb0 += rb[p] == 0 ? 1.f : 0.f;
-        float deg = (float)(vrec[ru[p]].pad + vrec[rv[p]].pad + 2);
-        sum_deg += deg;
-        max_deg = fmaxf(max_deg, deg);
+    if (g1 - g0 > local_max) {
+        if (lane < GSS_NFEAT) feat[(int64_t)s * GSS_NFEAT + lane] = 0.f;
+        return;
     }
-    for (int d = 32; d > 0; d >>= 1) {
-        sum_path += __shfl_xor(sum_path, d, GSS_WAVE);
-        max_path = fmaxf(max_path, __shfl_xor(max_path, d, GSS_WAVE));
-        sum_beta += __shfl_xor(sum_beta, d, GSS_WAVE);
-        nb0 += __shfl_xor(nb0, d, GSS_WAVE);
-        sum_deg += __shfl_xor(sum_deg, d, GSS_WAVE);
-        max_deg = fmaxf(max_deg, __shfl_xor(max_deg, d, GSS_WAVE));
-    }
-    if (lane == 0) {
-        float S = (float)(g1 - g0);
-        float *f = feat + (int64_t)s * GSS_NFEAT;
-        f[0] = log2f(1.f + S);
-        f[1] = sum_path / S;
-        f[2] = max_path;
-        f[3] = sum_beta / S;
-        f[4] = nb0 / S;
-        f[5] = sum_deg / S;
-        f[6] = max_deg;
-        f[7] = log2f(1.f + (float)rl.pad);
-        f[8] = log2f(1.f + (float)rl.depth);
-        f[9] = S / fmaxf((float)P, 1.f);  // share of the resolved prefix
-        f[10] = log2f(1.f + sum_path);    // total tree-path length
-        f[11] = log2f(1.f + S * S);
-    }
+    const VRec rl = vrec[sub_lca[s]];
+    FeatSums a = {0, 0, 0, 0, 0, 0};
+    for (int32_t g = g0 + lane; g < g1; g += GSS_WAVE) feat_edge(grp[g], rl.depth, rdu, rdv, rb, ru, rv, vrec, a);
+    feat_wave_reduce(a);
+    if (lane == 0) feat_write(feat + (int64_t)s * GSS_NFEAT, g1 - g0, a, rl, P);
 }
 
 void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32_t *head)
@@ -359,8 +386,9 @@ void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
 
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
                              const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
-                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, float *feat)
+                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, int32_t local_max,
+                             float *feat)
 {
     GSS_LAUNCH(k_subtask_features, dim3(grid_for((int64_t)nsub * GSS_WAVE, 256)), dim3(256), 0, ctx->stream, nsub,
-               sub_ptr, sub_lca, grp, rdu, rdv, rb, ru, rv, vrec, P, feat);
+               sub_ptr, sub_lca, grp, rdu, rdv, rb, ru, rv, vrec, P, local_max, feat);
 }

@@ -52,6 +52,26 @@ def test_training_fits_a_smooth_target(gpu_ctx):
     assert np.mean((y_cpu - logc) ** 2) < 0.15 * np.var(logc)
 
 
+def test_data_parallel_training_is_deterministic(gpu_ctx):
+    """A training set large enough for several 64-sample slices per mini-batch (40000
+    rows: two workgroups per step): the fixed-order gradient sum makes two runs with one
+    seed give bit-identical weights, and the fit still converges."""
+    rng = np.random.default_rng(12)
+    n = 40000
+    x = rng.normal(0, 1, (n, mlp.NF)).astype(np.float32)
+    logc = 10 + 2 * x[:, 0] + np.abs(x[:, 1]) - 0.5 * x[:, 2] * x[:, 3]
+    cyc = np.exp2(logc).astype(np.float64)
+    loss1 = gpu_ctx.costmodel_train(x, cyc, epochs=8, lr=3e-3, seed=4)
+    w1 = gpu_ctx.costmodel_save()
+    loss2 = gpu_ctx.costmodel_train(x, cyc, epochs=8, lr=3e-3, seed=4)
+    w2 = gpu_ctx.costmodel_save()
+    assert np.array_equal(w1.view(np.uint32), w2.view(np.uint32))
+    assert np.array_equal(loss1, loss2)
+    assert loss1[-1] < 0.5 * loss1[0] and loss1[-1] < 0.1 * np.var(logc), (loss1, np.var(logc))
+    y_cpu, _ = mlp.forward(w1.astype(np.float64), x.astype(np.float64))
+    assert np.mean((y_cpu - logc) ** 2) < 0.15 * np.var(logc)
+
+
 def test_learned_schedule_is_bit_exact(gpu_ctx):
     g = synth.config("grid3d_32")
     gpu_ctx.trace_clear()
