@@ -270,6 +270,24 @@ def bench_batch(args):
     feat, cyc, size = ctx.trace_read()
     ctx.trace_clear()
     b.free()
+    # held-out error: subtasks (identified by their feature row, so the repeated
+    # recordings of one subtask fall on one side) split 4:1; the model trained on the
+    # larger part predicts the rest, next to a least-squares fit of log2(cycles) on
+    # log2(1 + edge count), the information the edge-count schedule uses
+    hkey = np.frombuffer(np.ascontiguousarray(feat, np.float32).tobytes(), np.uint32).reshape(len(cyc), -1)
+    hkey = (hkey.astype(np.uint64) * np.uint64(0x9E3779B1)).sum(axis=1) % np.uint64(5)
+    held, fit = hkey == 0, hkey != 0
+    heldout = None
+    if held.sum() >= 16 and fit.sum() >= 16:
+        ctx.costmodel_train(feat[fit], cyc[fit], epochs=args.epochs, lr=1e-3, seed=0)
+        pred = ctx.costmodel_predict(torch.from_numpy(np.ascontiguousarray(feat[held])).to(dev)).cpu().numpy()
+        y = np.log2(np.maximum(cyc, 1.0))
+        A = np.stack([np.ones(len(cyc)), np.log2(1.0 + size)], axis=1)
+        coef = np.linalg.lstsq(A[fit], y[fit], rcond=None)[0]
+        heldout = {"samples": int(held.sum()),
+                   "mlp_median_abs_log2_err": round(float(np.median(np.abs(pred - y[held]))), 4),
+                   "edgecount_fit_median_abs_log2_err": round(float(np.median(np.abs(A[held] @ coef - y[held]))), 4)}
+        print(f"[bench] held-out cost error (median |log2 pred/measured|): {heldout}", file=sys.stderr, flush=True)
     t = time.perf_counter()
     loss = ctx.costmodel_train(feat, cyc, epochs=args.epochs, lr=1e-3, seed=0)
     train_s = time.perf_counter() - t
@@ -318,7 +336,7 @@ def bench_batch(args):
                    "autotune": {"local_max": lm, "blocks": lb},
                    "costmodel": {"samples": int(len(cyc)), "epochs": args.epochs,
                                  "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
-                                 "train_s": round(train_s, 3)}},
+                                 "train_s": round(train_s, 3), "heldout": heldout}},
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -137,15 +137,19 @@ gss_status gss_recover(gss_ctx ctx, gss_tree tree, const gss_params *params, uin
  * gss_batch_prep copies nb graphs (host array of device CSRs, host array of device
  * parent arrays) into one disjoint union whose trees hang under a virtual root with
  * zero-resistance links, validates every graph as gss_tree_prep does, and prepares the
- * union once.  Edge ids, masks and orders stay per graph.  The caller's arrays may be
- * released after the call.  Errors: as gss_tree_prep. */
+ * union once.  A graph with at least the batch split size of CSR entries (default 2^25,
+ * gss_ctx_set_batch_split) fills the GPU by itself: it is prepared on its own, as by
+ * gss_tree_prep, without a copy, and recovered by its own pass; so is a single graph
+ * left over.  Edge ids, masks and orders stay per graph.  The caller keeps the arrays
+ * alive and unchanged until gss_tree_free.  Errors: as gss_tree_prep. */
 gss_status gss_batch_prep(gss_ctx ctx, int32_t nb, const gss_csr *graphs, const int32_t *const *parents,
                           uint32_t flags, gss_tree *out);
 /* Recovers every graph of a batch tree: params, masks (device uint8 [m_g]) and orders
  * (device int32 [K_g], or NULL for the whole array or an entry) are host arrays of nb;
  * infos host [nb] or NULL.  All graphs must use the same beta and schedule.  Subtasks of
- * all graphs share one work queue and one persistent launch.  Returns GSS_SHORT if any
- * graph had fewer than K_g off-tree edges. */
+ * all graphs of the union share one work queue and one persistent launch; graphs prepared
+ * on their own follow, one pass each.  Returns GSS_SHORT if any graph had fewer than K_g
+ * off-tree edges. */
 gss_status gss_recover_batch(gss_ctx ctx, gss_tree batch, const gss_params *params, uint8_t *const *masks,
                              int32_t *const *orders, gss_info *infos);
 /* Autotuner of the work-queue settings (gss_ctx_set_tuning) for a tree (a single graph or
@@ -194,6 +198,9 @@ int64_t gss_tree_num_edges(gss_tree tree);
 #define GSS_COSTMODEL_FLOATS 5081
 #define GSS_COSTMODEL_PARAMS 5057
 
+/* Sets the batch split size (CSR entries, >= 0; 0 prepares every graph of a batch on its
+ * own).  Errors: ARG. */
+gss_status gss_ctx_set_batch_split(gss_ctx ctx, int64_t own_nnz);
 /* Sets the work-queue limits: subtasks of at most local_max edges (0..1024; 0 sends every
  * subtask to the hash join) use the persistent kernel, which runs local_blocks (1..65536)
  * workgroups of four wavefronts.  Returns GSS_ERR_ARG outside those ranges. */

@@ -30,6 +30,66 @@ gss_status guarded(gss_ctx ctx, F &&f)
 }
 }  // namespace
 
+// frees a tree, its parts and the arrays it owns
+static void delete_tree(gss_tree t)
+{
+    for (gss_tree p : t->parts) delete_tree(p);
+    free_tree_arrays(t);
+    delete t;
+}
+
+// one graph on its own, borrowing the caller's arrays (as gss_tree_prep)
+static gss_tree prep_single_part(gss_ctx ctx, const gss_csr &g, const int32_t *parent, uint32_t flags)
+{
+    if (g.nnz >= ((int64_t)1 << 31) || g.n >= (1 << 30)) throw gss_error{GSS_ERR_ARG, "graph too large"};
+    gss_tree t = new gss_tree_s();
+    t->ctx = ctx;
+    t->n = g.n;
+    t->nnz = g.nnz;
+    t->row_ptr = g.row_ptr;
+    t->col = g.col;
+    t->w = g.w;
+    t->parent = parent;
+    try {
+        prep_tree(ctx, t, flags);
+    } catch (...) {
+        (void)hipStreamSynchronize(ctx->stream);
+        delete_tree(t);
+        throw;
+    }
+    return t;
+}
+
+// recover_impl over a batch tree: the union and every graph prepared on its own in turn
+gss_status recover_batch_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t *const *masks,
+                              int32_t *const *orders, gss_info *infos)
+{
+    if (t->parts.empty()) return recover_impl(ctx, t, prms, masks, orders, nullptr, infos);
+    gss_status worst = GSS_OK;
+    for (size_t q = 0; q < t->parts.size(); q++) {
+        std::vector<gss_params> pp;
+        std::vector<uint8_t *> mp;
+        std::vector<int32_t *> op;
+        std::vector<int32_t> gid;
+        for (int32_t g = 0; g < t->G; g++)
+            if (t->part_of[g] == (int32_t)q) gid.push_back(g);
+        std::sort(gid.begin(), gid.end(), [&](int32_t a, int32_t b) { return t->part_idx[a] < t->part_idx[b]; });
+        for (int32_t g : gid) {
+            pp.push_back(prms[g]);
+            mp.push_back(masks[g]);
+            op.push_back(orders ? orders[g] : nullptr);
+        }
+        std::vector<gss_info> ip(gid.size());
+        const gss_status s = recover_impl(ctx, t->parts[q], pp.data(), mp.data(), orders ? op.data() : nullptr,
+                                          nullptr, infos ? ip.data() : nullptr);
+        if (s < 0) return s;
+        if (s > worst) worst = s;
+        if (infos)
+            for (size_t i = 0; i < gid.size(); i++) infos[gid[i]] = ip[i];
+    }
+    return worst;
+}
+
 extern "C" {
 
 gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
@@ -134,18 +194,56 @@ gss_status gss_batch_prep(gss_ctx ctx, int32_t nb, const gss_csr *graphs, const 
             return GSS_ERR_ARG;
         }
     }
+    // graphs that fill the GPU by themselves are prepared and recovered on their own (no
+    // copy into the union); the rest share one union
+    std::vector<int32_t> own, rest;
+    for (int32_t g = 0; g < nb; g++) (graphs[g].nnz >= ctx->batch_own_nnz ? own : rest).push_back(g);
+    if (rest.size() == 1) {
+        own.push_back(rest[0]);
+        rest.clear();
+    }
     gss_tree t = new (std::nothrow) gss_tree_s();
     if (!t) return GSS_ERR_OOM;
     t->ctx = ctx;
     gss_status s = guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
-        prep_batch(ctx, t, nb, graphs, parents, flags);
+        if (own.empty()) {
+            prep_batch(ctx, t, nb, graphs, parents, flags);
+            return GSS_OK;
+        }
+        t->G = nb;
+        t->part_of.assign(nb, 0);
+        t->part_idx.assign(nb, 0);
+        t->n = 0;
+        if (!rest.empty()) {
+            std::vector<gss_csr> gs;
+            std::vector<const int32_t *> ps;
+            for (size_t i = 0; i < rest.size(); i++) {
+                gs.push_back(graphs[rest[i]]);
+                ps.push_back(parents[rest[i]]);
+                t->part_of[rest[i]] = 0;
+                t->part_idx[rest[i]] = (int32_t)i;
+            }
+            gss_tree u = new gss_tree_s();
+            u->ctx = ctx;
+            t->parts.push_back(u);  // freed with t on failure
+            prep_batch(ctx, u, (int32_t)rest.size(), gs.data(), ps.data(), flags);
+        }
+        for (int32_t g : own) {
+            t->part_of[g] = (int32_t)t->parts.size();
+            t->part_idx[g] = 0;
+            t->parts.push_back(prep_single_part(ctx, graphs[g], parents[g], flags));
+        }
+        for (gss_tree p : t->parts) {
+            t->n += p->n;
+            t->m += p->m;
+            t->M += p->M;
+        }
         return GSS_OK;
     });
     if (s != GSS_OK) {
         (void)hipStreamSynchronize(ctx->stream);
-        free_tree_arrays(t);
-        delete t;
+        delete_tree(t);
         return s;
     }
     *out = t;
@@ -157,8 +255,14 @@ int32_t gss_tree_num_graphs(gss_tree t) { return t ? t->G : -1; }
 int64_t gss_tree_graph_edges(gss_tree t, int32_t g)
 {
     if (!t || g < 0 || g >= t->G) return -1;
+    if (!t->parts.empty()) {
+        gss_tree p = t->parts[t->part_of[g]];
+        return p->ebase.empty() ? p->m : gss_tree_graph_edges(p, t->part_idx[g]);
+    }
+    if (t->ebase.empty()) return t->m;
     return t->ebase[g + 1] - t->ebase[g];
 }
+
 
 gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, uint8_t *const *masks,
                              int32_t *const *orders, gss_info *infos)
@@ -179,7 +283,7 @@ gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, 
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         ctx->record = (params[0].flags & GSS_F_RECORD) != 0;
-        gss_status s = recover_impl(ctx, t, params, masks, orders, nullptr, infos);
+        gss_status s = recover_batch_impl(ctx, t, params, masks, orders, infos);
         ctx->record = false;
         return s;
     });
@@ -200,8 +304,7 @@ gss_status gss_tree_free(gss_tree t)
 {
     if (!t) return GSS_ERR_ARG;
     (void)hipStreamSynchronize(t->ctx->stream);
-    free_tree_arrays(t);
-    delete t;
+    delete_tree(t);
     return GSS_OK;
 }
 
@@ -223,7 +326,8 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         ctx->record = (p->flags & GSS_F_RECORD) != 0;
-        if (t->virt_root >= 0) throw gss_error{GSS_ERR_ARG, "a batch tree needs gss_recover_batch"};
+        if (t->virt_root >= 0 || !t->parts.empty())
+            throw gss_error{GSS_ERR_ARG, "a batch tree needs gss_recover_batch"};
         uint8_t *masks[1] = {mask};
         int32_t *orders[1] = {order};
         gss_status s = recover_impl(ctx, t, p, masks, order ? orders : nullptr, stretch, info);
@@ -235,6 +339,10 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
 gss_status gss_tree_export(gss_tree t, int32_t *depth, uint64_t *Dlo, uint64_t *Dhi, int32_t *scale)
 {
     if (!t) return GSS_ERR_ARG;
+    if (!t->parts.empty()) {
+        t->ctx->last_error = "a batch with graphs prepared on their own has no single tree";
+        return GSS_ERR_ARG;
+    }
     gss_ctx ctx = t->ctx;
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
@@ -254,6 +362,10 @@ gss_status gss_tree_export(gss_tree t, int32_t *depth, uint64_t *Dlo, uint64_t *
 gss_status gss_edge_lca(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar)
 {
     if (!ctx || !t || t->ctx != ctx || beta < 0 || beta > GSS_MAX_BETA) return GSS_ERR_ARG;
+    if (!t->parts.empty()) {
+        ctx->last_error = "a batch with graphs prepared on their own has no single tree";
+        return GSS_ERR_ARG;
+    }
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         edge_lca_impl(ctx, t, beta, lca, bstar);
@@ -299,6 +411,13 @@ gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_bloc
         return GSS_ERR_ARG;
     ctx->local_max = local_max;
     ctx->local_blocks = local_blocks;
+    return GSS_OK;
+}
+
+gss_status gss_ctx_set_batch_split(gss_ctx ctx, int64_t own_nnz)
+{
+    if (!ctx || own_nnz < 0) return GSS_ERR_ARG;
+    ctx->batch_own_nnz = own_nnz;
     return GSS_OK;
 }
 

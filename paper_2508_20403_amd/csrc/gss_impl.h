@@ -63,6 +63,7 @@ struct gss_ctx_s {
     // subtask engine settings (autotuned) and the learned cost model
     int32_t local_max = 64;       // subtasks up to this size use the persistent kernel
     int32_t local_blocks = 2048;  // workgroups of the persistent kernel (4 wavefronts each)
+    int64_t batch_own_nnz = (int64_t)1 << 25;  // batch graphs this large are prepared on their own
     bool record = false;          // record per-subtask features and cycles
     bool model_ready = false;     // cost-model weights loaded
     std::vector<float> trace_feat;      // [rows * 12]
@@ -140,6 +141,10 @@ struct gss_tree_s {
     // union arrays owned by a batch tree
     int32_t *own_row_ptr = nullptr, *own_col = nullptr, *own_parent = nullptr;
     double *own_w = nullptr;
+    // a batch split into parts (a union of the smaller graphs and every large graph on
+    // its own): graph g of the batch is graph part_idx[g] of parts[part_of[g]]
+    std::vector<gss_tree_s *> parts;
+    std::vector<int32_t> part_of, part_idx;
 };
 
 // ---- host entry points of the translation units --------------------------------------
@@ -149,6 +154,9 @@ void prep_batch(gss_ctx ctx, gss_tree t, int32_t G, const gss_csr *gs, const int
 void free_tree_arrays(gss_tree t);
 gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t *const *masks,
                         int32_t *const *orders, double *stretch, gss_info *infos);
+// recover_impl over a batch tree, part by part when it is split
+gss_status recover_batch_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t *const *masks,
+                              int32_t *const *orders, gss_info *infos);
 void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar);
 gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *const *masks,
                          int32_t *const *orders, const char *cache_path, int32_t *out_lm, int32_t *out_lb,

@@ -70,7 +70,7 @@ gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *
             double t_best = 1e300;
             for (int rep = 0; rep < 2; rep++) {
                 HIP_OK(hipEventRecord(a, ctx->stream));
-                gss_status s = recover_impl(ctx, t, p, masks, orders, nullptr, nullptr);
+                gss_status s = recover_batch_impl(ctx, t, p, masks, orders, nullptr);
                 HIP_OK(hipEventRecord(b, ctx->stream));
                 HIP_OK(hipEventSynchronize(b));
                 if (s < 0) {

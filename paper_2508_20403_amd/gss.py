@@ -29,7 +29,7 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_ctx_profile_read", "gss_ctx_set_tuning", "gss_trace_read", "gss_trace_clear",
            "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
            "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
-           "gss_tree_graph_edges", "gss_autotune"]
+           "gss_tree_graph_edges", "gss_autotune", "gss_ctx_set_batch_split"]
 GSS_F_RECORD = 2
 GSS_F_STATS = 4
 NFEAT = 12
@@ -108,6 +108,8 @@ def load_library(path=LIB_PATH):
     lib.gss_costmodel_grad.argtypes = [P, P, P, ctypes.c_int32, P, P]
     lib.gss_batch_prep.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_uint32, ctypes.POINTER(P)]
     lib.gss_recover_batch.argtypes = [P, P, P, P, P, P]
+    lib.gss_ctx_set_batch_split.argtypes = [P, ctypes.c_int64]
+    lib.gss_ctx_set_batch_split.restype = ctypes.c_int32
     lib.gss_tree_num_graphs.argtypes = [P]
     lib.gss_tree_num_graphs.restype = ctypes.c_int32
     lib.gss_tree_graph_edges.argtypes = [P, ctypes.c_int32]
@@ -173,6 +175,10 @@ class Context:
         return out
 
     # ---- subtask scheduling and the learned cost model --------------------------------
+    def set_batch_split(self, own_nnz):
+        """Batch graphs with at least own_nnz CSR entries are prepared on their own."""
+        self.check(self.lib.gss_ctx_set_batch_split(self.handle, int(own_nnz)))
+
     def set_tuning(self, local_max, local_blocks):
         self.check(self.lib.gss_ctx_set_tuning(self.handle, int(local_max), int(local_blocks)))
 
@@ -329,6 +335,7 @@ class Batch:
         self.graphs = list(graphs)
         nb = len(self.graphs)
         t = lambda a: torch.from_numpy(a).to(device)  # noqa: E731
+        # kept alive with the batch: graphs prepared on their own are borrowed, not copied
         self.arrays = arrays if arrays is not None else \
             [(t(g.row_ptr), t(g.col), t(g.w), t(g.parent)) for g in self.graphs]
         csrs = (Csr * nb)()
@@ -342,7 +349,6 @@ class Batch:
                                     ctypes.cast(parents, ctypes.c_void_p), GSS_PREP_TRUSTED if trusted else 0,
                                     ctypes.byref(self.handle))
         ctx.check(st)
-        self.arrays = None  # the union holds copies of the graphs
         self.m = [ctx.lib.gss_tree_graph_edges(self.handle, i) for i in range(nb)]
         self.n = [g.n for g in self.graphs]
 

@@ -46,6 +46,33 @@ def test_batch_matches_per_graph_oracle(gpu_ctx, seed):
     b.free()
 
 
+@pytest.mark.parametrize("split", ["median", "all_own", "one_left"])
+def test_batch_split_matches_per_graph_oracle(gpu_ctx, split):
+    """Graphs at or above the batch split size are prepared and recovered on their own,
+    the rest share the union; every graph still matches its oracle run, the schedule
+    (edge count or learned) does not matter, and infos map back to the right graphs."""
+    graphs = small_batch(2)
+    nnz = sorted(len(g.col) for g in graphs)
+    limit = {"median": nnz[len(nnz) // 2], "all_own": 0, "one_left": nnz[1]}[split]
+    print(f"[gpu-batch] split {split}: limit {limit}, nnz {nnz}", flush=True)
+    gpu_ctx.set_batch_split(limit)
+    try:
+        b = gss.Batch(gpu_ctx, graphs)
+    finally:
+        gpu_ctx.set_batch_split(1 << 25)
+    assert [gss_m for gss_m in b.m] == [g.m for g in graphs]
+    st, masks, orders, infos = b.recover(stats=True)
+    torch.cuda.synchronize()
+    for g, mk, od, inf in zip(graphs, masks, orders, infos):
+        ref = oracle.recover(g)
+        nrec = ref.info["n_recovered"]
+        assert inf["n_recovered"] == nrec and inf["k"] == ref.K and inf["m"] == g.m
+        assert inf["n_subtasks"] == ref.info["n_subtasks"]
+        np.testing.assert_array_equal(mk.cpu().numpy(), ref.mask)
+        np.testing.assert_array_equal(od.cpu().numpy()[:nrec], ref.order[:nrec])
+    b.free()
+
+
 def test_batch_of_one_equals_single(gpu_ctx):
     g = synth.config("grid3d_32")
     b = gss.Batch(gpu_ctx, [g])

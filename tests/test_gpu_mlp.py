@@ -85,3 +85,36 @@ def test_learned_schedule_is_bit_exact(gpu_ctx):
     for sched in (gss.SCHED_LEARNED, gss.SCHED_EDGECOUNT):
         gpu = run_gpu(gpu_ctx, g, sched=sched)
         assert_same_recovery(gpu, orc)
+
+
+def test_trained_model_beats_edge_count_on_held_out_subtasks(gpu_ctx):
+    """What the trained network gains over the schedule without it: on subtasks it never
+    saw (split by feature row, so repeated recordings of one subtask stay on one side),
+    its median |log2(predicted / measured cycles)| is below that of the best
+    least-squares fit of log2(cycles) on log2(1 + edge count), the only information the
+    edge-count schedule has."""
+    graphs = synth.batch_config(count=8, nmin=2e4, nmax=2e5, seed=1)
+    b = gss.Batch(gpu_ctx, graphs)
+    gpu_ctx.set_tuning(256, 1024)
+    try:
+        gpu_ctx.trace_clear()
+        for _ in range(3):
+            b.recover(record=True)
+        feat, cyc, size = gpu_ctx.trace_read()
+        gpu_ctx.trace_clear()
+    finally:
+        gpu_ctx.set_tuning(64, 2048)
+        b.free()
+    assert len(cyc) > 1000
+    key = np.frombuffer(feat.tobytes(), np.uint32).reshape(len(cyc), -1).astype(np.uint64)
+    key = (key * np.uint64(0x9E3779B1)).sum(axis=1) % np.uint64(5)
+    held, fit = key == 0, key != 0
+    gpu_ctx.costmodel_train(feat[fit], cyc[fit], epochs=20, lr=1e-3, seed=0)
+    pred = gpu_ctx.costmodel_predict(torch.from_numpy(np.ascontiguousarray(feat[held])).cuda()).cpu().numpy()
+    y = np.log2(np.maximum(cyc, 1.0))
+    A = np.stack([np.ones(len(cyc)), np.log2(1.0 + size)], axis=1)
+    coef = np.linalg.lstsq(A[fit], y[fit], rcond=None)[0]
+    err_mlp = np.median(np.abs(pred - y[held]))
+    err_cnt = np.median(np.abs(A[held] @ coef - y[held]))
+    print(f"held-out median |log2 error|: network {err_mlp:.3f}, edge-count fit {err_cnt:.3f}")
+    assert err_mlp < err_cnt, (err_mlp, err_cnt)
