@@ -82,18 +82,27 @@ struct RmqLoads {
     uint64_t psuf, ppre, pmask, bsuf, bpre, bmask, st0, st1;
 };
 
+// Only the loads the query's case needs are issued: the position-level arrays are far
+// larger than the caches, so a wasted load there costs a random HBM access.
 __device__ __forceinline__ RmqLoads rmq_issue(const RmqView &q, const RmqPlan &P)
 {
-    RmqLoads L;
-    L.pmask = q.pmask[P.j];
-    L.psuf = q.psuf[P.i];
-    L.ppre = q.ppre[P.j];
-    L.bmask = q.bmask[P.b1];
-    L.bsuf = q.bsuf[P.b0];
-    L.bpre = q.bpre[P.b1];
-    const uint64_t *lv = q.sbst + (int64_t)P.k * q.nsb;
-    L.st0 = lv[P.a];
-    L.st1 = lv[P.c - (P.has_super ? (1 << P.k) - 1 : 0)];
+    RmqLoads L = {~0ull, ~0ull, 0ull, ~0ull, ~0ull, 0ull, ~0ull, ~0ull};
+    if (P.same_block) {
+        L.pmask = q.pmask[P.j];
+    } else {
+        L.psuf = q.psuf[P.i];
+        L.ppre = q.ppre[P.j];
+    }
+    if (P.has_blocks) {
+        L.bmask = q.bmask[P.b1];
+        L.bsuf = q.bsuf[P.b0];
+        L.bpre = q.bpre[P.b1];
+    }
+    if (P.has_super) {
+        const uint64_t *lv = q.sbst + (int64_t)P.k * q.nsb;
+        L.st0 = lv[P.a];
+        L.st1 = lv[P.c - (1 << P.k) + 1];
+    }
     return L;
 }
 
