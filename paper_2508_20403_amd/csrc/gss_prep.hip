@@ -39,12 +39,39 @@ __device__ __forceinline__ int32_t row_of(const int32_t *__restrict__ row_ptr, i
 }
 
 // index of key in the sorted range col[lo,hi), or -1
+__device__ __forceinline__ int64_t clamp_idx(int64_t x, int64_t lo, int64_t hi)
+{
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// Position of key in the sorted columns [lo, hi), or -1.  Long rows are first narrowed
+// by interpolation between the end columns (a few steps on rows whose columns spread
+// evenly, as hub rows of relabelled graphs do; at most four, so skewed rows cost no more
+// than four extra loads), then bisected.
 __device__ __forceinline__ int64_t find_in_row(const int32_t *__restrict__ col, int64_t lo, int64_t hi,
                                                int32_t key)
 {
-    int64_t end = hi;
+    const int64_t end = hi;
+    if (hi - lo > 32) {
+        int32_t a = col[lo], b = col[hi - 1];
+        for (int step = 0; step < 4 && hi - lo > 32; step++) {
+            if (key < a || key > b) return -1;
+            // a <= key <= b: a guess inside [lo, hi)
+            const int64_t mid = clamp_idx(
+                lo + (int64_t)((double)(key - a) / ((double)(b - a) + 1.0) * (double)(hi - lo)), lo, hi - 1);
+            const int32_t c = col[mid];
+            if (c == key) return mid;
+            if (c < key) {
+                lo = mid + 1;
+                a = col[lo];  // lo < hi: c < key <= b = col[hi - 1]
+            } else {
+                hi = mid;
+                b = col[hi - 1];  // hi > lo: a <= key < c
+            }
+        }
+    }
     while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
+        const int64_t mid = lo + ((hi - lo) >> 1);
         if (col[mid] < key) lo = mid + 1;
         else hi = mid;
     }
@@ -58,10 +85,6 @@ __device__ __forceinline__ int64_t find_in_row(const int32_t *__restrict__ col, 
 // ------------------------------------------------------------------------------------
 #define ETILE (PB * ENT_ITEMS)
 
-__device__ __forceinline__ int64_t clamp_idx(int64_t x, int64_t lo, int64_t hi)
-{
-    return x < lo ? lo : (x > hi ? hi : x);
-}
 
 // tile_row[b] = the row holding entry b*ETILE: one thread per row marks the tiles that
 // start inside it (row_ptr reads are clamped, so malformed input yields wrong but
