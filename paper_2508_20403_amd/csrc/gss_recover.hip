@@ -643,31 +643,67 @@ struct JRec {
 __device__ __forceinline__ uint64_t jp_hash(uint64_t ab) { return mix64(ab * 0x9E3779B97F4A7C15ull + 1); }
 __device__ __forceinline__ uint32_t jp_part(uint64_t ab, int bits) { return (uint32_t)(jp_hash(ab) >> (64 - bits)); }
 
-// record slot s = (listed edge gi, r): r < 2(c+1)^2 build, then (c+1)^2 probe slots.
-// Stage 1 reads the rank, stage 2 the ancestors, so that a batch of slots has all its
-// loads of one stage in flight together.
-__device__ __forceinline__ int32_t jp_rank(int64_t s, int64_t nslots, int32_t S, const int32_t *__restrict__ glist)
+// record slot s = (listed edge g, r) = g * S + r: r < 2(c+1)^2 build, then (c+1)^2 probe
+// slots.  A workgroup divides its first slot by S once; every other slot is a small
+// offset from it, split by a float reciprocal with one correction step (offsets stay
+// below 2^24, so the estimate is within one of the quotient).  r is split by (c+1) and
+// (c+1)^2 with 16-bit multiply-shift reciprocals, exact for r < 3(c+1)^2 <= 243.
+struct JpSlots {
+    int64_t g0;
+    int32_t r0, S;
+    float invS;
+    int32_t C1, C1sq;
+    uint32_t M1, M2;  // ceil(2^16 / (c+1)), ceil(2^16 / (c+1)^2)
+};
+__device__ __forceinline__ JpSlots jp_slots(int64_t s0, int32_t c)
 {
-    return s < nslots ? glist[s / S] : -1;
+    JpSlots b;
+    b.C1 = c + 1;
+    b.C1sq = b.C1 * b.C1;
+    b.S = 3 * b.C1sq;
+    b.g0 = s0 / b.S;
+    b.r0 = (int32_t)(s0 - b.g0 * b.S);
+    b.invS = 1.0f / (float)b.S;
+    b.M1 = (65536u + b.C1 - 1) / b.C1;
+    b.M2 = (65536u + b.C1sq - 1) / b.C1sq;
+    return b;
 }
-__device__ __forceinline__ bool jp_record(int64_t s, int32_t S, int32_t p, int64_t P, int32_t c,
+__device__ __forceinline__ void jp_slot(const JpSlots &b, int32_t o, int64_t &g, int32_t &r)
+{
+    const int32_t x = b.r0 + o;
+    int32_t q = (int32_t)((float)x * b.invS);
+    int32_t rem = x - q * b.S;
+    if (rem >= b.S) {
+        q++;
+        rem -= b.S;
+    } else if (rem < 0) {
+        q--;
+        rem += b.S;
+    }
+    g = b.g0 + q;
+    r = rem;
+}
+// rank of listed edge g (-1 past the list)
+__device__ __forceinline__ int32_t jp_rank(int64_t g, int64_t ng, const int32_t *__restrict__ glist)
+{
+    return g < ng ? glist[g] : -1;
+}
+__device__ __forceinline__ bool jp_record(const JpSlots &sl, int32_t r, int32_t p, int64_t P,
                                           const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
                                           const int32_t *__restrict__ ancV, JRec &rec)
 {
     if (p < 0) return false;
-    const int C1 = c + 1, nb = 2 * C1 * C1;
-    int r = (int)(s % S);
     int32_t A, B;
-    if (r < nb) {
-        const int orient = r / (C1 * C1);
-        r -= orient * C1 * C1;
-        const int i = r / C1, k = r % C1;
+    if (r < 2 * sl.C1sq) {
+        const int32_t orient = (int32_t)(((uint32_t)r * sl.M2) >> 16);
+        const int32_t q = r - orient * sl.C1sq;
+        const int32_t i = (int32_t)(((uint32_t)q * sl.M1) >> 16), k = q - i * sl.C1;
         A = (orient ? ancV : ancU)[(int64_t)i * P + p];
         B = (orient ? ancU : ancV)[(int64_t)k * P + p];
         rec.meta = ((uint32_t)i << 8) | (uint32_t)k;
     } else {
-        r -= nb;
-        const int j = r / C1, l = r % C1;
+        const int32_t q = r - 2 * sl.C1sq;
+        const int32_t j = (int32_t)(((uint32_t)q * sl.M1) >> 16), l = q - j * sl.C1;
         const int beta = rb[p];
         if (beta == 0 || j > beta || l > beta) return false;  // beta* = 0 marks nothing
         A = ancU[(int64_t)j * P + p];
@@ -692,17 +728,21 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_count(int64_t nslots, int32_t S
     const int nparts = 1 << bits;
     for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) sh[b] = 0;
     __syncthreads();
-    const int64_t s0 = (int64_t)blockIdx.x * JP_BLOCK * items;
+    const JpSlots sl = jp_slots((int64_t)blockIdx.x * JP_BLOCK * items, c);
+    const int64_t ng = nslots / S;
     for (int it0 = 0; it0 < items; it0 += JP_BATCH) {
-        int32_t pr[JP_BATCH];
+        int64_t g[JP_BATCH];
+        int32_t r[JP_BATCH], pr[JP_BATCH];
 #pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) pr[b] = jp_rank(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, nslots, S, glist);
+        for (int b = 0; b < JP_BATCH; b++) {
+            jp_slot(sl, (it0 + b) * JP_BLOCK + (int32_t)threadIdx.x, g[b], r[b]);
+            pr[b] = jp_rank(g[b], ng, glist);
+        }
         uint32_t part[JP_BATCH];
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++) {
             JRec rec;
-            part[b] = jp_record(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, S, pr[b], P, c, rb, ancU, ancV, rec)
-                          ? jp_part(rec.ab, bits) : (uint32_t)nparts;
+            part[b] = jp_record(sl, r[b], pr[b], P, rb, ancU, ancV, rec) ? jp_part(rec.ab, bits) : (uint32_t)nparts;
         }
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++)
@@ -726,16 +766,20 @@ __global__ __launch_bounds__(JP_BLOCK) void k_jp_scatter(int64_t nslots, int32_t
     const int nparts = 1 << bits;
     for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) sh[b] = off[(int64_t)b * nblk + blockIdx.x];
     __syncthreads();
-    const int64_t s0 = (int64_t)blockIdx.x * JP_BLOCK * items;
+    const JpSlots sl = jp_slots((int64_t)blockIdx.x * JP_BLOCK * items, c);
+    const int64_t ng = nslots / S;
     for (int it0 = 0; it0 < items; it0 += JP_BATCH) {
-        int32_t pr[JP_BATCH];
+        int64_t g[JP_BATCH];
+        int32_t r[JP_BATCH], pr[JP_BATCH];
 #pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) pr[b] = jp_rank(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, nslots, S, glist);
+        for (int b = 0; b < JP_BATCH; b++) {
+            jp_slot(sl, (it0 + b) * JP_BLOCK + (int32_t)threadIdx.x, g[b], r[b]);
+            pr[b] = jp_rank(g[b], ng, glist);
+        }
         JRec rec[JP_BATCH];
         bool ok[JP_BATCH];
 #pragma unroll
-        for (int b = 0; b < JP_BATCH; b++)
-            ok[b] = jp_record(s0 + (int64_t)(it0 + b) * JP_BLOCK + threadIdx.x, S, pr[b], P, c, rb, ancU, ancV, rec[b]);
+        for (int b = 0; b < JP_BATCH; b++) ok[b] = jp_record(sl, r[b], pr[b], P, rb, ancU, ancV, rec[b]);
 #pragma unroll
         for (int b = 0; b < JP_BATCH; b++) {
             if (ok[b]) {
