@@ -1099,6 +1099,24 @@ __global__ __launch_bounds__(PB) void k_offtree(
             run += s_wsum[i][w2];
         }
     }
+    // batches: the graphs of the tile's first and last rows bound every entry's graph
+    // (usually one graph per tile, so no per-entry search)
+    __shared__ int32_t s_glo, s_ghi;
+    if (off_g) {
+        if (threadIdx.x < 2) {
+            const int64_t last = min((int64_t)ETILE, nnz - base) - 1;
+            const int32_t u = srow[threadIdx.x == 0 ? 0 : last];
+            int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (vbase[mid] <= u) lo = mid;
+                else hi = mid;
+            }
+            if (threadIdx.x == 0) s_glo = lo;
+            else s_ghi = lo;
+        }
+        __syncthreads();
+    }
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
@@ -1115,7 +1133,7 @@ __global__ __launch_bounds__(PB) void k_offtree(
         off_v[o] = cv[i];
         off_w[o] = w[k];
         if (off_g) {
-            int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
+            int32_t lo = s_glo, hi = s_ghi + 1;  // vbase[lo] <= u < vbase[hi]
             while (hi - lo > 1) {
                 const int32_t mid = (lo + hi) >> 1;
                 if (vbase[mid] <= u) lo = mid;
