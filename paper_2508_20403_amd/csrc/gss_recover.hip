@@ -1365,11 +1365,15 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     int cost_bits = 1;
     while (cost_bits < 31 && ((int64_t)1 << cost_bits) <= P) cost_bits++;
     if (pred) cost_bits = 32;
+    // counters: queued subtasks in the low half of word 4, the lane-sized ones among them
+    // in its high half, join-path edges in word 6
     launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
-                        (int32_t *)(ctx->d_counters + 4), (unsigned long long *)(ctx->d_counters + 6));
-    radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub, bytes_for(((uint64_t)2 << cost_bits) - 1));
+                        (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
+                        (unsigned long long *)(ctx->d_counters + 6));
+    radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub, bytes_for(((uint64_t)3 << cost_bits) - 1));
     read_counters(ctx, 7);
-    const int32_t nlocal = (int32_t)ctx->h_counters[4];
+    const int32_t nlocal = (int32_t)(ctx->h_counters[4] & 0xffffffffll);
+    const int32_t nsmall = (int32_t)((uint64_t)ctx->h_counters[4] >> 32);
     const int64_t nglobal_edges = ctx->h_counters[6];
     res.nlocal = nlocal;
     res.njoin = nglobal_edges;
@@ -1399,8 +1403,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         a.sub_ptr = B.sub_ptr;
         a.queue = qv;
         a.nqueue = nlocal;
+        a.nbig = nlocal;  // set below once the grid is known
         a.local_max = local_max;
-        a.queue_head = (unsigned int *)(ctx->d_counters + 5);
+        a.queue_head = (unsigned int *)(ctx->d_counters + 5);  // two 32-bit heads, zeroed above
         a.ancU = B.ancU;
         a.ancV = B.ancV;
         a.rdu = B.rdu;
@@ -1412,8 +1417,11 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         // candidate scratch: at most ~256 MB whatever the setting
         const size_t per_wave = (size_t)std::max<int32_t>(local_max, 1) * local_desc_bytes(c);
         blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(1, ((int64_t)256 << 20) / (4 * per_wave)));
+        // small subtasks run one per lane when there are enough of them to give every
+        // wavefront several full takes; otherwise whole wavefronts take them too
+        a.nbig = (nsmall >= (int64_t)16 * blocks * 4) ? nlocal - nsmall : nlocal;
         // about 16 chunks per wavefront; one subtask per take while the queue is short
-        a.chunk = std::max<int32_t>(1, std::min<int32_t>(64, nlocal / (blocks * 4 * 16)));
+        a.chunk = std::max<int32_t>(1, std::min<int32_t>(64, a.nbig / (blocks * 4 * 16)));
         void *scr = ctx->alloc<uint8_t>((size_t)blocks * 4 * per_wave + 64);
         scratch.push_back(scr);
         a.cand_scratch = scr;

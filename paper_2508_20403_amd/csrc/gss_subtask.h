@@ -4,17 +4,20 @@
 
 #define GSS_NFEAT 12          // features per subtask for the cost model
 #define GSS_LOCAL_CAP 1024    // largest subtask the persistent kernel accepts
+#define GSS_LANE_MAX 8        // queued subtasks this small are run by one lane each
 enum : uint8_t { ST_UNDEC_ = 0, ST_CAND_ = 1, ST_MARK_ = 2 };
 
 struct SubtaskArgs {
     int64_t P;                    // prefix length
     const int32_t *grp;           // ranks grouped by LCA, rank order inside a group
     const int32_t *sub_ptr;       // [nsub+1]
-    const int32_t *queue;         // subtask ids in work order
+    const int32_t *queue;         // subtask ids in work order: nbig wavefront subtasks, then
+                                  // the lane subtasks (at most GSS_LANE_MAX edges)
     int32_t nqueue;               // subtasks in the queue
+    int32_t nbig;                 // wavefront subtasks at the front of the queue
     int32_t local_max;            // size limit of queued subtasks (<= GSS_LOCAL_CAP)
     int32_t chunk;                // queue entries taken per atomic on the head
-    unsigned int *queue_head;     // atomic pop counter
+    unsigned int *queue_head;     // atomic pop counters: [0] wavefront part, [1] lane part
     const int32_t *ancU, *ancV;   // [(c+1) * P] ancestor chains per rank
     const int32_t *rdu, *rdv;     // depths of the endpoints per rank
     const uint8_t *rb;            // beta* per rank
@@ -29,7 +32,7 @@ void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
                       int32_t *sub_lca, int32_t nsub);
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
                          int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
-                         unsigned long long *nglobal_edges);
+                         int32_t *nsmall, unsigned long long *nglobal_edges);
 void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
                       const int32_t *grp, int32_t *glist);
 void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,

@@ -11,6 +11,10 @@
 //   * the unmarked lanes are then resolved in rank order: the lowest pending lane is a
 //     candidate, its descriptor is broadcast, lanes after it test strict similarity and
 //     the ballot of hits removes them.
+// Subtasks of at most GSS_LANE_MAX edges (most of them on uniform graphs) are queued
+// after the others and run one per lane: the lane walks its few edges in rank order and
+// tests each against the earlier candidates of its subtask, so a wavefront finishes 64
+// of them in the time one would take with the whole wavefront.
 // Strict similarity is tested with ancestor chains: x is in the beta-ball of u iff
 // anc_i(x) = anc_j(u) for some i + j <= beta; with depths known, for each i only
 // j = depth(u) - depth(x) + i can match.  Larger subtasks go to the global hash-join path.
@@ -87,7 +91,31 @@ __device__ __forceinline__ Desc<C> shfl_desc(const Desc<C> &d, int src)
     return r;
 }
 
-// persistent kernel: one wavefront per subtask, pulled from a device work queue
+// serial greedy of one small subtask [g0, g1) by one lane: each edge is tested against
+// the candidates found before it (their descriptors are loaded again: they were just
+// read by this lane and sit in the cache)
+template <int C>
+__device__ __forceinline__ void lane_subtask(const SubtaskArgs &a, int32_t g0, int32_t g1)
+{
+    uint32_t cand = 0;
+    for (int32_t j = 0; j < g1 - g0; j++) {
+        const int32_t pj = a.grp[g0 + j];
+        Desc<C> dj;
+        load_desc<C>(dj, a.P, pj, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+        bool marked = false;
+        for (int32_t i = 0; i < j && !marked; i++) {
+            if (!((cand >> i) & 1u)) continue;
+            Desc<C> di;
+            load_desc<C>(di, a.P, a.grp[g0 + i], a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+            marked = strictly_similar<C>(dj, di);
+        }
+        if (!marked) cand |= 1u << j;
+        a.state[pj] = marked ? ST_MARK_ : ST_CAND_;
+    }
+}
+
+// persistent kernel: first the larger subtasks, one wavefront each, pulled from the front
+// of the work queue; then the small ones, 64 at a time, one per lane
 template <int C>
 __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
 {
@@ -101,10 +129,10 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
     // chunk rather than one per subtask
     for (;;) {
         int32_t q0 = 0;
-        if (lane == 0) q0 = (int32_t)atomicAdd(a.queue_head, (unsigned)a.chunk);
+        if (lane == 0) q0 = (int32_t)atomicAdd(&a.queue_head[0], (unsigned)a.chunk);
         q0 = __shfl(q0, 0, GSS_WAVE);
-        if (q0 >= a.nqueue) break;
-        const int32_t q1 = (q0 + a.chunk < a.nqueue) ? q0 + a.chunk : a.nqueue;
+        if (q0 >= a.nbig) break;
+        const int32_t q1 = (q0 + a.chunk < a.nbig) ? q0 + a.chunk : a.nbig;
         for (int32_t qi = q0; qi < q1; qi++) {
             const int32_t s = a.queue[qi];
             const uint64_t t0 = clock64();
@@ -143,6 +171,21 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
             }
             const uint64_t t1 = clock64();
             if (lane == 0 && a.cycles) a.cycles[s] = t1 - t0;
+        }
+    }
+    // small subtasks: 64 queue entries per take, one per lane
+    for (;;) {
+        int32_t q0 = 0;
+        if (lane == 0) q0 = a.nbig + (int32_t)atomicAdd(&a.queue_head[1], (unsigned)GSS_WAVE);
+        q0 = __shfl(q0, 0, GSS_WAVE);
+        if (q0 >= a.nqueue) break;
+        const int32_t qi = q0 + lane;
+        if (qi < a.nqueue) {
+            const int32_t s = a.queue[qi];
+            const uint64_t t0 = clock64();
+            lane_subtask<C>(a, a.sub_ptr[s], a.sub_ptr[s + 1]);
+            const uint64_t t1 = clock64();
+            if (a.cycles) a.cycles[s] = t1 - t0;
         }
     }
 }
@@ -205,44 +248,52 @@ __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_
                                                       int cost_bits, uint64_t *__restrict__ qkey,
                                                       int32_t *__restrict__ qval,
                                                       int32_t *__restrict__ is_local, int32_t *__restrict__ nlocal,
+                                                      int32_t *__restrict__ nsmall,
                                                       unsigned long long *__restrict__ nglobal_edges)
 {
     __shared__ unsigned long long s_ge[256 / GSS_WAVE];
-    __shared__ int32_t s_nl[256 / GSS_WAVE];
+    __shared__ int32_t s_nl[256 / GSS_WAVE], s_ns[256 / GSS_WAVE];
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     int32_t size = 0;
     if (s < nsub) size = sub_ptr[s + 1] - sub_ptr[s];
     const bool loc = s < nsub && size <= local_max;
+    const bool small = loc && size <= GSS_LANE_MAX;
     if (s < nsub) {
         is_local[s] = loc ? 1 : 0;
         uint64_t cost;
         if (pred) cost = (uint64_t)__float_as_uint(fmaxf(pred[s], 0.f));  // non-negative floats order as ints
         else cost = (uint64_t)size;
-        // ascending sort of this key = local subtasks first, by cost descending, then id
-        // (a stable sort of ids in order); cost < 2^cost_bits
+        // ascending sort of this key = queued subtasks for wavefronts, then those for
+        // lanes, each by cost descending, then id (a stable sort of ids in order), then
+        // the join's; cost < 2^cost_bits
         const uint64_t cmask = ((uint64_t)1 << cost_bits) - 1;
-        qkey[s] = ((uint64_t)(loc ? 0 : 1) << cost_bits) | ((~cost) & cmask);
+        const uint64_t cls = loc ? (small ? 1 : 0) : 2;
+        qkey[s] = (cls << cost_bits) | ((~cost) & cmask);
         qval[s] = s;
     }
-    // edges on the join path and local subtasks: one atomic per workgroup each
+    // edges on the join path, queued and small subtasks: one atomic per workgroup each
     unsigned long long ge = (s < nsub && !loc) ? (unsigned long long)size : 0ull;
-    int32_t nl = loc ? 1 : 0;
+    int32_t nl = loc ? 1 : 0, ns = small ? 1 : 0;
     for (int d = 32; d > 0; d >>= 1) {
         ge += __shfl_xor(ge, d, GSS_WAVE);
         nl += __shfl_xor(nl, d, GSS_WAVE);
+        ns += __shfl_xor(ns, d, GSS_WAVE);
     }
     if (lane_id() == 0) {
         s_ge[threadIdx.x / GSS_WAVE] = ge;
         s_nl[threadIdx.x / GSS_WAVE] = nl;
+        s_ns[threadIdx.x / GSS_WAVE] = ns;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < 256 / GSS_WAVE; w++) {
             ge += s_ge[w];
             nl += s_nl[w];
+            ns += s_ns[w];
         }
         if (ge) atomicAdd(nglobal_edges, ge);
         if (nl) atomicAdd(nlocal, nl);
+        if (ns) atomicAdd(nsmall, ns);
     }
 }
 
@@ -366,10 +417,10 @@ void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
 
 void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
                          int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
-                         unsigned long long *nglobal_edges)
+                         int32_t *nsmall, unsigned long long *nglobal_edges)
 {
     GSS_LAUNCH(k_subtask_keys, dim3(grid_for(nsub, 256)), dim3(256), 0, ctx->stream, nsub, sub_ptr, local_max, pred,
-               cost_bits, qkey, qval, is_local, nlocal, nglobal_edges);
+               cost_bits, qkey, qval, is_local, nlocal, nsmall, nglobal_edges);
 }
 
 void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
