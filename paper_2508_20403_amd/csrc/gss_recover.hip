@@ -984,48 +984,91 @@ __global__ void k_arc_compact(int64_t A, const int2 *__restrict__ arcs, const ui
     if (keep) out[base + __popcll(m & lanemask_lt())] = e;
 }
 
-__global__ __launch_bounds__(1024) void k_resolve(int64_t A, const int2 *__restrict__ arcs,
-                                                  const int32_t *__restrict__ indeg, uint8_t *state,
-                                                  int32_t *mcnt, int64_t *rounds_out)
+// Dependency rounds over the compacted arcs (x -> y: y is strictly similar to the earlier
+// x).  A round marks every undecided target with a recovered source, counts for each
+// undecided target its marked sources, and recovers the targets whose sources are all
+// marked.  Arcs always point forward in the order, so the rounds end.
+//
+// Many arcs: each phase is a grid-wide kernel over the arcs and a round is three
+// launches; the first phase of round r also resets the counts of undecided targets and
+// records whether any target is still undecided (flag[r]); once a round finds none,
+// every later launch returns at once.  The rounds are queued without host waits, and a
+// single-workgroup kernel finishes whatever they left (usually nothing).
+// rf: [0] done, [1] rounds completed by the grid-wide kernels, [2 + r] flag[r]
+#define RES_GRID_ROUNDS 4
+#define RES_GRID_MIN 65536  // arcs (before settling) from which the grid-wide rounds pay
+__global__ void k_round_mark(const unsigned long long *A, const int2 *__restrict__ arcs, uint8_t *state,
+                             int32_t *mcnt, int32_t *rf, int r)
 {
-    int64_t rounds = 0;
-    for (;;) {
-        for (int64_t a = threadIdx.x; a < A; a += blockDim.x) {
-            int2 e = arcs[a];
-            if (state[e.y] == ST_UNDEC && state[e.x] == ST_CAND) state[e.y] = ST_MARK;
+    if (rf[0]) return;
+    const int64_t n = (int64_t)*A;
+    bool und = false;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+        const int2 e = arcs[a];
+        if (state[e.y] == ST_UNDEC) {
+            und = true;
+            mcnt[e.y] = 0;
+            if (state[e.x] == ST_CAND) state[e.y] = ST_MARK;
         }
-        __syncthreads();
-        for (int64_t a = threadIdx.x; a < A; a += blockDim.x) {
-            int2 e = arcs[a];
-            if (state[e.y] == ST_UNDEC && state[e.x] == ST_MARK) atomicAdd(&mcnt[e.y], 1);
+    }
+    if (__syncthreads_or(und) && threadIdx.x == 0) rf[2 + r] = 1;
+}
+__global__ void k_round_count(const unsigned long long *A, const int2 *__restrict__ arcs,
+                              const uint8_t *__restrict__ state, int32_t *mcnt, int32_t *rf, int r)
+{
+    if (rf[0]) return;
+    if (!rf[2 + r]) {  // nothing was undecided when round r began: r rounds settled it
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            rf[0] = 1;
+            rf[1] = r;
         }
-        __syncthreads();
-        for (int64_t a = threadIdx.x; a < A; a += blockDim.x) {
-            int2 e = arcs[a];
-            if (state[e.y] == ST_UNDEC && mcnt[e.y] == indeg[e.y]) state[e.y] = ST_CAND;
-        }
-        __syncthreads();
+        return;
+    }
+    const int64_t n = (int64_t)*A;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+        const int2 e = arcs[a];
+        if (state[e.y] == ST_UNDEC && state[e.x] == ST_MARK) atomicAdd(&mcnt[e.y], 1);
+    }
+}
+__global__ void k_round_settle(const unsigned long long *A, const int2 *__restrict__ arcs,
+                               const int32_t *__restrict__ indeg, uint8_t *state, const int32_t *__restrict__ mcnt,
+                               int32_t *rf, int r)
+{
+    if (rf[0]) return;
+    const int64_t n = (int64_t)*A;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+        const int2 e = arcs[a];
+        if (state[e.y] == ST_UNDEC && mcnt[e.y] == indeg[e.y]) state[e.y] = ST_CAND;
+    }
+    if (r == RES_GRID_ROUNDS - 1 && blockIdx.x == 0 && threadIdx.x == 0) rf[1] = RES_GRID_ROUNDS;
+}
+
+// single workgroup: the remaining rounds (all of them when rf is null); rounds_out gets
+// the total number of rounds
+__global__ __launch_bounds__(1024) void k_resolve_dev(const unsigned long long *A, const int2 *__restrict__ arcs,
+                                                      const int32_t *__restrict__ indeg, uint8_t *state, int32_t *mcnt,
+                                                      const int32_t *rf, int64_t *rounds_out)
+{
+    const int64_t n = (int64_t)*A;
+    int64_t rounds = rf ? rf[1] : 0;
+    if (rf && rf[0]) {
+        if (threadIdx.x == 0) *rounds_out = rounds;
+        return;
+    }
+    if (rf) {  // counts left by the grid-wide rounds; stop if nothing is undecided
         int undec = 0;
-        for (int64_t a = threadIdx.x; a < A; a += blockDim.x) {
-            int2 e = arcs[a];
+        for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+            const int2 e = arcs[a];
             if (state[e.y] == ST_UNDEC) {
                 mcnt[e.y] = 0;
                 undec = 1;
             }
         }
-        rounds++;
-        if (!__syncthreads_or(undec)) break;
+        if (!__syncthreads_or(undec)) {
+            if (threadIdx.x == 0) *rounds_out = rounds;
+            return;
+        }
     }
-    if (threadIdx.x == 0) *rounds_out = rounds;
-}
-
-// rounds over the compacted arcs; the count is read from device memory
-__global__ __launch_bounds__(1024) void k_resolve_dev(const unsigned long long *A, const int2 *__restrict__ arcs,
-                                                      const int32_t *__restrict__ indeg, uint8_t *state, int32_t *mcnt,
-                                                      int64_t *rounds_out)
-{
-    const int64_t n = (int64_t)*A;
-    int64_t rounds = 0;
     while (n > 0) {
         for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
             int2 e = arcs[a];
@@ -1509,8 +1552,21 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                 GSS_LAUNCH(k_arc_settle, dim3(grid_for(A, RB)), dim3(RB), 0, st, A, arcs, B.indeg, B.state);
                 GSS_LAUNCH(k_arc_compact, dim3(grid_for(A, RB)), dim3(RB), 0, st, A, arcs, B.state, arcs2,
                            (unsigned long long *)(ctx->d_counters + 2));
-                GSS_LAUNCH(k_resolve_dev, dim3(1), dim3(1024), 0, st, (const unsigned long long *)(ctx->d_counters + 2),
-                           arcs2, B.indeg, B.state, B.mcnt, ctx->d_counters + 1);
+                const unsigned long long *dA = (const unsigned long long *)(ctx->d_counters + 2);
+                int32_t *rf = nullptr;
+                if (A >= RES_GRID_MIN) {  // many arcs: grid-wide rounds first
+                    rf = ctx->alloc<int32_t>(2 + RES_GRID_ROUNDS);
+                    HIP_OK(hipMemsetAsync(rf, 0, sizeof(int32_t) * (2 + RES_GRID_ROUNDS), st));
+                    const dim3 g((unsigned)std::min<int64_t>(grid_for(A, RB), 4096));
+                    for (int r = 0; r < RES_GRID_ROUNDS; r++) {
+                        GSS_LAUNCH(k_round_mark, g, dim3(RB), 0, st, dA, arcs2, B.state, B.mcnt, rf, r);
+                        GSS_LAUNCH(k_round_count, g, dim3(RB), 0, st, dA, arcs2, B.state, B.mcnt, rf, r);
+                        GSS_LAUNCH(k_round_settle, g, dim3(RB), 0, st, dA, arcs2, B.indeg, B.state, B.mcnt, rf, r);
+                    }
+                }
+                GSS_LAUNCH(k_resolve_dev, dim3(1), dim3(1024), 0, st, dA, arcs2, B.indeg, B.state, B.mcnt,
+                           (const int32_t *)rf, ctx->d_counters + 1);
+                if (rf) ctx->free(rf);
                 // rounds (for the info record) arrive with the next synchronisation
                 HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], ctx->d_counters + 1, sizeof(int64_t),
                                       hipMemcpyDeviceToHost, st));
