@@ -46,7 +46,7 @@ __host__ __device__ __forceinline__ u128 shl128(uint64_t m, int s)
 // per-vertex record read by the per-edge kernel with one 32-byte gather
 struct VRec {
     u128 D;          // root resistance in fixed point (units of 2^scale)
-    int32_t first;   // first Euler position
+    int32_t first;   // preorder index (root 0)
     int32_t depth;   // hops from the root
     int32_t parent;  // -1 at the root
     int32_t pad;

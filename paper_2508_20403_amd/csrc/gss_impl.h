@@ -112,9 +112,9 @@ struct gss_tree_s {
     int32_t *tpos = nullptr;     // [n] CSR index of (x, parent x) in row x, -1 at root
     int32_t *tree_eid = nullptr; // [n] edge id of (x, parent x), -1 at root
     // tree / Euler tour
-    VRec *vrec = nullptr;        // [n] root resistance, first Euler position, depth, parent
-    int32_t L = 0;               // Euler sequence length 2n-1
-    uint64_t *epk = nullptr;     // [L] (depth << 32) | vertex
+    VRec *vrec = nullptr;        // [n] root resistance, preorder index, depth, parent
+    int32_t L = 0;               // LCA sequence length n
+    uint64_t *epk = nullptr;     // [L] (depth << 32) | parent of the vertex at each preorder index
     uint64_t *pmask = nullptr;   // [L] in-block suffix-minimum masks
     uint64_t *ppre = nullptr;    // [L] minimum from the block start to each position
     uint64_t *psuf = nullptr;    // [L] minimum from each position to the block end

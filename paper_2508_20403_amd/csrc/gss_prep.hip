@@ -6,10 +6,13 @@
 //     upper-triangle CSR entries,
 //   * the Euler tour of the tree, ranked by a recursive sparse-ruling-set list ranking
 //     that carries (position, depth, root resistance) sums along the walk,
-//   * depth, first Euler position and the exact root-to-node resistance
+//   * depth, preorder index and the exact root-to-node resistance
 //     D(x) = sum over the root->x path of RN(1/w) in 128-bit fixed point
 //     (paper: Def. "Resistance distance", eq. RT, resistive weight 1/w),
-//   * a two-level in-block-mask RMQ over the Euler depth sequence (for LCA queries),
+//   * a two-level in-block-mask RMQ over the preorder sequence of (depth, parent): for
+//     vertices u != v with pre(u) < pre(v), the shallowest vertex in preorder positions
+//     (pre(u), pre(v)] is a child of LCA(u, v) (every vertex there at that depth is one),
+//     so the minimum's parent is the LCA,
 //   * the list of off-tree edges in id order.
 #include <algorithm>
 
@@ -289,13 +292,16 @@ __global__ __launch_bounds__(1024) void k_hash_total(const uint64_t *__restrict_
     }
 }
 
-// first upper entry of each row and the number of upper entries
+// first upper entry of each row and the number of upper entries.  Row bounds are
+// clamped to [0, nnz]: the entry checks run concurrently and are only read back later,
+// so malformed input must stay in bounds here.
 __global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t n,
-                       int32_t *__restrict__ ufirst, int32_t *__restrict__ ucnt)
+                       int64_t nnz, int32_t *__restrict__ ufirst, int32_t *__restrict__ ucnt)
 {
     int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
-    int64_t lo = row_ptr[u], hi = row_ptr[u + 1], end = hi;
+    int64_t lo = clamp_idx(row_ptr[u], 0, nnz);
+    int64_t hi = clamp_idx(row_ptr[u + 1], lo, nnz), end = hi;
     while (lo < hi) {
         int64_t mid = lo + ((hi - lo) >> 1);
         if (col[mid] <= u) lo = mid + 1;
@@ -306,11 +312,13 @@ __global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__res
 }
 
 // parent checks, child counts, tree-edge positions and the exponent range of 1/w;
-// a fixed grid strides over the vertices and each block issues one set of atomics
+// a fixed grid strides over the vertices and each block issues one set of atomics.
+// Memory-safe on any CSR (row bounds clamped), so it runs before the CSR checks are read.
 __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ parent,
                                                    const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const double *__restrict__ w,
-                                                   int32_t n, int32_t virt_root, int32_t *__restrict__ ccnt,
+                                                   int32_t n, int64_t nnz, int32_t virt_root,
+                                                   int32_t *__restrict__ ccnt,
                                                    int32_t *__restrict__ tpos, uint32_t *flags, int64_t *counters)
 {
     __shared__ int32_t sred[5][PB / GSS_WAVE];
@@ -331,7 +339,9 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
             atomicAdd(&ccnt[p], 1);  // zero-resistance link of a batch graph's root
         } else {
             atomicAdd(&ccnt[p], 1);
-            int64_t k = find_in_row(col, row_ptr[x], row_ptr[x + 1], p);
+            // row bounds clamped: the CSR checks are read back together with these
+            const int64_t lo = clamp_idx(row_ptr[x], 0, nnz);
+            int64_t k = find_in_row(col, lo, clamp_idx(row_ptr[x + 1], lo, nnz), p);
             if (k < 0) {
                 f |= F_TREE_EDGE;
             } else {
@@ -401,17 +411,54 @@ __global__ void k_children_fill(const int32_t *__restrict__ parent, int32_t n,
     cslot[x] = s;
 }
 
-// fixed-point resistance term of each tree edge, and per-block sums for the range check
-__global__ __launch_bounds__(PB) void k_terms(const int32_t *__restrict__ tpos,
-                                              const double *__restrict__ w, int32_t n, int32_t root,
-                                              int emin, int ok, u128 *__restrict__ T,
-                                              u128 *__restrict__ bsum, uint64_t *__restrict__ bcarry)
+// Per-vertex tour record of level 0 of the list ranking: the successors of both arcs
+// of x (arc 2x = down(parent x -> x), arc 2x+1 = up(x -> parent x)), the parent, the
+// tree degree and the fixed-point resistance term of the tree edge (x, parent x), so
+// one 32-byte load serves a step of the walk whichever arc it is on.
+struct __attribute__((aligned(32))) TRec {
+    int32_t nd, nu, par, deg;
+    u128 t;
+};
+
+// Tour records, the successor array of the arcs (read by the ruler selection) and the
+// per-block sums of the terms for the 127-bit range check.  Successors: the down arc
+// into x continues with the down arc into its first child, or returns (up arc of x);
+// the up arc of x continues with the down arc into its next sibling, or the up arc of
+// its parent, or ends the tour when the parent is the root.  The root's arcs are not on
+// the tour (-2).
+__global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpos, const double *__restrict__ w,
+                                                 const int32_t *__restrict__ parent,
+                                                 const int32_t *__restrict__ cptr,
+                                                 const int32_t *__restrict__ clist,
+                                                 const int32_t *__restrict__ cslot, int32_t n, int32_t root,
+                                                 int emin, int ok, TRec *__restrict__ trec,
+                                                 int32_t *__restrict__ succ, u128 *__restrict__ bsum,
+                                                 uint64_t *__restrict__ bcarry)
 {
     __shared__ uint64_t slo[PB], shi[PB], sc[PB];
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     u128 t = mk128(0, 0);
-    if (ok && x < n && x != root && tpos[x] >= 0) t = fixed_term(1.0 / w[tpos[x]], emin);
-    if (x < n) T[x] = t;
+    if (x < n) {
+        if (ok && x != root && tpos[x] >= 0) t = fixed_term(1.0 / w[tpos[x]], emin);
+        const int32_t c0 = cptr[x], c1 = cptr[x + 1];
+        TRec e;
+        e.par = parent[x];
+        e.deg = c1 - c0;
+        e.t = t;
+        if (x == root) {
+            e.nd = -2;
+            e.nu = -2;
+        } else {
+            e.nd = (c0 < c1) ? 2 * clist[c0] : 2 * x + 1;
+            const int32_t p = e.par;
+            const int32_t s = cslot[x] + 1;
+            if (s < cptr[p + 1]) e.nu = 2 * clist[s];
+            else if (p == root) e.nu = GSS_END;
+            else e.nu = 2 * p + 1;
+        }
+        trec[x] = e;
+        *(int2 *)(succ + 2 * (int64_t)x) = make_int2(e.nd, e.nu);
+    }
     slo[threadIdx.x] = t.lo;
     shi[threadIdx.x] = t.hi;
     sc[threadIdx.x] = 0;
@@ -469,31 +516,6 @@ __global__ __launch_bounds__(1024) void k_terms_total(const u128 *__restrict__ b
 }
 
 // ------------------------------------------------------------------------------------
-// Euler tour successor: arc 2x = down(parent x -> x), arc 2x+1 = up(x -> parent x)
-// ------------------------------------------------------------------------------------
-__global__ void k_succ(const int32_t *__restrict__ parent, const int32_t *__restrict__ cptr,
-                       const int32_t *__restrict__ clist, const int32_t *__restrict__ cslot,
-                       int32_t n, int32_t root, int32_t *__restrict__ succ)
-{
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    if (x == root) {
-        succ[2 * x] = -2;
-        succ[2 * x + 1] = -2;
-        return;
-    }
-    int32_t c0 = cptr[x], c1 = cptr[x + 1];
-    succ[2 * x] = (c0 < c1) ? 2 * clist[c0] : 2 * x + 1;
-    int32_t p = parent[x];
-    int32_t s = cslot[x] + 1;
-    int32_t up;
-    if (s < cptr[p + 1]) up = 2 * clist[s];
-    else if (p == root) up = GSS_END;
-    else up = 2 * p + 1;
-    succ[2 * x + 1] = up;
-}
-
-// ------------------------------------------------------------------------------------
 // list ranking
 // ------------------------------------------------------------------------------------
 struct LVal {
@@ -531,20 +553,19 @@ __device__ __forceinline__ bool is_ruler(int32_t i, int32_t head, int32_t level)
                          ((level == 0 ? RULE_RATE0 : RULE_RATE) - 1)) == 0;
 }
 
-// level-0 element value: arc i of vertex x = i>>1
-__device__ __forceinline__ LVal arc_val(int32_t i, const u128 *__restrict__ T)
+// level-0 step: adds arc i (of vertex i>>1, whose tour record is e) to acc and
+// returns the arc's successor
+__device__ __forceinline__ int32_t arc_step(int32_t i, const TRec &e, LVal &acc)
 {
-    LVal v;
-    u128 t = T[i >> 1];
-    v.cnt = 1;
+    acc.cnt += 1;
     if (i & 1) {
-        v.dep = -1;
-        v.D = neg128(t);
-    } else {
-        v.dep = 1;
-        v.D = t;
+        acc.dep -= 1;
+        acc.D = sub128(acc.D, e.t);
+        return e.nu;
     }
-    return v;
+    acc.dep += 1;
+    acc.D = add128(acc.D, e.t);
+    return e.nd;
 }
 
 // The list ranking runs without host round trips: every level's length and head live
@@ -554,18 +575,17 @@ __device__ __forceinline__ LVal arc_val(int32_t i, const u128 *__restrict__ T)
 //
 // Level l: elements i < N_l with successor nxt[i] (GSS_END ends the list, -2 = not in
 // the list) and value val(i).  Rulers (the head and a hashed 1/RULE_RATE sample) walk
-// their sublists once, recording for every element its ruler (owner) and the exclusive
-// sum of the sublist before it (loc); the rulers form the level l+1 list.  Once level
-// l+1 is ranked, every element's exclusive prefix is rpre[owner] + loc, one coalesced
-// pass with no walking.
-__device__ __forceinline__ LVal level_val(const LVal *__restrict__ val, const u128 *__restrict__ T, int32_t i)
-{
-    return val ? val[i] : arc_val(i, T);
-}
+// their sublists once; the sublist sums and the next rulers form the level l+1 list.
+// Level 0 (the 2n arcs) walks the tour records and keeps nothing per arc: once level 1
+// is ranked, every ruler walks its sublist again from its prefix and writes the Euler
+// sequence and the vertex records directly.  Upper levels record for every element its
+// ruler (owner) and the exclusive sum of the sublist before it (loc), and the way down
+// is the coalesced pass rpre[owner] + loc.
 
 // Ruler selection and numbering in one pass (a stream compaction with decoupled
 // look-back): rid[i] = number of rulers before i (written for rulers only), relem[rid] =
-// i, the level length R_{l+1} and head; owner[i] = -1 for every element.  Thread t of
+// i, the level length R_{l+1} and head; owner[i] = -1 for every element (upper levels;
+// level 0 keeps no owners).  Thread t of
 // round r owns the four consecutive elements at tile offset 4 (r*256 + t).
 #define RC_BLOCK 256
 #define RC_ROUNDS 4
@@ -602,12 +622,12 @@ __global__ __launch_bounds__(RC_BLOCK) void k_ruler_compact(int64_t cap, int64_t
             nx[1] = v.y;
             nx[2] = v.z;
             nx[3] = v.w;
-            *(int4 *)(owner + e) = make_int4(-1, -1, -1, -1);
+            if (owner) *(int4 *)(owner + e) = make_int4(-1, -1, -1, -1);
         } else {
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 nx[q] = (e + q < N) ? nxt[e + q] : -2;
-                if (e + q < N) owner[e + q] = -1;
+                if (owner && e + q < N) owner[e + q] = -1;
             }
         }
         uint32_t f = 0;
@@ -669,13 +689,85 @@ __global__ __launch_bounds__(RC_BLOCK) void k_ruler_compact(int64_t cap, int64_t
     }
 }
 
-// walk: one thread per ruler r < R_{l+1}
+// level-0 walk: one thread per ruler r < R_1; per arc one tour-record load, nothing
+// written; per ruler the sublist sum and the next ruler
+__global__ __launch_bounds__(PB) void k_walk0(int64_t cap_next, const int64_t *__restrict__ Rp,
+                                              const int32_t *__restrict__ relem, const int32_t *__restrict__ rid,
+                                              const TRec *__restrict__ trec, const int32_t *__restrict__ headp,
+                                              int64_t N, int32_t *__restrict__ rnxt, LVal *__restrict__ rval,
+                                              uint32_t *flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= cap_next || r >= *Rp) return;
+    const int32_t head = *headp;
+    int32_t i = relem[r];
+    LVal acc = lv_zero();
+    int32_t j;
+    for (int64_t steps = 0;; steps++) {
+        const TRec e = trec[i >> 1];
+        j = arc_step(i, e, acc);
+        if (j < 0 || is_ruler(j, head, 0)) break;
+        if (steps > N) {  // a cycle without rulers beyond this one: not a tree
+            atomicOr(flags, F_NOT_TREE);
+            j = GSS_END;
+            break;
+        }
+        i = j;
+    }
+    int32_t nr = (j < 0) ? GSS_END : rid[j];
+    if (nr >= cap_next) nr = GSS_END;  // overflow, already flagged by k_ruler_compact
+    rnxt[r] = nr;
+    rval[r] = acc;
+}
+
+// level-0 way down: ruler r walks its sublist again from its exclusive prefix rpre[r].
+// The down arc into x is the (arcs before it + 1)-th step of the tour, and x's preorder
+// index is (that position + depth(x)) / 2; it writes x's vertex record (depth, preorder
+// index, exact root resistance, parent, tree degree) and the LCA sequence entry
+// epk[pre(x)] = depth(x) << 32 | parent(x).  A valid tour reaches every vertex; the
+// base level checks that it holds all 2(n-1) arcs.
+__global__ __launch_bounds__(PB) void k_walk0_down(int64_t cap_next, const int64_t *__restrict__ Rp,
+                                                   const int32_t *__restrict__ relem, const TRec *__restrict__ trec,
+                                                   const LVal *__restrict__ rpre, const int32_t *__restrict__ headp,
+                                                   int64_t N, int32_t n, VRec *__restrict__ vrec,
+                                                   uint64_t *__restrict__ epk, uint32_t *flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= cap_next || r >= *Rp) return;
+    const int32_t head = *headp;
+    int32_t i = relem[r];
+    LVal acc = rpre[r];
+    for (int64_t steps = 0;; steps++) {
+        const TRec e = trec[i >> 1];
+        const int32_t pos = acc.cnt + 1;
+        const int32_t j = arc_step(i, e, acc);
+        if (!(i & 1)) {
+            const int32_t x = i >> 1;
+            const int32_t pre = (pos + acc.dep) >> 1;
+            if (pos < 1 || pre < 1 || pre >= n) {
+                atomicOr(flags, F_NOT_TREE);
+                break;
+            }
+            VRec v;
+            v.D = acc.D;
+            v.first = pre;
+            v.depth = acc.dep;
+            v.parent = e.par;
+            v.pad = e.deg;
+            vrec[x] = v;
+            epk[pre] = ((uint64_t)(uint32_t)acc.dep << 32) | (uint32_t)e.par;
+        }
+        if (j < 0 || is_ruler(j, head, 0) || steps > N) break;
+        i = j;
+    }
+}
+
+// upper-level walk: one thread per ruler r < R_{l+1}
 __global__ void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp, const int32_t *__restrict__ relem,
                         const int32_t *__restrict__ rid, const int32_t *__restrict__ nxt,
-                        const LVal *__restrict__ val, const u128 *__restrict__ T, const int32_t *__restrict__ headp,
-                        int32_t level, const int64_t *__restrict__ Np, int32_t *__restrict__ owner,
-                        LVal *__restrict__ loc, int32_t *__restrict__ rnxt, LVal *__restrict__ rval,
-                        uint32_t *flags)
+                        const LVal *__restrict__ val, const int32_t *__restrict__ headp, int32_t level,
+                        const int64_t *__restrict__ Np, int32_t *__restrict__ owner, LVal *__restrict__ loc,
+                        int32_t *__restrict__ rnxt, LVal *__restrict__ rval, uint32_t *flags)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= cap_next || r >= *Rp) return;
@@ -687,7 +779,7 @@ __global__ void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp, const 
     for (int64_t steps = 0;; steps++) {
         owner[i] = (int32_t)r;
         loc[i] = acc;
-        acc = lv_add(acc, level_val(val, T, i));
+        acc = lv_add(acc, val[i]);
         j = nxt[i];
         if (j < 0 || is_ruler(j, head, level)) break;
         if (steps > N) {  // a cycle without rulers beyond this one: not a tree
@@ -780,40 +872,6 @@ __global__ void k_rank_apply(int64_t cap, const int64_t *__restrict__ Np, const 
     pre[i] = (o >= 0) ? lv_add(rpre[o], loc[i]) : lv_zero();
 }
 
-// downward pass, level 0: emit the Euler tour, depth, first position and root resistance
-// of every arc's vertex.  Arc 2x enters x from its parent, arc 2x+1 returns to it.
-__global__ void k_euler_emit(int32_t N, const int32_t *__restrict__ owner, const LVal *__restrict__ loc,
-                             const LVal *__restrict__ rpre, const u128 *__restrict__ T,
-                             const int32_t *__restrict__ parent, int32_t L, VRec *__restrict__ vrec,
-                             uint64_t *__restrict__ epk, uint32_t *flags)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int32_t o = owner[i];
-    if (o < 0) return;  // not on the tour: k_vrec_finish reports it
-    const LVal acc = lv_add(rpre[o], loc[i]);
-    const LVal after = lv_add(acc, arc_val(i, T));
-    const int32_t x = i >> 1;
-    const int32_t pos = acc.cnt + 1;  // Euler index of the vertex entered by this arc
-    if (pos < 1 || pos >= L) {
-        atomicOr(flags, F_NOT_TREE);
-        return;
-    }
-    const int32_t p = parent[x];
-    if (i & 1) {
-        epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)p;
-    } else {
-        VRec r;
-        r.D = after.D;
-        r.first = pos;
-        r.depth = after.dep;
-        r.parent = p;
-        r.pad = 0;
-        vrec[x] = r;
-        epk[pos] = ((uint64_t)(uint32_t)after.dep << 32) | (uint32_t)x;
-    }
-}
-
 __global__ void k_level_init(int64_t N0, const int64_t *__restrict__ head0, int nlev, int64_t *__restrict__ len,
                              int32_t *__restrict__ heads)
 {
@@ -829,10 +887,10 @@ static inline int64_t next_cap(int64_t cap, int mult, int level)
     return cap * mult * 21 / (rate * 16) + 256;  // 1.3125x the expected ruler count
 }
 
-// Ranks the Euler tour (succ over N = 2n arcs, head arc in *d_head) and emits vrec / epk.
-// Returns without a host round trip; F_OVERFLOW in the flags asks for a retry with a
-// larger capacity multiplier.
-static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 *T, const int64_t *d_head,
+// Ranks the Euler tour (succ over N = 2n arcs, tour records trec, head arc in *d_head)
+// and emits vrec / epk.  Returns without a host round trip; F_OVERFLOW in the flags asks
+// for a retry with a larger capacity multiplier.
+static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const TRec *trec, const int64_t *d_head,
                        int mult, std::vector<void *> &bufs)
 {
     hipStream_t st = ctx->stream;
@@ -847,6 +905,7 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
         int32_t *owner;
         LVal *loc;
         LVal *pre;
+        int32_t *relem;  // this level's rulers (kept for level 0's way down)
     };
     // device scalars: level lengths and heads
     const int max_levels = 40;
@@ -856,7 +915,7 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
     bufs.push_back(d_heads);
     GSS_LAUNCH(k_level_init, dim3(1), dim3(64), 0, st, N0, d_head, max_levels, d_len, d_heads);
     std::vector<Lv> lv;
-    lv.push_back(Lv{N0, succ, nullptr, d_heads, d_len, nullptr, nullptr, nullptr});
+    lv.push_back(Lv{N0, succ, nullptr, d_heads, d_len, nullptr, nullptr, nullptr, nullptr});
     // upward: build levels until the capacity fits one workgroup
     for (int l = 0; l == 0 || lv.back().cap > BASE_MAX; l++) {
         if (l + 1 >= max_levels) throw gss_error{GSS_ERR_HIP, "list ranking: too many levels"};
@@ -864,26 +923,36 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
         const int64_t cap = a.cap;
         const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult, l), cap);
         int32_t *rid = ctx->alloc<int32_t>(cap + 1);
-        a.owner = ctx->alloc<int32_t>(cap + 1);
-        a.loc = ctx->alloc<LVal>(cap + 1);
-        int32_t *relem = ctx->alloc<int32_t>(cap2 + 1);
+        if (l > 0) {
+            a.owner = ctx->alloc<int32_t>(cap + 1);
+            a.loc = ctx->alloc<LVal>(cap + 1);
+            bufs.push_back(a.owner);
+            bufs.push_back(a.loc);
+        }
+        a.relem = ctx->alloc<int32_t>(cap2 + 1);
         int32_t *rnxt = ctx->alloc<int32_t>(cap2 + 1);
         LVal *rval = ctx->alloc<LVal>(cap2 + 1);
-        for (void *p : {(void *)rid, (void *)a.owner, (void *)a.loc, (void *)relem, (void *)rnxt, (void *)rval})
-            bufs.push_back(p);
+        for (void *p : {(void *)rid, (void *)a.relem, (void *)rnxt, (void *)rval}) bufs.push_back(p);
         const int64_t ntiles = (cap + RC_TILE - 1) / RC_TILE;
         uint32_t epoch = 0;
         uint64_t *status = lb_begin(ctx, ntiles, &epoch);
-        // successor read and owner cleared per element; rid and relem written per ruler
-        GSS_LAUNCH_B(8 * cap + 8 * cap2, k_ruler_compact, dim3((unsigned)ntiles), dim3(RC_BLOCK), 0, st, cap, ntiles,
-                     a.Np, a.nxt, a.headp, l, rid, a.owner, relem, cap2, d_heads + l + 1, d_len + l + 1, status, epoch,
-                     lb_ticket_ptr(ctx), ctx->d_flags);
-        // one walk over every element: successor and value read, owner and local prefix
-        // written; one record per ruler
-        GSS_LAUNCH_B((l == 0 ? 24 : 32) * cap + 28 * cap + 36 * cap2, k_walk1, dim3(grid_for(cap2, PB)), dim3(PB), 0,
-                     st, cap2, d_len + l + 1, relem, rid, a.nxt, a.val, T, a.headp, l, a.Np, a.owner, a.loc, rnxt,
-                     rval, ctx->d_flags);
-        lv.push_back(Lv{cap2, rnxt, rval, d_heads + l + 1, d_len + l + 1, nullptr, nullptr, nullptr});
+        // successor read (and owner cleared) per element; rid and relem written per ruler
+        GSS_LAUNCH_B((l == 0 ? 4 : 8) * cap + 8 * cap2, k_ruler_compact, dim3((unsigned)ntiles), dim3(RC_BLOCK), 0,
+                     st, cap, ntiles, a.Np, a.nxt, a.headp, l, rid, a.owner, a.relem, cap2, d_heads + l + 1,
+                     d_len + l + 1, status, epoch, lb_ticket_ptr(ctx), ctx->d_flags);
+        if (l == 0) {
+            // one tour record per arc (a vertex's record serves both of its arcs); one
+            // record per ruler
+            GSS_LAUNCH_B(16 * N0 + 36 * cap2, k_walk0, dim3(grid_for(cap2, PB)), dim3(PB), 0, st, cap2, d_len + 1,
+                         a.relem, rid, trec, a.headp, N0, rnxt, rval, ctx->d_flags);
+        } else {
+            // one walk over every element: successor and value read, owner and local
+            // prefix written; one record per ruler
+            GSS_LAUNCH_B(28 * cap + 28 * cap + 36 * cap2, k_walk1, dim3(grid_for(cap2, PB)), dim3(PB), 0, st, cap2,
+                         d_len + l + 1, a.relem, rid, a.nxt, a.val, a.headp, l, a.Np, a.owner, a.loc, rnxt, rval,
+                         ctx->d_flags);
+        }
+        lv.push_back(Lv{cap2, rnxt, rval, d_heads + l + 1, d_len + l + 1, nullptr, nullptr, nullptr, nullptr});
     }
     // base level
     Lv &b = lv.back();
@@ -900,15 +969,16 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const u128 
                      dim3(grid_for(a.cap, PB)), dim3(PB), 0, st, a.cap, a.Np, a.owner, a.loc, lv[l + 1].pre, a.pre);
     }
     if (lv.size() == 1) throw gss_error{GSS_ERR_HIP, "list ranking: tour shorter than one workgroup"};
-    // level 0: per arc owner, local prefix, term and parent read, Euler entry written; per
-    // vertex a 32-byte record
-    GSS_LAUNCH_B(52 * N0 + 24 * lv[1].cap + 8 * N0 + 16 * N0, k_euler_emit, dim3(grid_for(N0, PB)), dim3(PB), 0, st,
-                 (int32_t)N0, lv[0].owner, lv[0].loc, lv[1].pre, T, t->parent, t->L, t->vrec, t->epk, ctx->d_flags);
+    // level 0: per arc its tour record read; per vertex a 32-byte record and its LCA
+    // sequence entry; per ruler its prefix
+    const int64_t cap1 = lv[1].cap;
+    GSS_LAUNCH_B(16 * N0 + 4 * N0 + 16 * N0 + 28 * cap1, k_walk0_down, dim3(grid_for(cap1, PB)), dim3(PB), 0, st,
+                 cap1, d_len + 1, lv[0].relem, trec, lv[1].pre, d_heads, N0, n, t->vrec, t->epk, ctx->d_flags);
     HIP_OK(hipGetLastError());
 }
 
 // ------------------------------------------------------------------------------------
-// RMQ over the Euler sequence: blocks of 64 positions, superblocks of 64 blocks
+// RMQ over the preorder LCA sequence: blocks of 64 positions, superblocks of 64 blocks
 // ------------------------------------------------------------------------------------
 // One wave handles a run of up to 64 packed values, lane i holding value i (+inf past
 // the end).  Lane i computes: mask = positions q <= i whose value is strictly smaller
@@ -1173,37 +1243,21 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
-// vertex records before the tour: the root's is final (first = 0, depth 0, D = 0), the
-// others are marked unreached; the root's thread also writes the first Euler entry and
-// the head arc of the tour (the down arc into its first child; n > 1)
-__global__ void k_vrec_init(VRec *vrec, int32_t n, int32_t root, uint64_t *__restrict__ epk,
+// the root's vertex record (preorder index 0, depth 0, D = 0, its tree degree), its LCA
+// sequence entry (never inside a query range) and the head arc of the tour (the down
+// arc into its first child; n > 1); the tour writes every other record
+__global__ void k_vrec_root(VRec *vrec, int32_t n, int32_t root, uint64_t *__restrict__ epk,
                             const int32_t *__restrict__ cptr, const int32_t *__restrict__ clist, int64_t *head)
 {
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
     VRec r;
     r.D = mk128(0, 0);
-    r.first = x == root ? 0 : -1;
+    r.first = 0;
     r.depth = 0;
     r.parent = -1;
-    r.pad = 0;
-    vrec[x] = r;
-    if (x == root) {
-        epk[0] = (uint64_t)(uint32_t)root;
-        if (n > 1) *head = 2 * (int64_t)clist[cptr[root]];
-    }
-}
-
-// every vertex must have been reached by the tour; its tree degree goes to the record
-__global__ void k_vrec_finish(const int32_t *__restrict__ cptr, int32_t n, VRec *__restrict__ vrec, uint32_t *flags)
-{
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (x < n) {
-        bad = vrec[x].first < 0;
-        vrec[x].pad = cptr[x + 1] - cptr[x];
-    }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(flags, F_NOT_TREE);
+    r.pad = cptr[root + 1] - cptr[root];
+    vrec[root] = r;
+    epk[0] = (uint64_t)(uint32_t)root;
+    if (n > 1) *head = 2 * (int64_t)clist[cptr[root]];
 }
 
 
@@ -1255,23 +1309,20 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
                        (unsigned long long *)(ctx->d_counters + 10));
             ctx->free(hpart);
         }
+        // the CSR flags and hash sums are read back with the tree checks below (every
+        // kernel until then is memory-safe on malformed input)
         HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, 2 * sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
-        uint32_t f = read_flags(ctx);
-        if (f) fail(status_from_flags(f), "invalid graph");
-        if (ctx->h_counters[10] != 0 || ctx->h_counters[11] != 0)
-            fail(GSS_ERR_ASYM, "the graph is not symmetric");
     }
     t->ufirst = ctx->alloc<int32_t>(n);
     t->uptr = ctx->alloc<int32_t>(n + 1);
-    GSS_LAUNCH(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, t->ufirst, t->uptr);
+    GSS_LAUNCH(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, nnz, t->ufirst, t->uptr);
     HIP_OK(hipMemsetAsync(t->uptr + n, 0, sizeof(int32_t), st));
     int64_t m;
     scan_exclusive_i32_dev(ctx, t->uptr, n + 1, ctx->d_counters + 13);
     if (validate) {
-        // the symmetry check above makes m = nnz / 2; the scan total is compared with it
-        // at the final synchronisation instead of waiting for it here
-        if (nnz % 2) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
+        // the symmetry check makes m = nnz / 2; the scan total is compared with it at the
+        // final synchronisation instead of waiting for it here
         m = nnz / 2;
     } else {
         HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], ctx->d_counters + 13, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -1290,9 +1341,20 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
     GSS_LAUNCH_B(32 * (int64_t)n, k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st,
                  t->parent, t->row_ptr,
-               t->col, t->w, n, t->virt_root, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
+               t->col, t->w, n, nnz, t->virt_root, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     uint32_t f = read_flags(ctx);  // syncs
+    if (validate) {  // CSR checks first (their precedence), then the tree checks
+        const uint32_t fg = f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
+        if (fg) {
+            ctx->free(ccnt);
+            fail(status_from_flags(fg), "invalid graph");
+        }
+        if (ctx->h_counters[10] != 0 || ctx->h_counters[11] != 0 || nnz % 2) {
+            ctx->free(ccnt);
+            fail(GSS_ERR_ASYM, "the graph is not symmetric");
+        }
+    }
     int64_t roots = ctx->h_counters[0];
     t->root = (int32_t)ctx->h_counters[1];
     int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
@@ -1318,54 +1380,52 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     GSS_LAUNCH_B(20 * (int64_t)n, k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr,
                  cfill, clist, cslot);
 
-    // fixed-point terms and the 127-bit range check
-    u128 *T = ctx->alloc<u128>(n);
+    // tour records (successors, parent, degree, fixed-point term) and the 127-bit range
+    // check of the terms
+    TRec *trec = ctx->alloc<TRec>(n);
+    int32_t *succ = ctx->alloc<int32_t>(2 * (int64_t)n);
     int64_t tb = grid_for(n, PB);
     u128 *tbs = ctx->alloc<u128>(tb);
     uint64_t *tbc = ctx->alloc<uint64_t>(tb);
     const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
-    GSS_LAUNCH_B(28 * (int64_t)n, k_terms, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, n, t->root, (int)emin,
-                 terms_ok, T, tbs,
-               tbc);
+    // per vertex: tree-edge position, weight, parent, child range, slot and first child
+    // read; record and both successors written
+    GSS_LAUNCH_B(76 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, t->parent, cptr,
+                 clist, cslot, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
     GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
 
     // Euler tour
-    t->L = 2 * n - 1;
+    t->L = n;  // the LCA sequence is indexed by preorder
     t->vrec = ctx->alloc<VRec>(n);
     t->epk = ctx->alloc<uint64_t>(t->L);
-    GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, t->root, t->epk, cptr, clist,
+    GSS_LAUNCH(k_vrec_root, dim3(1), dim3(1), 0, st, t->vrec, n, t->root, t->epk, cptr, clist,
                ctx->d_counters + 12);
     if (n > 1) {
-        int32_t N = 2 * n;
-        int32_t *succ = ctx->alloc<int32_t>(N);
-        GSS_LAUNCH_B(24 * (int64_t)n, k_succ, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, cptr, clist, cslot, n,
-                     t->root, succ);
+        uint32_t earlier = 0;  // flags raised before a retry (the range check of the terms)
         for (int mult = 1;; mult *= 2) {
             std::vector<void *> bufs;
-            euler_rank(ctx, t, succ, T, ctx->d_counters + 12, mult, bufs);
-            GSS_LAUNCH(k_vrec_finish, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec, ctx->d_flags);
-            f = read_flags(ctx);
+            euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, bufs);
+            f = read_flags(ctx) | earlier;
             for (void *p : bufs) ctx->free(p);
             if (!(f & F_OVERFLOW) || (f & F_NOT_TREE)) break;
+            earlier = f & ~F_OVERFLOW;
             if (mult >= 8) {
                 ctx->free(succ);
+                ctx->free(trec);
                 fail(GSS_ERR_HIP, "list ranking: level capacity exceeded");
             }
             // a level outgrew its capacity (vanishingly rare): rank again with more room
             HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
-            GSS_LAUNCH(k_vrec_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->vrec, n, t->root, t->epk, cptr,
-                       clist, ctx->d_counters + 12);
         }
-        ctx->free(succ);
     } else {
-        GSS_LAUNCH(k_vrec_finish, dim3(grid_for(n, PB)), dim3(PB), 0, st, cptr, n, t->vrec, ctx->d_flags);
         f = read_flags(ctx);
     }
+    ctx->free(succ);
+    ctx->free(trec);
     ctx->free(cfill);
     ctx->free(clist);
     ctx->free(cslot);
     ctx->free(ccnt);
-    ctx->free(T);
     ctx->free(tbs);
     ctx->free(tbc);
     if (f & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array has a cycle");

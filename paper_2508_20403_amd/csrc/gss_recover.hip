@@ -4,7 +4,7 @@
 // Lemma "strictly similar edges share their LCA".
 //
 // Path of one pass:
-//  1. k_edge_stretch  every off-tree edge: LCA by RMQ over the Euler tour, exact
+//  1. k_edge_stretch  every off-tree edge: LCA by RMQ over the preorder sequence, exact
 //                     R_T = RN(D(u)+D(v)-2D(lca)), stretch = RN(w*R_T), beta*, sort key;
 //                     a 12-bit histogram of the key for the prefix selection.
 //  2. radix select    the smallest key threshold T whose set {key >= T} holds at least
@@ -45,7 +45,7 @@ struct RmqView {
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int ctz64(uint64_t x) { return __ffsll((long long)x) - 1; }
 
-// RMQ over Euler positions i..j (i <= j) with every load addressable from (i, j) issued
+// RMQ over preorder positions i..j (i <= j) with every load addressable from (i, j) issued
 // up front; only the in-block argmin reads depend on an earlier load.
 struct RmqPlan {
     int32_t i, j, bi, bj, b0, b1, s0, s1, a, c, k;
@@ -123,7 +123,7 @@ __device__ __forceinline__ uint64_t rmq_finish(const RmqView &q, const RmqPlan &
     return best;
 }
 
-// minimum packed (depth<<32|vertex) over Euler positions i..j (i <= j)
+// minimum packed (depth<<32|parent) over preorder positions i..j (i <= j)
 __device__ __forceinline__ uint64_t rmq(const RmqView &q, int32_t i, int32_t j)
 {
     RmqPlan P = rmq_plan(q, i, j);
@@ -179,8 +179,10 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
         RmqLoads ld[EDGE_ITEMS];
 #pragma unroll
         for (int t = 0; t < EDGE_ITEMS; t++) {
-            int32_t fu = ru[t].first, fv = rv[t].first;
-            pl[t] = rmq_plan(q, min(fu, fv), max(fu, fv));
+            // preorder positions (min, max]: u != v, so the range is not empty
+            const int32_t fu = ru[t].first, fv = rv[t].first;
+            const int32_t hi = max(fu, fv);
+            pl[t] = rmq_plan(q, min(min(fu, fv) + 1, hi), hi);
             ld[t] = rmq_issue(q, pl[t]);
         }
         uint64_t pk[EDGE_ITEMS];
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
             if (!ok[t]) continue;
             const int64_t j = jj[t];
             const int32_t l = (int32_t)(uint32_t)pk[t];
-            const int32_t dl = (int32_t)(pk[t] >> 32);
+            const int32_t dl = (int32_t)(pk[t] >> 32) - 1;  // the minimum is a child of l
             const int32_t du = ru[t].depth - dl, dv = rv[t].depth - dl;
             u128 R = add128(sub128(ru[t].D, Dl[t]), sub128(rv[t].D, Dl[t]));
             double r;
@@ -1703,7 +1705,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
     if (lcacnt) HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
     // per off-tree edge: u, v, w (16 B); first, depth and D of u and v and D of the LCA
-    // (56 B); the two Euler entries that answer the range minimum (16 B); key, LCA and
+    // (56 B); the two LCA-sequence entries that answer the range minimum (16 B); key, LCA and
     // beta* written (13 B); optional stretch (8 B)
     if (M > 0)
         if (STRETCH_HIST && G == 1)
