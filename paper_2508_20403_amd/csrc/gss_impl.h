@@ -1,5 +1,6 @@
 // gss_impl.h -- host-side internals of the gfx950 library.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -56,8 +57,8 @@ struct gss_ctx_s {
     std::vector<hipEvent_t> prof_events;           // free events
     std::map<std::string, prof_sum> prof_acc;      // name -> totals
     int64_t prof_bytes = 0;                        // algorithmic bytes of the next launch
-    void prof_begin(const char *name);
-    void prof_end();
+    // a timed launch's event pair (the launch records its own start and end), or null
+    prof_rec *prof_begin(const char *name);
     void prof_collect();                           // after a sync: accumulate elapsed times
 
     // subtask engine settings (autotuned) and the learned cost model
@@ -174,12 +175,16 @@ inline unsigned long long *lb_ticket_ptr(gss_ctx ctx) { return (unsigned long lo
 uint32_t read_flags(gss_ctx ctx);
 gss_status status_from_flags(uint32_t f);
 
-// every kernel launch goes through this, so it can be timed with events when asked
-#define GSS_LAUNCH(kern, grid, block, shmem, stream, ...)               \
-    do {                                                                \
-        if (ctx->prof) ctx->prof_begin(#kern);                          \
-        hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__); \
-        if (ctx->prof) ctx->prof_end();                                 \
+// every kernel launch goes through this, so it can be timed when asked: a timed launch
+// carries its start and stop events in the dispatch itself (no separate event packets
+// between kernels, so timing barely changes the stream's pace)
+#define GSS_LAUNCH(kern, grid, block, shmem, stream, ...)                                         \
+    do {                                                                                          \
+        prof_rec *pr_ = ctx->prof ? ctx->prof_begin(#kern) : nullptr;                              \
+        if (pr_)                                                                                  \
+            hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, pr_->a, pr_->b, 0, __VA_ARGS__); \
+        else                                                                                      \
+            hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                    \
     } while (0)
 // the same, stating the launch's algorithmic bytes: the least HBM traffic the step it
 // performs needs (each input read once, each output written once), for roofline figures

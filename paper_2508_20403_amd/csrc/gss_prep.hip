@@ -21,8 +21,12 @@
 
 #define PB 256          // default block size
 #define ENT_ITEMS 16    // CSR entries per thread in entry-parallel kernels
+#ifndef RULE_RATE0
 #define RULE_RATE0 4    // level 0 of the list ranking: one ruler per ~RULE_RATE0 arcs (power of two)
-#define RULE_RATE 4     // upper levels: one ruler per ~RULE_RATE elements (power of two)
+#endif
+#ifndef RULE_RATE
+#define RULE_RATE 8     // upper levels: one ruler per ~RULE_RATE elements (power of two)
+#endif
 #define BASE_MAX 4096   // lists this short are ranked by one workgroup
 #define BASE_THREADS 1024
 

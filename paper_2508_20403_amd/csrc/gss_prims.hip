@@ -59,14 +59,11 @@ void dev_pool::release_all()
 // ------------------------------------------------------------------------------------
 // live kernel timing
 // ------------------------------------------------------------------------------------
-void gss_ctx_s::prof_begin(const char *name)
+prof_rec *gss_ctx_s::prof_begin(const char *name)
 {
     const int64_t bytes = prof_bytes;
     prof_bytes = 0;
-    if (!prof_filter.empty() && prof_filter != name) {
-        prof_pending.push_back(prof_rec{nullptr, nullptr, nullptr, 0});
-        return;
-    }
+    if (!prof_filter.empty() && prof_filter != name) return nullptr;
     prof_rec r;
     r.name = name;
     r.bytes = bytes;
@@ -77,14 +74,8 @@ void gss_ctx_s::prof_begin(const char *name)
             prof_events.pop_back();
         }
     }
-    HIP_OK(hipEventRecord(r.a, stream));
     prof_pending.push_back(r);
-}
-
-void gss_ctx_s::prof_end()
-{
-    prof_rec &r = prof_pending.back();
-    if (r.name) HIP_OK(hipEventRecord(r.b, stream));
+    return &prof_pending.back();
 }
 
 void gss_ctx_s::prof_collect()
