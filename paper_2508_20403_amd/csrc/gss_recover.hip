@@ -496,7 +496,9 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restric
 // round) with wave-private digit counters, so the only workgroup barriers are around the
 // per-digit totals; tile order = (wave, round, lane) = index order.  The tile's base for
 // digit d is the global start of d plus the count of d in all earlier tiles (look-back
-// over status[tile][256]).
+// over status[tile][256]).  A digit position on which every key agrees needs no
+// scatter: the pass then copies its tile in place (so the ping-pong buffers stay in
+// step) and neither publishes nor reads look-back status.
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__restrict__ kin,
                                                           const int32_t *__restrict__ vin, int64_t n, int shift,
                                                           int64_t ntiles, const int32_t *__restrict__ ghist,
@@ -509,14 +511,32 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__rest
     __shared__ int32_t s_base[NW][256];  // per wavefront: output base of each digit
     __shared__ int32_t s_scan[NW + 1];
     __shared__ int64_t s_tile;
+    __shared__ int s_const;
     const int t = threadIdx.x, wid = t / GSS_WAVE, lane = lane_id();
-    if (t == 0) s_tile = lb_ticket(ticket, ntiles);
+    if (t == 0) {
+        s_tile = lb_ticket(ticket, ntiles);
+        s_const = 0;
+    }
 #pragma unroll
     for (int w = 0; w < NW; w++) s_cnt[w][t] = 0;
+    const int32_t gh = ghist[t];
     int32_t gtot;
-    const int32_t gstart = block_exclusive_scan<int32_t>(ghist[t], s_scan, &gtot);  // synchronises
+    const int32_t gstart = block_exclusive_scan<int32_t>(gh, s_scan, &gtot);  // synchronises
+    if ((int64_t)gh == n) s_const = 1;  // one digit holds every key
+    __syncthreads();
     const int64_t tile = s_tile;
     const int64_t wbase = tile * RS_TILE + (int64_t)wid * (RS_ITEMS * GSS_WAVE);
+    if (s_const) {
+#pragma unroll
+        for (int i = 0; i < RS_ITEMS; i++) {
+            const int64_t idx = wbase + i * GSS_WAVE + lane;
+            if (idx < n) {
+                kout[idx] = kin[idx];
+                vout[idx] = vin[idx];
+            }
+        }
+        return;
+    }
     uint64_t kk[RS_ITEMS];
     int32_t vv[RS_ITEMS], pos[RS_ITEMS];
 #pragma unroll
@@ -631,7 +651,6 @@ __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const i
 #define JP_BITS_MIN 11                   // 2048 partitions ...
 #define JP_BITS_MAX 14                   // ... up to 16384, about 1024 records each
 #define JP_BLOCK 256
-#define JP_ITEMS 32                      // record slots per thread per 2048 partitions
 #define JP_CAP 2048                      // records of a partition held in LDS at once
 #define JP_TAB (2 * JP_CAP)              // LDS hash slots
 #define JP_PROBE (1u << 31)
@@ -645,151 +664,112 @@ struct JRec {
 __device__ __forceinline__ uint64_t jp_hash(uint64_t ab) { return mix64(ab * 0x9E3779B97F4A7C15ull + 1); }
 __device__ __forceinline__ uint32_t jp_part(uint64_t ab, int bits) { return (uint32_t)(jp_hash(ab) >> (64 - bits)); }
 
-// record slot s = (listed edge g, r) = g * S + r: r < 2(c+1)^2 build, then (c+1)^2 probe
-// slots.  A workgroup divides its first slot by S once; every other slot is a small
-// offset from it, split by a float reciprocal with one correction step (offsets stay
-// below 2^24, so the estimate is within one of the quotient).  r is split by (c+1) and
-// (c+1)^2 with 16-bit multiply-shift reciprocals, exact for r < 3(c+1)^2 <= 243.
-struct JpSlots {
-    int64_t g0;
-    int32_t r0, S;
-    float invS;
-    int32_t C1, C1sq;
-    uint32_t M1, M2;  // ceil(2^16 / (c+1)), ceil(2^16 / (c+1)^2)
-};
-__device__ __forceinline__ JpSlots jp_slots(int64_t s0, int32_t c)
+// Every listed edge is handled by one thread, which loads the edge's ancestor chains once
+// and emits all its records: build records for both orientations and every i, k <= c,
+// probe records for j, l <= beta* (none when beta* = 0: such an edge marks nothing).
+// A record whose key holds a missing ancestor (above the root) is not emitted.  The
+// count and scatter passes give each workgroup the same edges, so the per-workgroup
+// partition counts of the first pass are exactly the records the second one writes.
+template <int C, bool WRITE>
+__device__ __forceinline__ void jp_emit_edge(int32_t p, int beta, const int32_t (&au)[C + 1],
+                                             const int32_t (&av)[C + 1], int bits, int32_t *sh,
+                                             JRec *__restrict__ recs)
 {
-    JpSlots b;
-    b.C1 = c + 1;
-    b.C1sq = b.C1 * b.C1;
-    b.S = 3 * b.C1sq;
-    b.g0 = s0 / b.S;
-    b.r0 = (int32_t)(s0 - b.g0 * b.S);
-    b.invS = 1.0f / (float)b.S;
-    b.M1 = (65536u + b.C1 - 1) / b.C1;
-    b.M2 = (65536u + b.C1sq - 1) / b.C1sq;
-    return b;
-}
-__device__ __forceinline__ void jp_slot(const JpSlots &b, int32_t o, int64_t &g, int32_t &r)
-{
-    const int32_t x = b.r0 + o;
-    int32_t q = (int32_t)((float)x * b.invS);
-    int32_t rem = x - q * b.S;
-    if (rem >= b.S) {
-        q++;
-        rem -= b.S;
-    } else if (rem < 0) {
-        q--;
-        rem += b.S;
-    }
-    g = b.g0 + q;
-    r = rem;
-}
-// rank of listed edge g (-1 past the list)
-__device__ __forceinline__ int32_t jp_rank(int64_t g, int64_t ng, const int32_t *__restrict__ glist)
-{
-    return g < ng ? glist[g] : -1;
-}
-__device__ __forceinline__ bool jp_record(const JpSlots &sl, int32_t r, int32_t p, int64_t P,
-                                          const uint8_t *__restrict__ rb, const int32_t *__restrict__ ancU,
-                                          const int32_t *__restrict__ ancV, JRec &rec)
-{
-    if (p < 0) return false;
-    int32_t A, B;
-    if (r < 2 * sl.C1sq) {
-        const int32_t orient = (int32_t)(((uint32_t)r * sl.M2) >> 16);
-        const int32_t q = r - orient * sl.C1sq;
-        const int32_t i = (int32_t)(((uint32_t)q * sl.M1) >> 16), k = q - i * sl.C1;
-        A = (orient ? ancV : ancU)[(int64_t)i * P + p];
-        B = (orient ? ancU : ancV)[(int64_t)k * P + p];
-        rec.meta = ((uint32_t)i << 8) | (uint32_t)k;
-    } else {
-        const int32_t q = r - 2 * sl.C1sq;
-        const int32_t j = (int32_t)(((uint32_t)q * sl.M1) >> 16), l = q - j * sl.C1;
-        const int beta = rb[p];
-        if (beta == 0 || j > beta || l > beta) return false;  // beta* = 0 marks nothing
-        A = ancU[(int64_t)j * P + p];
-        B = ancV[(int64_t)l * P + p];
-        rec.meta = JP_PROBE | ((uint32_t)j << 16) | ((uint32_t)l << 8) | (uint32_t)beta;
-    }
-    if (A < 0 || B < 0) return false;
-    rec.ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
-    rec.p = p;
-    return true;
-}
-#define JP_BATCH 8
-
-// pass 1: per-block partition histogram, stored partition-major: hist[part * nblk + block]
-__global__ __launch_bounds__(JP_BLOCK) void k_jp_count(int64_t nslots, int32_t S, const int32_t *__restrict__ glist,
-                                                        int64_t P, int32_t c, const uint8_t *__restrict__ rb,
-                                                        const int32_t *__restrict__ ancU,
-                                                        const int32_t *__restrict__ ancV, int bits, int items,
-                                                        int32_t nblk, int32_t *__restrict__ hist)
-{
-    extern __shared__ int32_t sh[];  // one counter per partition
-    const int nparts = 1 << bits;
-    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) sh[b] = 0;
-    __syncthreads();
-    const JpSlots sl = jp_slots((int64_t)blockIdx.x * JP_BLOCK * items, c);
-    const int64_t ng = nslots / S;
-    for (int it0 = 0; it0 < items; it0 += JP_BATCH) {
-        int64_t g[JP_BATCH];
-        int32_t r[JP_BATCH], pr[JP_BATCH];
-#pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) {
-            jp_slot(sl, (it0 + b) * JP_BLOCK + (int32_t)threadIdx.x, g[b], r[b]);
-            pr[b] = jp_rank(g[b], ng, glist);
+    auto emit = [&](int32_t A, int32_t B, uint32_t meta) {
+        if (A < 0 || B < 0) return;
+        const unsigned long long ab = ((unsigned long long)(uint32_t)A << 32) | (uint32_t)B;
+        const uint32_t part = jp_part(ab, bits);
+        if (WRITE) {
+            JRec r;
+            r.ab = ab;
+            r.p = p;
+            r.meta = meta;
+            recs[atomicAdd(&sh[part], 1)] = r;
+        } else {
+            atomicAdd(&sh[part], 1);
         }
-        uint32_t part[JP_BATCH];
+    };
 #pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) {
-            JRec rec;
-            part[b] = jp_record(sl, r[b], pr[b], P, rb, ancU, ancV, rec) ? jp_part(rec.ab, bits) : (uint32_t)nparts;
+    for (int i = 0; i <= C; i++)
+#pragma unroll
+        for (int k = 0; k <= C; k++) {
+            emit(au[i], av[k], ((uint32_t)i << 8) | (uint32_t)k);
+            emit(av[i], au[k], ((uint32_t)i << 8) | (uint32_t)k);
         }
+    if (beta > 0) {
 #pragma unroll
-        for (int b = 0; b < JP_BATCH; b++)
-            if (part[b] < (uint32_t)nparts) atomicAdd(&sh[part[b]], 1);
+        for (int j = 0; j <= C; j++)
+#pragma unroll
+            for (int l = 0; l <= C; l++)
+                if (j <= beta && l <= beta)
+                    emit(au[j], av[l], JP_PROBE | ((uint32_t)j << 16) | ((uint32_t)l << 8) | (uint32_t)beta);
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) hist[(int64_t)b * nblk + blockIdx.x] = sh[b];
 }
 
-// pass 2: the same records, written at their partition offsets (order inside a
-// partition is immaterial)
-__global__ __launch_bounds__(JP_BLOCK) void k_jp_scatter(int64_t nslots, int32_t S,
-                                                          const int32_t *__restrict__ glist, int64_t P, int32_t c,
+// pass 1 (WRITE = false): per-workgroup partition histogram, stored partition-major:
+// hist[part * nblk + block].  Pass 2 (WRITE = true): the same records, written at their
+// partition offsets off[part * nblk + block] (order inside a partition is immaterial).
+// Workgroup b owns listed edges [b * JP_BLOCK * ept, (b + 1) * JP_BLOCK * ept).
+template <int C, bool WRITE>
+__global__ __launch_bounds__(JP_BLOCK) void k_jp_records(int64_t ng, const int32_t *__restrict__ glist, int64_t P,
                                                           const uint8_t *__restrict__ rb,
                                                           const int32_t *__restrict__ ancU,
-                                                          const int32_t *__restrict__ ancV, int bits, int items,
-                                                          int32_t nblk, const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ ancV, int bits, int ept,
+                                                          int32_t nblk, int32_t *__restrict__ hist,
                                                           JRec *__restrict__ recs)
 {
-    extern __shared__ int32_t sh[];  // one output cursor per partition
+    extern __shared__ int32_t sh[];  // one counter (or output cursor) per partition
     const int nparts = 1 << bits;
-    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) sh[b] = off[(int64_t)b * nblk + blockIdx.x];
+    for (int b = threadIdx.x; b < nparts; b += JP_BLOCK)
+        sh[b] = WRITE ? hist[(int64_t)b * nblk + blockIdx.x] : 0;
     __syncthreads();
-    const JpSlots sl = jp_slots((int64_t)blockIdx.x * JP_BLOCK * items, c);
-    const int64_t ng = nslots / S;
-    for (int it0 = 0; it0 < items; it0 += JP_BATCH) {
-        int64_t g[JP_BATCH];
-        int32_t r[JP_BATCH], pr[JP_BATCH];
+    const int64_t g0 = (int64_t)blockIdx.x * JP_BLOCK * ept;
+    for (int it = 0; it < ept; it++) {
+        const int64_t g = g0 + (int64_t)it * JP_BLOCK + threadIdx.x;
+        if (g >= ng) break;
+        const int32_t p = glist[g];
+        const int beta = rb[p];
+        int32_t au[C + 1], av[C + 1];
 #pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) {
-            jp_slot(sl, (it0 + b) * JP_BLOCK + (int32_t)threadIdx.x, g[b], r[b]);
-            pr[b] = jp_rank(g[b], ng, glist);
+        for (int i = 0; i <= C; i++) {
+            au[i] = ancU[(int64_t)i * P + p];
+            av[i] = ancV[(int64_t)i * P + p];
         }
-        JRec rec[JP_BATCH];
-        bool ok[JP_BATCH];
-#pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) ok[b] = jp_record(sl, r[b], pr[b], P, rb, ancU, ancV, rec[b]);
-#pragma unroll
-        for (int b = 0; b < JP_BATCH; b++) {
-            if (ok[b]) {
-                const int32_t pos = atomicAdd(&sh[jp_part(rec[b].ab, bits)], 1);
-                recs[pos] = rec[b];
-            }
-        }
+        jp_emit_edge<C, WRITE>(p, beta, au, av, bits, sh, recs);
     }
+    if (!WRITE) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < nparts; b += JP_BLOCK) hist[(int64_t)b * nblk + blockIdx.x] = sh[b];
+    }
+}
+
+static void launch_jp_records(gss_ctx ctx, int C, bool write, int64_t ng, const int32_t *glist, int64_t P,
+                              const uint8_t *rb, const int32_t *ancU, const int32_t *ancV, int bits, int ept,
+                              int32_t nblk, int32_t *hist, JRec *recs)
+{
+    hipStream_t st = ctx->stream;
+    const size_t lds = sizeof(int32_t) << bits;
+    // per listed edge: rank, beta* and 2(c+1) ancestors read; with WRITE, 16 B per
+    // record written
+    const int64_t rd = ng * (5 + 8 * (int64_t)(C + 1));
+    const int64_t wr = write ? 16 * ng * 3 * (int64_t)(C + 1) * (C + 1) : 0;
+    switch (C) {
+#define CASE(k)                                                                                            \
+    case k: {                                                                                              \
+        auto k_jp_count = &k_jp_records<k, false>;                                                         \
+        auto k_jp_scatter = &k_jp_records<k, true>;                                                        \
+        if (write)                                                                                         \
+            GSS_LAUNCH_B(rd + wr, k_jp_scatter, dim3(nblk), dim3(JP_BLOCK), lds, st, ng, glist, P, rb, ancU, \
+                         ancV, bits, ept, nblk, hist, recs);                                               \
+        else                                                                                               \
+            GSS_LAUNCH_B(rd, k_jp_count, dim3(nblk), dim3(JP_BLOCK), lds, st, ng, glist, P, rb, ancU, ancV,  \
+                         bits, ept, nblk, hist, recs);                                                     \
+    } break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: throw gss_error{GSS_ERR_ARG, "beta out of range"};
+    }
+    HIP_OK(hipGetLastError());
 }
 
 // pass 3: one workgroup per partition.  Build records of a chunk of JP_CAP records go
@@ -1224,10 +1204,10 @@ static void read_counters(gss_ctx ctx, int nwords)
     ctx->sync();
 }
 
-// Stable LSD radix sort of (key, val) pairs by key ascending.  With key_bytes = 0 the
-// digit histograms are read back and only varying digits are sorted; with key_bytes > 0
-// (keys known to be below 2^(8 key_bytes)) every low digit is sorted and the host never
-// waits for the device.
+// Stable LSD radix sort of (key, val) pairs by key ascending, with no host round trip.
+// With key_bytes = 0 all eight digit positions run (a position where every key agrees
+// is a plain copy); with key_bytes > 0 (keys known to be below 2^(8 key_bytes)) only the
+// low key_bytes positions run.
 static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n,
                              int key_bytes = 0)
 {
@@ -1238,22 +1218,8 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     HIP_OK(hipMemsetAsync(ghist, 0, sizeof(int32_t) * 8 * 256, st));
     GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n,
                  ghist);
-    bool run[8];
-    if (key_bytes > 0) {
-        for (int p = 0; p < 8; p++) run[p] = p < key_bytes;
-    } else {
-        std::vector<int32_t> h(8 * 256);
-        HIP_OK(hipMemcpyAsync(h.data(), ghist, sizeof(int32_t) * 8 * 256, hipMemcpyDeviceToHost, st));
-        ctx->sync();
-        for (int p = 0; p < 8; p++) {
-            // a byte position is constant when one digit holds every key
-            bool constant = false;
-            for (int d = 0; d < 256; d++) constant |= (h[p * 256 + d] == n);
-            run[p] = !constant;
-        }
-    }
-    for (int p = 0; p < 8; p++) {
-        if (!run[p]) continue;
+    const int npos = key_bytes > 0 ? key_bytes : 8;
+    for (int p = 0; p < npos; p++) {
         uint32_t epoch = 0;
         uint64_t *status = lb_begin(ctx, ntiles * 256, &epoch);
         GSS_LAUNCH_B(24 * n, k_rs_onesweep, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, k, v, n, 8 * p, ntiles,
@@ -1340,7 +1306,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
     if (G > 1) {  // stable by graph: each graph's prefix becomes contiguous, in rank order
         GSS_LAUNCH(k_graph_key, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, v1, t->off_g, k1);
-        radix_sort_pairs(ctx, k1, v1, k2, v2, P);
+        radix_sort_pairs(ctx, k1, v1, k2, v2, P, bytes_for((uint64_t)(G - 1)));
     }
     B.sj = v1;
     std::vector<int64_t> ps(G + 1, 0);
@@ -1485,20 +1451,20 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         int bits = JP_BITS_MIN;
         while (bits < JP_BITS_MAX && nslots > ((int64_t)1024 << bits)) bits++;
         const int32_t nparts = 1 << bits;
-        const int items = JP_ITEMS << (bits - JP_BITS_MIN);  // keeps the histogram matrix at nslots / 4 entries
-        const int32_t nblk = (int32_t)((nslots + (int64_t)JP_BLOCK * items - 1) / ((int64_t)JP_BLOCK * items));
+        // edges per thread: about four records per partition counter in each workgroup,
+        // which keeps the histogram matrix near nslots / 4 entries
+        const int64_t per_edge = 3 * (int64_t)(c + 1) * (c + 1);
+        const int ept = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4 * (int64_t)nparts + JP_BLOCK * per_edge - 1) /
+                                                                            (JP_BLOCK * per_edge)));
+        const int32_t nblk = (int32_t)((nglobal_edges + (int64_t)JP_BLOCK * ept - 1) / ((int64_t)JP_BLOCK * ept));
         int32_t *jhist = ctx->alloc<int32_t>((int64_t)nparts * nblk + 1);
         JRec *recs = ctx->alloc<JRec>(nslots + 1);
         int64_t *d_total = ctx->d_counters + 8;
-        const size_t lds = sizeof(int32_t) * nparts;
-        const int32_t S = 3 * (c + 1) * (c + 1);
-        // per listed edge: rank, beta* and 2(c+1) ancestors read (twice: count, scatter);
-        // 16 B per record written and read back by the join
-        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)), k_jp_count, dim3(nblk), dim3(JP_BLOCK), lds, st, nslots, S,
-                     B.glist, P, c, B.rb, B.ancU, B.ancV, bits, items, nblk, jhist);
+        launch_jp_records(ctx, c, false, nglobal_edges, B.glist, P, B.rb, B.ancU, B.ancV, bits, ept, nblk, jhist,
+                          recs);
         scan_exclusive_i32_dev(ctx, jhist, (int64_t)nparts * nblk, d_total);
-        GSS_LAUNCH_B(nglobal_edges * (5 + 8 * (c + 1)) + 16 * nslots, k_jp_scatter, dim3(nblk), dim3(JP_BLOCK), lds, st,
-                     nslots, S, B.glist, P, c, B.rb, B.ancU, B.ancV, bits, items, nblk, jhist, recs);
+        launch_jp_records(ctx, c, true, nglobal_edges, B.glist, P, B.rb, B.ancU, B.ancV, bits, ept, nblk, jhist,
+                          recs);
         const int32_t arc_slot = 128;
         int32_t *arc_cnt = ctx->alloc<int32_t>(nparts + 1);
         int32_t *arc_off = ctx->alloc<int32_t>(nparts + 1);
