@@ -25,7 +25,7 @@
 #define RULE_RATE0 4    // level 0 of the list ranking: one ruler per ~RULE_RATE0 arcs (power of two)
 #endif
 #ifndef RULE_RATE
-#define RULE_RATE 8     // upper levels: one ruler per ~RULE_RATE elements (power of two)
+#define RULE_RATE 4     // upper levels: one ruler per ~RULE_RATE elements (power of two)
 #endif
 #define BASE_MAX 4096   // lists this short are ranked by one workgroup
 #define BASE_THREADS 1024
@@ -551,6 +551,29 @@ __device__ __forceinline__ LVal lv_zero()
     return r;
 }
 
+// element of an upper level of the list ranking (a ruler of the level below): its
+// successor and its sublist sum in one 32-byte record, so a step of a walk is one load
+struct __attribute__((aligned(32))) LRec {
+    int32_t nxt, cnt, dep, pad;
+    u128 D;
+};
+__device__ __forceinline__ LRec lrec(int32_t nxt, const LVal &v)
+{
+    LRec r;
+    r.nxt = nxt;
+    r.cnt = v.cnt;
+    r.dep = v.dep;
+    r.pad = 0;
+    r.D = v.D;
+    return r;
+}
+__device__ __forceinline__ void lv_acc(LVal &acc, const LRec &e)
+{
+    acc.cnt += e.cnt;
+    acc.dep += e.dep;
+    acc.D = add128(acc.D, e.D);
+}
+
 __device__ __forceinline__ bool is_ruler(int32_t i, int32_t head, int32_t level)
 {
     return i == head || (mix32((uint32_t)i * 0x9E3779B9u + (uint32_t)level * 0x7F4A7C15u) &
@@ -580,16 +603,16 @@ __device__ __forceinline__ int32_t arc_step(int32_t i, const TRec &e, LVal &acc)
 // Level l: elements i < N_l with successor nxt[i] (GSS_END ends the list, -2 = not in
 // the list) and value val(i).  Rulers (the head and a hashed 1/RULE_RATE sample) walk
 // their sublists once; the sublist sums and the next rulers form the level l+1 list.
-// Level 0 (the 2n arcs) walks the tour records and keeps nothing per arc: once level 1
-// is ranked, every ruler walks its sublist again from its prefix and writes the Euler
-// sequence and the vertex records directly.  Upper levels record for every element its
-// ruler (owner) and the exclusive sum of the sublist before it (loc), and the way down
-// is the coalesced pass rpre[owner] + loc.
+// Level 0 (the 2n arcs, read from the per-vertex tour records) keeps nothing per arc:
+// once level 1 is ranked, every ruler walks its sublist again from its prefix and writes
+// the vertex records and the LCA sequence directly.  Upper levels record for every
+// element its ruler (owner) and the exclusive sum of the sublist before it (loc), and
+// their way down is the coalesced pass rpre[owner] + loc.
 
 // Ruler selection and numbering in one pass (a stream compaction with decoupled
 // look-back): rid[i] = number of rulers before i (written for rulers only), relem[rid] =
-// i, the level length R_{l+1} and head; owner[i] = -1 for every element (upper levels;
-// level 0 keeps no owners).  Thread t of
+// i, the level length R_{l+1} and head; owner[i] = -1 for every element when an owner
+// array is given (upper levels).  Thread t of
 // round r owns the four consecutive elements at tile offset 4 (r*256 + t).
 #define RC_BLOCK 256
 #define RC_ROUNDS 4
@@ -698,7 +721,7 @@ __global__ __launch_bounds__(RC_BLOCK) void k_ruler_compact(int64_t cap, int64_t
 __global__ __launch_bounds__(PB) void k_walk0(int64_t cap_next, const int64_t *__restrict__ Rp,
                                               const int32_t *__restrict__ relem, const int32_t *__restrict__ rid,
                                               const TRec *__restrict__ trec, const int32_t *__restrict__ headp,
-                                              int64_t N, int32_t *__restrict__ rnxt, LVal *__restrict__ rval,
+                                              int64_t N, int32_t *__restrict__ rnxt, LRec *__restrict__ rrec,
                                               uint32_t *flags)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -721,7 +744,7 @@ __global__ __launch_bounds__(PB) void k_walk0(int64_t cap_next, const int64_t *_
     int32_t nr = (j < 0) ? GSS_END : rid[j];
     if (nr >= cap_next) nr = GSS_END;  // overflow, already flagged by k_ruler_compact
     rnxt[r] = nr;
-    rval[r] = acc;
+    rrec[r] = lrec(nr, acc);
 }
 
 // level-0 way down: ruler r walks its sublist again from its exclusive prefix rpre[r].
@@ -766,25 +789,27 @@ __global__ __launch_bounds__(PB) void k_walk0_down(int64_t cap_next, const int64
     }
 }
 
-// upper-level walk: one thread per ruler r < R_{l+1}
-__global__ void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp, const int32_t *__restrict__ relem,
-                        const int32_t *__restrict__ rid, const int32_t *__restrict__ nxt,
-                        const LVal *__restrict__ val, const int32_t *__restrict__ headp, int32_t level,
-                        const int64_t *__restrict__ Np, int32_t *__restrict__ owner, LVal *__restrict__ loc,
-                        int32_t *__restrict__ rnxt, LVal *__restrict__ rval, uint32_t *flags)
+// upper-level walk (level l >= 1): one thread per ruler r < R_{l+1}; per element one
+// record load, its owner and local prefix written; per ruler the next level's record
+__global__ __launch_bounds__(PB) void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp,
+                                              const int32_t *__restrict__ relem, const int32_t *__restrict__ rid,
+                                              const LRec *__restrict__ rec, const int32_t *__restrict__ headp,
+                                              int32_t level, int64_t N, int32_t *__restrict__ owner,
+                                              LVal *__restrict__ loc, int32_t *__restrict__ rnxt,
+                                              LRec *__restrict__ rrec, uint32_t *flags)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= cap_next || r >= *Rp) return;
-    const int64_t N = *Np;
     const int32_t head = *headp;
     int32_t i = relem[r];
     LVal acc = lv_zero();
     int32_t j;
     for (int64_t steps = 0;; steps++) {
+        const LRec e = rec[i];
         owner[i] = (int32_t)r;
         loc[i] = acc;
-        acc = lv_add(acc, val[i]);
-        j = nxt[i];
+        lv_acc(acc, e);
+        j = e.nxt;
         if (j < 0 || is_ruler(j, head, level)) break;
         if (steps > N) {  // a cycle without rulers beyond this one: not a tree
             atomicOr(flags, F_NOT_TREE);
@@ -796,14 +821,14 @@ __global__ void k_walk1(int64_t cap_next, const int64_t *__restrict__ Rp, const 
     int32_t nr = (j < 0) ? GSS_END : rid[j];
     if (nr >= cap_next) nr = GSS_END;  // overflow, already flagged by k_ruler_compact
     rnxt[r] = nr;
-    rval[r] = acc;
+    rrec[r] = lrec(nr, acc);
 }
 
 // base case: Wyllie pointer jumping in LDS, exclusive prefix from the head; every thread
 // owns BASE_MAX / BASE_THREADS elements
-__global__ __launch_bounds__(BASE_THREADS) void k_rank_base(const int64_t *__restrict__ Np,
+__global__ __launch_bounds__(BASE_THREADS) void k_rank_base(const int64_t *__restrict__ Np, int64_t cap,
                                                             const int32_t *__restrict__ nxt,
-                                                            const LVal *__restrict__ val,
+                                                            const LRec *__restrict__ rec,
                                                             const int32_t *__restrict__ headp, int64_t expect,
                                                             LVal *__restrict__ pre, uint32_t *flags)
 {
@@ -811,7 +836,7 @@ __global__ __launch_bounds__(BASE_THREADS) void k_rank_base(const int64_t *__res
     __shared__ int32_t snx[BASE_MAX];
     __shared__ LVal ssuf[BASE_MAX];
     const int64_t N64 = *Np;
-    if (N64 > BASE_MAX) {  // uniform across the workgroup
+    if (N64 > BASE_MAX || N64 > cap) {  // uniform across the workgroup
         if (threadIdx.x == 0) atomicOr(flags, F_OVERFLOW);
         return;
     }
@@ -819,7 +844,10 @@ __global__ __launch_bounds__(BASE_THREADS) void k_rank_base(const int64_t *__res
     const int32_t head = *headp;
     for (int32_t i = threadIdx.x; i < N; i += BASE_THREADS) {
         snx[i] = nxt[i];
-        ssuf[i] = val[i];
+        const LRec e = rec[i];
+        ssuf[i].cnt = e.cnt;
+        ssuf[i].dep = e.dep;
+        ssuf[i].D = e.D;
     }
     __syncthreads();
     int rounds = 1;
@@ -902,14 +930,14 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const TRec 
     const int64_t N0 = 2 * (int64_t)n;
     struct Lv {
         int64_t cap;
-        const int32_t *nxt;
-        const LVal *val;
+        const int32_t *nxt;    // successors (ruler selection, base level)
+        const LRec *rec;       // records (levels >= 1)
         const int32_t *headp;
         const int64_t *Np;
-        int32_t *owner;
-        LVal *loc;
-        LVal *pre;
-        int32_t *relem;  // this level's rulers (kept for level 0's way down)
+        LVal *pre;             // exclusive prefixes (levels >= 1)
+        int32_t *relem;        // this level's rulers
+        int32_t *owner;        // ruler of each element (levels >= 1)
+        LVal *loc;             // sum of the element's sublist before it (levels >= 1)
     };
     // device scalars: level lengths and heads
     const int max_levels = 40;
@@ -927,16 +955,16 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const TRec 
         const int64_t cap = a.cap;
         const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult, l), cap);
         int32_t *rid = ctx->alloc<int32_t>(cap + 1);
+        a.relem = ctx->alloc<int32_t>(cap2 + 1);
+        int32_t *rnxt = ctx->alloc<int32_t>(cap2 + 1);
+        LRec *rrec = ctx->alloc<LRec>(cap2 + 1);
+        for (void *p : {(void *)rid, (void *)a.relem, (void *)rnxt, (void *)rrec}) bufs.push_back(p);
         if (l > 0) {
             a.owner = ctx->alloc<int32_t>(cap + 1);
             a.loc = ctx->alloc<LVal>(cap + 1);
             bufs.push_back(a.owner);
             bufs.push_back(a.loc);
         }
-        a.relem = ctx->alloc<int32_t>(cap2 + 1);
-        int32_t *rnxt = ctx->alloc<int32_t>(cap2 + 1);
-        LVal *rval = ctx->alloc<LVal>(cap2 + 1);
-        for (void *p : {(void *)rid, (void *)a.relem, (void *)rnxt, (void *)rval}) bufs.push_back(p);
         const int64_t ntiles = (cap + RC_TILE - 1) / RC_TILE;
         uint32_t epoch = 0;
         uint64_t *status = lb_begin(ctx, ntiles, &epoch);
@@ -944,25 +972,23 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const TRec 
         GSS_LAUNCH_B((l == 0 ? 4 : 8) * cap + 8 * cap2, k_ruler_compact, dim3((unsigned)ntiles), dim3(RC_BLOCK), 0,
                      st, cap, ntiles, a.Np, a.nxt, a.headp, l, rid, a.owner, a.relem, cap2, d_heads + l + 1,
                      d_len + l + 1, status, epoch, lb_ticket_ptr(ctx), ctx->d_flags);
-        if (l == 0) {
-            // one tour record per arc (a vertex's record serves both of its arcs); one
-            // record per ruler
-            GSS_LAUNCH_B(16 * N0 + 36 * cap2, k_walk0, dim3(grid_for(cap2, PB)), dim3(PB), 0, st, cap2, d_len + 1,
-                         a.relem, rid, trec, a.headp, N0, rnxt, rval, ctx->d_flags);
-        } else {
-            // one walk over every element: successor and value read, owner and local
-            // prefix written; one record per ruler
-            GSS_LAUNCH_B(28 * cap + 28 * cap + 36 * cap2, k_walk1, dim3(grid_for(cap2, PB)), dim3(PB), 0, st, cap2,
-                         d_len + l + 1, a.relem, rid, a.nxt, a.val, a.headp, l, a.Np, a.owner, a.loc, rnxt, rval,
+        // one record per element (level 0: a vertex's tour record serves both of its
+        // arcs; upper levels also write the element's owner and local prefix); per ruler
+        // its successor and record
+        if (l == 0)
+            GSS_LAUNCH_B(16 * N0 + 44 * cap2, k_walk0, dim3(grid_for(cap2, PB)), dim3(PB), 0, st, cap2, d_len + 1,
+                         a.relem, rid, trec, a.headp, N0, rnxt, rrec, ctx->d_flags);
+        else
+            GSS_LAUNCH_B(60 * cap + 44 * cap2, k_walk1, dim3(grid_for(cap2, PB)), dim3(PB), 0, st, cap2,
+                         d_len + l + 1, a.relem, rid, a.rec, a.headp, l, cap, a.owner, a.loc, rnxt, rrec,
                          ctx->d_flags);
-        }
-        lv.push_back(Lv{cap2, rnxt, rval, d_heads + l + 1, d_len + l + 1, nullptr, nullptr, nullptr, nullptr});
+        lv.push_back(Lv{cap2, rnxt, rrec, d_heads + l + 1, d_len + l + 1, nullptr, nullptr, nullptr, nullptr});
     }
     // base level
     Lv &b = lv.back();
     b.pre = ctx->alloc<LVal>(b.cap + 1);
     bufs.push_back(b.pre);
-    GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_THREADS), 0, st, b.Np, b.nxt, b.val, b.headp, N0 - 2, b.pre,
+    GSS_LAUNCH(k_rank_base, dim3(1), dim3(BASE_THREADS), 0, st, b.Np, b.cap, b.nxt, b.rec, b.headp, N0 - 2, b.pre,
                ctx->d_flags);
     // downward
     for (int l = (int)lv.size() - 2; l >= 1; l--) {
@@ -1411,13 +1437,15 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
             euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, bufs);
             f = read_flags(ctx) | earlier;
             for (void *p : bufs) ctx->free(p);
-            if (!(f & F_OVERFLOW) || (f & F_NOT_TREE)) break;
-            earlier = f & ~F_OVERFLOW;
+            if (!(f & F_OVERFLOW)) break;
             if (mult >= 8) {
+                if (f & F_NOT_TREE) break;
                 ctx->free(succ);
                 ctx->free(trec);
                 fail(GSS_ERR_HIP, "list ranking: level capacity exceeded");
             }
+            // an attempt that ran out of room proves nothing about the tree: rank again
+            earlier = f & ~(F_OVERFLOW | F_NOT_TREE);
             // a level outgrew its capacity (vanishingly rare): rank again with more room
             HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
         }
