@@ -108,6 +108,7 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         HIP_OK(hipMalloc(&ctx->d_flags, 256));
         HIP_OK(hipMalloc(&ctx->d_counters, 16 * sizeof(int64_t)));
         HIP_OK(hipHostMalloc(&ctx->h_counters, 16 * sizeof(int64_t), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc(&ctx->h_stage, gss_ctx_s::STAGE_BYTES, hipHostMallocDefault));
         HIP_OK(hipMemset(ctx->d_flags, 0, 256));
         HIP_OK(hipMemset(ctx->d_counters, 0, 16 * sizeof(int64_t)));
         return GSS_OK;
@@ -117,6 +118,7 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         if (ctx->d_flags) (void)hipFree(ctx->d_flags);
         if (ctx->d_counters) (void)hipFree(ctx->d_counters);
         if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+        if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
         delete ctx;
         return s;
     }
@@ -130,7 +132,7 @@ gss_status gss_ctx_set_stream(gss_ctx ctx, void *hip_stream)
     // the context's work must stay in one stream order: drain the old stream first
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
-        HIP_OK(hipStreamSynchronize(ctx->stream));
+        ctx->sync();
         ctx->stream = (hipStream_t)hip_stream;
         return GSS_OK;
     });
@@ -145,6 +147,7 @@ gss_status gss_ctx_destroy(gss_ctx ctx)
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     delete ctx;
     return GSS_OK;
 }

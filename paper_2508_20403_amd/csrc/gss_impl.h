@@ -80,6 +80,12 @@ struct gss_ctx_s {
     uint32_t *d_flags = nullptr;      // device error flags
     int64_t *d_counters = nullptr;    // small device scratch (16 words; word 15: look-back ticket)
     int64_t *h_counters = nullptr;    // pinned host mirror
+    // pinned staging area for small host-to-device copies (asynchronous, unlike copies
+    // from pageable memory): a bump area that restarts at every synchronisation of the
+    // stream, by which time every copy staged before it has run
+    char *h_stage = nullptr;
+    size_t stage_off = 0;
+    static constexpr size_t STAGE_BYTES = (size_t)1 << 20;
     hipEvent_t ev_done = nullptr;
     // status words of single-pass (look-back) scans and sorts, reused by epoch
     uint64_t *lb_status = nullptr;
@@ -95,7 +101,25 @@ struct gss_ctx_s {
     {
         if (p) pool.put(p);
     }
-    void sync() { HIP_OK(hipStreamSynchronize(stream)); }
+    void sync()
+    {
+        HIP_OK(hipStreamSynchronize(stream));
+        stage_off = 0;
+    }
+    // enqueues a copy of bytes host bytes to dst on the stream; src may be reused at once
+    void h2d(void *dst, const void *src, size_t bytes)
+    {
+        if (bytes == 0) return;
+        if (!h_stage || bytes > STAGE_BYTES) {
+            HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+            return;
+        }
+        if (stage_off + bytes > STAGE_BYTES) sync();
+        char *h = h_stage + stage_off;
+        memcpy(h, src, bytes);
+        stage_off += (bytes + 63) & ~(size_t)63;
+        HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream));
+    }
 };
 
 struct gss_tree_s {

@@ -467,7 +467,9 @@ __global__ void k_graph_key(int64_t P, const int32_t *__restrict__ pj, const int
 // digit, whose tiles learn their per-digit output bases by decoupled look-back
 // ------------------------------------------------------------------------------------
 #define RS_BLOCK 256
+#ifndef RS_ITEMS
 #define RS_ITEMS 8
+#endif
 #define RS_TILE (RS_BLOCK * RS_ITEMS)
 
 // global digit counts of all eight byte positions: ghist[pos * 256 + digit] (zeroed)
@@ -1312,7 +1314,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     std::vector<int64_t> ps(G + 1, 0);
     for (int32_t g = 0; g < G; g++) ps[g + 1] = ps[g] + res.Pg[g];
     B.pstart = ctx->alloc<int64_t>(G + 1);
-    HIP_OK(hipMemcpyAsync(B.pstart, ps.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+    ctx->h2d(B.pstart, ps.data(), sizeof(int64_t) * (G + 1));
     if (G > 1) {
         B.rg = ctx->alloc<int32_t>(P + 1);
         GSS_LAUNCH(k_rank_graph, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_g, B.rg);
@@ -1587,17 +1589,20 @@ static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const ui
     }
     const int shifts[6] = {51, 39, 27, 15, 3, 0};
     const int widths[6] = {12, 12, 12, 12, 12, 3};
-    int64_t *dneed = ctx->alloc<int64_t>(G);
-    uint64_t *dpm = ctx->alloc<uint64_t>(G), *dpv = ctx->alloc<uint64_t>(G);
+    // per graph: remaining count, then the fixed high bits (mask, value), in one copy
+    int64_t *dsel = ctx->alloc<int64_t>(3 * G);
+    int64_t *dneed = dsel;
+    uint64_t *dpm = (uint64_t *)(dsel + G), *dpv = (uint64_t *)(dsel + 2 * G);
     int64_t *dout = ctx->alloc<int64_t>(3 * G);
-    std::vector<int64_t> out(3 * G);
+    std::vector<int64_t> out(3 * G), sel(3 * G);
     for (int lv = 0; lv < 6 && any; lv++) {
-        std::vector<int64_t> needl(G, 0);
-        for (int32_t g = 0; g < G; g++) needl[g] = need[g] > 0 ? need[g] - above[g] : 0;
-        HIP_OK(hipMemcpyAsync(dneed, needl.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
+        for (int32_t g = 0; g < G; g++) {
+            sel[g] = need[g] > 0 ? need[g] - above[g] : 0;
+            sel[G + g] = (int64_t)pmask[g];
+            sel[2 * G + g] = (int64_t)pval[g];
+        }
+        ctx->h2d(dsel, sel.data(), sizeof(int64_t) * 3 * G);
         if (lv > 0 || !hist_ready || G > 1) {
-            HIP_OK(hipMemcpyAsync(dpm, pmask.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
-            HIP_OK(hipMemcpyAsync(dpv, pval.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
             HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS * G, st));
             GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key, t->M,
                        off_g, shifts[lv], widths[lv], dpm, dpv, dneed, hist);
@@ -1624,9 +1629,7 @@ static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const ui
             else any = true;
         }
     }
-    ctx->free(dneed);
-    ctx->free(dpm);
-    ctx->free(dpv);
+    ctx->free(dsel);
     ctx->free(dout);
     return thr;
 }
@@ -1738,7 +1741,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         std::vector<uint64_t> thr = select_thresholds(ctx, t, key, hist, hist_ready, want, eligible);
         hist_ready = false;
         uint64_t *dthr = ctx->alloc<uint64_t>(G);
-        HIP_OK(hipMemcpyAsync(dthr, thr.data(), sizeof(uint64_t) * G, hipMemcpyHostToDevice, st));
+        ctx->h2d(dthr, thr.data(), sizeof(uint64_t) * G);
         PrefixBufs B;
         PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, B, &prms[0]);
         ctx->free(dthr);
@@ -1776,7 +1779,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             }
         }
         if (write) {
-            HIP_OK(hipMemcpyAsync(dgo, go.data(), sizeof(GraphOut) * G, hipMemcpyHostToDevice, st));
+            ctx->h2d(dgo, go.data(), sizeof(GraphOut) * G);
             GSS_LAUNCH(k_cand_write, dim3(grid_for(r.P, RB)), dim3(RB), 0, st, r.P, B.state, B.candq, B.rg, dgo,
                        B.rid, B.sj, key);
             HIP_OK(hipGetLastError());
