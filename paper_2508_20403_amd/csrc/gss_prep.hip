@@ -315,14 +315,15 @@ __global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__res
     ucnt[u] = (int32_t)(end - lo);
 }
 
-// parent checks, child counts, tree-edge positions and the exponent range of 1/w;
-// a fixed grid strides over the vertices and each block issues one set of atomics.
-// Memory-safe on any CSR (row bounds clamped), so it runs before the CSR checks are read.
+// parent checks, child counts (cloc[x] = x's place among its parent's children, -1 at a
+// root or a bad parent), tree-edge positions and the exponent range of 1/w; a fixed grid
+// strides over the vertices and each block issues one set of atomics.  Memory-safe on
+// any CSR (row bounds clamped), so it runs before the CSR checks are read.
 __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ parent,
                                                    const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col, const double *__restrict__ w,
                                                    int32_t n, int64_t nnz, int32_t virt_root,
-                                                   int32_t *__restrict__ ccnt,
+                                                   int32_t *__restrict__ ccnt, int32_t *__restrict__ cloc,
                                                    int32_t *__restrict__ tpos, uint32_t *flags, int64_t *counters)
 {
     __shared__ int32_t sred[5][PB / GSS_WAVE];
@@ -333,16 +334,16 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
     for (int64_t xx = (int64_t)blockIdx.x * PB + threadIdx.x; xx < n; xx += (int64_t)gridDim.x * PB) {
         int32_t x = (int32_t)xx;
         int32_t p = parent[x];
-        int32_t tp = -1;
+        int32_t tp = -1, loc = -1;
         if (p == -1) {
             roots++;
             root = min(root, x);
         } else if (p < 0 || p >= n || p == x) {
             f |= F_NOT_TREE;
         } else if (p == virt_root) {
-            atomicAdd(&ccnt[p], 1);  // zero-resistance link of a batch graph's root
+            loc = atomicAdd(&ccnt[p], 1);  // zero-resistance link of a batch graph's root
         } else {
-            atomicAdd(&ccnt[p], 1);
+            loc = atomicAdd(&ccnt[p], 1);
             // row bounds clamped: the CSR checks are read back together with these
             const int64_t lo = clamp_idx(row_ptr[x], 0, nnz);
             int64_t k = find_in_row(col, lo, clamp_idx(row_ptr[x + 1], lo, nnz), p);
@@ -362,6 +363,7 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
             }
         }
         tpos[x] = tp;
+        cloc[x] = loc;
     }
     for (int d = 32; d > 0; d >>= 1) {
         f |= __shfl_xor(f, d, GSS_WAVE);
@@ -399,9 +401,11 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
     }
 }
 
+// children CSR: cslot holds each vertex's place among its siblings on entry (from the
+// tree check) and its position in clist on exit
 __global__ void k_children_fill(const int32_t *__restrict__ parent, int32_t n,
-                                const int32_t *__restrict__ cptr, int32_t *__restrict__ cfill,
-                                int32_t *__restrict__ clist, int32_t *__restrict__ cslot)
+                                const int32_t *__restrict__ cptr, int32_t *__restrict__ clist,
+                                int32_t *__restrict__ cslot)
 {
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
@@ -410,7 +414,7 @@ __global__ void k_children_fill(const int32_t *__restrict__ parent, int32_t n,
         cslot[x] = -1;
         return;
     }
-    int32_t s = cptr[p] + atomicAdd(&cfill[p], 1);
+    const int32_t s = cptr[p] + cslot[x];
     clist[s] = x;
     cslot[x] = s;
 }
@@ -1364,6 +1368,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
 
     // tree checks
     int32_t *ccnt = ctx->alloc<int32_t>(n + 1);
+    int32_t *cslot = ctx->alloc<int32_t>(n);
     t->tpos = ctx->alloc<int32_t>(n);
     HIP_OK(hipMemsetAsync(ccnt, 0, sizeof(int32_t) * (n + 1), st));
     int64_t init_c[4] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40)};
@@ -1371,17 +1376,19 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
     GSS_LAUNCH_B(32 * (int64_t)n, k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st,
                  t->parent, t->row_ptr,
-               t->col, t->w, n, nnz, t->virt_root, ccnt, t->tpos, ctx->d_flags, ctx->d_counters);
+               t->col, t->w, n, nnz, t->virt_root, ccnt, cslot, t->tpos, ctx->d_flags, ctx->d_counters);
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     uint32_t f = read_flags(ctx);  // syncs
     if (validate) {  // CSR checks first (their precedence), then the tree checks
         const uint32_t fg = f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
         if (fg) {
             ctx->free(ccnt);
+            ctx->free(cslot);
             fail(status_from_flags(fg), "invalid graph");
         }
         if (ctx->h_counters[10] != 0 || ctx->h_counters[11] != 0 || nnz % 2) {
             ctx->free(ccnt);
+            ctx->free(cslot);
             fail(GSS_ERR_ASYM, "the graph is not symmetric");
         }
     }
@@ -1390,6 +1397,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
     if (f & F_NOT_TREE || roots != 1) {
         ctx->free(ccnt);
+        ctx->free(cslot);
         fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
     }
     bool tree_edge_missing = (f & F_TREE_EDGE) != 0;
@@ -1403,12 +1411,9 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     // children CSR
     int32_t *cptr = ccnt;  // scanned in place, cptr[n] = n-1
     scan_exclusive_i32(ctx, cptr, n + 1, false);
-    int32_t *cfill = ctx->alloc<int32_t>(n);
     int32_t *clist = ctx->alloc<int32_t>(n);
-    int32_t *cslot = ctx->alloc<int32_t>(n);
-    HIP_OK(hipMemsetAsync(cfill, 0, sizeof(int32_t) * n, st));
     GSS_LAUNCH_B(20 * (int64_t)n, k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr,
-                 cfill, clist, cslot);
+                 clist, cslot);
 
     // tour records (successors, parent, degree, fixed-point term) and the 127-bit range
     // check of the terms
@@ -1430,39 +1435,12 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->epk = ctx->alloc<uint64_t>(t->L);
     GSS_LAUNCH(k_vrec_root, dim3(1), dim3(1), 0, st, t->vrec, n, t->root, t->epk, cptr, clist,
                ctx->d_counters + 12);
-    if (n > 1) {
-        uint32_t earlier = 0;  // flags raised before a retry (the range check of the terms)
-        for (int mult = 1;; mult *= 2) {
-            std::vector<void *> bufs;
-            euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, bufs);
-            f = read_flags(ctx) | earlier;
-            for (void *p : bufs) ctx->free(p);
-            if (!(f & F_OVERFLOW)) break;
-            if (mult >= 8) {
-                if (f & F_NOT_TREE) break;
-                ctx->free(succ);
-                ctx->free(trec);
-                fail(GSS_ERR_HIP, "list ranking: level capacity exceeded");
-            }
-            // an attempt that ran out of room proves nothing about the tree: rank again
-            earlier = f & ~(F_OVERFLOW | F_NOT_TREE);
-            // a level outgrew its capacity (vanishingly rare): rank again with more room
-            HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
-        }
-    } else {
-        f = read_flags(ctx);
-    }
-    ctx->free(succ);
-    ctx->free(trec);
-    ctx->free(cfill);
-    ctx->free(clist);
-    ctx->free(cslot);
-    ctx->free(ccnt);
-    ctx->free(tbs);
-    ctx->free(tbc);
-    if (f & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array has a cycle");
-    if (tree_edge_missing) fail(GSS_ERR_TREE_EDGE, "a tree edge is not an edge of the graph");
-    if (range_bad || (f & F_RANGE)) fail(GSS_ERR_RANGE, "tree resistances exceed the 127-bit fixed point");
+    // the tour is ranked without waiting for the host: its flags (overflow, cycle) are read
+    // together with the off-tree enumeration's below; every kernel in between is
+    // memory-safe on a failed ranking
+    std::vector<void *> rank_bufs;
+    int mult = 1;
+    if (n > 1) euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, rank_bufs);
 
     // RMQ structure
     int32_t L = t->L;
@@ -1479,12 +1457,19 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->bpre = ctx->alloc<uint64_t>(t->nb);
     t->bsuf = ctx->alloc<uint64_t>(t->nb);
     t->sbst = ctx->alloc<uint64_t>((int64_t)t->sblevels * t->nsb);
-    GSS_LAUNCH_B(32 * (int64_t)L + 8 * (int64_t)t->nb, k_rmq_blocks, dim3(grid_for(t->nb, RMQ_WPB)),
-                 dim3(RMQ_WPB * 64), 0, st, t->epk, L, t->pmask, t->ppre,
-               t->psuf, t->bmin, t->nb);
-    GSS_LAUNCH(k_rmq_super, dim3(grid_for(t->nsb, RMQ_WPB)), dim3(RMQ_WPB * 64), 0, st, t->bmin, t->nb, t->bmask,
-               t->bpre, t->bsuf, t->sbst, t->nsb);
-    GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
+    auto build_rmq = [&]() {
+        GSS_LAUNCH_B(32 * (int64_t)L + 8 * (int64_t)t->nb, k_rmq_blocks, dim3(grid_for(t->nb, RMQ_WPB)),
+                     dim3(RMQ_WPB * 64), 0, st, t->epk, L, t->pmask, t->ppre, t->psuf, t->bmin, t->nb);
+        GSS_LAUNCH(k_rmq_super, dim3(grid_for(t->nsb, RMQ_WPB)), dim3(RMQ_WPB * 64), 0, st, t->bmin, t->nb,
+                   t->bmask, t->bpre, t->bsuf, t->sbst, t->nsb);
+        GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
+    };
+    build_rmq();
+    ctx->free(clist);
+    ctx->free(cslot);
+    ctx->free(ccnt);
+    ctx->free(tbs);
+    ctx->free(tbc);
 
     // off-tree edges (links to a batch's virtual root are tree edges without graph edges)
     t->M = t->m - (n - 1) + (t->virt_root >= 0 ? t->G : 0);
@@ -1520,6 +1505,31 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(&ctx->h_counters[9], ctx->d_counters + 9, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     f = read_flags(ctx);  // syncs
+    uint32_t earlier = 0;  // flags raised outside the ranking (kept over a retry)
+    for (;;) {
+        for (void *p : rank_bufs) ctx->free(p);
+        rank_bufs.clear();
+        if (!(f & F_OVERFLOW)) break;
+        if (mult >= 8) {
+            if (f & F_NOT_TREE) break;
+            ctx->free(succ);
+            ctx->free(trec);
+            fail(GSS_ERR_HIP, "list ranking: level capacity exceeded");
+        }
+        // a level outgrew its capacity (vanishingly rare): rank again with more room; an
+        // attempt that ran out of room proves nothing about the tree
+        earlier = f & ~(F_OVERFLOW | F_NOT_TREE);
+        HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+        mult *= 2;
+        euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, rank_bufs);
+        build_rmq();
+        f = read_flags(ctx) | earlier;
+    }
+    ctx->free(succ);
+    ctx->free(trec);
+    if (f & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array has a cycle");
+    if (tree_edge_missing) fail(GSS_ERR_TREE_EDGE, "a tree edge is not an edge of the graph");
+    if (range_bad || (f & F_RANGE)) fail(GSS_ERR_RANGE, "tree resistances exceed the 127-bit fixed point");
     if (ctx->h_counters[13] != t->m) fail(GSS_ERR_ASYM, "upper and lower triangles differ in size");
     if (nnz > 0 && (ctx->h_counters[9] != t->M || (f & F_TREE_EDGE)))
         fail(GSS_ERR_TREE_EDGE, "off-tree edge count does not match m-n+1");
