@@ -76,3 +76,19 @@ def test_recover_rmat14(gpu_ctx):
         gpu = run_gpu(gpu_ctx, g, beta=beta)
         orc = run_oracle(g, beta=beta)
         assert_same_recovery(gpu, orc)
+
+
+@pytest.mark.parametrize("beta", [3, 5, 8])
+def test_recover_large_beta(gpu_ctx, beta):
+    """Every BFS-step constant c has its own work-queue and join-record kernels; c = 8 is
+    the largest accepted (and feGRASS's default).  Small graphs (with forced extra passes),
+    a 40^3 grid whose large subtasks take the join, and R-MAT with hub subtasks."""
+    for name, make in SMALL:
+        g = make(0)
+        for k in (-1, g.m):
+            assert_same_recovery(run_gpu(gpu_ctx, g, beta=beta, k_override=k),
+                                 run_oracle(g, beta=beta, k_override=k))
+    for g in (synth.grid((40, 40, 40), 1.0, 1e4, seed=3, alpha=0.05, beta=beta), synth.config("rmat14")):
+        gpu = run_gpu(gpu_ctx, g, beta=beta)
+        assert gpu["info"]["n_join"] > 0  # the partitioned join ran
+        assert_same_recovery(gpu, run_oracle(g, beta=beta))
