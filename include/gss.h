@@ -113,8 +113,8 @@ gss_status gss_ctx_destroy(gss_ctx ctx);
 
 /* Tree preparation (Alg. 1 Step 1 set-up: the ancestor/LCA structure and the
  * root-to-node distances): validates g and parent (unless flags has
- * GSS_PREP_TRUSTED), enumerates edges, and builds the Euler-tour LCA structure, depths
- * and the exact fixed-point root resistances.  parent: device [n], parent[root] = -1.
+ * GSS_PREP_TRUSTED), enumerates edges, ranks the Euler tour and builds the preorder
+ * range-minimum LCA structure, depths and the exact fixed-point root resistances.  parent: device [n], parent[root] = -1.
  * The tree keeps pointers to g's arrays; the caller keeps them alive and unchanged
  * until gss_tree_free.  Errors: ARG, NOT_SIMPLE, WEIGHT, ASYM, NOT_TREE, TREE_EDGE,
  * RANGE, HIP, OOM. */
