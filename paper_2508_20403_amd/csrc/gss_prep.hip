@@ -316,7 +316,8 @@ __global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__res
 }
 
 // parent checks, child counts (cloc[x] = x's place among its parent's children, -1 at a
-// root or a bad parent), tree-edge positions and the exponent range of 1/w; a fixed grid
+// root or a bad parent), tree-edge positions, the resistance 1/w of each tree edge
+// (tinv, 0 where there is none) and the exponent range of 1/w; a fixed grid
 // strides over the vertices and each block issues one set of atomics.  Memory-safe on
 // any CSR (row bounds clamped), so it runs before the CSR checks are read.
 __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ parent,
@@ -324,7 +325,8 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
                                                    const int32_t *__restrict__ col, const double *__restrict__ w,
                                                    int32_t n, int64_t nnz, int32_t virt_root,
                                                    int32_t *__restrict__ ccnt, int32_t *__restrict__ cloc,
-                                                   int32_t *__restrict__ tpos, uint32_t *flags, int64_t *counters)
+                                                   int32_t *__restrict__ tpos, double *__restrict__ tinv,
+                                                   uint32_t *flags, int64_t *counters)
 {
     __shared__ int32_t sred[5][PB / GSS_WAVE];
     uint32_t f = 0;
@@ -335,6 +337,7 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
         int32_t x = (int32_t)xx;
         int32_t p = parent[x];
         int32_t tp = -1, loc = -1;
+        double ti = 0.0;
         if (p == -1) {
             roots++;
             root = min(root, x);
@@ -352,6 +355,7 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
             } else {
                 tp = (int32_t)k;
                 double t = 1.0 / w[k];
+                ti = t;
                 uint64_t b = (uint64_t)__double_as_longlong(t);
                 int ef = (int)((b >> 52) & 0x7ff);
                 if (ef == 0 || ef == 0x7ff) {
@@ -363,6 +367,7 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
             }
         }
         tpos[x] = tp;
+        tinv[x] = ti;
         cloc[x] = loc;
     }
     for (int d = 32; d > 0; d >>= 1) {
@@ -434,7 +439,7 @@ struct __attribute__((aligned(32))) TRec {
 // the up arc of x continues with the down arc into its next sibling, or the up arc of
 // its parent, or ends the tour when the parent is the root.  The root's arcs are not on
 // the tour (-2).
-__global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpos, const double *__restrict__ w,
+__global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpos, const double *__restrict__ tinv,
                                                  const int32_t *__restrict__ parent,
                                                  const int32_t *__restrict__ cptr,
                                                  const int32_t *__restrict__ clist,
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpo
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     u128 t = mk128(0, 0);
     if (x < n) {
-        if (ok && x != root && tpos[x] >= 0) t = fixed_term(1.0 / w[tpos[x]], emin);
+        if (ok && x != root && tpos[x] >= 0) t = fixed_term(tinv[x], emin);
         const int32_t c0 = cptr[x], c1 = cptr[x + 1];
         TRec e;
         e.par = parent[x];
@@ -1194,15 +1199,23 @@ __global__ __launch_bounds__(PB) void k_offtree(
         }
         return;
     }
-    int64_t off[ENT_ITEMS];
-    int64_t run = tile_cnt[blockIdx.x];
+    // output offset of every (round, wave) piece in tile order, in LDS (wave-uniform, so
+    // no per-thread registers): one wave scans the ENT_ITEMS * NW piece counts
+    static_assert(ENT_ITEMS * NW <= GSS_WAVE, "one wave scans the piece counts");
+    __shared__ int64_t s_off[ENT_ITEMS][NW];
+    if (wid == 0) {
+        const int i = lane / NW, w2 = lane % NW;
+        const bool has = lane < ENT_ITEMS * NW;
+        int64_t x = has ? (int64_t)s_wsum[i][w2] : 0;
+        const int64_t own = x;
 #pragma unroll
-    for (int i = 0; i < ENT_ITEMS; i++) {
-        for (int w2 = 0; w2 < NW; w2++) {
-            if (w2 == wid) off[i] = run;
-            run += s_wsum[i][w2];
+        for (int d = 1; d < GSS_WAVE; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, GSS_WAVE);
+            if (lane >= d) x += y;
         }
+        if (has) s_off[i][w2] = (int64_t)tile_cnt[blockIdx.x] + x - own;
     }
+    __syncthreads();
     // batches: the graphs of the tile's first and last rows bound every entry's graph
     // (usually one graph per tile, so no per-entry search)
     __shared__ int32_t s_glo, s_ghi;
@@ -1226,7 +1239,7 @@ __global__ __launch_bounds__(PB) void k_offtree(
     for (int i = 0; i < ENT_ITEMS; i++) {
         if (!((keepm[i] >> lane) & 1ull)) continue;
         const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        const int64_t o = off[i] + __popcll(keepm[i] & lt);
+        const int64_t o = s_off[i][wid] + __popcll(keepm[i] & lt);
         if (o >= Mcap) {
             atomicOr(flags, F_TREE_EDGE);  // more off-tree entries than m - n + 1
             continue;
@@ -1369,6 +1382,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     // tree checks
     int32_t *ccnt = ctx->alloc<int32_t>(n + 1);
     int32_t *cslot = ctx->alloc<int32_t>(n);
+    double *tinv = ctx->alloc<double>(n);
     t->tpos = ctx->alloc<int32_t>(n);
     HIP_OK(hipMemsetAsync(ccnt, 0, sizeof(int32_t) * (n + 1), st));
     int64_t init_c[4] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40)};
@@ -1376,7 +1390,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
     GSS_LAUNCH_B(32 * (int64_t)n, k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st,
                  t->parent, t->row_ptr,
-               t->col, t->w, n, nnz, t->virt_root, ccnt, cslot, t->tpos, ctx->d_flags, ctx->d_counters);
+               t->col, t->w, n, nnz, t->virt_root, ccnt, cslot, t->tpos, tinv, ctx->d_flags, ctx->d_counters);
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     uint32_t f = read_flags(ctx);  // syncs
     if (validate) {  // CSR checks first (their precedence), then the tree checks
@@ -1384,11 +1398,13 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         if (fg) {
             ctx->free(ccnt);
             ctx->free(cslot);
+            ctx->free(tinv);
             fail(status_from_flags(fg), "invalid graph");
         }
         if (ctx->h_counters[10] != 0 || ctx->h_counters[11] != 0 || nnz % 2) {
             ctx->free(ccnt);
             ctx->free(cslot);
+            ctx->free(tinv);
             fail(GSS_ERR_ASYM, "the graph is not symmetric");
         }
     }
@@ -1398,6 +1414,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     if (f & F_NOT_TREE || roots != 1) {
         ctx->free(ccnt);
         ctx->free(cslot);
+        ctx->free(tinv);
         fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
     }
     bool tree_edge_missing = (f & F_TREE_EDGE) != 0;
@@ -1425,7 +1442,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
     // per vertex: tree-edge position, weight, parent, child range, slot and first child
     // read; record and both successors written
-    GSS_LAUNCH_B(76 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, t->w, t->parent, cptr,
+    GSS_LAUNCH_B(76 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, tinv, t->parent, cptr,
                  clist, cslot, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
     GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
 
@@ -1465,6 +1482,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
     };
     build_rmq();
+    ctx->free(tinv);
     ctx->free(clist);
     ctx->free(cslot);
     ctx->free(ccnt);
