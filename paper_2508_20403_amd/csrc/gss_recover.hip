@@ -1348,30 +1348,35 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     int32_t *hid = ctx->alloc<int32_t>(P + 1);
     scratch.push_back(hid);
     launch_grouping_kernels(ctx, P, glca, hid);
-    int64_t nsub = scan_exclusive_i32(ctx, hid, P, true);
-    res.nsub = nsub;
-    B.sub_ptr = ctx->alloc<int32_t>(nsub + 1);
-    B.sub_lca = ctx->alloc<int32_t>(nsub + 1);
-    launch_group_ptr(ctx, P, glca, hid, B.sub_ptr, B.sub_lca, (int32_t)nsub);
+    // the subtask count stays on the device until the queue split is read back below;
+    // everything sized by it takes the bound P instead
+    int64_t *d_nsub = ctx->d_counters + 14;
+    if (P > 0) scan_exclusive_i32_dev(ctx, hid, P, d_nsub);
+    else HIP_OK(hipMemsetAsync(d_nsub, 0, sizeof(int64_t), st));
+    const int32_t cap = (int32_t)P;  // nsub <= P
+    B.sub_ptr = ctx->alloc<int32_t>(P + 1);
+    B.sub_lca = ctx->alloc<int32_t>(P + 1);
+    launch_group_ptr(ctx, P, glca, hid, B.sub_ptr, B.sub_lca);
 
     // work queue: local subtasks first, heaviest predicted cost first
     const int32_t local_max = std::min<int32_t>(ctx->local_max, GSS_LOCAL_CAP);
     float *feat = nullptr, *pred = nullptr;
     const bool want_feat = (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) || ctx->record;
-    if (want_feat && nsub > 0) {
-        feat = ctx->alloc<float>(nsub * GSS_NFEAT + 1);
+    if (want_feat && P > 0) {
+        feat = ctx->alloc<float>(P * GSS_NFEAT + 1);
         scratch.push_back(feat);
-        launch_subtask_features(ctx, (int32_t)nsub, B.sub_ptr, B.sub_lca, B.grp, B.rdu, B.rdv, B.rb, B.ru, B.rv,
+        launch_subtask_features(ctx, d_nsub, cap, B.sub_ptr, B.sub_lca, B.grp, B.rdu, B.rdv, B.rb, B.ru, B.rv,
                                 t->vrec, P, local_max, feat);
         if (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) {
-            pred = ctx->alloc<float>(nsub + 1);
+            // rows past the subtask count are never read back
+            pred = ctx->alloc<float>(P + 1);
             scratch.push_back(pred);
-            costmodel_predict(ctx, feat, nsub, pred);
+            costmodel_predict(ctx, feat, P, pred);
         }
     }
-    uint64_t *qk = ctx->alloc<uint64_t>(nsub + 1), *qk2 = ctx->alloc<uint64_t>(nsub + 1);
-    int32_t *qv = ctx->alloc<int32_t>(nsub + 1), *qv2 = ctx->alloc<int32_t>(nsub + 1);
-    int32_t *is_local = ctx->alloc<int32_t>(nsub + 1);
+    uint64_t *qk = ctx->alloc<uint64_t>(P + 1), *qk2 = ctx->alloc<uint64_t>(P + 1);
+    int32_t *qv = ctx->alloc<int32_t>(P + 1), *qv2 = ctx->alloc<int32_t>(P + 1);
+    int32_t *is_local = ctx->alloc<int32_t>(P + 1);
     HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(int64_t), st));
     // queue keys: cost in the low cost_bits (sizes are at most P; predicted costs are float
     // bits), the on-join-path flag above them
@@ -1380,11 +1385,13 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     if (pred) cost_bits = 32;
     // counters: queued subtasks in the low half of word 4, the lane-sized ones among them
     // in its high half, join-path edges in word 6
-    launch_subtask_keys(ctx, (int32_t)nsub, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
+    launch_subtask_keys(ctx, d_nsub, cap, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
                         (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
                         (unsigned long long *)(ctx->d_counters + 6));
-    radix_sort_pairs(ctx, qk, qv, qk2, qv2, nsub, bytes_for(((uint64_t)3 << cost_bits) - 1));
-    read_counters(ctx, 7);
+    radix_sort_pairs(ctx, qk, qv, qk2, qv2, P, bytes_for(((uint64_t)3 << cost_bits) - 1));
+    read_counters(ctx, 15);  // words 0..14: the queue split and the subtask count
+    const int64_t nsub = ctx->h_counters[14];
+    res.nsub = nsub;
     const int32_t nlocal = (int32_t)(ctx->h_counters[4] & 0xffffffffll);
     const int32_t nsmall = (int32_t)((uint64_t)ctx->h_counters[4] >> 32);
     const int64_t nglobal_edges = ctx->h_counters[6];

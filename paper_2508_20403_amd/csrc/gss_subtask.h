@@ -29,16 +29,18 @@ struct SubtaskArgs {
 void launch_local_recover(gss_ctx ctx, int C, const SubtaskArgs &a, int blocks);
 void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32_t *head);
 void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, int32_t *sub_ptr,
-                      int32_t *sub_lca, int32_t nsub);
-void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
-                         int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
-                         int32_t *nsmall, unsigned long long *nglobal_edges);
+                      int32_t *sub_lca);
+// nsubp: the subtask count in device memory; cap >= it: queue slots (keys past the count
+// sort last)
+void launch_subtask_keys(gss_ctx ctx, const int64_t *nsubp, int32_t cap, const int32_t *sub_ptr, int32_t local_max,
+                         const float *pred, int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local,
+                         int32_t *nlocal, int32_t *nsmall, unsigned long long *nglobal_edges);
 void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
                       const int32_t *grp, int32_t *glist);
-void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
-                             const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
-                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, int32_t local_max,
-                             float *feat);
+void launch_subtask_features(gss_ctx ctx, const int64_t *nsubp, int32_t cap, const int32_t *sub_ptr,
+                             const int32_t *sub_lca, const int32_t *grp, const int32_t *rdu, const int32_t *rdv,
+                             const uint8_t *rb, const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P,
+                             int32_t local_max, float *feat);
 
 // learned cost model (gss_mlp.hip): predicted cost per subtask from its features
 void costmodel_predict(gss_ctx ctx, const float *feat, int64_t nsub, float *pred);

@@ -242,8 +242,11 @@ __global__ void k_group_ptr(int64_t P, const uint64_t *__restrict__ glca, const 
     if (i == P - 1) sub_ptr[hid[i] + (head ? 1 : 0)] = (int32_t)P;
 }
 
-// per subtask: queue key (descending cost first) and the local/global split
-__global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_t *__restrict__ sub_ptr,
+// per subtask: queue key (descending cost first) and the local/global split.  The
+// subtask count nsub is read on the device; the queue has cap >= nsub slots and the ones
+// past nsub get the largest key, so a stable ascending sort leaves them last.
+__global__ __launch_bounds__(256) void k_subtask_keys(const int64_t *__restrict__ nsubp, int32_t cap,
+                                                      const int32_t *__restrict__ sub_ptr,
                                                       int32_t local_max, const float *__restrict__ pred,
                                                       int cost_bits, uint64_t *__restrict__ qkey,
                                                       int32_t *__restrict__ qval,
@@ -254,6 +257,7 @@ __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_
     __shared__ unsigned long long s_ge[256 / GSS_WAVE];
     __shared__ int32_t s_nl[256 / GSS_WAVE], s_ns[256 / GSS_WAVE];
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t nsub = (int32_t)*nsubp;
     int32_t size = 0;
     if (s < nsub) size = sub_ptr[s + 1] - sub_ptr[s];
     const bool loc = s < nsub && size <= local_max;
@@ -269,6 +273,9 @@ __global__ __launch_bounds__(256) void k_subtask_keys(int32_t nsub, const int32_
         const uint64_t cmask = ((uint64_t)1 << cost_bits) - 1;
         const uint64_t cls = loc ? (small ? 1 : 0) : 2;
         qkey[s] = (cls << cost_bits) | ((~cost) & cmask);
+        qval[s] = s;
+    } else if (s < cap) {
+        qkey[s] = ((uint64_t)2 << cost_bits) | (((uint64_t)1 << cost_bits) - 1);
         qval[s] = s;
     }
     // edges on the join path, queued and small subtasks: one atomic per workgroup each
@@ -377,8 +384,9 @@ __device__ __forceinline__ void feat_write(float *__restrict__ f, int32_t size, 
     f[11] = log2f(1.f + S * S);
 }
 
-// one wave per subtask
-__global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const int32_t *__restrict__ sub_ptr,
+// one wave per subtask (grid-stride; the subtask count is read on the device)
+__global__ __launch_bounds__(256) void k_subtask_features(const int64_t *__restrict__ nsubp,
+                                                          const int32_t *__restrict__ sub_ptr,
                                                           const int32_t *__restrict__ sub_lca,
                                                           const int32_t *__restrict__ grp,
                                                           const int32_t *__restrict__ rdu,
@@ -390,18 +398,21 @@ __global__ __launch_bounds__(256) void k_subtask_features(int32_t nsub, const in
                                                           int32_t local_max, float *__restrict__ feat)
 {
     const int lane = lane_id();
-    const int32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
-    if (s >= nsub) return;
-    const int32_t g0 = sub_ptr[s], g1 = sub_ptr[s + 1];
-    if (g1 - g0 > local_max) {
-        if (lane < GSS_NFEAT) feat[(int64_t)s * GSS_NFEAT + lane] = 0.f;
-        return;
+    const int32_t nsub = (int32_t)*nsubp;
+    const int32_t waves = (int32_t)(gridDim.x * blockDim.x / GSS_WAVE);
+    for (int32_t s = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE); s < nsub; s += waves) {
+        const int32_t g0 = sub_ptr[s], g1 = sub_ptr[s + 1];
+        if (g1 - g0 > local_max) {
+            if (lane < GSS_NFEAT) feat[(int64_t)s * GSS_NFEAT + lane] = 0.f;
+            continue;
+        }
+        const VRec rl = vrec[sub_lca[s]];
+        FeatSums a = {0, 0, 0, 0, 0, 0};
+        for (int32_t g = g0 + lane; g < g1; g += GSS_WAVE)
+            feat_edge(grp[g], rl.depth, rdu, rdv, rb, ru, rv, vrec, a);
+        feat_wave_reduce(a);
+        if (lane == 0) feat_write(feat + (int64_t)s * GSS_NFEAT, g1 - g0, a, rl, P);
     }
-    const VRec rl = vrec[sub_lca[s]];
-    FeatSums a = {0, 0, 0, 0, 0, 0};
-    for (int32_t g = g0 + lane; g < g1; g += GSS_WAVE) feat_edge(grp[g], rl.depth, rdu, rdv, rb, ru, rv, vrec, a);
-    feat_wave_reduce(a);
-    if (lane == 0) feat_write(feat + (int64_t)s * GSS_NFEAT, g1 - g0, a, rl, P);
 }
 
 void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32_t *head)
@@ -410,17 +421,17 @@ void launch_grouping_kernels(gss_ctx ctx, int64_t P, const uint64_t *glca, int32
 }
 
 void launch_group_ptr(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, int32_t *sub_ptr,
-                      int32_t *sub_lca, int32_t nsub)
+                      int32_t *sub_lca)
 {
     GSS_LAUNCH(k_group_ptr, dim3(grid_for(P, 256)), dim3(256), 0, ctx->stream, P, glca, hid, sub_ptr, sub_lca);
 }
 
-void launch_subtask_keys(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, int32_t local_max, const float *pred,
-                         int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local, int32_t *nlocal,
-                         int32_t *nsmall, unsigned long long *nglobal_edges)
+void launch_subtask_keys(gss_ctx ctx, const int64_t *nsubp, int32_t cap, const int32_t *sub_ptr, int32_t local_max,
+                         const float *pred, int cost_bits, uint64_t *qkey, int32_t *qval, int32_t *is_local,
+                         int32_t *nlocal, int32_t *nsmall, unsigned long long *nglobal_edges)
 {
-    GSS_LAUNCH(k_subtask_keys, dim3(grid_for(nsub, 256)), dim3(256), 0, ctx->stream, nsub, sub_ptr, local_max, pred,
-               cost_bits, qkey, qval, is_local, nlocal, nsmall, nglobal_edges);
+    GSS_LAUNCH(k_subtask_keys, dim3(grid_for(cap, 256)), dim3(256), 0, ctx->stream, nsubp, cap, sub_ptr, local_max,
+               pred, cost_bits, qkey, qval, is_local, nlocal, nsmall, nglobal_edges);
 }
 
 void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_t *hid, const int32_t *is_local,
@@ -435,11 +446,12 @@ void launch_join_list(gss_ctx ctx, int64_t P, const uint64_t *glca, const int32_
     ctx->free(flag);
 }
 
-void launch_subtask_features(gss_ctx ctx, int32_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca,
-                             const int32_t *grp, const int32_t *rdu, const int32_t *rdv, const uint8_t *rb,
-                             const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P, int32_t local_max,
-                             float *feat)
+void launch_subtask_features(gss_ctx ctx, const int64_t *nsubp, int32_t cap, const int32_t *sub_ptr,
+                             const int32_t *sub_lca, const int32_t *grp, const int32_t *rdu, const int32_t *rdv,
+                             const uint8_t *rb, const int32_t *ru, const int32_t *rv, const VRec *vrec, int64_t P,
+                             int32_t local_max, float *feat)
 {
-    GSS_LAUNCH(k_subtask_features, dim3(grid_for((int64_t)nsub * GSS_WAVE, 256)), dim3(256), 0, ctx->stream, nsub,
-               sub_ptr, sub_lca, grp, rdu, rdv, rb, ru, rv, vrec, P, local_max, feat);
+    const unsigned blocks = std::min<unsigned>(grid_for((int64_t)cap * GSS_WAVE, 256), 4096);
+    GSS_LAUNCH(k_subtask_features, dim3(blocks), dim3(256), 0, ctx->stream, nsubp, sub_ptr, sub_lca, grp, rdu, rdv,
+               rb, ru, rv, vrec, P, local_max, feat);
 }
