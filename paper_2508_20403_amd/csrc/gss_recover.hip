@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256) void k_prefix_before(const uint64_t *__restric
 __global__ __launch_bounds__(256) void k_prefix_write(const uint64_t *__restrict__ key, int64_t M,
                                                       const int32_t *__restrict__ off_g,
                                                       const uint64_t *__restrict__ thr, const int32_t *__restrict__ off,
-                                                      int32_t *__restrict__ pj, uint64_t *__restrict__ pk)
+                                                      int64_t cap, int32_t *__restrict__ pj, uint64_t *__restrict__ pk)
 {
     constexpr int NW = 256 / GSS_WAVE;
     __shared__ int32_t s_w[PX_ITEMS][NW];
@@ -447,9 +447,23 @@ __global__ __launch_bounds__(256) void k_prefix_write(const uint64_t *__restrict
         }
         if ((keepm[i] >> lane) & 1ull) {
             o += __popcll(keepm[i] & lt);
-            pj[o] = (int32_t)(base + (int64_t)i * 256 + threadIdx.x);
-            pk[o] = ~kv[i];  // ascending order of ~key = descending stretch
+            if (o < cap) {  // cap = the length the host sized the prefix for
+                pj[o] = (int32_t)(base + (int64_t)i * 256 + threadIdx.x);
+                pk[o] = ~kv[i];  // ascending order of ~key = descending stretch
+            }
         }
+    }
+}
+
+// slots [*total, cap) of a prefix sized from the selection, should the scan find fewer
+// keys: a valid index and the largest sort key (the host compares the lengths at its
+// next read-back and fails the call on a difference)
+__global__ void k_prefix_pad(const int64_t *__restrict__ total, int64_t cap, int32_t *__restrict__ pj,
+                             uint64_t *__restrict__ pk)
+{
+    for (int64_t i = *total + threadIdx.x; i < cap; i += blockDim.x) {
+        pj[i] = 0;
+        pk[i] = ~0ull;
     }
 }
 
@@ -1271,8 +1285,8 @@ __global__ void k_rank_graph(int64_t P, const int32_t *__restrict__ sj, const in
 
 // Resolves, for every graph g, the prefix {key >= thr[g]} of its criticality order.
 static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uint64_t *key, const uint8_t *bst,
-                                   const int32_t *lca, const uint64_t *thr, PrefixBufs &B,
-                                   const gss_params *prm)
+                                   const int32_t *lca, const uint64_t *thr, const std::vector<int64_t> &plen,
+                                   PrefixBufs &B, const gss_params *prm)
 {
     hipStream_t st = ctx->stream;
     const int64_t M = t->M;
@@ -1285,7 +1299,16 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
     GSS_LAUNCH_B(8 * M, k_prefix_count, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M, off_g,
                  thr, pc);
-    int64_t P = scan_exclusive_i32(ctx, pc, nthr, true);
+    // a single graph's prefix length is known from the selection; the scan's total is
+    // compared with it at the next read-back instead of being waited for here
+    const bool p_known = G == 1;
+    int64_t P;
+    if (p_known) {
+        scan_exclusive_i32_dev(ctx, pc, nthr, ctx->d_counters + 13);
+        P = plen[0];
+    } else {
+        P = scan_exclusive_i32(ctx, pc, nthr, true);
+    }
     res.P = P;
     res.Pg.assign(G, 0);
     if (G > 1) {
@@ -1302,8 +1325,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
     GSS_LAUNCH_B(8 * M + 12 * P, k_prefix_write, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M,
-                 off_g, thr, pc, v1,
-                 k1);
+                 off_g, thr, pc, P, v1, k1);
+    if (p_known) GSS_LAUNCH(k_prefix_pad, dim3(1), dim3(256), 0, st, ctx->d_counters + 13, P, v1, k1);
     ctx->free(pc);
     radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
     if (G > 1) {  // stable by graph: each graph's prefix becomes contiguous, in rank order
@@ -1389,7 +1412,11 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                         (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
                         (unsigned long long *)(ctx->d_counters + 6));
     radix_sort_pairs(ctx, qk, qv, qk2, qv2, P, bytes_for(((uint64_t)3 << cost_bits) - 1));
-    read_counters(ctx, 15);  // words 0..14: the queue split and the subtask count
+    read_counters(ctx, 15);  // words 0..14: the queue split, the subtask count, the prefix length
+    if (p_known && ctx->h_counters[13] != P) {
+        for (void *p : scratch) ctx->free(p);
+        throw gss_error{GSS_ERR_HIP, "prefix length differs from the selection"};
+    }
     const int64_t nsub = ctx->h_counters[14];
     res.nsub = nsub;
     const int32_t nlocal = (int32_t)(ctx->h_counters[4] & 0xffffffffll);
@@ -1575,20 +1602,26 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
 
 // Per graph, a key threshold T such that {key >= T} holds at least want[g] eligible edges
 // (and not many more).  want[g] <= 0: graph not selected (threshold above every key).
+//
+// plen[g] receives the number of keys >= thr[g]: the keys above the chosen bucket plus the
+// bucket's own (every key of the bucket is at least its lowest key, every key below it is
+// smaller), all eligible keys when the threshold is 1, none when the graph is not selected.
 static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist,
                                                bool hist_ready, const std::vector<int64_t> &want,
-                                               const std::vector<int64_t> &eligible)
+                                               const std::vector<int64_t> &eligible, std::vector<int64_t> &plen)
 {
     hipStream_t st = ctx->stream;
     const int32_t G = t->G;
     const int32_t *off_g = (G > 1) ? t->off_g : nullptr;
     std::vector<uint64_t> thr(G, ~0ull), pmask(G, 0), pval(G, 0);
     std::vector<int64_t> above(G, 0), need(G, 0);
+    plen.assign(G, 0);
     bool any = false;
     for (int32_t g = 0; g < G; g++) {
         if (want[g] <= 0) continue;
         if (want[g] >= eligible[g]) {
             thr[g] = 1;  // every eligible key is >= 1
+            plen[g] = eligible[g];
             continue;
         }
         need[g] = want[g];
@@ -1624,6 +1657,7 @@ static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const ui
             int64_t d = out[3 * g], cum = out[3 * g + 1], cnt = out[3 * g + 2];
             if (d < 0) {  // fewer keys than wanted: take everything
                 thr[g] = 1;
+                plen[g] = eligible[g];
                 need[g] = 0;
                 continue;
             }
@@ -1631,7 +1665,10 @@ static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const ui
             pval[g] |= (uint64_t)d << shifts[lv];
             above[g] += cum;
             const int64_t slack = std::max<int64_t>(1024, need[g] / 16);
-            thr[g] = pval[g];  // lowest key of the bucket
+            // lowest key of the bucket, and never 0: a zero key is an edge already
+            // recovered (the histograms skip those too)
+            thr[g] = std::max<uint64_t>(pval[g], 1);
+            plen[g] = above[g] + cnt;
             if (above[g] + cnt - need[g] <= slack || lv == 5) need[g] = 0;
             else any = true;
         }
@@ -1745,12 +1782,13 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     GraphOut *dgo = ctx->alloc<GraphOut>(G);
     std::vector<GraphOut> go(G);
     while (any_active) {
-        std::vector<uint64_t> thr = select_thresholds(ctx, t, key, hist, hist_ready, want, eligible);
+        std::vector<int64_t> plen;
+        std::vector<uint64_t> thr = select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen);
         hist_ready = false;
         uint64_t *dthr = ctx->alloc<uint64_t>(G);
         ctx->h2d(dthr, thr.data(), sizeof(uint64_t) * G);
         PrefixBufs B;
-        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, B, &prms[0]);
+        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, plen, B, &prms[0]);
         ctx->free(dthr);
         if (!flags_checked) {
             ctx->sync();
