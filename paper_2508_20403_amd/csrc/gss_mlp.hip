@@ -60,13 +60,16 @@ __global__ void k_mlp_to_bf16(const float *__restrict__ w, uint16_t *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// inference: a block of 4 wavefronts handles 64 subtasks per iteration
+// inference: a block of 4 wavefronts handles 64 subtasks per iteration; with np given,
+// only the first min(n, *np) rows (a count known on the device only)
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
+                                                   const int64_t *__restrict__ np,
                                                    const float *__restrict__ w, const uint16_t *__restrict__ wb,
                                                    float *__restrict__ out, int log_out)
 {
     __shared__ float sh[4][16][HD + 1];
+    if (np && *np < n) n = *np;
     const int lane = lane_id(), wv = threadIdx.x / GSS_WAVE;
     const int col = lane & 15, quad = lane >> 4;
     const uint16_t *wb1 = wb, *wb2 = wb + HD * 16;
@@ -374,12 +377,12 @@ static void refresh_bf16(gss_ctx ctx)
                (uint16_t *)ctx->mlp_wbf16);
 }
 
-void costmodel_predict(gss_ctx ctx, const float *feat, int64_t nsub, float *pred)
+void costmodel_predict(gss_ctx ctx, const float *feat, int64_t cap, const int64_t *d_nsub, float *pred)
 {
     if (!ctx->model_ready) throw gss_error{GSS_ERR_ARG, "no cost model loaded"};
-    if (nsub <= 0) return;
-    int blocks = (int)std::min<int64_t>((nsub + 63) / 64, 2048);
-    GSS_LAUNCH(k_mlp_infer, dim3(blocks), dim3(256), 0, ctx->stream, feat, nsub, ctx->mlp_w,
+    if (cap <= 0) return;
+    int blocks = (int)std::min<int64_t>((cap + 63) / 64, 2048);
+    GSS_LAUNCH(k_mlp_infer, dim3(blocks), dim3(256), 0, ctx->stream, feat, cap, d_nsub, ctx->mlp_w,
                (const uint16_t *)ctx->mlp_wbf16, pred, 0);
 }
 
@@ -388,7 +391,7 @@ void costmodel_predict_log2(gss_ctx ctx, const float *feat, int64_t n, float *ou
     if (!ctx->model_ready) throw gss_error{GSS_ERR_ARG, "no cost model loaded"};
     if (n <= 0) return;
     int blocks = (int)std::min<int64_t>((n + 63) / 64, 2048);
-    GSS_LAUNCH(k_mlp_infer, dim3(blocks), dim3(256), 0, ctx->stream, feat, n, ctx->mlp_w,
+    GSS_LAUNCH(k_mlp_infer, dim3(blocks), dim3(256), 0, ctx->stream, feat, n, (const int64_t *)nullptr, ctx->mlp_w,
                (const uint16_t *)ctx->mlp_wbf16, out, 1);
 }
 

@@ -1391,10 +1391,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         launch_subtask_features(ctx, d_nsub, cap, B.sub_ptr, B.sub_lca, B.grp, B.rdu, B.rdv, B.rb, B.ru, B.rv,
                                 t->vrec, P, local_max, feat);
         if (prm->sched == GSS_SCHED_LEARNED && ctx->model_ready) {
-            // rows past the subtask count are never read back
             pred = ctx->alloc<float>(P + 1);
             scratch.push_back(pred);
-            costmodel_predict(ctx, feat, P, pred);
+            costmodel_predict(ctx, feat, P, d_nsub, pred);
         }
     }
     uint64_t *qk = ctx->alloc<uint64_t>(P + 1), *qk2 = ctx->alloc<uint64_t>(P + 1);

@@ -43,7 +43,8 @@ void launch_subtask_features(gss_ctx ctx, const int64_t *nsubp, int32_t cap, con
                              int32_t local_max, float *feat);
 
 // learned cost model (gss_mlp.hip): predicted cost per subtask from its features
-void costmodel_predict(gss_ctx ctx, const float *feat, int64_t nsub, float *pred);
+// rows: min(cap, *d_nsub) (the subtask count in device memory)
+void costmodel_predict(gss_ctx ctx, const float *feat, int64_t cap, const int64_t *d_nsub, float *pred);
 // appends this call's per-subtask features, sizes and cycles to the context trace
 void trace_append(gss_ctx ctx, int64_t nsub, const int32_t *sub_ptr, const float *feat, const uint64_t *cycles,
                   const int32_t *queue, int32_t nlocal);
