@@ -92,3 +92,20 @@ def test_recover_large_beta(gpu_ctx, beta):
         gpu = run_gpu(gpu_ctx, g, beta=beta)
         assert gpu["info"]["n_join"] > 0  # the partitioned join ran
         assert_same_recovery(gpu, run_oracle(g, beta=beta))
+
+
+@pytest.mark.parametrize("name,make", SMALL[:3], ids=[s[0] for s in SMALL[:3]])
+def test_trusted_prep_matches_oracle(gpu_ctx, name, make):
+    """GSS_PREP_TRUSTED skips the input checks (the edge count comes from the row scan
+    instead of nnz / 2); the recovery must not change."""
+    g = make(1)
+    dev = torch.device("cuda:0")
+    arrays = [torch.from_numpy(a).to(dev) for a in (g.row_ptr, g.col, g.w, g.parent)]
+    tree = gss.Tree(gpu_ctx, *arrays, trusted=True)
+    assert tree.m == g.m
+    st, mask, order, stretch, info = tree.recover(g.alpha, g.beta, want_stretch=True)
+    torch.cuda.synchronize()
+    gpu = dict(status=st, mask=mask.cpu().numpy(), order=order.cpu().numpy(),
+               stretch=stretch.cpu().numpy(), info=info)
+    tree.free()
+    assert_same_recovery(gpu, run_oracle(g))
