@@ -261,8 +261,8 @@ def bench_batch(args):
         batch_step(gss.SCHED_EDGECOUNT)
     # autotune the work queue on this batch (untimed, cached per device and workload)
     b = gss.Batch(ctx, graphs, arrays=arrays)
-    lm, lb, tms = b.autotune(os.path.join(ROOT, "_data", "autotune.txt"))
-    print(f"[bench] autotune: local_max={lm} blocks={lb} ({tms:.3f} ms)", file=sys.stderr, flush=True)
+    lm, lb, ch, tms = b.autotune(os.path.join(ROOT, "_data", "autotune.txt"))
+    print(f"[bench] autotune: local_max={lm} blocks={lb} chunk={ch} ({tms:.3f} ms)", file=sys.stderr, flush=True)
     # the plain kernel records per-subtask cycles; the cost model trains on them (untimed)
     ctx.trace_clear()
     for _ in range(3):

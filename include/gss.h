@@ -75,7 +75,8 @@ typedef struct {
                                   count; -1 in those fields otherwise)                     */
 
 /* gss_params.sched: order in which the subtask work queue is drained (never changes
- * the output). */
+ * the output).  GSS_SCHED_LEARNED without a loaded cost model falls back to the
+ * edge-count order; gss_info.sched reports which one ran. */
 enum { GSS_SCHED_EDGECOUNT = 0, GSS_SCHED_LEARNED = 1 };
 
 typedef struct {
@@ -100,6 +101,9 @@ typedef struct {
                                   resolved by the anchor hash join (all graphs of a batch) */
     int32_t passes;            /* passes that recovered at least one edge                */
     int32_t rounds;            /* dependency rounds used to resolve the prefix           */
+    int32_t sched;             /* schedule that ran: GSS_SCHED_LEARNED only when it was
+                                  asked for and a cost model is loaded; otherwise the
+                                  edge-count order (the fallback)                        */
 } gss_info;
 
 /* Creates a context on `device` bound to `hip_stream` (a hipStream_t, may be NULL for
@@ -153,15 +157,24 @@ gss_status gss_batch_prep(gss_ctx ctx, int32_t nb, const gss_csr *graphs, const 
 gss_status gss_recover_batch(gss_ctx ctx, gss_tree batch, const gss_params *params, uint8_t *const *masks,
                              int32_t *const *orders, gss_info *infos);
 /* Autotuner of the work-queue settings (gss_ctx_set_tuning) for a tree (a single graph or
- * a batch) and its parameters: runs the recovery for each candidate setting, timed with
- * HIP events on the context stream, keeps the fastest in the context and appends it to
- * the text file cache_path (NULL: no cache; an entry for the same device and workload
- * is reused without timing).  masks/orders as for gss_recover_batch (their contents are
- * overwritten).  Outputs (host, may be NULL): the chosen local_max and local_blocks and
- * the best time in ms (-1 when taken from the cache). */
+ * a batch) and its parameters: runs the recovery for each candidate setting (queue limit
+ * local_max, workgroups local_blocks and queue chunk), timed with HIP events on the
+ * context stream, keeps the fastest in the context and appends it to the text file
+ * cache_path (NULL: no cache; an entry for the same device and workload is reused
+ * without timing when its values pass the gss_ctx_set_tuning range checks; other entries
+ * are ignored).  masks/orders as for gss_recover_batch (their contents are overwritten).
+ * On an error the context keeps the settings it had before the call.  Outputs (host, may
+ * be NULL): the chosen local_max, local_blocks and chunk and the best time in ms (-1
+ * when taken from the cache). */
 gss_status gss_autotune(gss_ctx ctx, gss_tree tree, const gss_params *params, uint8_t *const *masks,
                         int32_t *const *orders, const char *cache_path, int32_t *local_max, int32_t *local_blocks,
-                        double *best_ms);
+                        int32_t *chunk, double *best_ms);
+/* Target count K of graph g of a tree under params p (one gss_params, as passed for that
+ * graph): p->k_override when >= 0, else floor(alpha * n_g) with the product rounded to
+ * double first (Sec. II-B: the sparsifier keeps alpha|V| off-tree edges).  This is the
+ * length the order output of gss_recover / gss_recover_batch must have.  Returns -1 on a
+ * bad argument. */
+int64_t gss_target_count(gss_tree tree, int32_t g, const gss_params *p);
 /* Number of graphs of a tree (1 for gss_tree_prep) and the edge count m_g of graph g. */
 int32_t gss_tree_num_graphs(gss_tree tree);
 int64_t gss_tree_graph_edges(gss_tree tree, int32_t g);
@@ -198,25 +211,54 @@ int64_t gss_tree_num_edges(gss_tree tree);
 #define GSS_COSTMODEL_FLOATS 5081
 #define GSS_COSTMODEL_PARAMS 5057
 
+/* Diagnostics of the Euler-tour list ranking in gss_tree_prep.  Each level's buffers
+ * have a capacity of about 1.3 times the expected ruler count; a level that outgrows it
+ * is detected on the device and the ranking is repeated with twice (then four and eight
+ * times) the capacities.  gss_ctx_set_rank_capacity divides the first attempt's
+ * capacities by divisor (1..4; 1 is the default) so that tests can drive that retry;
+ * the prepared tree is the same.  gss_tree_rank_attempts returns the number of
+ * attempts the preparation of a tree took (the largest over a batch's parts), or -1. */
+gss_status gss_ctx_set_rank_capacity(gss_ctx ctx, int32_t divisor);
+/* Diagnostics of the short sorts of the recovery (a prefix of the criticality order, its
+ * LCA grouping and the work queue; up to 524288 pairs).  They run as a sample sort: a
+ * sorted sample gives bucket splitters, the pairs are counted and scattered into their
+ * buckets, and one workgroup sorts each bucket, in LDS when it holds at most bucket_cap
+ * pairs (0: the kernel's limit, 8192), otherwise in global memory.  radix = 1 sorts them
+ * with the stable LSD radix sort of longer sorts instead.  Neither changes the output;
+ * tests use them to drive every path.  Errors: ARG (radix not 0/1, bucket_cap 1 or
+ * outside 0..8192). */
+gss_status gss_ctx_set_sort(gss_ctx ctx, int32_t radix, int32_t bucket_cap);
+int32_t gss_tree_rank_attempts(gss_tree tree);
+
 /* Sets the batch split size (CSR entries, >= 0; 0 prepares every graph of a batch on its
  * own).  Errors: ARG. */
 gss_status gss_ctx_set_batch_split(gss_ctx ctx, int64_t own_nnz);
 /* Sets the work-queue limits: subtasks of at most local_max edges (0..1024; 0 sends every
  * subtask to the hash join) use the persistent kernel, which runs local_blocks (1..65536)
- * workgroups of four wavefronts.  Returns GSS_ERR_ARG outside those ranges. */
-gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks);
+ * workgroups of four wavefronts; a wavefront takes chunk (1..64) queue entries per pop of
+ * the queue head, or, with chunk = 0, about a sixteenth of its share of the queue (at
+ * most 64).  Returns GSS_ERR_ARG outside those ranges. */
+gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks, int32_t chunk);
 /* Copies up to cap rows of the context trace (host arrays feat[cap][12], cycles[cap],
- * size[cap]; any may be NULL) and returns the number of rows held, or -1. */
-int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int64_t cap);
+ * size[cap], lca[cap] (the subtask's LCA vertex; in a batch, the vertex of the union),
+ * prefix_len[cap] (the length of the criticality-order prefix the subtask was resolved
+ * in); any may be NULL) and returns the number of rows held, or -1. */
+int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int32_t *lca, int64_t *prefix_len,
+                       int64_t cap);
 gss_status gss_trace_clear(gss_ctx ctx);
 /* Trains the cost model on the GPU (FP32 forward/backward and Adam kernels, data
  * parallel: each mini-batch is cut into 64-sample slices, one workgroup per slice, and
  * the slice gradients are summed in a fixed order, so training is deterministic) from
  * host arrays feat[n][12] and cycles[n]; the target is log2(cycles).  Mini-batches hold
  * 64 * clamp(n / 16384, 1, 64) samples; rows are visited in a seeded permutation per
- * epoch.  loss: host [epochs] mean squared error per epoch, or NULL. */
+ * epoch.  Adam: beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, moments from zero.
+ * flags: 0 starts from seeded random weights and the training set's feature mean and
+ * standard deviation; GSS_TRAIN_WARM continues from the loaded weights and keeps their
+ * normalisation (ARG if none is loaded).  loss: host [epochs] mean squared error per
+ * epoch, or NULL. */
+#define GSS_TRAIN_WARM 1u
 gss_status gss_costmodel_train(gss_ctx ctx, const float *feat, const double *cycles, int64_t n, int32_t epochs,
-                               float lr, uint64_t seed, float *loss);
+                               float lr, uint64_t seed, uint32_t flags, float *loss);
 /* Loads / saves the weights (host arrays of GSS_COSTMODEL_FLOATS floats). */
 gss_status gss_costmodel_load(gss_ctx ctx, const float *weights);
 gss_status gss_costmodel_save(gss_ctx ctx, float *weights);

@@ -1,5 +1,6 @@
 // gss_api.hip -- the exported C ABI (declared in include/gss.h).
 #include <algorithm>
+#include <cmath>
 #include <iterator>
 
 #include "gss_impl.h"
@@ -7,6 +8,16 @@
 
 namespace {
 thread_local std::string g_err;
+
+// after a failed call: wait for auxiliary-stream work and release its deferred blocks
+void aux_settle(gss_ctx ctx)
+{
+    if (!ctx) return;
+    ctx->lb_lane = 0;
+    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
+    for (void *p : ctx->aux_frees) ctx->pool.put(p);
+    ctx->aux_frees.clear();
+}
 
 template <typename F>
 gss_status guarded(gss_ctx ctx, F &&f)
@@ -16,19 +27,36 @@ gss_status guarded(gss_ctx ctx, F &&f)
         if (ctx && ctx->prof) ctx->prof_collect();
         return s;
     } catch (const gss_error &e) {
+        aux_settle(ctx);
         if (ctx) ctx->last_error = e.msg;
         g_err = e.msg;
         if (ctx && e.status == GSS_ERR_HIP) (void)hipGetLastError();
         return e.status;
     } catch (const std::bad_alloc &) {
+        aux_settle(ctx);
         if (ctx) ctx->last_error = "host allocation failed";
         return GSS_ERR_OOM;
     } catch (...) {
+        aux_settle(ctx);
         if (ctx) ctx->last_error = "unexpected exception";
         return GSS_ERR_HIP;
     }
 }
 }  // namespace
+
+int64_t target_count(gss_tree t, int32_t g, const gss_params *p)
+{
+    if (p->k_override >= 0) return p->k_override;
+    int64_t ng;
+    if (!t->parts.empty()) {
+        gss_tree q = t->parts[t->part_of[g]];
+        const int32_t i = t->part_idx[g];
+        ng = q->vbase.empty() ? q->n : q->vbase[i + 1] - q->vbase[i];
+    } else {
+        ng = t->vbase.empty() ? t->n : t->vbase[g + 1] - t->vbase[g];
+    }
+    return (int64_t)std::floor(p->alpha * (double)ng);
+}
 
 // frees a tree, its parts and the arrays it owns
 static void delete_tree(gss_tree t)
@@ -106,11 +134,14 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         ctx->device = device;
         ctx->stream = (hipStream_t)hip_stream;
         HIP_OK(hipMalloc(&ctx->d_flags, 256));
-        HIP_OK(hipMalloc(&ctx->d_counters, 16 * sizeof(int64_t)));
-        HIP_OK(hipHostMalloc(&ctx->h_counters, 16 * sizeof(int64_t), hipHostMallocDefault));
+        HIP_OK(hipMalloc(&ctx->d_counters, 32 * sizeof(int64_t)));
+        HIP_OK(hipHostMalloc(&ctx->h_counters, 32 * sizeof(int64_t), hipHostMallocDefault));
+        HIP_OK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         HIP_OK(hipHostMalloc(&ctx->h_stage, gss_ctx_s::STAGE_BYTES, hipHostMallocDefault));
         HIP_OK(hipMemset(ctx->d_flags, 0, 256));
-        HIP_OK(hipMemset(ctx->d_counters, 0, 16 * sizeof(int64_t)));
+        HIP_OK(hipMemset(ctx->d_counters, 0, 32 * sizeof(int64_t)));
         return GSS_OK;
     });
     if (s != GSS_OK) {
@@ -119,6 +150,9 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         if (ctx->d_counters) (void)hipFree(ctx->d_counters);
         if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
         if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+        if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+        if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+        if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
         delete ctx;
         return s;
     }
@@ -143,7 +177,11 @@ gss_status gss_ctx_destroy(gss_ctx ctx)
     if (!ctx) return GSS_ERR_ARG;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
     ctx->pool.release_all();
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
@@ -279,10 +317,6 @@ gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, 
             return GSS_ERR_ARG;
         }
     }
-    if (params[0].sched == GSS_SCHED_LEARNED && !ctx->model_ready) {
-        ctx->last_error = "learned schedule requested but no cost model is loaded";
-        return GSS_ERR_ARG;
-    }
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         ctx->record = (params[0].flags & GSS_F_RECORD) != 0;
@@ -294,13 +328,27 @@ gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, 
 
 gss_status gss_autotune(gss_ctx ctx, gss_tree t, const gss_params *params, uint8_t *const *masks,
                         int32_t *const *orders, const char *cache_path, int32_t *local_max, int32_t *local_blocks,
-                        double *best_ms)
+                        int32_t *chunk, double *best_ms)
 {
     if (!ctx || !t || !params || !masks || t->ctx != ctx) return GSS_ERR_ARG;
+    for (int32_t g = 0; g < t->G; g++) {
+        const gss_params &p = params[g];
+        if (!masks[g] || !(p.alpha >= 0.0 && p.alpha <= 1.0) || p.beta < 0 || p.beta > GSS_MAX_BETA ||
+            p.reserved != 0 || (p.sched != GSS_SCHED_EDGECOUNT && p.sched != GSS_SCHED_LEARNED)) {
+            ctx->last_error = "bad recovery parameters";
+            return GSS_ERR_ARG;
+        }
+    }
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
-        return autotune_impl(ctx, t, params, masks, orders, cache_path, local_max, local_blocks, best_ms);
+        return autotune_impl(ctx, t, params, masks, orders, cache_path, local_max, local_blocks, chunk, best_ms);
     });
+}
+
+int64_t gss_target_count(gss_tree t, int32_t g, const gss_params *p)
+{
+    if (!t || !p || g < 0 || g >= t->G || !(p->alpha >= 0.0 && p->alpha <= 1.0)) return -1;
+    return target_count(t, g, p);
 }
 
 gss_status gss_tree_free(gss_tree t)
@@ -320,10 +368,6 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
     if (!(p->alpha >= 0.0 && p->alpha <= 1.0) || p->beta < 0 || p->beta > GSS_MAX_BETA || p->reserved != 0 ||
         (p->sched != GSS_SCHED_EDGECOUNT && p->sched != GSS_SCHED_LEARNED)) {
         ctx->last_error = "bad recovery parameters";
-        return GSS_ERR_ARG;
-    }
-    if (p->sched == GSS_SCHED_LEARNED && !ctx->model_ready) {
-        ctx->last_error = "learned schedule requested but no cost model is loaded";
         return GSS_ERR_ARG;
     }
     return guarded(ctx, [&]() -> gss_status {
@@ -408,13 +452,37 @@ int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen
     return count;
 }
 
-gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks)
+gss_status gss_ctx_set_tuning(gss_ctx ctx, int32_t local_max, int32_t local_blocks, int32_t chunk)
 {
-    if (!ctx || local_max < 0 || local_max > GSS_LOCAL_CAP || local_blocks < 1 || local_blocks > 65536)
-        return GSS_ERR_ARG;
+    if (!ctx || !tuning_valid(local_max, local_blocks, chunk)) return GSS_ERR_ARG;
     ctx->local_max = local_max;
     ctx->local_blocks = local_blocks;
+    ctx->local_chunk = chunk;
     return GSS_OK;
+}
+
+gss_status gss_ctx_set_sort(gss_ctx ctx, int32_t radix, int32_t bucket_cap)
+{
+    if (!ctx || (radix != 0 && radix != 1) || bucket_cap < 0 || bucket_cap == 1 || bucket_cap > 8192)
+        return GSS_ERR_ARG;
+    ctx->sort_radix = radix != 0;
+    ctx->sort_cap = bucket_cap;
+    return GSS_OK;
+}
+
+gss_status gss_ctx_set_rank_capacity(gss_ctx ctx, int32_t divisor)
+{
+    if (!ctx || divisor < 1 || divisor > 4) return GSS_ERR_ARG;
+    ctx->rank_cap_div = divisor;
+    return GSS_OK;
+}
+
+int32_t gss_tree_rank_attempts(gss_tree t)
+{
+    if (!t) return -1;
+    int32_t a = t->rank_attempts;
+    for (gss_tree p : t->parts) a = std::max(a, p->rank_attempts);
+    return a;
 }
 
 gss_status gss_ctx_set_batch_split(gss_ctx ctx, int64_t own_nnz)
@@ -424,7 +492,8 @@ gss_status gss_ctx_set_batch_split(gss_ctx ctx, int64_t own_nnz)
     return GSS_OK;
 }
 
-int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int64_t cap)
+int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, int32_t *lca, int64_t *prefix_len,
+                       int64_t cap)
 {
     if (!ctx || cap < 0) return -1;
     int64_t rows = (int64_t)ctx->trace_cycles.size();
@@ -432,6 +501,8 @@ int64_t gss_trace_read(gss_ctx ctx, float *feat, double *cycles, int32_t *size, 
     if (feat) memcpy(feat, ctx->trace_feat.data(), sizeof(float) * GSS_NFEAT * k);
     if (cycles) memcpy(cycles, ctx->trace_cycles.data(), sizeof(double) * k);
     if (size) memcpy(size, ctx->trace_size.data(), sizeof(int32_t) * k);
+    if (lca) memcpy(lca, ctx->trace_lca.data(), sizeof(int32_t) * k);
+    if (prefix_len) memcpy(prefix_len, ctx->trace_plen.data(), sizeof(int64_t) * k);
     return rows;
 }
 
@@ -441,16 +512,18 @@ gss_status gss_trace_clear(gss_ctx ctx)
     ctx->trace_feat.clear();
     ctx->trace_cycles.clear();
     ctx->trace_size.clear();
+    ctx->trace_lca.clear();
+    ctx->trace_plen.clear();
     return GSS_OK;
 }
 
 gss_status gss_costmodel_train(gss_ctx ctx, const float *feat, const double *cycles, int64_t n, int32_t epochs,
-                               float lr, uint64_t seed, float *loss)
+                               float lr, uint64_t seed, uint32_t flags, float *loss)
 {
-    if (!ctx || !feat || !cycles || n < 2 || epochs < 1 || !(lr > 0.f)) return GSS_ERR_ARG;
+    if (!ctx || !feat || !cycles || n < 2 || epochs < 1 || !(lr > 0.f) || (flags & ~GSS_TRAIN_WARM)) return GSS_ERR_ARG;
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
-        costmodel_train(ctx, feat, cycles, n, epochs, lr, seed, loss);
+        costmodel_train(ctx, feat, cycles, n, epochs, lr, seed, flags, loss);
         return GSS_OK;
     });
 }

@@ -64,12 +64,18 @@ struct gss_ctx_s {
     // subtask engine settings (autotuned) and the learned cost model
     int32_t local_max = 64;       // subtasks up to this size use the persistent kernel
     int32_t local_blocks = 2048;  // workgroups of the persistent kernel (4 wavefronts each)
+    int32_t local_chunk = 0;      // queue entries per pop (0: from the queue length)
     int64_t batch_own_nnz = (int64_t)1 << 25;  // batch graphs this large are prepared on their own
+    int32_t rank_cap_div = 1;     // list ranking: first-attempt level capacities divided by this
+    int32_t sort_cap = 0;         // sample sort: largest bucket sorted in LDS (0: the kernel's limit)
+    bool sort_radix = false;      // short sorts by the radix sort instead of the sample sort
     bool record = false;          // record per-subtask features and cycles
     bool model_ready = false;     // cost-model weights loaded
     std::vector<float> trace_feat;      // [rows * 12]
     std::vector<double> trace_cycles;   // [rows]
     std::vector<int32_t> trace_size;    // [rows]
+    std::vector<int32_t> trace_lca;     // [rows] LCA vertex of the subtask
+    std::vector<int64_t> trace_plen;    // [rows] length of the prefix it was resolved in
     float *mlp_w = nullptr;             // device weights (FP32 master copy)
     void *mlp_wbf16 = nullptr;          // device BF16 copy for inference
 
@@ -78,7 +84,8 @@ struct gss_ctx_s {
     std::string last_error;
     dev_pool pool;
     uint32_t *d_flags = nullptr;      // device error flags
-    int64_t *d_counters = nullptr;    // small device scratch (16 words; word 15: look-back ticket)
+    int64_t *d_counters = nullptr;    // small device scratch (32 words; words 15 and 31: the
+                                      // look-back tickets of the main and the auxiliary stream)
     int64_t *h_counters = nullptr;    // pinned host mirror
     // pinned staging area for small host-to-device copies (asynchronous, unlike copies
     // from pageable memory): a bump area that restarts at every synchronisation of the
@@ -87,10 +94,17 @@ struct gss_ctx_s {
     size_t stage_off = 0;
     static constexpr size_t STAGE_BYTES = (size_t)1 << 20;
     hipEvent_t ev_done = nullptr;
-    // status words of single-pass (look-back) scans and sorts, reused by epoch
-    uint64_t *lb_status = nullptr;
-    int64_t lb_cap = 0;
-    uint32_t lb_epoch = 0;
+    // status words of single-pass (look-back) scans and sorts, reused by epoch; one set
+    // per stream (lane 0: the context stream, lane 1: the auxiliary stream)
+    uint64_t *lb_status[2] = {nullptr, nullptr};
+    int64_t lb_cap[2] = {0, 0};
+    uint32_t lb_epoch[2] = {0, 0};
+    int lb_lane = 0;
+    // auxiliary stream (default priority, non-blocking) for independent work inside a
+    // call: forked from and joined back into the context stream with events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<void *> aux_frees;   // blocks released by auxiliary work, freed at the join
 
     template <typename T>
     T *alloc(size_t count)
@@ -99,11 +113,14 @@ struct gss_ctx_s {
     }
     void free(void *p)
     {
-        if (p) pool.put(p);
+        if (!p) return;
+        if (lb_lane == 1) aux_frees.push_back(p);  // still in use by the auxiliary stream
+        else pool.put(p);
     }
     void sync()
     {
         HIP_OK(hipStreamSynchronize(stream));
+        if (aux && stream != aux) HIP_OK(hipStreamSynchronize(aux));
         stage_off = 0;
     }
     // enqueues a copy of bytes host bytes to dst on the stream; src may be reused at once
@@ -131,6 +148,7 @@ struct gss_tree_s {
     int32_t root = 0;
     int32_t emin = 0;    // smallest binary exponent of any tree resistance 1/w
     int32_t scale = 0;   // root resistances are integers in units of 2^scale
+    int32_t rank_attempts = 0;  // list-ranking attempts (more than one after a capacity retry)
     // edges
     int32_t *uptr = nullptr;     // [n+1] id of the first upper entry of each row
     int32_t *ufirst = nullptr;   // [n] CSR index of the first upper entry of each row
@@ -185,7 +203,15 @@ gss_status recover_batch_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, u
 void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca, int32_t *bstar);
 gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *const *masks,
                          int32_t *const *orders, const char *cache_path, int32_t *out_lm, int32_t *out_lb,
-                         double *out_ms);
+                         int32_t *out_ch, double *out_ms);
+bool tuning_valid(int32_t local_max, int32_t local_blocks, int32_t chunk);
+// K of graph g: the override when >= 0, else floor(fl(alpha * n_g))
+int64_t target_count(gss_tree t, int32_t g, const gss_params *p);
+
+// ---- sorting (gss_sort.hip) -----------------------------------------------------------
+// sorts n <= sample_sort_max() pairs by (key, value); result in (k, v), (k2, v2) scratch
+void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n);
+int64_t sample_sort_max();
 
 // ---- shared launch helpers (gss_prims.hip) -------------------------------------------
 // exclusive scan of int32 counts in place over [0,n); returns the total (host sync)
@@ -195,7 +221,35 @@ void scan_exclusive_i32_dev(gss_ctx ctx, int32_t *data, int64_t n, int64_t *d_to
 // status array of at least `words` words for one look-back launch, its epoch, and the
 // ticket counter (always zero between launches)
 uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch);
-inline unsigned long long *lb_ticket_ptr(gss_ctx ctx) { return (unsigned long long *)(ctx->d_counters + 15); }
+inline unsigned long long *lb_ticket_ptr(gss_ctx ctx)
+{
+    return (unsigned long long *)(ctx->d_counters + (ctx->lb_lane ? 31 : 15));
+}
+
+// Work enqueued while an AuxScope is alive goes to the auxiliary stream, which first
+// waits for everything enqueued on the context stream so far.  The host code in the
+// scope must not synchronise; blocks it frees stay reserved until aux_join.  Every
+// block the scope allocates must be allocated inside it (before the context stream's
+// later work is enqueued), so the two streams never share a pool block.
+struct AuxScope {
+    gss_ctx ctx;
+    hipStream_t saved;
+    explicit AuxScope(gss_ctx c) : ctx(c), saved(c->stream)
+    {
+        HIP_OK(hipEventRecord(ctx->ev_fork, ctx->stream));
+        HIP_OK(hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
+        ctx->stream = ctx->aux;
+        ctx->lb_lane = 1;
+    }
+    ~AuxScope()
+    {
+        ctx->stream = saved;
+        ctx->lb_lane = 0;
+    }
+};
+// the context stream waits for the auxiliary stream's work; its deferred frees return
+// to the pool (later users are ordered after the join)
+void aux_join(gss_ctx ctx);
 uint32_t read_flags(gss_ctx ctx);
 gss_status status_from_flags(uint32_t f);
 

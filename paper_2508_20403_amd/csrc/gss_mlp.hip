@@ -312,10 +312,11 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ w, c
 
 // feature statistics (mean, std) and log2 targets of a training set
 __global__ __launch_bounds__(256) void k_mlp_prepare(const float *__restrict__ feat, const double *__restrict__ cyc,
-                                                     int64_t n, float *__restrict__ w, float *__restrict__ tgt)
+                                                     int64_t n, float *__restrict__ w, float *__restrict__ tgt,
+                                                     int stats)
 {
     __shared__ double s1[256], s2[256];
-    for (int k = 0; k < NF; k++) {
+    for (int k = 0; k < NF && stats; k++) {
         double a = 0, b = 0;
         for (int64_t r = threadIdx.x; r < n; r += 256) {
             double x = feat[r * NF + k];
@@ -432,9 +433,11 @@ static void epoch_order(uint64_t seed, int32_t ep, int64_t n, int64_t &offset, i
 }
 
 void costmodel_train(gss_ctx ctx, const float *host_feat, const double *host_cycles, int64_t n, int32_t epochs,
-                     float lr, uint64_t seed, float *host_loss)
+                     float lr, uint64_t seed, uint32_t flags, float *host_loss)
 {
     if (n < 2 || epochs < 1) throw gss_error{GSS_ERR_ARG, "training needs at least 2 samples and 1 epoch"};
+    const bool warm = (flags & GSS_TRAIN_WARM) != 0;
+    if (warm && !ctx->model_ready) throw gss_error{GSS_ERR_ARG, "a warm start needs a loaded cost model"};
     hipStream_t st = ctx->stream;
     ensure_model(ctx);
     // slices per mini-batch: one for small sets, growing so that an epoch keeps at least
@@ -453,8 +456,8 @@ void costmodel_train(gss_ctx ctx, const float *host_feat, const double *host_cyc
     HIP_OK(hipMemcpyAsync(cyc, host_cycles, sizeof(double) * n, hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(mom, 0, sizeof(float) * 2 * NPARAM, st));
     HIP_OK(hipMemsetAsync(loss, 0, sizeof(float) * epochs, st));
-    GSS_LAUNCH(k_mlp_init, dim3(grid_for(NPARAM, 256)), dim3(256), 0, st, ctx->mlp_w, seed);
-    GSS_LAUNCH(k_mlp_prepare, dim3(1), dim3(256), 0, st, feat, cyc, n, ctx->mlp_w, tgt);
+    if (!warm) GSS_LAUNCH(k_mlp_init, dim3(grid_for(NPARAM, 256)), dim3(256), 0, st, ctx->mlp_w, seed);
+    GSS_LAUNCH(k_mlp_prepare, dim3(1), dim3(256), 0, st, feat, cyc, n, ctx->mlp_w, tgt, warm ? 0 : 1);
     int64_t t = 0;
     for (int32_t ep = 0; ep < epochs; ep++) {
         int64_t offset, stride;
@@ -506,13 +509,14 @@ void costmodel_grad(gss_ctx ctx, const float *host_x, const float *host_y, int32
 // ------------------------------------------------------------------------------------
 // trace of per-subtask features and cycles (training data)
 // ------------------------------------------------------------------------------------
-void trace_append(gss_ctx ctx, int64_t nsub, const int32_t *sub_ptr, const float *feat, const uint64_t *cycles,
-                  const int32_t *queue, int32_t nlocal)
+void trace_append(gss_ctx ctx, int64_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca, int64_t P,
+                  const float *feat, const uint64_t *cycles, const int32_t *queue, int32_t nlocal)
 {
     if (!feat || !cycles || nlocal <= 0) return;
     std::vector<float> f((size_t)nsub * NF);
     std::vector<uint64_t> cy((size_t)nsub);
-    std::vector<int32_t> ptr((size_t)nsub + 1), q((size_t)nlocal);
+    std::vector<int32_t> ptr((size_t)nsub + 1), q((size_t)nlocal), lc((size_t)nsub);
+    HIP_OK(hipMemcpyAsync(lc.data(), sub_lca, sizeof(int32_t) * lc.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipMemcpyAsync(f.data(), feat, sizeof(float) * f.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipMemcpyAsync(cy.data(), cycles, sizeof(uint64_t) * cy.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipMemcpyAsync(ptr.data(), sub_ptr, sizeof(int32_t) * ptr.size(), hipMemcpyDeviceToHost, ctx->stream));
@@ -523,6 +527,8 @@ void trace_append(gss_ctx ctx, int64_t nsub, const int32_t *sub_ptr, const float
         ctx->trace_feat.insert(ctx->trace_feat.end(), f.begin() + (size_t)s * NF, f.begin() + (size_t)(s + 1) * NF);
         ctx->trace_cycles.push_back((double)cy[s]);
         ctx->trace_size.push_back(ptr[s + 1] - ptr[s]);
+        ctx->trace_lca.push_back(lc[s]);
+        ctx->trace_plen.push_back(P);
     }
 }
 

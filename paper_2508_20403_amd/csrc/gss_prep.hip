@@ -167,30 +167,21 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
 }
 
 
-// Symmetry is checked as a multiset identity: the upper entries (u,v,w) and the
-// transposed lower entries must be the same multiset.  Each entry contributes two
-// independent 64-bit hashes of (min, max, bits(w)), added with sign +1 (upper) or -1
-// (lower); a symmetric graph sums to zero, an asymmetric one to zero with probability
-// 2^-128.  Together with the equal triangle sizes this replaces a mirror search per entry.
-__device__ __forceinline__ void entry_hash(int32_t a, int32_t b, double w, uint64_t &h1, uint64_t &h2)
-{
-    uint64_t key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
-    uint64_t wb = (uint64_t)__double_as_longlong(w);
-    h1 = mix64(key ^ mix64(wb + 0x9E3779B97F4A7C15ull));
-    h2 = mix64((key * 0xD1B54A32D192ED03ull) ^ mix64(wb ^ 0xA0761D6478BD642Full) ^ 0x8CB92BA72F3D8DD7ull);
-}
-
-// column range, strictly increasing rows, no self-loops, positive finite weights, and
-// the symmetric-multiset hash sums
+// Symmetry is checked exactly: every lower entry (u, c), c < u, must find its mirror
+// (c, u) in row c with the same weight, and the triangles must hold equally many entries.
+// Mirroring is injective, so with equal counts it is a bijection between the triangles:
+// every upper entry then has its mirror too.
+// column range, strictly increasing rows, no self-loops, positive finite weights, the
+// mirror of every lower entry, and per block the number of upper minus lower entries
 __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
                                                       const int32_t *__restrict__ tile_row, uint32_t *flags,
-                                                      uint64_t *__restrict__ hpart)
+                                                      int64_t *__restrict__ bpart)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t scol[ETILE];
-    __shared__ uint64_t sh[2][PB / GSS_WAVE];
+    __shared__ int64_t sh[PB / GSS_WAVE];
     __shared__ int32_t s_prev[2];  // row and column of entry base-1 (-1 if none)
     const int64_t base = (int64_t)blockIdx.x * ETILE;
     // every global load of the tile is issued before any is used
@@ -218,11 +209,11 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     for (int i = 0; i < ENT_ITEMS; i++) scol[i * PB + threadIdx.x] = cv[i];
     __syncthreads();
     uint32_t f = 0;
-    uint64_t h1 = 0, h2 = 0;
+    int64_t bal = 0;  // upper minus lower entries
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
         const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        if (k >= nnz) break;
+        if (k >= nnz) continue;
         const int32_t u = srow[k - base];
         const int32_t c = cv[i];
         if (c < 0 || c >= n) {
@@ -236,63 +227,75 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
         if (prev_same && pc >= c) f |= F_NOT_SIMPLE;
         const double x = wv[i];
         if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
-        uint64_t a1, a2;
-        entry_hash(min(u, c), max(u, c), x, a1, a2);
-        if (c > u) {
-            h1 += a1;
-            h2 += a2;
-        } else {
-            h1 -= a1;
-            h2 -= a2;
+        bal += (c > u) ? 1 : (c < u ? -1 : 0);
+    }
+    // The mirror (c, u) of every lower entry (u, c) is searched in row c.  The searches of
+    // eight entries run in lockstep so that their loads overlap: lo/hi bisect row c
+    // for the first column >= u.  Row bounds are clamped so malformed input stays in bounds.
+    constexpr int MB = 8;
+#pragma unroll 1
+    for (int h = 0; h < ENT_ITEMS; h += MB) {
+        int32_t lo[MB], hi[MB], end[MB], key[MB];
+#pragma unroll
+        for (int q = 0; q < MB; q++) {
+            const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
+            lo[q] = hi[q] = end[q] = 0;
+            key[q] = -1;
+            if (k >= nnz) continue;
+            const int32_t u = srow[k - base];
+            const int32_t c = scol[k - base];
+            if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
+            lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
+            hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
+            key[q] = u;
         }
+        for (;;) {
+            bool busy = false;
+#pragma unroll
+            for (int q = 0; q < MB; q++) {
+                if (key[q] >= 0 && lo[q] < hi[q]) {
+                    const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
+                    if (col[mid] < key[q]) lo[q] = mid + 1;
+                    else hi[q] = mid;
+                    busy = true;
+                }
+            }
+            if (!__any(busy)) break;
+        }
+#pragma unroll
+        for (int q = 0; q < MB; q++)
+            if (key[q] >= 0 && (lo[q] >= end[q] || col[lo[q]] != key[q] ||
+                                w[lo[q]] != w[base + (int64_t)(h + q) * PB + threadIdx.x]))
+                f |= F_ASYM;
     }
     for (int d = 32; d > 0; d >>= 1) {
         f |= __shfl_xor(f, d, GSS_WAVE);
-        h1 += __shfl_xor(h1, d, GSS_WAVE);
-        h2 += __shfl_xor(h2, d, GSS_WAVE);
+        bal += __shfl_xor(bal, d, GSS_WAVE);
     }
     if (lane_id() == 0) {
-        sh[0][threadIdx.x / GSS_WAVE] = h1;
-        sh[1][threadIdx.x / GSS_WAVE] = h2;
+        sh[threadIdx.x / GSS_WAVE] = bal;
         if (f) atomicOr(flags, f);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < PB / GSS_WAVE; i++) {
-            h1 += sh[0][i];
-            h2 += sh[1][i];
-        }
-        hpart[2 * (int64_t)blockIdx.x] = h1;  // per-block partial sums (no contended atomics)
-        hpart[2 * (int64_t)blockIdx.x + 1] = h2;
+        for (int i = 1; i < PB / GSS_WAVE; i++) bal += sh[i];
+        bpart[blockIdx.x] = bal;  // per-block partial sums (no contended atomics)
     }
 }
 
-// sums the per-block hash partials of k_check_entries into hsum[0..1]
-__global__ __launch_bounds__(1024) void k_hash_total(const uint64_t *__restrict__ hpart, int64_t nblk,
-                                                     unsigned long long *hsum)
+// sums the per-block balances (upper minus lower entries) of k_check_entries into *total
+__global__ __launch_bounds__(1024) void k_balance_total(const int64_t *__restrict__ bpart, int64_t nblk,
+                                                        int64_t *total)
 {
-    __shared__ uint64_t s1[1024 / GSS_WAVE], s2[1024 / GSS_WAVE];
-    uint64_t a = 0, b = 0;
-    for (int64_t i = threadIdx.x; i < nblk; i += 1024) {
-        a += hpart[2 * i];
-        b += hpart[2 * i + 1];
-    }
-    for (int d = 32; d > 0; d >>= 1) {
-        a += __shfl_xor(a, d, GSS_WAVE);
-        b += __shfl_xor(b, d, GSS_WAVE);
-    }
-    if (lane_id() == 0) {
-        s1[threadIdx.x / GSS_WAVE] = a;
-        s2[threadIdx.x / GSS_WAVE] = b;
-    }
+    __shared__ int64_t s1[1024 / GSS_WAVE];
+    int64_t a = 0;
+    for (int64_t i = threadIdx.x; i < nblk; i += 1024) a += bpart[i];
+    for (int d = 32; d > 0; d >>= 1) a += __shfl_xor(a, d, GSS_WAVE);
+    if (lane_id() == 0) s1[threadIdx.x / GSS_WAVE] = a;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < 1024 / GSS_WAVE; i++) {
-            a += s1[i];
-            b += s2[i];
-        }
-        hsum[0] = a;
-        hsum[1] = b;
+        for (int i = 1; i < 1024 / GSS_WAVE; i++) a += s1[i];
+        *total = a;
     }
 }
 
@@ -922,10 +925,12 @@ __global__ void k_level_init(int64_t N0, const int64_t *__restrict__ head0, int 
     }
 }
 
-static inline int64_t next_cap(int64_t cap, int mult, int level)
+// mult: the attempt's capacity multiplier (1, 2, 4 or 8); div: a divisor of the first
+// attempt's capacities (1 normally; larger values drive the capacity retry in tests)
+static inline int64_t next_cap(int64_t cap, int mult, int div, int level)
 {
     const int64_t rate = level == 0 ? RULE_RATE0 : RULE_RATE;
-    return cap * mult * 21 / (rate * 16) + 256;  // 1.3125x the expected ruler count
+    return cap * mult * 21 / (rate * 16 * div) + 256;  // 1.3125x the expected ruler count
 }
 
 // Ranks the Euler tour (succ over N = 2n arcs, tour records trec, head arc in *d_head)
@@ -962,7 +967,7 @@ static void euler_rank(gss_ctx ctx, gss_tree t, const int32_t *succ, const TRec 
         if (l + 1 >= max_levels) throw gss_error{GSS_ERR_HIP, "list ranking: too many levels"};
         Lv &a = lv.back();
         const int64_t cap = a.cap;
-        const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult, l), cap);
+        const int64_t cap2 = std::min<int64_t>(next_cap(cap, mult, ctx->rank_cap_div, l), cap);
         int32_t *rid = ctx->alloc<int32_t>(cap + 1);
         a.relem = ctx->alloc<int32_t>(cap2 + 1);
         int32_t *rnxt = ctx->alloc<int32_t>(cap2 + 1);
@@ -1345,21 +1350,17 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         ~TileRowsFree() { c->free(p); }
     } tile_row_guard{ctx, tile_row};
 
-    // validation (memory-safe on malformed input) and edge numbering
-    if (validate) {
-        HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, 2 * sizeof(int64_t), st));
-        if (nnz > 0) {
-            uint64_t *hpart = ctx->alloc<uint64_t>(2 * etiles + 2);
-            GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0, st,
-                         t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, hpart);
-            GSS_LAUNCH(k_hash_total, dim3(1), dim3(1024), 0, st, hpart, etiles,
-                       (unsigned long long *)(ctx->d_counters + 10));
-            ctx->free(hpart);
-        }
-        // the CSR flags and hash sums are read back with the tree checks below (every
-        // kernel until then is memory-safe on malformed input)
-        HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, 2 * sizeof(int64_t),
-                              hipMemcpyDeviceToHost, st));
+    // validation (memory-safe on malformed input) on the auxiliary stream, beside the
+    // edge numbering and the tree checks below
+    const bool check_entries = validate && nnz > 0;
+    if (validate) HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, sizeof(int64_t), st));
+    if (check_entries) {
+        AuxScope aux(ctx);
+        int64_t *bpart = ctx->alloc<int64_t>(etiles + 1);
+        GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0,
+                     ctx->stream, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart);
+        GSS_LAUNCH(k_balance_total, dim3(1), dim3(1024), 0, ctx->stream, bpart, etiles, ctx->d_counters + 10);
+        ctx->free(bpart);
     }
     t->ufirst = ctx->alloc<int32_t>(n);
     t->uptr = ctx->alloc<int32_t>(n + 1);
@@ -1391,7 +1392,13 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     GSS_LAUNCH_B(32 * (int64_t)n, k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st,
                  t->parent, t->row_ptr,
                t->col, t->w, n, nnz, t->virt_root, ccnt, cslot, t->tpos, tinv, ctx->d_flags, ctx->d_counters);
+    if (check_entries) aux_join(ctx);
+    // the CSR flags and the triangle balance are read back with the tree checks (every
+    // kernel until then is memory-safe on malformed input)
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (validate)
+        HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
     uint32_t f = read_flags(ctx);  // syncs
     if (validate) {  // CSR checks first (their precedence), then the tree checks
         const uint32_t fg = f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
@@ -1401,7 +1408,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
             ctx->free(tinv);
             fail(status_from_flags(fg), "invalid graph");
         }
-        if (ctx->h_counters[10] != 0 || ctx->h_counters[11] != 0 || nnz % 2) {
+        if ((f & F_ASYM) || ctx->h_counters[10] != 0 || nnz % 2) {
             ctx->free(ccnt);
             ctx->free(cslot);
             ctx->free(tinv);
@@ -1424,6 +1431,41 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
     t->emin = (int32_t)emin;
     t->scale = (int32_t)emin - 52;
+
+    // off-tree edges (links to a batch's virtual root are tree edges without graph edges),
+    // on the auxiliary stream: they need only the tree-edge positions, so they run beside
+    // the Euler-tour ranking below (a chain of short, latency-bound launches)
+    t->M = t->m - (n - 1) + (t->virt_root >= 0 ? t->G : 0);
+    t->off_id = ctx->alloc<int32_t>(t->M + 1);
+    t->off_u = ctx->alloc<int32_t>(t->M + 1);
+    t->off_v = ctx->alloc<int32_t>(t->M + 1);
+    t->off_w = ctx->alloc<double>(t->M + 1);
+    t->tree_eid = ctx->alloc<int32_t>(n);
+    if (nnz > 0 && (t->G > 1 || t->virt_root >= 0)) t->off_g = ctx->alloc<int32_t>(t->M + 1);
+    {
+        AuxScope aux(ctx);
+        hipStream_t sa = ctx->stream;
+        // tree edge ids, and a flag byte per edge id
+        uint8_t *tflag = ctx->alloc<uint8_t>(t->m + 1);
+        HIP_OK(hipMemsetAsync(tflag, 0, t->m + 1, sa));
+        GSS_LAUNCH_B(21 * (int64_t)n, k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, sa, t->parent, t->row_ptr,
+                     t->col, t->uptr, t->ufirst, t->tpos, n, t->m, t->tree_eid, tflag);
+        if (nnz > 0) {
+            int32_t *tcnt = ctx->alloc<int32_t>(etiles + 1);
+            // CSR columns, row starts and tree flags read; one count per tile
+            GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m, k_offtree<false>, dim3((unsigned)etiles), dim3(PB), 0, sa,
+                         t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row, tcnt, t->M,
+                         t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, ctx->d_flags);
+            scan_exclusive_i32_dev(ctx, tcnt, etiles, ctx->d_counters + 9);
+            // the same reads again; per off-tree edge its id, endpoints and weight written
+            GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m + 28 * t->M, k_offtree<true>, dim3((unsigned)etiles),
+                         dim3(PB), 0, sa, t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row,
+                         tcnt, t->M, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g,
+                         ctx->d_flags);
+            ctx->free(tcnt);
+        }
+        ctx->free(tflag);  // held until the join
+    }
 
     // children CSR
     int32_t *cptr = ccnt;  // scanned in place, cptr[n] = n-1
@@ -1457,6 +1499,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     // memory-safe on a failed ranking
     std::vector<void *> rank_bufs;
     int mult = 1;
+    t->rank_attempts = n > 1 ? 1 : 0;
     if (n > 1) euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, rank_bufs);
 
     // RMQ structure
@@ -1489,37 +1532,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     ctx->free(tbs);
     ctx->free(tbc);
 
-    // off-tree edges (links to a batch's virtual root are tree edges without graph edges)
-    t->M = t->m - (n - 1) + (t->virt_root >= 0 ? t->G : 0);
-    t->off_id = ctx->alloc<int32_t>(t->M + 1);
-    t->off_u = ctx->alloc<int32_t>(t->M + 1);
-    t->off_v = ctx->alloc<int32_t>(t->M + 1);
-    t->off_w = ctx->alloc<double>(t->M + 1);
-    // tree edge ids, and a flag byte per edge id
-    t->tree_eid = ctx->alloc<int32_t>(n);
-    uint8_t *tflag = ctx->alloc<uint8_t>(t->m + 1);
-    struct TflagFree {
-        gss_ctx c;
-        uint8_t *p;
-        ~TflagFree() { c->free(p); }
-    } tflag_guard{ctx, tflag};
-    HIP_OK(hipMemsetAsync(tflag, 0, t->m + 1, st));
-    GSS_LAUNCH_B(21 * (int64_t)n, k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, t->row_ptr, t->col,
-                 t->uptr, t->ufirst, t->tpos, n, t->m, t->tree_eid, tflag);
-    if (nnz > 0) {
-        if (t->G > 1 || t->virt_root >= 0) t->off_g = ctx->alloc<int32_t>(t->M + 1);
-        int32_t *tcnt = ctx->alloc<int32_t>(etiles + 1);
-        // CSR columns, row starts and tree flags read; one count per tile
-        GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m, k_offtree<false>, dim3((unsigned)etiles), dim3(PB), 0, st,
-                     t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row, tcnt, t->M,
-                     t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, ctx->d_flags);
-        scan_exclusive_i32_dev(ctx, tcnt, etiles, ctx->d_counters + 9);
-        // the same reads again; per off-tree edge its id, endpoints and weight written
-        GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m + 28 * t->M, k_offtree<true>, dim3((unsigned)etiles), dim3(PB),
-                     0, st, t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row, tcnt, t->M,
-                     t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, ctx->d_flags);
-        ctx->free(tcnt);
-    }
+    aux_join(ctx);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(&ctx->h_counters[9], ctx->d_counters + 9, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     f = read_flags(ctx);  // syncs
@@ -1539,6 +1552,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         earlier = f & ~(F_OVERFLOW | F_NOT_TREE);
         HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
         mult *= 2;
+        t->rank_attempts++;
         euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, rank_bufs);
         build_rmq();
         f = read_flags(ctx) | earlier;

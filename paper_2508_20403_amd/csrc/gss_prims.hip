@@ -213,20 +213,29 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_onepass(int32_t *__restrict
 
 uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch)
 {
-    if (words > ctx->lb_cap) {
-        ctx->free(ctx->lb_status);
+    const int l = ctx->lb_lane;
+    if (words > ctx->lb_cap[l]) {
+        ctx->free(ctx->lb_status[l]);
         const int64_t cap = std::max<int64_t>(words, 1 << 16);
-        ctx->lb_status = ctx->alloc<uint64_t>(cap);
-        HIP_OK(hipMemsetAsync(ctx->lb_status, 0, sizeof(uint64_t) * cap, ctx->stream));
-        ctx->lb_cap = cap;
-        ctx->lb_epoch = 0;
+        ctx->lb_status[l] = ctx->alloc<uint64_t>(cap);
+        HIP_OK(hipMemsetAsync(ctx->lb_status[l], 0, sizeof(uint64_t) * cap, ctx->stream));
+        ctx->lb_cap[l] = cap;
+        ctx->lb_epoch[l] = 0;
     }
-    if (++ctx->lb_epoch >= (1u << LB_EPOCH_BITS)) {
-        HIP_OK(hipMemsetAsync(ctx->lb_status, 0, sizeof(uint64_t) * ctx->lb_cap, ctx->stream));
-        ctx->lb_epoch = 1;
+    if (++ctx->lb_epoch[l] >= (1u << LB_EPOCH_BITS)) {
+        HIP_OK(hipMemsetAsync(ctx->lb_status[l], 0, sizeof(uint64_t) * ctx->lb_cap[l], ctx->stream));
+        ctx->lb_epoch[l] = 1;
     }
-    *epoch = ctx->lb_epoch;
-    return ctx->lb_status;
+    *epoch = ctx->lb_epoch[l];
+    return ctx->lb_status[l];
+}
+
+void aux_join(gss_ctx ctx)
+{
+    HIP_OK(hipEventRecord(ctx->ev_join, ctx->aux));
+    HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+    for (void *p : ctx->aux_frees) ctx->pool.put(p);
+    ctx->aux_frees.clear();
 }
 
 // one workgroup scans the whole array in chunks (short arrays: one launch instead of three)

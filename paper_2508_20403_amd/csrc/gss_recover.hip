@@ -620,7 +620,8 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__rest
 __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const int32_t *__restrict__ off_id,
                               const int32_t *__restrict__ off_u, const int32_t *__restrict__ off_v,
                               const uint8_t *__restrict__ bst, const int32_t *__restrict__ lca,
-                              const VRec *__restrict__ vrec, int32_t c, int32_t *__restrict__ rid,
+                              const VRec *__restrict__ vrec, const int32_t *__restrict__ parent, int32_t c,
+                              int32_t *__restrict__ rid,
                               uint8_t *__restrict__ rb, int32_t *__restrict__ ru, int32_t *__restrict__ rv,
                               int32_t *__restrict__ rdu, int32_t *__restrict__ rdv, int32_t *__restrict__ rl,
                               uint64_t *__restrict__ lkey, int32_t *__restrict__ lval,
@@ -643,12 +644,15 @@ __global__ void k_rank_gather(int64_t P, const int32_t *__restrict__ sj, const i
     rdv[p] = rbv.depth;
     ancU[p] = a;
     ancV[p] = b;
+    // the ancestor chains walk the 4-byte parent array (vrec[x].parent == parent[x]), not
+    // the 32-byte vertex records
     int32_t pa = ra.parent, pb = rbv.parent;
     for (int i = 1; i <= c; i++) {
         ancU[(int64_t)i * P + p] = pa;
         ancV[(int64_t)i * P + p] = pb;
-        pa = (pa >= 0) ? vrec[pa].parent : -1;
-        pb = (pb >= 0) ? vrec[pb].parent : -1;
+        if (i == c) break;
+        pa = (pa >= 0) ? parent[pa] : -1;
+        pb = (pb >= 0) ? parent[pb] : -1;
     }
 }
 
@@ -1247,6 +1251,16 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     ctx->free(ghist);
 }
 
+// Sort of (key, value) pairs with distinct values by (key, value): the sample sort for
+// the short sorts of a prefix (a few launches whatever the key width), the radix sort
+// (stable, so the same order) above its size limit.
+static void sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n,
+                       int key_bytes = 0)
+{
+    if (n <= sample_sort_max() && !ctx->sort_radix) sample_sort_pairs(ctx, k, v, k2, v2, n);
+    else radix_sort_pairs(ctx, k, v, k2, v2, n, key_bytes);
+}
+
 static int bytes_for(uint64_t maxkey)
 {
     int b = 1;
@@ -1328,7 +1342,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                  off_g, thr, pc, P, v1, k1);
     if (p_known) GSS_LAUNCH(k_prefix_pad, dim3(1), dim3(256), 0, st, ctx->d_counters + 13, P, v1, k1);
     ctx->free(pc);
-    radix_sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
+    sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
     if (G > 1) {  // stable by graph: each graph's prefix becomes contiguous, in rank order
         GSS_LAUNCH(k_graph_key, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, v1, t->off_g, k1);
         radix_sort_pairs(ctx, k1, v1, k2, v2, P, bytes_for((uint64_t)(G - 1)));
@@ -1358,11 +1372,11 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     // record, the (LCA, rank) pair and the ancestor columns written
     GSS_LAUNCH_B((58 + 16 * (int64_t)(c + 1)) * P, k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj,
                  t->off_id, t->off_u, t->off_v, bst,
-               lca, t->vrec, c, B.rid, B.rb, B.ru, B.rv, B.rdu, B.rdv, B.rl, lkey, lval, B.ancU, B.ancV);
+               lca, t->vrec, t->parent, c, B.rid, B.rb, B.ru, B.rv, B.rdu, B.rdv, B.rl, lkey, lval, B.ancU, B.ancV);
 
     // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA.  LCAs
     // of different graphs of a batch are different vertices, so subtasks never mix graphs.
-    radix_sort_pairs(ctx, lkey, lval, lkey2, lval2, P, bytes_for((uint64_t)(t->n - 1)));  // LCA < n
+    sort_pairs(ctx, lkey, lval, lkey2, lval2, P, bytes_for((uint64_t)(t->n - 1)));  // LCA < n
     B.grp = lval;
     scratch.push_back(lkey2);
     scratch.push_back(lval2);
@@ -1410,7 +1424,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     launch_subtask_keys(ctx, d_nsub, cap, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
                         (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
                         (unsigned long long *)(ctx->d_counters + 6));
-    radix_sort_pairs(ctx, qk, qv, qk2, qv2, P, bytes_for(((uint64_t)3 << cost_bits) - 1));
+    sort_pairs(ctx, qk, qv, qk2, qv2, P, bytes_for(((uint64_t)3 << cost_bits) - 1));
     read_counters(ctx, 15);  // words 0..14: the queue split, the subtask count, the prefix length
     if (p_known && ctx->h_counters[13] != P) {
         for (void *p : scratch) ctx->free(p);
@@ -1467,7 +1481,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         // wavefront several full takes; otherwise whole wavefronts take them too
         a.nbig = (nsmall >= (int64_t)16 * blocks * 4) ? nlocal - nsmall : nlocal;
         // about 16 chunks per wavefront; one subtask per take while the queue is short
-        a.chunk = std::max<int32_t>(1, std::min<int32_t>(64, a.nbig / (blocks * 4 * 16)));
+        a.chunk = ctx->local_chunk > 0 ? ctx->local_chunk
+                                       : std::max<int32_t>(1, std::min<int32_t>(64, a.nbig / (blocks * 4 * 16)));
         void *scr = ctx->alloc<uint8_t>((size_t)blocks * 4 * per_wave + 64);
         scratch.push_back(scr);
         a.cand_scratch = scr;
@@ -1594,7 +1609,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     ctx->sync();
     if (res.rounds_pending) res.rounds = ctx->h_counters[12];
     ctx->free(cg);
-    if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, feat, cycles, qv, nlocal);
+    if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, B.sub_lca, P, feat, cycles, qv, nlocal);
     for (void *p : scratch) ctx->free(p);
     return res;
 }
@@ -1693,8 +1708,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     std::vector<int64_t> lastP(G, 0), nsubg(G, 0), largest(G, 0);
     std::vector<bool> active(G);
     for (int32_t g = 0; g < G; g++) {
-        const int64_t ng = t->vbase[g + 1] - t->vbase[g];
-        K[g] = prms[g].k_override >= 0 ? prms[g].k_override : (int64_t)std::floor(prms[g].alpha * (double)ng);
+        K[g] = target_count(t, g, &prms[g]);
         mg[g] = t->ebase[g + 1] - t->ebase[g];
         eligible[g] = t->Mg[g];
         HIP_OK(hipMemsetAsync(masks[g], 0, (size_t)mg[g], st));
@@ -1882,6 +1896,8 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         info.n_join = njoin;
         info.passes = passes[g];
         info.rounds = (int32_t)rounds;
+        info.sched = (prms[0].sched == GSS_SCHED_LEARNED && ctx->model_ready) ? GSS_SCHED_LEARNED
+                                                                               : GSS_SCHED_EDGECOUNT;
     }
     return short_any ? GSS_SHORT : GSS_OK;
 }

@@ -46,13 +46,13 @@ void launch_subtask_features(gss_ctx ctx, const int64_t *nsubp, int32_t cap, con
 // rows: min(cap, *d_nsub) (the subtask count in device memory)
 void costmodel_predict(gss_ctx ctx, const float *feat, int64_t cap, const int64_t *d_nsub, float *pred);
 // appends this call's per-subtask features, sizes and cycles to the context trace
-void trace_append(gss_ctx ctx, int64_t nsub, const int32_t *sub_ptr, const float *feat, const uint64_t *cycles,
-                  const int32_t *queue, int32_t nlocal);
+void trace_append(gss_ctx ctx, int64_t nsub, const int32_t *sub_ptr, const int32_t *sub_lca, int64_t P,
+                  const float *feat, const uint64_t *cycles, const int32_t *queue, int32_t nlocal);
 void costmodel_predict_log2(gss_ctx ctx, const float *feat, int64_t n, float *out);
 void costmodel_load(gss_ctx ctx, const float *host_w);
 void costmodel_save(gss_ctx ctx, float *host_w);
 void costmodel_train(gss_ctx ctx, const float *host_feat, const double *host_cycles, int64_t n, int32_t epochs,
-                     float lr, uint64_t seed, float *host_loss);
+                     float lr, uint64_t seed, uint32_t flags, float *host_loss);
 void costmodel_grad(gss_ctx ctx, const float *host_x, const float *host_y, int32_t nb, float *host_g,
                     float *host_loss);
 int64_t costmodel_nparam_total();

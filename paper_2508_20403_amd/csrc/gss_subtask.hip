@@ -345,7 +345,8 @@ __device__ __forceinline__ void feat_edge(int32_t p, int32_t lca_depth, const in
 {
     const int32_t path = rdu[p] - lca_depth + rdv[p] - lca_depth;
     const int32_t b = rb[p];
-    const int32_t deg = vrec[ru[p]].pad + vrec[rv[p]].pad + 2;
+    const VRec xu = vrec[ru[p]], xv = vrec[rv[p]];
+    const int32_t deg = xu.pad + (xu.parent >= 0) + xv.pad + (xv.parent >= 0);  // deg_T(u) + deg_T(v)
     a.path += (unsigned long long)path;
     a.max_path = max(a.max_path, path);
     a.beta += (unsigned long long)b;
@@ -377,7 +378,7 @@ __device__ __forceinline__ void feat_write(float *__restrict__ f, int32_t size, 
     f[4] = (float)((double)a.nb0 / size);   // share of edges with beta* = 0
     f[5] = (float)((double)a.deg / size);   // mean endpoint tree-degree sum
     f[6] = (float)a.max_deg;
-    f[7] = log2f(1.f + (float)rl.pad);      // tree degree of the LCA
+    f[7] = log2f(1.f + (float)(rl.pad + (rl.parent >= 0)));  // tree degree of the LCA
     f[8] = log2f(1.f + (float)rl.depth);    // depth of the LCA
     f[9] = S / fmaxf((float)P, 1.f);        // share of the resolved prefix
     f[10] = log2f(1.f + (float)a.path);     // total tree-path length

@@ -29,7 +29,8 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_ctx_profile_read", "gss_ctx_set_tuning", "gss_trace_read", "gss_trace_clear",
            "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
            "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
-           "gss_tree_graph_edges", "gss_autotune", "gss_ctx_set_batch_split"]
+           "gss_tree_graph_edges", "gss_autotune", "gss_ctx_set_batch_split", "gss_target_count",
+           "gss_ctx_set_rank_capacity", "gss_tree_rank_attempts", "gss_ctx_set_sort"]
 GSS_F_RECORD = 2
 GSS_F_STATS = 4
 NFEAT = 12
@@ -59,7 +60,7 @@ class Info(ctypes.Structure):
                 ("n_recovered", ctypes.c_int64), ("n_subtasks", ctypes.c_int64),
                 ("largest_subtask", ctypes.c_int64), ("prefix_len", ctypes.c_int64),
                 ("n_arcs", ctypes.c_int64), ("n_join", ctypes.c_int64), ("passes", ctypes.c_int32),
-                ("rounds", ctypes.c_int32)]
+                ("rounds", ctypes.c_int32), ("sched", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -97,17 +98,26 @@ def load_library(path=LIB_PATH):
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]
     lib.gss_ctx_profile_read.restype = ctypes.c_int32
-    lib.gss_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
-    lib.gss_trace_read.argtypes = [P, P, P, P, ctypes.c_int64]
+    lib.gss_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.gss_target_count.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Params)]
+    lib.gss_target_count.restype = ctypes.c_int64
+    lib.gss_trace_read.argtypes = [P, P, P, P, P, P, ctypes.c_int64]
     lib.gss_trace_read.restype = ctypes.c_int64
     lib.gss_trace_clear.argtypes = [P]
-    lib.gss_costmodel_train.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, P]
+    lib.gss_costmodel_train.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                                        ctypes.c_uint32, P]
     lib.gss_costmodel_load.argtypes = [P, P]
     lib.gss_costmodel_save.argtypes = [P, P]
     lib.gss_costmodel_predict.argtypes = [P, P, ctypes.c_int64, P]
     lib.gss_costmodel_grad.argtypes = [P, P, P, ctypes.c_int32, P, P]
     lib.gss_batch_prep.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_uint32, ctypes.POINTER(P)]
     lib.gss_recover_batch.argtypes = [P, P, P, P, P, P]
+    lib.gss_ctx_set_sort.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.gss_ctx_set_sort.restype = ctypes.c_int32
+    lib.gss_ctx_set_rank_capacity.argtypes = [P, ctypes.c_int32]
+    lib.gss_ctx_set_rank_capacity.restype = ctypes.c_int32
+    lib.gss_tree_rank_attempts.argtypes = [P]
+    lib.gss_tree_rank_attempts.restype = ctypes.c_int32
     lib.gss_ctx_set_batch_split.argtypes = [P, ctypes.c_int64]
     lib.gss_ctx_set_batch_split.restype = ctypes.c_int32
     lib.gss_tree_num_graphs.argtypes = [P]
@@ -115,7 +125,8 @@ def load_library(path=LIB_PATH):
     lib.gss_tree_graph_edges.argtypes = [P, ctypes.c_int32]
     lib.gss_tree_graph_edges.restype = ctypes.c_int64
     lib.gss_autotune.argtypes = [P, P, P, P, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
-                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
     for name in ("gss_autotune", "gss_batch_prep", "gss_recover_batch", "gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_prep",
                  "gss_tree_free", "gss_recover", "gss_tree_export", "gss_edge_lca", "gss_ctx_set_tuning",
                  "gss_trace_clear", "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save",
@@ -179,33 +190,45 @@ class Context:
         """Batch graphs with at least own_nnz CSR entries are prepared on their own."""
         self.check(self.lib.gss_ctx_set_batch_split(self.handle, int(own_nnz)))
 
-    def set_tuning(self, local_max, local_blocks):
-        self.check(self.lib.gss_ctx_set_tuning(self.handle, int(local_max), int(local_blocks)))
+    def set_sort(self, radix=False, bucket_cap=0):
+        """Short sorts by the radix sort (radix=True) or the sample sort with at most
+        bucket_cap pairs per LDS bucket (0: the kernel's limit); diagnostic."""
+        self.check(self.lib.gss_ctx_set_sort(self.handle, 1 if radix else 0, int(bucket_cap)))
 
-    def trace_read(self):
-        """(features [rows,12] float32, cycles [rows] float64, sizes [rows] int32) recorded so far."""
+    def set_rank_capacity(self, divisor):
+        """Divides the list ranking's first-attempt capacities (diagnostic; 1 = default)."""
+        self.check(self.lib.gss_ctx_set_rank_capacity(self.handle, int(divisor)))
+
+    def set_tuning(self, local_max, local_blocks, chunk=0):
+        """Work-queue settings; chunk 0 derives the queue entries per pop from the queue length."""
+        self.check(self.lib.gss_ctx_set_tuning(self.handle, int(local_max), int(local_blocks), int(chunk)))
+
+    def trace_read(self, extended=False):
+        """(features [rows,12] float32, cycles [rows] float64, sizes [rows] int32) recorded so
+        far; with extended=True also (LCA vertex [rows] int32, prefix length [rows] int64)."""
         import numpy as np
-        rows = self.lib.gss_trace_read(self.handle, None, None, None, 0)
+        rows = self.lib.gss_trace_read(self.handle, None, None, None, None, None, 0)
         feat = np.zeros((rows, NFEAT), np.float32)
         cyc = np.zeros(rows, np.float64)
         size = np.zeros(rows, np.int32)
+        lca = np.zeros(rows, np.int32)
+        plen = np.zeros(rows, np.int64)
         if rows:
-            self.lib.gss_trace_read(self.handle, feat.ctypes.data_as(ctypes.c_void_p),
-                                    cyc.ctypes.data_as(ctypes.c_void_p), size.ctypes.data_as(ctypes.c_void_p),
-                                    rows)
-        return feat, cyc, size
+            vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+            self.lib.gss_trace_read(self.handle, vp(feat), vp(cyc), vp(size), vp(lca), vp(plen), rows)
+        return (feat, cyc, size, lca, plen) if extended else (feat, cyc, size)
 
     def trace_clear(self):
         self.check(self.lib.gss_trace_clear(self.handle))
 
-    def costmodel_train(self, feat, cycles, epochs=10, lr=1e-3, seed=0):
+    def costmodel_train(self, feat, cycles, epochs=10, lr=1e-3, seed=0, warm=False):
         import numpy as np
         feat = np.ascontiguousarray(feat, np.float32)
         cycles = np.ascontiguousarray(cycles, np.float64)
         loss = np.zeros(epochs, np.float32)
         self.check(self.lib.gss_costmodel_train(self.handle, feat.ctypes.data_as(ctypes.c_void_p),
                                                 cycles.ctypes.data_as(ctypes.c_void_p), len(cycles),
-                                                int(epochs), float(lr), int(seed),
+                                                int(epochs), float(lr), int(seed), 1 if warm else 0,
                                                 loss.ctypes.data_as(ctypes.c_void_p)))
         return loss
 
@@ -274,6 +297,9 @@ class Tree:
         t = lambda a: torch.from_numpy(a).to(device)  # noqa: E731
         return cls(ctx, t(g.row_ptr), t(g.col), t(g.w), t(g.parent), trusted)
 
+    def rank_attempts(self):
+        return int(self.ctx.lib.gss_tree_rank_attempts(self.handle))
+
     def export(self):
         dev = self.arrays[3].device
         depth = torch.empty(self.n, dtype=torch.int32, device=dev)
@@ -292,11 +318,19 @@ class Tree:
                                                  _ptr(bstar)))
         return lca, bstar
 
+    def target_count(self, alpha, k_override=-1):
+        """K as the library computes it (gss_target_count)."""
+        p = Params(float(alpha), 0, 0, int(k_override), 0, 0)
+        k = self.ctx.lib.gss_target_count(self.handle, 0, ctypes.byref(p))
+        if k < 0:
+            raise GSSError(-1, "bad arguments for gss_target_count")
+        return int(k)
+
     def recover(self, alpha, beta, k_override=-1, sched=SCHED_EDGECOUNT, mask_tree=False,
                 want_order=True, want_stretch=False, out=None, record=False, stats=False):
         """Runs gss_recover.  Returns (status, mask, order, stretch, info dict)."""
         dev = self.arrays[3].device
-        k = int(k_override) if k_override >= 0 else int(float(alpha) * float(self.n) // 1)
+        k = self.target_count(alpha, k_override)
         if out is None:
             mask = torch.empty(max(self.m, 1), dtype=torch.uint8, device=dev)
             order = torch.empty(max(k, 1), dtype=torch.int32, device=dev) if want_order else None
@@ -362,18 +396,30 @@ class Batch:
         return params
 
     def autotune(self, cache_path=None, sched=SCHED_EDGECOUNT):
-        """Picks the work-queue settings for this batch; returns (local_max, blocks, ms)."""
+        """Picks the work-queue settings for this batch; returns (local_max, blocks, chunk, ms)."""
         nb = len(self.graphs)
         params = self._params([g.alpha for g in self.graphs], self.graphs[0].beta, sched, None, False)
         dev = torch.device("cuda")
         masks = [torch.empty(max(self.m[i], 1), dtype=torch.uint8, device=dev) for i in range(nb)]
         mp = (ctypes.c_void_p * nb)(*[m.data_ptr() for m in masks])
-        lm, lb, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        lm, lb, ch, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         self.ctx.check(self.ctx.lib.gss_autotune(self.ctx.handle, self.handle, ctypes.cast(params, ctypes.c_void_p),
                                                  ctypes.cast(mp, ctypes.c_void_p), None,
                                                  cache_path.encode() if cache_path else None,
-                                                 ctypes.byref(lm), ctypes.byref(lb), ctypes.byref(ms)))
-        return lm.value, lb.value, ms.value
+                                                 ctypes.byref(lm), ctypes.byref(lb), ctypes.byref(ch),
+                                                 ctypes.byref(ms)))
+        return lm.value, lb.value, ch.value, ms.value
+
+    def target_counts(self, alphas, k_override=None):
+        """Per-graph K as the library computes it (gss_target_count)."""
+        out = []
+        for i in range(len(self.graphs)):
+            p = Params(float(alphas[i]), 0, 0, int(k_override[i]) if k_override is not None else -1, 0, 0)
+            k = self.ctx.lib.gss_target_count(self.handle, i, ctypes.byref(p))
+            if k < 0:
+                raise GSSError(-1, "bad arguments for gss_target_count")
+            out.append(int(k))
+        return out
 
     def recover(self, alphas=None, beta=None, sched=SCHED_EDGECOUNT, k_override=None, out=None, record=False,
                 stats=False):
@@ -382,8 +428,7 @@ class Batch:
         dev = torch.device("cuda")
         alphas = [g.alpha for g in self.graphs] if alphas is None else alphas
         beta = self.graphs[0].beta if beta is None else beta
-        ks = [int(k_override[i]) if k_override is not None else int(float(alphas[i]) * float(self.n[i]) // 1)
-              for i in range(nb)]
+        ks = self.target_counts(alphas, k_override)
         if out is None:
             masks = [torch.empty(max(self.m[i], 1), dtype=torch.uint8, device=dev) for i in range(nb)]
             orders = [torch.empty(max(ks[i], 1), dtype=torch.int32, device=dev) for i in range(nb)]

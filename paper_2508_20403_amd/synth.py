@@ -85,46 +85,101 @@ def _sort_edges(u, v, w=None):
     v = np.asarray(v, dtype=np.int64)
     a = np.minimum(u, v)
     b = np.maximum(u, v)
-    o = np.lexsort((b, a))
+    # one int64 key per edge orders like (a, b); inputs that are already in order (most
+    # generators emit them so) skip the sort
+    key = a * (int(b.max(initial=0)) + 1) + b
+    if key.size > 1 and not bool(np.all(key[1:] >= key[:-1])):
+        o = np.argsort(key, kind="stable")
+        a, b = a[o], b[o]
+        if w is not None:
+            w = np.asarray(w, dtype=np.float64)[o]
     if w is None:
-        return a[o], b[o]
-    return a[o], b[o], np.asarray(w, dtype=np.float64)[o]
+        return a, b
+    return a, b, np.asarray(w, dtype=np.float64)
 
 
 def to_csr(n, eu, ev, ew):
-    """Symmetric CSR from upper edges (eu < ev), columns sorted within each row."""
+    """Symmetric CSR from upper edges (eu < ev) in edge-id order, columns sorted in each row.
+
+    A counting sort by row keeps the input order inside a row.  Listing the mirrored
+    entries (row ev, column eu) before the upper ones (row eu, column ev) therefore gives
+    sorted rows: for a fixed row r the mirrored entries have columns < r in ascending
+    order (edge-id order sorts them by eu), the upper ones columns > r in ascending order.
+    """
     eu = np.asarray(eu, dtype=np.int64)
     ev = np.asarray(ev, dtype=np.int64)
-    rows = np.concatenate([eu, ev])
-    cols = np.concatenate([ev, eu])
-    vals = np.concatenate([ew, ew])
-    o = np.lexsort((cols, rows))
-    rows, cols, vals = rows[o], cols[o], vals[o]
-    row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
-    if row_ptr[-1] >= 2 ** 31:
+    ew = np.asarray(ew, dtype=np.float64)
+    if 2 * len(eu) >= 2 ** 31:
         raise ValueError("graph too large for int32 CSR")
-    return row_ptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64)
+    rows = np.concatenate([ev, eu]).astype(np.int32)
+    cols = np.concatenate([eu, ev]).astype(np.int32)
+    vals = np.concatenate([ew, ew])
+    # scipy's COO -> CSR conversion is such a counting sort (linear, input order kept
+    # within a row); the rows come out sorted, so no entry moves afterwards
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    del rows, cols, vals
+    if not A.has_sorted_indices or A.nnz != 2 * len(eu):
+        raise ValueError("edges are not simple or not in edge-id order")
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
 
 
 def max_spanning_tree_parent(n, eu, ev, ew, root=None):
     """Parent array of the maximum spanning tree under (w desc, id asc), BFS-rooted.
 
     Edges must be given in edge-id order.  Raises if G is disconnected.
+
+    The tree is found by a filtered Kruskal: the spanning forest F of the edges heavier
+    than the (4n)-th largest weight first, then the spanning tree of F plus the other
+    edges that join two components of F.  Such a lighter edge inside one component of F
+    is the lightest edge of a cycle, so it is in no maximum spanning tree; the keys
+    (w desc, id asc) are distinct, so the tree is unique and equals the one of the whole
+    graph.
     """
+    eu = np.asarray(eu, dtype=np.int64)
+    ev = np.asarray(ev, dtype=np.int64)
+    w = np.asarray(ew, dtype=np.float64)
     m = len(eu)
     deg = np.bincount(eu, minlength=n) + np.bincount(ev, minlength=n)
     if root is None:
         root = int(np.argmax(deg))  # lowest id among the maximum-degree vertices
     if n == 1:
         return np.array([-1], dtype=np.int32), root
-    ids = np.arange(m, dtype=np.int64)
-    order = np.lexsort((ids, -np.asarray(ew)))          # w desc, then id asc
-    rank = np.empty(m, dtype=np.float64)
-    rank[order] = np.arange(1, m + 1, dtype=np.float64)  # distinct positive keys
-    A = sp.coo_matrix((rank, (eu, ev)), shape=(n, n)).tocsr()
-    T = csg.minimum_spanning_tree(A)
-    T = (T + T.T).tocsr()
+    rank = np.zeros(m, dtype=np.float64)
+    by_rank = []  # edge ids in (w desc, id asc) order, one array per group
+
+    def ranked(sel):
+        """Gives the edges sel (ascending ids, all lighter than every edge ranked so far)
+        the next ranks in (w desc, id asc) order."""
+        o = sel[np.argsort(-w[sel], kind="stable")]
+        start = sum(len(x) for x in by_rank)
+        rank[o] = np.arange(start + 1, start + len(o) + 1, dtype=np.float64)
+        by_rank.append(o)
+
+    def msf(sel):
+        sel = np.sort(sel)
+        A = sp.coo_matrix((rank[sel], (eu[sel], ev[sel])), shape=(n, n)).tocsr()
+        T = csg.minimum_spanning_tree(A).tocoo()
+        return np.concatenate(by_rank)[T.data.astype(np.int64) - 1]  # rank r is by_rank[r - 1]
+
+    h = min(m, 4 * n)
+    if h < m:
+        thr = np.partition(w, m - h)[m - h]  # the h-th largest weight
+        heavy = np.flatnonzero(w > thr)
+        light = np.flatnonzero(w <= thr)
+    else:
+        heavy = np.arange(m)
+        light = np.zeros(0, dtype=np.int64)
+    ranked(heavy)
+    forest = msf(heavy)
+    if len(light):
+        F = sp.coo_matrix((np.ones(len(forest), dtype=np.int8), (eu[forest], ev[forest])), shape=(n, n))
+        _, lab = csg.connected_components(F, directed=False)
+        light = light[lab[eu[light]] != lab[ev[light]]]
+        ranked(light)
+        forest = msf(np.concatenate([forest, light]))
+    if len(forest) != n - 1:
+        raise ValueError("graph is not connected")
+    T = sp.coo_matrix((np.ones(n - 1, dtype=np.int8), (eu[forest], ev[forest])), shape=(n, n)).tocsr()
     bfs, pred = csg.breadth_first_order(T, root, directed=False, return_predecessors=True)
     if len(bfs) != n:
         raise ValueError("graph is not connected")
@@ -144,7 +199,13 @@ def from_edges(n, eu, ev, ew, alpha=0.02, beta=2, name="graph", parent=None, roo
 
 
 def _largest_cc(n, x, y):
-    A = sp.coo_matrix((np.ones(len(x), dtype=np.int8), (x, y)), shape=(n, n))
+    """Largest connected component of the edges (x, y), compactly relabelled in id order
+    (x, y sorted by (x, y), so the upper-triangle CSR is built without a sort)."""
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(x, minlength=n), out=indptr[1:])
+    A = sp.csr_matrix((np.ones(len(x), dtype=np.int8), y, indptr), shape=(n, n))
     _, lab = csg.connected_components(A, directed=False)
     big = np.argmax(np.bincount(lab))
     keepv = lab == big
@@ -187,16 +248,34 @@ def rmat(scale, avg_deg=16, a=0.57, b=0.19, c=0.19, seed=0, alpha=0.10, beta=2, 
     rng = np.random.default_rng(seed)
     nfull = 1 << scale
     samples = (avg_deg * nfull) // 2
-    u = np.zeros(samples, dtype=np.int64)
-    v = np.zeros(samples, dtype=np.int64)
+    # vertex bits accumulate in int32 (scale <= 30); each level's draws are processed in
+    # cache-sized chunks (the draw order, level by level, is unchanged)
+    ab, abc = a + b, a + b + c
+    u = np.zeros(samples, dtype=np.int32)
+    v = np.zeros(samples, dtype=np.int32)
+    r = np.empty(samples, dtype=np.float64)
+    CH = 1 << 18
+    bit = np.empty(CH, dtype=np.int32)
+    t0 = np.empty(CH, dtype=bool)
+    t1 = np.empty(CH, dtype=bool)
     for lvl in range(scale):
-        r = rng.random(samples)
-        bu = r >= a + b                                  # quadrants c, d set the row bit
-        bv = ((r >= a) & (r < a + b)) | (r >= a + b + c)  # quadrants b, d set the column bit
-        u |= bu.astype(np.int64) << lvl
-        v |= bv.astype(np.int64) << lvl
-        del r, bu, bv
+        rng.random(out=r)
+        for s0 in range(0, samples, CH):
+            rr = r[s0:s0 + CH]
+            k = len(rr)
+            b0, b1, bb = t0[:k], t1[:k], bit[:k]
+            np.greater_equal(rr, ab, out=b0)                  # quadrants c, d set the row bit
+            bb[...] = b0
+            bb <<= lvl
+            u[s0:s0 + k] |= bb
+            np.greater_equal(rr, a, out=b1)                   # quadrant b, or d, sets the column bit
+            np.logical_and(b1, np.less(rr, ab, out=b0), out=b1)
+            np.logical_or(b1, np.greater_equal(rr, abc, out=b0), out=b1)
+            bb[...] = b1
+            bb <<= lvl
+            v[s0:s0 + k] |= bb
         _log(f"rmat{scale}: level {lvl + 1}/{scale}")
+    del r, bit, t0, t1
     perm = rng.permutation(nfull)
     u = perm[u]
     v = perm[v]

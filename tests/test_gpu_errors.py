@@ -94,3 +94,44 @@ def test_tree_only_and_tiny(gpu_ctx):
             1, np.zeros(2, np.int32), np.zeros(0, np.int32), np.zeros(0), np.array([-1], np.int32), 0, 0.5, 2, "one")
         st = gpu_status(gpu_ctx, g)
         assert st == oracle.recover(g, k_override=-1).status
+
+
+def _swap_lower_mirror(g):
+    """A CSR with as many lower as upper entries whose lower triangle is not the mirror
+    of the upper one: in some row u, one lower entry (u, c) is moved to a column c' < u
+    that is not a neighbour of u (the row stays sorted and simple)."""
+    rp, col, w = g.row_ptr, g.col.copy(), g.w.copy()
+    for u in range(g.n):
+        row = col[rp[u]:rp[u + 1]]
+        lower = [k for k in range(rp[u], rp[u + 1]) if col[k] < u]
+        if not lower:
+            continue
+        k = lower[-1]
+        lo = col[k - 1] + 1 if k > rp[u] else 0
+        free = [c for c in range(lo, col[k]) if c not in row and c != u]
+        if free:
+            col[k] = free[0]
+            return col, w
+    raise AssertionError("no row to alter")
+
+
+def test_unmirrored_lower_entry_with_equal_counts_is_asym(gpu_ctx):
+    """Triangle sizes agree, so only an exact mirror check can reject this CSR."""
+    g = synth.random_connected(60, 90, seed=4)
+    col2, w2 = _swap_lower_mirror(g)
+    o = oracle.recover(n=g.n, row_ptr=g.row_ptr, col=col2, w=w2, parent=g.parent, alpha=g.alpha, beta=g.beta)
+    assert o.status == -3
+    assert gpu_status(gpu_ctx, g, col=col2, w=w2) == -3
+
+
+def test_swapped_lower_weights_is_asym(gpu_ctx):
+    """Two lower entries exchange their weights: same columns, same multiset of weights."""
+    g = synth.random_connected(60, 90, seed=6)
+    rp, col, w = g.row_ptr, g.col, g.w.copy()
+    lows = [k for u in range(g.n) for k in range(rp[u], rp[u + 1]) if col[k] < u]
+    a, b = lows[3], lows[17]
+    assert w[a] != w[b]
+    w[a], w[b] = w[b], w[a]
+    o = oracle.recover(n=g.n, row_ptr=rp, col=col, w=w, parent=g.parent, alpha=g.alpha, beta=g.beta)
+    assert o.status == -3
+    assert gpu_status(gpu_ctx, g, w=w) == -3

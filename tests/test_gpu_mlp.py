@@ -118,3 +118,43 @@ def test_trained_model_beats_edge_count_on_held_out_subtasks(gpu_ctx):
     err_cnt = np.median(np.abs(A[held] @ coef - y[held]))
     print(f"held-out median |log2 error|: network {err_mlp:.3f}, edge-count fit {err_cnt:.3f}")
     assert err_mlp < err_cnt, (err_mlp, err_cnt)
+
+
+def _adam_reference(w0, x, y, steps, lr):
+    """Full-batch Adam in float64 (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
+    moments from zero) on the float64 mean-squared-error gradient of oracle/mlp.py."""
+    P = mlp.NPARAM
+    w = np.array(w0, np.float64)
+    m = np.zeros(P)
+    v = np.zeros(P)
+    for t in range(1, steps + 1):
+        _, g = mlp.loss_and_grad(w, x, y)
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        w[:P] -= lr * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+    return w
+
+
+def test_adam_steps_match_float64(gpu_ctx):
+    """Four training steps of the FP32 kernels (one 64-sample mini-batch per epoch, warm
+    start from known weights) against four float64 Adam steps.  Tolerance: 2e-3 lr + 1e-6
+    |w| per parameter; FP32 gradients and moments move a weight by about 1e-4 lr over four
+    steps, while a wrong moment, bias correction or epsilon moves it by a sizeable share
+    of lr."""
+    rng = np.random.default_rng(21)
+    lr = 1e-3
+    for seed in (3, 4):
+        w0 = mlp.random_weights(seed).astype(np.float32)
+        gpu_ctx.costmodel_load(w0)
+        x = rng.normal(0, 2, (64, mlp.NF)).astype(np.float32)
+        y = np.clip(rng.normal(12, 3, 64), 1, 30).astype(np.float32)
+        gpu_ctx.costmodel_train(x, np.exp2(y.astype(np.float64)), epochs=4, lr=lr, seed=seed, warm=True)
+        w_gpu = gpu_ctx.costmodel_save().astype(np.float64)
+        w_ref = _adam_reference(w0.astype(np.float64), x.astype(np.float64), y.astype(np.float64), 4, lr)
+        # the warm start keeps the loaded feature normalisation
+        np.testing.assert_array_equal(w_gpu[mlp.NPARAM:], w0[mlp.NPARAM:].astype(np.float64))
+        d = np.abs(w_gpu - w_ref)[: mlp.NPARAM]
+        assert np.all(d <= 2e-3 * lr + 1e-6 * np.abs(w_ref[: mlp.NPARAM])), (seed, d.max() / lr)
+        # and the step moved the weights: about lr per parameter with a gradient
+        moved = np.abs(w_ref - w0.astype(np.float64))[: mlp.NPARAM]
+        assert np.median(moved) > lr

@@ -109,3 +109,34 @@ def test_trusted_prep_matches_oracle(gpu_ctx, name, make):
                stretch=stretch.cpu().numpy(), info=info)
     tree.free()
     assert_same_recovery(gpu, run_oracle(g))
+
+
+@pytest.mark.parametrize("make", [lambda: synth.grid((40, 40, 40), 1.0, 1e4, seed=3, alpha=0.05, beta=2),
+                                  lambda: synth.random_connected(60000, 90000, seed=2, alpha=0.05, beta=2,
+                                                                 tree="random")],
+                         ids=["grid40", "rand60000"])
+def test_rank_capacity_retry_matches_oracle(gpu_ctx, make):
+    """The list ranking's capacity retry: with the first attempt's level capacities cut
+    to a quarter, levels outgrow them, the device flags it and the host ranks again with
+    twice and then four times the capacities (three attempts).  The prepared tree and
+    the recovery must still equal the oracle's bit for bit; with the default capacities
+    one attempt suffices."""
+    g = make()
+    orc = run_oracle(g)
+    for divisor, attempts in ((4, 3), (1, 1)):
+        gpu_ctx.set_rank_capacity(divisor)
+        try:
+            tree = gss.Tree.from_graph(gpu_ctx, g)
+        finally:
+            gpu_ctx.set_rank_capacity(1)
+        assert tree.rank_attempts() == attempts
+        depth, dlo, dhi, scale = tree.export()
+        np.testing.assert_array_equal(depth.cpu().numpy(), orc.depth)
+        np.testing.assert_array_equal(dlo.cpu().numpy().view(np.uint64), orc.Dlo)
+        np.testing.assert_array_equal(dhi.cpu().numpy().view(np.uint64), orc.Dhi)
+        st, mask, order, stretch, info = tree.recover(g.alpha, g.beta, want_stretch=True)
+        torch.cuda.synchronize()
+        gpu = dict(status=st, mask=mask.cpu().numpy(), order=order.cpu().numpy(), stretch=stretch.cpu().numpy(),
+                   info=info)
+        assert_same_recovery(gpu, orc)
+        tree.free()
