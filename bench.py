@@ -1,15 +1,22 @@
 """Benchmark: one step = gss_tree_prep + gss_recover for one sparsifier on one GPU.
 
-Prints ONE JSON line (see the repository's benchmark contract).  The workload is the
-3D 7-point grid 128^3 (2,097,152 vertices, 6,242,304 edges), weights log-uniform in
-[1, 1e4], maximum-weight spanning tree, alpha = 0.05, beta = 2, seed 0.  Inputs are
-resident in HBM before the timed region.  `value` is off-tree edges processed per
-second (M / step time).
+Prints ONE JSON line (see the repository's benchmark contract).  The headline workload
+is the 3D 7-point grid 128^3 (2,097,152 vertices, 6,242,304 edges), weights log-uniform
+in [1, 1e4], maximum-weight spanning tree, alpha = 0.05, beta = 2, seed 0.  Inputs are
+resident in HBM before the timed region.  `value` is off-tree edges processed per second
+(M / step time).
 
 The roofline entry is for the dominant kernel: its launches are bracketed live by HIP
 events on the library's stream during the timed steps; `achieved` is that kernel's
 algorithmic bytes per launch divided by its mean launch time.  The CPU baseline is the
-serial oracle (test infrastructure, never tuned) on the same workload.
+serial oracle (test infrastructure, never tuned) on the same workload, pinned to one host
+core, best of three.
+
+`config.batched` covers the rest of the headline metric ("learned-sched vs plain") on the
+64-graph random geometric batch: per-graph calls (the plain form) against one batched
+call with the edge-count and with the learned queue order, the makespan of the work-queue
+kernel under both orders, and bit-exactness of every graph against the oracle's stored
+digests.  `--no-batch` skips it.
 """
 from __future__ import annotations
 
@@ -17,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+GOLD_PATH = os.path.join(ROOT, "tests", "golden", "full_size.json")
 
 WORKLOADS = {
     "grid3d_128": "3D 7-point grid 128^3 (2,097,152 vertices, 6,242,304 edges), w log-uniform [1,1e4] "
@@ -37,6 +46,8 @@ WORKLOADS = {
     "grid3d_160": "3D 7-point grid 160^3, w log-uniform [1,1e4], alpha=0.10, beta=2, seed 0",
     "rmat24": "R-MAT scale 24 LCC, w uniform (0,1], alpha=0.10, beta=2, seed 0",
 }
+RGG_DESC = ("64 random geometric graphs, n log-uniform in [1e4,1e6) (sum n = %d), radius for average degree ~10, "
+            "w = 1/distance, alpha in {.02,.05,.10}, beta 2, seed 0")
 
 
 def step_alg_bytes(n, m, M, K):
@@ -55,6 +66,55 @@ def src_digest(paths):
     return h.hexdigest()[:16]
 
 
+def sha(a, dtype):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(g, M, runs=3):
+    """The serial oracle on one pinned host core, best of `runs`, with its per-step times
+    (Alg. 1 Step 1: tree, LCA and stretch; Step 2: sort; Step 3: grouping count; Step 4:
+    greedy).  Returns (baseline dict, oracle result of the last run)."""
+    import oracle
+    model, ncpu, navail = host_cpu()
+    saved = os.sched_getaffinity(0)
+    core = min(saved)
+    best, phases, ref = None, None, None
+    try:
+        os.sched_setaffinity(0, {core})
+        for _ in range(runs):
+            t = time.perf_counter()
+            ref = oracle.recover(g)
+            s = time.perf_counter() - t
+            if best is None or s < best:
+                best, phases = s, ref.times.copy()
+    finally:
+        os.sched_setaffinity(0, saved)
+    return {"value": round(M / best, 1), "unit": "off-tree edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole workload (tree preparation + recovery of one sparsifier), best of {runs} runs "
+                      f"pinned to host core {core}",
+            "ms_per_sparsifier": round(best * 1e3, 1),
+            "phase_ms": {"step1_tree_lca_stretch": round(phases[0] * 1e3, 1), "step2_sort": round(phases[1] * 1e3, 1),
+                         "step3_grouping": round(phases[2] * 1e3, 1), "step4_greedy": round(phases[3] * 1e3, 1)},
+            "host_cpu": model, "host_nproc": ncpu, "host_cpus_available": navail}, ref
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,15 +122,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid3d_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-schedule record")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline entry (default: dominant)")
     ap.add_argument("--breakdown", action="store_true", help="print a per-kernel time table to stderr")
     ap.add_argument("--mode", default="plain", choices=["plain", "batch"],
-                    help="plain: one sparsifier (the headline line); batch: many graphs, plain form vs "
-                         "batched and learned-scheduled forms")
-    ap.add_argument("--graphs", default="rgg64", help="batch mode workload: rgg64, or a comma list of names")
-    ap.add_argument("--epochs", type=int, default=20, help="batch mode: cost-model training epochs")
-    ap.add_argument("--tuning", default=None, metavar="LOCAL_MAX,BLOCKS",
-                    help="plain mode: work-queue limits (default: the library's)")
+                    help="plain: one sparsifier (the headline line, with the batched record); batch: only the "
+                         "batched comparison, as its own line")
+    ap.add_argument("--graphs", default="rgg64", help="batch workload: rgg64, or a comma list of names")
+    ap.add_argument("--epochs", type=int, default=20, help="cost-model training epochs")
+    ap.add_argument("--tuning", default=None, metavar="LOCAL_MAX,BLOCKS[,CHUNK]",
+                    help="plain mode: work-queue settings (default: the library's)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -85,24 +146,21 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.mode == "batch":
-        return bench_batch(args)
+        out = bench_batch(args)
+        print(json.dumps(out), flush=True)
+        return
     t0 = time.time()
     g = synth.config(args.workload)
-    print(f"[bench] workload {args.workload}: n={g.n} m={g.m} ({time.time() - t0:.1f}s to build)",
-          file=sys.stderr, flush=True)
+    log(f"workload {args.workload}: n={g.n} m={g.m} ({time.time() - t0:.1f}s to build)")
     dev = torch.device("cuda:0")
     row_ptr = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
     w = torch.from_numpy(g.w).to(dev)
     parent = torch.from_numpy(g.parent).to(dev)
-    K = synth.k_of(g.alpha, g.n)
-    mask = torch.empty(g.m, dtype=torch.uint8, device=dev)
-    order = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     ctx = gss.Context(0, torch.cuda.current_stream())
     if args.tuning:
-        lm, nb = (int(x) for x in args.tuning.split(","))
-        ctx.set_tuning(lm, nb)
+        ctx.set_tuning(*(int(x) for x in args.tuning.split(",")))
     if args.copy_probe:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -110,6 +168,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    probe = gss.Tree(ctx, row_ptr, col, w, parent)
+    K = probe.target_count(g.alpha)
+    probe.free()
+    mask = torch.empty(g.m, dtype=torch.uint8, device=dev)
+    order = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
 
     def step():
         tree = gss.Tree(ctx, row_ptr, col, w, parent)
@@ -133,7 +196,7 @@ def main():
         for k, (ms, nl, nb) in sorted(table.items(), key=lambda kv: -kv[1][0]):
             gbs = f"{nb / (ms * 1e-3) / 1e9:8.1f} GB/s" if nb else "       -     "
             print(f"  {k:24s} {ms:9.3f} ms  {nl:5d} launches  {100 * ms / tot:5.1f}%  {gbs}", file=sys.stderr)
-    print(f"[bench] dominant kernel {dominant}; info {info}", file=sys.stderr, flush=True)
+    log(f"dominant kernel {dominant}; info {info}")
 
     ctx.profile(True, dominant)
     torch.cuda.synchronize()
@@ -165,8 +228,7 @@ def main():
             digest = src_digest([os.path.join(csrc, f) for f in sorted(os.listdir(csrc))])
             if tr.get("source_digest") == digest:
                 roofline["traffic"] = tr.get("traffic_bytes")
-    K_all = info["k"]
-    step_bytes = step_alg_bytes(g.n, g.m, M, K_all)
+    step_bytes = step_alg_bytes(g.n, g.m, M, info["k"])
     step_roof = {"alg_bytes": int(step_bytes), "achieved_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
                  "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -174,18 +236,21 @@ def main():
     cpu = None
     bit_exact = None
     if not args.no_cpu:
-        import oracle
-        os.environ.setdefault("OMP_NUM_THREADS", "1")
-        t = time.perf_counter()
-        ref = oracle.recover(g)
-        cpu_s = time.perf_counter() - t
-        cpu = {"value": round(M / cpu_s, 1), "unit": "off-tree edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole {args.workload} workload once (tree preparation + recovery of one "
-                         f"sparsifier), {cpu_s:.2f} s on one host core",
-               "ms_per_sparsifier": round(cpu_s * 1e3, 1)}
+        cpu, ref = cpu_baseline(g, M)
+        log(f"cpu baseline {cpu}")
         bit_exact = bool(np.array_equal(mask.cpu().numpy(), ref.mask) and
                          np.array_equal(order[:K].cpu().numpy(), ref.order))
 
+    config = {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m, "offtree_edges": M, "k": K,
+              "alpha": g.alpha, "beta": g.beta, "ms_per_sparsifier": round(ms_step, 4),
+              "recovered_per_s": round(K / (ms_step * 1e-3), 1), "bit_exact_vs_oracle": bit_exact,
+              "prefix_len": info["prefix_len"], "passes": info["passes"], "join_edges": info["n_join"],
+              "step_roofline": step_roof}
+    ctx.close()
+    del row_ptr, col, w, parent, mask, order
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        config["batched"] = bench_batch(args)["config"]
     out = {
         "metric": "off-tree edges recovered/s + ms per sparsifier, learned-sched vs plain, bit-exact",
         "value": round(value, 1),
@@ -199,43 +264,44 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "n": g.n, "m": g.m, "offtree_edges": M, "k": K,
-                   "alpha": g.alpha, "beta": g.beta, "ms_per_sparsifier": round(ms_step, 4),
-                   "recovered_per_s": round(K / (ms_step * 1e-3), 1), "bit_exact_vs_oracle": bit_exact,
-                   "prefix_len": info["prefix_len"], "passes": info["passes"], "join_edges": info["n_join"],
-                   "step_roofline": step_roof},
+        "config": config,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 def bench_batch(args):
     """Plain form (gss_tree_prep + gss_recover per graph) against the batched form
     (gss_batch_prep + one gss_recover_batch), with the edge-count and the learned
-    schedule.  All forms must give identical outputs."""
+    schedule.  Every form must give the oracle's outputs (stored digests for the 64-graph
+    batch; the plain form's outputs otherwise)."""
     import torch
     from paper_2508_20403_amd import gss, synth
 
     t0 = time.time()
+    gold = None
     if args.graphs == "rgg64":
         graphs = synth.batch_config()
-        desc = ("64 random geometric graphs, n log-uniform in [1e4,1e6) (sum n = %d), radius for average "
-                "degree ~10, w = 1/distance, alpha in {.02,.05,.10}, beta 2, seed 0" % sum(g.n for g in graphs))
+        desc = RGG_DESC % sum(g.n for g in graphs)
+        if os.path.exists(GOLD_PATH):
+            gold = json.load(open(GOLD_PATH)).get("rgg64", {}).get("graphs")
     else:
-        graphs = [synth.config(x) for x in args.graphs.split(",")]
-        desc = " + ".join(WORKLOADS.get(x, x) for x in args.graphs.split(","))
-    print(f"[bench] batch of {len(graphs)} graphs built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        names = args.graphs.split(",")
+        graphs = [synth.config(x) for x in names]
+        desc = " + ".join(WORKLOADS.get(x, x) for x in names)
+    log(f"batch of {len(graphs)} graphs built in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     arrays = [tuple(torch.from_numpy(a).to(dev) for a in (g.row_ptr, g.col, g.w, g.parent)) for g in graphs]
-    Ks = [synth.k_of(g.alpha, g.n) for g in graphs]
+    torch.cuda.synchronize()
+    ctx = gss.Context(0, torch.cuda.current_stream())
+    b0 = gss.Batch(ctx, graphs, arrays=arrays)
+    Ks = b0.target_counts([g.alpha for g in graphs])
+    b0.free()
     outs = [(torch.empty(max(g.m, 1), dtype=torch.uint8, device=dev), torch.empty(max(k, 1), dtype=torch.int32,
                                                                                    device=dev)) for g, k in zip(graphs, Ks)]
     bmasks = [torch.empty(max(g.m, 1), dtype=torch.uint8, device=dev) for g in graphs]
     borders = [torch.empty(max(k, 1), dtype=torch.int32, device=dev) for k in Ks]
-    torch.cuda.synchronize()
-    ctx = gss.Context(0, torch.cuda.current_stream())
 
     def plain_step():
         for g, (rp, col, w, par), (mk, od) in zip(graphs, arrays, outs):
@@ -256,13 +322,33 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t) / steps
 
+    def queue_kernel_ms(fn):
+        """Makespan of the persistent work-queue kernel in one (untimed) call."""
+        torch.cuda.synchronize()
+        ctx.profile(True, None)
+        fn()
+        torch.cuda.synchronize()
+        table = ctx.profile_read()
+        ctx.profile(False)
+        return round(sum(v[0] for k, v in table.items() if k.startswith("k_local_recover")), 4)
+
+    def outputs(masks, orders):
+        return [(masks[i][:g.m].cpu().numpy().copy(), orders[i][:Ks[i]].cpu().numpy().copy())
+                for i, g in enumerate(graphs)]
+
+    def matches(got, ref):
+        if gold is not None:
+            return all(sha(o, "<i4") == r["order_sha256"] and sha(mk, np.uint8) == r["mask_sha256"]
+                       for (mk, o), r in zip(got, gold))
+        return all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(got, ref))
+
     for _ in range(max(args.warmup, 1)):
         plain_step()
         batch_step(gss.SCHED_EDGECOUNT)
     # autotune the work queue on this batch (untimed, cached per device and workload)
     b = gss.Batch(ctx, graphs, arrays=arrays)
     lm, lb, ch, tms = b.autotune(os.path.join(ROOT, "_data", "autotune.txt"))
-    print(f"[bench] autotune: local_max={lm} blocks={lb} chunk={ch} ({tms:.3f} ms)", file=sys.stderr, flush=True)
+    log(f"autotune: local_max={lm} blocks={lb} chunk={ch} ({tms:.3f} ms)")
     # the plain kernel records per-subtask cycles; the cost model trains on them (untimed)
     ctx.trace_clear()
     for _ in range(3):
@@ -287,12 +373,11 @@ def bench_batch(args):
         heldout = {"samples": int(held.sum()),
                    "mlp_median_abs_log2_err": round(float(np.median(np.abs(pred - y[held]))), 4),
                    "edgecount_fit_median_abs_log2_err": round(float(np.median(np.abs(A[held] @ coef - y[held]))), 4)}
-        print(f"[bench] held-out cost error (median |log2 pred/measured|): {heldout}", file=sys.stderr, flush=True)
+        log(f"held-out cost error (median |log2 pred/measured|): {heldout}")
     t = time.perf_counter()
     loss = ctx.costmodel_train(feat, cyc, epochs=args.epochs, lr=1e-3, seed=0)
     train_s = time.perf_counter() - t
-    print(f"[bench] cost model: {len(cyc)} samples, loss {loss[0]:.3f} -> {loss[-1]:.3f}, {train_s:.2f}s",
-          file=sys.stderr, flush=True)
+    log(f"cost model: {len(cyc)} samples, loss {loss[0]:.3f} -> {loss[-1]:.3f}, {train_s:.2f}s")
 
     if args.breakdown:  # per-kernel tables of one plain, one batched and one learned step (untimed)
         for label, fn in (("plain", plain_step), ("batched", lambda: batch_step(gss.SCHED_EDGECOUNT)),
@@ -304,27 +389,29 @@ def bench_batch(args):
             table = ctx.profile_read()
             ctx.profile(False)
             tot = sum(v[0] for v in table.values())
-            print(f"[bench] {label} step: {tot:.3f} ms of kernels", file=sys.stderr)
+            log(f"{label} step: {tot:.3f} ms of kernels")
             for k, (ms, nl, nb) in sorted(table.items(), key=lambda kv: -kv[1][0])[:24]:
                 print(f"  {k:24s} {ms:9.3f} ms  {nl:5d} launches", file=sys.stderr)
     steps = max(args.steps // 4, 2)
     ms_plain = timed(plain_step, steps)
-    ref = [(mk[:g.m].cpu().numpy().copy(), od[:k].cpu().numpy().copy()) for g, (mk, od), k in zip(graphs, outs, Ks)]
+    ref = outputs([o[0] for o in outs], [o[1] for o in outs])
+    same_p = matches(ref, ref)
     ms_batch = timed(lambda: batch_step(gss.SCHED_EDGECOUNT), steps)
-    same_b = all(np.array_equal(bmasks[i][:g.m].cpu().numpy(), ref[i][0]) and
-                 np.array_equal(borders[i][:Ks[i]].cpu().numpy(), ref[i][1]) for i, g in enumerate(graphs))
+    same_b = matches(outputs(bmasks, borders), ref)
     ms_learn = timed(lambda: batch_step(gss.SCHED_LEARNED), steps)
-    same_l = all(np.array_equal(bmasks[i][:g.m].cpu().numpy(), ref[i][0]) and
-                 np.array_equal(borders[i][:Ks[i]].cpu().numpy(), ref[i][1]) for i, g in enumerate(graphs))
+    same_l = matches(outputs(bmasks, borders), ref)
+    mk_edge = queue_kernel_ms(lambda: batch_step(gss.SCHED_EDGECOUNT))
+    mk_learn = queue_kernel_ms(lambda: batch_step(gss.SCHED_LEARNED))
     M = sum(g.m - g.n + 1 for g in graphs)
-    out = {
+    ctx.close()
+    return {
         "metric": "off-tree edges recovered/s + ms per sparsifier, learned-sched vs plain, bit-exact",
         "value": round(M / (ms_learn * 1e-3), 1),
         "unit": "off-tree edges/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": round(ms_learn, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": desc, "graphs": len(graphs), "offtree_edges": M,
+        "config": {"workload": desc, "graphs": len(graphs), "offtree_edges": M, "steps": steps,
                    "plain_ms_per_batch": round(ms_plain, 3), "batched_ms_per_batch": round(ms_batch, 3),
                    "batched_learned_ms_per_batch": round(ms_learn, 3),
                    "ms_per_sparsifier_plain": round(ms_plain / len(graphs), 4),
@@ -332,14 +419,15 @@ def bench_batch(args):
                    "gain_batched_learned_vs_plain": round(ms_plain / ms_learn, 3),
                    "gain_batched_vs_plain": round(ms_plain / ms_batch, 3),
                    "gain_learned_vs_edgecount_batched": round(ms_batch / ms_learn, 3),
-                   "bit_exact_batched": bool(same_b), "bit_exact_learned": bool(same_l),
-                   "autotune": {"local_max": lm, "blocks": lb},
+                   "queue_kernel_ms_edgecount": mk_edge, "queue_kernel_ms_learned": mk_learn,
+                   "bit_exact_vs_oracle": {"reference": "stored oracle digests" if gold is not None else
+                                           "the plain form", "plain": bool(same_p), "batched": bool(same_b),
+                                           "learned": bool(same_l)},
+                   "autotune": {"local_max": lm, "blocks": lb, "chunk": ch},
                    "costmodel": {"samples": int(len(cyc)), "epochs": args.epochs,
                                  "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
                                  "train_s": round(train_s, 3), "heldout": heldout}},
     }
-    print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -73,6 +73,11 @@ typedef struct {
                                   queue kernel to the context trace (cost-model training data) */
 #define GSS_F_STATS 4u         /* fill gss_info.n_subtasks / largest_subtask (an extra per-edge
                                   count; -1 in those fields otherwise)                     */
+#define GSS_F_KEY_RT 8u        /* order the off-tree edges by the tree-path resistance R_T
+                                  alone (the literal wording of Alg. 1 Step 2, "sort L based
+                                  on resistances") instead of the stretch w*R_T; ties still
+                                  by ascending id.  The stretch output is unchanged.  All
+                                  graphs of a batch must agree on it.                     */
 
 /* gss_params.sched: order in which the subtask work queue is drained (never changes
  * the output).  GSS_SCHED_LEARNED without a loaded cost model falls back to the

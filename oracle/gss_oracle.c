@@ -25,6 +25,15 @@
  *       over the unrecovered edges with all marks cleared (feGRASS multi-pass rule,
  *       Sec. II-B).
  *
+ * Variants (bit flags, each from its own passage of the paper):
+ *   ORC_KEY_RT   O8 sorts by the tree-path resistance R_T itself, the literal wording of
+ *                Alg. 1 Step 2 ("sort L based on resistances"), instead of the stretch.
+ *   ORC_LOOSE    O9 uses feGRASS's loose condition (Def. "Similar edge (Loose)", eq.
+ *                cond-loose-2): with balls of the constant radius c around u and v, every
+ *                later off-tree edge with EITHER endpoint in S_u or S_v is marked.  Passes
+ *                repeat with marks cleared (the multi-pass rule of Sec. II-B).  The LCA
+ *                lemma does not hold for it, so it has no subtask mode.
+ *
  * Marking enumeration modes (must agree):
  *   ORC_MODE_INDEXED  -- scan the graph rows of every ball vertex except lca(e).
  *   ORC_MODE_BRUTE    -- test every later off-tree edge in pi.
@@ -50,6 +59,7 @@ enum {
     ORC_ERR_NOT_TREE = -5, ORC_ERR_TREE_EDGE = -6, ORC_ERR_RANGE = -7, ORC_ERR_OOM = -9
 };
 enum { ORC_MODE_INDEXED = 0, ORC_MODE_BRUTE = 1, ORC_MODE_SUBTASK = 2 };
+enum { ORC_KEY_RT = 1, ORC_LOOSE = 2 };
 
 /* info[] slots */
 enum {
@@ -86,6 +96,7 @@ typedef struct {
     const int32_t *parent;
     int64_t nnz, m, M;
     int32_t root, c;
+    int32_t variant;           /* ORC_KEY_RT | ORC_LOOSE */
     /* edges */
     int32_t *eu, *ev;          /* [m] */
     double *ew;                /* [m] */
@@ -101,6 +112,7 @@ typedef struct {
     /* per edge */
     int32_t *lca, *bstar;      /* [m] */
     double *stretch;           /* [m] */
+    double *res;               /* [m] R_T of each off-tree edge */
     int32_t *pi;               /* [M] */
     int32_t *rank_of;          /* [m] */
 } run_t;
@@ -110,7 +122,7 @@ static void run_free(run_t *r)
     free(r->eu); free(r->ev); free(r->ew); free(r->eid_entry); free(r->is_tree); free(r->off);
     free(r->cptr); free(r->clist); free(r->depth); free(r->D);
     if (r->up) { for (int i = 0; i < r->levels; i++) free(r->up[i]); free(r->up); }
-    free(r->lca); free(r->bstar); free(r->stretch); free(r->pi); free(r->rank_of);
+    free(r->lca); free(r->bstar); free(r->stretch); free(r->res); free(r->pi); free(r->rank_of);
 }
 
 /* O1: validation and edge enumeration */
@@ -292,8 +304,9 @@ static int step_stretch(run_t *r)
     r->lca = malloc(sizeof(int32_t) * (size_t)(r->m + 1));
     r->bstar = malloc(sizeof(int32_t) * (size_t)(r->m + 1));
     r->stretch = malloc(sizeof(double) * (size_t)(r->m + 1));
-    if (!r->lca || !r->bstar || !r->stretch) return ORC_ERR_OOM;
-    for (int64_t e = 0; e < r->m; e++) { r->lca[e] = -1; r->bstar[e] = 0; r->stretch[e] = 0.0; }
+    r->res = malloc(sizeof(double) * (size_t)(r->m + 1));
+    if (!r->lca || !r->bstar || !r->stretch || !r->res) return ORC_ERR_OOM;
+    for (int64_t e = 0; e < r->m; e++) { r->lca[e] = -1; r->bstar[e] = 0; r->stretch[e] = 0.0; r->res[e] = 0.0; }
     for (int64_t j = 0; j < r->M; j++) {
         int32_t e = r->off[j], u = r->eu[e], v = r->ev[e];
         int32_t l = lca_query(r, u, v);
@@ -304,17 +317,18 @@ static int step_stretch(run_t *r)
         int32_t du = r->depth[u] - r->depth[l], dv = r->depth[v] - r->depth[l];
         int32_t b = du < dv ? du : dv;
         if (r->c < b) b = r->c;
-        r->lca[e] = l; r->bstar[e] = b; r->stretch[e] = s;
+        r->lca[e] = l; r->bstar[e] = b; r->stretch[e] = s; r->res[e] = R;
     }
     return ORC_OK;
 }
 
-/* O8: criticality order */
+/* O8: criticality order (key: the stretch, or R_T with ORC_KEY_RT) */
 static const run_t *g_sort_run;
 static int cmp_pi(const void *pa, const void *pb)
 {
     int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
-    double sa = g_sort_run->stretch[a], sb = g_sort_run->stretch[b];
+    const double *key = (g_sort_run->variant & ORC_KEY_RT) ? g_sort_run->res : g_sort_run->stretch;
+    double sa = key[a], sb = key[b];
     if (sa > sb) return -1;
     if (sa < sb) return 1;
     return (a < b) ? -1 : (a > b);
@@ -386,6 +400,13 @@ static inline int similar_now(const run_t *r, const balls_t *b, int32_t f)
            (b->stampV[x] == b->cur && b->stampU[y] == b->cur);
 }
 
+/* loosely similar (eq. cond-loose-2): an endpoint of f lies in S_u or in S_v */
+static inline int loose_now(const balls_t *b, const run_t *r, int32_t f)
+{
+    int32_t x = r->eu[f], y = r->ev[f];
+    return b->stampU[x] == b->cur || b->stampV[x] == b->cur || b->stampU[y] == b->cur || b->stampV[y] == b->cur;
+}
+
 /* O9 in the two global modes */
 static int step_greedy_global(run_t *r, int mode, int64_t K, uint8_t *rec_pass, int32_t *order,
                               int64_t *nrec_out, int32_t *passes_out, balls_t *b)
@@ -404,11 +425,33 @@ static int step_greedy_global(run_t *r, int mode, int64_t K, uint8_t *rec_pass, 
             order[nrec++] = e;
             got++;
             int32_t u = r->eu[e], v = r->ev[e], l = r->lca[e], beta = r->bstar[e];
+            const int loose = (r->variant & ORC_LOOSE) != 0;
+            if (loose) beta = r->c;  /* feGRASS: the constant BFS step c */
             b->cur++;
             int64_t nu = tree_ball(r, u, beta, b->stampU, b->cur, b->listU, b->distU);
             int64_t nv = tree_ball(r, v, beta, b->stampV, b->cur, b->listV, b->distV);
             b->ball_verts += nu + nv;
-            if (mode == ORC_MODE_BRUTE) {
+            if (loose && mode == ORC_MODE_BRUTE) {
+                for (int64_t j = i + 1; j < r->M; j++) {
+                    int32_t f = r->pi[j];
+                    if (!rec_pass[f] && loose_now(b, r, f)) marked[f] = 1;
+                }
+            } else if (loose) {
+                /* every off-tree edge incident to a vertex of S_u or S_v */
+                for (int side = 0; side < 2; side++) {
+                    const int32_t *list = side ? b->listV : b->listU;
+                    int64_t cnt = side ? nv : nu;
+                    for (int64_t q = 0; q < cnt; q++) {
+                        int32_t x = list[q];
+                        for (int64_t k = r->row_ptr[x]; k < r->row_ptr[x + 1]; k++) {
+                            int32_t f = r->eid_entry[k];
+                            b->row_entries++;
+                            if (r->is_tree[f]) continue;
+                            if (r->rank_of[f] > i && !rec_pass[f]) marked[f] = 1;
+                        }
+                    }
+                }
+            } else if (mode == ORC_MODE_BRUTE) {
                 for (int64_t j = i + 1; j < r->M; j++) {
                     int32_t f = r->pi[j];
                     if (!rec_pass[f] && similar_now(r, b, f)) marked[f] = 1;
@@ -517,17 +560,20 @@ int64_t orc_num_edges(int32_t n, const int32_t *row_ptr)
  *   depth[n]; Dlo[n], Dhi[n]: the 128-bit fixed-point root resistance; rank_of[m]
  *   info[INF_LEN]; times[4] = step 1 (tree+LCA+stretch), step 2 (sort),
  *   step 3 (grouping count), step 4 (greedy), seconds.
+ *   variant: ORC_KEY_RT and/or ORC_LOOSE (0: the method as the paper states it).
  */
 int orc_recover(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *w,
                 const int32_t *parent, double alpha, int32_t c, int64_t k_override, int32_t mode,
-                uint8_t *mask, int32_t *order, uint8_t *pass_of, double *stretch, int32_t *lca,
-                int32_t *bstar, int32_t *eu, int32_t *ev, uint8_t *is_tree, int32_t *depth,
+                int32_t variant, uint8_t *mask, int32_t *order, uint8_t *pass_of, double *stretch,
+                int32_t *lca, int32_t *bstar, int32_t *eu, int32_t *ev, uint8_t *is_tree, int32_t *depth,
                 uint64_t *Dlo, uint64_t *Dhi, int32_t *rank_of, int64_t *info, double *times)
 {
     run_t r;
     memset(&r, 0, sizeof r);
-    r.n = n; r.row_ptr = row_ptr; r.col = col; r.w = w; r.parent = parent; r.c = c;
+    r.n = n; r.row_ptr = row_ptr; r.col = col; r.w = w; r.parent = parent; r.c = c; r.variant = variant;
     if (!(alpha >= 0.0 && alpha <= 1.0) || c < 0 || mode < 0 || mode > 2) return ORC_ERR_ARG;
+    if ((variant & ~(ORC_KEY_RT | ORC_LOOSE)) || ((variant & ORC_LOOSE) && mode == ORC_MODE_SUBTASK))
+        return ORC_ERR_ARG;
     double t0 = now_s();
     int st = step_edges(&r);
     if (st == ORC_OK) st = step_tree(&r);

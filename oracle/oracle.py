@@ -12,6 +12,7 @@ SRC = os.path.join(HERE, "gss_oracle.c")
 LIB = os.path.join(HERE, "libgss_oracle.so")
 
 MODE_INDEXED, MODE_BRUTE, MODE_SUBTASK = 0, 1, 2
+KEY_RT, LOOSE = 1, 2  # variants: sort by R_T instead of the stretch; feGRASS's loose condition
 STATUS = {0: "OK", 1: "SHORT", -1: "ERR_ARG", -2: "ERR_NOT_SIMPLE", -3: "ERR_ASYM",
           -4: "ERR_WEIGHT", -5: "ERR_NOT_TREE", -6: "ERR_TREE_EDGE", -7: "ERR_RANGE",
           -9: "ERR_OOM"}
@@ -37,7 +38,7 @@ def _bind(lib):
     P = ctypes.c_void_p
     lib.orc_recover.restype = ctypes.c_int
     lib.orc_recover.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_double, ctypes.c_int32,
-                                ctypes.c_int64, ctypes.c_int32] + [P] * 15
+                                ctypes.c_int64, ctypes.c_int32, ctypes.c_int32] + [P] * 15
     lib.orc_num_edges.restype = ctypes.c_int64
     lib.orc_num_edges.argtypes = [ctypes.c_int32, P]
     return lib
@@ -84,8 +85,9 @@ def _ptr(a):
 
 
 def recover(g=None, *, n=None, row_ptr=None, col=None, w=None, parent=None, alpha=None,
-            beta=None, k_override=-1, mode=MODE_INDEXED, full=False, lib=None):
-    """Run the oracle on a synth.Graph (or raw arrays).  ``full`` also returns per-edge data."""
+            beta=None, k_override=-1, mode=MODE_INDEXED, full=False, lib=None, key_rt=False, loose=False):
+    """Run the oracle on a synth.Graph (or raw arrays).  ``full`` also returns per-edge data.
+    key_rt: order by R_T instead of the stretch; loose: feGRASS's loose similarity."""
     lib = lib or load()
     if g is not None:
         n = g.n if n is None else n
@@ -117,7 +119,8 @@ def recover(g=None, *, n=None, row_ptr=None, col=None, w=None, parent=None, alph
                         Dhi=np.zeros(n, np.uint64), rank_of=np.zeros(m + 1, np.int32))
     pe = per_edge
     st = lib.orc_recover(int(n), _ptr(row_ptr), _ptr(col), _ptr(w), _ptr(parent), float(alpha),
-                         int(beta), int(k_override), int(mode), _ptr(mask), _ptr(order),
+                         int(beta), int(k_override), int(mode),
+                         (KEY_RT if key_rt else 0) | (LOOSE if loose else 0), _ptr(mask), _ptr(order),
                          _ptr(pass_of), _ptr(pe.get("stretch")), _ptr(pe.get("lca")),
                          _ptr(pe.get("bstar")), _ptr(pe.get("eu")), _ptr(pe.get("ev")),
                          _ptr(pe.get("is_tree")), _ptr(pe.get("depth")), _ptr(pe.get("Dlo")),

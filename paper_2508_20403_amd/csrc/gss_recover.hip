@@ -143,7 +143,7 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
     const int32_t *__restrict__ off_v, const double *__restrict__ off_w,
     const VRec *__restrict__ vrec, RmqView q, int32_t scale, int32_t c, uint64_t *__restrict__ key,
     int32_t *__restrict__ lca, uint8_t *__restrict__ bst, double *__restrict__ stretch_out,
-    uint32_t *__restrict__ hist, int32_t *__restrict__ lcacnt, uint32_t *flags)
+    uint32_t *__restrict__ hist, int32_t *__restrict__ lcacnt, uint32_t *flags, int key_rt)
 {
     // the first-level key histogram (HIST only: the LDS array limits occupancy)
     __shared__ uint32_t sh[HIST ? SEL_BINS : 1];
@@ -204,8 +204,10 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
             double r;
             bool good = u128_to_double_rne(R, scale, &r);
             double s = w[t] * r;
-            uint64_t bits = (uint64_t)__double_as_longlong(s);
-            if (!good || ((bits >> 52) & 0x7ff) == 0x7ff) {
+            const uint64_t sbits = (uint64_t)__double_as_longlong(s);
+            // the sort key: the stretch, or R_T itself (positive doubles order like their bits)
+            uint64_t bits = key_rt ? (uint64_t)__double_as_longlong(r) : sbits;
+            if (!good || ((sbits >> 52) & 0x7ff) == 0x7ff) {
                 atomicOr(flags, F_RANGE);
                 bits = 1;
             }
@@ -1481,6 +1483,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         // wavefront several full takes; otherwise whole wavefronts take them too
         a.nbig = (nsmall >= (int64_t)16 * blocks * 4) ? nlocal - nsmall : nlocal;
         // about 16 chunks per wavefront; one subtask per take while the queue is short
+        // the heaviest 2 W queue entries are dealt to the W wavefronts (LPT bins)
+        a.lpt_rounds = 2;
         a.chunk = ctx->local_chunk > 0 ? ctx->local_chunk
                                        : std::max<int32_t>(1, std::min<int32_t>(64, a.nbig / (blocks * 4 * 16)));
         void *scr = ctx->alloc<uint8_t>((size_t)blocks * 4 * per_wave + 64);
@@ -1700,9 +1704,11 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     const int32_t n = t->n, G = t->G;
     const int64_t M = t->M;
     const int32_t c = prms[0].beta;
+    const int key_rt = (prms[0].flags & GSS_F_KEY_RT) ? 1 : 0;
     for (int32_t g = 1; g < G; g++)
-        if (prms[g].beta != c || prms[g].sched != prms[0].sched)
-            throw gss_error{GSS_ERR_ARG, "all graphs of a batch need the same beta and schedule"};
+        if (prms[g].beta != c || prms[g].sched != prms[0].sched ||
+            ((prms[g].flags & GSS_F_KEY_RT) ? 1 : 0) != key_rt)
+            throw gss_error{GSS_ERR_ARG, "all graphs of a batch need the same beta, schedule and sort key"};
     std::vector<int64_t> K(G), nrec(G, 0), eligible(G), want(G), mg(G);
     std::vector<int32_t> passes(G, 0);
     std::vector<int64_t> lastP(G, 0), nsubg(G, 0), largest(G, 0);
@@ -1738,12 +1744,12 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch<true>,
                          dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0, st,
                          M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
-                         stretch, hist, lcacnt, ctx->d_flags);
+                         stretch, hist, lcacnt, ctx->d_flags, key_rt);
         else
             GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch<false>,
                          dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0, st,
                          M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
-                         stretch, (uint32_t *)nullptr, lcacnt, ctx->d_flags);
+                         stretch, (uint32_t *)nullptr, lcacnt, ctx->d_flags, key_rt);
     HIP_OK(hipGetLastError());
     if (!lcacnt) {
         for (int32_t g = 0; g < G; g++) nsubg[g] = largest[g] = -1;
@@ -1918,7 +1924,7 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     if (M > 0) {
         GSS_LAUNCH(k_edge_stretch<false>, dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)),
                    dim3(RB), 0, st, M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta,
-                   key, lca, bst, (double *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr, ctx->d_flags);
+                   key, lca, bst, (double *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr, ctx->d_flags, 0);
         GSS_LAUNCH(k_edge_lca_out, dim3(grid_for(M, RB)), dim3(RB), 0, st, M, t->off_id, lca, bst,
                            lca_out, b_out);
     }

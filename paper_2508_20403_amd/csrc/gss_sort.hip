@@ -8,8 +8,9 @@
 //   2. every tile counts its pairs per bucket (binary search over the splitters in LDS),
 //   3. one workgroup turns the counts into bucket starts and per-tile output offsets,
 //   4. every tile scatters its pairs into their buckets,
-//   5. one workgroup per bucket sorts it: in LDS when it fits (about four times the
-//      mean bucket size), otherwise in place in global memory (same network, slower).
+//   5. one workgroup per bucket sorts it: in LDS when it fits (eight times the mean
+//      bucket size of about 1024 pairs), otherwise in place in global memory (same
+//      network, slower).
 // Pairs are ordered by (key, value); the callers' values are distinct, so the order is
 // total and the result does not depend on the order in which a bucket is filled.
 // The sorting network is the bitonic one in its one-direction form (the first step of
@@ -21,9 +22,9 @@
 
 #define SS_SAMPLES 4096  // largest sample (power of two)
 #define SS_TT 256        // threads of the counting and scatter kernels
-#define SS_TI 8          // pairs per thread there
+#define SS_TI 16         // pairs per thread there
 #define SS_TILE (SS_TT * SS_TI)
-#define SS_MAXB 256      // largest bucket count
+#define SS_MAXB 512      // largest bucket count
 #define SS_BT 1024       // threads of the sample and bucket kernels
 #define SS_CAP 8192      // largest bucket sorted in LDS
 
@@ -34,25 +35,23 @@ __device__ __forceinline__ bool ss_less(uint64_t ak, uint32_t av, uint64_t bk, u
 
 // One-direction bitonic sort of keys/values [0, S) by all threads of the workgroup.
 // K and V may be LDS or global memory (the same workgroup only: the barriers order the
-// steps).  N2 is the power of two at or above S; positions >= S act as +infinity and are
-// never touched, since every comparison moves the smaller pair to the lower position.
+// steps).  N2 = 2^lgN is the power of two at or above S; positions >= S act as +infinity
+// and are never touched, since every comparison moves the smaller pair to the lower
+// position.  Step (k = 2^lk, j = 2^lj): pair i joins a = (i >> lj) << (lj + 1) | (i & (j-1))
+// with its mirror in the k-block (first step of a merge, lj = lk - 1) or with a + j.
 template <typename KP, typename VP>
-__device__ void ss_network(KP K, VP V, int64_t S)
+__device__ void ss_network(KP K, VP V, int S)
 {
-    int64_t N2 = 1;
-    while (N2 < S) N2 <<= 1;
-    for (int64_t k = 2; k <= N2; k <<= 1) {
-        for (int64_t j = k >> 1; j > 0; j >>= 1) {
-            for (int64_t i = threadIdx.x; i < N2 / 2; i += blockDim.x) {
-                int64_t a, b;
-                if (j == (k >> 1)) {  // first step of the merge: mirrored pairs of a k-block
-                    const int64_t blk = i / j, r = i % j;
-                    a = blk * k + r;
-                    b = blk * k + k - 1 - r;
-                } else {  // half-cleaner with stride j
-                    a = 2 * j * (i / j) + (i % j);
-                    b = a + j;
-                }
+    int lgN = 0;
+    while ((1 << lgN) < S) lgN++;
+    const int half = (1 << lgN) >> 1;
+    for (int lk = 1; lk <= lgN; lk++) {
+        for (int lj = lk - 1; lj >= 0; lj--) {
+            const int j = 1 << lj;
+            for (int i = threadIdx.x; i < half; i += blockDim.x) {
+                const int lo = i & (j - 1);
+                const int a = ((i >> lj) << (lj + 1)) + lo;
+                const int b = (lj == lk - 1) ? a - lo + (2 * j - 1 - lo) : a + j;
                 if (b >= S) continue;
                 const uint64_t ka = K[a], kb = K[b];
                 const uint32_t va = V[a], vb = V[b];
@@ -194,16 +193,17 @@ __global__ __launch_bounds__(SS_BT) void k_ss_bucket(uint64_t *__restrict__ k, i
 {
     __shared__ uint64_t sk[SS_CAP];
     __shared__ uint32_t sv[SS_CAP];
-    const int64_t s0 = bptr[blockIdx.x], S = (int64_t)bptr[blockIdx.x + 1] - s0;
+    const int64_t s0 = bptr[blockIdx.x];
+    const int S = bptr[blockIdx.x + 1] - bptr[blockIdx.x];
     if (S <= 1) return;
     if (S <= cap) {
-        for (int64_t i = threadIdx.x; i < S; i += SS_BT) {
+        for (int i = threadIdx.x; i < S; i += SS_BT) {
             sk[i] = k[s0 + i];
             sv[i] = (uint32_t)v[s0 + i];
         }
         __syncthreads();
         ss_network(sk, sv, S);
-        for (int64_t i = threadIdx.x; i < S; i += SS_BT) {
+        for (int i = threadIdx.x; i < S; i += SS_BT) {
             k[s0 + i] = sk[i];
             v[s0 + i] = (int32_t)sv[i];
         }
@@ -219,7 +219,7 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
     if (n <= 1) return;
     if (n > sample_sort_max()) throw gss_error{GSS_ERR_ARG, "sample sort: too many pairs"};
     hipStream_t st = ctx->stream;
-    const int nb = (int)std::min<int64_t>(SS_MAXB, (n + 2047) / 2048);
+    const int nb = (int)std::min<int64_t>(SS_MAXB, (n + 1023) / 1024);  // about 1024 pairs per bucket
     const int64_t ntiles = (n + SS_TILE - 1) / SS_TILE;
     const int64_t cap = std::min<int64_t>(ctx->sort_cap > 0 ? ctx->sort_cap : SS_CAP, SS_CAP);
     int32_t *bptr = ctx->alloc<int32_t>(nb + 1);
@@ -251,4 +251,4 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
     ctx->free(bptr);
 }
 
-int64_t sample_sort_max() { return (int64_t)SS_MAXB * 2048; }
+int64_t sample_sort_max() { return (int64_t)SS_MAXB * 1024; }

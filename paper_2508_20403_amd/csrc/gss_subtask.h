@@ -17,6 +17,7 @@ struct SubtaskArgs {
     int32_t nbig;                 // wavefront subtasks at the front of the queue
     int32_t local_max;            // size limit of queued subtasks (<= GSS_LOCAL_CAP)
     int32_t chunk;                // queue entries taken per atomic on the head
+    int32_t lpt_rounds;           // queue entries dealt to each wavefront before pulling
     unsigned int *queue_head;     // atomic pop counters: [0] wavefront part, [1] lane part
     const int32_t *ancU, *ancV;   // [(c+1) * P] ancestor chains per rank
     const int32_t *rdu, *rdv;     // depths of the endpoints per rank

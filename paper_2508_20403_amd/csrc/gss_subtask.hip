@@ -47,21 +47,19 @@ __device__ __forceinline__ void load_desc(Desc<C> &d, int64_t P, int32_t p, cons
 }
 
 // is vertex x (chain ax, depth dx) within `beta` tree hops of vertex u (chain au, depth du)?
+// anc_i(x) = anc_j(u) can hold only for j - i = du - dx; every (i, j) pair is tested with
+// constant indices, so the chains stay in registers (a chain indexed by a computed j would
+// have to live in private memory)
 template <int C>
 __device__ __forceinline__ bool in_ball(const int32_t *ax, int32_t dx, const int32_t *au, int32_t du, int beta)
 {
+    const int d = du - dx;
     bool hit = false;
 #pragma unroll
-    for (int i = 0; i <= C; i++) {
-        int j = du - dx + i;
-        if (i <= beta && j >= 0 && i + j <= beta) {
-            int32_t aj = au[0];
+    for (int i = 0; i <= C; i++)
 #pragma unroll
-            for (int q = 1; q <= C; q++)
-                if (q == j) aj = au[q];
-            hit |= (ax[i] == aj) && (ax[i] >= 0);
-        }
-    }
+        for (int j = 0; j <= C; j++)
+            hit |= (j - i == d) & (i + j <= beta) & (ax[i] == au[j]) & (ax[i] >= 0);
     return hit;
 }
 
@@ -74,6 +72,34 @@ __device__ __forceinline__ bool strictly_similar(const Desc<C> &t, const Desc<C>
     bool o1 = in_ball<C>(t.au, t.du, m.au, m.du, b) && in_ball<C>(t.av, t.dv, m.av, m.dv, b);
     bool o2 = in_ball<C>(t.au, t.du, m.av, m.dv, b) && in_ball<C>(t.av, t.dv, m.au, m.du, b);
     return o1 || o2;
+}
+
+// field-by-field copies to and from the candidate scratch (a whole-struct copy of a
+// global Desc went through private memory)
+template <int C>
+__device__ __forceinline__ void read_desc(Desc<C> &d, const Desc<C> *__restrict__ src)
+{
+#pragma unroll
+    for (int i = 0; i <= C; i++) {
+        d.au[i] = src->au[i];
+        d.av[i] = src->av[i];
+    }
+    d.du = src->du;
+    d.dv = src->dv;
+    d.beta = src->beta;
+}
+
+template <int C>
+__device__ __forceinline__ void write_desc(Desc<C> *__restrict__ dst, const Desc<C> &d)
+{
+#pragma unroll
+    for (int i = 0; i <= C; i++) {
+        dst->au[i] = d.au[i];
+        dst->av[i] = d.av[i];
+    }
+    dst->du = d.du;
+    dst->dv = d.dv;
+    dst->beta = d.beta;
 }
 
 template <int C>
@@ -114,8 +140,58 @@ __device__ __forceinline__ void lane_subtask(const SubtaskArgs &a, int32_t g0, i
     }
 }
 
-// persistent kernel: first the larger subtasks, one wavefront each, pulled from the front
-// of the work queue; then the small ones, 64 at a time, one per lane
+// greedy of one wavefront-sized subtask (queue entry qi) by one wavefront
+template <int C>
+__device__ __forceinline__ void wave_subtask(const SubtaskArgs &a, int32_t qi, Desc<C> *cand)
+{
+    const int lane = lane_id();
+    const int32_t s = a.queue[qi];
+    const uint64_t t0 = clock64();
+    const int32_t g0 = a.sub_ptr[s], g1 = a.sub_ptr[s + 1];
+    int32_t ncand = 0;
+    for (int32_t c0 = g0; c0 < g1; c0 += GSS_WAVE) {
+        const int32_t gi = c0 + lane;
+        const bool valid = gi < g1;
+        const int32_t p = valid ? a.grp[gi] : 0;
+        Desc<C> me;  // loaded for every lane (p = 0 on idle lanes, any valid rank)
+        load_desc<C>(me, a.P, p, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
+        // against candidates of earlier chunks
+        bool marked = false;
+        for (int32_t k = 0; k < ncand; k++) {
+            Desc<C> m;
+            read_desc<C>(m, cand + k);
+            marked |= valid && strictly_similar<C>(me, m);
+        }
+        // in-chunk greedy in rank order
+        uint64_t pending = __ballot(valid && !marked);
+        uint64_t recovered = 0;
+        while (pending) {
+            const int i = __ffsll((long long)pending) - 1;
+            Desc<C> m = shfl_desc<C>(me, i);
+            const bool hit = valid && lane > i && strictly_similar<C>(me, m);
+            const uint64_t hits = __ballot(hit);
+            recovered |= 1ull << i;
+            pending &= ~((1ull << i) | hits);
+        }
+        const bool is_cand = (recovered >> lane) & 1ull;
+        if (valid) a.state[p] = is_cand ? ST_CAND_ : ST_MARK_;
+        // append this chunk's candidates (rank order) to the candidate list
+        const int before = __popcll(recovered & lanemask_lt());
+        if (is_cand && ncand + before < a.local_max) write_desc<C>(cand + ncand + before, me);
+        ncand += __popcll(recovered);
+        __threadfence_block();
+    }
+    const uint64_t t1 = clock64();
+    if (lane == 0 && a.cycles) a.cycles[s] = t1 - t0;
+}
+
+// persistent kernel: first the larger subtasks, one wavefront each, then the small ones,
+// one per lane.  The queue is ordered by predicted cost, largest first.  Its first
+// lpt_rounds * W entries (W = wavefronts of the grid) are dealt to the wavefronts in
+// boustrophedon order before any is pulled: round r gives entry r W + w to wavefront w
+// on even rounds and entry (r + 1) W - 1 - w on odd ones, so every wavefront starts with
+// a balanced share of the heaviest subtasks (longest-processing-time bins) without
+// touching the shared head; the rest is pulled from the head, `chunk` entries at a time.
 template <int C>
 __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
 {
@@ -124,54 +200,22 @@ __global__ __launch_bounds__(256) void k_local_recover(SubtaskArgs a)
     // that stay in this CU's caches
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GSS_WAVE;
+    const int64_t W = (int64_t)gridDim.x * blockDim.x / GSS_WAVE;
     Desc<C> *cand = (Desc<C> *)a.cand_scratch + gw * a.local_max;
+    for (int r = 0; r < a.lpt_rounds; r++) {
+        const int64_t qi = (r & 1) ? (int64_t)(r + 1) * W - 1 - gw : (int64_t)r * W + gw;
+        if (qi < a.nbig) wave_subtask<C>(a, (int32_t)qi, cand);
+    }
+    const int64_t dealt = (int64_t)a.lpt_rounds * W;
     // queue entries are taken `chunk` at a time, so the shared head sees one atomic per
     // chunk rather than one per subtask
     for (;;) {
-        int32_t q0 = 0;
-        if (lane == 0) q0 = (int32_t)atomicAdd(&a.queue_head[0], (unsigned)a.chunk);
+        int64_t q0 = 0;
+        if (lane == 0) q0 = dealt + (int64_t)atomicAdd(&a.queue_head[0], (unsigned)a.chunk);
         q0 = __shfl(q0, 0, GSS_WAVE);
         if (q0 >= a.nbig) break;
-        const int32_t q1 = (q0 + a.chunk < a.nbig) ? q0 + a.chunk : a.nbig;
-        for (int32_t qi = q0; qi < q1; qi++) {
-            const int32_t s = a.queue[qi];
-            const uint64_t t0 = clock64();
-            const int32_t g0 = a.sub_ptr[s], g1 = a.sub_ptr[s + 1];
-            int32_t ncand = 0;
-            for (int32_t c0 = g0; c0 < g1; c0 += GSS_WAVE) {
-                const int32_t gi = c0 + lane;
-                const bool valid = gi < g1;
-                const int32_t p = valid ? a.grp[gi] : 0;
-                Desc<C> me;
-                if (valid) load_desc<C>(me, a.P, p, a.ancU, a.ancV, a.rdu, a.rdv, a.rb);
-                // against candidates of earlier chunks
-                bool marked = false;
-                for (int32_t k = 0; k < ncand; k++) {
-                    const Desc<C> m = cand[k];
-                    marked |= valid && strictly_similar<C>(me, m);
-                }
-                // in-chunk greedy in rank order
-                uint64_t pending = __ballot(valid && !marked);
-                uint64_t recovered = 0;
-                while (pending) {
-                    const int i = __ffsll((long long)pending) - 1;
-                    Desc<C> m = shfl_desc<C>(me, i);
-                    const bool hit = valid && lane > i && strictly_similar<C>(me, m);
-                    const uint64_t hits = __ballot(hit);
-                    recovered |= 1ull << i;
-                    pending &= ~((1ull << i) | hits);
-                }
-                const bool is_cand = (recovered >> lane) & 1ull;
-                if (valid) a.state[p] = is_cand ? ST_CAND_ : ST_MARK_;
-                // append this chunk's candidates (rank order) to the candidate list
-                const int before = __popcll(recovered & lanemask_lt());
-                if (is_cand && ncand + before < a.local_max) cand[ncand + before] = me;
-                ncand += __popcll(recovered);
-                __threadfence_block();
-            }
-            const uint64_t t1 = clock64();
-            if (lane == 0 && a.cycles) a.cycles[s] = t1 - t0;
-        }
+        const int64_t q1 = (q0 + a.chunk < a.nbig) ? q0 + a.chunk : a.nbig;
+        for (int64_t qi = q0; qi < q1; qi++) wave_subtask<C>(a, (int32_t)qi, cand);
     }
     // small subtasks: 64 queue entries per take, one per lane
     for (;;) {

@@ -33,6 +33,7 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_ctx_set_rank_capacity", "gss_tree_rank_attempts", "gss_ctx_set_sort"]
 GSS_F_RECORD = 2
 GSS_F_STATS = 4
+GSS_F_KEY_RT = 8
 NFEAT = 12
 COSTMODEL_FLOATS = 5081
 COSTMODEL_PARAMS = 5057
@@ -327,7 +328,7 @@ class Tree:
         return int(k)
 
     def recover(self, alpha, beta, k_override=-1, sched=SCHED_EDGECOUNT, mask_tree=False,
-                want_order=True, want_stretch=False, out=None, record=False, stats=False):
+                want_order=True, want_stretch=False, out=None, record=False, stats=False, key_rt=False):
         """Runs gss_recover.  Returns (status, mask, order, stretch, info dict)."""
         dev = self.arrays[3].device
         k = self.target_count(alpha, k_override)
@@ -338,7 +339,7 @@ class Tree:
         else:
             mask, order, stretch = out
         flags = (GSS_F_MASK_TREE if mask_tree else 0) | (GSS_F_RECORD if record else 0) | \
-            (GSS_F_STATS if stats else 0)
+            (GSS_F_STATS if stats else 0) | (GSS_F_KEY_RT if key_rt else 0)
         p = Params(float(alpha), int(beta), int(sched), int(k_override), flags, 0)
         info = Info()
         st = self.ctx.lib.gss_recover(self.ctx.handle, self.handle, ctypes.byref(p), _ptr(mask),

@@ -210,3 +210,57 @@ def pcg_iterations(g, keep_mask, tol=1e-6, seed=0, maxiter=5000):
 
 def log_uniform(rng, lo, hi, n):
     return np.exp(rng.uniform(math.log(lo), math.log(hi), n))
+
+
+def greedy_brute_variant(g, c, k, key_rt=False, loose=False):
+    """The greedy with the two variants, from the definitions, all-pairs.
+
+    key_rt: edges ordered by the exact tree-path resistance R_T (rounded once), ties by
+    id, instead of the stretch.  loose: feGRASS's condition (eq. cond-loose-2): a later
+    edge is marked when either endpoint is within the constant c tree hops of u or of v.
+    Returns (order, passes)."""
+    eu, ev, ew, is_tree = edges_of(g)
+    dep = depth_bfs(g)
+    key, bstar = {}, {}
+    for e in np.flatnonzero(~is_tree):
+        a, b = int(eu[e]), int(ev[e])
+        R, l = exact_path_resistance(g, a, b)
+        key[int(e)] = float(R) if key_rt else ew[e] * float(R)
+        bstar[int(e)] = min(int(dep[a] - dep[l]), int(dep[b] - dep[l]), c)
+    off = sorted(key, key=lambda e: (-key[e], e))
+    adj = tree_adj(g)
+    cache = {}
+
+    def dist(src):
+        if src not in cache:
+            cache[src] = tree_dist_from(adj, src)
+        return cache[src]
+
+    recovered, rec_set, passes = [], set(), 0
+    while len(recovered) < k:
+        marked, got = set(), 0
+        for i, e in enumerate(off):
+            if len(recovered) == k:
+                break
+            if e in rec_set or e in marked:
+                continue
+            recovered.append(e)
+            rec_set.add(e)
+            got += 1
+            u, v = int(eu[e]), int(ev[e])
+            du, dv = dist(u), dist(v)
+            r = c if loose else bstar[e]
+            for f in off[i + 1:]:
+                if f in rec_set:
+                    continue
+                x, y = int(eu[f]), int(ev[f])
+                if loose:
+                    hit = min(du[x], dv[x]) <= r or min(du[y], dv[y]) <= r
+                else:
+                    hit = (du[x] <= r and dv[y] <= r) or (dv[x] <= r and du[y] <= r)
+                if hit:
+                    marked.add(f)
+        if got == 0:
+            break
+        passes += 1
+    return recovered, passes

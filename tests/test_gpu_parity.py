@@ -140,3 +140,21 @@ def test_rank_capacity_retry_matches_oracle(gpu_ctx, make):
                    info=info)
         assert_same_recovery(gpu, orc)
         tree.free()
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_rt_key_matches_oracle(gpu_ctx, name, make):
+    """GSS_F_KEY_RT (order by R_T alone): mask, order and stretch bit for bit against the
+    oracle's R_T-key variant, including forced extra passes and short results."""
+    g = make(3)
+    for beta in (1, 2):
+        for k in (-1, 7, g.m):
+            gpu = run_gpu(gpu_ctx, g, beta=beta, k_override=k, key_rt=True)
+            orc = run_oracle(g, beta=beta, k_override=k, key_rt=True)
+            assert_same_recovery(gpu, orc)
+
+
+@pytest.mark.parametrize("name", ["grid3d_32", "rmat14"])
+def test_rt_key_named_workloads(gpu_ctx, name):
+    g = synth.config(name)
+    assert_same_recovery(run_gpu(gpu_ctx, g, key_rt=True), run_oracle(g, key_rt=True))
