@@ -3,26 +3,29 @@
 // (Step 3) and the subtask work queue.  These sorts hold a few hundred thousand pairs,
 // too few for a radix sort to reach bandwidth: every radix pass is a launch bounded by
 // its latency.  A sample sort needs five launches whatever the key width:
-//   1. one workgroup sorts a stratified sample of the pairs in LDS and keeps nb - 1
-//      evenly spaced splitters,
-//   2. every tile counts its pairs per bucket (binary search over the splitters in LDS),
-//   3. one workgroup turns the counts into bucket starts and per-tile output offsets,
+//   1. one workgroup sorts a stratified sample of the pairs and keeps nb - 1 evenly
+//      spaced splitters,
+//   2. every tile counts its pairs per bucket (binary search over the splitters in LDS)
+//      into a bucket-major count matrix,
+//   3. an exclusive scan of that matrix gives every (bucket, tile) its output offset and
+//      every bucket its start,
 //   4. every tile scatters its pairs into their buckets,
-//   5. one workgroup per bucket sorts it: in LDS when it fits (eight times the mean
-//      bucket size of about 1024 pairs), otherwise in place in global memory (same
-//      network, slower).
+//   5. one workgroup per bucket sorts it in registers when it holds at most eight times
+//      the mean bucket size of about 1024 pairs, otherwise in place in global memory.
 // Pairs are ordered by (key, value); the callers' values are distinct, so the order is
 // total and the result does not depend on the order in which a bucket is filled.
 // The sorting network is the bitonic one in its one-direction form (the first step of
-// every merge compares mirrored positions), so sizes need not be powers of two:
-// comparisons that reach past the end are skipped.
+// every merge compares mirrored positions, so every comparison puts the smaller pair at
+// the lower position).  In registers, thread t of the 1024 holds positions r * 1024 + t:
+// partners closer than a wavefront are exchanged by lane shuffles, partners 1024 or more
+// apart sit in the same thread, and only the remaining steps go through LDS.
 #include <algorithm>
 
 #include "gss_impl.h"
 
 #define SS_SAMPLES 4096  // largest sample (power of two)
 #define SS_TT 256        // threads of the counting and scatter kernels
-#define SS_TI 16         // pairs per thread there
+#define SS_TI 4          // pairs per thread there
 #define SS_TILE (SS_TT * SS_TI)
 #define SS_MAXB 512      // largest bucket count
 #define SS_BT 1024       // threads of the sample and bucket kernels
@@ -67,6 +70,104 @@ __device__ void ss_network(KP K, VP V, int S)
     }
 }
 
+// compare-exchange with a partner: the lower position keeps the smaller pair
+__device__ __forceinline__ void ss_keep(uint64_t &k, uint32_t &v, uint64_t pk, uint32_t pv, bool lower)
+{
+    const bool take = lower ? ss_less(pk, pv, k, v) : ss_less(k, v, pk, pv);
+    if (take) {
+        k = pk;
+        v = pv;
+    }
+}
+
+__device__ __forceinline__ uint64_t ss_shfl_xor64(uint64_t x, int m)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)x, m, GSS_WAVE), hi = __shfl_xor((uint32_t)(x >> 32), m, GSS_WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Sorts the 1024 * E pairs held in registers by a workgroup of 1024 threads (thread t
+// holds positions r * 1024 + t).  ek/ev: LDS of 1024 * E entries for the steps whose
+// partners are in other wavefronts.
+template <int E>
+__device__ void ss_reg_sort(uint64_t (&k)[E], uint32_t (&v)[E], uint64_t *ek, uint32_t *ev)
+{
+    constexpr int LGE = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : 3;
+    constexpr int LG = 10 + LGE;
+    const int t = threadIdx.x;
+    for (int lk = 1; lk <= LG; lk++) {
+        for (int lj = lk - 1; lj >= 0; lj--) {
+            // partner = position ^ m: the mirror in the 2^lk block, or the position 2^lj away
+            const int m = (lj == lk - 1) ? (2 << lj) - 1 : 1 << lj;
+            if (m < GSS_WAVE) {
+#pragma unroll
+                for (int r = 0; r < E; r++) {
+                    const uint64_t pk = ss_shfl_xor64(k[r], m);
+                    const uint32_t pv = __shfl_xor(v[r], m, GSS_WAVE);
+                    ss_keep(k[r], v[r], pk, pv, (t ^ m) > t);
+                }
+            } else if ((m & 1023) == 0) {  // same thread: registers r and r ^ (m >> 10)
+                const int rm = m >> 10;
+#pragma unroll
+                for (int r = 0; r < E; r++) {
+                    if (r & rm) continue;
+                    const int q = r ^ rm;  // q > r: position q * 1024 + t is the higher one
+                    if (ss_less(k[q], v[q], k[r], v[r])) {
+                        const uint64_t tk = k[r];
+                        const uint32_t tv = v[r];
+                        k[r] = k[q];
+                        v[r] = v[q];
+                        k[q] = tk;
+                        v[q] = tv;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; r++) {
+                    ek[r * 1024 + t] = k[r];
+                    ev[r * 1024 + t] = v[r];
+                }
+                __syncthreads();
+                uint64_t pk[E];
+                uint32_t pv[E];
+#pragma unroll
+                for (int r = 0; r < E; r++) {
+                    const int q = (r * 1024 + t) ^ m;
+                    pk[r] = ek[q];
+                    pv[r] = ev[q];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < E; r++) ss_keep(k[r], v[r], pk[r], pv[r], (r * 1024 + t) < ((r * 1024 + t) ^ m));
+            }
+        }
+    }
+}
+
+// loads S <= 1024 E pairs (padded with the largest pair), sorts them in registers and
+// stores them back
+template <int E>
+__device__ void ss_sort_run(uint64_t *__restrict__ k, int32_t *__restrict__ v, int S, uint64_t *ek, uint32_t *ev)
+{
+    uint64_t kk[E];
+    uint32_t vv[E];
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const int p = r * 1024 + (int)threadIdx.x;
+        kk[r] = p < S ? k[p] : ~0ull;
+        vv[r] = p < S ? (uint32_t)v[p] : ~0u;
+    }
+    ss_reg_sort<E>(kk, vv, ek, ev);
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const int p = r * 1024 + (int)threadIdx.x;
+        if (p < S) {
+            k[p] = kk[r];
+            v[p] = (int32_t)vv[r];
+        }
+    }
+}
+
 // bucket of (k, v): the number of splitters at or below it (splitters ascending)
 __device__ __forceinline__ int ss_bucket(uint64_t k, uint32_t v, const uint64_t *spk, const uint32_t *spv,
                                          int nsp)
@@ -80,28 +181,49 @@ __device__ __forceinline__ int ss_bucket(uint64_t k, uint32_t v, const uint64_t 
     return lo;
 }
 
-// 1. the sample: ns strata of equal length, one pair from each at a hashed offset;
-// splitter b (b < nb - 1) is sample (b + 1) * ns / nb of the sorted sample
-__global__ __launch_bounds__(SS_BT) void k_ss_sample(const uint64_t *__restrict__ k, const int32_t *__restrict__ v,
-                                                    int64_t n, int ns, int nb, uint64_t *__restrict__ spk,
-                                                    uint32_t *__restrict__ spv)
+// 1. the sample: ns = 1024 E strata of equal length, one pair from each at a hashed
+// offset, sorted in registers; splitter b (b < nb - 1) is sample (b + 1) * ns / nb
+template <int E>
+__device__ void ss_sample_run(const uint64_t *__restrict__ k, const int32_t *__restrict__ v, int64_t n, int nb,
+                              uint64_t *__restrict__ spk, uint32_t *__restrict__ spv, uint64_t *ek, uint32_t *ev)
 {
-    __shared__ uint64_t sk[SS_SAMPLES];
-    __shared__ uint32_t sv[SS_SAMPLES];
-    for (int i = threadIdx.x; i < ns; i += SS_BT) {
-        const int64_t lo = (int64_t)i * n / ns, hi = (int64_t)(i + 1) * n / ns;
+    constexpr int NS = 1024 * E;
+    uint64_t kk[E];
+    uint32_t vv[E];
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const int i = r * 1024 + (int)threadIdx.x;
+        const int64_t lo = (int64_t)i * n / NS, hi = (int64_t)(i + 1) * n / NS;
         int64_t p = lo;
-        if (hi > lo) p = lo + (int64_t)(mix64(0x9E3779B97F4A7C15ull * (uint64_t)(i + 1)) % (uint64_t)(hi - lo));
+        if (hi > lo) p = lo + (int64_t)(mix32(0x9E3779B9u * (uint32_t)(i + 1)) % (uint32_t)(hi - lo));
         if (p >= n) p = n - 1;
-        sk[i] = k[p];
-        sv[i] = (uint32_t)v[p];
+        kk[r] = k[p];
+        vv[r] = (uint32_t)v[p];
+    }
+    ss_reg_sort<E>(kk, vv, ek, ev);
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        ek[r * 1024 + threadIdx.x] = kk[r];
+        ev[r * 1024 + threadIdx.x] = vv[r];
     }
     __syncthreads();
-    ss_network(sk, sv, ns);
     for (int b = threadIdx.x; b < nb - 1; b += SS_BT) {
-        const int s = (int)((int64_t)(b + 1) * ns / nb);
-        spk[b] = sk[s];
-        spv[b] = sv[s];
+        const int q = (int)((int64_t)(b + 1) * NS / nb);
+        spk[b] = ek[q];
+        spv[b] = ev[q];
+    }
+}
+
+__global__ __launch_bounds__(SS_BT) void k_ss_sample(const uint64_t *__restrict__ k, const int32_t *__restrict__ v,
+                                                    int64_t n, int se, int nb, uint64_t *__restrict__ spk,
+                                                    uint32_t *__restrict__ spv)
+{
+    __shared__ uint64_t ek[SS_SAMPLES];
+    __shared__ uint32_t ev[SS_SAMPLES];
+    switch (se) {
+    case 1: ss_sample_run<1>(k, v, n, nb, spk, spv, ek, ev); break;
+    case 2: ss_sample_run<2>(k, v, n, nb, spk, spv, ek, ev); break;
+    default: ss_sample_run<4>(k, v, n, nb, spk, spv, ek, ev); break;
     }
 }
 
@@ -114,7 +236,7 @@ __device__ __forceinline__ void ss_load_splitters(const uint64_t *__restrict__ s
     }
 }
 
-// 2. per tile and bucket: hist[tile * nb + b]
+// 2. per tile and bucket, bucket-major: hist[b * ntiles + tile]
 __global__ __launch_bounds__(SS_TT) void k_ss_count(const uint64_t *__restrict__ k, const int32_t *__restrict__ v,
                                                    int64_t n, int nb, const uint64_t *__restrict__ spk,
                                                    const uint32_t *__restrict__ spv, int32_t *__restrict__ hist)
@@ -132,32 +254,7 @@ __global__ __launch_bounds__(SS_TT) void k_ss_count(const uint64_t *__restrict__
         if (e < n) atomicAdd(&cnt[ss_bucket(k[e], (uint32_t)v[e], sk, sv, nb - 1)], 1);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += SS_TT) hist[(int64_t)blockIdx.x * nb + b] = cnt[b];
-}
-
-// 3. offsets: hist[t][b] becomes the output position of tile t's first pair of bucket b
-// (bucket-major order); bptr[b] = start of bucket b, bptr[nb] = n.  One thread per bucket
-// walks the tiles.
-__global__ __launch_bounds__(SS_MAXB) void k_ss_offsets(int32_t *__restrict__ hist, int64_t ntiles, int nb,
-                                                       int32_t *__restrict__ bptr)
-{
-    __shared__ int32_t lds[SS_MAXB / GSS_WAVE + 1];
-    const int b = threadIdx.x;
-    int32_t run = 0;
-    if (b < nb) {
-        for (int64_t t = 0; t < ntiles; t++) {
-            const int32_t c = hist[t * nb + b];
-            hist[t * nb + b] = run;
-            run += c;
-        }
-    }
-    int32_t total;
-    const int32_t start = block_exclusive_scan<int32_t>(b < nb ? run : 0, lds, &total);
-    if (b < nb) {
-        bptr[b] = start;
-        for (int64_t t = 0; t < ntiles; t++) hist[t * nb + b] += start;
-    }
-    if (b == 0) bptr[nb] = total;
+    for (int b = threadIdx.x; b < nb; b += SS_TT) hist[(int64_t)b * gridDim.x + blockIdx.x] = cnt[b];
 }
 
 // 4. scatter into buckets (slot order inside a bucket is arbitrary: step 5 sorts it)
@@ -171,7 +268,8 @@ __global__ __launch_bounds__(SS_TT) void k_ss_scatter(const uint64_t *__restrict
     __shared__ uint32_t sv[SS_MAXB];
     __shared__ int32_t cur[SS_MAXB];
     ss_load_splitters(spk, spv, nb - 1, sk, sv);
-    for (int b = threadIdx.x; b < nb; b += SS_TT) cur[b] = hist[(int64_t)blockIdx.x * nb + b];
+    // the scanned counts: output position of this tile's first pair of bucket b
+    for (int b = threadIdx.x; b < nb; b += SS_TT) cur[b] = hist[(int64_t)b * gridDim.x + blockIdx.x];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SS_TILE;
 #pragma unroll
@@ -187,27 +285,25 @@ __global__ __launch_bounds__(SS_TT) void k_ss_scatter(const uint64_t *__restrict
     }
 }
 
-// 5. one workgroup per bucket
+// 5. one workgroup per bucket: bucket b is [hist[b * ntiles], hist[(b + 1) * ntiles]) of
+// the scanned counts (the last one ends at n)
 __global__ __launch_bounds__(SS_BT) void k_ss_bucket(uint64_t *__restrict__ k, int32_t *__restrict__ v,
-                                                    const int32_t *__restrict__ bptr, int64_t cap)
+                                                    const int32_t *__restrict__ hist, int64_t ntiles, int nb,
+                                                    int64_t n, int64_t cap)
 {
-    __shared__ uint64_t sk[SS_CAP];
-    __shared__ uint32_t sv[SS_CAP];
-    const int64_t s0 = bptr[blockIdx.x];
-    const int S = bptr[blockIdx.x + 1] - bptr[blockIdx.x];
+    __shared__ uint64_t ek[SS_CAP];
+    __shared__ uint32_t ev[SS_CAP];
+    const int b = blockIdx.x;
+    const int64_t s0 = hist[(int64_t)b * ntiles];
+    const int64_t s1 = (b + 1 < nb) ? hist[(int64_t)(b + 1) * ntiles] : n;
+    const int S = (int)(s1 - s0);
     if (S <= 1) return;
     if (S <= cap) {
-        for (int i = threadIdx.x; i < S; i += SS_BT) {
-            sk[i] = k[s0 + i];
-            sv[i] = (uint32_t)v[s0 + i];
-        }
-        __syncthreads();
-        ss_network(sk, sv, S);
-        for (int i = threadIdx.x; i < S; i += SS_BT) {
-            k[s0 + i] = sk[i];
-            v[s0 + i] = (int32_t)sv[i];
-        }
-    } else {  // a bucket far above its expected size: the same network in global memory
+        if (S <= 1024) ss_sort_run<1>(k + s0, v + s0, S, ek, ev);
+        else if (S <= 2048) ss_sort_run<2>(k + s0, v + s0, S, ek, ev);
+        else if (S <= 4096) ss_sort_run<4>(k + s0, v + s0, S, ek, ev);
+        else ss_sort_run<8>(k + s0, v + s0, S, ek, ev);
+    } else {  // a bucket far above its expected size: the LDS network in global memory
         ss_network(k + s0, (uint32_t *)(v + s0), S);
     }
 }
@@ -221,34 +317,32 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
     hipStream_t st = ctx->stream;
     const int nb = (int)std::min<int64_t>(SS_MAXB, (n + 1023) / 1024);  // about 1024 pairs per bucket
     const int64_t ntiles = (n + SS_TILE - 1) / SS_TILE;
+    // the LDS limit, or a smaller one set for tests (buckets above it take the global path)
     const int64_t cap = std::min<int64_t>(ctx->sort_cap > 0 ? ctx->sort_cap : SS_CAP, SS_CAP);
-    int32_t *bptr = ctx->alloc<int32_t>(nb + 1);
-    if (nb == 1) {
-        // one bucket: sort in place
-        int32_t h[2] = {0, (int32_t)n};
-        ctx->h2d(bptr, h, sizeof h);
-        GSS_LAUNCH_B(24 * n, k_ss_bucket, dim3(1), dim3(SS_BT), 0, st, k, v, bptr, cap);
-        ctx->free(bptr);
+    int32_t *hist = ctx->alloc<int32_t>(ntiles * nb + 1);
+    if (nb == 1) {  // one bucket: sort in place
+        int32_t h = 0;
+        ctx->h2d(hist, &h, sizeof h);
+        GSS_LAUNCH_B(24 * n, k_ss_bucket, dim3(1), dim3(SS_BT), 0, st, k, v, hist, (int64_t)1, 1, n, cap);
+        ctx->free(hist);
         return;
     }
-    int ns = 32;
-    while (ns < 16 * nb && ns < SS_SAMPLES) ns <<= 1;
+    // about 8 samples per bucket, at least 1024
+    const int se = nb <= 128 ? 1 : nb <= 256 ? 2 : 4;
     uint64_t *spk = ctx->alloc<uint64_t>(nb);
     uint32_t *spv = ctx->alloc<uint32_t>(nb);
-    int32_t *hist = ctx->alloc<int32_t>(ntiles * nb);
-    GSS_LAUNCH_B(12 * (int64_t)ns, k_ss_sample, dim3(1), dim3(SS_BT), 0, st, k, v, n, ns, nb, spk, spv);
+    GSS_LAUNCH_B(12 * 1024 * (int64_t)se, k_ss_sample, dim3(1), dim3(SS_BT), 0, st, k, v, n, se, nb, spk, spv);
     GSS_LAUNCH_B(12 * n, k_ss_count, dim3((unsigned)ntiles), dim3(SS_TT), 0, st, k, v, n, nb, spk, spv, hist);
-    GSS_LAUNCH(k_ss_offsets, dim3(1), dim3(SS_MAXB), 0, st, hist, ntiles, nb, bptr);
+    scan_exclusive_i32_dev(ctx, hist, ntiles * nb, ctx->d_counters + 11);
     GSS_LAUNCH_B(24 * n, k_ss_scatter, dim3((unsigned)ntiles), dim3(SS_TT), 0, st, k, v, n, nb, spk, spv, hist, k2,
                  v2);
-    GSS_LAUNCH_B(24 * n, k_ss_bucket, dim3(nb), dim3(SS_BT), 0, st, k2, v2, bptr, cap);
+    GSS_LAUNCH_B(24 * n, k_ss_bucket, dim3(nb), dim3(SS_BT), 0, st, k2, v2, hist, ntiles, nb, n, cap);
     HIP_OK(hipGetLastError());
     std::swap(k, k2);
     std::swap(v, v2);
     ctx->free(spk);
     ctx->free(spv);
     ctx->free(hist);
-    ctx->free(bptr);
 }
 
 int64_t sample_sort_max() { return (int64_t)SS_MAXB * 1024; }

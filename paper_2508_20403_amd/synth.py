@@ -31,7 +31,7 @@ import scipy.sparse as sp
 import scipy.sparse.csgraph as csg
 
 __all__ = [
-    "Graph", "grid", "rmat", "rgg", "random_connected", "path_graph", "star_graph",
+    "Graph", "grid", "rmat", "rgg", "random_connected", "path_graph", "star_graph", "skewed_cost",
     "from_edges", "max_spanning_tree_parent", "config", "batch_config", "CONFIGS",
     "k_of", "data_dir",
 ]
@@ -398,6 +398,55 @@ def star_graph(n, extra, seed=0, alpha=0.5, beta=2):
     w = np.exp(rng.uniform(0.0, math.log(100.0), len(x)))
     parent = np.concatenate([[-1], np.zeros(n - 1)]).astype(np.int32)
     return from_edges(n, x, y, w, alpha, beta, f"star{n}", parent=parent, root=0)
+
+
+def skewed_cost(nheavy, nlight, side=16, seed=0, beta=2, name=None):
+    """A forest of LCA gadgets under one root whose subtasks all hold side^2 off-tree
+    edges but cost very differently in the greedy, so a queue ordered by edge count
+    cannot tell them apart.
+
+    light gadget: LCA x with children a and b, each with `side` leaves; the off-tree
+      edges join every leaf of a to every leaf of b (beta* = 2: the first recovered edge
+      marks all the others, one candidate per subtask);
+    heavy gadget: LCA y with `side` children, each with `side` leaves; the off-tree edges
+      join y to every grandchild (beta* = 0: nothing is marked, every edge is a candidate).
+    Heavy gadgets get the highest vertex ids.  Weights are drawn from [1, 10); the tree is
+    given (not a maximum spanning tree), rooted at vertex 0.  K should be the number of
+    candidates, nlight + side^2 * nheavy, so that one pass over every edge recovers it."""
+    rng = np.random.default_rng(seed)
+    S = side * side
+    nl_v = 3 + 2 * side
+    nh_v = 1 + side + S
+    n = 1 + nlight * nl_v + nheavy * nh_v
+    parent = np.full(n, -1, dtype=np.int64)
+    eu, ev = [], []
+    base = 1
+    for _ in range(nlight):
+        x, a, b = base, base + 1, base + 2
+        la = np.arange(base + 3, base + 3 + side)
+        lb = la + side
+        parent[[x, a, b]] = [0, x, x]
+        parent[la] = a
+        parent[lb] = b
+        eu.append(np.repeat(la, side))
+        ev.append(np.tile(lb, side))
+        base += nl_v
+    for _ in range(nheavy):
+        y = base
+        ch = np.arange(base + 1, base + 1 + side)
+        gc = np.arange(base + 1 + side, base + 1 + side + S)
+        parent[y] = 0
+        parent[ch] = y
+        parent[gc] = np.repeat(ch, side)
+        eu.append(np.full(S, y))
+        ev.append(gc)
+        base += nh_v
+    tx = np.arange(1, n)
+    eu = np.concatenate([tx] + eu)
+    ev = np.concatenate([parent[1:]] + ev)
+    w = rng.uniform(1.0, 10.0, len(eu))
+    return from_edges(n, eu, ev, w, 1.0, beta, name or f"skewed{nheavy}x{nlight}", parent=parent.astype(np.int32),
+                      root=0)
 
 
 # ----------------------------------------------------------------------------------------
