@@ -142,6 +142,21 @@ gss_status gss_tree_free(gss_tree tree);
 gss_status gss_recover(gss_ctx ctx, gss_tree tree, const gss_params *params, uint8_t *mask,
                        int32_t *order, double *stretch, gss_info *info);
 
+/* ---- allocation-free recovery -------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gss_recover_noalloc computes exactly
+ * what gss_recover computes, with the same arguments and outputs, but allocates nothing.
+ * Its scratch is one static device array of GSS_NOALLOC_SCRATCH_BYTES bytes per device
+ * (held from the first context on that device until the process ends); every call on a
+ * device shares it, so calls that overlap on one device (other contexts or streams)
+ * race and must be ordered by the caller.  The tree must come from gss_tree_prep.
+ * Errors: as gss_recover; GSS_ERR_OOM with a message naming the limit when the input
+ * needs more scratch than the array holds (checked before any kernel runs from the edge
+ * count and K, and again as buffers are taken). */
+#define GSS_NOALLOC_SCRATCH_BYTES 268435456
+gss_status gss_recover_noalloc(gss_ctx ctx, gss_tree tree, const gss_params *params, uint8_t *mask,
+                               int32_t *order, double *stretch, gss_info *info);
+
 /* ---- batches: many graphs recovered by one pass of kernels -------------------------
  * gss_batch_prep copies nb graphs (host array of device CSRs, host array of device
  * parent arrays) into one disjoint union whose trees hang under a virtual root with

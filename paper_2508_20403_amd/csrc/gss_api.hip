@@ -142,6 +142,7 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         HIP_OK(hipHostMalloc(&ctx->h_stage, gss_ctx_s::STAGE_BYTES, hipHostMallocDefault));
         HIP_OK(hipMemset(ctx->d_flags, 0, 256));
         HIP_OK(hipMemset(ctx->d_counters, 0, 32 * sizeof(int64_t)));
+        noalloc_scratch_init(device);  // once per device, with the device current
         return GSS_OK;
     });
     if (s != GSS_OK) {
@@ -378,6 +379,32 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
         uint8_t *masks[1] = {mask};
         int32_t *orders[1] = {order};
         gss_status s = recover_impl(ctx, t, p, masks, order ? orders : nullptr, stretch, info);
+        ctx->record = false;
+        return s;
+    });
+}
+
+gss_status gss_recover_noalloc(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *mask, int32_t *order,
+                               double *stretch, gss_info *info)
+{
+    if (!ctx || !t || !p || !mask || t->ctx != ctx) return GSS_ERR_ARG;
+    if (!(p->alpha >= 0.0 && p->alpha <= 1.0) || p->beta < 0 || p->beta > GSS_MAX_BETA || p->reserved != 0 ||
+        (p->sched != GSS_SCHED_EDGECOUNT && p->sched != GSS_SCHED_LEARNED)) {
+        ctx->last_error = "bad recovery parameters";
+        return GSS_ERR_ARG;
+    }
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        if (t->virt_root >= 0 || !t->parts.empty())
+            throw gss_error{GSS_ERR_ARG, "a batch tree needs gss_recover_batch"};
+        ctx->record = (p->flags & GSS_F_RECORD) != 0;
+        gss_status s = GSS_OK;
+        try {
+            s = recover_noalloc_impl(ctx, t, p, mask, order, stretch, info);
+        } catch (...) {
+            ctx->record = false;
+            throw;
+        }
         ctx->record = false;
         return s;
     });

@@ -106,14 +106,40 @@ struct gss_ctx_s {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<void *> aux_frees;   // blocks released by auxiliary work, freed at the join
 
+    // allocation-free calls: scratch is bumped out of a fixed device arena (the
+    // library's static scratch array) instead of the pool; frees are no-ops and the
+    // caller rolls the offset back between rounds (arena_mark / arena_reset)
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_off = 0, arena_peak = 0;
+
     template <typename T>
     T *alloc(size_t count)
     {
-        return (T *)pool.get(count * sizeof(T) + 16);
+        const size_t bytes = count * sizeof(T) + 16;
+        if (arena) return (T *)arena_bump(bytes);
+        return (T *)pool.get(bytes);
+    }
+    void *arena_bump(size_t bytes)
+    {
+        const size_t off = (arena_off + 255) & ~(size_t)255;
+        if (off + bytes > arena_size)
+            throw gss_error{GSS_ERR_OOM, "the allocation-free entry point's scratch (" +
+                                             std::to_string(arena_size >> 20) + " MiB) is too small for this "
+                                             "input (it needs more than " + std::to_string((off + bytes) >> 20) +
+                                             " MiB); use gss_recover"};
+        arena_off = off + bytes;
+        if (arena_off > arena_peak) arena_peak = arena_off;
+        return arena + off;
+    }
+    size_t arena_mark() const { return arena_off; }
+    void arena_reset(size_t mark)
+    {
+        if (arena) arena_off = mark;
     }
     void free(void *p)
     {
         if (!p) return;
+        if (arena && (char *)p >= arena && (char *)p < arena + arena_size) return;
         if (lb_lane == 1) aux_frees.push_back(p);  // still in use by the auxiliary stream
         else pool.put(p);
     }
@@ -205,6 +231,11 @@ gss_status autotune_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *
                          int32_t *const *orders, const char *cache_path, int32_t *out_lm, int32_t *out_lb,
                          int32_t *out_ch, double *out_ms);
 bool tuning_valid(int32_t local_max, int32_t local_blocks, int32_t chunk);
+// allocation-free recovery (gss_noalloc.hip): the device scratch array's address, looked
+// up once per device at context creation, and the recovery that draws on it
+void noalloc_scratch_init(int device);
+gss_status recover_noalloc_impl(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *mask, int32_t *order,
+                                double *stretch, gss_info *info);
 // K of graph g: the override when >= 0, else floor(fl(alpha * n_g))
 int64_t target_count(gss_tree t, int32_t g, const gss_params *p);
 

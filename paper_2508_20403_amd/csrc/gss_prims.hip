@@ -213,6 +213,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_onepass(int32_t *__restrict
 
 uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch)
 {
+    if (ctx->arena) {  // allocation-free call: a fresh, cleared status array from the arena
+        uint64_t *s = ctx->alloc<uint64_t>(words);
+        HIP_OK(hipMemsetAsync(s, 0, sizeof(uint64_t) * words, ctx->stream));
+        *epoch = 1;
+        return s;
+    }
     const int l = ctx->lb_lane;
     if (words > ctx->lb_cap[l]) {
         ctx->free(ctx->lb_status[l]);

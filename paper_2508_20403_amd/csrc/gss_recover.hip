@@ -1801,6 +1801,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     GraphOut *dgo = ctx->alloc<GraphOut>(G);
     std::vector<GraphOut> go(G);
     while (any_active) {
+        const size_t amark = ctx->arena_mark();  // allocation-free calls: rounds reuse the scratch
         std::vector<int64_t> plen;
         std::vector<uint64_t> thr = select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen);
         hist_ready = false;
@@ -1873,6 +1874,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             any_active |= active[g];
         }
         B.release(ctx);
+        ctx->arena_reset(amark);
     }
     ctx->sync();
     if (!flags_checked) {

@@ -30,7 +30,8 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
            "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
            "gss_tree_graph_edges", "gss_autotune", "gss_ctx_set_batch_split", "gss_target_count",
-           "gss_ctx_set_rank_capacity", "gss_tree_rank_attempts", "gss_ctx_set_sort"]
+           "gss_ctx_set_rank_capacity", "gss_tree_rank_attempts", "gss_ctx_set_sort",
+           "gss_recover_noalloc"]
 GSS_F_RECORD = 2
 GSS_F_STATS = 4
 GSS_F_KEY_RT = 8
@@ -85,6 +86,8 @@ def load_library(path=LIB_PATH):
     lib.gss_tree_prep.argtypes = [P, ctypes.POINTER(Csr), P, ctypes.c_uint32, ctypes.POINTER(P)]
     lib.gss_tree_free.argtypes = [P]
     lib.gss_recover.argtypes = [P, P, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Info)]
+    lib.gss_recover_noalloc.argtypes = [P, P, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Info)]
+    lib.gss_recover_noalloc.restype = ctypes.c_int32
     lib.gss_tree_export.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_int32)]
     lib.gss_edge_lca.argtypes = [P, P, ctypes.c_int32, P, P]
     lib.gss_tree_num_edges.argtypes = [P]
