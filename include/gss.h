@@ -78,6 +78,15 @@ typedef struct {
                                   on resistances") instead of the stretch w*R_T; ties still
                                   by ascending id.  The stretch output is unchanged.  All
                                   graphs of a batch must agree on it.                     */
+#define GSS_F_LOOSE 16u        /* feGRASS's loose similarity (Def. "Similar edge (Loose)",
+                                  eq. cond-loose-2) instead of the strict one: a recovered
+                                  edge marks every later off-tree edge with an endpoint
+                                  within beta tree hops of either of its endpoints (the
+                                  constant radius c = beta for every edge, not beta*).
+                                  Passes repeat as under the strict condition (Sec. II-B).
+                                  The in-repo baseline of the paper's comparison; the
+                                  subtask schedule plays no part.  All graphs of a batch
+                                  must agree on it.                                       */
 
 /* gss_params.sched: order in which the subtask work queue is drained (never changes
  * the output).  GSS_SCHED_LEARNED without a loaded cost model falls back to the
@@ -294,12 +303,12 @@ gss_status gss_costmodel_grad(gss_ctx ctx, const float *x, const float *y, int32
  * clears the accumulated figures. */
 gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name);
 /* Reads accumulated entry idx: its kernel name (copied into buf, NUL-terminated), total
- * milliseconds, launch count and the algorithmic bytes of those launches (the least HBM
+ * milliseconds, launch count, the algorithmic bytes of those launches (the least HBM
  * traffic each launch's step needs: inputs read once, outputs written once; 0 for kernels
- * without such a model).  Any output pointer may be NULL.  Returns the number of entries,
- * -1 on a bad argument. */
+ * without such a model) and the milliseconds of the latest launch.  Any output pointer
+ * may be NULL.  Returns the number of entries, -1 on a bad argument. */
 int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
-                             int64_t *launches, int64_t *alg_bytes);
+                             int64_t *launches, int64_t *alg_bytes, double *last_ms);
 
 /* Library-owned, static strings. */
 const char *gss_status_str(gss_status s);

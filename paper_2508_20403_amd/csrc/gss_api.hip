@@ -461,7 +461,7 @@ gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name)
 }
 
 int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
-                             int64_t *launches, int64_t *alg_bytes)
+                             int64_t *launches, int64_t *alg_bytes, double *last_ms)
 {
     if (!ctx) return -1;
     int32_t count = (int32_t)ctx->prof_acc.size();
@@ -476,6 +476,7 @@ int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen
     if (total_ms) *total_ms = it->second.ms;
     if (launches) *launches = it->second.launches;
     if (alg_bytes) *alg_bytes = it->second.bytes;
+    if (last_ms) *last_ms = it->second.last_ms;
     return count;
 }
 

@@ -47,6 +47,7 @@ struct prof_sum {
     double ms = 0;
     int64_t launches = 0;
     int64_t bytes = 0;
+    double last_ms = 0;  // the latest launch
 };
 
 struct gss_ctx_s {
@@ -242,6 +243,9 @@ int64_t target_count(gss_tree t, int32_t g, const gss_params *p);
 // ---- sorting (gss_sort.hip) -----------------------------------------------------------
 // sorts n <= sample_sort_max() pairs by (key, value); result in (k, v), (k2, v2) scratch
 void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n);
+// one pass of the greedy under the loose condition over a resolved prefix (gss_loose.hip)
+int64_t loose_greedy(gss_ctx ctx, int32_t n, int32_t vroot, int64_t P, int32_t c, const int32_t *ancU,
+                     const int32_t *ancV, uint8_t *state);
 int64_t sample_sort_max();
 
 // ---- shared launch helpers (gss_prims.hip) -------------------------------------------

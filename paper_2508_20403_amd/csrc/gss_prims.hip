@@ -87,6 +87,7 @@ void gss_ctx_s::prof_collect()
         HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
         prof_sum &acc = prof_acc[r.name];
         acc.ms += ms;
+        acc.last_ms = ms;
         acc.launches += 1;
         acc.bytes += r.bytes;
         prof_events.push_back(r.a);

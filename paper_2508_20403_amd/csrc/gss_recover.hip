@@ -1299,6 +1299,22 @@ __global__ void k_rank_graph(int64_t P, const int32_t *__restrict__ sj, const in
     if (p < P) rg[p] = off_g[sj[p]];
 }
 
+// Candidates per graph (ranks among the recovered edges) into res.cand; synchronises.
+static void count_candidates(gss_ctx ctx, int32_t G, int64_t P, PrefixBufs &B, PrefixResult &res)
+{
+    hipStream_t st = ctx->stream;
+    B.candq = ctx->alloc<int32_t>(P + 2);
+    GSS_LAUNCH(k_cand_flags, dim3(grid_for(P + 1, RB)), dim3(RB), 0, st, P, B.state, B.candq);
+    scan_exclusive_i32(ctx, B.candq, P + 1, false);
+    int64_t *cg = ctx->alloc<int64_t>(G);
+    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, cg);
+    res.cand.assign(G, 0);
+    HIP_OK(hipMemcpyAsync(res.cand.data(), cg, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
+    ctx->sync();
+    if (res.rounds_pending) res.rounds = ctx->h_counters[12];
+    ctx->free(cg);
+}
+
 // Resolves, for every graph g, the prefix {key >= thr[g]} of its criticality order.
 static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uint64_t *key, const uint8_t *bst,
                                    const int32_t *lca, const uint64_t *thr, const std::vector<int64_t> &plen,
@@ -1375,6 +1391,20 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     GSS_LAUNCH_B((58 + 16 * (int64_t)(c + 1)) * P, k_rank_gather, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj,
                  t->off_id, t->off_u, t->off_v, bst,
                lca, t->vrec, t->parent, c, B.rid, B.rb, B.ru, B.rv, B.rdu, B.rdv, B.rl, lkey, lval, B.ancU, B.ancV);
+
+    if (prm->flags & GSS_F_LOOSE) {
+        // feGRASS's loose condition (Def. "Similar edge (Loose)"): loosely similar edges
+        // need not share their LCA, so there are no subtasks; the whole prefix is decided
+        // by rounds over tree-ancestor cells, with the constant radius c for every edge
+        ctx->free(lkey);
+        ctx->free(lkey2);
+        ctx->free(lval);
+        ctx->free(lval2);
+        B.state = ctx->alloc<uint8_t>(P + 1);
+        res.rounds = loose_greedy(ctx, t->n, t->virt_root, P, c, B.ancU, B.ancV, B.state);
+        count_candidates(ctx, G, P, B, res);
+        return res;
+    }
 
     // LCA subtasks (Alg. 1 Step 3): stable sort of the rank-ordered prefix by LCA.  LCAs
     // of different graphs of a batch are different vertices, so subtasks never mix graphs.
@@ -1602,17 +1632,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         ctx->free(arc_cnt);
         ctx->free(arc_off);
     }
-    // candidates per graph (ranks among the recovered edges)
-    B.candq = ctx->alloc<int32_t>(P + 2);
-    GSS_LAUNCH(k_cand_flags, dim3(grid_for(P + 1, RB)), dim3(RB), 0, st, P, B.state, B.candq);
-    scan_exclusive_i32(ctx, B.candq, P + 1, false);
-    int64_t *cg = ctx->alloc<int64_t>(G);
-    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, cg);
-    res.cand.assign(G, 0);
-    HIP_OK(hipMemcpyAsync(res.cand.data(), cg, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
-    ctx->sync();
-    if (res.rounds_pending) res.rounds = ctx->h_counters[12];
-    ctx->free(cg);
+    count_candidates(ctx, G, P, B, res);
     if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, B.sub_lca, P, feat, cycles, qv, nlocal);
     for (void *p : scratch) ctx->free(p);
     return res;
@@ -1707,8 +1727,10 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     const int key_rt = (prms[0].flags & GSS_F_KEY_RT) ? 1 : 0;
     for (int32_t g = 1; g < G; g++)
         if (prms[g].beta != c || prms[g].sched != prms[0].sched ||
-            ((prms[g].flags & GSS_F_KEY_RT) ? 1 : 0) != key_rt)
-            throw gss_error{GSS_ERR_ARG, "all graphs of a batch need the same beta, schedule and sort key"};
+            ((prms[g].flags & GSS_F_KEY_RT) ? 1 : 0) != key_rt ||
+            ((prms[g].flags ^ prms[0].flags) & GSS_F_LOOSE))
+            throw gss_error{GSS_ERR_ARG,
+                            "all graphs of a batch need the same beta, schedule, sort key and similarity condition"};
     std::vector<int64_t> K(G), nrec(G, 0), eligible(G), want(G), mg(G);
     std::vector<int32_t> passes(G, 0);
     std::vector<int64_t> lastP(G, 0), nsubg(G, 0), largest(G, 0);

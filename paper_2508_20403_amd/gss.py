@@ -35,6 +35,7 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
 GSS_F_RECORD = 2
 GSS_F_STATS = 4
 GSS_F_KEY_RT = 8
+GSS_F_LOOSE = 16
 NFEAT = 12
 COSTMODEL_FLOATS = 5081
 COSTMODEL_PARAMS = 5057
@@ -100,7 +101,7 @@ def load_library(path=LIB_PATH):
     lib.gss_ctx_profile.restype = ctypes.c_int32
     lib.gss_ctx_profile_read.argtypes = [P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
-                                         ctypes.POINTER(ctypes.c_int64)]
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
     lib.gss_ctx_profile_read.restype = ctypes.c_int32
     lib.gss_ctx_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.gss_target_count.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Params)]
@@ -175,18 +176,20 @@ class Context:
         self.check(self.lib.gss_ctx_profile(self.handle, 1 if enable else 0,
                                             kernel.encode() if kernel else None))
 
-    def profile_read(self):
-        """{kernel name: (total ms, launches, algorithmic bytes)} accumulated since profile()."""
+    def profile_read(self, last=False):
+        """{kernel name: (total ms, launches, algorithmic bytes)} accumulated since profile();
+        with last=True each tuple also carries the milliseconds of the latest launch."""
         out = {}
-        count = self.lib.gss_ctx_profile_read(self.handle, 0, None, 0, None, None, None)
+        count = self.lib.gss_ctx_profile_read(self.handle, 0, None, 0, None, None, None, None)
         buf = ctypes.create_string_buffer(128)
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         nb = ctypes.c_int64()
+        lm = ctypes.c_double()
         for i in range(max(count, 0)):
             self.lib.gss_ctx_profile_read(self.handle, i, buf, 128, ctypes.byref(ms), ctypes.byref(n),
-                                          ctypes.byref(nb))
-            out[buf.value.decode()] = (ms.value, n.value, nb.value)
+                                          ctypes.byref(nb), ctypes.byref(lm))
+            out[buf.value.decode()] = (ms.value, n.value, nb.value) + ((lm.value,) if last else ())
         return out
 
     # ---- subtask scheduling and the learned cost model --------------------------------
@@ -331,8 +334,10 @@ class Tree:
         return int(k)
 
     def recover(self, alpha, beta, k_override=-1, sched=SCHED_EDGECOUNT, mask_tree=False,
-                want_order=True, want_stretch=False, out=None, record=False, stats=False, key_rt=False):
-        """Runs gss_recover.  Returns (status, mask, order, stretch, info dict)."""
+                want_order=True, want_stretch=False, out=None, record=False, stats=False, key_rt=False,
+                loose=False):
+        """Runs gss_recover.  Returns (status, mask, order, stretch, info dict).  key_rt: order
+        by R_T alone; loose: feGRASS's loose similarity with the constant radius beta."""
         dev = self.arrays[3].device
         k = self.target_count(alpha, k_override)
         if out is None:
@@ -342,7 +347,7 @@ class Tree:
         else:
             mask, order, stretch = out
         flags = (GSS_F_MASK_TREE if mask_tree else 0) | (GSS_F_RECORD if record else 0) | \
-            (GSS_F_STATS if stats else 0) | (GSS_F_KEY_RT if key_rt else 0)
+            (GSS_F_STATS if stats else 0) | (GSS_F_KEY_RT if key_rt else 0) | (GSS_F_LOOSE if loose else 0)
         p = Params(float(alpha), int(beta), int(sched), int(k_override), flags, 0)
         info = Info()
         st = self.ctx.lib.gss_recover(self.ctx.handle, self.handle, ctypes.byref(p), _ptr(mask),
@@ -390,13 +395,14 @@ class Batch:
         self.m = [ctx.lib.gss_tree_graph_edges(self.handle, i) for i in range(nb)]
         self.n = [g.n for g in self.graphs]
 
-    def _params(self, alphas, beta, sched, k_override, record, stats=False):
+    def _params(self, alphas, beta, sched, k_override, record, stats=False, loose=False):
         nb = len(self.graphs)
         params = (Params * nb)()
         for i in range(nb):
             params[i] = Params(float(alphas[i]), int(beta), int(sched),
                                int(k_override[i]) if k_override is not None else -1,
-                               (GSS_F_RECORD if record else 0) | (GSS_F_STATS if stats else 0), 0)
+                               (GSS_F_RECORD if record else 0) | (GSS_F_STATS if stats else 0) |
+                               (GSS_F_LOOSE if loose else 0), 0)
         return params
 
     def autotune(self, cache_path=None, sched=SCHED_EDGECOUNT):
@@ -426,7 +432,7 @@ class Batch:
         return out
 
     def recover(self, alphas=None, beta=None, sched=SCHED_EDGECOUNT, k_override=None, out=None, record=False,
-                stats=False):
+                stats=False, loose=False):
         """Returns (status, masks, orders, infos) lists over the graphs."""
         nb = len(self.graphs)
         dev = torch.device("cuda")
@@ -438,7 +444,7 @@ class Batch:
             orders = [torch.empty(max(ks[i], 1), dtype=torch.int32, device=dev) for i in range(nb)]
         else:
             masks, orders = out
-        params = self._params(alphas, beta, sched, k_override, record, stats)
+        params = self._params(alphas, beta, sched, k_override, record, stats, loose)
         mp = (ctypes.c_void_p * nb)(*[m.data_ptr() for m in masks])
         op = (ctypes.c_void_p * nb)(*[o.data_ptr() for o in orders])
         infos = (Info * nb)()

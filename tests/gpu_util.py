@@ -7,14 +7,15 @@ from paper_2508_20403_amd import gss
 
 
 def run_gpu(ctx, g, alpha=None, beta=None, k_override=-1, want_stretch=True, sched=0, mask_tree=False,
-            key_rt=False):
+            key_rt=False, loose=False):
     alpha = g.alpha if alpha is None else alpha
     beta = g.beta if beta is None else beta
-    print(f"[gpu] {g.name} n={g.n} m={g.m} alpha={alpha} beta={beta} k={k_override}", flush=True)
+    print(f"[gpu] {g.name} n={g.n} m={g.m} alpha={alpha} beta={beta} k={k_override}"
+          f"{' key_rt' if key_rt else ''}{' loose' if loose else ''}", flush=True)
     tree = gss.Tree.from_graph(ctx, g)
     st, mask, order, stretch, info = tree.recover(alpha, beta, k_override, sched=sched,
                                                   want_stretch=want_stretch, mask_tree=mask_tree, stats=True,
-                                                  key_rt=key_rt)
+                                                  key_rt=key_rt, loose=loose)
     torch.cuda.synchronize()
     out = dict(status=st, mask=mask.cpu().numpy(), order=order.cpu().numpy() if order is not None else None,
                stretch=stretch.cpu().numpy() if stretch is not None else None, info=info)
@@ -22,8 +23,10 @@ def run_gpu(ctx, g, alpha=None, beta=None, k_override=-1, want_stretch=True, sch
     return out
 
 
-def run_oracle(g, alpha=None, beta=None, k_override=-1, mode=oracle.MODE_INDEXED, full=True, key_rt=False):
-    return oracle.recover(g, alpha=alpha, beta=beta, k_override=k_override, mode=mode, full=full, key_rt=key_rt)
+def run_oracle(g, alpha=None, beta=None, k_override=-1, mode=oracle.MODE_INDEXED, full=True, key_rt=False,
+               loose=False):
+    return oracle.recover(g, alpha=alpha, beta=beta, k_override=k_override, mode=mode, full=full, key_rt=key_rt,
+                          loose=loose)
 
 
 def assert_same_recovery(gpu, orc):
