@@ -125,9 +125,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched / learned-schedule record")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline entry (default: dominant)")
     ap.add_argument("--breakdown", action="store_true", help="print a per-kernel time table to stderr")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "ablation"],
                     help="plain: one sparsifier (the headline line, with the batched record); batch: only the "
-                         "batched comparison, as its own line")
+                         "batched comparison, as its own line; ablation: strict vs loose similarity, the "
+                         "R_T-only key and an alpha sweep (--workloads), as its own line")
+    ap.add_argument("--workloads", default="grid3d_128,rmat22", help="ablation workloads (comma list)")
+    ap.add_argument("--alphas", default="0.02,0.05,0.1,0.2", help="ablation alpha sweep (comma list)")
     ap.add_argument("--graphs", default="rgg64", help="batch workload: rgg64, or a comma list of names")
     ap.add_argument("--epochs", type=int, default=20, help="cost-model training epochs")
     ap.add_argument("--tuning", default=None, metavar="LOCAL_MAX,BLOCKS[,CHUNK]",
@@ -147,6 +150,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.mode == "batch":
         out = bench_batch(args)
+        print(json.dumps(out), flush=True)
+        return
+    if args.mode == "ablation":
+        out = bench_ablation(args)
         print(json.dumps(out), flush=True)
         return
     t0 = time.time()
@@ -427,6 +434,77 @@ def bench_batch(args):
                    "costmodel": {"samples": int(len(cyc)), "epochs": args.epochs,
                                  "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
                                  "train_s": round(train_s, 3), "heldout": heldout}},
+    }
+
+
+def bench_ablation(args):
+    """The density-aware strict condition against feGRASS's loose one (Sec. III-A; Def.
+    "Similar edge (Loose)" with the multi-pass rule of Sec. II-B), the R_T-only sort key
+    (Alg. 1 Step 2) and an alpha sweep (Sec. V "pdGRASS parameters"), on the GPU: per
+    workload, alpha and variant, the best-of-steps time of one recovery (tree prepared
+    once, outside the timing), the passes it needed, the prefix length of its last pass
+    and the dependency or decision rounds.  The loose condition uses the constant radius
+    c for every edge; c = 8 is feGRASS's default BFS step.  Parity of these variants with
+    the oracle is the test suite's (the loose and R_T-key tests, and the full-size
+    ablation test on the 128^3 grid)."""
+    import torch
+    from paper_2508_20403_amd import gss, synth
+
+    variants = [("strict", 2, False, False), ("strict", 8, False, False), ("loose", 2, True, False),
+                ("loose", 8, True, False), ("strict_rt_key", 2, False, True)]
+    alphas = [float(a) for a in args.alphas.split(",")]
+    dev = torch.device("cuda:0")
+    ctx = gss.Context(0, torch.cuda.current_stream())
+    rows = []
+    descs = {}
+    for name in args.workloads.split(","):
+        t0 = time.time()
+        g = synth.config(name)
+        descs[name] = WORKLOADS.get(name, name)
+        log(f"ablation workload {name}: n={g.n} m={g.m} ({time.time() - t0:.1f}s to build)")
+        arrays = [torch.from_numpy(a).to(dev) for a in (g.row_ptr, g.col, g.w, g.parent)]
+        tree = gss.Tree(ctx, *arrays)
+        for alpha in alphas:
+            K = tree.target_count(alpha)
+            mask = torch.empty(g.m, dtype=torch.uint8, device=dev)
+            order = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
+            for label, c, loose, rt in variants:
+                def run():
+                    return tree.recover(alpha, c, out=(mask, order, None), loose=loose, key_rt=rt)
+                st, _, _, _, info = run()  # warm-up
+                best = None
+                steps = max(2, args.steps // 5)
+                for _ in range(steps):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    run()
+                    torch.cuda.synchronize()
+                    ms = 1e3 * (time.perf_counter() - t)
+                    best = ms if best is None else min(best, ms)
+                rows.append({"workload": name, "alpha": alpha, "variant": label, "c": c, "k": info["k"],
+                             "recovered": info["n_recovered"], "passes": info["passes"],
+                             "prefix_len_last_pass": info["prefix_len"], "rounds": info["rounds"],
+                             "recover_ms": round(best, 3), "status": int(st)})
+                log(f"{name} alpha={alpha} {label} c={c}: {best:.3f} ms, {info['passes']} passes, "
+                    f"prefix {info['prefix_len']}, rounds {info['rounds']}")
+        tree.free()
+        del arrays
+    ctx.close()
+    strict = {(r["workload"], r["alpha"], r["c"]): r for r in rows if r["variant"] == "strict"}
+    loose = {(r["workload"], r["alpha"], r["c"]): r for r in rows if r["variant"] == "loose"}
+    summary = {f"{w} alpha={a} c={c}": {"passes_strict": strict[(w, a, c)]["passes"],
+                                         "passes_loose": loose[(w, a, c)]["passes"],
+                                         "speedup_strict_vs_loose": round(loose[(w, a, c)]["recover_ms"] /
+                                                                          strict[(w, a, c)]["recover_ms"], 3)}
+               for (w, a, c) in strict if (w, a, c) in loose}
+    first = rows[0]
+    return {
+        "metric": "recovery ms: density-aware strict vs feGRASS loose similarity, R_T key, alpha sweep",
+        "value": first["recover_ms"], "unit": "ms", "n_gpus": 1, "steps": max(2, args.steps // 5),
+        "warmup": 1, "ms_per_step": first["recover_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "; ".join(f"{k}: {v}" for k, v in descs.items()), "variants": rows,
+                   "strict_vs_loose": summary},
     }
 
 

@@ -245,38 +245,57 @@ void aux_join(gss_ctx ctx)
     ctx->aux_frees.clear();
 }
 
-// one workgroup scans the whole array in chunks (short arrays: one launch instead of three)
-#define SMALL_ITEMS 8
+// one workgroup scans a short array (at most 1024 * SMALL_ITEMS elements) in one sweep:
+// thread t owns the SMALL_ITEMS consecutive elements at t * SMALL_ITEMS, read and written
+// as 16-byte vectors when the array is 16-byte aligned; a single latency-bound launch
+// instead of the three of the tiled scan
+#define SMALL_ITEMS 32
 __global__ __launch_bounds__(1024) void k_scan_single(int32_t *__restrict__ data, int64_t n,
                                                       int64_t *__restrict__ total)
 {
     __shared__ int64_t lds[1024 / GSS_WAVE + 1];
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < n; c0 += 1024 * SMALL_ITEMS) {
-        int64_t base = c0 + (int64_t)threadIdx.x * SMALL_ITEMS;
-        int32_t v[SMALL_ITEMS];
-        int64_t s = 0;
+    const int64_t base = (int64_t)threadIdx.x * SMALL_ITEMS;
+    int32_t v[SMALL_ITEMS];
+    const bool vec = (((uintptr_t)data & 15) == 0) && base + SMALL_ITEMS <= n;
+    if (vec) {
 #pragma unroll
-        for (int i = 0; i < SMALL_ITEMS; i++) {
-            v[i] = (base + i < n) ? data[base + i] : 0;
-            s += v[i];
+        for (int i = 0; i < SMALL_ITEMS; i += 4) {
+            const int4 q = *(const int4 *)(data + base + i);
+            v[i] = q.x;
+            v[i + 1] = q.y;
+            v[i + 2] = q.z;
+            v[i + 3] = q.w;
         }
-        int64_t tot;
-        int64_t ex = block_exclusive_scan<int64_t>(s, lds, &tot) + carry;
+    } else {
 #pragma unroll
-        for (int i = 0; i < SMALL_ITEMS; i++) {
-            if (base + i < n) data[base + i] = (int32_t)ex;
-            ex += v[i];
-        }
-        carry += tot;
+        for (int i = 0; i < SMALL_ITEMS; i++) v[i] = (base + i < n) ? data[base + i] : 0;
     }
-    if (threadIdx.x == 0) *total = carry;
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SMALL_ITEMS; i++) s += v[i];
+    int64_t tot;
+    int64_t ex = block_exclusive_scan<int64_t>(s, lds, &tot);
+    int32_t o[SMALL_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SMALL_ITEMS; i++) {
+        o[i] = (int32_t)ex;
+        ex += v[i];
+    }
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < SMALL_ITEMS; i += 4) *(int4 *)(data + base + i) = make_int4(o[i], o[i + 1], o[i + 2], o[i + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < SMALL_ITEMS; i++)
+            if (base + i < n) data[base + i] = o[i];
+    }
+    if (threadIdx.x == 0) *total = tot;
 }
 
 void scan_exclusive_i32_dev(gss_ctx ctx, int32_t *data, int64_t n, int64_t *d_total)
 {
     if (n <= 0) throw gss_error{GSS_ERR_ARG, "scan: empty array"};
-    if (n <= 32 * 1024) {
+    if (n <= 1024 * SMALL_ITEMS) {
         GSS_LAUNCH_B(8 * n, k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, data, n, d_total);
     } else {
         if (((uintptr_t)data & 15) != 0) throw gss_error{GSS_ERR_ARG, "scan: misaligned array"};

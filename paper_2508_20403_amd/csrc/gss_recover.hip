@@ -281,10 +281,12 @@ __global__ __launch_bounds__(RB) void k_lca_stats(const int32_t *__restrict__ lc
 __global__ __launch_bounds__(RB) void k_key_hist(const uint64_t *__restrict__ key, int64_t M,
                                                  const int32_t *__restrict__ off_g, int shift, int width,
                                                  const uint64_t *__restrict__ pmask, const uint64_t *__restrict__ pval,
-                                                 const int64_t *__restrict__ need, uint32_t *__restrict__ hist)
+                                                 const int64_t *__restrict__ need, uint32_t *__restrict__ hist,
+                                                 const int32_t *__restrict__ active)
 {
     __shared__ uint32_t sh[SEL_BINS];
     __shared__ int32_t gblk;
+    if (*active == 0) return;  // no graph refines at this level
     for (int i = threadIdx.x; i < SEL_BINS; i += RB) sh[i] = 0;
     const int64_t per = ((M + gridDim.x - 1) / gridDim.x + RB - 1) / RB * RB;  // contiguous range per block
     const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(M, j0 + per);
@@ -304,51 +306,81 @@ __global__ __launch_bounds__(RB) void k_key_hist(const uint64_t *__restrict__ ke
         if (sh[i]) atomicAdd(&hist[(int64_t)gblk * SEL_BINS + i], sh[i]);
 }
 
-// per graph (block): digit holding the need-th largest key -> {digit, count above, count}
-__global__ __launch_bounds__(1024) void k_pick_bucket(const uint32_t *__restrict__ hist, int width,
-                                                      const int64_t *__restrict__ need_in, int64_t *out)
+// Device state of the threshold selection, one entry per graph (arrays of G):
+//   need      keys wanted (<= 0: the graph is not refining any more)
+//   above     keys above the bucket the fixed high digits select
+//   pmask/pval the fixed high digits
+//   thr, plen the threshold so far and the number of keys at or above it
+//   eligible  the graph's eligible keys
+// active[lv] counts the graphs refining at level lv.
+struct SelState {
+    int64_t *need, *above, *plen, *eligible;
+    uint64_t *pmask, *pval, *thr;
+    int32_t *active;
+};
+
+// Per graph (block): the digit at this level that holds the target-th largest key of the
+// selected bucket (target = need - above), and the state update the level implies.  The
+// graph's histogram row is cleared for the next level.  The graph stops refining once its
+// bucket overshoots need by at most max(1024, need / 16) keys, or at the last level.
+__global__ __launch_bounds__(1024) void k_pick_update(uint32_t *__restrict__ hist, int lv, int shift, int width,
+                                                      int last, SelState S)
 {
     __shared__ int64_t lds[1024 / GSS_WAVE + 1];
+    __shared__ int64_t s_found[3];
     const int g = blockIdx.x;
-    const int64_t need = need_in[g];
-    if (need <= 0) {
-        if (threadIdx.x == 0) {
-            out[3 * g] = -2;
-            out[3 * g + 1] = 0;
-            out[3 * g + 2] = 0;
-        }
-        return;
-    }
-    const uint32_t *h = hist + (int64_t)g * SEL_BINS;
+    if (S.active[lv] == 0) return;
+    const int64_t need = S.need[g];
+    if (need <= 0) return;
+    const int64_t target = need - S.above[g];
+    uint32_t *h = hist + (int64_t)g * SEL_BINS;
     const int nb = 1 << width;
     const int per = (nb + 1023) / 1024;
-    int64_t s = 0;
+    if (threadIdx.x == 0) s_found[0] = -1;
+    int64_t sum = 0;
     for (int i = 0; i < per; i++) {
-        int r = threadIdx.x * per + i;
-        if (r < nb) s += h[nb - 1 - r];
+        const int r = threadIdx.x * per + i;
+        if (r < nb) sum += h[nb - 1 - r];
     }
     int64_t tot;
-    int64_t before = block_exclusive_scan<int64_t>(s, lds, &tot);
-    if (before < need && before + s >= need) {
+    const int64_t before = block_exclusive_scan<int64_t>(sum, lds, &tot);  // synchronises
+    if (before < target && before + sum >= target) {
         int64_t acc = before;
         for (int i = 0; i < per; i++) {
-            int r = threadIdx.x * per + i;
+            const int r = threadIdx.x * per + i;
             if (r >= nb) break;
-            int64_t c = h[nb - 1 - r];
-            if (acc + c >= need) {
-                out[3 * g] = nb - 1 - r;
-                out[3 * g + 1] = acc;
-                out[3 * g + 2] = c;
+            const int64_t c = h[nb - 1 - r];
+            if (acc + c >= target) {
+                s_found[0] = nb - 1 - r;
+                s_found[1] = acc;
+                s_found[2] = c;
                 break;
             }
             acc += c;
         }
     }
-    if (threadIdx.x == 0 && tot < need) {
-        out[3 * g] = -1;
-        out[3 * g + 1] = tot;
-        out[3 * g + 2] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
+    if (threadIdx.x != 0) return;
+    const int64_t d = s_found[0];
+    if (d < 0) {  // fewer keys than wanted: take every eligible key
+        S.thr[g] = 1;
+        S.plen[g] = S.eligible[g];
+        S.need[g] = 0;
+        return;
     }
+    const uint64_t dmask = ((uint64_t)1 << width) - 1;
+    S.pmask[g] |= dmask << shift;
+    const uint64_t pval = S.pval[g] | ((uint64_t)d << shift);
+    S.pval[g] = pval;
+    const int64_t above = S.above[g] + s_found[1];
+    S.above[g] = above;
+    const int64_t slack = max((int64_t)1024, need / 16);
+    // the bucket's lowest key, never 0 (a zero key is an edge already recovered)
+    S.thr[g] = pval > 1 ? pval : 1;
+    S.plen[g] = above + s_found[2];
+    if (above + s_found[2] - need <= slack || last) S.need[g] = 0;
+    else atomicAdd(&S.active[lv + 1], 1);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1640,80 +1672,69 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
 
 // Per graph, a key threshold T such that {key >= T} holds at least want[g] eligible edges
 // (and not many more).  want[g] <= 0: graph not selected (threshold above every key).
+// The digit levels run on the device, each graph's state updated by the pick kernel,
+// without a host round trip between levels; dthr (device, G) receives the thresholds.
 //
 // plen[g] receives the number of keys >= thr[g]: the keys above the chosen bucket plus the
 // bucket's own (every key of the bucket is at least its lowest key, every key below it is
 // smaller), all eligible keys when the threshold is 1, none when the graph is not selected.
-static std::vector<uint64_t> select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist,
-                                               bool hist_ready, const std::vector<int64_t> &want,
-                                               const std::vector<int64_t> &eligible, std::vector<int64_t> &plen)
+static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist, bool hist_ready,
+                              const std::vector<int64_t> &want, const std::vector<int64_t> &eligible,
+                              std::vector<int64_t> &plen, uint64_t *dthr)
 {
     hipStream_t st = ctx->stream;
     const int32_t G = t->G;
     const int32_t *off_g = (G > 1) ? t->off_g : nullptr;
-    std::vector<uint64_t> thr(G, ~0ull), pmask(G, 0), pval(G, 0);
-    std::vector<int64_t> above(G, 0), need(G, 0);
+    constexpr int LEVELS = 6;
+    const int shifts[LEVELS] = {51, 39, 27, 15, 3, 0};
+    const int widths[LEVELS] = {12, 12, 12, 12, 12, 3};
+    // initial state, packed in int64 words: need, above, plen, eligible, pmask, pval, thr
+    // (G each), then the per-level active counts (int32, LEVELS + 1)
+    const size_t words = 7 * (size_t)G + (LEVELS + 2) / 2;
+    std::vector<int64_t> init(words, 0);
+    int64_t *h_need = init.data(), *h_plen = h_need + 2 * G, *h_elig = h_need + 3 * G;
+    uint64_t *h_thr = (uint64_t *)(h_need + 6 * G);
+    int32_t *h_active = (int32_t *)(h_need + 7 * G);
+    int32_t refining = 0;
     plen.assign(G, 0);
-    bool any = false;
     for (int32_t g = 0; g < G; g++) {
+        h_elig[g] = eligible[g];
+        h_thr[g] = ~0ull;  // not selected: above every key
         if (want[g] <= 0) continue;
         if (want[g] >= eligible[g]) {
-            thr[g] = 1;  // every eligible key is >= 1
-            plen[g] = eligible[g];
-            continue;
-        }
-        need[g] = want[g];
-        any = true;
-    }
-    const int shifts[6] = {51, 39, 27, 15, 3, 0};
-    const int widths[6] = {12, 12, 12, 12, 12, 3};
-    // per graph: remaining count, then the fixed high bits (mask, value), in one copy
-    int64_t *dsel = ctx->alloc<int64_t>(3 * G);
-    int64_t *dneed = dsel;
-    uint64_t *dpm = (uint64_t *)(dsel + G), *dpv = (uint64_t *)(dsel + 2 * G);
-    int64_t *dout = ctx->alloc<int64_t>(3 * G);
-    std::vector<int64_t> out(3 * G), sel(3 * G);
-    for (int lv = 0; lv < 6 && any; lv++) {
-        for (int32_t g = 0; g < G; g++) {
-            sel[g] = need[g] > 0 ? need[g] - above[g] : 0;
-            sel[G + g] = (int64_t)pmask[g];
-            sel[2 * G + g] = (int64_t)pval[g];
-        }
-        ctx->h2d(dsel, sel.data(), sizeof(int64_t) * 3 * G);
-        if (lv > 0 || !hist_ready || G > 1) {
-            HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS * G, st));
-            GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key, t->M,
-                       off_g, shifts[lv], widths[lv], dpm, dpv, dneed, hist);
-        }
-        GSS_LAUNCH(k_pick_bucket, dim3(G), dim3(1024), 0, st, hist, widths[lv], dneed, dout);
-        HIP_OK(hipMemcpyAsync(out.data(), dout, sizeof(int64_t) * 3 * G, hipMemcpyDeviceToHost, st));
-        ctx->sync();
-        any = false;
-        const int64_t dmask = ((1ll << widths[lv]) - 1);
-        for (int32_t g = 0; g < G; g++) {
-            if (need[g] <= 0) continue;
-            int64_t d = out[3 * g], cum = out[3 * g + 1], cnt = out[3 * g + 2];
-            if (d < 0) {  // fewer keys than wanted: take everything
-                thr[g] = 1;
-                plen[g] = eligible[g];
-                need[g] = 0;
-                continue;
-            }
-            pmask[g] |= (uint64_t)dmask << shifts[lv];
-            pval[g] |= (uint64_t)d << shifts[lv];
-            above[g] += cum;
-            const int64_t slack = std::max<int64_t>(1024, need[g] / 16);
-            // lowest key of the bucket, and never 0: a zero key is an edge already
-            // recovered (the histograms skip those too)
-            thr[g] = std::max<uint64_t>(pval[g], 1);
-            plen[g] = above[g] + cnt;
-            if (above[g] + cnt - need[g] <= slack || lv == 5) need[g] = 0;
-            else any = true;
+            h_thr[g] = 1;  // every eligible key is >= 1
+            h_plen[g] = eligible[g];
+        } else {
+            h_need[g] = want[g];
+            refining++;
         }
     }
-    ctx->free(dsel);
-    ctx->free(dout);
-    return thr;
+    h_active[0] = refining;
+    int64_t *dstate = ctx->alloc<int64_t>((int64_t)words);
+    ctx->h2d(dstate, init.data(), sizeof(int64_t) * words);
+    SelState S;
+    S.need = dstate;
+    S.above = dstate + G;
+    S.plen = dstate + 2 * G;
+    S.eligible = dstate + 3 * G;
+    S.pmask = (uint64_t *)(dstate + 4 * G);
+    S.pval = (uint64_t *)(dstate + 5 * G);
+    S.thr = (uint64_t *)(dstate + 6 * G);
+    S.active = (int32_t *)(dstate + 7 * G);
+    if (refining > 0) {
+        if (!hist_ready || G > 1) HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS * G, st));
+        for (int lv = 0; lv < LEVELS; lv++) {
+            if (lv > 0 || !hist_ready || G > 1)
+                GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key, t->M,
+                           off_g, shifts[lv], widths[lv], S.pmask, S.pval, S.need, hist, S.active + lv);
+            GSS_LAUNCH(k_pick_update, dim3(G), dim3(1024), 0, st, hist, lv, shifts[lv], widths[lv],
+                       lv == LEVELS - 1 ? 1 : 0, S);
+        }
+    }
+    HIP_OK(hipMemcpyAsync(dthr, S.thr, sizeof(uint64_t) * G, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(plen.data(), S.plen, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
+    ctx->sync();
+    ctx->free(dstate);
 }
 
 // Recovery of every graph of a tree (a single graph, or a batch).
@@ -1825,10 +1846,9 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     while (any_active) {
         const size_t amark = ctx->arena_mark();  // allocation-free calls: rounds reuse the scratch
         std::vector<int64_t> plen;
-        std::vector<uint64_t> thr = select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen);
-        hist_ready = false;
         uint64_t *dthr = ctx->alloc<uint64_t>(G);
-        ctx->h2d(dthr, thr.data(), sizeof(uint64_t) * G);
+        select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen, dthr);
+        hist_ready = false;
         PrefixBufs B;
         PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, plen, B, &prms[0]);
         ctx->free(dthr);

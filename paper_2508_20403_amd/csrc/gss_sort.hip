@@ -3,8 +3,9 @@
 // (Step 3) and the subtask work queue.  These sorts hold a few hundred thousand pairs,
 // too few for a radix sort to reach bandwidth: every radix pass is a launch bounded by
 // its latency.  A sample sort needs five launches whatever the key width:
-//   1. one workgroup sorts a stratified sample of the pairs and keeps nb - 1 evenly
-//      spaced splitters,
+//   1. a stratified sample of the pairs is ranked by counting (every sample compared
+//      with every other, spread over the grid) and nb - 1 evenly spaced ranks become
+//      the splitters,
 //   2. every tile counts its pairs per bucket (binary search over the splitters in LDS)
 //      into a bucket-major count matrix,
 //   3. an exclusive scan of that matrix gives every (bucket, tile) its output offset and
@@ -181,49 +182,55 @@ __device__ __forceinline__ int ss_bucket(uint64_t k, uint32_t v, const uint64_t 
     return lo;
 }
 
-// 1. the sample: ns = 1024 E strata of equal length, one pair from each at a hashed
-// offset, sorted in registers; splitter b (b < nb - 1) is sample (b + 1) * ns / nb
-template <int E>
-__device__ void ss_sample_run(const uint64_t *__restrict__ k, const int32_t *__restrict__ v, int64_t n, int nb,
-                              uint64_t *__restrict__ spk, uint32_t *__restrict__ spv, uint64_t *ek, uint32_t *ev)
+// 1. the splitters: ns strata of equal length give one sample each, the pair at a hashed
+// offset in the stratum.  Every block gathers all samples into LDS; SS_RT threads count
+// the rank of one sample among them (each compares it with every SS_RT-th sample, then
+// the counts are summed across those lanes).  Samples are distinct pairs, so the ranks
+// are a permutation, and the sample of rank (b + 1) ns / nb becomes splitter b
+// (b < nb - 1): no sort, and every step runs on the whole grid.
+#define SS_RT 32   // threads ranking one sample (consecutive lanes)
+#define SS_RB 256  // threads of the ranking kernel
+
+// ns is a power of two (2^lgns <= n): stratum i is [i n / ns, (i + 1) n / ns), and the
+// hashed offset in it is taken by a multiply-high (no 64-bit division on the device)
+__device__ __forceinline__ int64_t ss_sample_pos(int i, int64_t n, int lgns)
 {
-    constexpr int NS = 1024 * E;
-    uint64_t kk[E];
-    uint32_t vv[E];
-#pragma unroll
-    for (int r = 0; r < E; r++) {
-        const int i = r * 1024 + (int)threadIdx.x;
-        const int64_t lo = (int64_t)i * n / NS, hi = (int64_t)(i + 1) * n / NS;
-        int64_t p = lo;
-        if (hi > lo) p = lo + (int64_t)(mix32(0x9E3779B9u * (uint32_t)(i + 1)) % (uint32_t)(hi - lo));
-        if (p >= n) p = n - 1;
-        kk[r] = k[p];
-        vv[r] = (uint32_t)v[p];
-    }
-    ss_reg_sort<E>(kk, vv, ek, ev);
-#pragma unroll
-    for (int r = 0; r < E; r++) {
-        ek[r * 1024 + threadIdx.x] = kk[r];
-        ev[r * 1024 + threadIdx.x] = vv[r];
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb - 1; b += SS_BT) {
-        const int q = (int)((int64_t)(b + 1) * NS / nb);
-        spk[b] = ek[q];
-        spv[b] = ev[q];
-    }
+    const int64_t lo = ((int64_t)i * n) >> lgns, hi = ((int64_t)(i + 1) * n) >> lgns;
+    const uint64_t h = mix32(0x9E3779B9u * (uint32_t)(i + 1));
+    const int64_t p = lo + (int64_t)((h * (uint64_t)(hi - lo)) >> 32);
+    return p < n ? p : n - 1;
 }
 
-__global__ __launch_bounds__(SS_BT) void k_ss_sample(const uint64_t *__restrict__ k, const int32_t *__restrict__ v,
-                                                    int64_t n, int se, int nb, uint64_t *__restrict__ spk,
-                                                    uint32_t *__restrict__ spv)
+__global__ __launch_bounds__(SS_RB) void k_ss_splitters(const uint64_t *__restrict__ k, const int32_t *__restrict__ v,
+                                                       int64_t n, int lgns, int nb, uint64_t *__restrict__ spk,
+                                                       uint32_t *__restrict__ spv)
 {
-    __shared__ uint64_t ek[SS_SAMPLES];
-    __shared__ uint32_t ev[SS_SAMPLES];
-    switch (se) {
-    case 1: ss_sample_run<1>(k, v, n, nb, spk, spv, ek, ev); break;
-    case 2: ss_sample_run<2>(k, v, n, nb, spk, spv, ek, ev); break;
-    default: ss_sample_run<4>(k, v, n, nb, spk, spv, ek, ev); break;
+    __shared__ uint64_t sk[SS_SAMPLES];
+    __shared__ uint32_t sv[SS_SAMPLES];
+    const int ns = 1 << lgns;
+    for (int i = threadIdx.x; i < ns; i += SS_RB) {
+        const int64_t p = ss_sample_pos(i, n, lgns);
+        sk[i] = k[p];
+        sv[i] = (uint32_t)v[p];
+    }
+    __syncthreads();
+    const int t = blockIdx.x * SS_RB + (int)threadIdx.x;
+    const int i = t / SS_RT, part = t % SS_RT;
+    const bool valid = i < ns;
+    const uint64_t mk = valid ? sk[i] : 0;
+    const uint32_t mv = valid ? sv[i] : 0;
+    int cnt = 0;
+    if (valid)
+        for (int j = part; j < ns; j += SS_RT) cnt += ss_less(sk[j], sv[j], mk, mv) ? 1 : 0;
+#pragma unroll
+    for (int d = SS_RT / 2; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, GSS_WAVE);
+    if (valid && part == 0) {
+        // the one b + 1 that could select rank cnt: the least q with q ns / nb >= cnt
+        const int64_t q = ((int64_t)cnt * nb + ns - 1) / ns;
+        if (q >= 1 && q <= nb - 1 && (q * ns) / nb == cnt) {
+            spk[q - 1] = mk;
+            spv[q - 1] = mv;
+        }
     }
 }
 
@@ -328,10 +335,11 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
         return;
     }
     // about 8 samples per bucket, at least 1024
-    const int se = nb <= 128 ? 1 : nb <= 256 ? 2 : 4;
+    const int lgns = nb <= 128 ? 10 : nb <= 256 ? 11 : 12;
     uint64_t *spk = ctx->alloc<uint64_t>(nb);
     uint32_t *spv = ctx->alloc<uint32_t>(nb);
-    GSS_LAUNCH_B(12 * 1024 * (int64_t)se, k_ss_sample, dim3(1), dim3(SS_BT), 0, st, k, v, n, se, nb, spk, spv);
+    GSS_LAUNCH_B(12 * ((int64_t)1 << lgns), k_ss_splitters, dim3((unsigned)(((int64_t)SS_RT << lgns) / SS_RB)),
+                 dim3(SS_RB), 0, st, k, v, n, lgns, nb, spk, spv);
     GSS_LAUNCH_B(12 * n, k_ss_count, dim3((unsigned)ntiles), dim3(SS_TT), 0, st, k, v, n, nb, spk, spv, hist);
     scan_exclusive_i32_dev(ctx, hist, ntiles * nb, ctx->d_counters + 11);
     GSS_LAUNCH_B(24 * n, k_ss_scatter, dim3((unsigned)ntiles), dim3(SS_TT), 0, st, k, v, n, nb, spk, spv, hist, k2,

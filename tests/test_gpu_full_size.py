@@ -157,3 +157,21 @@ def test_full_batch_matches_oracle(gpu_ctx):
         b.free()
     finally:
         ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_strict_vs_loose_full_size_matches_oracle(gpu_ctx):
+    """The strict-vs-loose ablation at full size (the 128^3 grid): strict with c = 8 and
+    feGRASS's loose condition with c = 2 and c = 8 (its default BFS step, where a pass
+    ends short and further passes run), at alpha = 0.02 and 0.10, against the oracle run
+    live (a few seconds each)."""
+    import oracle
+    from tests.gpu_util import assert_same_recovery, run_gpu
+    g = _graph("grid3d_128")
+    for alpha in (0.02, 0.1):
+        for c, loose in ((8, False), (2, True), (8, True)):
+            gpu = run_gpu(gpu_ctx, g, alpha=alpha, beta=c, loose=loose, want_stretch=False)
+            orc = oracle.recover(g, alpha=alpha, beta=c, loose=loose)
+            assert_same_recovery(gpu, orc)
+            print(f"[full] grid3d_128 alpha={alpha} c={c} {'loose' if loose else 'strict'}: "
+                  f"{orc.info['passes']} passes", flush=True)
