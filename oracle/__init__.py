@@ -4,4 +4,4 @@ Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark m
 import this package.  The GPU library never uses it.
 """
 from .oracle import (OracleResult, build, load, recover, MODE_INDEXED, MODE_BRUTE,  # noqa: F401
-                     MODE_SUBTASK, STATUS)
+                     MODE_SUBTASK, STATUS, spanning_tree)

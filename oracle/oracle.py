@@ -9,6 +9,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gss_oracle.c")
+SRC_TREE = os.path.join(HERE, "gss_oracle_tree.c")
 LIB = os.path.join(HERE, "libgss_oracle.so")
 
 MODE_INDEXED, MODE_BRUTE, MODE_SUBTASK = 0, 1, 2
@@ -25,7 +26,7 @@ _lib = None
 def build(verbose=False):
     """Compile the oracle with plain gcc: FP64, no contraction, no fast-math."""
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-Wall", "-o", LIB + ".tmp", SRC, SRC_TREE, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -41,6 +42,9 @@ def _bind(lib):
                                 ctypes.c_int64, ctypes.c_int32, ctypes.c_int32] + [P] * 15
     lib.orc_num_edges.restype = ctypes.c_int64
     lib.orc_num_edges.argtypes = [ctypes.c_int32, P]
+    if hasattr(lib, "orc_spanning_tree"):
+        lib.orc_spanning_tree.restype = ctypes.c_int
+        lib.orc_spanning_tree.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int, P, P, P, P]
     return lib
 
 
@@ -57,7 +61,8 @@ def build_variant(src_text, out_path):
 def load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC),
+                                                                  os.path.getmtime(SRC_TREE)):
             build()
         lib = ctypes.CDLL(LIB)
         _lib = _bind(lib)
@@ -131,3 +136,28 @@ def recover(g=None, *, n=None, row_ptr=None, col=None, w=None, parent=None, alph
     for k, v in pe.items():
         out[k] = v[:m] if len(v) == m + 1 else v
     return OracleResult(st, **out)
+
+
+def spanning_tree(g=None, *, n=None, row_ptr=None, col=None, w=None, lib=None, plain=False):
+    """feGRASS's spanning tree (gss_oracle_tree.c): returns (parent, root, ordering weight per
+    edge id, BFS distance from the root), or raises ValueError for a graph that is not
+    connected.  plain: order by w itself (a maximum-weight spanning tree)."""
+    lib = lib or load()
+    if g is not None:
+        n = g.n if n is None else n
+        row_ptr = g.row_ptr if row_ptr is None else row_ptr
+        col = g.col if col is None else col
+        w = g.w if w is None else w
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    m = int(row_ptr[-1]) // 2
+    parent = np.zeros(n, np.int32)
+    root = ctypes.c_int32(-1)
+    weff = np.zeros(m + 1, np.float64)
+    dist = np.zeros(n, np.int32)
+    st = lib.orc_spanning_tree(int(n), _ptr(row_ptr), _ptr(col), _ptr(w), 1 if plain else 0, _ptr(parent),
+                               ctypes.cast(ctypes.pointer(root), ctypes.c_void_p), _ptr(weff), _ptr(dist))
+    if st != 0:
+        raise ValueError("spanning tree: bad arguments or a graph that is not connected")
+    return parent, int(root.value), weff[:m], dist
