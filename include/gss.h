@@ -310,6 +310,44 @@ gss_status gss_ctx_profile(gss_ctx ctx, int32_t enable, const char *kernel_name)
 int32_t gss_ctx_profile_read(gss_ctx ctx, int32_t idx, char *buf, int32_t buflen, double *total_ms,
                              int64_t *launches, int64_t *alg_bytes, double *last_ms);
 
+/* ---- spanning tree: the step before the recovery ----------------------------------
+ * feGRASS's spanning tree (Sec. II-B "feGRASS Algorithm"; Def. "Effective weight",
+ * eq. weff): root = the vertex of largest degree (the smallest id among ties); unweighted
+ * breadth-first distances dist from it; per edge W_eff = w * log(max(deg u, deg v)) /
+ * (dist u + dist v) (natural log, each operation rounded once); the maximum spanning
+ * tree under the total order (W_eff descending, edge id ascending), rooted at root.
+ * With flags = GSS_TREE_WEIGHT the order is by w itself (a maximum-weight spanning
+ * tree; same root).  g: device CSR as for gss_tree_prep, and connected.  parent: device
+ * int32 [n], receives the tree (-1 at the root), ready for gss_tree_prep; root: host
+ * int32, receives the root; weff: device double [m] indexed by edge id (the ordering
+ * weight of every edge), or NULL.  Errors: GSS_ERR_ARG (sizes, an unordered row, a
+ * column out of range or on the diagonal, a graph that is not connected),
+ * GSS_ERR_ASYM (an odd number of upper entries against nnz). */
+#define GSS_TREE_WEIGHT 1u
+gss_status gss_spanning_tree(gss_ctx ctx, const gss_csr *g, uint32_t flags, int32_t *parent, int32_t *root,
+                             double *weff);
+
+/* ---- memoized graph capture of recoveries ------------------------------------------
+ * With enable = 1, gss_recover and gss_recover_batch remember each call's key: the tree,
+ * the parameters, the output pointers and the context's settings (work-queue tuning,
+ * sort settings, cost model).  The first call with a key runs eagerly and records every
+ * value the host reads back; the second runs the same host code with the context stream
+ * in capture mode, each read-back replaced by its recorded value plus a device-side
+ * comparison with it, then launches the resulting HIP graph; every later call with the key
+ * replays that graph: one launch and one host synchronisation.  Outputs and infos are
+ * those of an eager call, since a recovery is a function of its key: a tree's arrays may
+ * not change until gss_tree_free, which drops the tree's graphs.  Should a replayed value
+ * ever differ from the recorded one, the graph is dropped and the call reruns eagerly.
+ * Calls with GSS_F_RECORD, calls while kernel timing is on, and gss_recover_noalloc always
+ * run eagerly.  At most 8 keys are kept per context (the oldest is dropped); each captured
+ * key holds its own scratch arena (the recording call's peak) until dropped.  enable = 0
+ * drops every graph.  Errors: GSS_ERR_ARG. */
+gss_status gss_ctx_set_capture(gss_ctx ctx, int32_t enable);
+/* Counts since the context was created: recording (eager) calls, captures, replays, and
+ * host synchronisations of the context stream.  Any pointer may be NULL. */
+gss_status gss_ctx_capture_stats(gss_ctx ctx, int64_t *records, int64_t *captures, int64_t *replays,
+                                 int64_t *syncs);
+
 /* Library-owned, static strings. */
 const char *gss_status_str(gss_status s);
 const char *gss_last_error(gss_ctx ctx);

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgss.so")
-SOURCES = ["gss_prims.hip", "gss_sort.hip", "gss_prep.hip", "gss_recover.hip", "gss_subtask.hip", "gss_loose.hip", "gss_mlp.hip", "gss_tune.hip", "gss_noalloc.hip", "gss_api.hip"]
+SOURCES = ["gss_prims.hip", "gss_sort.hip", "gss_prep.hip", "gss_recover.hip", "gss_subtask.hip", "gss_loose.hip", "gss_treegen.hip", "gss_mlp.hip", "gss_tune.hip", "gss_noalloc.hip", "gss_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -58,6 +58,241 @@ int64_t target_count(gss_tree t, int32_t g, const gss_params *p)
     return (int64_t)std::floor(p->alpha * (double)ng);
 }
 
+// ------------------------------------------------------------------------------------
+// memoized graph capture of recoveries
+// ------------------------------------------------------------------------------------
+// A recovery is a pure function of the tree (whose arrays may not change until it is
+// freed), the parameters, the output pointers and the context's settings.  The first call
+// with a given key runs eagerly and records what it reads back; the second runs the same
+// host code while the stream is captured, every read-back replaced by its recorded value
+// (and a device-side comparison with it), and launches the graph; later calls replay it.
+struct GraphEntry {
+    gss_tree t = nullptr;
+    std::vector<uint8_t> key, tape;
+    size_t arena_bytes = 0, h2d_bytes = 0;
+    std::vector<gss_info> infos;
+    gss_status status = GSS_OK;
+    bool no_capture = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *arena = nullptr;
+    uint32_t *flag = nullptr;
+    char *pinned = nullptr;  // host data the graph's copies read at every replay
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (arena) (void)hipFree(arena);
+        if (flag) (void)hipFree(flag);
+        if (pinned) (void)hipHostFree(pinned);
+        exec = nullptr;
+        graph = nullptr;
+        arena = nullptr;
+        flag = nullptr;
+        pinned = nullptr;
+    }
+    ~GraphEntry() { release(); }
+};
+
+namespace {
+constexpr size_t MAX_GRAPHS = 8;  // remembered recoveries per context (oldest dropped first)
+
+std::vector<uint8_t> graph_key(gss_ctx ctx, gss_tree t, int32_t G, const gss_params *p, uint8_t *const *masks,
+                               int32_t *const *orders, const double *stretch)
+{
+    std::vector<uint8_t> k;
+    auto put = [&](const void *x, size_t n) { k.insert(k.end(), (const uint8_t *)x, (const uint8_t *)x + n); };
+    put(&t, sizeof t);
+    put(&G, sizeof G);
+    put(p, sizeof(gss_params) * (size_t)G);
+    for (int32_t g = 0; g < G; g++) {
+        const void *m = masks[g], *o = orders ? orders[g] : nullptr;
+        put(&m, sizeof m);
+        put(&o, sizeof o);
+    }
+    put(&stretch, sizeof stretch);
+    const int64_t s[7] = {ctx->local_max, ctx->local_blocks, ctx->local_chunk, ctx->sort_cap,
+                          ctx->sort_radix ? 1 : 0, ctx->model_ready ? 1 : 0, ctx->device};
+    put(s, sizeof s);
+    put(&ctx->mlp_w, sizeof ctx->mlp_w);
+    put(&ctx->mlp_wbf16, sizeof ctx->mlp_wbf16);
+    return k;
+}
+
+void drop_entry(gss_ctx ctx, GraphEntry *e)
+{
+    auto it = std::find(ctx->graphs.begin(), ctx->graphs.end(), e);
+    if (it != ctx->graphs.end()) ctx->graphs.erase(it);
+    delete e;
+}
+
+// one launch of a captured recovery and its single synchronisation; false when a
+// replayed read-back value differed from the recorded one
+bool replay(gss_ctx ctx, GraphEntry *e)
+{
+    HIP_OK(hipGraphLaunch(e->exec, ctx->stream));
+    HIP_OK(hipMemcpyAsync(&ctx->h_counters[16], e->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    uint32_t f = 0;
+    memcpy(&f, &ctx->h_counters[16], sizeof f);
+    if (f) ctx->last_error = "graph replay: read-back check " + std::to_string(f) + " differed from the recording";
+    return f == 0;
+}
+
+// the capturing call: the same host code, read-backs from the tape, into a graph
+template <typename F>
+bool capture(gss_ctx ctx, GraphEntry *e, int32_t ninfo, F &&fn)
+{
+    if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const size_t arena_bytes = e->arena_bytes + 4096;
+    if (hipMalloc(&e->arena, arena_bytes) != hipSuccess || hipMalloc((void **)&e->flag, 256) != hipSuccess ||
+        hipHostMalloc((void **)&e->pinned, e->h2d_bytes + 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        e->release();
+        return false;
+    }
+    hipStream_t user = ctx->stream;
+    ctx->arena = (char *)e->arena;
+    ctx->arena_size = arena_bytes;
+    ctx->arena_off = ctx->arena_peak = 0;
+    ctx->cap_mode = gss_ctx_s::CAP_CAPTURE;
+    ctx->tape = e->tape;
+    ctx->tape_pos = 0;
+    ctx->pending.clear();
+    ctx->cap_host = e->pinned;
+    ctx->cap_host_size = e->h2d_bytes + 64;
+    ctx->cap_host_off = 0;
+    ctx->cap_flag = e->flag;
+    ctx->stream = ctx->cap_stream;
+    ctx->cap_checks = 0;
+    std::string why;
+    const hipError_t eb = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
+    bool ok = eb == hipSuccess;
+    if (!ok) why = std::string("begin: ") + hipGetErrorString(eb);
+    if (ok) {
+        try {
+            fill_bytes(ctx, e->flag, 0, sizeof(uint32_t));
+            std::vector<gss_info> tmp((size_t)std::max<int32_t>(ninfo, 1));
+            const gss_status s = fn(tmp.data());
+            ok = s == e->status && ctx->tape_pos == ctx->tape.size() && ctx->pending.empty();
+            if (!ok)
+                why = "the capturing call left the recorded path (status " + std::to_string(s) + ", tape " +
+                      std::to_string(ctx->tape_pos) + "/" + std::to_string(ctx->tape.size()) + ")";
+        } catch (const gss_error &x) {
+            ok = false;
+            why = "exception: " + x.msg;
+        } catch (...) {
+            ok = false;
+            why = "exception";
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (ee != hipSuccess) {
+            if (ok) why = std::string("end: ") + hipGetErrorString(ee);
+            ok = false;
+        }
+        e->graph = g;
+    }
+    (void)hipGetLastError();
+    ctx->stream = user;
+    ctx->cap_mode = gss_ctx_s::CAP_OFF;
+    ctx->arena = nullptr;
+    ctx->arena_size = ctx->arena_off = ctx->arena_peak = 0;
+    ctx->tape.clear();
+    ctx->tape_pos = 0;
+    ctx->pending.clear();
+    ctx->cap_host = nullptr;
+    ctx->cap_host_size = ctx->cap_host_off = 0;
+    ctx->cap_flag = nullptr;
+    if (ok && e->graph) {
+        const hipError_t ei = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            ok = false;
+            why = std::string("instantiate: ") + hipGetErrorString(ei);
+        }
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        e->release();
+        ctx->last_error = "graph capture abandoned, the call ran eagerly: " + why;
+    }
+    return ok;
+}
+
+// runs fn(infos) (a recovery writing ninfo infos) eagerly, or records, captures or
+// replays it as the key's history says
+template <typename F>
+gss_status memoized(gss_ctx ctx, gss_tree t, std::vector<uint8_t> key, int32_t ninfo, gss_info *infos, F &&fn)
+{
+    if (!ctx->capture_on || ctx->record || ctx->prof || ctx->arena || ctx->cap_mode != gss_ctx_s::CAP_OFF)
+        return fn(infos);
+    GraphEntry *e = nullptr;
+    for (GraphEntry *x : ctx->graphs)
+        if (x->t == t && x->key == key) e = x;
+    auto deliver = [&](GraphEntry *x) {
+        if (infos) std::copy(x->infos.begin(), x->infos.begin() + ninfo, infos);
+        return x->status;
+    };
+    if (e && e->exec) {
+        if (replay(ctx, e)) {
+            ctx->n_replays++;
+            return deliver(e);
+        }
+        drop_entry(ctx, e);  // never expected: the recovery is deterministic
+        e = nullptr;
+    }
+    if (e && !e->no_capture) {
+        if (capture(ctx, e, ninfo, fn) && replay(ctx, e)) {
+            ctx->n_captures++;
+            return deliver(e);
+        }
+        e->release();
+        e->no_capture = true;
+    }
+    if (e) return fn(infos);
+    // recording
+    std::vector<gss_info> tmp((size_t)std::max<int32_t>(ninfo, 1));
+    ctx->cap_mode = gss_ctx_s::CAP_RECORD;
+    ctx->tape.clear();
+    ctx->tape_pos = 0;
+    ctx->pending.clear();
+    ctx->arena_off = ctx->arena_peak = 0;
+    ctx->rec_h2d = 0;
+    gss_status s;
+    try {
+        s = fn(tmp.data());
+    } catch (...) {
+        ctx->cap_mode = gss_ctx_s::CAP_OFF;
+        ctx->tape.clear();
+        ctx->pending.clear();
+        ctx->arena_off = ctx->arena_peak = 0;
+        throw;
+    }
+    ctx->cap_mode = gss_ctx_s::CAP_OFF;
+    GraphEntry *n = new GraphEntry();
+    n->t = t;
+    n->key = std::move(key);
+    n->tape.swap(ctx->tape);
+    n->arena_bytes = ctx->arena_peak;
+    n->h2d_bytes = ctx->rec_h2d;
+    ctx->arena_off = ctx->arena_peak = 0;
+    n->infos.assign(tmp.begin(), tmp.begin() + ninfo);
+    n->status = s;
+    if (ctx->graphs.size() >= MAX_GRAPHS) drop_entry(ctx, ctx->graphs.front());
+    ctx->graphs.push_back(n);
+    ctx->n_records++;
+    return deliver(n);
+}
+
+void drop_tree_graphs(gss_ctx ctx, gss_tree t)
+{
+    std::vector<GraphEntry *> gone;
+    for (GraphEntry *x : ctx->graphs)
+        if (x->t == t) gone.push_back(x);
+    for (GraphEntry *x : gone) drop_entry(ctx, x);
+}
+}  // namespace
+
 // frees a tree, its parts and the arrays it owns
 static void delete_tree(gss_tree t)
 {
@@ -179,6 +414,8 @@ gss_status gss_ctx_destroy(gss_ctx ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
+    while (!ctx->graphs.empty()) drop_entry(ctx, ctx->graphs.back());
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->pool.release_all();
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
@@ -321,7 +558,8 @@ gss_status gss_recover_batch(gss_ctx ctx, gss_tree t, const gss_params *params, 
     return guarded(ctx, [&]() -> gss_status {
         HIP_OK(hipSetDevice(ctx->device));
         ctx->record = (params[0].flags & GSS_F_RECORD) != 0;
-        gss_status s = recover_batch_impl(ctx, t, params, masks, orders, infos);
+        gss_status s = memoized(ctx, t, graph_key(ctx, t, t->G, params, masks, orders, nullptr), t->G, infos,
+                                [&](gss_info *inf) { return recover_batch_impl(ctx, t, params, masks, orders, inf); });
         ctx->record = false;
         return s;
     });
@@ -356,6 +594,7 @@ gss_status gss_tree_free(gss_tree t)
 {
     if (!t) return GSS_ERR_ARG;
     (void)hipStreamSynchronize(t->ctx->stream);
+    drop_tree_graphs(t->ctx, t);
     delete_tree(t);
     return GSS_OK;
 }
@@ -378,7 +617,10 @@ gss_status gss_recover(gss_ctx ctx, gss_tree t, const gss_params *p, uint8_t *ma
             throw gss_error{GSS_ERR_ARG, "a batch tree needs gss_recover_batch"};
         uint8_t *masks[1] = {mask};
         int32_t *orders[1] = {order};
-        gss_status s = recover_impl(ctx, t, p, masks, order ? orders : nullptr, stretch, info);
+        gss_status s = memoized(ctx, t, graph_key(ctx, t, 1, p, masks, order ? orders : nullptr, stretch), 1, info,
+                                [&](gss_info *inf) {
+                                    return recover_impl(ctx, t, p, masks, order ? orders : nullptr, stretch, inf);
+                                });
         ctx->record = false;
         return s;
     });
@@ -495,6 +737,45 @@ gss_status gss_ctx_set_sort(gss_ctx ctx, int32_t radix, int32_t bucket_cap)
         return GSS_ERR_ARG;
     ctx->sort_radix = radix != 0;
     ctx->sort_cap = bucket_cap;
+    return GSS_OK;
+}
+
+gss_status gss_spanning_tree(gss_ctx ctx, const gss_csr *g, uint32_t flags, int32_t *parent, int32_t *root,
+                             double *weff)
+{
+    if (!ctx || !g || !parent || !root || (flags & ~GSS_TREE_WEIGHT) != 0) return GSS_ERR_ARG;
+    if (g->n < 1 || g->nnz < 0 || g->nnz >= ((int64_t)1 << 31) || g->n >= (1 << 30) || !g->row_ptr ||
+        (g->nnz > 0 && (!g->col || !g->w)))
+        return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        spanning_tree_impl(ctx, g, parent, root, weff, flags);
+        return GSS_OK;
+    });
+}
+
+gss_status gss_ctx_set_capture(gss_ctx ctx, int32_t enable)
+{
+    if (!ctx || (enable != 0 && enable != 1)) return GSS_ERR_ARG;
+    return guarded(ctx, [&]() -> gss_status {
+        HIP_OK(hipSetDevice(ctx->device));
+        if (!enable) {
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+            while (!ctx->graphs.empty()) drop_entry(ctx, ctx->graphs.back());
+        }
+        ctx->capture_on = enable != 0;
+        return GSS_OK;
+    });
+}
+
+gss_status gss_ctx_capture_stats(gss_ctx ctx, int64_t *records, int64_t *captures, int64_t *replays,
+                                 int64_t *syncs)
+{
+    if (!ctx) return GSS_ERR_ARG;
+    if (records) *records = ctx->n_records;
+    if (captures) *captures = ctx->n_captures;
+    if (replays) *replays = ctx->n_replays;
+    if (syncs) *syncs = ctx->n_syncs;
     return GSS_OK;
 }
 

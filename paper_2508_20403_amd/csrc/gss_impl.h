@@ -50,6 +50,8 @@ struct prof_sum {
     double last_ms = 0;  // the latest launch
 };
 
+struct GraphEntry;  // a recorded (and possibly captured) recovery, gss_api.hip
+
 struct gss_ctx_s {
     // live kernel timing with HIP events on the context stream (off by default)
     bool prof = false;
@@ -113,12 +115,42 @@ struct gss_ctx_s {
     char *arena = nullptr;
     size_t arena_size = 0, arena_off = 0, arena_peak = 0;
 
+    // Memoized graph capture of recoveries (gss_ctx_set_capture).  A recording call runs
+    // eagerly and logs, in order, every value it reads back to the host (the tape) and
+    // the arena bytes its allocations would take.  A capturing call runs the same host
+    // code with the stream in capture mode: read-backs take their values from the tape
+    // (a kernel compares the device value with it and raises cap_flag on a difference),
+    // allocations come from a graph-owned arena, host data is staged in graph-owned
+    // pinned memory, and synchronisations are skipped.
+    enum { CAP_OFF = 0, CAP_RECORD = 1, CAP_CAPTURE = 2 };
+    bool capture_on = false;
+    int cap_mode = CAP_OFF;
+    std::vector<uint8_t> tape;
+    size_t tape_pos = 0;
+    std::vector<std::pair<void *, size_t>> pending;  // asynchronous read-backs, delivered at the next sync
+    size_t rec_h2d = 0;                              // recording: host-to-device bytes (64-byte units)
+    char *cap_host = nullptr;                        // capturing: the graph's pinned staging block
+    size_t cap_host_size = 0, cap_host_off = 0;
+    uint32_t *cap_flag = nullptr;                    // capturing: the graph's mismatch word
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry *> graphs;                // recorded and captured recoveries
+    int64_t n_syncs = 0, n_records = 0, n_captures = 0, n_replays = 0;
+    uint32_t cap_checks = 0;                         // capturing: read-back checks enqueued so far
+
     template <typename T>
     T *alloc(size_t count)
     {
         const size_t bytes = count * sizeof(T) + 16;
         if (arena) return (T *)arena_bump(bytes);
+        if (cap_mode == CAP_RECORD) arena_account(bytes);
         return (T *)pool.get(bytes);
+    }
+    // recording: the arena offset the same allocation would move to
+    void arena_account(size_t bytes)
+    {
+        const size_t off = (arena_off + 255) & ~(size_t)255;
+        arena_off = off + bytes;
+        if (arena_off > arena_peak) arena_peak = arena_off;
     }
     void *arena_bump(size_t bytes)
     {
@@ -135,7 +167,7 @@ struct gss_ctx_s {
     size_t arena_mark() const { return arena_off; }
     void arena_reset(size_t mark)
     {
-        if (arena) arena_off = mark;
+        if (arena || cap_mode == CAP_RECORD) arena_off = mark;
     }
     void free(void *p)
     {
@@ -144,16 +176,70 @@ struct gss_ctx_s {
         if (lb_lane == 1) aux_frees.push_back(p);  // still in use by the auxiliary stream
         else pool.put(p);
     }
+    // waits for the stream (skipped while capturing); asynchronous read-backs are
+    // delivered (recording: appended to the tape; capturing: taken from it)
     void sync()
     {
-        HIP_OK(hipStreamSynchronize(stream));
-        if (aux && stream != aux) HIP_OK(hipStreamSynchronize(aux));
-        stage_off = 0;
+        if (cap_mode != CAP_CAPTURE) {
+            HIP_OK(hipStreamSynchronize(stream));
+            if (aux && stream != aux) HIP_OK(hipStreamSynchronize(aux));
+            stage_off = 0;
+            n_syncs++;
+        }
+        for (auto &pb : pending) tape_io(pb.first, pb.second);
+        pending.clear();
     }
+    // a tape entry: its length (4 bytes), then the bytes read back
+    void tape_io(void *dst, size_t bytes)
+    {
+        const uint32_t len = (uint32_t)bytes;
+        if (cap_mode == CAP_RECORD) {
+            tape.insert(tape.end(), (const uint8_t *)&len, (const uint8_t *)&len + sizeof len);
+            tape.insert(tape.end(), (const uint8_t *)dst, (const uint8_t *)dst + bytes);
+        } else if (cap_mode == CAP_CAPTURE) {
+            uint32_t rec = 0;
+            if (tape_pos + sizeof rec <= tape.size()) memcpy(&rec, tape.data() + tape_pos, sizeof rec);
+            if (tape_pos + sizeof rec + bytes > tape.size() || rec != len)
+                throw gss_error{GSS_ERR_HIP, "capture left the recorded path"};
+            memcpy(dst, tape.data() + tape_pos + sizeof rec, bytes);
+            tape_pos += sizeof rec + bytes;
+        }
+    }
+    // copies bytes device bytes to the host and waits for them.  words: the 8-byte words
+    // of the range the caller uses (bit i: word i; the first 64 words), the only ones a
+    // replay compares with the recording (the others may hold leftovers of other calls)
+    void readback(void *dst, const void *src, size_t bytes, uint64_t words = ~0ull)
+    {
+        if (cap_mode == CAP_CAPTURE) {
+            sync();  // delivers earlier asynchronous read-backs first, in the recorded order
+            tape_io(dst, bytes);
+            check_replay(src, dst, bytes, words);
+            return;
+        }
+        HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
+        sync();
+        tape_io(dst, bytes);
+    }
+    // the same, delivered by the next sync()
+    void readback_async(void *dst, const void *src, size_t bytes)
+    {
+        if (cap_mode != CAP_CAPTURE) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
+        pending.push_back({dst, bytes});
+    }
+    void check_replay(const void *dev, const void *expect, size_t bytes, uint64_t words);  // capturing
     // enqueues a copy of bytes host bytes to dst on the stream; src may be reused at once
     void h2d(void *dst, const void *src, size_t bytes)
     {
         if (bytes == 0) return;
+        if (cap_mode == CAP_RECORD) rec_h2d += (bytes + 63) & ~(size_t)63;
+        if (cap_mode == CAP_CAPTURE) {  // the graph reads its own pinned copy at every replay
+            if (cap_host_off + bytes > cap_host_size) throw gss_error{GSS_ERR_HIP, "capture staging overflow"};
+            char *h = cap_host + cap_host_off;
+            cap_host_off += (bytes + 63) & ~(size_t)63;
+            memcpy(h, src, bytes);
+            HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream));
+            return;
+        }
         if (!h_stage || bytes > STAGE_BYTES) {
             HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
             return;
@@ -256,6 +342,10 @@ void scan_exclusive_i32_dev(gss_ctx ctx, int32_t *data, int64_t n, int64_t *d_to
 // status array of at least `words` words for one look-back launch, its epoch, and the
 // ticket counter (always zero between launches)
 uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch);
+// feGRASS's spanning tree (gss_treegen.hip)
+void spanning_tree_impl(gss_ctx ctx, const gss_csr *g, int32_t *parent, int32_t *root, double *weff, uint32_t flags);
+// byte fill of device memory on the context stream by a kernel (capturable)
+void fill_bytes(gss_ctx ctx, void *p, int value, size_t bytes);
 inline unsigned long long *lb_ticket_ptr(gss_ctx ctx)
 {
     return (unsigned long long *)(ctx->d_counters + (ctx->lb_lane ? 31 : 15));

@@ -133,7 +133,7 @@ int64_t loose_greedy(gss_ctx ctx, int32_t n, int32_t vroot, int64_t P, int32_t c
                      const int32_t *ancV, uint8_t *state)
 {
     hipStream_t st = ctx->stream;
-    HIP_OK(hipMemsetAsync(state, 0, (size_t)P + 1, st));
+    fill_bytes(ctx, state, 0, (size_t)P + 1);
     if (P <= 0) return 0;
     const int64_t cells = (int64_t)n * (c + 1);
     int32_t *A = ctx->alloc<int32_t>(cells);
@@ -141,8 +141,8 @@ int64_t loose_greedy(gss_ctx ctx, int32_t n, int32_t vroot, int64_t P, int32_t c
     unsigned long long *rem = ctx->alloc<unsigned long long>(3);
     GSS_LAUNCH(k_lo_fill, dim3(std::min<unsigned>(grid_for(cells, LO_BLOCK), 4096u)), dim3(LO_BLOCK), 0, st, A,
                cells, INT_MAX);
-    HIP_OK(hipMemsetAsync(C, 0, (size_t)cells, st));
-    HIP_OK(hipMemsetAsync(rem, 0, 3 * sizeof(unsigned long long), st));
+    fill_bytes(ctx, C, 0, (size_t)cells);
+    fill_bytes(ctx, rem, 0, 3 * sizeof(unsigned long long));
     const dim3 g(grid_for(P, LO_BLOCK)), b(LO_BLOCK);
     // rounds are launched in growing groups; the undecided count is read after each group
     int64_t round = 0;
@@ -153,8 +153,7 @@ int64_t loose_greedy(gss_ctx ctx, int32_t n, int32_t vroot, int64_t P, int32_t c
             GSS_LAUNCH(k_lo_decide, g, b, 0, st, P, state, ancU, ancV, c, vroot, A, C);
             GSS_LAUNCH(k_lo_settle, g, b, 0, st, P, state, ancU, ancV, c, vroot, A, C, rem, (int32_t)round);
         }
-        HIP_OK(hipMemcpyAsync(h, rem, sizeof h, hipMemcpyDeviceToHost, st));
-        ctx->sync();
+        ctx->readback(h, rem, sizeof h);
         if (h[(round - 1) & 1] == 0) break;
     }
     HIP_OK(hipGetLastError());

@@ -212,11 +212,64 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_onepass(int32_t *__restrict
     }
 }
 
+// Byte fill by a kernel: 16-byte stores over the aligned middle, single bytes at the
+// ends.  A kernel rather than a runtime memset, so the recovery's launches can be
+// captured into a graph and replayed with the fills as ordinary kernel nodes.
+__global__ void k_fill_bytes(uint8_t *__restrict__ p, uint64_t bytes, uint32_t v4)
+{
+    const uint64_t head = min(bytes, (uint64_t)((16 - ((uintptr_t)p & 15)) & 15));
+    const uint64_t chunks = (bytes - head) / 16;
+    const uint64_t tail0 = head + chunks * 16;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint4 q = make_uint4(v4, v4, v4, v4);
+    uint4 *body = (uint4 *)(p + head);
+    for (uint64_t i = t; i < chunks; i += stride) body[i] = q;
+    if (t < head) p[t] = (uint8_t)v4;
+    if (t < bytes - tail0) p[tail0 + t] = (uint8_t)v4;
+}
+
+void fill_bytes(gss_ctx ctx, void *p, int value, size_t bytes)
+{
+    if (!p || bytes == 0) return;
+    const uint32_t v = (uint32_t)(value & 0xff) * 0x01010101u;
+    const unsigned blocks = (unsigned)std::min<uint64_t>(std::max<uint64_t>((bytes / 16 + 255) / 256, 1), 2048);
+    GSS_LAUNCH(k_fill_bytes, dim3(blocks), dim3(256), 0, ctx->stream, (uint8_t *)p, (uint64_t)bytes, v);
+}
+
+// capturing: compares replayed device bytes with the recorded ones, in chunks passed by
+// value, and raises the graph's mismatch word on a difference
+struct ReplayBytes {
+    uint8_t b[512];
+};
+__global__ void k_check_replay(const uint8_t *__restrict__ dev, uint32_t n, ReplayBytes expect, uint64_t words,
+                               uint32_t id, uint32_t *flag)
+{
+    const uint32_t i = threadIdx.x;
+    const bool bad = i < n && ((words >> (i / 8)) & 1) && dev[i] != expect.b[i];
+    if (__any(bad) && lane_id() == 0) atomicMax(flag, id);  // the last differing check (numbered from 1)
+}
+
+void gss_ctx_s::check_replay(const void *dev, const void *expect, size_t bytes, uint64_t words)
+{
+    gss_ctx ctx = this;
+    for (size_t off = 0; off < bytes; off += sizeof(ReplayBytes)) {
+        ReplayBytes e;
+        const size_t n = std::min(bytes - off, sizeof(ReplayBytes));
+        memcpy(e.b, (const uint8_t *)expect + off, n);
+        // chunk c covers words [c * 64, c * 64 + 64); the mask names the first 64 only
+        const uint64_t w = off == 0 ? words : ~0ull;
+        GSS_LAUNCH(k_check_replay, dim3(1), dim3(512), 0, stream, (const uint8_t *)dev + off, (uint32_t)n, e, w,
+                   ++cap_checks, cap_flag);
+    }
+}
+
 uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch)
 {
+    if (ctx->cap_mode == gss_ctx_s::CAP_RECORD) ctx->arena_account(sizeof(uint64_t) * words + 16);
     if (ctx->arena) {  // allocation-free call: a fresh, cleared status array from the arena
         uint64_t *s = ctx->alloc<uint64_t>(words);
-        HIP_OK(hipMemsetAsync(s, 0, sizeof(uint64_t) * words, ctx->stream));
+        fill_bytes(ctx, s, 0, sizeof(uint64_t) * words);
         *epoch = 1;
         return s;
     }
@@ -225,12 +278,12 @@ uint64_t *lb_begin(gss_ctx ctx, int64_t words, uint32_t *epoch)
         ctx->free(ctx->lb_status[l]);
         const int64_t cap = std::max<int64_t>(words, 1 << 16);
         ctx->lb_status[l] = ctx->alloc<uint64_t>(cap);
-        HIP_OK(hipMemsetAsync(ctx->lb_status[l], 0, sizeof(uint64_t) * cap, ctx->stream));
+        fill_bytes(ctx, ctx->lb_status[l], 0, sizeof(uint64_t) * cap);
         ctx->lb_cap[l] = cap;
         ctx->lb_epoch[l] = 0;
     }
     if (++ctx->lb_epoch[l] >= (1u << LB_EPOCH_BITS)) {
-        HIP_OK(hipMemsetAsync(ctx->lb_status[l], 0, sizeof(uint64_t) * ctx->lb_cap[l], ctx->stream));
+        fill_bytes(ctx, ctx->lb_status[l], 0, sizeof(uint64_t) * ctx->lb_cap[l]);
         ctx->lb_epoch[l] = 1;
     }
     *epoch = ctx->lb_epoch[l];
@@ -313,8 +366,6 @@ int64_t scan_exclusive_i32(gss_ctx ctx, int32_t *data, int64_t n, bool want_tota
     if (n <= 0) return 0;
     scan_exclusive_i32_dev(ctx, data, n, ctx->d_counters + 14);
     if (!want_total) return -1;
-    HIP_OK(hipMemcpyAsync(&ctx->h_counters[14], ctx->d_counters + 14, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, ctx->stream));
-    ctx->sync();
+    ctx->readback(&ctx->h_counters[14], ctx->d_counters + 14, sizeof(int64_t));
     return ctx->h_counters[14];
 }

@@ -1251,11 +1251,10 @@ static RmqView rmq_view(gss_tree t)
     return q;
 }
 
-static void read_counters(gss_ctx ctx, int nwords)
+// reads counter words [0, nwords) back; `used` names the words the caller uses
+static void read_counters(gss_ctx ctx, int nwords, uint64_t used)
 {
-    HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, sizeof(int64_t) * nwords, hipMemcpyDeviceToHost,
-                          ctx->stream));
-    ctx->sync();
+    ctx->readback(ctx->h_counters, ctx->d_counters, sizeof(int64_t) * nwords, used);
 }
 
 // Stable LSD radix sort of (key, val) pairs by key ascending, with no host round trip.
@@ -1269,7 +1268,7 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     hipStream_t st = ctx->stream;
     const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
     int32_t *ghist = ctx->alloc<int32_t>(8 * 256);
-    HIP_OK(hipMemsetAsync(ghist, 0, sizeof(int32_t) * 8 * 256, st));
+    fill_bytes(ctx, ghist, 0, sizeof(int32_t) * 8 * 256);
     GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n,
                  ghist);
     const int npos = key_bytes > 0 ? key_bytes : 8;
@@ -1341,8 +1340,7 @@ static void count_candidates(gss_ctx ctx, int32_t G, int64_t P, PrefixBufs &B, P
     int64_t *cg = ctx->alloc<int64_t>(G);
     GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, cg);
     res.cand.assign(G, 0);
-    HIP_OK(hipMemcpyAsync(res.cand.data(), cg, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
-    ctx->sync();
+    ctx->readback(res.cand.data(), cg, sizeof(int64_t) * G);
     if (res.rounds_pending) res.rounds = ctx->h_counters[12];
     ctx->free(cg);
 }
@@ -1379,8 +1377,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         int64_t *before = ctx->alloc<int64_t>(G + 1);
         GSS_LAUNCH(k_prefix_before, dim3(G + 1), dim3(256), 0, st, key, M, off_g, thr, t->d_obase, pc, P, before);
         std::vector<int64_t> hb(G + 1);
-        HIP_OK(hipMemcpyAsync(hb.data(), before, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, st));
-        ctx->sync();
+        ctx->readback(hb.data(), before, sizeof(int64_t) * (G + 1));
         for (int32_t g = 0; g < G; g++) res.Pg[g] = hb[g + 1] - hb[g];
         ctx->free(before);
     } else {
@@ -1453,7 +1450,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     // everything sized by it takes the bound P instead
     int64_t *d_nsub = ctx->d_counters + 14;
     if (P > 0) scan_exclusive_i32_dev(ctx, hid, P, d_nsub);
-    else HIP_OK(hipMemsetAsync(d_nsub, 0, sizeof(int64_t), st));
+    else fill_bytes(ctx, d_nsub, 0, sizeof(int64_t));
     const int32_t cap = (int32_t)P;  // nsub <= P
     B.sub_ptr = ctx->alloc<int32_t>(P + 1);
     B.sub_lca = ctx->alloc<int32_t>(P + 1);
@@ -1477,7 +1474,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     uint64_t *qk = ctx->alloc<uint64_t>(P + 1), *qk2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *qv = ctx->alloc<int32_t>(P + 1), *qv2 = ctx->alloc<int32_t>(P + 1);
     int32_t *is_local = ctx->alloc<int32_t>(P + 1);
-    HIP_OK(hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(int64_t), st));
+    fill_bytes(ctx, ctx->d_counters + 4, 0, 4 * sizeof(int64_t));
     // queue keys: cost in the low cost_bits (sizes are at most P; predicted costs are float
     // bits), the on-join-path flag above them
     int cost_bits = 1;
@@ -1489,7 +1486,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                         (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
                         (unsigned long long *)(ctx->d_counters + 6));
     sort_pairs(ctx, qk, qv, qk2, qv2, P, bytes_for(((uint64_t)3 << cost_bits) - 1));
-    read_counters(ctx, 15);  // words 0..14: the queue split, the subtask count, the prefix length
+    // words 4 and 6: the queue split; 14: the subtask count; 13: the prefix length (one graph)
+    read_counters(ctx, 15, (1ull << 4) | (1ull << 6) | (1ull << 14) | (p_known ? 1ull << 13 : 0ull));
     if (p_known && ctx->h_counters[13] != P) {
         for (void *p : scratch) ctx->free(p);
         throw gss_error{GSS_ERR_HIP, "prefix length differs from the selection"};
@@ -1518,9 +1516,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         if (ctx->record) {
             cycles = ctx->alloc<uint64_t>(nsub + 1);
             scratch.push_back(cycles);
-            HIP_OK(hipMemsetAsync(cycles, 0, sizeof(uint64_t) * (nsub + 1), st));
+            fill_bytes(ctx, cycles, 0, sizeof(uint64_t) * (nsub + 1));
         }
-        HIP_OK(hipMemsetAsync(ctx->d_counters + 5, 0, sizeof(int64_t), st));
+        fill_bytes(ctx, ctx->d_counters + 5, 0, sizeof(int64_t));
         SubtaskArgs a;
         a.P = P;
         a.grp = B.grp;
@@ -1586,11 +1584,11 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         int32_t *arc_off = ctx->alloc<int32_t>(nparts + 1);
         {
             int2 *arc_buf = ctx->alloc<int2>((int64_t)nparts * arc_slot);
-            HIP_OK(hipMemsetAsync(B.indeg, 0, sizeof(int32_t) * (P + 1), st));
+            fill_bytes(ctx, B.indeg, 0, sizeof(int32_t) * (P + 1));
             GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(nparts), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, nparts, d_total,
                          arc_slot, arc_buf, arc_cnt, B.indeg, (const int32_t *)nullptr);
             GSS_LAUNCH(k_jp_offsets, dim3(1), dim3(1024), 0, st, arc_cnt, nparts, arc_off, ctx->d_counters);
-            read_counters(ctx, 4);
+            read_counters(ctx, 4, (1ull << 0) | (1ull << 3));
             const int64_t most = ctx->h_counters[3];
             const int64_t A = ctx->h_counters[0];
             // partitions with more arcs than their slice: joined again into a buffer of their own
@@ -1599,8 +1597,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             int32_t ov_size = 0;
             if (most > arc_slot) {
                 std::vector<int32_t> hc(nparts), slot(nparts, -1), list;
-                HIP_OK(hipMemcpyAsync(hc.data(), arc_cnt, sizeof(int32_t) * nparts, hipMemcpyDeviceToHost, st));
-                ctx->sync();
+                ctx->readback(hc.data(), arc_cnt, sizeof(int32_t) * nparts);
                 for (int32_t q = 0; q < nparts; q++)
                     if (hc[q] > arc_slot) {
                         slot[q] = (int32_t)list.size();
@@ -1610,13 +1607,11 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                 ov_slot = ctx->alloc<int32_t>(nparts);
                 ov_parts = ctx->alloc<int32_t>(list.size());
                 ov_buf = ctx->alloc<int2>((int64_t)list.size() * ov_size);
-                HIP_OK(hipMemcpyAsync(ov_slot, slot.data(), sizeof(int32_t) * nparts, hipMemcpyHostToDevice, st));
-                HIP_OK(hipMemcpyAsync(ov_parts, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice,
-                                      st));
+                ctx->h2d(ov_slot, slot.data(), sizeof(int32_t) * nparts);
+                ctx->h2d(ov_parts, list.data(), sizeof(int32_t) * list.size());
                 GSS_LAUNCH(k_jp_join, dim3((unsigned)list.size()), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, nparts,
                            d_total,
                            ov_size, ov_buf, arc_cnt, B.indeg, (const int32_t *)ov_parts);
-                ctx->sync();  // the host vectors are the copies' sources
             }
             int2 *arcs = ctx->alloc<int2>(A + 1);
             if (A > 0)
@@ -1627,12 +1622,12 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             ctx->free(ov_parts);
             ctx->free(ov_buf);
             res.arcs = A;
-            HIP_OK(hipMemsetAsync(B.mcnt, 0, sizeof(int32_t) * (P + 1), st));
+            fill_bytes(ctx, B.mcnt, 0, sizeof(int32_t) * (P + 1));
             GSS_LAUNCH(k_state_init, dim3(grid_for(nglobal_edges, RB)), dim3(RB), 0, st, nglobal_edges, B.glist,
                        B.indeg, B.state);
             if (A > 0) {
                 int2 *arcs2 = ctx->alloc<int2>(A + 1);
-                HIP_OK(hipMemsetAsync(ctx->d_counters + 2, 0, sizeof(int64_t), st));
+                fill_bytes(ctx, ctx->d_counters + 2, 0, sizeof(int64_t));
                 GSS_LAUNCH(k_arc_settle, dim3(grid_for(A, RB)), dim3(RB), 0, st, A, arcs, B.indeg, B.state);
                 GSS_LAUNCH(k_arc_compact, dim3(grid_for(A, RB)), dim3(RB), 0, st, A, arcs, B.state, arcs2,
                            (unsigned long long *)(ctx->d_counters + 2));
@@ -1640,7 +1635,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                 int32_t *rf = nullptr;
                 if (A >= RES_GRID_MIN) {  // many arcs: grid-wide rounds first
                     rf = ctx->alloc<int32_t>(2 + RES_GRID_ROUNDS);
-                    HIP_OK(hipMemsetAsync(rf, 0, sizeof(int32_t) * (2 + RES_GRID_ROUNDS), st));
+                    fill_bytes(ctx, rf, 0, sizeof(int32_t) * (2 + RES_GRID_ROUNDS));
                     const dim3 g((unsigned)std::min<int64_t>(grid_for(A, RB), 4096));
                     for (int r = 0; r < RES_GRID_ROUNDS; r++) {
                         GSS_LAUNCH(k_round_mark, g, dim3(RB), 0, st, dA, arcs2, B.state, B.mcnt, rf, r);
@@ -1652,8 +1647,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
                            (const int32_t *)rf, ctx->d_counters + 1);
                 if (rf) ctx->free(rf);
                 // rounds (for the info record) arrive with the next synchronisation
-                HIP_OK(hipMemcpyAsync(&ctx->h_counters[12], ctx->d_counters + 1, sizeof(int64_t),
-                                      hipMemcpyDeviceToHost, st));
+                ctx->readback_async(&ctx->h_counters[12], ctx->d_counters + 1, sizeof(int64_t));
                 res.rounds_pending = true;
                 ctx->free(arcs2);
             }
@@ -1722,7 +1716,7 @@ static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint
     S.thr = (uint64_t *)(dstate + 6 * G);
     S.active = (int32_t *)(dstate + 7 * G);
     if (refining > 0) {
-        if (!hist_ready || G > 1) HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS * G, st));
+        if (!hist_ready || G > 1) fill_bytes(ctx, hist, 0, sizeof(uint32_t) * SEL_BINS * G);
         for (int lv = 0; lv < LEVELS; lv++) {
             if (lv > 0 || !hist_ready || G > 1)
                 GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key, t->M,
@@ -1732,8 +1726,7 @@ static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint
         }
     }
     HIP_OK(hipMemcpyAsync(dthr, S.thr, sizeof(uint64_t) * G, hipMemcpyDeviceToDevice, st));
-    HIP_OK(hipMemcpyAsync(plen.data(), S.plen, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st));
-    ctx->sync();
+    ctx->readback(plen.data(), S.plen, sizeof(int64_t) * G);
     ctx->free(dstate);
 }
 
@@ -1760,15 +1753,15 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         K[g] = target_count(t, g, &prms[g]);
         mg[g] = t->ebase[g + 1] - t->ebase[g];
         eligible[g] = t->Mg[g];
-        HIP_OK(hipMemsetAsync(masks[g], 0, (size_t)mg[g], st));
+        fill_bytes(ctx, masks[g], 0, (size_t)mg[g]);
         if (prms[g].flags & GSS_F_MASK_TREE) {
             int32_t x0 = (int32_t)t->vbase[g], x1 = (int32_t)t->vbase[g + 1];
             GSS_LAUNCH(k_mask_tree, dim3(grid_for(x1 - x0, RB)), dim3(RB), 0, st, t->tree_eid, x0, x1, t->ebase[g],
                        masks[g]);
         }
     }
-    if (stretch) HIP_OK(hipMemsetAsync(stretch, 0, sizeof(double) * (size_t)t->m, st));
-    HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+    if (stretch) fill_bytes(ctx, stretch, 0, sizeof(double) * (size_t)t->m);
+    fill_bytes(ctx, ctx->d_flags, 0, sizeof(uint32_t));
 
     uint64_t *key = ctx->alloc<uint64_t>(M + 1);
     int32_t *lca = ctx->alloc<int32_t>(M + 1);
@@ -1777,8 +1770,8 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     // per-LCA edge counts: subtask statistics, and two of the cost model's features
     const bool need_lca_counts = (prms[0].flags & GSS_F_STATS) != 0;
     int32_t *lcacnt = need_lca_counts ? ctx->alloc<int32_t>(n) : nullptr;
-    HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
-    if (lcacnt) HIP_OK(hipMemsetAsync(lcacnt, 0, sizeof(int32_t) * n, st));
+    fill_bytes(ctx, hist, 0, sizeof(uint32_t) * SEL_BINS);
+    if (lcacnt) fill_bytes(ctx, lcacnt, 0, sizeof(int32_t) * n);
     // per off-tree edge: u, v, w (16 B); first, depth and D of u and v and D of the LCA
     // (56 B); the two LCA-sequence entries that answer the range minimum (16 B); key, LCA and
     // beta* written (13 B); optional stretch (8 B)
@@ -1798,19 +1791,17 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         for (int32_t g = 0; g < G; g++) nsubg[g] = largest[g] = -1;
     } else if (G == 1) {
         int64_t init2[2] = {0, 0};
-        memcpy(ctx->h_counters + 2, init2, sizeof init2);
-        HIP_OK(hipMemcpyAsync(ctx->d_counters + 2, ctx->h_counters + 2, sizeof init2, hipMemcpyHostToDevice, st));
+        ctx->h2d(ctx->d_counters + 2, init2, sizeof init2);
         GSS_LAUNCH(k_lca_stats, dim3(std::min<int64_t>(grid_for(n, RB), 1024)), dim3(RB), 0, st, lcacnt, n,
                    ctx->d_counters + 2);
-        read_counters(ctx, 4);
+        read_counters(ctx, 4, (1ull << 2) | (1ull << 3));
         nsubg[0] = ctx->h_counters[2];
         largest[0] = ctx->h_counters[3];
     } else {
         int64_t *dst = ctx->alloc<int64_t>(2 * G);
         std::vector<int64_t> hs(2 * G);
         GSS_LAUNCH(k_lca_stats_g, dim3(G), dim3(RB), 0, st, lcacnt, t->d_vbase, dst);
-        HIP_OK(hipMemcpyAsync(hs.data(), dst, sizeof(int64_t) * 2 * G, hipMemcpyDeviceToHost, st));
-        ctx->sync();
+        ctx->readback(hs.data(), dst, sizeof(int64_t) * 2 * G);
         ctx->free(dst);
         for (int32_t g = 0; g < G; g++) {
             nsubg[g] = hs[2 * g];
@@ -1819,7 +1810,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     }
     // the range flag is fetched without waiting; it is checked after the first prefix is
     // resolved (that step synchronises, and nothing is written to the outputs before it)
-    HIP_OK(hipMemcpyAsync(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    ctx->readback_async(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t));
     bool flags_checked = false;
     auto cleanup = [&]() {
         ctx->free(key);
@@ -1959,12 +1950,12 @@ void edge_lca_impl(gss_ctx ctx, gss_tree t, int32_t beta, int32_t *lca_out, int3
     if (lca_out) {
         GSS_LAUNCH(k_fill_i32_r, dim3(grid_for(m, RB)), dim3(RB), 0, st, lca_out, m, -1);
     }
-    if (b_out) HIP_OK(hipMemsetAsync(b_out, 0, sizeof(int32_t) * (size_t)m, st));
+    if (b_out) fill_bytes(ctx, b_out, 0, sizeof(int32_t) * (size_t)m);
     uint64_t *key = ctx->alloc<uint64_t>(M + 1);
     int32_t *lca = ctx->alloc<int32_t>(M + 1);
     uint8_t *bst = ctx->alloc<uint8_t>(M + 1);
     uint32_t *hist = ctx->alloc<uint32_t>(SEL_BINS);
-    HIP_OK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * SEL_BINS, st));
+    fill_bytes(ctx, hist, 0, sizeof(uint32_t) * SEL_BINS);
     if (M > 0) {
         GSS_LAUNCH(k_edge_stretch<false>, dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)),
                    dim3(RB), 0, st, M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, beta,

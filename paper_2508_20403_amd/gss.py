@@ -30,12 +30,14 @@ EXPORTS = ["gss_ctx_create", "gss_ctx_set_stream", "gss_ctx_destroy", "gss_tree_
            "gss_costmodel_train", "gss_costmodel_load", "gss_costmodel_save", "gss_costmodel_predict",
            "gss_costmodel_grad", "gss_batch_prep", "gss_recover_batch", "gss_tree_num_graphs",
            "gss_tree_graph_edges", "gss_autotune", "gss_ctx_set_batch_split", "gss_target_count",
-           "gss_ctx_set_rank_capacity", "gss_tree_rank_attempts", "gss_ctx_set_sort",
+           "gss_ctx_set_rank_capacity", "gss_tree_rank_attempts", "gss_ctx_set_sort", "gss_ctx_set_capture",
+           "gss_ctx_capture_stats", "gss_spanning_tree",
            "gss_recover_noalloc"]
 GSS_F_RECORD = 2
 GSS_F_STATS = 4
 GSS_F_KEY_RT = 8
 GSS_F_LOOSE = 16
+GSS_TREE_WEIGHT = 1
 NFEAT = 12
 COSTMODEL_FLOATS = 5081
 COSTMODEL_PARAMS = 5057
@@ -119,6 +121,12 @@ def load_library(path=LIB_PATH):
     lib.gss_recover_batch.argtypes = [P, P, P, P, P, P]
     lib.gss_ctx_set_sort.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.gss_ctx_set_sort.restype = ctypes.c_int32
+    lib.gss_spanning_tree.argtypes = [P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.c_int32), P]
+    lib.gss_spanning_tree.restype = ctypes.c_int32
+    lib.gss_ctx_set_capture.argtypes = [P, ctypes.c_int32]
+    lib.gss_ctx_set_capture.restype = ctypes.c_int32
+    lib.gss_ctx_capture_stats.argtypes = [P] + [ctypes.POINTER(ctypes.c_int64)] * 4
+    lib.gss_ctx_capture_stats.restype = ctypes.c_int32
     lib.gss_ctx_set_rank_capacity.argtypes = [P, ctypes.c_int32]
     lib.gss_ctx_set_rank_capacity.restype = ctypes.c_int32
     lib.gss_tree_rank_attempts.argtypes = [P]
@@ -196,6 +204,32 @@ class Context:
     def set_batch_split(self, own_nnz):
         """Batch graphs with at least own_nnz CSR entries are prepared on their own."""
         self.check(self.lib.gss_ctx_set_batch_split(self.handle, int(own_nnz)))
+
+    def spanning_tree(self, row_ptr, col, w, weight=False, want_weff=False):
+        """feGRASS's spanning tree on the GPU (gss_spanning_tree) of a device CSR: returns
+        (parent tensor, root, per-edge ordering weight tensor or None).  weight=True orders
+        the edges by w itself (a maximum-weight spanning tree)."""
+        n = row_ptr.numel() - 1
+        csr = Csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                  w.data_ptr() if w.numel() else None)
+        parent = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+        weff = torch.empty(max(col.numel() // 2, 1), dtype=torch.float64, device=row_ptr.device) if want_weff \
+            else None
+        root = ctypes.c_int32(-1)
+        self.check(self.lib.gss_spanning_tree(self.handle, ctypes.byref(csr), GSS_TREE_WEIGHT if weight else 0,
+                                              parent.data_ptr(), ctypes.byref(root), _ptr(weff)))
+        return parent, int(root.value), (weff[: col.numel() // 2] if weff is not None else None)
+
+    def set_capture(self, enable=True):
+        """Memoized graph capture of recoveries (gss_ctx_set_capture): a repeated call with the
+        same tree, parameters and output buffers replays a HIP graph."""
+        self.check(self.lib.gss_ctx_set_capture(self.handle, 1 if enable else 0))
+
+    def capture_stats(self):
+        """{records, captures, replays, syncs} counted since the context was created."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        self.check(self.lib.gss_ctx_capture_stats(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("records", "captures", "replays", "syncs"), (x.value for x in v)))
 
     def set_sort(self, radix=False, bucket_cap=0):
         """Short sorts by the radix sort (radix=True) or the sample sort with at most
