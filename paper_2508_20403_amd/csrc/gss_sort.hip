@@ -71,20 +71,89 @@ __device__ void ss_network(KP K, VP V, int S)
     }
 }
 
-// compare-exchange with a partner: the lower position keeps the smaller pair
+// compare-exchange with a partner, without branches: the lower position keeps the smaller
+// pair, the upper one the larger (equal pairs, the padding, need no exchange)
 __device__ __forceinline__ void ss_keep(uint64_t &k, uint32_t &v, uint64_t pk, uint32_t pv, bool lower)
 {
-    const bool take = lower ? ss_less(pk, pv, k, v) : ss_less(k, v, pk, pv);
-    if (take) {
-        k = pk;
-        v = pv;
+    const bool take = ss_less(pk, pv, k, v) == lower;
+    k = take ? pk : k;
+    v = take ? pv : v;
+}
+
+// the value of lane (lane ^ M) of the wavefront, M a constant below 64: quad permutes and
+// the row mirrors of DPP where they express it, the bitmask swizzle within 32 lanes
+// (source lane (lane & 31) ^ M) for the other masks below 32, a permute beyond
+template <int M>
+__device__ __forceinline__ uint32_t ss_lane_xor(uint32_t x)
+{
+    if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);  // [1,0,3,2]
+    else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);  // [2,3,0,1]
+    else if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x1B, 0xF, 0xF, true);  // [3,2,1,0]
+    else if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, true);  // half-row mirror
+    else if constexpr (M == 15) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, true);  // row mirror
+    else if constexpr (M < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (M << 10));
+    else return (uint32_t)__shfl_xor((int)x, M, GSS_WAVE);
+}
+
+// one step of the network: partner = position ^ M
+template <int E, int M>
+__device__ __forceinline__ void ss_step(uint64_t (&k)[E], uint32_t (&v)[E], uint64_t *ek, uint32_t *ev)
+{
+    const int t = threadIdx.x;
+    if constexpr (M < GSS_WAVE) {  // partner in the same wavefront
+        const bool lower = (t ^ M) > t;
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            const uint32_t lo = ss_lane_xor<M>((uint32_t)k[r]), hi = ss_lane_xor<M>((uint32_t)(k[r] >> 32));
+            const uint32_t pv = ss_lane_xor<M>(v[r]);
+            ss_keep(k[r], v[r], ((uint64_t)hi << 32) | lo, pv, lower);
+        }
+    } else if constexpr ((M & 1023) == 0) {  // same thread: registers r and r ^ (M >> 10)
+        constexpr int RM = M >> 10;
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            if (r & RM) continue;
+            const int q = r ^ RM;  // q > r: position q * 1024 + t is the higher one
+            const bool lt = ss_less(k[q], v[q], k[r], v[r]);
+            const uint64_t a = k[r], b = k[q];
+            const uint32_t av = v[r], bv = v[q];
+            k[r] = lt ? b : a;
+            v[r] = lt ? bv : av;
+            k[q] = lt ? a : b;
+            v[q] = lt ? av : bv;
+        }
+    } else {  // through LDS
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            ek[r * 1024 + t] = k[r];
+            ev[r * 1024 + t] = v[r];
+        }
+        __syncthreads();
+        uint64_t pk[E];
+        uint32_t pv[E];
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            const int q = (r * 1024 + t) ^ M;
+            pk[r] = ek[q];
+            pv[r] = ev[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; r++) ss_keep(k[r], v[r], pk[r], pv[r], (r * 1024 + t) < ((r * 1024 + t) ^ M));
     }
 }
 
-__device__ __forceinline__ uint64_t ss_shfl_xor64(uint64_t x, int m)
+// the steps (LK, LJ) of the one-direction bitonic network in order, unrolled at compile
+// time: merge size 2^LK from 1 to LG, distance 2^LJ from LK - 1 down to 0; the first
+// step of every merge compares mirrored positions
+template <int E, int LG, int LK, int LJ>
+__device__ __forceinline__ void ss_steps(uint64_t (&k)[E], uint32_t (&v)[E], uint64_t *ek, uint32_t *ev)
 {
-    const uint32_t lo = __shfl_xor((uint32_t)x, m, GSS_WAVE), hi = __shfl_xor((uint32_t)(x >> 32), m, GSS_WAVE);
-    return ((uint64_t)hi << 32) | lo;
+    if constexpr (LK <= LG) {
+        ss_step<E, (LJ == LK - 1) ? (2 << LJ) - 1 : (1 << LJ)>(k, v, ek, ev);
+        if constexpr (LJ > 0) ss_steps<E, LG, LK, LJ - 1>(k, v, ek, ev);
+        else ss_steps<E, LG, LK + 1, LK>(k, v, ek, ev);
+    }
 }
 
 // Sorts the 1024 * E pairs held in registers by a workgroup of 1024 threads (thread t
@@ -94,55 +163,7 @@ template <int E>
 __device__ void ss_reg_sort(uint64_t (&k)[E], uint32_t (&v)[E], uint64_t *ek, uint32_t *ev)
 {
     constexpr int LGE = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : 3;
-    constexpr int LG = 10 + LGE;
-    const int t = threadIdx.x;
-    for (int lk = 1; lk <= LG; lk++) {
-        for (int lj = lk - 1; lj >= 0; lj--) {
-            // partner = position ^ m: the mirror in the 2^lk block, or the position 2^lj away
-            const int m = (lj == lk - 1) ? (2 << lj) - 1 : 1 << lj;
-            if (m < GSS_WAVE) {
-#pragma unroll
-                for (int r = 0; r < E; r++) {
-                    const uint64_t pk = ss_shfl_xor64(k[r], m);
-                    const uint32_t pv = __shfl_xor(v[r], m, GSS_WAVE);
-                    ss_keep(k[r], v[r], pk, pv, (t ^ m) > t);
-                }
-            } else if ((m & 1023) == 0) {  // same thread: registers r and r ^ (m >> 10)
-                const int rm = m >> 10;
-#pragma unroll
-                for (int r = 0; r < E; r++) {
-                    if (r & rm) continue;
-                    const int q = r ^ rm;  // q > r: position q * 1024 + t is the higher one
-                    if (ss_less(k[q], v[q], k[r], v[r])) {
-                        const uint64_t tk = k[r];
-                        const uint32_t tv = v[r];
-                        k[r] = k[q];
-                        v[r] = v[q];
-                        k[q] = tk;
-                        v[q] = tv;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < E; r++) {
-                    ek[r * 1024 + t] = k[r];
-                    ev[r * 1024 + t] = v[r];
-                }
-                __syncthreads();
-                uint64_t pk[E];
-                uint32_t pv[E];
-#pragma unroll
-                for (int r = 0; r < E; r++) {
-                    const int q = (r * 1024 + t) ^ m;
-                    pk[r] = ek[q];
-                    pv[r] = ev[q];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < E; r++) ss_keep(k[r], v[r], pk[r], pv[r], (r * 1024 + t) < ((r * 1024 + t) ^ m));
-            }
-        }
-    }
+    ss_steps<E, 10 + LGE, 1, 0>(k, v, ek, ev);
 }
 
 // loads S <= 1024 E pairs (padded with the largest pair), sorts them in registers and
