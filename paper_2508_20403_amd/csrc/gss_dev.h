@@ -119,6 +119,17 @@ __device__ __forceinline__ bool u128_to_double_rne(u128 x, int scale, double *ou
 // wave helpers (wave64)
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (GSS_WAVE - 1)); }
+
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b mod 8), and every
+// XCD has an L2 of its own.  This bijection of [0, G) gives every XCD a contiguous range
+// of tiles, so tiles that read each other's neighbourhood (the rows of nearby vertices)
+// share an L2 instead of missing in eight.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G)
+{
+    constexpr int64_t X = 8;
+    const int64_t per = G / X, rem = G % X, xcd = b % X, idx = b / X;
+    return (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     int l = lane_id();

@@ -183,7 +183,8 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     __shared__ int32_t scol[ETILE];
     __shared__ int64_t sh[PB / GSS_WAVE];
     __shared__ int32_t s_prev[2];  // row and column of entry base-1 (-1 if none)
-    const int64_t base = (int64_t)blockIdx.x * ETILE;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = tile * ETILE;
     // every global load of the tile is issued before any is used
     int32_t cv[ENT_ITEMS];
     double wv[ENT_ITEMS];
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
         s_prev[0] = -1;
         s_prev[1] = -1;
         if (base > 0) {
-            const int32_t r0 = tile_row[blockIdx.x];
+            const int32_t r0 = tile_row[tile];
             const int32_t rc = r0 < 0 ? 0 : (r0 > n - 1 ? n - 1 : r0);
             // entry base-1 lies in row r0 exactly when that row starts before the tile
             if ((int64_t)row_ptr[rc] < base) s_prev[0] = rc;
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < PB / GSS_WAVE; i++) bal += sh[i];
-        bpart[blockIdx.x] = bal;  // per-block partial sums (no contended atomics)
+        bpart[tile] = bal;  // per-tile partial sums (no contended atomics)
     }
 }
 
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ p
     int roots = 0;
     int32_t root = INT32_MAX;
     int emin = 1 << 30, emax = -(1 << 30);
-    for (int64_t xx = (int64_t)blockIdx.x * PB + threadIdx.x; xx < n; xx += (int64_t)gridDim.x * PB) {
+    for (int64_t xx = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x; xx < n; xx += (int64_t)gridDim.x * PB) {
         int32_t x = (int32_t)xx;
         int32_t p = parent[x];
         int32_t tp = -1, loc = -1;
@@ -1167,7 +1168,8 @@ __global__ __launch_bounds__(PB) void k_offtree(
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t s_wsum[ENT_ITEMS][NW];
     const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
-    const int64_t base = (int64_t)blockIdx.x * ETILE;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = tile * ETILE;
     int32_t cv[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
@@ -1200,7 +1202,7 @@ __global__ __launch_bounds__(PB) void k_offtree(
             int32_t t = 0;
             for (int i = 0; i < ENT_ITEMS; i++)
                 for (int w2 = 0; w2 < NW; w2++) t += s_wsum[i][w2];
-            tile_cnt[blockIdx.x] = t;
+            tile_cnt[tile] = t;
         }
         return;
     }
@@ -1218,7 +1220,7 @@ __global__ __launch_bounds__(PB) void k_offtree(
             const int64_t y = __shfl_up(x, d, GSS_WAVE);
             if (lane >= d) x += y;
         }
-        if (has) s_off[i][w2] = (int64_t)tile_cnt[blockIdx.x] + x - own;
+        if (has) s_off[i][w2] = (int64_t)tile_cnt[tile] + x - own;
     }
     __syncthreads();
     // batches: the graphs of the tile's first and last rows bound every entry's graph
@@ -1271,7 +1273,7 @@ __global__ void k_tree_eid(const int32_t *__restrict__ parent, const int32_t *__
                            const int32_t *__restrict__ ufirst, const int32_t *__restrict__ tpos,
                            int32_t n, int64_t m, int32_t *__restrict__ tree_eid, uint8_t *__restrict__ tflag)
 {
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t x = (int32_t)(xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
     if (x >= n) return;
     int32_t p = parent[x];
     if (p < 0 || tpos[x] < 0) {

@@ -154,7 +154,8 @@ __global__ __launch_bounds__(RB) void k_edge_stretch(
     // grid-stride over tiles of RB * EDGE_ITEMS edges, so the histogram is flushed once
     // per workgroup rather than once per tile
     const int64_t ntiles = (M + RB * EDGE_ITEMS - 1) / (RB * EDGE_ITEMS);
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t t0 = blockIdx.x; t0 < ntiles; t0 += gridDim.x) {
+        const int64_t tile = xcd_tile(t0, ntiles);  // contiguous edge ranges per XCD
         const int64_t base = tile * RB * EDGE_ITEMS + threadIdx.x;
         int64_t jj[EDGE_ITEMS];
         bool ok[EDGE_ITEMS];
