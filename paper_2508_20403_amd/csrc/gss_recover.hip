@@ -1716,18 +1716,26 @@ static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint
     S.pval = (uint64_t *)(dstate + 5 * G);
     S.thr = (uint64_t *)(dstate + 6 * G);
     S.active = (int32_t *)(dstate + 7 * G);
-    if (refining > 0) {
-        if (!hist_ready || G > 1) fill_bytes(ctx, hist, 0, sizeof(uint32_t) * SEL_BINS * G);
-        for (int lv = 0; lv < LEVELS; lv++) {
-            if (lv > 0 || !hist_ready || G > 1)
-                GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key, t->M,
-                           off_g, shifts[lv], widths[lv], S.pmask, S.pval, S.need, hist, S.active + lv);
-            GSS_LAUNCH(k_pick_update, dim3(G), dim3(1024), 0, st, hist, lv, shifts[lv], widths[lv],
-                       lv == LEVELS - 1 ? 1 : 0, S);
+    // the first two levels settle most selections; the state read back after them says
+    // whether the remaining levels are needed (one more read-back if so)
+    int lv = 0;
+    for (int upto : {2, LEVELS}) {
+        if (refining > 0) {
+            if (lv == 0 && (!hist_ready || G > 1)) fill_bytes(ctx, hist, 0, sizeof(uint32_t) * SEL_BINS * G);
+            for (; lv < upto; lv++) {
+                if (lv > 0 || !hist_ready || G > 1)
+                    GSS_LAUNCH(k_key_hist, dim3(std::min<int64_t>(grid_for(t->M, RB), 2048)), dim3(RB), 0, st, key,
+                               t->M, off_g, shifts[lv], widths[lv], S.pmask, S.pval, S.need, hist, S.active + lv);
+                GSS_LAUNCH(k_pick_update, dim3(G), dim3(1024), 0, st, hist, lv, shifts[lv], widths[lv],
+                           lv == LEVELS - 1 ? 1 : 0, S);
+            }
         }
+        ctx->readback(init.data(), dstate, sizeof(int64_t) * words);
+        refining = lv < LEVELS ? h_active[lv] : 0;
+        if (refining == 0) break;
     }
+    memcpy(plen.data(), h_plen, sizeof(int64_t) * G);
     HIP_OK(hipMemcpyAsync(dthr, S.thr, sizeof(uint64_t) * G, hipMemcpyDeviceToDevice, st));
-    ctx->readback(plen.data(), S.plen, sizeof(int64_t) * G);
     ctx->free(dstate);
 }
 
