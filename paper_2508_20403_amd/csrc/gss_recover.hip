@@ -522,7 +522,7 @@ __global__ void k_graph_key(int64_t P, const int32_t *__restrict__ pj, const int
 #define RS_TILE (RS_BLOCK * RS_ITEMS)
 
 // global digit counts of all eight byte positions: ghist[pos * 256 + digit] (zeroed)
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restrict__ k, int64_t n,
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restrict__ k, int64_t n, int npos,
                                                        int32_t *__restrict__ ghist)
 {
     __shared__ int32_t sh[8][256];
@@ -532,12 +532,13 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restric
     for (int64_t i = (int64_t)blockIdx.x * RS_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * RS_BLOCK) {
         const uint64_t kk = k[i];
 #pragma unroll
-        for (int p = 0; p < 8; p++) atomicAdd(&sh[p][(uint32_t)(kk >> (8 * p)) & 255u], 1);
+        for (int p = 0; p < 8; p++)
+            if (p < npos) atomicAdd(&sh[p][(uint32_t)(kk >> (8 * p)) & 255u], 1);
     }
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 8; p++) {
-        const int32_t c = sh[p][threadIdx.x];
+        const int32_t c = p < npos ? sh[p][threadIdx.x] : 0;
         if (c) atomicAdd(&ghist[p * 256 + threadIdx.x], c);
     }
 }
@@ -1270,9 +1271,9 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
     int32_t *ghist = ctx->alloc<int32_t>(8 * 256);
     fill_bytes(ctx, ghist, 0, sizeof(int32_t) * 8 * 256);
-    GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n,
-                 ghist);
     const int npos = key_bytes > 0 ? key_bytes : 8;
+    GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n, npos,
+                 ghist);
     for (int p = 0; p < npos; p++) {
         uint32_t epoch = 0;
         uint64_t *status = lb_begin(ctx, ntiles * 256, &epoch);
@@ -1291,7 +1292,8 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
 static void sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n,
                        int key_bytes = 0)
 {
-    if (n <= sample_sort_max() && !ctx->sort_radix) sample_sort_pairs(ctx, k, v, k2, v2, n);
+    // one-byte keys take one radix pass (two launches), fewer than the sample sort's five
+    if (n <= sample_sort_max() && !ctx->sort_radix && key_bytes != 1) sample_sort_pairs(ctx, k, v, k2, v2, n);
     else radix_sort_pairs(ctx, k, v, k2, v2, n, key_bytes);
 }
 
@@ -1478,15 +1480,16 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     fill_bytes(ctx, ctx->d_counters + 4, 0, 4 * sizeof(int64_t));
     // queue keys: cost in the low cost_bits (sizes are at most P; predicted costs are float
     // bits), the on-join-path flag above them
-    int cost_bits = 1;
-    while (cost_bits < 31 && ((int64_t)1 << cost_bits) <= P) cost_bits++;
+    // (the edge-count order uses the dense key of k_subtask_keys: cost_bits = 0)
+    int cost_bits = 0;
     if (pred) cost_bits = 32;
     // counters: queued subtasks in the low half of word 4, the lane-sized ones among them
     // in its high half, join-path edges in word 6
     launch_subtask_keys(ctx, d_nsub, cap, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
                         (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
                         (unsigned long long *)(ctx->d_counters + 6));
-    sort_pairs(ctx, qk, qv, qk2, qv2, P, bytes_for(((uint64_t)3 << cost_bits) - 1));
+    sort_pairs(ctx, qk, qv, qk2, qv2, P,
+               bytes_for(cost_bits == 0 ? 3 * ((uint64_t)local_max + 1) - 1 : ((uint64_t)3 << cost_bits) - 1));
     // words 4 and 6: the queue split; 14: the subtask count; 13: the prefix length (one graph)
     read_counters(ctx, 15, (1ull << 4) | (1ull << 6) | (1ull << 14) | (p_known ? 1ull << 13 : 0ull));
     if (p_known && ctx->h_counters[13] != P) {

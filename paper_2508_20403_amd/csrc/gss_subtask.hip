@@ -288,7 +288,10 @@ __global__ void k_group_ptr(int64_t P, const uint64_t *__restrict__ glca, const 
 
 // per subtask: queue key (descending cost first) and the local/global split.  The
 // subtask count nsub is read on the device; the queue has cap >= nsub slots and the ones
-// past nsub get the largest key, so a stable ascending sort leaves them last.
+// past nsub get the largest key, so a stable ascending sort leaves them last.  With
+// cost_bits = 0 (the edge-count order) the key is dense: class * (local_max + 1) +
+// (local_max - size), sizes of the join's subtasks clamped to local_max (their order is
+// never used), so small limits give one-byte keys.
 __global__ __launch_bounds__(256) void k_subtask_keys(const int64_t *__restrict__ nsubp, int32_t cap,
                                                       const int32_t *__restrict__ sub_ptr,
                                                       int32_t local_max, const float *__restrict__ pred,
@@ -314,12 +317,18 @@ __global__ __launch_bounds__(256) void k_subtask_keys(const int64_t *__restrict_
         // ascending sort of this key = queued subtasks for wavefronts, then those for
         // lanes, each by cost descending, then id (a stable sort of ids in order), then
         // the join's; cost < 2^cost_bits
-        const uint64_t cmask = ((uint64_t)1 << cost_bits) - 1;
         const uint64_t cls = loc ? (small ? 1 : 0) : 2;
-        qkey[s] = (cls << cost_bits) | ((~cost) & cmask);
+        if (cost_bits == 0) {
+            const uint64_t L = (uint64_t)local_max, c = cost < L ? cost : L;
+            qkey[s] = cls * (L + 1) + (L - c);
+        } else {
+            const uint64_t cmask = ((uint64_t)1 << cost_bits) - 1;
+            qkey[s] = (cls << cost_bits) | ((~cost) & cmask);
+        }
         qval[s] = s;
     } else if (s < cap) {
-        qkey[s] = ((uint64_t)2 << cost_bits) | (((uint64_t)1 << cost_bits) - 1);
+        qkey[s] = cost_bits == 0 ? 3 * ((uint64_t)local_max + 1) - 1
+                                 : ((uint64_t)2 << cost_bits) | (((uint64_t)1 << cost_bits) - 1);
         qval[s] = s;
     }
     // edges on the join path, queued and small subtasks: one atomic per workgroup each
