@@ -189,6 +189,15 @@ struct gss_ctx_s {
         for (auto &pb : pending) tape_io(pb.first, pb.second);
         pending.clear();
     }
+    // waits for the context stream only: the auxiliary stream keeps running, so the
+    // caller reads back only what the context stream produced (staging memory is kept)
+    void sync_stream()
+    {
+        if (cap_mode != CAP_CAPTURE) {
+            HIP_OK(hipStreamSynchronize(stream));
+            n_syncs++;
+        }
+    }
     // a tape entry: its length (4 bytes), then the bytes read back
     void tape_io(void *dst, size_t bytes)
     {
@@ -263,9 +272,6 @@ struct gss_tree_s {
     int32_t scale = 0;   // root resistances are integers in units of 2^scale
     int32_t rank_attempts = 0;  // list-ranking attempts (more than one after a capacity retry)
     // edges
-    int32_t *uptr = nullptr;     // [n+1] id of the first upper entry of each row
-    int32_t *ufirst = nullptr;   // [n] CSR index of the first upper entry of each row
-    int32_t *tpos = nullptr;     // [n] CSR index of (x, parent x) in row x, -1 at root
     int32_t *tree_eid = nullptr; // [n] edge id of (x, parent x), -1 at root
     // tree / Euler tour
     VRec *vrec = nullptr;        // [n] root resistance, preorder index, depth, parent

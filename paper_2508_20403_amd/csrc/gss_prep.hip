@@ -167,12 +167,14 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
 }
 
 
+// CSR checks: column range, strictly increasing rows, no self-loops, positive finite
+// weights, the mirror of every lower entry, and per tile the number of upper minus lower
+// entries.
 // Symmetry is checked exactly: every lower entry (u, c), c < u, must find its mirror
 // (c, u) in row c with the same weight, and the triangles must hold equally many entries.
 // Mirroring is injective, so with equal counts it is a bijection between the triangles:
 // every upper entry then has its mirror too.
-// column range, strictly increasing rows, no self-loops, positive finite weights, the
-// mirror of every lower entry, and per block the number of upper minus lower entries
+// Memory-safe on any input: rows are clamped.
 __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
         const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        cv[i] = k < nnz ? col[k] : 0;
+        cv[i] = k < nnz ? col[k] : -1;
         wv[i] = k < nnz ? w[k] : 1.0;
     }
     if (threadIdx.x == 0) {
@@ -211,63 +213,66 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     __syncthreads();
     uint32_t f = 0;
     int64_t bal = 0;  // upper minus lower entries
+    {
 #pragma unroll
-    for (int i = 0; i < ENT_ITEMS; i++) {
-        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        if (k >= nnz) continue;
-        const int32_t u = srow[k - base];
-        const int32_t c = cv[i];
-        if (c < 0 || c >= n) {
-            f |= F_ARG;
-            continue;
-        }
-        if (c == u) f |= F_NOT_SIMPLE;
-        // columns strictly increase within a row
-        const bool prev_same = (k > base) ? (srow[k - 1 - base] == u) : (s_prev[0] == u);
-        const int32_t pc = (k > base) ? scol[k - 1 - base] : s_prev[1];
-        if (prev_same && pc >= c) f |= F_NOT_SIMPLE;
-        const double x = wv[i];
-        if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
-        bal += (c > u) ? 1 : (c < u ? -1 : 0);
-    }
-    // The mirror (c, u) of every lower entry (u, c) is searched in row c.  The searches of
-    // eight entries run in lockstep so that their loads overlap: lo/hi bisect row c
-    // for the first column >= u.  Row bounds are clamped so malformed input stays in bounds.
-    constexpr int MB = 8;
-#pragma unroll 1
-    for (int h = 0; h < ENT_ITEMS; h += MB) {
-        int32_t lo[MB], hi[MB], end[MB], key[MB];
-#pragma unroll
-        for (int q = 0; q < MB; q++) {
-            const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
-            lo[q] = hi[q] = end[q] = 0;
-            key[q] = -1;
+        for (int i = 0; i < ENT_ITEMS; i++) {
+            const int64_t k = base + (int64_t)i * PB + threadIdx.x;
             if (k >= nnz) continue;
             const int32_t u = srow[k - base];
-            const int32_t c = scol[k - base];
-            if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
-            lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
-            hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
-            key[q] = u;
+            const int32_t c = cv[i];
+            if (c < 0 || c >= n) {
+                f |= F_ARG;
+                continue;
+            }
+            if (c == u) f |= F_NOT_SIMPLE;
+            // columns strictly increase within a row
+            const bool prev_same = (k > base) ? (srow[k - 1 - base] == u) : (s_prev[0] == u);
+            const int32_t pcol = (k > base) ? scol[k - 1 - base] : s_prev[1];
+            if (prev_same && pcol >= c) f |= F_NOT_SIMPLE;
+            const double x = wv[i];
+            if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
+            bal += (c > u) ? 1 : (c < u ? -1 : 0);
         }
-        for (;;) {
-            bool busy = false;
+        // The mirror (c, u) of every lower entry (u, c) is searched in row c.  The searches
+        // of eight entries run in lockstep so that their loads overlap: lo/hi bisect row c
+        // for the first column >= u.  Row bounds are clamped so malformed input stays in
+        // bounds.
+        constexpr int MB = 8;
+#pragma unroll 1
+        for (int h = 0; h < ENT_ITEMS; h += MB) {
+            int32_t lo[MB], hi[MB], end[MB], key[MB];
 #pragma unroll
             for (int q = 0; q < MB; q++) {
-                if (key[q] >= 0 && lo[q] < hi[q]) {
-                    const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
-                    if (col[mid] < key[q]) lo[q] = mid + 1;
-                    else hi[q] = mid;
-                    busy = true;
-                }
+                const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
+                lo[q] = hi[q] = end[q] = 0;
+                key[q] = -1;
+                if (k >= nnz) continue;
+                const int32_t u = srow[k - base];
+                const int32_t c = scol[k - base];
+                if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
+                lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
+                hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
+                key[q] = u;
             }
-            if (!__any(busy)) break;
-        }
+            for (;;) {
+                bool busy = false;
 #pragma unroll
-        for (int q = 0; q < MB; q++)
-            if (key[q] >= 0 && (lo[q] >= end[q] || col[lo[q]] != key[q] ||
-                                w[lo[q]] != w[base + (int64_t)(h + q) * PB + threadIdx.x]))
-                f |= F_ASYM;
+                for (int q = 0; q < MB; q++) {
+                    if (key[q] >= 0 && lo[q] < hi[q]) {
+                        const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
+                        if (col[mid] < key[q]) lo[q] = mid + 1;
+                        else hi[q] = mid;
+                        busy = true;
+                    }
+                }
+                if (!__any(busy)) break;
+            }
+#pragma unroll
+            for (int q = 0; q < MB; q++)
+                if (key[q] >= 0 && (lo[q] >= end[q] || col[lo[q]] != key[q] ||
+                                    w[lo[q]] != w[base + (int64_t)(h + q) * PB + threadIdx.x]))
+                    f |= F_ASYM;
+        }
     }
     for (int d = 32; d > 0; d >>= 1) {
         f |= __shfl_xor(f, d, GSS_WAVE);
@@ -300,132 +305,149 @@ __global__ __launch_bounds__(1024) void k_balance_total(const int64_t *__restric
     }
 }
 
-// first upper entry of each row and the number of upper entries.  Row bounds are
-// clamped to [0, nnz]: the entry checks run concurrently and are only read back later,
-// so malformed input must stay in bounds here.
-__global__ void k_rows(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t n,
-                       int64_t nnz, int32_t *__restrict__ ufirst, int32_t *__restrict__ ucnt)
+// Tree edges found from the child's side: the entry (x, c) of row x with c = parent[x] is
+// the tree edge of x.  Its position and resistance 1/w are recorded (tpos[x], tinv[x]).
+// Per tile: the number of tree edges found and the exponent range of their resistances,
+// written to part[tile] (no atomics on shared words; k_tree_total combines them).  One
+// streaming pass over the columns; a weight is read only where an entry matches.
+// Memory-safe on any input: rows are clamped and parent values are only compared.
+__global__ __launch_bounds__(PB) void k_tree_entries(const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ w,
+                                                     const int32_t *__restrict__ parent, int32_t n, int64_t nnz,
+                                                     const int32_t *__restrict__ tile_row,
+                                                     int32_t *__restrict__ tpos, double *__restrict__ tinv,
+                                                     int4 *__restrict__ part)
 {
-    int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    int64_t lo = clamp_idx(row_ptr[u], 0, nnz);
-    int64_t hi = clamp_idx(row_ptr[u + 1], lo, nnz), end = hi;
-    while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (col[mid] <= u) lo = mid + 1;
-        else hi = mid;
+    __shared__ int32_t srow[ETILE];
+    __shared__ int32_t sred[4][PB / GSS_WAVE];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = tile * ETILE;
+    int32_t cv[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        cv[i] = k < nnz ? col[k] : -1;
     }
-    ufirst[u] = (int32_t)lo;
-    ucnt[u] = (int32_t)(end - lo);
-}
-
-// parent checks, child counts (cloc[x] = x's place among its parent's children, -1 at a
-// root or a bad parent), tree-edge positions, the resistance 1/w of each tree edge
-// (tinv, 0 where there is none) and the exponent range of 1/w; a fixed grid
-// strides over the vertices and each block issues one set of atomics.  Memory-safe on
-// any CSR (row bounds clamped), so it runs before the CSR checks are read.
-__global__ __launch_bounds__(PB) void k_tree_check(const int32_t *__restrict__ parent,
-                                                   const int32_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ w,
-                                                   int32_t n, int64_t nnz, int32_t virt_root,
-                                                   int32_t *__restrict__ ccnt, int32_t *__restrict__ cloc,
-                                                   int32_t *__restrict__ tpos, double *__restrict__ tinv,
-                                                   uint32_t *flags, int64_t *counters)
-{
-    __shared__ int32_t sred[5][PB / GSS_WAVE];
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+    int32_t pu[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) pu[i] = cv[i] >= 0 ? parent[srow[i * PB + threadIdx.x]] : -1;
     uint32_t f = 0;
-    int roots = 0;
-    int32_t root = INT32_MAX;
+    int found = 0;
     int emin = 1 << 30, emax = -(1 << 30);
-    for (int64_t xx = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x; xx < n; xx += (int64_t)gridDim.x * PB) {
-        int32_t x = (int32_t)xx;
-        int32_t p = parent[x];
-        int32_t tp = -1, loc = -1;
-        double ti = 0.0;
-        if (p == -1) {
-            roots++;
-            root = min(root, x);
-        } else if (p < 0 || p >= n || p == x) {
-            f |= F_NOT_TREE;
-        } else if (p == virt_root) {
-            loc = atomicAdd(&ccnt[p], 1);  // zero-resistance link of a batch graph's root
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        if (cv[i] < 0 || cv[i] != pu[i]) continue;
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        const int32_t x = srow[i * PB + threadIdx.x];
+        found++;
+        const double t = 1.0 / w[k];
+        tpos[x] = (int32_t)k;
+        tinv[x] = t;
+        const int ef = (int)(((uint64_t)__double_as_longlong(t) >> 52) & 0x7ff);
+        if (ef == 0 || ef == 0x7ff) {
+            f |= F_RANGE;
         } else {
-            loc = atomicAdd(&ccnt[p], 1);
-            // row bounds clamped: the CSR checks are read back together with these
-            const int64_t lo = clamp_idx(row_ptr[x], 0, nnz);
-            int64_t k = find_in_row(col, lo, clamp_idx(row_ptr[x + 1], lo, nnz), p);
-            if (k < 0) {
-                f |= F_TREE_EDGE;
-            } else {
-                tp = (int32_t)k;
-                double t = 1.0 / w[k];
-                ti = t;
-                uint64_t b = (uint64_t)__double_as_longlong(t);
-                int ef = (int)((b >> 52) & 0x7ff);
-                if (ef == 0 || ef == 0x7ff) {
-                    f |= F_RANGE;
-                } else {
-                    emin = min(emin, ef - 1023);
-                    emax = max(emax, ef - 1023);
-                }
-            }
+            emin = min(emin, ef - 1023);
+            emax = max(emax, ef - 1023);
         }
-        tpos[x] = tp;
-        tinv[x] = ti;
-        cloc[x] = loc;
     }
     for (int d = 32; d > 0; d >>= 1) {
         f |= __shfl_xor(f, d, GSS_WAVE);
-        roots += __shfl_xor(roots, d, GSS_WAVE);
-        root = min(root, __shfl_xor(root, d, GSS_WAVE));
+        found += __shfl_xor(found, d, GSS_WAVE);
         emin = min(emin, __shfl_xor(emin, d, GSS_WAVE));
         emax = max(emax, __shfl_xor(emax, d, GSS_WAVE));
     }
     const int wid = threadIdx.x / GSS_WAVE;
     if (lane_id() == 0) {
         sred[0][wid] = (int32_t)f;
-        sred[1][wid] = roots;
-        sred[2][wid] = root;
-        sred[3][wid] = emin;
-        sred[4][wid] = emax;
+        sred[1][wid] = found;
+        sred[2][wid] = emin;
+        sred[3][wid] = emax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < PB / GSS_WAVE; i++) {
             f |= (uint32_t)sred[0][i];
-            roots += sred[1][i];
-            root = min(root, sred[2][i]);
-            emin = min(emin, sred[3][i]);
-            emax = max(emax, sred[4][i]);
+            found += sred[1][i];
+            emin = min(emin, sred[2][i]);
+            emax = max(emax, sred[3][i]);
+        }
+        part[tile] = make_int4((int32_t)f, found, emin, emax);
+    }
+}
+
+// combines the per-tile results of k_tree_entries: flags, the number of tree edges found
+// (counters[4]) and the exponent range (counters[2], counters[3])
+__global__ __launch_bounds__(1024) void k_tree_total(const int4 *__restrict__ part, int64_t ntiles, uint32_t *flags,
+                                                     int64_t *counters)
+{
+    __shared__ int32_t sred[4][1024 / GSS_WAVE];
+    uint32_t f = 0;
+    int64_t found = 0;
+    int emin = 1 << 30, emax = -(1 << 30);
+    for (int64_t i = threadIdx.x; i < ntiles; i += 1024) {
+        const int4 p = part[i];
+        f |= (uint32_t)p.x;
+        found += p.y;
+        emin = min(emin, p.z);
+        emax = max(emax, p.w);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        f |= __shfl_xor(f, d, GSS_WAVE);
+        found += __shfl_xor(found, d, GSS_WAVE);
+        emin = min(emin, __shfl_xor(emin, d, GSS_WAVE));
+        emax = max(emax, __shfl_xor(emax, d, GSS_WAVE));
+    }
+    const int wid = threadIdx.x / GSS_WAVE;
+    if (lane_id() == 0) {
+        sred[0][wid] = (int32_t)f;
+        sred[1][wid] = (int32_t)found;  // per wave below 2^31: at most n tree edges
+        sred[2][wid] = emin;
+        sred[3][wid] = emax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 1024 / GSS_WAVE; i++) {
+            f |= (uint32_t)sred[0][i];
+            found += sred[1][i];
+            emin = min(emin, sred[2][i]);
+            emax = max(emax, sred[3][i]);
         }
         if (f) atomicOr(flags, f);
-        if (roots) {
-            atomicAdd((unsigned long long *)&counters[0], (unsigned long long)roots);
-            atomicMin((long long *)&counters[1], (long long)root);
-        }
+        counters[4] = found;
         if (emin <= emax) {
-            atomicMin((long long *)&counters[2], (long long)emin);
-            atomicMax((long long *)&counters[3], (long long)emax);
+            counters[2] = emin;
+            counters[3] = emax;
         }
     }
 }
 
-// children CSR: cslot holds each vertex's place among its siblings on entry (from the
-// tree check) and its position in clist on exit
-__global__ void k_children_fill(const int32_t *__restrict__ parent, int32_t n,
-                                const int32_t *__restrict__ cptr, int32_t *__restrict__ clist,
-                                int32_t *__restrict__ cslot)
+// Parent checks, roots, child counts and the children of every vertex as a list linked
+// by atomic exchange (fc[p] = the child that linked itself last, nsib[x] = the child
+// linked before x; the order of siblings is immaterial to every later result).  One
+// vertex per thread, so every thread's exchange is in flight at once; counter atomics
+// only where there is something to count (the root's block, or an error).
+__global__ __launch_bounds__(PB) void k_tree_vertices(const int32_t *__restrict__ parent, int32_t n,
+                                                      int32_t *__restrict__ ccnt, int32_t *__restrict__ fc,
+                                                      int32_t *__restrict__ nsib, uint32_t *flags, int64_t *counters)
 {
-    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    int32_t p = parent[x];
-    if (p < 0) {
-        cslot[x] = -1;
-        return;
+    const int64_t xx = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x;
+    if (xx >= n) return;
+    const int32_t x = (int32_t)xx;
+    const int32_t p = parent[x];
+    int32_t s = -1;
+    if (p == -1) {
+        atomicAdd((unsigned long long *)&counters[0], 1ull);
+        atomicMin((long long *)&counters[1], (long long)x);
+    } else if (p < 0 || p >= n || p == x) {
+        atomicOr(flags, F_NOT_TREE);
+    } else {
+        atomicAdd(&ccnt[p], 1);
+        s = atomicExch(&fc[p], x);
     }
-    const int32_t s = cptr[p] + cslot[x];
-    clist[s] = x;
-    cslot[x] = s;
+    nsib[x] = s;
 }
 
 // Per-vertex tour record of level 0 of the list ranking: the successors of both arcs
@@ -442,12 +464,12 @@ struct __attribute__((aligned(32))) TRec {
 // into x continues with the down arc into its first child, or returns (up arc of x);
 // the up arc of x continues with the down arc into its next sibling, or the up arc of
 // its parent, or ends the tour when the parent is the root.  The root's arcs are not on
-// the tour (-2).
+// the tour (-2).  Every read is a coalesced per-vertex load (the children lists are
+// linked through the vertices themselves).
 __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpos, const double *__restrict__ tinv,
                                                  const int32_t *__restrict__ parent,
-                                                 const int32_t *__restrict__ cptr,
-                                                 const int32_t *__restrict__ clist,
-                                                 const int32_t *__restrict__ cslot, int32_t n, int32_t root,
+                                                 const int32_t *__restrict__ ccnt, const int32_t *__restrict__ fc,
+                                                 const int32_t *__restrict__ nsib, int32_t n, int32_t root,
                                                  int emin, int ok, TRec *__restrict__ trec,
                                                  int32_t *__restrict__ succ, u128 *__restrict__ bsum,
                                                  uint64_t *__restrict__ bcarry)
@@ -457,21 +479,20 @@ __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpo
     u128 t = mk128(0, 0);
     if (x < n) {
         if (ok && x != root && tpos[x] >= 0) t = fixed_term(tinv[x], emin);
-        const int32_t c0 = cptr[x], c1 = cptr[x + 1];
+        const int32_t c = fc[x];
         TRec e;
         e.par = parent[x];
-        e.deg = c1 - c0;
+        e.deg = ccnt[x];
         e.t = t;
         if (x == root) {
             e.nd = -2;
             e.nu = -2;
         } else {
-            e.nd = (c0 < c1) ? 2 * clist[c0] : 2 * x + 1;
-            const int32_t p = e.par;
-            const int32_t s = cslot[x] + 1;
-            if (s < cptr[p + 1]) e.nu = 2 * clist[s];
-            else if (p == root) e.nu = GSS_END;
-            else e.nu = 2 * p + 1;
+            e.nd = (c >= 0) ? 2 * c : 2 * x + 1;
+            const int32_t s = nsib[x];
+            if (s >= 0) e.nu = 2 * s;
+            else if (e.par == root) e.nu = GSS_END;
+            else e.nu = 2 * e.par + 1;
         }
         trec[x] = e;
         *(int2 *)(succ + 2 * (int64_t)x) = make_int2(e.nd, e.nu);
@@ -1148,27 +1169,36 @@ __global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, 
 }
 
 // ------------------------------------------------------------------------------------
-// off-tree edges (id order) and tree edge ids
+// edge numbering, off-tree edges (id order) and tree edge ids
 // ------------------------------------------------------------------------------------
-// off-tree upper entries per tile
-// Off-tree edges in id order: entry (u,v) with u < v is kept unless its edge id carries
-// the tree flag.  A counting pass gives every tile its number of kept entries, a scan
-// turns the counts into offsets, and the writing pass keeps (round, wave, lane) = index
-// order inside each tile.
-template <bool WRITE>
-__global__ __launch_bounds__(PB) void k_offtree(
+// The id of edge {u, v}, u < v, is the rank of the upper entry (u, v) among all upper
+// entries in CSR order; an upper entry is a tree edge when parent[u] = v or parent[v] =
+// u.  One pass with decoupled look-back: every tile counts its upper and its off-tree
+// upper entries, takes the counts of the tiles before it from their published status
+// (two counters, wave 0 and wave 1 look back in parallel), ranks both kinds inside the
+// tile in entry order (round, wave, lane), writes every off-tree edge's id, endpoints
+// and weight at its place, and gives each tree edge's id to the child endpoint
+// (tree_eid).  The last tile writes both totals.  Memory-safe on any input: rows are
+// clamped, output places are bounded by Mcap (F_TREE_EDGE beyond it) and parent values
+// are only compared.
+__global__ __launch_bounds__(PB) void k_off_write(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ w,
-    const uint8_t *__restrict__ tflag, const int32_t *__restrict__ uptr, const int32_t *__restrict__ ufirst,
-    int32_t n, int64_t nnz, int64_t m, const int32_t *__restrict__ tile_row, int32_t *__restrict__ tile_cnt,
+    const int32_t *__restrict__ parent, int32_t n, int64_t nnz, int64_t ntiles, const int32_t *__restrict__ tile_row,
     int64_t Mcap, int32_t *__restrict__ off_id, int32_t *__restrict__ off_u, int32_t *__restrict__ off_v,
     double *__restrict__ off_w, const int32_t *__restrict__ vbase, int32_t G, int32_t *__restrict__ off_g,
-    uint32_t *flags)
+    int32_t *__restrict__ tree_eid, uint64_t *__restrict__ status, uint32_t epoch, unsigned long long *ticket,
+    int64_t *__restrict__ m_total, int64_t *__restrict__ off_total, uint32_t *flags)
 {
     constexpr int NW = PB / GSS_WAVE;
+    static_assert(ENT_ITEMS * NW <= GSS_WAVE, "one wave scans the piece counts");
     __shared__ int32_t srow[ETILE];
-    __shared__ int32_t s_wsum[ENT_ITEMS][NW];
+    __shared__ int32_t s_cnt[2][ENT_ITEMS][NW];
+    __shared__ int64_t s_off[2][ENT_ITEMS][NW];
+    __shared__ int64_t s_tile, s_ex[2];
     const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (threadIdx.x == 0) s_tile = lb_ticket(ticket, ntiles);
+    __syncthreads();
+    const int64_t tile = s_tile;
     const int64_t base = tile * ETILE;
     int32_t cv[ENT_ITEMS];
 #pragma unroll
@@ -1176,83 +1206,90 @@ __global__ __launch_bounds__(PB) void k_offtree(
         const int64_t k = base + (int64_t)i * PB + threadIdx.x;
         cv[i] = k < nnz ? col[k] : -1;
     }
-    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);
-    // edge id of every upper entry, then its tree flag (consecutive ids of a row are
-    // consecutive bytes)
-    int32_t eid[ENT_ITEMS];
-    uint8_t tf[ENT_ITEMS];
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+    int32_t pu[ENT_ITEMS], pc[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        const int32_t u = srow[(k - base) & (ETILE - 1)];
-        eid[i] = -1;
-        if (k < nnz && cv[i] > u) eid[i] = uptr[u] + (int32_t)(k - ufirst[u]);
+        const int32_t u = srow[i * PB + threadIdx.x];
+        const bool up = cv[i] > u && cv[i] < n;  // k >= nnz has cv = -1
+        pu[i] = up ? parent[u] : -1;
+        pc[i] = up ? parent[cv[i]] : -1;
     }
-#pragma unroll
-    for (int i = 0; i < ENT_ITEMS; i++) tf[i] = (eid[i] >= 0 && eid[i] < m) ? tflag[eid[i]] : 1;
-    uint64_t keepm[ENT_ITEMS];
+    uint64_t um[ENT_ITEMS], om[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        keepm[i] = __ballot(tf[i] == 0);
-        if (lane == 0) s_wsum[i][wid] = __popcll(keepm[i]);
+        const int32_t u = srow[i * PB + threadIdx.x];
+        const bool up = cv[i] > u && cv[i] < n;
+        um[i] = __ballot(up);
+        om[i] = __ballot(up && pu[i] != cv[i] && pc[i] != u);
+        if (lane == 0) {
+            s_cnt[0][i][wid] = __popcll(um[i]);
+            s_cnt[1][i][wid] = __popcll(om[i]);
+        }
     }
     __syncthreads();
-    if (!WRITE) {
-        if (threadIdx.x == 0) {
-            int32_t t = 0;
-            for (int i = 0; i < ENT_ITEMS; i++)
-                for (int w2 = 0; w2 < NW; w2++) t += s_wsum[i][w2];
-            tile_cnt[tile] = t;
-        }
-        return;
-    }
-    // output offset of every (round, wave) piece in tile order, in LDS (wave-uniform, so
-    // no per-thread registers): one wave scans the ENT_ITEMS * NW piece counts
-    static_assert(ENT_ITEMS * NW <= GSS_WAVE, "one wave scans the piece counts");
-    __shared__ int64_t s_off[ENT_ITEMS][NW];
-    if (wid == 0) {
+    // wave 0 handles the upper entries, wave 1 the off-tree ones: exclusive offsets of the
+    // (round, wave) pieces inside the tile, then the tile's place among the tiles before it
+    if (wid < 2) {
         const int i = lane / NW, w2 = lane % NW;
         const bool has = lane < ENT_ITEMS * NW;
-        int64_t x = has ? (int64_t)s_wsum[i][w2] : 0;
+        int64_t x = has ? (int64_t)s_cnt[wid][i][w2] : 0;
         const int64_t own = x;
 #pragma unroll
         for (int d = 1; d < GSS_WAVE; d <<= 1) {
             const int64_t y = __shfl_up(x, d, GSS_WAVE);
             if (lane >= d) x += y;
         }
-        if (has) s_off[i][w2] = (int64_t)tile_cnt[tile] + x - own;
+        if (has) s_off[wid][i][w2] = x - own;
+        const int64_t tot = __shfl(x, GSS_WAVE - 1, GSS_WAVE);
+        int64_t excl = 0;
+        if (tile == 0) {
+            if (lane == 0) lb_store(status + wid, lb_word(LB_INC, epoch, (uint64_t)tot));
+        } else {
+            if (lane == 0) lb_store(status + 2 * tile + wid, lb_word(LB_AGG, epoch, (uint64_t)tot));
+            excl = lb_lookback_wave(status + wid, 2, tile, epoch);
+            if (lane == 0) lb_store(status + 2 * tile + wid, lb_word(LB_INC, epoch, (uint64_t)(excl + tot)));
+        }
+        if (lane == 0) {
+            s_ex[wid] = excl;
+            if (tile == ntiles - 1) *(wid == 0 ? m_total : off_total) = excl + tot;
+        }
     }
-    __syncthreads();
     // batches: the graphs of the tile's first and last rows bound every entry's graph
     // (usually one graph per tile, so no per-entry search)
     __shared__ int32_t s_glo, s_ghi;
-    if (off_g) {
-        if (threadIdx.x < 2) {
-            const int64_t last = min((int64_t)ETILE, nnz - base) - 1;
-            const int32_t u = srow[threadIdx.x == 0 ? 0 : last];
-            int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
-            while (hi - lo > 1) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (vbase[mid] <= u) lo = mid;
-                else hi = mid;
-            }
-            if (threadIdx.x == 0) s_glo = lo;
-            else s_ghi = lo;
+    if (off_g && wid == 2 && lane < 2) {
+        const int64_t last = min((int64_t)ETILE, nnz - base) - 1;
+        const int32_t u = srow[lane == 0 ? 0 : last];
+        int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (vbase[mid] <= u) lo = mid;
+            else hi = mid;
         }
-        __syncthreads();
+        if (lane == 0) s_glo = lo;
+        else s_ghi = lo;
     }
+    __syncthreads();
     const uint64_t lt = lanemask_lt();
+    const int64_t ex_u = s_ex[0], ex_o = s_ex[1];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        if (!((keepm[i] >> lane) & 1ull)) continue;
+        if (!((um[i] >> lane) & 1ull)) continue;
         const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        const int64_t o = s_off[i][wid] + __popcll(keepm[i] & lt);
+        const int32_t u = srow[i * PB + threadIdx.x];
+        const int32_t id = (int32_t)(ex_u + s_off[0][i][wid] + __popcll(um[i] & lt));
+        if (!((om[i] >> lane) & 1ull)) {  // a tree edge: its id goes to the child
+            if (pc[i] == u) tree_eid[cv[i]] = id;
+            if (pu[i] == cv[i]) tree_eid[u] = id;
+            continue;
+        }
+        const int64_t o = ex_o + s_off[1][i][wid] + __popcll(om[i] & lt);
         if (o >= Mcap) {
             atomicOr(flags, F_TREE_EDGE);  // more off-tree entries than m - n + 1
             continue;
         }
-        const int32_t u = srow[k - base];
-        off_id[o] = eid[i];
+        off_id[o] = id;
         off_u[o] = u;
         off_v[o] = cv[i];
         off_w[o] = w[k];
@@ -1268,50 +1305,21 @@ __global__ __launch_bounds__(PB) void k_offtree(
     }
 }
 
-__global__ void k_tree_eid(const int32_t *__restrict__ parent, const int32_t *__restrict__ row_ptr,
-                           const int32_t *__restrict__ col, const int32_t *__restrict__ uptr,
-                           const int32_t *__restrict__ ufirst, const int32_t *__restrict__ tpos,
-                           int32_t n, int64_t m, int32_t *__restrict__ tree_eid, uint8_t *__restrict__ tflag)
-{
-    int32_t x = (int32_t)(xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-    if (x >= n) return;
-    int32_t p = parent[x];
-    if (p < 0 || tpos[x] < 0) {
-        tree_eid[x] = -1;
-        return;
-    }
-    int32_t e;
-    if (x < p) {
-        e = uptr[x] + (tpos[x] - ufirst[x]);
-    } else {
-        int64_t k = find_in_row(col, row_ptr[p], row_ptr[p + 1], x);
-        e = k < 0 ? -1 : uptr[p] + (int32_t)(k - ufirst[p]);
-    }
-    tree_eid[x] = e;
-    if (e >= 0 && e < m) tflag[e] = 1;
-}
-
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // the root's vertex record (preorder index 0, depth 0, D = 0, its tree degree), its LCA
 // sequence entry (never inside a query range) and the head arc of the tour (the down
 // arc into its first child; n > 1); the tour writes every other record
 __global__ void k_vrec_root(VRec *vrec, int32_t n, int32_t root, uint64_t *__restrict__ epk,
-                            const int32_t *__restrict__ cptr, const int32_t *__restrict__ clist, int64_t *head)
+                            const int32_t *__restrict__ ccnt, const int32_t *__restrict__ fc, int64_t *head)
 {
     VRec r;
     r.D = mk128(0, 0);
     r.first = 0;
     r.depth = 0;
     r.parent = -1;
-    r.pad = cptr[root + 1] - cptr[root];
+    r.pad = ccnt[root];
     vrec[root] = r;
     epk[0] = (uint64_t)(uint32_t)root;
-    if (n > 1) *head = 2 * (int64_t)clist[cptr[root]];
+    if (n > 1) *head = 2 * (int64_t)fc[root];
 }
 
 
@@ -1323,7 +1331,7 @@ static void fail(gss_status s, const char *msg) { throw gss_error{s, msg}; }
 void free_tree_arrays(gss_tree t)
 {
     gss_ctx c = t->ctx;
-    void *ptrs[] = {t->uptr,   t->ufirst, t->tpos,   t->tree_eid, t->vrec,       t->epk,    t->pmask,
+    void *ptrs[] = {t->tree_eid, t->vrec,       t->epk,    t->pmask,
                     t->ppre,   t->psuf,   t->bmin,   t->bmask,    t->bpre,       t->bsuf,   t->sbst,
                     t->off_id, t->off_u,  t->off_v,  t->off_w,    t->off_g,      t->d_vbase, t->own_row_ptr,
                     t->own_col, t->own_parent, t->own_w, t->d_obase};
@@ -1338,12 +1346,12 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     const int32_t n = t->n;
     const int64_t nnz = t->nnz;
     const bool validate = !(flags & GSS_PREP_TRUSTED);
-    HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+    fill_bytes(ctx, ctx->d_flags, 0, sizeof(uint32_t));
 
     // the row at the start of every tile of ETILE entries (and the row_ptr checks)
     const int64_t etiles = nnz > 0 ? (nnz + ETILE - 1) / ETILE : 0;
     int32_t *tile_row = ctx->alloc<int32_t>(etiles + 1);
-    if (nnz > 0) HIP_OK(hipMemsetAsync(tile_row, 0, sizeof(int32_t) * (etiles + 1), st));
+    if (nnz > 0) fill_bytes(ctx, tile_row, 0, sizeof(int32_t) * (etiles + 1));
     GSS_LAUNCH_B(8 * (int64_t)n, k_tile_rows, dim3(grid_for((int64_t)n + 1, PB)), dim3(PB), 0, st, t->row_ptr, n, nnz,
                  etiles, tile_row, validate ? 1 : 0, ctx->d_flags);
     struct TileRowsFree {
@@ -1352,129 +1360,111 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         ~TileRowsFree() { c->free(p); }
     } tile_row_guard{ctx, tile_row};
 
-    // validation (memory-safe on malformed input) on the auxiliary stream, beside the
-    // edge numbering and the tree checks below
-    const bool check_entries = validate && nnz > 0;
-    if (validate) HIP_OK(hipMemsetAsync(ctx->d_counters + 10, 0, sizeof(int64_t), st));
-    if (check_entries) {
-        AuxScope aux(ctx);
-        int64_t *bpart = ctx->alloc<int64_t>(etiles + 1);
-        GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0,
-                     ctx->stream, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart);
-        GSS_LAUNCH(k_balance_total, dim3(1), dim3(1024), 0, ctx->stream, bpart, etiles, ctx->d_counters + 10);
-        ctx->free(bpart);
-    }
-    t->ufirst = ctx->alloc<int32_t>(n);
-    t->uptr = ctx->alloc<int32_t>(n + 1);
-    GSS_LAUNCH(k_rows, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->row_ptr, t->col, n, nnz, t->ufirst, t->uptr);
-    HIP_OK(hipMemsetAsync(t->uptr + n, 0, sizeof(int32_t), st));
-    int64_t m;
-    scan_exclusive_i32_dev(ctx, t->uptr, n + 1, ctx->d_counters + 13);
-    if (validate) {
-        // the symmetry check makes m = nnz / 2; the scan total is compared with it at the
-        // final synchronisation instead of waiting for it here
-        m = nnz / 2;
-    } else {
-        HIP_OK(hipMemcpyAsync(&ctx->h_counters[13], ctx->d_counters + 13, sizeof(int64_t), hipMemcpyDeviceToHost,
-                              st));
-        ctx->sync();
-        m = ctx->h_counters[13];
-    }
+    // A symmetric simple graph has m = nnz / 2 edges (with validation the checks below
+    // confirm it; trusted input promises it).  The edge count found by the numbering is
+    // compared with m at the final synchronisation.
+    const int64_t m = nnz / 2;
     t->m = m;
-
-    // tree checks
-    int32_t *ccnt = ctx->alloc<int32_t>(n + 1);
-    int32_t *cslot = ctx->alloc<int32_t>(n);
-    double *tinv = ctx->alloc<double>(n);
-    t->tpos = ctx->alloc<int32_t>(n);
-    HIP_OK(hipMemsetAsync(ccnt, 0, sizeof(int32_t) * (n + 1), st));
-    int64_t init_c[4] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40)};
-    memcpy(ctx->h_counters, init_c, sizeof init_c);
-    HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
-    GSS_LAUNCH_B(32 * (int64_t)n, k_tree_check, dim3(std::min<int64_t>(grid_for(n, PB), 512)), dim3(PB), 0, st,
-                 t->parent, t->row_ptr,
-               t->col, t->w, n, nnz, t->virt_root, ccnt, cslot, t->tpos, tinv, ctx->d_flags, ctx->d_counters);
-    if (check_entries) aux_join(ctx);
-    // the CSR flags and the triangle balance are read back with the tree checks (every
-    // kernel until then is memory-safe on malformed input)
-    HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if (validate)
-        HIP_OK(hipMemcpyAsync(ctx->h_counters + 10, ctx->d_counters + 10, sizeof(int64_t), hipMemcpyDeviceToHost,
-                              st));
-    uint32_t f = read_flags(ctx);  // syncs
-    if (validate) {  // CSR checks first (their precedence), then the tree checks
-        const uint32_t fg = f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
-        if (fg) {
-            ctx->free(ccnt);
-            ctx->free(cslot);
-            ctx->free(tinv);
-            fail(status_from_flags(fg), "invalid graph");
-        }
-        if ((f & F_ASYM) || ctx->h_counters[10] != 0 || nnz % 2) {
-            ctx->free(ccnt);
-            ctx->free(cslot);
-            ctx->free(tinv);
-            fail(GSS_ERR_ASYM, "the graph is not symmetric");
-        }
-    }
-    int64_t roots = ctx->h_counters[0];
-    t->root = (int32_t)ctx->h_counters[1];
-    int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
-    if (f & F_NOT_TREE || roots != 1) {
-        ctx->free(ccnt);
-        ctx->free(cslot);
-        ctx->free(tinv);
-        fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
-    }
-    bool tree_edge_missing = (f & F_TREE_EDGE) != 0;
-    bool range_bad = (f & F_RANGE) != 0;
-    if (n == 1) emin = emax = 0;
-    if (!range_bad && !tree_edge_missing && emax - emin > 74) range_bad = true;
-    if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
-    t->emin = (int32_t)emin;
-    t->scale = (int32_t)emin - 52;
-
-    // off-tree edges (links to a batch's virtual root are tree edges without graph edges),
-    // on the auxiliary stream: they need only the tree-edge positions, so they run beside
-    // the Euler-tour ranking below (a chain of short, latency-bound launches)
-    t->M = t->m - (n - 1) + (t->virt_root >= 0 ? t->G : 0);
+    t->M = m - (n - 1) + (t->virt_root >= 0 ? t->G : 0);
+    if (t->M < 0) t->M = 0;  // fewer entries than a tree needs: the counts below fail
     t->off_id = ctx->alloc<int32_t>(t->M + 1);
     t->off_u = ctx->alloc<int32_t>(t->M + 1);
     t->off_v = ctx->alloc<int32_t>(t->M + 1);
     t->off_w = ctx->alloc<double>(t->M + 1);
     t->tree_eid = ctx->alloc<int32_t>(n);
     if (nnz > 0 && (t->G > 1 || t->virt_root >= 0)) t->off_g = ctx->alloc<int32_t>(t->M + 1);
+    int64_t init_c[5] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40), 0};
+    memcpy(ctx->h_counters, init_c, sizeof init_c);
+    HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
+    fill_bytes(ctx, ctx->d_counters + 9, 0, 2 * sizeof(int64_t));
+    fill_bytes(ctx, ctx->d_counters + 13, 0, sizeof(int64_t));
+
+    // tree checks on the context stream: the tree edges from the child's rows, then the
+    // parent array (roots, cycles of length one, child lists)
+    int32_t *ccnt = ctx->alloc<int32_t>(n);
+    int32_t *fc = ctx->alloc<int32_t>(2 * (int64_t)n);  // fc[0, n) and tpos[n, 2n)
+    int32_t *nsib = ctx->alloc<int32_t>(n);
+    double *tinv = ctx->alloc<double>(n);
+    int32_t *tpos = fc + n;
+    fill_bytes(ctx, ccnt, 0, sizeof(int32_t) * n);
+    fill_bytes(ctx, fc, 0xFF, sizeof(int32_t) * 2 * (int64_t)n);
+    if (nnz > 0) {
+        int4 *part = ctx->alloc<int4>(etiles);
+        GSS_LAUNCH_B(4 * nnz + 4 * (int64_t)n + 20 * (int64_t)n, k_tree_entries, dim3((unsigned)etiles), dim3(PB),
+                     0, st, t->row_ptr, t->col, t->w, t->parent, n, nnz, tile_row, tpos, tinv, part);
+        GSS_LAUNCH(k_tree_total, dim3(1), dim3(1024), 0, st, part, etiles, ctx->d_flags, ctx->d_counters);
+        ctx->free(part);
+    }
+    GSS_LAUNCH_B(12 * (int64_t)n, k_tree_vertices, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, ccnt, fc,
+                 nsib, ctx->d_flags, ctx->d_counters);
+
+    // The auxiliary stream numbers the edges (off-tree edges, tree edge ids) and validates
+    // the CSR (entry checks with the mirror search of the symmetry check) beside the rest
+    // of the tree preparation, which waits for it only at its end; everything on the
+    // context stream is memory-safe on a malformed CSR.  It starts after the tree checks
+    // above, which the first host wait needs, so they get the whole device.
     {
         AuxScope aux(ctx);
         hipStream_t sa = ctx->stream;
-        // tree edge ids, and a flag byte per edge id
-        uint8_t *tflag = ctx->alloc<uint8_t>(t->m + 1);
-        HIP_OK(hipMemsetAsync(tflag, 0, t->m + 1, sa));
-        GSS_LAUNCH_B(21 * (int64_t)n, k_tree_eid, dim3(grid_for(n, PB)), dim3(PB), 0, sa, t->parent, t->row_ptr,
-                     t->col, t->uptr, t->ufirst, t->tpos, n, t->m, t->tree_eid, tflag);
+        fill_bytes(ctx, t->tree_eid, 0xFF, sizeof(int32_t) * n);
         if (nnz > 0) {
-            int32_t *tcnt = ctx->alloc<int32_t>(etiles + 1);
-            // CSR columns, row starts and tree flags read; one count per tile
-            GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m, k_offtree<false>, dim3((unsigned)etiles), dim3(PB), 0, sa,
-                         t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row, tcnt, t->M,
-                         t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, ctx->d_flags);
-            scan_exclusive_i32_dev(ctx, tcnt, etiles, ctx->d_counters + 9);
-            // the same reads again; per off-tree edge its id, endpoints and weight written
-            GSS_LAUNCH_B(4 * nnz + 8 * (int64_t)n + t->m + 28 * t->M, k_offtree<true>, dim3((unsigned)etiles),
-                         dim3(PB), 0, sa, t->row_ptr, t->col, t->w, tflag, t->uptr, t->ufirst, n, nnz, t->m, tile_row,
-                         tcnt, t->M, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g,
-                         ctx->d_flags);
-            ctx->free(tcnt);
+            uint32_t epoch = 0;
+            uint64_t *status = lb_begin(ctx, 2 * etiles, &epoch);
+            // columns and both parents read per entry; per off-tree edge its id, endpoints
+            // and weight written, per tree edge its id
+            GSS_LAUNCH_B(8 * nnz + 28 * t->M + 4 * (int64_t)n, k_off_write, dim3((unsigned)etiles), dim3(PB), 0, sa,
+                         t->row_ptr, t->col, t->w, t->parent, n, nnz, etiles, tile_row, t->M, t->off_id, t->off_u,
+                         t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, t->tree_eid, status, epoch,
+                         lb_ticket_ptr(ctx), ctx->d_counters + 13, ctx->d_counters + 9, ctx->d_flags);
+            if (validate) {
+                int64_t *bpart = ctx->alloc<int64_t>(etiles + 1);
+                GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0,
+                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart);
+                GSS_LAUNCH(k_balance_total, dim3(1), dim3(1024), 0, sa, bpart, etiles, ctx->d_counters + 10);
+                ctx->free(bpart);
+            }
         }
-        ctx->free(tflag);  // held until the join
     }
-
-    // children CSR
-    int32_t *cptr = ccnt;  // scanned in place, cptr[n] = n-1
-    scan_exclusive_i32(ctx, cptr, n + 1, false);
-    int32_t *clist = ctx->alloc<int32_t>(n);
-    GSS_LAUNCH_B(20 * (int64_t)n, k_children_fill, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, cptr,
-                 clist, cslot);
+    HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    ctx->sync_stream();  // the auxiliary stream keeps running
+    uint32_t f;
+    memcpy(&f, &ctx->h_counters[15], sizeof f);
+    const int64_t roots = ctx->h_counters[0];
+    auto free_tree_tmp = [&]() {
+        ctx->free(ccnt);
+        ctx->free(fc);
+        ctx->free(nsib);
+        ctx->free(tinv);
+    };
+    // Errors keep their precedence (CSR checks, symmetry, then the tree): on any error
+    // the auxiliary stream's checks are awaited and read before the verdict.
+    auto fail_checked = [&](uint32_t tree_f) {
+        aux_join(ctx);
+        HIP_OK(hipMemcpyAsync(ctx->h_counters + 9, ctx->d_counters + 9, 5 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
+        const uint32_t all = read_flags(ctx) | tree_f;  // syncs
+        free_tree_tmp();
+        const uint32_t fg = all & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
+        if (fg) fail(status_from_flags(fg), "invalid graph");
+        if (validate && ((all & F_ASYM) || ctx->h_counters[10] != 0 || nnz % 2))
+            fail(GSS_ERR_ASYM, "the graph is not symmetric");
+        if (all & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
+        fail(status_from_flags(all), "invalid input");
+    };
+    if ((f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT | F_ASYM)) || (f & F_NOT_TREE) || roots != 1)
+        fail_checked(roots != 1 ? F_NOT_TREE : 0);
+    t->root = (int32_t)ctx->h_counters[1];
+    int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
+    // every tree edge but the links to a batch's virtual root must be a graph edge
+    const int64_t need = (int64_t)(n - 1) - (t->virt_root >= 0 ? t->G : 0);
+    bool tree_edge_missing = ctx->h_counters[4] != need;
+    bool range_bad = (f & F_RANGE) != 0;
+    if (n == 1) emin = emax = 0;
+    if (!range_bad && !tree_edge_missing && emax - emin > 74) range_bad = true;
+    if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
+    t->emin = (int32_t)emin;
+    t->scale = (int32_t)emin - 52;
 
     // tour records (successors, parent, degree, fixed-point term) and the 127-bit range
     // check of the terms
@@ -1484,18 +1474,17 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     u128 *tbs = ctx->alloc<u128>(tb);
     uint64_t *tbc = ctx->alloc<uint64_t>(tb);
     const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
-    // per vertex: tree-edge position, weight, parent, child range, slot and first child
-    // read; record and both successors written
-    GSS_LAUNCH_B(76 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, t->tpos, tinv, t->parent, cptr,
-                 clist, cslot, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
+    // per vertex: tree-edge position, resistance, parent, child count, first child and
+    // next sibling read; record and both successors written
+    GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent, ccnt, fc,
+                 nsib, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
     GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
 
     // Euler tour
     t->L = n;  // the LCA sequence is indexed by preorder
     t->vrec = ctx->alloc<VRec>(n);
     t->epk = ctx->alloc<uint64_t>(t->L);
-    GSS_LAUNCH(k_vrec_root, dim3(1), dim3(1), 0, st, t->vrec, n, t->root, t->epk, cptr, clist,
-               ctx->d_counters + 12);
+    GSS_LAUNCH(k_vrec_root, dim3(1), dim3(1), 0, st, t->vrec, n, t->root, t->epk, ccnt, fc, ctx->d_counters + 12);
     // the tour is ranked without waiting for the host: its flags (overflow, cycle) are read
     // together with the off-tree enumeration's below; every kernel in between is
     // memory-safe on a failed ranking
@@ -1527,10 +1516,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
     };
     build_rmq();
-    ctx->free(tinv);
-    ctx->free(clist);
-    ctx->free(cslot);
-    ctx->free(ccnt);
+    free_tree_tmp();
     ctx->free(tbs);
     ctx->free(tbc);
 
@@ -1552,7 +1538,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         // a level outgrew its capacity (vanishingly rare): rank again with more room; an
         // attempt that ran out of room proves nothing about the tree
         earlier = f & ~(F_OVERFLOW | F_NOT_TREE);
-        HIP_OK(hipMemsetAsync(ctx->d_flags, 0, sizeof(uint32_t), st));
+        fill_bytes(ctx, ctx->d_flags, 0, sizeof(uint32_t));
         mult *= 2;
         t->rank_attempts++;
         euler_rank(ctx, t, succ, trec, ctx->d_counters + 12, mult, rank_bufs);
@@ -1561,6 +1547,11 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     }
     ctx->free(succ);
     ctx->free(trec);
+    // the auxiliary stream's CSR checks first (their precedence), then the tree's
+    const uint32_t fg = f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
+    if (fg) fail(status_from_flags(fg), "invalid graph");
+    if (validate && ((f & F_ASYM) || ctx->h_counters[10] != 0 || nnz % 2))
+        fail(GSS_ERR_ASYM, "the graph is not symmetric");
     if (f & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array has a cycle");
     if (tree_edge_missing) fail(GSS_ERR_TREE_EDGE, "a tree edge is not an edge of the graph");
     if (range_bad || (f & F_RANGE)) fail(GSS_ERR_RANGE, "tree resistances exceed the 127-bit fixed point");
@@ -1688,13 +1679,10 @@ void prep_batch(gss_ctx ctx, gss_tree t, int32_t G, const gss_csr *gs, const int
     if (f) fail(status_from_flags(f), "invalid graph in the batch");
     prep_tree(ctx, t, flags);
     // per-graph edge and off-tree ranges
+    // a symmetric simple graph holds nnz / 2 upper entries (the union passed its checks,
+    // and it is symmetric exactly when every graph is)
     t->ebase.assign(G + 1, 0);
-    std::vector<int32_t> up(G + 1);
-    for (int32_t g = 0; g <= G; g++) {
-        HIP_OK(hipMemcpyAsync(&up[g], t->uptr + t->vbase[g], sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    }
-    ctx->sync();
-    for (int32_t g = 0; g <= G; g++) t->ebase[g] = up[g];
+    for (int32_t g = 0; g < G; g++) t->ebase[g + 1] = t->ebase[g] + gs[g].nnz / 2;
     t->Mg.assign(G, 0);
     t->obase.assign(G + 1, 0);
     for (int32_t g = 0; g < G; g++) {
