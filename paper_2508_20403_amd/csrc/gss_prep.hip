@@ -22,10 +22,13 @@
 #define PB 256          // default block size
 #define ENT_ITEMS 16    // CSR entries per thread in entry-parallel kernels
 #ifndef RULE_RATE0
-#define RULE_RATE0 4    // level 0 of the list ranking: one ruler per ~RULE_RATE0 arcs (power of two)
+#define RULE_RATE0 8    // level 0 of the list ranking: one ruler per ~RULE_RATE0 arcs (power of two)
 #endif
 #ifndef RULE_RATE
-#define RULE_RATE 4     // upper levels: one ruler per ~RULE_RATE elements (power of two)
+#define RULE_RATE 8     // upper levels: one ruler per ~RULE_RATE elements (power of two)
+#endif
+#ifndef CHECK_BLOCKS
+#define CHECK_BLOCKS 0  // workgroups of the CSR checks (0: one per tile)
 #endif
 #define BASE_MAX 4096   // lists this short are ranked by one workgroup
 #define BASE_THREADS 1024
@@ -179,13 +182,16 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
                                                       const int32_t *__restrict__ tile_row, uint32_t *flags,
-                                                      int64_t *__restrict__ bpart)
+                                                      int64_t *__restrict__ bpart, int64_t ntiles)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t scol[ETILE];
     __shared__ int64_t sh[PB / GSS_WAVE];
     __shared__ int32_t s_prev[2];  // row and column of entry base-1 (-1 if none)
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // a bounded grid (a multiple of 8 workgroups) strides over the tiles, each XCD over a
+    // contiguous range, so the checks leave room for concurrent work on the device
+    for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
+    const int64_t tile = xcd_tile(j, ntiles);
     const int64_t base = tile * ETILE;
     // every global load of the tile is issued before any is used
     int32_t cv[ENT_ITEMS];
@@ -287,6 +293,8 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
         for (int i = 1; i < PB / GSS_WAVE; i++) bal += sh[i];
         bpart[tile] = bal;  // per-tile partial sums (no contended atomics)
     }
+    __syncthreads();  // the tile's shared arrays are reused by the next one
+    }
 }
 
 // sums the per-block balances (upper minus lower entries) of k_check_entries into *total
@@ -302,6 +310,36 @@ __global__ __launch_bounds__(1024) void k_balance_total(const int64_t *__restric
     if (threadIdx.x == 0) {
         for (int i = 1; i < 1024 / GSS_WAVE; i++) a += s1[i];
         *total = a;
+    }
+}
+
+// start values of the preparation's flags and counters (one launch instead of a copy
+// and several fills): roots, smallest root, exponent range, tree edges found, off-tree
+// and upper-entry totals, triangle balance
+__global__ void k_prep_init(uint32_t *flags, int64_t *counters, int32_t n)
+{
+    if (threadIdx.x == 0) {
+        *flags = 0;
+        counters[0] = 0;
+        counters[1] = n;
+        counters[2] = (int64_t)1 << 40;
+        counters[3] = -((int64_t)1 << 40);
+        counters[4] = 0;
+        counters[9] = 0;
+        counters[10] = 0;
+        counters[13] = 0;
+    }
+}
+
+// child counts to zero, first children and tree-edge positions to -1
+__global__ void k_tree_init(int32_t *__restrict__ ccnt, int32_t *__restrict__ fc, int32_t *__restrict__ tpos,
+                            int32_t n)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) {
+        ccnt[x] = 0;
+        fc[x] = -1;
+        tpos[x] = -1;
     }
 }
 
@@ -459,13 +497,14 @@ struct __attribute__((aligned(32))) TRec {
     u128 t;
 };
 
-// Tour records, the successor array of the arcs (read by the ruler selection) and the
-// per-block sums of the terms for the 127-bit range check.  Successors: the down arc
+// Tour records, the successor array of the arcs (read by the ruler selection) and, with
+// SUMS, the per-block sums of the terms for the 127-bit range check.  Successors: the down arc
 // into x continues with the down arc into its first child, or returns (up arc of x);
 // the up arc of x continues with the down arc into its next sibling, or the up arc of
 // its parent, or ends the tour when the parent is the root.  The root's arcs are not on
 // the tour (-2).  Every read is a coalesced per-vertex load (the children lists are
 // linked through the vertices themselves).
+template <bool SUMS>
 __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpos, const double *__restrict__ tinv,
                                                  const int32_t *__restrict__ parent,
                                                  const int32_t *__restrict__ ccnt, const int32_t *__restrict__ fc,
@@ -497,6 +536,7 @@ __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpo
         trec[x] = e;
         *(int2 *)(succ + 2 * (int64_t)x) = make_int2(e.nd, e.nu);
     }
+    if (!SUMS) return;
     slo[threadIdx.x] = t.lo;
     shi[threadIdx.x] = t.hi;
     sc[threadIdx.x] = 0;
@@ -1346,7 +1386,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     const int32_t n = t->n;
     const int64_t nnz = t->nnz;
     const bool validate = !(flags & GSS_PREP_TRUSTED);
-    fill_bytes(ctx, ctx->d_flags, 0, sizeof(uint32_t));
+    GSS_LAUNCH(k_prep_init, dim3(1), dim3(64), 0, st, ctx->d_flags, ctx->d_counters, n);
 
     // the row at the start of every tile of ETILE entries (and the row_ptr checks)
     const int64_t etiles = nnz > 0 ? (nnz + ETILE - 1) / ETILE : 0;
@@ -1373,21 +1413,15 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     t->off_w = ctx->alloc<double>(t->M + 1);
     t->tree_eid = ctx->alloc<int32_t>(n);
     if (nnz > 0 && (t->G > 1 || t->virt_root >= 0)) t->off_g = ctx->alloc<int32_t>(t->M + 1);
-    int64_t init_c[5] = {0, (int64_t)n, (int64_t)1 << 40, -((int64_t)1 << 40), 0};
-    memcpy(ctx->h_counters, init_c, sizeof init_c);
-    HIP_OK(hipMemcpyAsync(ctx->d_counters, ctx->h_counters, sizeof init_c, hipMemcpyHostToDevice, st));
-    fill_bytes(ctx, ctx->d_counters + 9, 0, 2 * sizeof(int64_t));
-    fill_bytes(ctx, ctx->d_counters + 13, 0, sizeof(int64_t));
 
     // tree checks on the context stream: the tree edges from the child's rows, then the
     // parent array (roots, cycles of length one, child lists)
     int32_t *ccnt = ctx->alloc<int32_t>(n);
-    int32_t *fc = ctx->alloc<int32_t>(2 * (int64_t)n);  // fc[0, n) and tpos[n, 2n)
+    int32_t *fc = ctx->alloc<int32_t>(n);
+    int32_t *tpos = ctx->alloc<int32_t>(n);
     int32_t *nsib = ctx->alloc<int32_t>(n);
     double *tinv = ctx->alloc<double>(n);
-    int32_t *tpos = fc + n;
-    fill_bytes(ctx, ccnt, 0, sizeof(int32_t) * n);
-    fill_bytes(ctx, fc, 0xFF, sizeof(int32_t) * 2 * (int64_t)n);
+    GSS_LAUNCH(k_tree_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, ccnt, fc, tpos, n);
     if (nnz > 0) {
         int4 *part = ctx->alloc<int4>(etiles);
         GSS_LAUNCH_B(4 * nnz + 4 * (int64_t)n + 20 * (int64_t)n, k_tree_entries, dim3((unsigned)etiles), dim3(PB),
@@ -1418,8 +1452,9 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
                          lb_ticket_ptr(ctx), ctx->d_counters + 13, ctx->d_counters + 9, ctx->d_flags);
             if (validate) {
                 int64_t *bpart = ctx->alloc<int64_t>(etiles + 1);
-                GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0,
-                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart);
+                const int64_t cgrid = CHECK_BLOCKS > 0 ? std::min<int64_t>(CHECK_BLOCKS, (etiles + 7) / 8 * 8) : etiles;
+                GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)cgrid), dim3(PB), 0,
+                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart, etiles);
                 GSS_LAUNCH(k_balance_total, dim3(1), dim3(1024), 0, sa, bpart, etiles, ctx->d_counters + 10);
                 ctx->free(bpart);
             }
@@ -1434,6 +1469,7 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     auto free_tree_tmp = [&]() {
         ctx->free(ccnt);
         ctx->free(fc);
+        ctx->free(tpos);
         ctx->free(nsib);
         ctx->free(tinv);
     };
@@ -1474,11 +1510,20 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     u128 *tbs = ctx->alloc<u128>(tb);
     uint64_t *tbc = ctx->alloc<uint64_t>(tb);
     const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
+    // Every term is below 2^(53 + emax - emin) and there are fewer than 2^30 of them, so
+    // with emax - emin <= 44 their sum (a bound on every root resistance) stays below
+    // 2^127 and the exact sum is not needed.
+    const bool sums = terms_ok && emax - emin > 44;
     // per vertex: tree-edge position, resistance, parent, child count, first child and
     // next sibling read; record and both successors written
-    GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent, ccnt, fc,
-                 nsib, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
-    GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
+    if (sums) {
+        GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec<true>, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent,
+                     ccnt, fc, nsib, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
+        GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
+    } else {
+        GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec<false>, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent,
+                     ccnt, fc, nsib, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
+    }
 
     // Euler tour
     t->L = n;  // the LCA sequence is indexed by preorder
