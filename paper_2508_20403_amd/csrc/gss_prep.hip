@@ -27,9 +27,6 @@
 #ifndef RULE_RATE
 #define RULE_RATE 8     // upper levels: one ruler per ~RULE_RATE elements (power of two)
 #endif
-#ifndef CHECK_BLOCKS
-#define CHECK_BLOCKS 0  // workgroups of the CSR checks (0: one per tile)
-#endif
 #define BASE_MAX 4096   // lists this short are ranked by one workgroup
 #define BASE_THREADS 1024
 
@@ -126,8 +123,13 @@ __global__ void k_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int6
 // rows wins), then an inclusive prefix maximum over the tile carries each row to its
 // entries.  The work is independent of row lengths (a hub row spanning many tiles costs
 // the same as short rows).
+// With rs (capacity RS_CAP), rs[r - r0] also receives the tile offset of the start of each
+// row r0 < r <= r1 that starts inside the tile, r - r0 < RS_CAP (a row's entries inside the
+// tile are then [rs[r - r0], rs[r + 1 - r0]) when both rows start inside it).
+#define RS_CAP 1024
 __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
-                                               int64_t base, const int32_t *__restrict__ tile_row, int32_t *srow)
+                                               int64_t base, const int32_t *__restrict__ tile_row, int32_t *srow,
+                                               int32_t *rs = nullptr)
 {
     constexpr int PER = ETILE / PB;
     __shared__ int32_t s_tmax[PB / GSS_WAVE];
@@ -141,7 +143,10 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
     __syncthreads();
     for (int32_t r = r0 + 1 + threadIdx.x; r <= r1; r += PB) {
         const int64_t k = row_ptr[r];
-        if (k >= base && k < base + ETILE) atomicMax(&srow[k - base], r);
+        if (k >= base && k < base + ETILE) {
+            atomicMax(&srow[k - base], r);
+            if (rs && r - r0 < RS_CAP) rs[r - r0] = (int32_t)(k - base);
+        }
     }
     __syncthreads();
     // inclusive prefix maximum: thread t owns entries [PER t, PER t + PER)
@@ -182,16 +187,14 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
                                                       const int32_t *__restrict__ tile_row, uint32_t *flags,
-                                                      int64_t *__restrict__ bpart, int64_t ntiles)
+                                                      int64_t *__restrict__ bpart)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t scol[ETILE];
+    __shared__ int32_t s_rs[RS_CAP];
     __shared__ int64_t sh[PB / GSS_WAVE];
     __shared__ int32_t s_prev[2];  // row and column of entry base-1 (-1 if none)
-    // a bounded grid (a multiple of 8 workgroups) strides over the tiles, each XCD over a
-    // contiguous range, so the checks leave room for concurrent work on the device
-    for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
-    const int64_t tile = xcd_tile(j, ntiles);
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = tile * ETILE;
     // every global load of the tile is issued before any is used
     int32_t cv[ENT_ITEMS];
@@ -213,71 +216,88 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
             s_prev[1] = col[base - 1];
         }
     }
-    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow, s_rs);  // synchronises
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) scol[i * PB + threadIdx.x] = cv[i];
     __syncthreads();
+    // rows r0 < r < r_last lie wholly inside the tile: their starts are in s_rs
+    const int32_t nloc = (int32_t)min((int64_t)ETILE, nnz - base);
+    const int32_t r0 = srow[0];
+    const int32_t r_last = srow[nloc - 1];
     uint32_t f = 0;
     int64_t bal = 0;  // upper minus lower entries
-    {
 #pragma unroll
-        for (int i = 0; i < ENT_ITEMS; i++) {
-            const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        if (k >= nnz) continue;
+        const int32_t u = srow[k - base];
+        const int32_t c = cv[i];
+        if (c < 0 || c >= n) {
+            f |= F_ARG;
+            continue;
+        }
+        if (c == u) f |= F_NOT_SIMPLE;
+        // columns strictly increase within a row
+        const bool prev_same = (k > base) ? (srow[k - 1 - base] == u) : (s_prev[0] == u);
+        const int32_t pcol = (k > base) ? scol[k - 1 - base] : s_prev[1];
+        if (prev_same && pcol >= c) f |= F_NOT_SIMPLE;
+        const double x = wv[i];
+        if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
+        bal += (c > u) ? 1 : (c < u ? -1 : 0);
+    }
+    // The mirror (c, u) of every lower entry (u, c) is searched in row c.  A row lying
+    // wholly inside the tile (r0 < c < r_last, its start within RS_CAP rows of r0) is
+    // bisected in LDS; any other row in global memory, the searches of eight entries in
+    // lockstep so that their loads overlap.  lo/hi bisect the row for the first column
+    // >= u (tile offsets for a row in LDS, CSR positions otherwise).  Row bounds are
+    // clamped so malformed input stays in bounds.
+    constexpr int MB = 8;
+#pragma unroll 1
+    for (int h = 0; h < ENT_ITEMS; h += MB) {
+        int32_t lo[MB], hi[MB], end[MB], key[MB];
+        uint32_t inlds = 0;
+#pragma unroll
+        for (int q = 0; q < MB; q++) {
+            const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
+            lo[q] = hi[q] = end[q] = 0;
+            key[q] = -1;
             if (k >= nnz) continue;
             const int32_t u = srow[k - base];
-            const int32_t c = cv[i];
-            if (c < 0 || c >= n) {
-                f |= F_ARG;
-                continue;
-            }
-            if (c == u) f |= F_NOT_SIMPLE;
-            // columns strictly increase within a row
-            const bool prev_same = (k > base) ? (srow[k - 1 - base] == u) : (s_prev[0] == u);
-            const int32_t pcol = (k > base) ? scol[k - 1 - base] : s_prev[1];
-            if (prev_same && pcol >= c) f |= F_NOT_SIMPLE;
-            const double x = wv[i];
-            if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
-            bal += (c > u) ? 1 : (c < u ? -1 : 0);
-        }
-        // The mirror (c, u) of every lower entry (u, c) is searched in row c.  The searches
-        // of eight entries run in lockstep so that their loads overlap: lo/hi bisect row c
-        // for the first column >= u.  Row bounds are clamped so malformed input stays in
-        // bounds.
-        constexpr int MB = 8;
-#pragma unroll 1
-        for (int h = 0; h < ENT_ITEMS; h += MB) {
-            int32_t lo[MB], hi[MB], end[MB], key[MB];
-#pragma unroll
-            for (int q = 0; q < MB; q++) {
-                const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
-                lo[q] = hi[q] = end[q] = 0;
-                key[q] = -1;
-                if (k >= nnz) continue;
-                const int32_t u = srow[k - base];
-                const int32_t c = scol[k - base];
-                if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
+            const int32_t c = scol[k - base];
+            if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
+            key[q] = u;
+            if (c > r0 && c < r_last && c + 1 - r0 < RS_CAP) {
+                // (clamped to the tile: on a malformed row_ptr, which the row checks flag,
+                // the starts may be stale)
+                inlds |= 1u << q;
+                lo[q] = min(max(s_rs[c - r0], 0), nloc);
+                hi[q] = end[q] = min(max(s_rs[c + 1 - r0], lo[q]), nloc);
+            } else {
                 lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
                 hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
-                key[q] = u;
             }
-            for (;;) {
-                bool busy = false;
+        }
+        for (;;) {
+            bool busy = false;
 #pragma unroll
-                for (int q = 0; q < MB; q++) {
-                    if (key[q] >= 0 && lo[q] < hi[q]) {
-                        const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
-                        if (col[mid] < key[q]) lo[q] = mid + 1;
-                        else hi[q] = mid;
-                        busy = true;
-                    }
+            for (int q = 0; q < MB; q++) {
+                if (key[q] >= 0 && lo[q] < hi[q]) {
+                    const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
+                    const int32_t cm = ((inlds >> q) & 1u) ? scol[mid] : col[mid];
+                    if (cm < key[q]) lo[q] = mid + 1;
+                    else hi[q] = mid;
+                    busy = true;
                 }
-                if (!__any(busy)) break;
             }
+            if (!__any(busy)) break;
+        }
 #pragma unroll
-            for (int q = 0; q < MB; q++)
-                if (key[q] >= 0 && (lo[q] >= end[q] || col[lo[q]] != key[q] ||
-                                    w[lo[q]] != w[base + (int64_t)(h + q) * PB + threadIdx.x]))
-                    f |= F_ASYM;
+        for (int q = 0; q < MB; q++) {
+            if (key[q] < 0) continue;
+            const bool loc = (inlds >> q) & 1u;
+            const int64_t pos = loc ? base + lo[q] : (int64_t)lo[q];
+            const bool found = lo[q] < end[q] && (loc ? scol[lo[q]] : col[pos]) == key[q];
+            if (!found || w[pos] != wv[h + q]) f |= F_ASYM;
         }
     }
     for (int d = 32; d > 0; d >>= 1) {
@@ -292,8 +312,6 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     if (threadIdx.x == 0) {
         for (int i = 1; i < PB / GSS_WAVE; i++) bal += sh[i];
         bpart[tile] = bal;  // per-tile partial sums (no contended atomics)
-    }
-    __syncthreads();  // the tile's shared arrays are reused by the next one
     }
 }
 
@@ -1452,9 +1470,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
                          lb_ticket_ptr(ctx), ctx->d_counters + 13, ctx->d_counters + 9, ctx->d_flags);
             if (validate) {
                 int64_t *bpart = ctx->alloc<int64_t>(etiles + 1);
-                const int64_t cgrid = CHECK_BLOCKS > 0 ? std::min<int64_t>(CHECK_BLOCKS, (etiles + 7) / 8 * 8) : etiles;
-                GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)cgrid), dim3(PB), 0,
-                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart, etiles);
+                GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0,
+                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart);
                 GSS_LAUNCH(k_balance_total, dim3(1), dim3(1024), 0, sa, bpart, etiles, ctx->d_counters + 10);
                 ctx->free(bpart);
             }

@@ -135,3 +135,65 @@ def test_swapped_lower_weights_is_asym(gpu_ctx):
     o = oracle.recover(n=g.n, row_ptr=rp, col=col, w=w, parent=g.parent, alpha=g.alpha, beta=g.beta)
     assert o.status == -3
     assert gpu_status(gpu_ctx, g, w=w) == -3
+
+
+def _multi_tile_cases():
+    """Lower entries of a CSR spanning many 4096-entry tiles (the entry checks work tile by
+    tile): mirrors in the same row neighbourhood (row u - 1, searched inside the tile),
+    far back (row u - 480, about 3300 entries back: in an earlier tile), and entries at
+    the first and last offsets of tiles (rows that straddle a tile boundary)."""
+    g = synth.grid((40, 40, 12), 1.0, 100.0, seed=5)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    lower = np.flatnonzero(g.col < rows)
+    off = lower % 4096
+    d = rows[lower] - g.col[lower]
+    later = lower >= 2 * 4096  # tiles with earlier tiles before them
+    picks = {
+        "near_mid_tile": lower[later & (d == 1) & (off > 1500) & (off < 2500)][[0, 5]],
+        "far_back": lower[later & (d == 480) & (off < 3000)][[0, 5]],
+        "tile_first": lower[later & (off < 4)][:2],
+        "tile_last": lower[later & (off > 4090)][:2],
+        "row_after_tile_start": lower[later & (d == 1) & (off < 12)][:2],
+    }
+    return g, picks
+
+
+@pytest.mark.parametrize("kind", ["near_mid_tile", "far_back", "tile_first", "tile_last", "row_after_tile_start"])
+def test_asym_weight_found_across_tiles(gpu_ctx, kind):
+    """One lower entry's weight changed: the mirror search must see it whether the mirror's
+    row lies inside the entry's tile or not (same status as the oracle's)."""
+    g, picks = _multi_tile_cases()
+    ks = picks[kind]
+    assert len(ks) >= 1
+    for j, k in enumerate(ks):
+        w = g.w.copy()
+        w[k] *= 1.5
+        if j == 0:
+            o = oracle.recover(n=g.n, row_ptr=g.row_ptr, col=g.col, w=w, parent=g.parent, alpha=g.alpha,
+                               beta=g.beta).status
+            assert o == -3
+        assert gpu_status(gpu_ctx, g, w=w) == -3, (kind, int(k))
+    # and the unchanged graph passes
+    assert gpu_status(gpu_ctx, g) >= 0
+
+
+@pytest.mark.parametrize("kind", ["near_mid_tile", "far_back", "tile_first", "tile_last"])
+def test_asym_column_found_across_tiles(gpu_ctx, kind):
+    """One lower entry (u, c) moved to another column c' < u that is not a neighbour of u
+    (rows stay sorted and simple, triangle sizes agree): only the exact mirror search can
+    reject it, wherever the mirror row lies."""
+    g, picks = _multi_tile_cases()
+    k = int(picks[kind][0])
+    rp, col = g.row_ptr, g.col.copy()
+    rows = np.repeat(np.arange(g.n), np.diff(rp))
+    u = int(rows[k])
+    lo = col[k - 1] + 1 if k > rp[u] else 0
+    hi = col[k + 1] if k + 1 < rp[u + 1] else u
+    hi = min(hi, u)
+    free = [c for c in range(lo, hi) if c != col[k] and c not in set(col[rp[u]:rp[u + 1]].tolist())]
+    if not free:
+        pytest.skip("no free column next to this entry")
+    col[k] = free[len(free) // 2]
+    o = oracle.recover(n=g.n, row_ptr=rp, col=col, w=g.w, parent=g.parent, alpha=g.alpha, beta=g.beta).status
+    assert o == -3
+    assert gpu_status(gpu_ctx, g, col=col) == -3
