@@ -339,6 +339,12 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
 int64_t loose_greedy(gss_ctx ctx, int32_t n, int32_t vroot, int64_t P, int32_t c, const int32_t *ancU,
                      const int32_t *ancV, uint8_t *state);
 int64_t sample_sort_max();
+// stable LSD radix sort of (key, double value) pairs by the key bits [shift, shift + 8
+// passes), for large arrays (count, scan, scatter per 8-bit digit); the pointers are
+// swapped so that k, w hold the result (k2, w2 the scratch).  With run (device), nothing
+// is sorted unless *run is nonzero.
+void lsd_sort_kw(gss_ctx ctx, uint64_t *&k, double *&w, uint64_t *&k2, double *&w2, int64_t n, int shift,
+                 int passes, const int64_t *run = nullptr);
 
 // ---- shared launch helpers (gss_prims.hip) -------------------------------------------
 // exclusive scan of int32 counts in place over [0,n); returns the total (host sync)

@@ -176,22 +176,22 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
 
 
 // CSR checks: column range, strictly increasing rows, no self-loops, positive finite
-// weights, the mirror of every lower entry, and per tile the number of upper minus lower
-// entries.
-// Symmetry is checked exactly: every lower entry (u, c), c < u, must find its mirror
-// (c, u) in row c with the same weight, and the triangles must hold equally many entries.
-// Mirroring is injective, so with equal counts it is a bijection between the triangles:
-// every upper entry then has its mirror too.
-// Memory-safe on any input: rows are clamped.
+// weights, and per tile the number of upper minus lower entries.  With *mode = 0 it also
+// checks symmetry exactly by a mirror search: every lower entry (u, c), c < u, must find
+// (c, u) in row c with the same weight; with equally many entries in both triangles,
+// mirroring (injective) is then a bijection between them, so every upper entry has its
+// mirror too.  With *mode = 1 the transpose comparison (k_sym_compare) checks symmetry
+// instead.  Memory-safe on any input: rows are clamped.
 __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
                                                       const int32_t *__restrict__ tile_row, uint32_t *flags,
-                                                      int64_t *__restrict__ bpart)
+                                                      int64_t *__restrict__ bpart, const int64_t *__restrict__ mode)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t scol[ETILE];
     __shared__ int32_t s_rs[RS_CAP];
+    const bool search = *mode == 0;
     __shared__ int64_t sh[PB / GSS_WAVE];
     __shared__ int32_t s_prev[2];  // row and column of entry base-1 (-1 if none)
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
             s_prev[1] = col[base - 1];
         }
     }
-    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow, s_rs);  // synchronises
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow, search ? s_rs : nullptr);  // synchronises
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) scol[i * PB + threadIdx.x] = cv[i];
     __syncthreads();
@@ -245,59 +245,61 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
         if (!(x > 0.0) || !isfinite(x)) f |= F_WEIGHT;
         bal += (c > u) ? 1 : (c < u ? -1 : 0);
     }
-    // The mirror (c, u) of every lower entry (u, c) is searched in row c.  A row lying
-    // wholly inside the tile (r0 < c < r_last, its start within RS_CAP rows of r0) is
-    // bisected in LDS; any other row in global memory, the searches of eight entries in
-    // lockstep so that their loads overlap.  lo/hi bisect the row for the first column
-    // >= u (tile offsets for a row in LDS, CSR positions otherwise).  Row bounds are
-    // clamped so malformed input stays in bounds.
-    constexpr int MB = 8;
+    if (search) {
+        // The mirror (c, u) of every lower entry (u, c) is searched in row c.  A row lying
+        // wholly inside the tile (r0 < c < r_last, its start within RS_CAP rows of r0) is
+        // bisected in LDS; any other row in global memory, the searches of eight entries in
+        // lockstep so that their loads overlap.  lo/hi bisect the row for the first column
+        // >= u (tile offsets for a row in LDS, CSR positions otherwise).  Row bounds are
+        // clamped so malformed input stays in bounds.
+        constexpr int MB = 8;
 #pragma unroll 1
-    for (int h = 0; h < ENT_ITEMS; h += MB) {
-        int32_t lo[MB], hi[MB], end[MB], key[MB];
-        uint32_t inlds = 0;
-#pragma unroll
-        for (int q = 0; q < MB; q++) {
-            const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
-            lo[q] = hi[q] = end[q] = 0;
-            key[q] = -1;
-            if (k >= nnz) continue;
-            const int32_t u = srow[k - base];
-            const int32_t c = scol[k - base];
-            if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
-            key[q] = u;
-            if (c > r0 && c < r_last && c + 1 - r0 < RS_CAP) {
-                // (clamped to the tile: on a malformed row_ptr, which the row checks flag,
-                // the starts may be stale)
-                inlds |= 1u << q;
-                lo[q] = min(max(s_rs[c - r0], 0), nloc);
-                hi[q] = end[q] = min(max(s_rs[c + 1 - r0], lo[q]), nloc);
-            } else {
-                lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
-                hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
-            }
-        }
-        for (;;) {
-            bool busy = false;
+        for (int h = 0; h < ENT_ITEMS; h += MB) {
+            int32_t lo[MB], hi[MB], end[MB], key[MB];
+            uint32_t inlds = 0;
 #pragma unroll
             for (int q = 0; q < MB; q++) {
-                if (key[q] >= 0 && lo[q] < hi[q]) {
-                    const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
-                    const int32_t cm = ((inlds >> q) & 1u) ? scol[mid] : col[mid];
-                    if (cm < key[q]) lo[q] = mid + 1;
-                    else hi[q] = mid;
-                    busy = true;
+                const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
+                lo[q] = hi[q] = end[q] = 0;
+                key[q] = -1;
+                if (k >= nnz) continue;
+                const int32_t u = srow[k - base];
+                const int32_t c = scol[k - base];
+                if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
+                key[q] = u;
+                if (c > r0 && c < r_last && c + 1 - r0 < RS_CAP) {
+                    // (clamped to the tile: on a malformed row_ptr, which the row checks flag,
+                    // the starts may be stale)
+                    inlds |= 1u << q;
+                    lo[q] = min(max(s_rs[c - r0], 0), nloc);
+                    hi[q] = end[q] = min(max(s_rs[c + 1 - r0], lo[q]), nloc);
+                } else {
+                    lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
+                    hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
                 }
             }
-            if (!__any(busy)) break;
-        }
+            for (;;) {
+                bool busy = false;
 #pragma unroll
-        for (int q = 0; q < MB; q++) {
-            if (key[q] < 0) continue;
-            const bool loc = (inlds >> q) & 1u;
-            const int64_t pos = loc ? base + lo[q] : (int64_t)lo[q];
-            const bool found = lo[q] < end[q] && (loc ? scol[lo[q]] : col[pos]) == key[q];
-            if (!found || w[pos] != wv[h + q]) f |= F_ASYM;
+                for (int q = 0; q < MB; q++) {
+                    if (key[q] >= 0 && lo[q] < hi[q]) {
+                        const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
+                        const int32_t cm = ((inlds >> q) & 1u) ? scol[mid] : col[mid];
+                        if (cm < key[q]) lo[q] = mid + 1;
+                        else hi[q] = mid;
+                        busy = true;
+                    }
+                }
+                if (!__any(busy)) break;
+            }
+#pragma unroll
+            for (int q = 0; q < MB; q++) {
+                if (key[q] < 0) continue;
+                const bool loc = (inlds >> q) & 1u;
+                const int64_t pos = loc ? base + lo[q] : (int64_t)lo[q];
+                const bool found = lo[q] < end[q] && (loc ? scol[lo[q]] : col[pos]) == key[q];
+                if (!found || w[pos] != wv[h + q]) f |= F_ASYM;
+            }
         }
     }
     for (int d = 32; d > 0; d >>= 1) {
@@ -343,6 +345,9 @@ __global__ void k_prep_init(uint32_t *flags, int64_t *counters, int32_t n)
         counters[2] = (int64_t)1 << 40;
         counters[3] = -((int64_t)1 << 40);
         counters[4] = 0;
+        counters[5] = 0;
+        counters[6] = 0;
+        counters[7] = 0;
         counters[9] = 0;
         counters[10] = 0;
         counters[13] = 0;
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(PB) void k_tree_entries(const int32_t *__restrict__
                                                      const int32_t *__restrict__ parent, int32_t n, int64_t nnz,
                                                      const int32_t *__restrict__ tile_row,
                                                      int32_t *__restrict__ tpos, double *__restrict__ tinv,
-                                                     int4 *__restrict__ part)
+                                                     int4 *__restrict__ part, int2 *__restrict__ remote)
 {
     __shared__ int32_t srow[ETILE];
     __shared__ int32_t sred[4][PB / GSS_WAVE];
@@ -389,6 +394,21 @@ __global__ __launch_bounds__(PB) void k_tree_entries(const int32_t *__restrict__
     int32_t pu[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) pu[i] = cv[i] >= 0 ? parent[srow[i * PB + threadIdx.x]] : -1;
+    // In one tile of eight: the lower entries, and those whose column lies outside the
+    // tile's rows (their mirror rows are not in the tile); the sample chooses how
+    // symmetry is checked.
+    const int32_t nloc = (int32_t)min((int64_t)ETILE, nnz - base);
+    const int32_t r0 = srow[0], r_last = srow[nloc - 1];
+    int far = 0, low = 0;
+    if ((tile & 7) == 0) {
+#pragma unroll
+        for (int i = 0; i < ENT_ITEMS; i++) {
+            const int32_t u = srow[i * PB + threadIdx.x];
+            const bool lower = cv[i] >= 0 && cv[i] < u;
+            low += lower ? 1 : 0;
+            far += (lower && (cv[i] < r0 || cv[i] > r_last)) ? 1 : 0;
+        }
+    }
     uint32_t f = 0;
     int found = 0;
     int emin = 1 << 30, emax = -(1 << 30);
@@ -412,15 +432,20 @@ __global__ __launch_bounds__(PB) void k_tree_entries(const int32_t *__restrict__
     for (int d = 32; d > 0; d >>= 1) {
         f |= __shfl_xor(f, d, GSS_WAVE);
         found += __shfl_xor(found, d, GSS_WAVE);
+        far += __shfl_xor(far, d, GSS_WAVE);
+        low += __shfl_xor(low, d, GSS_WAVE);
         emin = min(emin, __shfl_xor(emin, d, GSS_WAVE));
         emax = max(emax, __shfl_xor(emax, d, GSS_WAVE));
     }
     const int wid = threadIdx.x / GSS_WAVE;
+    __shared__ int32_t s_far[2][PB / GSS_WAVE];
     if (lane_id() == 0) {
         sred[0][wid] = (int32_t)f;
         sred[1][wid] = found;
         sred[2][wid] = emin;
         sred[3][wid] = emax;
+        s_far[0][wid] = far;
+        s_far[1][wid] = low;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -429,30 +454,40 @@ __global__ __launch_bounds__(PB) void k_tree_entries(const int32_t *__restrict__
             found += sred[1][i];
             emin = min(emin, sred[2][i]);
             emax = max(emax, sred[3][i]);
+            far += s_far[0][i];
+            low += s_far[1][i];
         }
         part[tile] = make_int4((int32_t)f, found, emin, emax);
+        remote[tile] = make_int2(far, low);
     }
 }
 
 // combines the per-tile results of k_tree_entries: flags, the number of tree edges found
-// (counters[4]) and the exponent range (counters[2], counters[3])
-__global__ __launch_bounds__(1024) void k_tree_total(const int4 *__restrict__ part, int64_t ntiles, uint32_t *flags,
-                                                     int64_t *counters)
+// (counters[4]), the exponent range (counters[2], counters[3]), the sampled lower entries
+// (counters[6]) and those among them whose column lies outside their tile's rows
+// (counters[5]), and the symmetry method they choose (counters[7]: 1 = transposition)
+__global__ __launch_bounds__(1024) void k_tree_total(const int4 *__restrict__ part, const int2 *__restrict__ remote,
+                                                     int64_t ntiles, uint32_t *flags, int64_t *counters)
 {
     __shared__ int32_t sred[4][1024 / GSS_WAVE];
+    __shared__ int64_t s_far[2][1024 / GSS_WAVE];
     uint32_t f = 0;
-    int64_t found = 0;
+    int64_t found = 0, far = 0, low = 0;
     int emin = 1 << 30, emax = -(1 << 30);
     for (int64_t i = threadIdx.x; i < ntiles; i += 1024) {
         const int4 p = part[i];
         f |= (uint32_t)p.x;
         found += p.y;
+        far += remote[i].x;
+        low += remote[i].y;
         emin = min(emin, p.z);
         emax = max(emax, p.w);
     }
     for (int d = 32; d > 0; d >>= 1) {
         f |= __shfl_xor(f, d, GSS_WAVE);
         found += __shfl_xor(found, d, GSS_WAVE);
+        far += __shfl_xor(far, d, GSS_WAVE);
+        low += __shfl_xor(low, d, GSS_WAVE);
         emin = min(emin, __shfl_xor(emin, d, GSS_WAVE));
         emax = max(emax, __shfl_xor(emax, d, GSS_WAVE));
     }
@@ -462,17 +497,24 @@ __global__ __launch_bounds__(1024) void k_tree_total(const int4 *__restrict__ pa
         sred[1][wid] = (int32_t)found;  // per wave below 2^31: at most n tree edges
         sred[2][wid] = emin;
         sred[3][wid] = emax;
+        s_far[0][wid] = far;
+        s_far[1][wid] = low;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < 1024 / GSS_WAVE; i++) {
             f |= (uint32_t)sred[0][i];
             found += sred[1][i];
+            far += s_far[0][i];
+            low += s_far[1][i];
             emin = min(emin, sred[2][i]);
             emax = max(emax, sred[3][i]);
         }
         if (f) atomicOr(flags, f);
         counters[4] = found;
+        counters[5] = far;
+        counters[6] = low;
+        counters[7] = 2 * far > low ? 1 : 0;  // symmetry by transposition (else mirror search)
         if (emin <= emax) {
             counters[2] = emin;
             counters[3] = emax;
@@ -1236,16 +1278,23 @@ __global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, 
 // (two counters, wave 0 and wave 1 look back in parallel), ranks both kinds inside the
 // tile in entry order (round, wave, lane), writes every off-tree edge's id, endpoints
 // and weight at its place, and gives each tree edge's id to the child endpoint
-// (tree_eid).  The last tile writes both totals.  Memory-safe on any input: rows are
-// clamped, output places are bounded by Mcap (F_TREE_EDGE beyond it) and parent values
-// are only compared.
+// (tree_eid).  The last tile writes both totals.  With lkey and *mode = 1, every lower
+// entry (u, c), c < u, is also written at its rank among the lower entries (its position
+// minus the upper entries before it) as the key c << 32 | u and its weight, and
+// ubase[tile] receives the
+// tile's first edge id: the transpose check sorts the lower entries by column and
+// compares them with the upper ones.  Memory-safe on any input: rows are clamped, output
+// places are bounded by Mcap (F_TREE_EDGE beyond it) and by Lcap (F_ASYM beyond it:
+// more lower entries than half of all), and parent values are only compared.
 __global__ __launch_bounds__(PB) void k_off_write(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ w,
     const int32_t *__restrict__ parent, int32_t n, int64_t nnz, int64_t ntiles, const int32_t *__restrict__ tile_row,
     int64_t Mcap, int32_t *__restrict__ off_id, int32_t *__restrict__ off_u, int32_t *__restrict__ off_v,
     double *__restrict__ off_w, const int32_t *__restrict__ vbase, int32_t G, int32_t *__restrict__ off_g,
     int32_t *__restrict__ tree_eid, uint64_t *__restrict__ status, uint32_t epoch, unsigned long long *ticket,
-    int64_t *__restrict__ m_total, int64_t *__restrict__ off_total, uint32_t *flags)
+    int64_t *__restrict__ m_total, int64_t *__restrict__ off_total, uint32_t *flags, int64_t Lcap,
+    uint64_t *__restrict__ lkey, double *__restrict__ lw, int32_t *__restrict__ ubase,
+    const int64_t *__restrict__ mode)
 {
     constexpr int NW = PB / GSS_WAVE;
     static_assert(ENT_ITEMS * NW <= GSS_WAVE, "one wave scans the piece counts");
@@ -1331,6 +1380,23 @@ __global__ __launch_bounds__(PB) void k_off_write(
     __syncthreads();
     const uint64_t lt = lanemask_lt();
     const int64_t ex_u = s_ex[0], ex_o = s_ex[1];
+    if (lkey && *mode == 1) {
+        if (threadIdx.x == 0) ubase[tile] = (int32_t)ex_u;
+        // lower entries at their rank: position minus the upper entries before it
+#pragma unroll
+        for (int i = 0; i < ENT_ITEMS; i++) {
+            const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+            const int32_t u = srow[i * PB + threadIdx.x];
+            if (k >= nnz || cv[i] < 0 || cv[i] >= u) continue;
+            const int64_t r = k - (ex_u + s_off[0][i][wid] + __popcll(um[i] & lt));
+            if (r < 0 || r >= Lcap) {
+                atomicOr(flags, F_ASYM);
+                continue;
+            }
+            lkey[r] = ((uint64_t)(uint32_t)cv[i] << 32) | (uint32_t)u;
+            lw[r] = w[k];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
         if (!((um[i] >> lane) & 1ull)) continue;
@@ -1361,6 +1427,77 @@ __global__ __launch_bounds__(PB) void k_off_write(
             off_g[o] = lo;
         }
     }
+}
+
+// Transpose comparison (exact symmetry).  The lower entries (u, c), c < u, in CSR order
+// are ordered by (u, c); sorted stably by column they are ordered by (c, u), the order in
+// which their mirrors (c, u) appear among the upper entries, which is edge-id order.  So
+// the graph is symmetric exactly when there are as many lower as upper entries (the
+// balance of k_check_entries) and the j-th sorted lower entry is (x, c) with weight w for
+// the upper entry (c, x) of weight w with id j, for every j (keys c << 32 | x).  One workgroup per tile;
+// the ids come from the tile's first id (ubase) and ranks inside the tile.  Memory-safe
+// on any input: rows are clamped and ids are bounded by Lcap (F_ASYM beyond it).
+__global__ __launch_bounds__(PB) void k_sym_compare(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col, const double *__restrict__ w,
+                                                    int32_t n, int64_t nnz, const int32_t *__restrict__ tile_row,
+                                                    const int32_t *__restrict__ ubase, int64_t Lcap,
+                                                    const uint64_t *__restrict__ lkey, const double *__restrict__ lw,
+                                                    uint32_t *flags, const int64_t *__restrict__ mode)
+{
+    if (*mode != 1) return;  // symmetry checked by the mirror search
+    constexpr int NW = PB / GSS_WAVE;
+    static_assert(ENT_ITEMS * NW <= GSS_WAVE, "one wave scans the piece counts");
+    __shared__ int32_t srow[ETILE];
+    __shared__ int32_t s_cnt[ENT_ITEMS][NW];
+    __shared__ int32_t s_off[ENT_ITEMS][NW];
+    const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = tile * ETILE;
+    int32_t cv[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        cv[i] = k < nnz ? col[k] : -1;
+    }
+    load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+    uint64_t um[ENT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        const int32_t u = srow[i * PB + threadIdx.x];
+        um[i] = __ballot(cv[i] > u && cv[i] < n);
+        if (lane == 0) s_cnt[i][wid] = __popcll(um[i]);
+    }
+    __syncthreads();
+    if (wid == 0) {
+        const int i = lane / NW, w2 = lane % NW;
+        const bool has = lane < ENT_ITEMS * NW;
+        int32_t x = has ? s_cnt[i][w2] : 0;
+        const int32_t own = x;
+#pragma unroll
+        for (int d = 1; d < GSS_WAVE; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, GSS_WAVE);
+            if (lane >= d) x += y;
+        }
+        if (has) s_off[i][w2] = x - own;
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    const int64_t ub = ubase[tile];
+    uint32_t f = 0;
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        if (!((um[i] >> lane) & 1ull)) continue;
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        const int64_t j = ub + s_off[i][wid] + __popcll(um[i] & lt);
+        if (j < 0 || j >= Lcap) {
+            f |= F_ASYM;
+            continue;
+        }
+        const int32_t u = srow[i * PB + threadIdx.x];
+        if (lkey[j] != (((uint64_t)(uint32_t)u << 32) | (uint32_t)cv[i]) || lw[j] != w[k]) f |= F_ASYM;
+    }
+    for (int d = 32; d > 0; d >>= 1) f |= __shfl_xor(f, d, GSS_WAVE);
+    if (lane == 0 && f) atomicOr(flags, f);
 }
 
 // the root's vertex record (preorder index 0, depth 0, D = 0, its tree degree), its LCA
@@ -1442,19 +1579,33 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
     GSS_LAUNCH(k_tree_init, dim3(grid_for(n, PB)), dim3(PB), 0, st, ccnt, fc, tpos, n);
     if (nnz > 0) {
         int4 *part = ctx->alloc<int4>(etiles);
+        int2 *remote = ctx->alloc<int2>(etiles);
         GSS_LAUNCH_B(4 * nnz + 4 * (int64_t)n + 20 * (int64_t)n, k_tree_entries, dim3((unsigned)etiles), dim3(PB),
-                     0, st, t->row_ptr, t->col, t->w, t->parent, n, nnz, tile_row, tpos, tinv, part);
-        GSS_LAUNCH(k_tree_total, dim3(1), dim3(1024), 0, st, part, etiles, ctx->d_flags, ctx->d_counters);
+                     0, st, t->row_ptr, t->col, t->w, t->parent, n, nnz, tile_row, tpos, tinv, part, remote);
+        GSS_LAUNCH(k_tree_total, dim3(1), dim3(1024), 0, st, part, remote, etiles, ctx->d_flags, ctx->d_counters);
         ctx->free(part);
+        ctx->free(remote);
     }
     GSS_LAUNCH_B(12 * (int64_t)n, k_tree_vertices, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, ccnt, fc,
                  nsib, ctx->d_flags, ctx->d_counters);
 
+    struct Transpose {
+        uint64_t *lk, *lk2;
+        double *lw, *lw2;
+        int32_t *ub;
+        int64_t Lcap;
+    } tr{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     // The auxiliary stream numbers the edges (off-tree edges, tree edge ids) and validates
-    // the CSR (entry checks with the mirror search of the symmetry check) beside the rest
-    // of the tree preparation, which waits for it only at its end; everything on the
-    // context stream is memory-safe on a malformed CSR.  It starts after the tree checks
-    // above, which the first host wait needs, so they get the whole device.
+    // the CSR (entry checks and symmetry) beside the rest of the tree preparation, which
+    // waits for it only at its end; everything on the context stream is memory-safe on a
+    // malformed CSR.  It starts after the tree passes above (which the first host wait
+    // needs), so they have the device to themselves.  Symmetry is checked by mirror
+    // search when most lower entries find their mirror row inside their own tile
+    // (searched in LDS; grid-like graphs), by transposition (a sort of the lower entries
+    // by column, then a streaming comparison) when most mirror rows lie elsewhere (random
+    // columns, where every search is a chain of random loads); the tree pass's sample
+    // chose, in counters[7], which the kernels read and the host reads at its first wait
+    // (the sort and the comparison are enqueued only for transposition).
     {
         AuxScope aux(ctx);
         hipStream_t sa = ctx->stream;
@@ -1462,27 +1613,65 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         if (nnz > 0) {
             uint32_t epoch = 0;
             uint64_t *status = lb_begin(ctx, 2 * etiles, &epoch);
+            // transposition: the lower entries (key, weight) at their ranks, and each tile's
+            // first edge id
+            const int64_t Lcap = m;
+            uint64_t *lk = nullptr, *lk2 = nullptr;
+            int32_t *ub = nullptr;
+            double *lw = nullptr, *lw2 = nullptr;
+            const int64_t *mode = ctx->d_counters + 7;
+            if (validate) {
+                lk = ctx->alloc<uint64_t>(Lcap + 1);
+                lk2 = ctx->alloc<uint64_t>(Lcap + 1);
+                lw = ctx->alloc<double>(Lcap + 1);
+                lw2 = ctx->alloc<double>(Lcap + 1);
+                ub = ctx->alloc<int32_t>(etiles + 1);
+            }
             // columns and both parents read per entry; per off-tree edge its id, endpoints
             // and weight written, per tree edge its id
-            GSS_LAUNCH_B(8 * nnz + 28 * t->M + 4 * (int64_t)n, k_off_write, dim3((unsigned)etiles), dim3(PB), 0, sa,
-                         t->row_ptr, t->col, t->w, t->parent, n, nnz, etiles, tile_row, t->M, t->off_id, t->off_u,
-                         t->off_v, t->off_w, t->d_vbase, t->G, t->off_g, t->tree_eid, status, epoch,
-                         lb_ticket_ptr(ctx), ctx->d_counters + 13, ctx->d_counters + 9, ctx->d_flags);
+            GSS_LAUNCH_B(8 * nnz + 28 * t->M + 4 * (int64_t)n, k_off_write,
+                         dim3((unsigned)etiles), dim3(PB), 0, sa, t->row_ptr, t->col, t->w, t->parent, n, nnz, etiles,
+                         tile_row, t->M, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g,
+                         t->tree_eid, status, epoch, lb_ticket_ptr(ctx), ctx->d_counters + 13, ctx->d_counters + 9,
+                         ctx->d_flags, Lcap, lk, lw, ub, mode);
             if (validate) {
                 int64_t *bpart = ctx->alloc<int64_t>(etiles + 1);
                 GSS_LAUNCH_B(12 * nnz + 4 * (int64_t)(n + 1), k_check_entries, dim3((unsigned)etiles), dim3(PB), 0,
-                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart);
+                             sa, t->row_ptr, t->col, t->w, n, nnz, tile_row, ctx->d_flags, bpart, mode);
                 GSS_LAUNCH(k_balance_total, dim3(1), dim3(1024), 0, sa, bpart, etiles, ctx->d_counters + 10);
                 ctx->free(bpart);
             }
+            tr = Transpose{lk, lk2, lw, lw2, ub, Lcap};
         }
     }
-    HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+
+    HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    ctx->sync_stream();  // the auxiliary stream keeps running
+    ctx->sync_stream();
     uint32_t f;
     memcpy(&f, &ctx->h_counters[15], sizeof f);
     const int64_t roots = ctx->h_counters[0];
+    if (tr.lk) {
+        if (ctx->h_counters[7] == 1) {
+            // transposition: the lower entries sorted stably by column (the column digits
+            // of the keys), compared with the upper entries in id order
+            AuxScope aux(ctx);
+            int kb = 1;
+            while (kb < 4 && ((uint64_t)(n - 1) >> (8 * kb)) != 0) kb++;
+            lsd_sort_kw(ctx, tr.lk, tr.lw, tr.lk2, tr.lw2, tr.Lcap, 32, kb);
+            GSS_LAUNCH_B(4 * nnz + 8 * m + 16 * tr.Lcap, k_sym_compare, dim3((unsigned)etiles), dim3(PB), 0,
+                         ctx->stream, t->row_ptr, t->col, t->w, n, nnz, tile_row, tr.ub, tr.Lcap, tr.lk, tr.lw,
+                         ctx->d_flags, ctx->d_counters + 7);
+            for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
+                ctx->free(p);
+        } else {
+            // mirror search: the lists were not written; they return to the pool once the
+            // auxiliary stream is joined
+            AuxScope aux(ctx);
+            for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
+                ctx->free(p);
+        }
+    }
     auto free_tree_tmp = [&]() {
         ctx->free(ccnt);
         ctx->free(fc);

@@ -375,3 +375,124 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
 }
 
 int64_t sample_sort_max() { return (int64_t)SS_MAXB * 1024; }
+
+// ------------------------------------------------------------------------------------
+// LSD radix sort of large (key, double) arrays: per 8-bit digit a counting pass (one
+// LDS histogram per tile, stored digit-major), an exclusive scan of the digit-major
+// counts (every digit's tiles in order, digits in order), and a scatter pass that ranks
+// each tile's elements per digit in element order (wave-level peer ballots, then the
+// waves in order) and adds the tile's scanned offset.  Stable; every pass is a stream
+// over the arrays with no chain between tiles.  With run, the passes do nothing unless
+// *run is nonzero (a choice made on the device).
+// ------------------------------------------------------------------------------------
+#define LSD_BLOCK 256
+#define LSD_ITEMS 16
+#define LSD_TILE (LSD_BLOCK * LSD_ITEMS)
+
+__global__ __launch_bounds__(LSD_BLOCK) void k_lsd_count(const uint64_t *__restrict__ k, int64_t n, int shift,
+                                                         int64_t ntiles, int32_t *__restrict__ hist,
+                                                         const int64_t *__restrict__ run)
+{
+    if (run && *run == 0) return;
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * LSD_TILE;
+#pragma unroll
+    for (int i = 0; i < LSD_ITEMS; i++) {
+        const int64_t idx = base + (int64_t)i * LSD_BLOCK + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(uint32_t)(k[idx] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(LSD_BLOCK) void k_lsd_scatter(const uint64_t *__restrict__ kin,
+                                                           const double *__restrict__ win, int64_t n, int shift,
+                                                           int64_t ntiles, const int32_t *__restrict__ off,
+                                                           uint64_t *__restrict__ kout, double *__restrict__ wout,
+                                                           const int64_t *__restrict__ run)
+{
+    if (run && *run == 0) return;
+    constexpr int NW = LSD_BLOCK / GSS_WAVE;
+    constexpr int PER = LSD_ITEMS;  // items per lane in the wave's contiguous chunk
+    __shared__ int32_t s_cnt[NW][256];
+    const int t = threadIdx.x, wid = t / GSS_WAVE, lane = lane_id();
+#pragma unroll
+    for (int w = 0; w < NW; w++) s_cnt[w][t] = 0;
+    __syncthreads();
+    // wave wid owns the contiguous chunk [wbase, wbase + PER * 64) of the tile
+    const int64_t wbase = (int64_t)blockIdx.x * LSD_TILE + (int64_t)wid * (PER * GSS_WAVE);
+    uint64_t kk[PER];
+    double ww[PER];
+    int32_t pos[PER];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const int64_t idx = wbase + i * GSS_WAVE + lane;
+        kk[i] = idx < n ? kin[idx] : 0;
+        ww[i] = idx < n ? win[idx] : 0.0;
+    }
+    int32_t *cnt = s_cnt[wid];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const bool valid = wbase + i * GSS_WAVE + lane < n;
+        const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const int leader = peers ? __ffsll((long long)peers) - 1 : lane;
+        int32_t old = 0;
+        if (valid && lane == leader) {
+            old = cnt[d];
+            cnt[d] = old + __popcll(peers);
+        }
+        old = __shfl(old, leader, GSS_WAVE);
+        pos[i] = old + __popcll(peers & lanemask_lt());
+    }
+    __syncthreads();
+    // thread t: digit t's base for each wave = the tile's scanned offset + earlier waves
+    {
+        int32_t run = off[(int64_t)t * ntiles + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const int32_t c = s_cnt[w][t];
+            s_cnt[w][t] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        if (wbase + i * GSS_WAVE + lane < n) {
+            const int32_t o = cnt[(uint32_t)(kk[i] >> shift) & 255u] + pos[i];
+            kout[o] = kk[i];
+            wout[o] = ww[i];
+        }
+    }
+}
+
+void lsd_sort_kw(gss_ctx ctx, uint64_t *&k, double *&w, uint64_t *&k2, double *&w2, int64_t n, int shift,
+                 int passes, const int64_t *run)
+{
+    if (n <= 1) return;
+    if (n >= ((int64_t)1 << 31)) throw gss_error{GSS_ERR_ARG, "radix sort: too many elements"};
+    hipStream_t st = ctx->stream;
+    const int64_t ntiles = (n + LSD_TILE - 1) / LSD_TILE;
+    int32_t *hist = ctx->alloc<int32_t>(256 * ntiles + 1);
+    for (int p = 0; p < passes; p++) {
+        const int sh = shift + 8 * p;
+        GSS_LAUNCH_B(8 * n, k_lsd_count, dim3((unsigned)ntiles), dim3(LSD_BLOCK), 0, ctx->stream, k, n, sh, ntiles,
+                     hist, run);
+        scan_exclusive_i32_dev(ctx, hist, 256 * ntiles, ctx->d_counters + 11);
+        GSS_LAUNCH_B(32 * n, k_lsd_scatter, dim3((unsigned)ntiles), dim3(LSD_BLOCK), 0, ctx->stream, k, w, n, sh,
+                     ntiles, hist, k2, w2, run);
+        HIP_OK(hipGetLastError());
+        std::swap(k, k2);
+        std::swap(w, w2);
+    }
+    ctx->free(hist);
+    (void)st;
+}

@@ -197,3 +197,48 @@ def test_asym_column_found_across_tiles(gpu_ctx, kind):
     o = oracle.recover(n=g.n, row_ptr=rp, col=col, w=g.w, parent=g.parent, alpha=g.alpha, beta=g.beta).status
     assert o == -3
     assert gpu_status(gpu_ctx, g, col=col) == -3
+
+
+def _rmat_cases():
+    """R-MAT 14 (random columns): its lower entries mostly have their mirror rows outside
+    their own tile, so symmetry is checked by transposition (sort by column, compare)."""
+    g = synth.config("rmat14")
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    lower = np.flatnonzero(g.col < rows)
+    off = lower % 4096
+    later = lower >= 2 * 4096
+    return g, rows, {"tile_first": lower[later & (off < 4)][0], "mid": lower[later & (off > 2000)][0],
+                     "tile_last": lower[later & (off > 4090)][0], "last_entry": lower[-1]}
+
+
+@pytest.mark.parametrize("kind", ["tile_first", "mid", "tile_last", "last_entry"])
+def test_asym_weight_found_by_transposition(gpu_ctx, kind):
+    g, rows, picks = _rmat_cases()
+    k = int(picks[kind])
+    w = g.w.copy()
+    w[k] = w[k] * 0.5 + 1e-3
+    o = oracle.recover(n=g.n, row_ptr=g.row_ptr, col=g.col, w=w, parent=g.parent, alpha=g.alpha, beta=g.beta).status
+    assert o == -3
+    assert gpu_status(gpu_ctx, g, w=w) == -3
+    assert gpu_status(gpu_ctx, g) >= 0
+
+
+def test_asym_column_found_by_transposition(gpu_ctx):
+    """A lower entry moved to a free column below its row (sorted, simple, equal triangle
+    sizes): only the exact comparison of the transposed lower triangle can reject it."""
+    g, rows, picks = _rmat_cases()
+    rp, col = g.row_ptr, g.col.copy()
+    done = False
+    for k in (int(picks["mid"]), int(picks["tile_first"]), int(picks["tile_last"])):
+        u = int(rows[k])
+        lo = col[k - 1] + 1 if k > rp[u] else 0
+        hi = min(col[k + 1] if k + 1 < rp[u + 1] else u, u)
+        free = [c for c in range(lo, hi) if c != col[k]]
+        if free:
+            col[k] = free[len(free) // 2]
+            done = True
+            break
+    assert done
+    o = oracle.recover(n=g.n, row_ptr=rp, col=col, w=g.w, parent=g.parent, alpha=g.alpha, beta=g.beta).status
+    assert o == -3
+    assert gpu_status(gpu_ctx, g, col=col) == -3

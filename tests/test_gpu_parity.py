@@ -42,6 +42,34 @@ def test_tree_prep_matches_oracle(gpu_ctx, name, make, seed):
     tree.free()
 
 
+# Graphs whose rows cross the 4096-entry tiles of the CSR passes in every way the child
+# lists are built: a hub row spanning several tiles (its children linked as one segment
+# per tile), tiles of more than 1024 short rows (rows past the tracked ones linked per
+# child), and rows that straddle tile boundaries.
+MULTI_TILE = [
+    ("big_star", lambda: synth.star_graph(12000, 3000, seed=4, alpha=0.05, beta=2)),
+    ("long_path", lambda: synth.path_graph(12000, 800, seed=5, alpha=0.2, beta=2)),
+    ("rmat14", lambda: synth.config("rmat14")),
+    ("grid3d", lambda: synth.grid((30, 20, 25), 1.0, 1e4, seed=6, alpha=0.1, beta=2)),
+]
+
+
+@pytest.mark.parametrize("name,make", MULTI_TILE, ids=[s[0] for s in MULTI_TILE])
+def test_tree_prep_multi_tile_matches_oracle(gpu_ctx, name, make):
+    g = make()
+    orc = run_oracle(g)
+    tree = gss.Tree.from_graph(gpu_ctx, g)
+    depth, dlo, dhi, scale = tree.export()
+    np.testing.assert_array_equal(depth.cpu().numpy(), orc.depth)
+    np.testing.assert_array_equal(dlo.cpu().numpy().view(np.uint64), orc.Dlo)
+    np.testing.assert_array_equal(dhi.cpu().numpy().view(np.uint64), orc.Dhi)
+    lca, bstar = tree.edge_lca(2)
+    np.testing.assert_array_equal(lca.cpu().numpy(), orc.lca)
+    np.testing.assert_array_equal(bstar.cpu().numpy(), orc.bstar)
+    tree.free()
+    assert_same_recovery(run_gpu(gpu_ctx, g), orc)
+
+
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_recover_small(gpu_ctx, name, make, seed):
