@@ -407,6 +407,11 @@ __global__ __launch_bounds__(LSD_BLOCK) void k_lsd_count(const uint64_t *__restr
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// The scatter stages each tile in LDS in digit order first (local place = the digit's
+// start in the tile + the earlier waves' count of it + the rank in the wave), then writes
+// the staged keys, and after them the staged values, in order: consecutive threads write
+// consecutive places of a digit's run, so the writes are coalesced instead of 256-way
+// scattered.
 __global__ __launch_bounds__(LSD_BLOCK) void k_lsd_scatter(const uint64_t *__restrict__ kin,
                                                            const double *__restrict__ win, int64_t n, int shift,
                                                            int64_t ntiles, const int32_t *__restrict__ off,
@@ -417,12 +422,17 @@ __global__ __launch_bounds__(LSD_BLOCK) void k_lsd_scatter(const uint64_t *__res
     constexpr int NW = LSD_BLOCK / GSS_WAVE;
     constexpr int PER = LSD_ITEMS;  // items per lane in the wave's contiguous chunk
     __shared__ int32_t s_cnt[NW][256];
+    __shared__ int32_t s_scan[NW + 1];
+    __shared__ int32_t s_dstart[256], s_goff[256];
+    __shared__ uint64_t s_k[LSD_TILE];  // keys, then values, in digit order
+    __shared__ uint8_t s_d[LSD_TILE];
     const int t = threadIdx.x, wid = t / GSS_WAVE, lane = lane_id();
 #pragma unroll
     for (int w = 0; w < NW; w++) s_cnt[w][t] = 0;
     __syncthreads();
     // wave wid owns the contiguous chunk [wbase, wbase + PER * 64) of the tile
-    const int64_t wbase = (int64_t)blockIdx.x * LSD_TILE + (int64_t)wid * (PER * GSS_WAVE);
+    const int64_t tbase = (int64_t)blockIdx.x * LSD_TILE;
+    const int64_t wbase = tbase + (int64_t)wid * (PER * GSS_WAVE);
     uint64_t kk[PER];
     double ww[PER];
     int32_t pos[PER];
@@ -453,24 +463,46 @@ __global__ __launch_bounds__(LSD_BLOCK) void k_lsd_scatter(const uint64_t *__res
         pos[i] = old + __popcll(peers & lanemask_lt());
     }
     __syncthreads();
-    // thread t: digit t's base for each wave = the tile's scanned offset + earlier waves
-    {
-        int32_t run = off[(int64_t)t * ntiles + blockIdx.x];
+    // thread t = digit t: the earlier waves' counts of it, its start inside the tile and
+    // its place in the output
+    int32_t tot_t = 0;
 #pragma unroll
-        for (int w = 0; w < NW; w++) {
-            const int32_t c = s_cnt[w][t];
-            s_cnt[w][t] = run;
-            run += c;
+    for (int w = 0; w < NW; w++) {
+        const int32_t c = s_cnt[w][t];
+        s_cnt[w][t] = tot_t;
+        tot_t += c;
+    }
+    int32_t all;
+    const int32_t dstart = block_exclusive_scan<int32_t>(tot_t, s_scan, &all);  // synchronises
+    s_dstart[t] = dstart;
+    s_goff[t] = off[(int64_t)t * ntiles + blockIdx.x];
+    __syncthreads();
+    int32_t lp[PER];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        lp[i] = -1;
+        if (wbase + i * GSS_WAVE + lane < n) {
+            const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
+            lp[i] = s_dstart[d] + cnt[d] + pos[i];
+            s_k[lp[i]] = kk[i];
+            s_d[lp[i]] = (uint8_t)d;
         }
     }
     __syncthreads();
+    const int nt = (int)(n - tbase < LSD_TILE ? n - tbase : LSD_TILE);
+    for (int q = t; q < nt; q += LSD_BLOCK) {
+        const int d = s_d[q];
+        kout[s_goff[d] + (q - s_dstart[d])] = s_k[q];
+    }
+    __syncthreads();
+    double *s_w = (double *)s_k;
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        if (wbase + i * GSS_WAVE + lane < n) {
-            const int32_t o = cnt[(uint32_t)(kk[i] >> shift) & 255u] + pos[i];
-            kout[o] = kk[i];
-            wout[o] = ww[i];
-        }
+    for (int i = 0; i < PER; i++)
+        if (lp[i] >= 0) s_w[lp[i]] = ww[i];
+    __syncthreads();
+    for (int q = t; q < nt; q += LSD_BLOCK) {
+        const int d = s_d[q];
+        wout[s_goff[d] + (q - s_dstart[d])] = s_w[q];
     }
 }
 
