@@ -91,6 +91,7 @@ __device__ __forceinline__ int64_t find_in_row(const int32_t *__restrict__ col, 
 // base + i*PB + tid).  Reads of row_ptr are clamped so malformed input stays in bounds.
 // ------------------------------------------------------------------------------------
 #define ETILE (PB * ENT_ITEMS)
+#define CK_TREE 0x80000000u  // in a sorted lower-entry key: the column is the row's parent
 
 
 // tile_row[b] = the row holding entry b*ETILE: one thread per row marks the tiles that
@@ -1278,10 +1279,11 @@ __global__ __launch_bounds__(1024) void k_rmq_sparse(uint64_t *__restrict__ st, 
 // (two counters, wave 0 and wave 1 look back in parallel), ranks both kinds inside the
 // tile in entry order (round, wave, lane), writes every off-tree edge's id, endpoints
 // and weight at its place, and gives each tree edge's id to the child endpoint
-// (tree_eid).  The last tile writes both totals.  With lkey and *mode = 1, every lower
-// entry (u, c), c < u, is also written at its rank among the lower entries (its position
-// minus the upper entries before it) as the key c << 32 | u and its weight, and
-// ubase[tile] receives the
+// (tree_eid).  The last tile writes both totals.  With lkey and *mode = 1 (symmetry by
+// transposition) it only numbers the edges: every lower entry (u, c), c < u, is written
+// at its rank among the lower entries (its position minus the upper entries before it)
+// as the key c << 32 | u (bit 31: c is u's parent) and its weight, ubase[tile] receives
+// the
 // tile's first edge id: the transpose check sorts the lower entries by column and
 // compares them with the upper ones.  Memory-safe on any input: rows are clamped, output
 // places are bounded by Mcap (F_TREE_EDGE beyond it) and by Lcap (F_ASYM beyond it:
@@ -1314,13 +1316,18 @@ __global__ __launch_bounds__(PB) void k_off_write(
         cv[i] = k < nnz ? col[k] : -1;
     }
     load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+    // Under transposition the off-tree edges are placed after the sort (k_sym_compare),
+    // which also tells which upper entries are their column vertex's tree edge: no
+    // gather of the column's parent here.
+    const bool defer = lkey && *mode == 1;
     int32_t pu[ENT_ITEMS], pc[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
         const int32_t u = srow[i * PB + threadIdx.x];
         const bool up = cv[i] > u && cv[i] < n;  // k >= nnz has cv = -1
-        pu[i] = up ? parent[u] : -1;
-        pc[i] = up ? parent[cv[i]] : -1;
+        const bool low = cv[i] >= 0 && cv[i] < u;
+        pu[i] = (up || (defer && low)) ? parent[u] : -1;
+        pc[i] = (up && !defer) ? parent[cv[i]] : -1;
     }
     uint64_t um[ENT_ITEMS], om[ENT_ITEMS];
 #pragma unroll
@@ -1328,7 +1335,7 @@ __global__ __launch_bounds__(PB) void k_off_write(
         const int32_t u = srow[i * PB + threadIdx.x];
         const bool up = cv[i] > u && cv[i] < n;
         um[i] = __ballot(up);
-        om[i] = __ballot(up && pu[i] != cv[i] && pc[i] != u);
+        om[i] = __ballot(!defer && up && pu[i] != cv[i] && pc[i] != u);
         if (lane == 0) {
             s_cnt[0][i][wid] = __popcll(um[i]);
             s_cnt[1][i][wid] = __popcll(om[i]);
@@ -1359,7 +1366,7 @@ __global__ __launch_bounds__(PB) void k_off_write(
         }
         if (lane == 0) {
             s_ex[wid] = excl;
-            if (tile == ntiles - 1) *(wid == 0 ? m_total : off_total) = excl + tot;
+            if (tile == ntiles - 1 && (wid == 0 || !defer)) *(wid == 0 ? m_total : off_total) = excl + tot;
         }
     }
     // batches: the graphs of the tile's first and last rows bound every entry's graph
@@ -1380,9 +1387,10 @@ __global__ __launch_bounds__(PB) void k_off_write(
     __syncthreads();
     const uint64_t lt = lanemask_lt();
     const int64_t ex_u = s_ex[0], ex_o = s_ex[1];
-    if (lkey && *mode == 1) {
+    if (defer) {
         if (threadIdx.x == 0) ubase[tile] = (int32_t)ex_u;
-        // lower entries at their rank: position minus the upper entries before it
+        // lower entries at their rank: position minus the upper entries before it; bit 31
+        // of the key marks the row's own tree edge (column = parent of the row)
 #pragma unroll
         for (int i = 0; i < ENT_ITEMS; i++) {
             const int64_t k = base + (int64_t)i * PB + threadIdx.x;
@@ -1393,9 +1401,10 @@ __global__ __launch_bounds__(PB) void k_off_write(
                 atomicOr(flags, F_ASYM);
                 continue;
             }
-            lkey[r] = ((uint64_t)(uint32_t)cv[i] << 32) | (uint32_t)u;
+            lkey[r] = ((uint64_t)(uint32_t)cv[i] << 32) | (pu[i] == cv[i] ? CK_TREE : 0u) | (uint32_t)u;
             lw[r] = w[k];
         }
+        return;
     }
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
@@ -1429,29 +1438,37 @@ __global__ __launch_bounds__(PB) void k_off_write(
     }
 }
 
-// Transpose comparison (exact symmetry).  The lower entries (u, c), c < u, in CSR order
-// are ordered by (u, c); sorted stably by column they are ordered by (c, u), the order in
-// which their mirrors (c, u) appear among the upper entries, which is edge-id order.  So
-// the graph is symmetric exactly when there are as many lower as upper entries (the
-// balance of k_check_entries) and the j-th sorted lower entry is (x, c) with weight w for
-// the upper entry (c, x) of weight w with id j, for every j (keys c << 32 | x).  One workgroup per tile;
-// the ids come from the tile's first id (ubase) and ranks inside the tile.  Memory-safe
-// on any input: rows are clamped and ids are bounded by Lcap (F_ASYM beyond it).
-__global__ __launch_bounds__(PB) void k_sym_compare(const int32_t *__restrict__ row_ptr,
-                                                    const int32_t *__restrict__ col, const double *__restrict__ w,
-                                                    int32_t n, int64_t nnz, const int32_t *__restrict__ tile_row,
-                                                    const int32_t *__restrict__ ubase, int64_t Lcap,
-                                                    const uint64_t *__restrict__ lkey, const double *__restrict__ lw,
-                                                    uint32_t *flags, const int64_t *__restrict__ mode)
+// Transpose comparison (exact symmetry), and the off-tree edges under transposition.
+// The lower entries (u, c), c < u, in CSR order are ordered by (u, c); sorted stably by
+// column they are ordered by (c, u), the order in which their mirrors (c, u) appear among
+// the upper entries, which is edge-id order.  So the graph is symmetric exactly when
+// there are as many lower as upper entries (the balance of k_check_entries) and the j-th
+// sorted lower entry is (x, c) with weight w for the upper entry (c, x) of weight w with
+// id j, for every j (keys c << 32 | x).  The sorted entry also says whether c is x's
+// parent (bit 31), so an upper entry (u, v) is a tree edge when parent[u] = v or that bit
+// is set: the off-tree edges are written here, in id order (decoupled look-back over
+// the tiles for their places), with the tree edge ids.  Memory-safe on any input: rows
+// are clamped, ids are bounded by Lcap (F_ASYM beyond it) and places by Mcap.
+__global__ __launch_bounds__(PB) void k_sym_compare(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ w,
+    const int32_t *__restrict__ parent, int32_t n, int64_t nnz, int64_t ntiles, const int32_t *__restrict__ tile_row,
+    const int32_t *__restrict__ ubase, int64_t Lcap, const uint64_t *__restrict__ lkey,
+    const double *__restrict__ lw, int64_t Mcap, int32_t *__restrict__ off_id, int32_t *__restrict__ off_u,
+    int32_t *__restrict__ off_v, double *__restrict__ off_w, const int32_t *__restrict__ vbase, int32_t G,
+    int32_t *__restrict__ off_g, int32_t *__restrict__ tree_eid, uint64_t *__restrict__ status, uint32_t epoch,
+    unsigned long long *ticket, int64_t *__restrict__ off_total, uint32_t *flags)
 {
-    if (*mode != 1) return;  // symmetry checked by the mirror search
     constexpr int NW = PB / GSS_WAVE;
     static_assert(ENT_ITEMS * NW <= GSS_WAVE, "one wave scans the piece counts");
     __shared__ int32_t srow[ETILE];
-    __shared__ int32_t s_cnt[ENT_ITEMS][NW];
-    __shared__ int32_t s_off[ENT_ITEMS][NW];
+    __shared__ int32_t s_cnt[2][ENT_ITEMS][NW];
+    __shared__ int32_t s_off[2][ENT_ITEMS][NW];
+    __shared__ int64_t s_tile, s_ex;
+    __shared__ int32_t s_glo, s_ghi;
     const int lane = lane_id(), wid = threadIdx.x / GSS_WAVE;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (threadIdx.x == 0) s_tile = lb_ticket(ticket, ntiles);
+    __syncthreads();
+    const int64_t tile = s_tile;
     const int64_t base = tile * ETILE;
     int32_t cv[ENT_ITEMS];
 #pragma unroll
@@ -1460,41 +1477,125 @@ __global__ __launch_bounds__(PB) void k_sym_compare(const int32_t *__restrict__ 
         cv[i] = k < nnz ? col[k] : -1;
     }
     load_tile_rows(row_ptr, n, nnz, base, tile_row, srow);  // synchronises
+    const int64_t ub = ubase[tile];
     uint64_t um[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
         const int32_t u = srow[i * PB + threadIdx.x];
         um[i] = __ballot(cv[i] > u && cv[i] < n);
-        if (lane == 0) s_cnt[i][wid] = __popcll(um[i]);
+        if (lane == 0) s_cnt[0][i][wid] = __popcll(um[i]);
     }
     __syncthreads();
-    if (wid == 0) {
+    if (wid == 0) {  // the upper entries' ranks inside the tile
         const int i = lane / NW, w2 = lane % NW;
         const bool has = lane < ENT_ITEMS * NW;
-        int32_t x = has ? s_cnt[i][w2] : 0;
+        int32_t x = has ? s_cnt[0][i][w2] : 0;
         const int32_t own = x;
 #pragma unroll
         for (int d = 1; d < GSS_WAVE; d <<= 1) {
             const int32_t y = __shfl_up(x, d, GSS_WAVE);
             if (lane >= d) x += y;
         }
-        if (has) s_off[i][w2] = x - own;
+        if (has) s_off[0][i][w2] = x - own;
     }
     __syncthreads();
+    // compare, and classify: off-tree unless parent[u] = v or the mirror's tree bit
     const uint64_t lt = lanemask_lt();
-    const int64_t ub = ubase[tile];
     uint32_t f = 0;
+    uint64_t om[ENT_ITEMS];
+    int32_t jid[ENT_ITEMS], tchild[ENT_ITEMS];
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
-        if (!((um[i] >> lane) & 1ull)) continue;
-        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
-        const int64_t j = ub + s_off[i][wid] + __popcll(um[i] & lt);
-        if (j < 0 || j >= Lcap) {
-            f |= F_ASYM;
+        const int32_t u = srow[i * PB + threadIdx.x];
+        const bool up = (um[i] >> lane) & 1ull;
+        bool off = false;
+        jid[i] = -1;
+        tchild[i] = -1;
+        if (up) {
+            const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+            const int64_t j = ub + s_off[0][i][wid] + __popcll(um[i] & lt);
+            if (j < 0 || j >= Lcap) {
+                f |= F_ASYM;
+            } else {
+                const uint64_t lkv = lkey[j];
+                if ((lkv & ~(uint64_t)CK_TREE) != (((uint64_t)(uint32_t)u << 32) | (uint32_t)cv[i]) || lw[j] != w[k])
+                    f |= F_ASYM;
+                jid[i] = (int32_t)j;
+                if (parent[u] == cv[i]) tchild[i] = u;
+                else if (lkv & CK_TREE) tchild[i] = cv[i];
+                else off = true;
+            }
+        }
+        om[i] = __ballot(off);
+        if (lane == 0) s_cnt[1][i][wid] = __popcll(om[i]);
+    }
+    __syncthreads();
+    if (wid == 1) {  // off-tree places: ranks inside the tile, the tile's place by look-back
+        const int i = lane / NW, w2 = lane % NW;
+        const bool has = lane < ENT_ITEMS * NW;
+        int32_t x = has ? s_cnt[1][i][w2] : 0;
+        const int32_t own = x;
+#pragma unroll
+        for (int d = 1; d < GSS_WAVE; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, GSS_WAVE);
+            if (lane >= d) x += y;
+        }
+        if (has) s_off[1][i][w2] = x - own;
+        const int64_t tot = __shfl(x, GSS_WAVE - 1, GSS_WAVE);
+        int64_t excl = 0;
+        if (tile == 0) {
+            if (lane == 0) lb_store(status, lb_word(LB_INC, epoch, (uint64_t)tot));
+        } else {
+            if (lane == 0) lb_store(status + tile, lb_word(LB_AGG, epoch, (uint64_t)tot));
+            excl = lb_lookback_wave(status, 1, tile, epoch);
+            if (lane == 0) lb_store(status + tile, lb_word(LB_INC, epoch, (uint64_t)(excl + tot)));
+        }
+        if (lane == 0) {
+            s_ex = excl;
+            if (tile == ntiles - 1) *off_total = excl + tot;
+        }
+    }
+    if (off_g && wid == 2 && lane < 2) {
+        const int64_t last = min((int64_t)ETILE, nnz - base) - 1;
+        const int32_t u = srow[lane == 0 ? 0 : last];
+        int32_t lo = 0, hi = G;  // vbase[lo] <= u < vbase[hi]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (vbase[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        if (lane == 0) s_glo = lo;
+        else s_ghi = lo;
+    }
+    __syncthreads();
+    const int64_t ex_o = s_ex;
+#pragma unroll
+    for (int i = 0; i < ENT_ITEMS; i++) {
+        if (jid[i] < 0) continue;
+        if (tchild[i] >= 0) {
+            tree_eid[tchild[i]] = jid[i];
             continue;
         }
+        const int64_t k = base + (int64_t)i * PB + threadIdx.x;
         const int32_t u = srow[i * PB + threadIdx.x];
-        if (lkey[j] != (((uint64_t)(uint32_t)u << 32) | (uint32_t)cv[i]) || lw[j] != w[k]) f |= F_ASYM;
+        const int64_t o = ex_o + s_off[1][i][wid] + __popcll(om[i] & lt);
+        if (o >= Mcap) {
+            atomicOr(flags, F_TREE_EDGE);  // more off-tree entries than m - n + 1
+            continue;
+        }
+        off_id[o] = jid[i];
+        off_u[o] = u;
+        off_v[o] = cv[i];
+        off_w[o] = w[k];
+        if (off_g) {
+            int32_t lo = s_glo, hi = s_ghi + 1;  // vbase[lo] <= u < vbase[hi]
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (vbase[mid] <= u) lo = mid;
+                else hi = mid;
+            }
+            off_g[o] = lo;
+        }
     }
     for (int d = 32; d > 0; d >>= 1) f |= __shfl_xor(f, d, GSS_WAVE);
     if (lane == 0 && f) atomicOr(flags, f);
@@ -1659,9 +1760,14 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
             int kb = 1;
             while (kb < 4 && ((uint64_t)(n - 1) >> (8 * kb)) != 0) kb++;
             lsd_sort_kw(ctx, tr.lk, tr.lw, tr.lk2, tr.lw2, tr.Lcap, 32, kb);
-            GSS_LAUNCH_B(4 * nnz + 8 * m + 16 * tr.Lcap, k_sym_compare, dim3((unsigned)etiles), dim3(PB), 0,
-                         ctx->stream, t->row_ptr, t->col, t->w, n, nnz, tile_row, tr.ub, tr.Lcap, tr.lk, tr.lw,
-                         ctx->d_flags, ctx->d_counters + 7);
+            uint32_t epoch = 0;
+            uint64_t *status = lb_begin(ctx, etiles, &epoch);
+            // per entry its column, per upper entry its weight, its row's parent and its
+            // sorted mirror; per off-tree edge its id, endpoints and weight written
+            GSS_LAUNCH_B(4 * nnz + 12 * m + 16 * tr.Lcap + 28 * t->M, k_sym_compare, dim3((unsigned)etiles), dim3(PB),
+                         0, ctx->stream, t->row_ptr, t->col, t->w, t->parent, n, nnz, etiles, tile_row, tr.ub, tr.Lcap,
+                         tr.lk, tr.lw, t->M, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g,
+                         t->tree_eid, status, epoch, lb_ticket_ptr(ctx), ctx->d_counters + 9, ctx->d_flags);
             for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
                 ctx->free(p);
         } else {
