@@ -374,6 +374,7 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         HIP_OK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
         HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
         HIP_OK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&ctx->ev_read, hipEventDisableTiming));
         HIP_OK(hipHostMalloc(&ctx->h_stage, gss_ctx_s::STAGE_BYTES, hipHostMallocDefault));
         HIP_OK(hipMemset(ctx->d_flags, 0, 256));
         HIP_OK(hipMemset(ctx->d_counters, 0, 32 * sizeof(int64_t)));
@@ -388,6 +389,8 @@ gss_status gss_ctx_create(int device, void *hip_stream, gss_ctx *out)
         if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
         if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
         if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_read) (void)hipEventDestroy(ctx->ev_read);
+        if (ctx->ev_read) (void)hipEventDestroy(ctx->ev_read);
         if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
         delete ctx;
         return s;
@@ -419,6 +422,7 @@ gss_status gss_ctx_destroy(gss_ctx ctx)
     ctx->pool.release_all();
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_read) (void)hipEventDestroy(ctx->ev_read);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);

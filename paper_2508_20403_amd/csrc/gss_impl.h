@@ -107,6 +107,7 @@ struct gss_ctx_s {
     // call: forked from and joined back into the context stream with events
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_read = nullptr;  // marks read-backs the host waits for while later work runs
     std::vector<void *> aux_frees;   // blocks released by auxiliary work, freed at the join
 
     // allocation-free calls: scratch is bumped out of a fixed device arena (the
@@ -189,12 +190,14 @@ struct gss_ctx_s {
         for (auto &pb : pending) tape_io(pb.first, pb.second);
         pending.clear();
     }
-    // waits for the context stream only: the auxiliary stream keeps running, so the
-    // caller reads back only what the context stream produced (staging memory is kept)
-    void sync_stream()
+    // waits for the context stream up to ev_read (recorded by the caller after its
+    // read-backs; work enqueued after it keeps running, and so does the auxiliary
+    // stream), so the caller reads back only what the context stream produced before the
+    // event (staging memory is kept)
+    void sync_read()
     {
         if (cap_mode != CAP_CAPTURE) {
-            HIP_OK(hipStreamSynchronize(stream));
+            HIP_OK(hipEventSynchronize(ev_read));
             n_syncs++;
         }
     }

@@ -523,11 +523,14 @@ __global__ __launch_bounds__(1024) void k_tree_total(const int4 *__restrict__ pa
     }
 }
 
-// Parent checks, roots, child counts and the children of every vertex as a list linked
-// by atomic exchange (fc[p] = the child that linked itself last, nsib[x] = the child
-// linked before x; the order of siblings is immaterial to every later result).  One
-// vertex per thread, so every thread's exchange is in flight at once; counter atomics
-// only where there is something to count (the root's block, or an error).
+// The vertex passes.  LINK = false: parent checks and roots, which the first host wait
+// reads (counter atomics only where there is something to count: the root's block, or an
+// error).  LINK = true: child counts and the children of every vertex as a list linked by
+// atomic exchange (fc[p] = the child that linked itself last, nsib[x] = the child linked
+// before x; the order of siblings is immaterial to every later result), enqueued after
+// the read-back so that it runs while the host waits.  One vertex per thread, so every
+// thread's exchange is in flight at once.
+template <bool LINK>
 __global__ __launch_bounds__(PB) void k_tree_vertices(const int32_t *__restrict__ parent, int32_t n,
                                                       int32_t *__restrict__ ccnt, int32_t *__restrict__ fc,
                                                       int32_t *__restrict__ nsib, uint32_t *flags, int64_t *counters)
@@ -536,13 +539,17 @@ __global__ __launch_bounds__(PB) void k_tree_vertices(const int32_t *__restrict_
     if (xx >= n) return;
     const int32_t x = (int32_t)xx;
     const int32_t p = parent[x];
+    if (!LINK) {
+        if (p == -1) {
+            atomicAdd((unsigned long long *)&counters[0], 1ull);
+            atomicMin((long long *)&counters[1], (long long)x);
+        } else if (p < 0 || p >= n || p == x) {
+            atomicOr(flags, F_NOT_TREE);
+        }
+        return;
+    }
     int32_t s = -1;
-    if (p == -1) {
-        atomicAdd((unsigned long long *)&counters[0], 1ull);
-        atomicMin((long long *)&counters[1], (long long)x);
-    } else if (p < 0 || p >= n || p == x) {
-        atomicOr(flags, F_NOT_TREE);
-    } else {
+    if (p >= 0 && p < n && p != x) {
         atomicAdd(&ccnt[p], 1);
         s = atomicExch(&fc[p], x);
     }
@@ -558,27 +565,61 @@ struct __attribute__((aligned(32))) TRec {
     u128 t;
 };
 
-// Tour records, the successor array of the arcs (read by the ruler selection) and, with
-// SUMS, the per-block sums of the terms for the 127-bit range check.  Successors: the down arc
-// into x continues with the down arc into its first child, or returns (up arc of x);
-// the up arc of x continues with the down arc into its next sibling, or the up arc of
-// its parent, or ends the tour when the parent is the root.  The root's arcs are not on
-// the tour (-2).  Every read is a coalesced per-vertex load (the children lists are
-// linked through the vertices themselves).
-template <bool SUMS>
+// What the tree passes' counters say about the tour: the root (counters[1], the smallest
+// root; n when there is none), the exponent range of the resistances (counters[2], [3]),
+// the tree edges found (counters[4], against need).  The fixed-point terms are used when
+// no resistance is out of range (F_RANGE), every tree edge was found and the range is at
+// most 74 (else zero terms; the host reports the error); their exact 127-bit sum is
+// checked when the range exceeds 44 (every term is below 2^(53 + range) and there are
+// fewer than 2^30 of them, so below that their sum, a bound on every root resistance,
+// stays below 2^127).  The same rule as the host's, read on the device, so the tour can
+// be built before the host has read the counters.
+struct TermsInfo {
+    int32_t root;
+    int emin;
+    bool ok, sums;
+};
+__device__ __forceinline__ TermsInfo terms_info(const int64_t *counters, const uint32_t *flags, int64_t need,
+                                                int32_t n)
+{
+    TermsInfo r;
+    r.root = (int32_t)counters[1];
+    int64_t emin = counters[2], emax = counters[3];
+    if (n == 1) emin = emax = 0;
+    const bool missing = counters[4] != need;
+    const bool range_bad = (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & F_RANGE) != 0 ||
+                           (!missing && emax - emin > 74);
+    r.ok = !range_bad && !missing;
+    if (!r.ok) emin = emax = 0;
+    r.emin = (int)emin;
+    r.sums = r.ok && emax - emin > 44;
+    return r;
+}
+
+// Tour records, the successor array of the arcs (read by the ruler selection) and, when
+// the exact sum of the terms is needed, the per-block sums for the 127-bit range check.
+// Successors: the down arc into x continues with the down arc into its first child, or
+// returns (up arc of x); the up arc of x continues with the down arc into its next
+// sibling, or the up arc of its parent, or ends the tour when the parent is the root (or
+// is no vertex: a parent array that is no tree, which the host rejects, still gives
+// successors inside the arcs).  The root's arcs are not on the tour (-2).  Every read
+// is a coalesced per-vertex load (the children lists are linked through the vertices
+// themselves).
 __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpos, const double *__restrict__ tinv,
                                                  const int32_t *__restrict__ parent,
                                                  const int32_t *__restrict__ ccnt, const int32_t *__restrict__ fc,
-                                                 const int32_t *__restrict__ nsib, int32_t n, int32_t root,
-                                                 int emin, int ok, TRec *__restrict__ trec,
-                                                 int32_t *__restrict__ succ, u128 *__restrict__ bsum,
-                                                 uint64_t *__restrict__ bcarry)
+                                                 const int32_t *__restrict__ nsib, int32_t n,
+                                                 const int64_t *__restrict__ counters, const uint32_t *flags,
+                                                 int64_t need, TRec *__restrict__ trec, int32_t *__restrict__ succ,
+                                                 u128 *__restrict__ bsum, uint64_t *__restrict__ bcarry)
 {
     __shared__ uint64_t slo[PB], shi[PB], sc[PB];
+    const TermsInfo ti = terms_info(counters, flags, need, n);
+    const int32_t root = ti.root;
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     u128 t = mk128(0, 0);
     if (x < n) {
-        if (ok && x != root && tpos[x] >= 0) t = fixed_term(tinv[x], emin);
+        if (ti.ok && x != root && tpos[x] >= 0) t = fixed_term(tinv[x], ti.emin);
         const int32_t c = fc[x];
         TRec e;
         e.par = parent[x];
@@ -591,13 +632,13 @@ __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpo
             e.nd = (c >= 0) ? 2 * c : 2 * x + 1;
             const int32_t s = nsib[x];
             if (s >= 0) e.nu = 2 * s;
-            else if (e.par == root) e.nu = GSS_END;
+            else if (e.par == root || e.par < 0 || e.par >= n || e.par == x) e.nu = GSS_END;
             else e.nu = 2 * e.par + 1;
         }
         trec[x] = e;
         *(int2 *)(succ + 2 * (int64_t)x) = make_int2(e.nd, e.nu);
     }
-    if (!SUMS) return;
+    if (!ti.sums) return;
     slo[threadIdx.x] = t.lo;
     shi[threadIdx.x] = t.hi;
     sc[threadIdx.x] = 0;
@@ -623,8 +664,10 @@ __global__ __launch_bounds__(PB) void k_tour_rec(const int32_t *__restrict__ tpo
 
 __global__ __launch_bounds__(1024) void k_terms_total(const u128 *__restrict__ bsum,
                                                       const uint64_t *__restrict__ bcarry, int64_t nb,
-                                                      uint32_t *flags)
+                                                      uint32_t *flags, const int64_t *__restrict__ counters,
+                                                      int64_t need, int32_t n)
 {
+    if (!terms_info(counters, flags, need, n).sums) return;  // the sum is bounded anyway
     __shared__ uint64_t slo[1024], shi[1024], sc[1024];
     u128 s = mk128(0, 0);
     uint64_t c = 0;
@@ -1604,9 +1647,14 @@ __global__ __launch_bounds__(PB) void k_sym_compare(
 // the root's vertex record (preorder index 0, depth 0, D = 0, its tree degree), its LCA
 // sequence entry (never inside a query range) and the head arc of the tour (the down
 // arc into its first child; n > 1); the tour writes every other record
-__global__ void k_vrec_root(VRec *vrec, int32_t n, int32_t root, uint64_t *__restrict__ epk,
+__global__ void k_vrec_root(VRec *vrec, int32_t n, const int64_t *__restrict__ counters, uint64_t *__restrict__ epk,
                             const int32_t *__restrict__ ccnt, const int32_t *__restrict__ fc, int64_t *head)
 {
+    const int64_t root = counters[1];  // the smallest root; n when there is none
+    if (root < 0 || root >= n) {
+        *head = -2;  // no tour: the ranking flags the parent array as no tree
+        return;
+    }
     VRec r;
     r.D = mk128(0, 0);
     r.first = 0;
@@ -1687,8 +1735,8 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         ctx->free(part);
         ctx->free(remote);
     }
-    GSS_LAUNCH_B(12 * (int64_t)n, k_tree_vertices, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, ccnt, fc,
-                 nsib, ctx->d_flags, ctx->d_counters);
+    GSS_LAUNCH_B(4 * (int64_t)n, k_tree_vertices<false>, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, ccnt,
+                 fc, nsib, ctx->d_flags, ctx->d_counters);
 
     struct Transpose {
         uint64_t *lk, *lk2;
@@ -1748,100 +1796,33 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
 
     HIP_OK(hipMemcpyAsync(ctx->h_counters, ctx->d_counters, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    ctx->sync_stream();
-    uint32_t f;
-    memcpy(&f, &ctx->h_counters[15], sizeof f);
-    const int64_t roots = ctx->h_counters[0];
-    if (tr.lk) {
-        if (ctx->h_counters[7] == 1) {
-            // transposition: the lower entries sorted stably by column (the column digits
-            // of the keys), compared with the upper entries in id order
-            AuxScope aux(ctx);
-            int kb = 1;
-            while (kb < 4 && ((uint64_t)(n - 1) >> (8 * kb)) != 0) kb++;
-            lsd_sort_kw(ctx, tr.lk, tr.lw, tr.lk2, tr.lw2, tr.Lcap, 32, kb);
-            uint32_t epoch = 0;
-            uint64_t *status = lb_begin(ctx, etiles, &epoch);
-            // per entry its column, per upper entry its weight, its row's parent and its
-            // sorted mirror; per off-tree edge its id, endpoints and weight written
-            GSS_LAUNCH_B(4 * nnz + 12 * m + 16 * tr.Lcap + 28 * t->M, k_sym_compare, dim3((unsigned)etiles), dim3(PB),
-                         0, ctx->stream, t->row_ptr, t->col, t->w, t->parent, n, nnz, etiles, tile_row, tr.ub, tr.Lcap,
-                         tr.lk, tr.lw, t->M, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g,
-                         t->tree_eid, status, epoch, lb_ticket_ptr(ctx), ctx->d_counters + 9, ctx->d_flags);
-            for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
-                ctx->free(p);
-        } else {
-            // mirror search: the lists were not written; they return to the pool once the
-            // auxiliary stream is joined
-            AuxScope aux(ctx);
-            for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
-                ctx->free(p);
-        }
-    }
-    auto free_tree_tmp = [&]() {
-        ctx->free(ccnt);
-        ctx->free(fc);
-        ctx->free(tpos);
-        ctx->free(nsib);
-        ctx->free(tinv);
-    };
-    // Errors keep their precedence (CSR checks, symmetry, then the tree): on any error
-    // the auxiliary stream's checks are awaited and read before the verdict.
-    auto fail_checked = [&](uint32_t tree_f) {
-        aux_join(ctx);
-        HIP_OK(hipMemcpyAsync(ctx->h_counters + 9, ctx->d_counters + 9, 5 * sizeof(int64_t), hipMemcpyDeviceToHost,
-                              st));
-        const uint32_t all = read_flags(ctx) | tree_f;  // syncs
-        free_tree_tmp();
-        const uint32_t fg = all & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
-        if (fg) fail(status_from_flags(fg), "invalid graph");
-        if (validate && ((all & F_ASYM) || ctx->h_counters[10] != 0 || nnz % 2))
-            fail(GSS_ERR_ASYM, "the graph is not symmetric");
-        if (all & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
-        fail(status_from_flags(all), "invalid input");
-    };
-    if ((f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT | F_ASYM)) || (f & F_NOT_TREE) || roots != 1)
-        fail_checked(roots != 1 ? F_NOT_TREE : 0);
-    t->root = (int32_t)ctx->h_counters[1];
-    int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
-    // every tree edge but the links to a batch's virtual root must be a graph edge
-    const int64_t need = (int64_t)(n - 1) - (t->virt_root >= 0 ? t->G : 0);
-    bool tree_edge_missing = ctx->h_counters[4] != need;
-    bool range_bad = (f & F_RANGE) != 0;
-    if (n == 1) emin = emax = 0;
-    if (!range_bad && !tree_edge_missing && emax - emin > 74) range_bad = true;
-    if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
-    t->emin = (int32_t)emin;
-    t->scale = (int32_t)emin - 52;
-
-    // tour records (successors, parent, degree, fixed-point term) and the 127-bit range
-    // check of the terms
+    HIP_OK(hipEventRecord(ctx->ev_read, st));
+    // memory-safe on any parent array: only valid parents are linked
+    GSS_LAUNCH_B(12 * (int64_t)n, k_tree_vertices<true>, dim3(grid_for(n, PB)), dim3(PB), 0, st, t->parent, n, ccnt,
+                 fc, nsib, ctx->d_flags, ctx->d_counters);
+    // Tour records (successors, parent, degree, fixed-point term), the tour ranking and
+    // the RMQ structure are enqueued before the host reads the counters: they take the
+    // root and the terms' scale from device memory and are memory-safe on any parent
+    // array (only valid parents are linked, successors stay inside the arcs, every walk
+    // is bounded), so the host's wait overlaps them; the verdict on the tree comes after.
+    const int64_t need = (int64_t)(n - 1) - (t->virt_root >= 0 ? t->G : 0);  // tree edges that are graph edges
     TRec *trec = ctx->alloc<TRec>(n);
     int32_t *succ = ctx->alloc<int32_t>(2 * (int64_t)n);
     int64_t tb = grid_for(n, PB);
     u128 *tbs = ctx->alloc<u128>(tb);
     uint64_t *tbc = ctx->alloc<uint64_t>(tb);
-    const int terms_ok = (range_bad || tree_edge_missing) ? 0 : 1;
-    // Every term is below 2^(53 + emax - emin) and there are fewer than 2^30 of them, so
-    // with emax - emin <= 44 their sum (a bound on every root resistance) stays below
-    // 2^127 and the exact sum is not needed.
-    const bool sums = terms_ok && emax - emin > 44;
     // per vertex: tree-edge position, resistance, parent, child count, first child and
     // next sibling read; record and both successors written
-    if (sums) {
-        GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec<true>, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent,
-                     ccnt, fc, nsib, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
-        GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags);
-    } else {
-        GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec<false>, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent,
-                     ccnt, fc, nsib, n, t->root, (int)emin, terms_ok, trec, succ, tbs, tbc);
-    }
+    GSS_LAUNCH_B(68 * (int64_t)n, k_tour_rec, dim3((unsigned)tb), dim3(PB), 0, st, tpos, tinv, t->parent, ccnt, fc,
+                 nsib, n, ctx->d_counters, ctx->d_flags, need, trec, succ, tbs, tbc);
+    GSS_LAUNCH(k_terms_total, dim3(1), dim3(1024), 0, st, tbs, tbc, tb, ctx->d_flags, ctx->d_counters, need, n);
 
     // Euler tour
     t->L = n;  // the LCA sequence is indexed by preorder
     t->vrec = ctx->alloc<VRec>(n);
     t->epk = ctx->alloc<uint64_t>(t->L);
-    GSS_LAUNCH(k_vrec_root, dim3(1), dim3(1), 0, st, t->vrec, n, t->root, t->epk, ccnt, fc, ctx->d_counters + 12);
+    GSS_LAUNCH(k_vrec_root, dim3(1), dim3(1), 0, st, t->vrec, n, ctx->d_counters, t->epk, ccnt, fc,
+               ctx->d_counters + 12);
     // the tour is ranked without waiting for the host: its flags (overflow, cycle) are read
     // together with the off-tree enumeration's below; every kernel in between is
     // memory-safe on a failed ranking
@@ -1873,9 +1854,74 @@ void prep_tree(gss_ctx ctx, gss_tree t, uint32_t flags)
         GSS_LAUNCH(k_rmq_sparse, dim3(1), dim3(1024), 0, st, t->sbst, t->nsb, t->sblevels);
     };
     build_rmq();
-    free_tree_tmp();
+    ctx->free(ccnt);
+    ctx->free(fc);
+    ctx->free(tpos);
+    ctx->free(nsib);
+    ctx->free(tinv);
     ctx->free(tbs);
     ctx->free(tbc);
+
+    // the tree passes' counters (the GPU ranks on meanwhile)
+    ctx->sync_read();
+    uint32_t f;
+    memcpy(&f, &ctx->h_counters[15], sizeof f);
+    const int64_t roots = ctx->h_counters[0];
+    if (tr.lk) {
+        if (ctx->h_counters[7] == 1) {
+            // transposition: the lower entries sorted stably by column (the column digits
+            // of the keys), compared with the upper entries in id order
+            AuxScope aux(ctx);
+            int kb = 1;
+            while (kb < 4 && ((uint64_t)(n - 1) >> (8 * kb)) != 0) kb++;
+            lsd_sort_kw(ctx, tr.lk, tr.lw, tr.lk2, tr.lw2, tr.Lcap, 32, kb);
+            uint32_t epoch = 0;
+            uint64_t *status = lb_begin(ctx, etiles, &epoch);
+            // per entry its column, per upper entry its weight, its row's parent and its
+            // sorted mirror; per off-tree edge its id, endpoints and weight written
+            GSS_LAUNCH_B(4 * nnz + 12 * m + 16 * tr.Lcap + 28 * t->M, k_sym_compare, dim3((unsigned)etiles), dim3(PB),
+                         0, ctx->stream, t->row_ptr, t->col, t->w, t->parent, n, nnz, etiles, tile_row, tr.ub, tr.Lcap,
+                         tr.lk, tr.lw, t->M, t->off_id, t->off_u, t->off_v, t->off_w, t->d_vbase, t->G, t->off_g,
+                         t->tree_eid, status, epoch, lb_ticket_ptr(ctx), ctx->d_counters + 9, ctx->d_flags);
+            for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
+                ctx->free(p);
+        } else {
+            // mirror search: the lists were not written; they return to the pool once the
+            // auxiliary stream is joined
+            AuxScope aux(ctx);
+            for (void *p : {(void *)tr.lk, (void *)tr.lk2, (void *)tr.lw, (void *)tr.lw2, (void *)tr.ub})
+                ctx->free(p);
+        }
+    }
+    // Errors keep their precedence (CSR checks, symmetry, then the tree): on any error
+    // the auxiliary stream's checks are awaited and read before the verdict.
+    auto fail_checked = [&](uint32_t tree_f) {
+        aux_join(ctx);
+        HIP_OK(hipMemcpyAsync(ctx->h_counters + 9, ctx->d_counters + 9, 5 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
+        const uint32_t all = read_flags(ctx) | tree_f;  // syncs
+        for (void *p : rank_bufs) ctx->free(p);
+        ctx->free(succ);
+        ctx->free(trec);
+        const uint32_t fg = all & (F_ARG | F_NOT_SIMPLE | F_WEIGHT);
+        if (fg) fail(status_from_flags(fg), "invalid graph");
+        if (validate && ((all & F_ASYM) || ctx->h_counters[10] != 0 || nnz % 2))
+            fail(GSS_ERR_ASYM, "the graph is not symmetric");
+        if (all & F_NOT_TREE) fail(GSS_ERR_NOT_TREE, "parent array is not a rooted tree");
+        fail(status_from_flags(all), "invalid input");
+    };
+    if ((f & (F_ARG | F_NOT_SIMPLE | F_WEIGHT | F_ASYM)) || (f & F_NOT_TREE) || roots != 1)
+        fail_checked(roots != 1 ? F_NOT_TREE : 0);
+    // the host's copy of the device's rule (terms_info)
+    t->root = (int32_t)ctx->h_counters[1];
+    int64_t emin = ctx->h_counters[2], emax = ctx->h_counters[3];
+    bool tree_edge_missing = ctx->h_counters[4] != need;
+    bool range_bad = (f & F_RANGE) != 0;
+    if (n == 1) emin = emax = 0;
+    if (!range_bad && !tree_edge_missing && emax - emin > 74) range_bad = true;
+    if (range_bad || tree_edge_missing) emin = emax = 0;  // keep the fixed-point terms bounded
+    t->emin = (int32_t)emin;
+    t->scale = (int32_t)emin - 52;
 
     aux_join(ctx);
     HIP_OK(hipGetLastError());
