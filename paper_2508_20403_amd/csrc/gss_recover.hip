@@ -521,10 +521,20 @@ __global__ void k_graph_key(int64_t P, const int32_t *__restrict__ pj, const int
 #endif
 #define RS_TILE (RS_BLOCK * RS_ITEMS)
 
+// the pairs to sort: the first n, or the first *dn of them when a device count is given
+__device__ __forceinline__ int64_t rs_count(int64_t n, const int64_t *dn)
+{
+    if (!dn) return n;
+    const int64_t d = *dn;
+    return d < 0 ? 0 : (d < n ? d : n);
+}
+
 // global digit counts of all eight byte positions: ghist[pos * 256 + digit] (zeroed)
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restrict__ k, int64_t n, int npos,
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restrict__ k, int64_t n_,
+                                                       const int64_t *__restrict__ dn, int npos,
                                                        int32_t *__restrict__ ghist)
 {
+    const int64_t n = rs_count(n_, dn);
     __shared__ int32_t sh[8][256];
 #pragma unroll
     for (int p = 0; p < 8; p++) sh[p][threadIdx.x] = 0;
@@ -552,7 +562,8 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_ghist(const uint64_t *__restric
 // scatter: the pass then copies its tile in place (so the ping-pong buffers stay in
 // step) and neither publishes nor reads look-back status.
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__restrict__ kin,
-                                                          const int32_t *__restrict__ vin, int64_t n, int shift,
+                                                          const int32_t *__restrict__ vin, int64_t n_,
+                                                          const int64_t *__restrict__ dn, int shift,
                                                           int64_t ntiles, const int32_t *__restrict__ ghist,
                                                           uint64_t *__restrict__ status, uint32_t epoch,
                                                           unsigned long long *ticket, uint64_t *__restrict__ kout,
@@ -565,6 +576,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__rest
     __shared__ int64_t s_tile;
     __shared__ int s_const;
     const int t = threadIdx.x, wid = t / GSS_WAVE, lane = lane_id();
+    const int64_t n = rs_count(n_, dn);
     if (t == 0) {
         s_tile = lb_ticket(ticket, ntiles);
         s_const = 0;
@@ -577,6 +589,8 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_onesweep(const uint64_t *__rest
     if ((int64_t)gh == n) s_const = 1;  // one digit holds every key
     __syncthreads();
     const int64_t tile = s_tile;
+    // tiles past a device count hold nothing; no tile before them waits on them
+    if (tile > 0 && tile * RS_TILE >= n) return;
     const int64_t wbase = tile * RS_TILE + (int64_t)wid * (RS_ITEMS * GSS_WAVE);
     if (s_const) {
 #pragma unroll
@@ -1262,9 +1276,10 @@ static void read_counters(gss_ctx ctx, int nwords, uint64_t used)
 // Stable LSD radix sort of (key, val) pairs by key ascending, with no host round trip.
 // With key_bytes = 0 all eight digit positions run (a position where every key agrees
 // is a plain copy); with key_bytes > 0 (keys known to be below 2^(8 key_bytes)) only the
-// low key_bytes positions run.
+// low key_bytes positions run.  With a device count dn only the first min(n, *dn) pairs
+// are sorted (the rest of the output is undefined).
 static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n,
-                             int key_bytes = 0)
+                             int key_bytes = 0, const int64_t *dn = nullptr)
 {
     if (n <= 1) return;
     hipStream_t st = ctx->stream;
@@ -1272,12 +1287,12 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
     int32_t *ghist = ctx->alloc<int32_t>(8 * 256);
     fill_bytes(ctx, ghist, 0, sizeof(int32_t) * 8 * 256);
     const int npos = key_bytes > 0 ? key_bytes : 8;
-    GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n, npos,
-                 ghist);
+    GSS_LAUNCH_B(8 * n, k_rs_ghist, dim3((unsigned)std::min<int64_t>(ntiles, 512)), dim3(RS_BLOCK), 0, st, k, n, dn,
+                 npos, ghist);
     for (int p = 0; p < npos; p++) {
         uint32_t epoch = 0;
         uint64_t *status = lb_begin(ctx, ntiles * 256, &epoch);
-        GSS_LAUNCH_B(24 * n, k_rs_onesweep, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, k, v, n, 8 * p, ntiles,
+        GSS_LAUNCH_B(24 * n, k_rs_onesweep, dim3((unsigned)ntiles), dim3(RS_BLOCK), 0, st, k, v, n, dn, 8 * p, ntiles,
                      ghist + p * 256, status, epoch, lb_ticket_ptr(ctx), k2, v2);
         HIP_OK(hipGetLastError());
         std::swap(k, k2);
@@ -1288,13 +1303,14 @@ static void radix_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&
 
 // Sort of (key, value) pairs with distinct values by (key, value): the sample sort for
 // the short sorts of a prefix (a few launches whatever the key width), the radix sort
-// (stable, so the same order) above its size limit.
+// (stable, so the same order) above its size limit.  dn: a device count of the pairs
+// that matter (the rest hold the largest key and stay last); only the radix sort uses it.
 static void sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, int32_t *&v2, int64_t n,
-                       int key_bytes = 0)
+                       int key_bytes = 0, const int64_t *dn = nullptr)
 {
-    // one-byte keys take one radix pass (two launches), fewer than the sample sort's five
+    // one-byte keys take one radix pass (two launches), fewer than the sample sort's four
     if (n <= sample_sort_max() && !ctx->sort_radix && key_bytes != 1) sample_sort_pairs(ctx, k, v, k2, v2, n);
-    else radix_sort_pairs(ctx, k, v, k2, v2, n, key_bytes);
+    else radix_sort_pairs(ctx, k, v, k2, v2, n, key_bytes, dn);
 }
 
 static int bytes_for(uint64_t maxkey)
@@ -1488,8 +1504,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     launch_subtask_keys(ctx, d_nsub, cap, B.sub_ptr, local_max, pred, cost_bits, qk, qv, is_local,
                         (int32_t *)(ctx->d_counters + 4), (int32_t *)(ctx->d_counters + 4) + 1,
                         (unsigned long long *)(ctx->d_counters + 6));
+    // only the nsub queued entries are read, so the radix sort orders just those
     sort_pairs(ctx, qk, qv, qk2, qv2, P,
-               bytes_for(cost_bits == 0 ? 3 * ((uint64_t)local_max + 1) - 1 : ((uint64_t)3 << cost_bits) - 1));
+               bytes_for(cost_bits == 0 ? 3 * ((uint64_t)local_max + 1) - 1 : ((uint64_t)3 << cost_bits) - 1), d_nsub);
     // words 4 and 6: the queue split; 14: the subtask count; 13: the prefix length (one graph)
     read_counters(ctx, 15, (1ull << 4) | (1ull << 6) | (1ull << 14) | (p_known ? 1ull << 13 : 0ull));
     if (p_known && ctx->h_counters[13] != P) {

@@ -12,13 +12,15 @@
 //      every bucket its start,
 //   4. every tile scatters its pairs into their buckets,
 //   5. one workgroup per bucket sorts it in registers when it holds at most eight times
-//      the mean bucket size of about 1024 pairs, otherwise in place in global memory.
+//      the workgroup size, otherwise in place in global memory.
+// Buckets hold about SS_MEAN pairs: the last launch takes as long as its largest bucket,
+// whose bitonic network runs on one compute unit, so buckets are kept small and many.
 // Pairs are ordered by (key, value); the callers' values are distinct, so the order is
 // total and the result does not depend on the order in which a bucket is filled.
 // The sorting network is the bitonic one in its one-direction form (the first step of
 // every merge compares mirrored positions, so every comparison puts the smaller pair at
-// the lower position).  In registers, thread t of the 1024 holds positions r * 1024 + t:
-// partners closer than a wavefront are exchanged by lane shuffles, partners 1024 or more
+// the lower position).  In registers, thread t of the SS_BT holds positions r * SS_BT + t:
+// partners closer than a wavefront are exchanged by lane shuffles, partners SS_BT or more
 // apart sit in the same thread, and only the remaining steps go through LDS.
 #include <algorithm>
 
@@ -28,9 +30,15 @@
 #define SS_TT 256        // threads of the counting and scatter kernels
 #define SS_TI 4          // pairs per thread there
 #define SS_TILE (SS_TT * SS_TI)
-#define SS_MAXB 512      // largest bucket count
-#define SS_BT 1024       // threads of the sample and bucket kernels
-#define SS_CAP 8192      // largest bucket sorted in LDS
+#define SS_MAXB 2048     // largest bucket count
+#ifndef SS_MEAN
+#define SS_MEAN 384      // pairs per bucket on average
+#endif
+#ifndef SS_LBT
+#define SS_LBT 9         // log2 of the bucket kernel's threads
+#endif
+#define SS_BT (1 << SS_LBT)
+#define SS_CAP (SS_BT * 8)  // largest bucket sorted in registers (eight pairs per thread)
 
 __device__ __forceinline__ bool ss_less(uint64_t ak, uint32_t av, uint64_t bk, uint32_t bv)
 {
@@ -108,12 +116,12 @@ __device__ __forceinline__ void ss_step(uint64_t (&k)[E], uint32_t (&v)[E], uint
             const uint32_t pv = ss_lane_xor<M>(v[r]);
             ss_keep(k[r], v[r], ((uint64_t)hi << 32) | lo, pv, lower);
         }
-    } else if constexpr ((M & 1023) == 0) {  // same thread: registers r and r ^ (M >> 10)
-        constexpr int RM = M >> 10;
+    } else if constexpr ((M & (SS_BT - 1)) == 0) {  // same thread: registers r and r ^ (M / SS_BT)
+        constexpr int RM = M >> SS_LBT;
 #pragma unroll
         for (int r = 0; r < E; r++) {
             if (r & RM) continue;
-            const int q = r ^ RM;  // q > r: position q * 1024 + t is the higher one
+            const int q = r ^ RM;  // q > r: position q * SS_BT + t is the higher one
             const bool lt = ss_less(k[q], v[q], k[r], v[r]);
             const uint64_t a = k[r], b = k[q];
             const uint32_t av = v[r], bv = v[q];
@@ -125,21 +133,21 @@ __device__ __forceinline__ void ss_step(uint64_t (&k)[E], uint32_t (&v)[E], uint
     } else {  // through LDS
 #pragma unroll
         for (int r = 0; r < E; r++) {
-            ek[r * 1024 + t] = k[r];
-            ev[r * 1024 + t] = v[r];
+            ek[r * SS_BT + t] = k[r];
+            ev[r * SS_BT + t] = v[r];
         }
         __syncthreads();
         uint64_t pk[E];
         uint32_t pv[E];
 #pragma unroll
         for (int r = 0; r < E; r++) {
-            const int q = (r * 1024 + t) ^ M;
+            const int q = (r * SS_BT + t) ^ M;
             pk[r] = ek[q];
             pv[r] = ev[q];
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < E; r++) ss_keep(k[r], v[r], pk[r], pv[r], (r * 1024 + t) < ((r * 1024 + t) ^ M));
+        for (int r = 0; r < E; r++) ss_keep(k[r], v[r], pk[r], pv[r], (r * SS_BT + t) < ((r * SS_BT + t) ^ M));
     }
 }
 
@@ -156,17 +164,17 @@ __device__ __forceinline__ void ss_steps(uint64_t (&k)[E], uint32_t (&v)[E], uin
     }
 }
 
-// Sorts the 1024 * E pairs held in registers by a workgroup of 1024 threads (thread t
-// holds positions r * 1024 + t).  ek/ev: LDS of 1024 * E entries for the steps whose
+// Sorts the SS_BT * E pairs held in registers by a workgroup of SS_BT threads (thread t
+// holds positions r * SS_BT + t).  ek/ev: LDS of SS_BT * E entries for the steps whose
 // partners are in other wavefronts.
 template <int E>
 __device__ void ss_reg_sort(uint64_t (&k)[E], uint32_t (&v)[E], uint64_t *ek, uint32_t *ev)
 {
     constexpr int LGE = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : 3;
-    ss_steps<E, 10 + LGE, 1, 0>(k, v, ek, ev);
+    ss_steps<E, SS_LBT + LGE, 1, 0>(k, v, ek, ev);
 }
 
-// loads S <= 1024 E pairs (padded with the largest pair), sorts them in registers and
+// loads S <= SS_BT E pairs (padded with the largest pair), sorts them in registers and
 // stores them back
 template <int E>
 __device__ void ss_sort_run(uint64_t *__restrict__ k, int32_t *__restrict__ v, int S, uint64_t *ek, uint32_t *ev)
@@ -175,14 +183,14 @@ __device__ void ss_sort_run(uint64_t *__restrict__ k, int32_t *__restrict__ v, i
     uint32_t vv[E];
 #pragma unroll
     for (int r = 0; r < E; r++) {
-        const int p = r * 1024 + (int)threadIdx.x;
+        const int p = r * SS_BT + (int)threadIdx.x;
         kk[r] = p < S ? k[p] : ~0ull;
         vv[r] = p < S ? (uint32_t)v[p] : ~0u;
     }
     ss_reg_sort<E>(kk, vv, ek, ev);
 #pragma unroll
     for (int r = 0; r < E; r++) {
-        const int p = r * 1024 + (int)threadIdx.x;
+        const int p = r * SS_BT + (int)threadIdx.x;
         if (p < S) {
             k[p] = kk[r];
             v[p] = (int32_t)vv[r];
@@ -229,10 +237,15 @@ __global__ __launch_bounds__(SS_RB) void k_ss_splitters(const uint64_t *__restri
     __shared__ uint64_t sk[SS_SAMPLES];
     __shared__ uint32_t sv[SS_SAMPLES];
     const int ns = 1 << lgns;
-    for (int i = threadIdx.x; i < ns; i += SS_RB) {
-        const int64_t p = ss_sample_pos(i, n, lgns);
-        sk[i] = k[p];
-        sv[i] = (uint32_t)v[p];
+    // the gathers of a thread are independent: all in flight before the LDS stores
+#pragma unroll
+    for (int r = 0; r < SS_SAMPLES / SS_RB; r++) {
+        const int i = r * SS_RB + (int)threadIdx.x;
+        if (i < ns) {
+            const int64_t p = ss_sample_pos(i, n, lgns);
+            sk[i] = k[p];
+            sv[i] = (uint32_t)v[p];
+        }
     }
     __syncthreads();
     const int t = blockIdx.x * SS_RB + (int)threadIdx.x;
@@ -327,9 +340,9 @@ __global__ __launch_bounds__(SS_BT) void k_ss_bucket(uint64_t *__restrict__ k, i
     const int S = (int)(s1 - s0);
     if (S <= 1) return;
     if (S <= cap) {
-        if (S <= 1024) ss_sort_run<1>(k + s0, v + s0, S, ek, ev);
-        else if (S <= 2048) ss_sort_run<2>(k + s0, v + s0, S, ek, ev);
-        else if (S <= 4096) ss_sort_run<4>(k + s0, v + s0, S, ek, ev);
+        if (S <= SS_BT) ss_sort_run<1>(k + s0, v + s0, S, ek, ev);
+        else if (S <= 2 * SS_BT) ss_sort_run<2>(k + s0, v + s0, S, ek, ev);
+        else if (S <= 4 * SS_BT) ss_sort_run<4>(k + s0, v + s0, S, ek, ev);
         else ss_sort_run<8>(k + s0, v + s0, S, ek, ev);
     } else {  // a bucket far above its expected size: the LDS network in global memory
         ss_network(k + s0, (uint32_t *)(v + s0), S);
@@ -343,9 +356,9 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
     if (n <= 1) return;
     if (n > sample_sort_max()) throw gss_error{GSS_ERR_ARG, "sample sort: too many pairs"};
     hipStream_t st = ctx->stream;
-    const int nb = (int)std::min<int64_t>(SS_MAXB, (n + 1023) / 1024);  // about 1024 pairs per bucket
+    const int nb = (int)std::min<int64_t>(SS_MAXB, (n + SS_MEAN - 1) / SS_MEAN);  // about SS_MEAN pairs per bucket
     const int64_t ntiles = (n + SS_TILE - 1) / SS_TILE;
-    // the LDS limit, or a smaller one set for tests (buckets above it take the global path)
+    // the register limit, or a smaller one set for tests (buckets above it take the global path)
     const int64_t cap = std::min<int64_t>(ctx->sort_cap > 0 ? ctx->sort_cap : SS_CAP, SS_CAP);
     int32_t *hist = ctx->alloc<int32_t>(ntiles * nb + 1);
     if (nb == 1) {  // one bucket: sort in place
@@ -355,8 +368,10 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
         ctx->free(hist);
         return;
     }
-    // about 8 samples per bucket, at least 1024
-    const int lgns = nb <= 128 ? 10 : nb <= 256 ? 11 : 12;
+    // at least 1024 samples and at most n; 2048 up to 1024 buckets (the ranking grows as the
+    // square of the sample), 4096 beyond
+    int lgns = nb <= 128 ? 10 : nb <= 1024 ? 11 : 12;
+    while (((int64_t)1 << lgns) > n) lgns--;
     uint64_t *spk = ctx->alloc<uint64_t>(nb);
     uint32_t *spv = ctx->alloc<uint32_t>(nb);
     GSS_LAUNCH_B(12 * ((int64_t)1 << lgns), k_ss_splitters, dim3((unsigned)(((int64_t)SS_RT << lgns) / SS_RB)),
@@ -374,7 +389,7 @@ void sample_sort_pairs(gss_ctx ctx, uint64_t *&k, int32_t *&v, uint64_t *&k2, in
     ctx->free(hist);
 }
 
-int64_t sample_sort_max() { return (int64_t)SS_MAXB * 1024; }
+int64_t sample_sort_max() { return (int64_t)SS_MAXB * SS_MEAN; }
 
 // ------------------------------------------------------------------------------------
 // LSD radix sort of large (key, double) arrays: per 8-bit digit a counting pass (one
