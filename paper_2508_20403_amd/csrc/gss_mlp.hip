@@ -3,8 +3,9 @@
 // A 12 -> 64 -> 64 -> 1 ReLU network predicts log2(cycles) of a subtask in the persistent
 // recovery kernel from 12 subtask features.  The scheduler orders the work queue by the
 // prediction (longest first); the recovery output never depends on it.
-//   * inference: layers 1 and 2 on BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k, FP32
-//     accumulation), one wavefront per 16 subtasks; layer 3 in FP32;
+//   * inference: layers 1 and 2 on BF16 matrix cores (CDNA4's v_mfma_f32_16x16x32_bf16,
+//     FP32 accumulation; lane l supplies row l % 16 and the eight K slots 8 (l / 16)..+7
+//     of A, the same slots of B), one wavefront per 16 subtasks; layer 3 in FP32;
 //   * training: FP32 mini-batch Adam, data parallel: a step's mini-batch is cut into
 //     64-sample slices, one workgroup per slice runs forward, MSE loss and backward in
 //     LDS and writes its share of the gradient, and a second kernel sums the shares in a
@@ -33,8 +34,16 @@
 
 static_assert(NPARAM == 5057, "parameter count");
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16x16 output tile += A (16 x 32) * B (32 x 16), BF16 operands given as bit patterns
+__device__ __forceinline__ v4f mfma_bf16_k32(v8s a, v8s b, v4f acc)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), acc, 0, 0,
+                                                   0);
+}
 
 // float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -75,13 +84,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
     const uint16_t *wb1 = wb, *wb2 = wb + HD * 16;
     for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
         const int64_t r0 = base + wv * 16;
-        // layer 1: A = normalised features (row = col, k = 4*quad..+3)
-        v4s a;
+        // layer 1: A = normalised features (row = col, k = 8*quad..+7; inputs past the
+        // twelve features are zero)
+        v8s a;
         {
             int64_t r = r0 + col;
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                int k = 4 * quad + i;
+            for (int i = 0; i < 8; i++) {
+                int k = 8 * quad + i;
                 float x = 0.f;
                 if (r < n && k < NF) x = (feat[r * NF + k] - w[OFF_MEAN + k]) / w[OFF_STD + k];
                 a[i] = (short)f2bf(x);
@@ -89,11 +99,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
         }
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-            v4s b;
+            v8s b;
 #pragma unroll
-            for (int i = 0; i < 4; i++) b[i] = (short)wb1[(16 * t + col) * 16 + 4 * quad + i];
+            for (int i = 0; i < 8; i++) {
+                const int k = 8 * quad + i;
+                b[i] = k < 16 ? (short)wb1[(16 * t + col) * 16 + k] : (short)0;
+            }
             v4f acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+            acc = mfma_bf16_k32(a, b, acc);
             // lane holds rows 4*quad+i, column 16t+col
 #pragma unroll
             for (int i = 0; i < 4; i++) sh[wv][4 * quad + i][16 * t + col] = fmaxf(acc[i] + w[OFF_B1 + 16 * t + col], 0.f);
@@ -105,14 +118,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
         for (int t = 0; t < 4; t++) {
             acc2[t] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kk = 0; kk < 4; kk++) {
-                v4s a2, b2;
+            for (int kk = 0; kk < 2; kk++) {
+                v8s a2, b2;
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    a2[i] = (short)f2bf(sh[wv][col][16 * kk + 4 * quad + i]);
-                    b2[i] = (short)wb2[(16 * t + col) * HD + 16 * kk + 4 * quad + i];
+                for (int i = 0; i < 8; i++) {
+                    a2[i] = (short)f2bf(sh[wv][col][32 * kk + 8 * quad + i]);
+                    b2[i] = (short)wb2[(16 * t + col) * HD + 32 * kk + 8 * quad + i];
                 }
-                acc2[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b2, acc2[t], 0, 0, 0);
+                acc2[t] = mfma_bf16_k32(a2, b2, acc2[t]);
             }
         }
         __syncthreads();
