@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2508_20403_amd import gss, synth
-from tests.test_oracle_pins import graph_from_json
+from tests.test_oracle_pins import RANGE_CASES, graph_from_json, range_case_graph
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,15 @@ def test_range_error(gpu_ctx):
     edges = [[0, 1, 1.0], [1, 2, 2.0 ** 80], [2, 3, 1.0], [3, 4, 1.0], [0, 4, 1.0]]
     g = graph_from_json(5, edges, [-1, 0, 1, 2, 3])
     assert gpu_status(gpu_ctx, g) == oracle.recover(g).status == -7
+
+
+@pytest.mark.parametrize("w12,ok", RANGE_CASES)
+def test_range_limits_match_oracle(gpu_ctx, w12, ok):
+    """Both sides of the 74-binade term limit and of the 2^127 sum limit."""
+    g = range_case_graph(w12)
+    st = oracle.recover(g).status
+    assert (st >= 0) if ok else (st == -7)
+    assert gpu_status(gpu_ctx, g) == st
 
 
 def test_missing_mirror_is_asym(gpu_ctx):

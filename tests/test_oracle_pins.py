@@ -334,6 +334,29 @@ def test_status_codes():
     assert oracle.recover(gg).status == -7
 
 
+# Tree resistances t = 1/w are summed exactly as 53-bit mantissas shifted to the scale of
+# the smallest binade (R19): a term fits 127 bits while its binade lies at most 74 above
+# the smallest one, and the sum of all terms must stay below 2^127.  The path 0-1-2-3-4
+# has t = 1 on three edges and t = 1/w12 on edge (1, 2).
+RANGE_CASES = [
+    (2.0 ** -74, True),   # binades 0 and 74: one term of 2^126, three of 2^52
+    (2.0 ** -75, False),  # binades 0 and 75: a 128-bit term
+    (2.0 ** 73, True),    # binades -73 and 0: three terms of 2^125 plus 2^52, below 2^127
+    (2.0 ** 74, False),   # binades -74 and 0: three terms of 2^126 reach 2^127
+]
+
+
+def range_case_graph(w12):
+    edges = [[0, 1, 1.0], [1, 2, w12], [2, 3, 1.0], [3, 4, 1.0], [0, 4, 1.0]]
+    return graph_from_json(5, edges, [-1, 0, 1, 2, 3])
+
+
+@pytest.mark.parametrize("w12,ok", RANGE_CASES)
+def test_range_limits_on_both_sides(w12, ok):
+    st = oracle.recover(range_case_graph(w12)).status
+    assert (st >= 0) if ok else (st == -7), st
+
+
 def test_short_when_fewer_offtree_edges_than_k():
     g = synth.random_connected(50, 10, seed=1)
     M = g.m - (g.n - 1)
