@@ -1175,21 +1175,30 @@ struct GraphOut {
     uint8_t *mask;
     int64_t ebase;       // union edge id of the graph's first edge
     int64_t nrec;        // edges already recovered (earlier passes)
-    int64_t take;        // candidates to take now
+    int64_t need;        // edges still wanted (0: the graph takes nothing in this round)
     int64_t pstart;      // first rank of the graph in the prefix
+    int32_t full;        // the prefix holds every eligible edge of the graph
 };
 
+// Writes the candidates a graph takes in this prefix round, decided on the device from
+// its candidate count cand[g] by the rule of the pass: the first `need` candidates when
+// there are that many, all of them when the prefix held every eligible edge (a pass
+// that ends short), otherwise none (a longer prefix follows).  A stretch that was not a
+// finite double (F_RANGE) fails the call: nothing is written then.
 __global__ void k_cand_write(int64_t P, const uint8_t *__restrict__ state, const int32_t *__restrict__ candq,
                              const int32_t *__restrict__ rg, const GraphOut *__restrict__ go,
-                             const int32_t *__restrict__ rid, const int32_t *__restrict__ sj,
-                             uint64_t *__restrict__ key)
+                             const int64_t *__restrict__ cand, const int32_t *__restrict__ rid,
+                             const int32_t *__restrict__ sj, uint64_t *__restrict__ key,
+                             const uint32_t *__restrict__ flags)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P || state[p] != ST_CAND) return;
+    if (p >= P || state[p] != ST_CAND || (*flags & F_RANGE)) return;
     const int32_t g = rg ? rg[p] : 0;
     const GraphOut o = go[g];
+    const int64_t c = cand[g];
+    const int64_t take = (c >= o.need || o.full) ? (c < o.need ? c : o.need) : 0;
     int64_t r = (int64_t)candq[p] - (int64_t)candq[o.pstart];
-    if (r >= o.take) return;
+    if (r >= take) return;
     int32_t local = (int32_t)(rid[p] - o.ebase);
     if (o.order) o.order[o.nrec + r] = local;
     o.mask[local] = 1;
@@ -1323,7 +1332,8 @@ static int bytes_for(uint64_t maxkey)
 struct PrefixResult {
     int64_t P = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0, njoin = 0;
     bool rounds_pending = false;  // rounds is in h_counters[12] after the next synchronisation
-    std::vector<int64_t> Pg, cand;  // per graph
+    std::vector<int64_t> Pg, cand;  // per graph (cand after finish_candidates)
+    int64_t *dcand = nullptr;       // per graph candidate counts on the device
 };
 
 struct PrefixBufs {
@@ -1349,19 +1359,27 @@ __global__ void k_rank_graph(int64_t P, const int32_t *__restrict__ sj, const in
     if (p < P) rg[p] = off_g[sj[p]];
 }
 
-// Candidates per graph (ranks among the recovered edges) into res.cand; synchronises.
+// Candidates per graph (ranks among the recovered edges), counted on the device into
+// res.dcand without waiting: the outputs are written from the device counts, and
+// finish_candidates reads them back afterwards.
 static void count_candidates(gss_ctx ctx, int32_t G, int64_t P, PrefixBufs &B, PrefixResult &res)
 {
     hipStream_t st = ctx->stream;
     B.candq = ctx->alloc<int32_t>(P + 2);
     GSS_LAUNCH(k_cand_flags, dim3(grid_for(P + 1, RB)), dim3(RB), 0, st, P, B.state, B.candq);
     scan_exclusive_i32(ctx, B.candq, P + 1, false);
-    int64_t *cg = ctx->alloc<int64_t>(G);
-    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, cg);
+    res.dcand = ctx->alloc<int64_t>(G);
+    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, res.dcand);
+}
+
+// res.cand (and the pending round count) from the device; synchronises
+static void finish_candidates(gss_ctx ctx, int32_t G, PrefixResult &res)
+{
     res.cand.assign(G, 0);
-    ctx->readback(res.cand.data(), cg, sizeof(int64_t) * G);
+    ctx->readback(res.cand.data(), res.dcand, sizeof(int64_t) * G);
     if (res.rounds_pending) res.rounds = ctx->h_counters[12];
-    ctx->free(cg);
+    ctx->free(res.dcand);
+    res.dcand = nullptr;
 }
 
 // Resolves, for every graph g, the prefix {key >= thr[g]} of its criticality order.
@@ -1872,8 +1890,28 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         PrefixBufs B;
         PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, plen, B, &prms[0]);
         ctx->free(dthr);
+        // the outputs are written before the candidate counts come back: k_cand_write
+        // applies the pass rule below to the device counts (and writes nothing on F_RANGE)
+        int64_t pst = 0;
+        for (int32_t g = 0; g < G; g++) {
+            go[g].order = orders ? orders[g] : nullptr;
+            go[g].mask = masks[g];
+            go[g].ebase = t->ebase[g];
+            go[g].nrec = nrec[g];
+            go[g].need = active[g] ? K[g] - nrec[g] : 0;
+            go[g].full = r.Pg[g] >= eligible[g] ? 1 : 0;
+            go[g].pstart = pst;
+            pst += r.Pg[g];
+            if (active[g]) lastP[g] = r.Pg[g];
+        }
+        if (r.P > 0) {
+            ctx->h2d(dgo, go.data(), sizeof(GraphOut) * G);
+            GSS_LAUNCH(k_cand_write, dim3(grid_for(r.P, RB)), dim3(RB), 0, st, r.P, B.state, B.candq, B.rg, dgo,
+                       r.dcand, B.rid, B.sj, key, ctx->d_flags);
+            HIP_OK(hipGetLastError());
+        }
+        finish_candidates(ctx, G, r);  // synchronises: also delivers the range flag
         if (!flags_checked) {
-            ctx->sync();
             uint32_t f = 0;
             memcpy(&f, &ctx->h_counters[15], sizeof f);
             flags_checked = true;
@@ -1887,30 +1925,6 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         arcs = r.arcs;
         rounds = r.rounds;
         njoin = r.njoin;
-        int64_t pst = 0;
-        bool write = false;
-        for (int32_t g = 0; g < G; g++) {
-            go[g].order = orders ? orders[g] : nullptr;
-            go[g].mask = masks[g];
-            go[g].ebase = t->ebase[g];
-            go[g].nrec = nrec[g];
-            go[g].take = 0;
-            go[g].pstart = pst;
-            pst += r.Pg[g];
-            if (!active[g]) continue;
-            const int64_t need = K[g] - nrec[g];
-            lastP[g] = r.Pg[g];
-            if (r.cand[g] >= need || r.Pg[g] >= eligible[g]) {
-                go[g].take = std::min<int64_t>(r.cand[g], need);
-                write |= go[g].take > 0;
-            }
-        }
-        if (write) {
-            ctx->h2d(dgo, go.data(), sizeof(GraphOut) * G);
-            GSS_LAUNCH(k_cand_write, dim3(grid_for(r.P, RB)), dim3(RB), 0, st, r.P, B.state, B.candq, B.rg, dgo,
-                       B.rid, B.sj, key);
-            HIP_OK(hipGetLastError());
-        }
         any_active = 0;
         for (int32_t g = 0; g < G; g++) {
             if (!active[g]) continue;
