@@ -201,6 +201,27 @@ struct gss_ctx_s {
             n_syncs++;
         }
     }
+    // a read-back whose wait comes later: the copy is followed by ev_read, the caller
+    // enqueues independent work and then calls wait_early() before reading dst (recording
+    // and capturing take the ordinary read-back)
+    bool early_pending = false;
+    void readback_early(void *dst, const void *src, size_t bytes, uint64_t words = ~0ull)
+    {
+        if (cap_mode != CAP_OFF) {
+            readback(dst, src, bytes, words);
+            return;
+        }
+        HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipEventRecord(ev_read, stream));
+        early_pending = true;
+    }
+    void wait_early()
+    {
+        if (!early_pending) return;
+        early_pending = false;
+        HIP_OK(hipEventSynchronize(ev_read));
+        n_syncs++;
+    }
     // a tape entry: its length (4 bytes), then the bytes read back
     void tape_io(void *dst, size_t bytes)
     {

@@ -1550,8 +1550,13 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     if (nsub > nlocal) launch_join_list(ctx, P, glca, hid, is_local, B.grp, B.glist);
 
     // Step 4, small and medium subtasks: persistent work-queue kernel
+    // launched at once without a join, else between the join's read-back and the wait for
+    // it (it touches neither the join's edges nor its counters), to cover the host round trip
     uint64_t *cycles = nullptr;
-    if (nlocal > 0) {
+    bool local_launched = false;
+    auto local_step = [&]() {
+        if (local_launched || nlocal <= 0) return;
+        local_launched = true;
         if (ctx->record) {
             cycles = ctx->alloc<uint64_t>(nsub + 1);
             scratch.push_back(cycles);
@@ -1593,7 +1598,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         // per subtask: queue entry and bounds
         if (ctx->prof) ctx->prof_bytes = (P - nglobal_edges) * (14 + 8 * (int64_t)(c + 1)) + 12 * (int64_t)nlocal;
         launch_local_recover(ctx, c, a, blocks);
-    }
+    };
+    if (nsub <= nlocal) local_step();
     // Step 4, large subtasks: hash join + dependency rounds over their edges
     B.indeg = ctx->alloc<int32_t>(P + 1);
     B.mcnt = ctx->alloc<int32_t>(P + 1);
@@ -1627,7 +1633,9 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
             GSS_LAUNCH_B(16 * nslots, k_jp_join, dim3(nparts), dim3(JP_BLOCK), 0, st, recs, jhist, nblk, nparts, d_total,
                          arc_slot, arc_buf, arc_cnt, B.indeg, (const int32_t *)nullptr);
             GSS_LAUNCH(k_jp_offsets, dim3(1), dim3(1024), 0, st, arc_cnt, nparts, arc_off, ctx->d_counters);
-            read_counters(ctx, 4, (1ull << 0) | (1ull << 3));
+            ctx->readback_early(ctx->h_counters, ctx->d_counters, sizeof(int64_t) * 4, (1ull << 0) | (1ull << 3));
+            local_step();
+            ctx->wait_early();
             const int64_t most = ctx->h_counters[3];
             const int64_t A = ctx->h_counters[0];
             // partitions with more arcs than their slice: joined again into a buffer of their own
@@ -1697,6 +1705,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         ctx->free(arc_cnt);
         ctx->free(arc_off);
     }
+    local_step();  // launched above when there was a join
     count_candidates(ctx, G, P, B, res);
     if (ctx->record && nsub > 0) trace_append(ctx, nsub, B.sub_ptr, B.sub_lca, P, feat, cycles, qv, nlocal);
     for (void *p : scratch) ctx->free(p);
