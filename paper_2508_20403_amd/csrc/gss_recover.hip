@@ -26,6 +26,7 @@
 // paper's LCA subtasks without materialising them; grouping is reported as statistics.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 
 #include "gss_impl.h"
 #include "gss_lookback.h"
@@ -1383,9 +1384,22 @@ static void finish_candidates(gss_ctx ctx, int32_t G, PrefixResult &res)
 }
 
 // Resolves, for every graph g, the prefix {key >= thr[g]} of its criticality order.
+// One graph: the prefix's per-tile counts {key >= thr} scanned in place (pc, one word per
+// PX_TILE keys and one more); the total goes to counter word 13
+static void prefix_tile_counts(gss_ctx ctx, gss_tree t, const uint64_t *key, const uint64_t *thr, int32_t *pc)
+{
+    const int64_t M = t->M;
+    const int64_t nthr = (M + PX_TILE - 1) / PX_TILE;
+    GSS_LAUNCH_B(8 * M, k_prefix_count, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, ctx->stream, key, M,
+                 (const int32_t *)nullptr, thr, pc);
+    scan_exclusive_i32_dev(ctx, pc, nthr, ctx->d_counters + 13);
+}
+
+// pc_ready (one graph): the scanned tile counts, already computed by prefix_tile_counts
+// (ownership passes here)
 static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uint64_t *key, const uint8_t *bst,
                                    const int32_t *lca, const uint64_t *thr, const std::vector<int64_t> &plen,
-                                   PrefixBufs &B, const gss_params *prm)
+                                   PrefixBufs &B, const gss_params *prm, int32_t *pc_ready = nullptr)
 {
     hipStream_t st = ctx->stream;
     const int64_t M = t->M;
@@ -1395,15 +1409,21 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     std::vector<void *> scratch;
     // compaction (id order: graph-major)
     int64_t nthr = (M + PX_TILE - 1) / PX_TILE;  // tiles
-    int32_t *pc = ctx->alloc<int32_t>(nthr + 1);
-    GSS_LAUNCH_B(8 * M, k_prefix_count, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M, off_g,
-                 thr, pc);
     // a single graph's prefix length is known from the selection; the scan's total is
     // compared with it at the next read-back instead of being waited for here
     const bool p_known = G == 1;
+    int32_t *pc = pc_ready;
+    if (!pc) {
+        pc = ctx->alloc<int32_t>(nthr + 1);
+        if (p_known) {
+            prefix_tile_counts(ctx, t, key, thr, pc);
+        } else {
+            GSS_LAUNCH_B(8 * M, k_prefix_count, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M,
+                         off_g, thr, pc);
+        }
+    }
     int64_t P;
     if (p_known) {
-        scan_exclusive_i32_dev(ctx, pc, nthr, ctx->d_counters + 13);
         P = plen[0];
     } else {
         P = scan_exclusive_i32(ctx, pc, nthr, true);
@@ -1720,9 +1740,14 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
 // plen[g] receives the number of keys >= thr[g]: the keys above the chosen bucket plus the
 // bucket's own (every key of the bucket is at least its lowest key, every key below it is
 // smaller), all eligible keys when the threshold is 1, none when the graph is not selected.
+// overlap (may be null) is called with the device thresholds after each read-back of the
+// state is enqueued and before it is waited for: work that needs only the thresholds runs
+// during the host round trip (it is called again after a later level, whose thresholds
+// then replace the earlier ones)
 static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist, bool hist_ready,
                               const std::vector<int64_t> &want, const std::vector<int64_t> &eligible,
-                              std::vector<int64_t> &plen, uint64_t *dthr)
+                              std::vector<int64_t> &plen, uint64_t *dthr,
+                              const std::function<void(const uint64_t *)> *overlap = nullptr)
 {
     hipStream_t st = ctx->stream;
     const int32_t G = t->G;
@@ -1777,7 +1802,13 @@ static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint
                            lv == LEVELS - 1 ? 1 : 0, S);
             }
         }
-        ctx->readback(init.data(), dstate, sizeof(int64_t) * words);
+        if (overlap) {
+            ctx->readback_early(init.data(), dstate, sizeof(int64_t) * words);
+            (*overlap)(S.thr);
+            ctx->wait_early();
+        } else {
+            ctx->readback(init.data(), dstate, sizeof(int64_t) * words);
+        }
         refining = lv < LEVELS ? h_active[lv] : 0;
         if (refining == 0) break;
     }
@@ -1894,10 +1925,17 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
         const size_t amark = ctx->arena_mark();  // allocation-free calls: rounds reuse the scratch
         std::vector<int64_t> plen;
         uint64_t *dthr = ctx->alloc<uint64_t>(G);
-        select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen, dthr);
+        // one graph: the prefix's tile counts run while the host waits for the selection
+        int32_t *pc = nullptr;
+        std::function<void(const uint64_t *)> tile_counts;
+        if (G == 1) {
+            pc = ctx->alloc<int32_t>((t->M + PX_TILE - 1) / PX_TILE + 1);
+            tile_counts = [&](const uint64_t *thr) { prefix_tile_counts(ctx, t, key, thr, pc); };
+        }
+        select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen, dthr, pc ? &tile_counts : nullptr);
         hist_ready = false;
         PrefixBufs B;
-        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, plen, B, &prms[0]);
+        PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, plen, B, &prms[0], pc);
         ctx->free(dthr);
         // the outputs are written before the candidate counts come back: k_cand_write
         // applies the pass rule below to the device counts (and writes nothing on F_RANGE)
