@@ -1895,8 +1895,8 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             largest[g] = hs[2 * g + 1];
         }
     }
-    // the range flag is fetched without waiting; it is checked after the first prefix is
-    // resolved (that step synchronises, and nothing is written to the outputs before it)
+    // the range flag is fetched without waiting; it is checked after the first prefix
+    // round's read-back (k_cand_write writes nothing while it is set)
     ctx->readback_async(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t));
     bool flags_checked = false;
     auto cleanup = [&]() {
