@@ -1545,8 +1545,15 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     // only the nsub queued entries are read, so the radix sort orders just those
     sort_pairs(ctx, qk, qv, qk2, qv2, P,
                bytes_for(cost_bits == 0 ? 3 * ((uint64_t)local_max + 1) - 1 : ((uint64_t)3 << cost_bits) - 1), d_nsub);
-    // words 4 and 6: the queue split; 14: the subtask count; 13: the prefix length (one graph)
-    read_counters(ctx, 15, (1ull << 4) | (1ull << 6) | (1ull << 14) | (p_known ? 1ull << 13 : 0ull));
+    // words 4 and 6: the queue split; 14: the subtask count; 13: the prefix length (one graph).
+    // The join list (ranks of the edges on the join path, in grouped order; at most P of
+    // them) needs only device data: it is built while the host waits, and left unused when
+    // no subtask goes to the join.
+    ctx->readback_early(ctx->h_counters, ctx->d_counters, sizeof(int64_t) * 15,
+                        (1ull << 4) | (1ull << 6) | (1ull << 14) | (p_known ? 1ull << 13 : 0ull));
+    B.glist = ctx->alloc<int32_t>(P + 1);
+    launch_join_list(ctx, P, glca, hid, is_local, B.grp, B.glist);
+    ctx->wait_early();
     if (p_known && ctx->h_counters[13] != P) {
         for (void *p : scratch) ctx->free(p);
         throw gss_error{GSS_ERR_HIP, "prefix length differs from the selection"};
@@ -1565,9 +1572,6 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     scratch.push_back(is_local);
 
     B.state = ctx->alloc<uint8_t>(P + 1);
-    // ranks of the edges on the join path, in grouped order
-    B.glist = ctx->alloc<int32_t>(nglobal_edges + 1);
-    if (nsub > nlocal) launch_join_list(ctx, P, glca, hid, is_local, B.grp, B.glist);
 
     // Step 4, small and medium subtasks: persistent work-queue kernel
     // launched at once without a join, else between the join's read-back and the wait for
