@@ -495,8 +495,12 @@ __global__ __launch_bounds__(256) void k_prefix_write(const uint64_t *__restrict
 // keys: a valid index and the largest sort key (the host compares the lengths at its
 // next read-back and fails the call on a difference)
 __global__ void k_prefix_pad(const int64_t *__restrict__ total, int64_t cap, int32_t *__restrict__ pj,
-                             uint64_t *__restrict__ pk)
+                             uint64_t *__restrict__ pk, int64_t *__restrict__ pstart)
 {
+    if (threadIdx.x == 0) {  // the one graph's rank range [0, cap)
+        pstart[0] = 0;
+        pstart[1] = cap;
+    }
     for (int64_t i = *total + threadIdx.x; i < cap; i += blockDim.x) {
         pj[i] = 0;
         pk[i] = ~0ull;
@@ -1163,12 +1167,14 @@ __global__ void k_cand_flags(int64_t P, const uint8_t *__restrict__ state, int32
     if (p == P) flag[p] = 0;
 }
 
-// per graph: candidates in its rank range [pstart[g], pstart[g+1])
+// per graph: candidates in its rank range [pstart[g], pstart[g+1]); out[G]: the flags word
+// (read back with the counts)
 __global__ void k_cand_per_graph(int32_t G, const int64_t *__restrict__ pstart, const int32_t *__restrict__ candq,
-                                 int64_t *__restrict__ out)
+                                 const uint32_t *__restrict__ flags, int64_t *__restrict__ out)
 {
     int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g < G) out[g] = (int64_t)candq[pstart[g + 1]] - (int64_t)candq[pstart[g]];
+    if (g == G) out[G] = (int64_t)*flags;
 }
 
 struct GraphOut {
@@ -1186,8 +1192,9 @@ struct GraphOut {
 // there are that many, all of them when the prefix held every eligible edge (a pass
 // that ends short), otherwise none (a longer prefix follows).  A stretch that was not a
 // finite double (F_RANGE) fails the call: nothing is written then.
+// go: one record per graph (device), or null for one graph whose record is go1
 __global__ void k_cand_write(int64_t P, const uint8_t *__restrict__ state, const int32_t *__restrict__ candq,
-                             const int32_t *__restrict__ rg, const GraphOut *__restrict__ go,
+                             const int32_t *__restrict__ rg, const GraphOut *__restrict__ go, GraphOut go1,
                              const int64_t *__restrict__ cand, const int32_t *__restrict__ rid,
                              const int32_t *__restrict__ sj, uint64_t *__restrict__ key,
                              const uint32_t *__restrict__ flags)
@@ -1195,7 +1202,7 @@ __global__ void k_cand_write(int64_t P, const uint8_t *__restrict__ state, const
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P || state[p] != ST_CAND || (*flags & F_RANGE)) return;
     const int32_t g = rg ? rg[p] : 0;
-    const GraphOut o = go[g];
+    const GraphOut o = go ? go[g] : go1;
     const int64_t c = cand[g];
     const int64_t take = (c >= o.need || o.full) ? (c < o.need ? c : o.need) : 0;
     int64_t r = (int64_t)candq[p] - (int64_t)candq[o.pstart];
@@ -1334,7 +1341,8 @@ struct PrefixResult {
     int64_t P = 0, arcs = 0, rounds = 0, nsub = 0, nlocal = 0, njoin = 0;
     bool rounds_pending = false;  // rounds is in h_counters[12] after the next synchronisation
     std::vector<int64_t> Pg, cand;  // per graph (cand after finish_candidates)
-    int64_t *dcand = nullptr;       // per graph candidate counts on the device
+    int64_t *dcand = nullptr;       // per graph candidate counts on the device (and the flags)
+    uint32_t flags = 0;             // the flags word read with the counts
 };
 
 struct PrefixBufs {
@@ -1369,15 +1377,19 @@ static void count_candidates(gss_ctx ctx, int32_t G, int64_t P, PrefixBufs &B, P
     B.candq = ctx->alloc<int32_t>(P + 2);
     GSS_LAUNCH(k_cand_flags, dim3(grid_for(P + 1, RB)), dim3(RB), 0, st, P, B.state, B.candq);
     scan_exclusive_i32(ctx, B.candq, P + 1, false);
-    res.dcand = ctx->alloc<int64_t>(G);
-    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, res.dcand);
+    res.dcand = ctx->alloc<int64_t>(G + 1);
+    GSS_LAUNCH(k_cand_per_graph, dim3(grid_for(G + 1, RB)), dim3(RB), 0, st, G, B.pstart, B.candq, ctx->d_flags,
+               res.dcand);
 }
 
-// res.cand (and the pending round count) from the device; synchronises
+// res.cand, the flags word (res.flags) and the pending round count from the device;
+// synchronises
 static void finish_candidates(gss_ctx ctx, int32_t G, PrefixResult &res)
 {
-    res.cand.assign(G, 0);
-    ctx->readback(res.cand.data(), res.dcand, sizeof(int64_t) * G);
+    res.cand.assign(G + 1, 0);
+    ctx->readback(res.cand.data(), res.dcand, sizeof(int64_t) * (G + 1));
+    res.flags = (uint32_t)res.cand[G];
+    res.cand.resize(G);
     if (res.rounds_pending) res.rounds = ctx->h_counters[12];
     ctx->free(res.dcand);
     res.dcand = nullptr;
@@ -1440,11 +1452,12 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
     } else {
         res.Pg[0] = P;
     }
+    B.pstart = ctx->alloc<int64_t>(G + 1);
     uint64_t *k1 = ctx->alloc<uint64_t>(P + 1), *k2 = ctx->alloc<uint64_t>(P + 1);
     int32_t *v1 = ctx->alloc<int32_t>(P + 1), *v2 = ctx->alloc<int32_t>(P + 1);
     GSS_LAUNCH_B(8 * M + 12 * P, k_prefix_write, dim3((unsigned)std::max<int64_t>(nthr, 1)), dim3(256), 0, st, key, M,
                  off_g, thr, pc, P, v1, k1);
-    if (p_known) GSS_LAUNCH(k_prefix_pad, dim3(1), dim3(256), 0, st, ctx->d_counters + 13, P, v1, k1);
+    if (p_known) GSS_LAUNCH(k_prefix_pad, dim3(1), dim3(256), 0, st, ctx->d_counters + 13, P, v1, k1, B.pstart);
     ctx->free(pc);
     sort_pairs(ctx, k1, v1, k2, v2, P);  // stretch descending, id ascending
     if (G > 1) {  // stable by graph: each graph's prefix becomes contiguous, in rank order
@@ -1452,10 +1465,11 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
         radix_sort_pairs(ctx, k1, v1, k2, v2, P, bytes_for((uint64_t)(G - 1)));
     }
     B.sj = v1;
-    std::vector<int64_t> ps(G + 1, 0);
-    for (int32_t g = 0; g < G; g++) ps[g + 1] = ps[g] + res.Pg[g];
-    B.pstart = ctx->alloc<int64_t>(G + 1);
-    ctx->h2d(B.pstart, ps.data(), sizeof(int64_t) * (G + 1));
+    if (!p_known) {  // one graph: written by k_prefix_pad
+        std::vector<int64_t> ps(G + 1, 0);
+        for (int32_t g = 0; g < G; g++) ps[g + 1] = ps[g] + res.Pg[g];
+        ctx->h2d(B.pstart, ps.data(), sizeof(int64_t) * (G + 1));
+    }
     if (G > 1) {
         B.rg = ctx->alloc<int32_t>(P + 1);
         GSS_LAUNCH(k_rank_graph, dim3(grid_for(P, RB)), dim3(RB), 0, st, P, B.sj, t->off_g, B.rg);
@@ -1739,7 +1753,8 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
 // Per graph, a key threshold T such that {key >= T} holds at least want[g] eligible edges
 // (and not many more).  want[g] <= 0: graph not selected (threshold above every key).
 // The digit levels run on the device, each graph's state updated by the pick kernel,
-// without a host round trip between levels; dthr (device, G) receives the thresholds.
+// without a host round trip between levels; dthr points at the thresholds (device, G) in the
+// state block state_out, which the caller frees.
 //
 // plen[g] receives the number of keys >= thr[g]: the keys above the chosen bucket plus the
 // bucket's own (every key of the bucket is at least its lowest key, every key below it is
@@ -1750,7 +1765,7 @@ static PrefixResult resolve_prefix(gss_ctx ctx, gss_tree t, int32_t c, const uin
 // then replace the earlier ones)
 static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint32_t *hist, bool hist_ready,
                               const std::vector<int64_t> &want, const std::vector<int64_t> &eligible,
-                              std::vector<int64_t> &plen, uint64_t *dthr,
+                              std::vector<int64_t> &plen, const uint64_t *&dthr, void *&state_out,
                               const std::function<void(const uint64_t *)> *overlap = nullptr)
 {
     hipStream_t st = ctx->stream;
@@ -1817,8 +1832,9 @@ static void select_thresholds(gss_ctx ctx, gss_tree t, const uint64_t *key, uint
         if (refining == 0) break;
     }
     memcpy(plen.data(), h_plen, sizeof(int64_t) * G);
-    HIP_OK(hipMemcpyAsync(dthr, S.thr, sizeof(uint64_t) * G, hipMemcpyDeviceToDevice, st));
-    ctx->free(dstate);
+    // the thresholds stay in the state block, which the caller frees after using them
+    dthr = S.thr;
+    state_out = dstate;
 }
 
 // Recovery of every graph of a tree (a single graph, or a batch).
@@ -1899,9 +1915,8 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             largest[g] = hs[2 * g + 1];
         }
     }
-    // the range flag is fetched without waiting; it is checked after the first prefix
-    // round's read-back (k_cand_write writes nothing while it is set)
-    ctx->readback_async(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t));
+    // the range flag comes back with the first prefix round's candidate counts (k_cand_write
+    // writes nothing while it is set), or, when no round runs, by itself at the end
     bool flags_checked = false;
     auto cleanup = [&]() {
         ctx->free(key);
@@ -1925,10 +1940,12 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     int64_t arcs = 0, rounds = 0, njoin = 0;
     GraphOut *dgo = ctx->alloc<GraphOut>(G);
     std::vector<GraphOut> go(G);
+    if (!any_active) ctx->readback_async(&ctx->h_counters[15], ctx->d_flags, sizeof(uint32_t));
     while (any_active) {
         const size_t amark = ctx->arena_mark();  // allocation-free calls: rounds reuse the scratch
         std::vector<int64_t> plen;
-        uint64_t *dthr = ctx->alloc<uint64_t>(G);
+        const uint64_t *dthr = nullptr;
+        void *sel_state = nullptr;
         // one graph: the prefix's tile counts run while the host waits for the selection
         int32_t *pc = nullptr;
         std::function<void(const uint64_t *)> tile_counts;
@@ -1936,11 +1953,12 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             pc = ctx->alloc<int32_t>((t->M + PX_TILE - 1) / PX_TILE + 1);
             tile_counts = [&](const uint64_t *thr) { prefix_tile_counts(ctx, t, key, thr, pc); };
         }
-        select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen, dthr, pc ? &tile_counts : nullptr);
+        select_thresholds(ctx, t, key, hist, hist_ready, want, eligible, plen, dthr, sel_state,
+                          pc ? &tile_counts : nullptr);
         hist_ready = false;
         PrefixBufs B;
         PrefixResult r = resolve_prefix(ctx, t, c, key, bst, lca, dthr, plen, B, &prms[0], pc);
-        ctx->free(dthr);
+        ctx->free(sel_state);
         // the outputs are written before the candidate counts come back: k_cand_write
         // applies the pass rule below to the device counts (and writes nothing on F_RANGE)
         int64_t pst = 0;
@@ -1956,15 +1974,15 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
             if (active[g]) lastP[g] = r.Pg[g];
         }
         if (r.P > 0) {
-            ctx->h2d(dgo, go.data(), sizeof(GraphOut) * G);
-            GSS_LAUNCH(k_cand_write, dim3(grid_for(r.P, RB)), dim3(RB), 0, st, r.P, B.state, B.candq, B.rg, dgo,
-                       r.dcand, B.rid, B.sj, key, ctx->d_flags);
+            if (G > 1) ctx->h2d(dgo, go.data(), sizeof(GraphOut) * G);  // one graph: a kernel argument
+            GSS_LAUNCH(k_cand_write, dim3(grid_for(r.P, RB)), dim3(RB), 0, st, r.P, B.state, B.candq, B.rg,
+                       G > 1 ? (const GraphOut *)dgo : (const GraphOut *)nullptr, go[0], r.dcand, B.rid, B.sj,
+                       key, ctx->d_flags);
             HIP_OK(hipGetLastError());
         }
         finish_candidates(ctx, G, r);  // synchronises: also delivers the range flag
         if (!flags_checked) {
-            uint32_t f = 0;
-            memcpy(&f, &ctx->h_counters[15], sizeof f);
+            const uint32_t f = r.flags;
             flags_checked = true;
             if (f & F_RANGE) {
                 B.release(ctx);
