@@ -53,7 +53,7 @@ struct RmqPlan {
     bool same_block, has_blocks, same_super, has_super;
 };
 
-__device__ __forceinline__ RmqPlan rmq_plan(const RmqView &q, int32_t i, int32_t j)
+__device__ __forceinline__ RmqPlan rmq_plan(const RmqView &, int32_t i, int32_t j)
 {
     RmqPlan P;
     P.i = i;
@@ -1882,7 +1882,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
     // per off-tree edge: u, v, w (16 B); first, depth and D of u and v and D of the LCA
     // (56 B); the two LCA-sequence entries that answer the range minimum (16 B); key, LCA and
     // beta* written (13 B); optional stretch (8 B)
-    if (M > 0)
+    if (M > 0) {
         if (STRETCH_HIST && G == 1)
             GSS_LAUNCH_B((101 + (stretch ? 8 : 0)) * M, k_edge_stretch<true>,
                          dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0, st,
@@ -1893,6 +1893,7 @@ gss_status recover_impl(gss_ctx ctx, gss_tree t, const gss_params *prms, uint8_t
                          dim3((unsigned)std::min<int64_t>(grid_for(M, RB * EDGE_ITEMS), EDGE_GRID)), dim3(RB), 0, st,
                          M, t->off_id, t->off_u, t->off_v, t->off_w, t->vrec, rmq_view(t), t->scale, c, key, lca, bst,
                          stretch, (uint32_t *)nullptr, lcacnt, ctx->d_flags, key_rt);
+    }
     HIP_OK(hipGetLastError());
     if (!lcacnt) {
         for (int32_t g = 0; g < G; g++) nsubg[g] = largest[g] = -1;
