@@ -183,6 +183,10 @@ __device__ __forceinline__ void load_tile_rows(const int32_t *__restrict__ row_p
 // mirroring (injective) is then a bijection between them, so every upper entry has its
 // mirror too.  With *mode = 1 the transpose comparison (k_sym_compare) checks symmetry
 // instead.  Memory-safe on any input: rows are clamped.
+// The distant mirror rows (more than RS_CAP rows before the tile) usually form one short
+// row range (on a grid, the rows one layer back): when its columns fit the LDS that held
+// the tile's row indices, they are loaded there in one coalesced pass and searched like
+// the tile's own rows; the near ones (the previous tile's rows) are searched in memory.
 __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const double *__restrict__ w, int32_t n, int64_t nnz,
@@ -227,11 +231,13 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     const int32_t r_last = srow[nloc - 1];
     uint32_t f = 0;
     int64_t bal = 0;  // upper minus lower entries
+    int32_t uv[ENT_ITEMS];  // row of each entry (srow's LDS is reused for the far rows below)
 #pragma unroll
     for (int i = 0; i < ENT_ITEMS; i++) {
         const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+        uv[i] = k < nnz ? srow[k - base] : 0;
         if (k >= nnz) continue;
-        const int32_t u = srow[k - base];
+        const int32_t u = uv[i];
         const int32_t c = cv[i];
         if (c < 0 || c >= n) {
             f |= F_ARG;
@@ -249,31 +255,79 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
     if (search) {
         // The mirror (c, u) of every lower entry (u, c) is searched in row c.  A row lying
         // wholly inside the tile (r0 < c < r_last, its start within RS_CAP rows of r0) is
-        // bisected in LDS; any other row in global memory, the searches of eight entries in
-        // lockstep so that their loads overlap.  lo/hi bisect the row for the first column
-        // >= u (tile offsets for a row in LDS, CSR positions otherwise).  Row bounds are
-        // clamped so malformed input stays in bounds.
+        // bisected in LDS; so is a row of the far range [f0, f1] of the other mirror rows
+        // when that range was loaded; any other row in global memory, the searches of eight
+        // entries in lockstep so that their loads overlap.  lo/hi bisect the row for the
+        // first column >= u (tile or far-range offsets for a row in LDS, CSR positions
+        // otherwise).  Row bounds are clamped so malformed input stays in bounds.
+        auto in_tile = [&](int32_t c) { return c > r0 && c < r_last && c + 1 - r0 < RS_CAP; };
+        __shared__ int32_t s_far[2];
+        __shared__ int32_t s_frs[RS_CAP];  // far-range row starts, offsets from flo
+        // the far range's columns go to srow (the tile's rows are in uv now)
+        if (threadIdx.x == 0) {
+            s_far[0] = 0x7fffffff;
+            s_far[1] = -1;
+        }
+        int32_t fmn = 0x7fffffff, fmx = -1;
+#pragma unroll
+        for (int i = 0; i < ENT_ITEMS; i++) {
+            const int64_t k = base + (int64_t)i * PB + threadIdx.x;
+            const int32_t c = cv[i];
+            if (k < nnz && c >= 0 && c < uv[i] && c < r0 - RS_CAP) {  // the distant mirror rows
+                fmn = min(fmn, c);
+                fmx = max(fmx, c);
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            fmn = min(fmn, __shfl_xor(fmn, d, GSS_WAVE));
+            fmx = max(fmx, __shfl_xor(fmx, d, GSS_WAVE));
+        }
+        __syncthreads();  // the rows in srow are no longer read; s_far initialised
+        if (lane_id() == 0 && fmx >= 0) {
+            atomicMin(&s_far[0], fmn);
+            atomicMax(&s_far[1], fmx);
+        }
+        __syncthreads();
+        const int32_t f0 = s_far[0], f1 = s_far[1];  // uniform across the workgroup
+        int64_t flo = 0;
+        int32_t fcnt = 0;
+        bool far_lds = false;
+        if (f1 >= 0 && f1 - f0 + 2 <= RS_CAP) {  // columns are in [0, n), so f1 + 1 <= n
+            // the range's first ETILE entries; a row is searched in LDS when it ends within them
+            flo = clamp_idx(row_ptr[f0], 0, nnz);
+            const int64_t fhi = clamp_idx(row_ptr[f1 + 1], flo, nnz);
+            far_lds = true;
+            fcnt = (int32_t)min(fhi - flo, (int64_t)ETILE);
+            for (int32_t i = threadIdx.x; i < fcnt; i += PB) srow[i] = col[flo + i];
+            for (int32_t r = threadIdx.x; r <= f1 + 1 - f0; r += PB)
+                s_frs[r] = (int32_t)(clamp_idx(row_ptr[f0 + r], flo, fhi) - flo);
+            __syncthreads();
+        }
         constexpr int MB = 8;
 #pragma unroll 1
         for (int h = 0; h < ENT_ITEMS; h += MB) {
             int32_t lo[MB], hi[MB], end[MB], key[MB];
-            uint32_t inlds = 0;
+            uint32_t inlds = 0, infar = 0;
 #pragma unroll
             for (int q = 0; q < MB; q++) {
                 const int64_t k = base + (int64_t)(h + q) * PB + threadIdx.x;
                 lo[q] = hi[q] = end[q] = 0;
                 key[q] = -1;
                 if (k >= nnz) continue;
-                const int32_t u = srow[k - base];
-                const int32_t c = scol[k - base];
+                const int32_t u = uv[h + q];
+                const int32_t c = cv[h + q];
                 if (c < 0 || c >= u) continue;  // not a lower entry (or out of range, flagged above)
                 key[q] = u;
-                if (c > r0 && c < r_last && c + 1 - r0 < RS_CAP) {
+                if (in_tile(c)) {
                     // (clamped to the tile: on a malformed row_ptr, which the row checks flag,
                     // the starts may be stale)
                     inlds |= 1u << q;
                     lo[q] = min(max(s_rs[c - r0], 0), nloc);
                     hi[q] = end[q] = min(max(s_rs[c + 1 - r0], lo[q]), nloc);
+                } else if (far_lds && c >= f0 && c <= f1 && s_frs[c + 1 - f0] <= fcnt) {
+                    infar |= 1u << q;
+                    lo[q] = min(max(s_frs[c - f0], 0), fcnt);
+                    hi[q] = end[q] = min(max(s_frs[c + 1 - f0], lo[q]), fcnt);
                 } else {
                     lo[q] = (int32_t)clamp_idx(row_ptr[c], 0, nnz);
                     hi[q] = end[q] = (int32_t)clamp_idx(row_ptr[c + 1], lo[q], nnz);
@@ -285,7 +339,13 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
                 for (int q = 0; q < MB; q++) {
                     if (key[q] >= 0 && lo[q] < hi[q]) {
                         const int32_t mid = lo[q] + ((hi[q] - lo[q]) >> 1);
-                        const int32_t cm = ((inlds >> q) & 1u) ? scol[mid] : col[mid];
+                        int32_t cm;
+                        if (((inlds | infar) >> q) & 1u) {
+                            const int32_t *lds = ((inlds >> q) & 1u) ? scol : srow;
+                            cm = lds[mid];
+                        } else {
+                            cm = col[mid];
+                        }
                         if (cm < key[q]) lo[q] = mid + 1;
                         else hi[q] = mid;
                         busy = true;
@@ -296,10 +356,18 @@ __global__ __launch_bounds__(PB) void k_check_entries(const int32_t *__restrict_
 #pragma unroll
             for (int q = 0; q < MB; q++) {
                 if (key[q] < 0) continue;
-                const bool loc = (inlds >> q) & 1u;
-                const int64_t pos = loc ? base + lo[q] : (int64_t)lo[q];
-                const bool found = lo[q] < end[q] && (loc ? scol[lo[q]] : col[pos]) == key[q];
-                if (!found || w[pos] != wv[h + q]) f |= F_ASYM;
+                const bool loc = (inlds >> q) & 1u, far = (infar >> q) & 1u;
+                const int64_t pos = loc ? base + lo[q] : far ? flo + lo[q] : (int64_t)lo[q];
+                int32_t cf = -1;
+                if (lo[q] < end[q]) {
+                    if (loc || far) {
+                        const int32_t *lds = loc ? scol : srow;
+                        cf = lds[lo[q]];
+                    } else {
+                        cf = col[pos];
+                    }
+                }
+                if (cf != key[q] || w[pos] != wv[h + q]) f |= F_ASYM;
             }
         }
     }
